@@ -1,0 +1,187 @@
+/*
+ * dski.h -- C ABI of the MI355X (gfx950) D-SKI library: GP regression with
+ * derivative observations under structured kernel interpolation.
+ *
+ * The operator (Sec. 3.1, "D-SKI"):  for n points x_i in R^d with values and
+ * gradients observed, the N x N matrix, N = n(d+1),
+ *
+ *     K~ = [W; dW_1; ...; dW_d] K_UU [W; dW_1; ...; dW_d]^T + D,
+ *
+ * where W holds cubic-convolution interpolation weights (Keys 1981, a = -1/2)
+ * onto a uniform grid U, dW_p their derivatives along axis p, K_UU the SE
+ * kernel (App. A) on the grid (Kronecker product of symmetric Toeplitz
+ * factors, applied by FFT over circulant embeddings, Sec. 2), and
+ * D = diag(sigma_f^2 1_n, sigma_g^2 1_{nd}) the value / gradient noise.
+ * On top of it: truncated pivoted Cholesky preconditioning (Sec. 3.3),
+ * preconditioned CG, stochastic Lanczos quadrature for log det (Sec. 2), and
+ * the log marginal likelihood eq. (1) with its hyper-parameter gradient.
+ *
+ * Conventions, for every call:
+ *  - Pointers are DEVICE pointers unless the name ends in _host.
+ *  - Ownership: the caller allocates and frees every buffer it passes.  The
+ *    library owns only what sits behind the opaque handles (plan, precond)
+ *    and releases it in the matching *_destroy.  No call keeps a caller
+ *    pointer after it returns (X is copied into the plan).
+ *  - Errors: every call returns a dski_status.  0 = success; > 0 = finished
+ *    with a warning, outputs valid; < 0 = error, outputs unspecified but no
+ *    memory is leaked.  dski_last_error() returns the message of the last
+ *    failure on the calling thread.  No exception or abort crosses the ABI.
+ *  - Streams: device work is enqueued on `stream` (0 = the null stream).
+ *    Calls with *_host outputs synchronise `stream` before returning.  A plan
+ *    (and its preconditioners) must not be used by two calls at once.
+ *  - Layout of an N-vector: block-major [f(x_1..x_n); d_1 f(x_1..x_n); ...;
+ *    d_d f(x_1..x_n)] (the block form of Sec. 3.1), points in USER order.
+ *    A block of R vectors is column-major with leading dimension ld >= N.
+ *  - Hyper-parameters are natural logs: log ell_1..log ell_d, log s,
+ *    log sigma_f, log sigma_g (this order wherever a gradient is returned).
+ *  - Arithmetic: N-vectors are stored in FP32; interpolation, K_UU, dot
+ *    products and all scalars are computed in FP64.
+ */
+#ifndef DSKI_H
+#define DSKI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSKI_OK = 0,
+  DSKI_NOT_CONVERGED = 1,      /* PCG hit max_iter; last iterate returned          */
+  DSKI_RANK_TRUNCATED = 2,     /* pivoted Cholesky stopped before rank k           */
+  DSKI_EINVAL = -1,            /* bad argument, shape, or non-finite input         */
+  DSKI_ENOMEM = -2,            /* device allocation failed                         */
+  DSKI_EHIP = -3,              /* a HIP runtime call failed                        */
+  DSKI_EBREAKDOWN = -4,        /* p^T K~ p <= 0 or r^T M^{-1} r < 0 in PCG         */
+  DSKI_ENOTSUP = -5            /* configuration not supported by this build        */
+} dski_status;
+
+typedef struct dski_plan_s* dski_plan;       /* points, grid, tile order, spectra  */
+typedef struct dski_precond_s* dski_precond; /* pivots, factor, log det M          */
+typedef void* dski_stream;                   /* a hipStream_t                      */
+
+/* Message of the last error on this thread ("" if none). */
+const char* dski_last_error(void);
+
+/* Build version string (library build identifier). */
+const char* dski_version(void);
+
+/* Create a D-SKI plan for n points in d = 1..3 dimensions (Sec. 3.1).
+ *   X        : n x d row-major FP64 point coordinates (device).
+ *   grid_m   : d grid sizes m_p >= 4 (host).
+ *   lo, hi   : data box per axis (host, FP64).  The grid is h_p =
+ *              (hi_p - lo_p)/(m_p - 3), first node lo_p - h_p, so every point
+ *              of the box has its 4-node stencil inside the grid.  NULL for
+ *              both = the bounding box of X.
+ * Setup (per data set, independent of the hyper-parameters): cell index and
+ * offsets of every point, points sorted by cell ("tile order"), per-axis FFT
+ * sizes.  Points outside the box give DSKI_EINVAL.  Hyper-parameters start at
+ * log ell = log s = 0, log sigma = log 0.1; call dski_set_hypers. */
+dski_status dski_plan_create(dski_plan* out, int n, int d, const double* X,
+                             const int* grid_m_host, const double* lo_host,
+                             const double* hi_host, dski_stream stream);
+dski_status dski_plan_destroy(dski_plan plan);
+
+/* Plan geometry: n, d, N, total grid nodes, and per axis (d entries each)
+ * the grid size, circulant FFT length, grid spacing and first node. */
+dski_status dski_plan_info(dski_plan plan, int* n, int* d, int* N, long long* grid_nodes,
+                           int* m_host, int* fft_len_host, double* h_host, double* lo_host);
+
+/* Set hyper-parameters (natural logs; log_ell has d entries).  Recomputes the
+ * circulant eigenvalues of every Toeplitz factor of K_UU on the device. */
+dski_status dski_set_hypers(dski_plan plan, const double* log_ell_host, double log_s,
+                            double log_sigma_f, double log_sigma_g, dski_stream stream);
+
+/* Y = K~ V for R vectors (user order).  V and Y must not overlap. */
+dski_status dski_mvm(dski_plan plan, int R, const float* V, int ldv, float* Y, int ldy,
+                     dski_stream stream);
+
+/* Y = (d K~ / d theta_which) V, which = 0..d+2 in hyper-parameter order
+ * (derivative of the approximate kernel, Sec. 3: weights fixed). */
+dski_status dski_mvm_dtheta(dski_plan plan, int which, int R, const float* V, int ldv,
+                            float* Y, int ldy, dski_stream stream);
+
+/* Tile order: the internal point order (sorted by interpolation cell) that the
+ * solvers use.  dir = +1: user -> tile, dir = -1: tile -> user.  perm_host (n
+ * ints, may be NULL) receives, for tile position k, the user index. */
+dski_status dski_permute(dski_plan plan, int dir, int R, const float* in, int ldi, float* out,
+                         int ldo, dski_stream stream);
+dski_status dski_tile_order(dski_plan plan, int* perm_host);
+
+/* Y = K~ V on tile-ordered vectors (the product the PCG iterations run). */
+dski_status dski_mvm_tiled(dski_plan plan, int R, const float* V, int ldv, float* Y, int ldy,
+                           dski_stream stream);
+
+/* Truncated pivoted Cholesky of the noise-free K (Sec. 3.3; greedy largest
+ * residual diagonal, lowest index among exact ties) and the preconditioner
+ * M = D + L L^T in square-root form.  rank_host receives the rank reached
+ * (< k when the largest residual diagonal fell below 1e-12 x the largest
+ * initial one: DSKI_RANK_TRUNCATED).  piv_host (k ints, user-order indices
+ * into the N-vector, may be NULL) receives the pivots. */
+dski_status pivchol_build(dski_plan plan, int k, dski_precond* out, int* rank_host,
+                          int* piv_host, dski_stream stream);
+dski_status dski_precond_destroy(dski_precond pc);
+
+/* Z = M^{-1} R for R vectors (user order), stable form of Sec. 3.3. */
+dski_status dski_precond_apply(dski_precond pc, int R, const float* Rm, int ld, float* Z,
+                               int ldz, dski_stream stream);
+
+/* log det M (host FP64). */
+dski_status dski_precond_logdet(dski_precond pc, double* out_host);
+
+/* Copy the rank-r factor L (N x r, column-major, user order, FP64) to the
+ * device buffer Lout (ld >= N). */
+dski_status dski_precond_factor(dski_precond pc, double* Lout, int ld, dski_stream stream);
+
+/* Preconditioned CG on the R columns of B independently (they share every
+ * MVM, not their Krylov spaces), x_0 = 0 (Sec. 2, Sec. 3.3).  Column c stops
+ * when ||r||_2 <= tol_host[c] ||b_c||_2 (recurrence residual).
+ *   pc        : NULL = no preconditioner.
+ *   iters_host, relres_host : R entries each (may be NULL).
+ *   alpha_beta: NULL or a device FP64 buffer of 2*max_iter*R entries that
+ *               receives alpha_j (column c at [c*max_iter + j]) and beta_j (at
+ *               [R*max_iter + c*max_iter + j]) for the Lanczos tridiagonal.
+ * Returns DSKI_NOT_CONVERGED if a column reached max_iter. */
+dski_status pcg_solve(dski_plan plan, dski_precond pc, int R, const float* B, int ldb,
+                      float* X, int ldx, const double* tol_host, int max_iter,
+                      int* iters_host, double* relres_host, double* alpha_beta,
+                      dski_stream stream);
+
+/* Stochastic Lanczos quadrature estimate of log det K~ (Sec. 2).  Probe i is
+ * z_i = C w_i with w_i the Rademacher column i of the SplitMix64 stream
+ * `seed` (see dski_rademacher) and C C^T = M (plain w_i when pc is NULL).
+ * lanczos_steps > 0: that many PCG/Lanczos steps per probe; 0: to tol.
+ * logdet = log det M + (1/t) sum_i (z_i^T M^{-1} z_i) e_1^T log(T_i) e_1. */
+dski_status slq_logdet(dski_plan plan, dski_precond pc, int num_probes, int lanczos_steps,
+                       double tol, int max_iter, uint64_t seed, double* logdet_host,
+                       double* stderr_host, dski_stream stream);
+
+/* Log marginal likelihood eq. (1) and its gradient (d+3 entries, hyper-
+ * parameter order) at the plan's current hyper-parameters.  One PCG on
+ * [y, z_1..z_t]; log det by SLQ from the same run; the trace terms
+ * tr(K~^{-1} dK~) by E[(K~^{-1} z)^T dK~ (M^{-1} z)].  pc NULL: build rank k.
+ * y is an N-vector in user order. */
+dski_status mll_and_grad(dski_plan plan, dski_precond pc, int k, const float* y,
+                         int num_probes, uint64_t seed, double tol, int max_iter,
+                         double* mll_host, double* grad_host, double* logdet_host,
+                         int* iters_host, dski_stream stream);
+
+/* out[c*ld + i] = +-1 (FP32): Rademacher column col0+c of the counter-based
+ * SplitMix64 stream `seed` (Steele et al. 2014): entry i of column c is -1
+ * iff bit 63 of mix64(seed + (c*N + i + 1) * 0x9E3779B97F4A7C15) is set. */
+dski_status dski_rademacher(uint64_t seed, int col0, int ncols, int N, float* out, int ld,
+                            dski_stream stream);
+
+/* Host utility: e_1^T log(T) e_1 for the Lanczos tridiagonal of J CG steps with
+ * coefficients alpha, beta (host arrays, as returned by pcg_solve):
+ * T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} = sqrt(beta_j)/alpha_j
+ * (Gauss quadrature of Sec. 2's Lanczos connection).  *ok = 0 if a Ritz value
+ * is not positive or the eigen-iteration fails. */
+double dski_lanczos_quad_log(const double* alpha_host, const double* beta_host, int J, int* ok);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSKI_H */

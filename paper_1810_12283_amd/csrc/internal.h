@@ -1,0 +1,143 @@
+// Internal declarations of the D-SKI library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dski.h"
+
+#define DSKI_MAXD 3
+
+namespace dski {
+
+void set_error(const char* fmt, ...);
+
+struct HipError {
+  hipError_t e;
+};
+
+#define DSKI_HIP(call)                                                                  \
+  do {                                                                                  \
+    hipError_t _e = (call);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      ::dski::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), __FILE__, \
+                        __LINE__);                                                      \
+      return DSKI_EHIP;                                                                 \
+    }                                                                                   \
+  } while (0)
+
+#define DSKI_TRY(call)                 \
+  do {                                 \
+    dski_status _s = (call);           \
+    if (_s < 0) return _s;             \
+  } while (0)
+
+// Device buffer that grows on demand (contents not preserved on growth).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  dski_status reserve(size_t want);
+  void release();
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-axis geometry of the grid and its circulant embedding.
+struct Axis {
+  int m = 0;          // grid nodes
+  int ncell = 0;      // interpolation cells = m - 3
+  int L = 0;          // circulant length (power of two >= 2m - 1)
+  double lo = 0, h = 0;
+  double* twiddle = nullptr;  // L complex e^{-2 pi i t / L} (device, interleaved cos, -sin)
+  double* spec = nullptr;     // L circulant eigenvalues of T_p, scaled (device)
+  double* dspec = nullptr;    // L eigenvalues of dT_p / dlog ell_p, scaled (device)
+  double* col = nullptr;      // m first column of T_p (device)
+};
+
+}  // namespace dski
+
+struct dski_plan_s {
+  int n = 0, d = 0, N = 0;
+  long long M = 0;             // grid nodes
+  int ncells = 0;              // total interpolation cells
+  dski::Axis ax[DSKI_MAXD];
+  // hyper-parameters
+  double ell[DSKI_MAXD] = {1, 1, 1};
+  double s = 1, sf = 0.1, sg = 0.1;
+  // point data in tile order (device)
+  int* perm = nullptr;         // tile position -> user index
+  int* cell = nullptr;         // linear cell id per tile position
+  float* toff = nullptr;       // d x n offsets in [0, 1] (SoA)
+  int* cell_start = nullptr;   // ncells + 1
+  // workspaces
+  dski::DevBuf grid;           // FP64 grid buffer, M * Rmax
+  dski::DevBuf vin, vout;      // tile-ordered FP32 vectors
+  dski::DevBuf partial;        // FP64 block partials
+  dski::DevBuf scal;           // FP64 small scalars
+};
+
+struct dski_precond_s {
+  dski_plan plan = nullptr;
+  int k = 0;                   // rank
+  double logdet = 0;
+  int* piv_tile = nullptr;     // device, k pivots (tile-order N-index)
+  double* L = nullptr;         // device, N x k FP64 (tile order, column-major)
+  float* U = nullptr;          // device, N x k FP32 left singular vectors of D^{-1/2} L
+  double* c = nullptr;         // device, k: 1 - (1 + sigma_i^2)^{-1/2}
+  double* rootc = nullptr;     // device, k: sqrt(1 + sigma_i^2) - 1
+  dski::DevBuf work;
+};
+
+namespace dski {
+
+constexpr int kBlock = 256;
+
+// --- plan / grid ------------------------------------------------------------------
+dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich = -1);
+dski_status scatter(dski_plan p, int R, const float* V, int ldv, double* G, hipStream_t st);
+dski_status gather(dski_plan p, int R, const double* G, const float* V, int ldv, float* Y,
+                   int ldy, double nv, double ng, double* pq_partial, hipStream_t st);
+dski_status mvm_dtheta(dski_plan p, int which, int R, const float* V, int ldv, float* Y, int ldy,
+                       hipStream_t st);
+int gather_blocks(dski_plan p);
+dski_status mvm_tiled(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
+                      double* pq_partial, hipStream_t st);
+dski_status permute(dski_plan p, int dir, int R, const float* in, int ldi, float* out, int ldo,
+                    hipStream_t st);
+
+// --- preconditioner -----------------------------------------------------------------
+// Z = M^{-1} Rm (tile order).  rz_partial (optional): block partials of sum Rm*Z per column.
+dski_status precond_apply_tiled(dski_precond pc, int R, const float* Rm, int ld, float* Z,
+                                int ldz, double* rz_partial, int* nblk_out, hipStream_t st);
+// Z = C W with C C^T = M (tile order).
+dski_status precond_factor_apply_tiled(dski_precond pc, int R, const float* W, int ld, float* Z,
+                                       int ldz, hipStream_t st);
+int vec_blocks(int N);
+
+// --- PCG core (tile order) -----------------------------------------------------------
+struct PcgResult {
+  std::vector<int> iters;
+  std::vector<double> relres;
+  std::vector<double> rz0;     // r_0^T M^{-1} r_0 per column
+  bool breakdown = false;
+};
+dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int ldb, float* X,
+                      int ldx, const double* tol_host, int max_iter, int fixed_iters,
+                      double* alpha_beta, PcgResult& res, hipStream_t st);
+
+// --- host numerics ---------------------------------------------------------------------
+double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok);
+int sym_eig_jacobi(int k, double* A, double* V, double* w);
+
+// --- rng ---------------------------------------------------------------------------------
+dski_status rademacher(uint64_t seed, int col0, int ncols, int N, float* out, int ld,
+                       hipStream_t st);
+
+// deterministic reductions
+dski_status reduce_partials(const double* partial, int nblk, int ncol, double* out,
+                            hipStream_t st);
+
+}  // namespace dski

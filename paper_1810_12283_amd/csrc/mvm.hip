@@ -1,0 +1,633 @@
+// The D-SKI matrix-vector product (Sec. 3.1):
+//     Y = [W; dW_1..dW_d] K_UU [W; dW_1..dW_d]^T V + D V
+// in three stages over tile-ordered vectors:
+//   scatter  G = S^T V      owner-computes: one thread per grid node pulls the
+//                           contributions of the points whose 4^d stencil covers
+//                           it, in a fixed order (no atomics, bitwise
+//                           reproducible), FP64 accumulation;
+//   K_UU     G <- K_UU G    per axis, per grid line: circulant-embedded Toeplitz
+//                           product by an LDS radix-4/2 Stockham FFT (FP64), two
+//                           real lines packed into one complex transform;
+//   gather   Y = S G + D V  one thread per point, FP64 accumulation, FP32 store,
+//                           optional fused per-block partials of V.Y.
+#include <cmath>
+
+#include "internal.h"
+
+namespace dski {
+
+// Keys cubic convolution (a = -1/2) weights of the stencil nodes i-1..i+2 for
+// offset t in [0, 1], and their derivatives with respect to t (divide by h for x).
+__device__ __forceinline__ void keys_weights(double t, double w[4], double dw[4]) {
+  double t2 = t * t, t3 = t2 * t;
+  w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+  w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+  w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+  w[3] = 0.5 * (t3 - t2);
+  dw[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0);
+  dw[1] = 0.5 * (9.0 * t2 - 10.0 * t);
+  dw[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0);
+  dw[3] = 0.5 * (3.0 * t2 - 2.0 * t);
+}
+
+__device__ __forceinline__ double keys_w1(int o, double t) {
+  double t2 = t * t, t3 = t2 * t;
+  switch (o) {
+    case 0: return 0.5 * (-t3 + 2.0 * t2 - t);
+    case 1: return 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    case 2: return 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    default: return 0.5 * (t3 - t2);
+  }
+}
+
+__device__ __forceinline__ double keys_dw1(int o, double t) {
+  double t2 = t * t;
+  switch (o) {
+    case 0: return 0.5 * (-3.0 * t2 + 4.0 * t - 1.0);
+    case 1: return 0.5 * (9.0 * t2 - 10.0 * t);
+    case 2: return 0.5 * (-9.0 * t2 + 8.0 * t + 1.0);
+    default: return 0.5 * (3.0 * t2 - 2.0 * t);
+  }
+}
+
+struct GeoK {
+  int m[DSKI_MAXD];
+  int nc[DSKI_MAXD];
+  double invh[DSKI_MAXD];
+};
+
+static GeoK geo_of(dski_plan p) {
+  GeoK g{};
+  for (int a = 0; a < p->d; ++a) {
+    g.m[a] = p->ax[a].m;
+    g.nc[a] = p->ax[a].ncell;
+    g.invh[a] = 1.0 / p->ax[a].h;
+  }
+  return g;
+}
+
+// ------------------------------------------------------------------ scatter
+// Grid node j receives sum over points k with j in stencil(k) of
+//   w(x_k)_j V_0[k] + sum_q d_q w(x_k)_j V_q[k].
+// Cell c (1-based per axis) covers nodes c-1..c+2, so node j is touched by
+// cells j-2..j+1 (clipped to 1..m-3); its stencil position in cell c is j-c+1.
+template <int D, int RB>
+__global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ cell,
+                                                 const float* __restrict__ toff,
+                                                 const int* __restrict__ cstart, int n, GeoK g,
+                                                 const float* __restrict__ V, int ldv, int r0,
+                                                 int rcount, double* __restrict__ G,
+                                                 long long M) {
+  int j[D];
+  if (D == 1) {
+    j[0] = blockIdx.x * 256 + threadIdx.x;
+    if (j[0] >= g.m[0]) return;
+  } else if (D == 2) {
+    j[1] = blockIdx.x * 16 + (threadIdx.x & 15);
+    j[0] = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (j[0] >= g.m[0] || j[1] >= g.m[1]) return;
+  } else {
+    j[2] = blockIdx.x * 8 + (threadIdx.x & 7);
+    j[1] = (blockIdx.y % ((g.m[1] + 7) / 8)) * 8 + ((threadIdx.x >> 3) & 7);
+    j[0] = (blockIdx.y / ((g.m[1] + 7) / 8)) * 4 + (threadIdx.x >> 6);
+    if (j[0] >= g.m[0] || j[1] >= g.m[1] || j[2] >= g.m[2]) return;
+  }
+  double acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+  int lo[D], hi[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = max(1, j[a] - 2);
+    hi[a] = min(g.nc[a], j[a] + 1);
+  }
+  const int last = D - 1;
+  const float* Vr = V + (size_t)r0 * ldv;
+  // iterate over the outer cell coordinates; the innermost axis is a contiguous run
+  int outer_cnt = 1;
+#pragma unroll
+  for (int a = 0; a < last; ++a) outer_cnt *= (hi[a] >= lo[a] ? hi[a] - lo[a] + 1 : 0);
+  for (int oc = 0; oc < outer_cnt; ++oc) {
+    int c[D];
+    int rem = oc;
+    int base = 0;
+#pragma unroll
+    for (int a = last - 1; a >= 0; --a) {
+      int span = hi[a] - lo[a] + 1;
+      c[a] = lo[a] + rem % span;
+      rem /= span;
+    }
+#pragma unroll
+    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+    base *= g.nc[last];
+    int kb = cstart[base + lo[last] - 1];
+    int ke = cstart[base + hi[last]];
+    for (int k = kb; k < ke; ++k) {
+      int cl = cell[k];
+      int clast = cl % g.nc[last] + 1;
+      double wv[D], wd[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        int ca = (a == last) ? clast : c[a];
+        int o = j[a] - ca + 1;
+        double t = (double)toff[(size_t)a * n + k];
+        wv[a] = keys_w1(o, t);
+        wd[a] = keys_dw1(o, t) * g.invh[a];
+      }
+      double wprod = 1.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) wprod *= wv[a];
+      double dprod[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        double v = 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) v *= (a == q) ? wd[a] : wv[a];
+        dprod[q] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (r < rcount) {
+          const float* vv = Vr + (size_t)r * ldv + k;
+          double a = wprod * (double)vv[0];
+#pragma unroll
+          for (int q = 0; q < D; ++q) a += dprod[q] * (double)vv[(size_t)(q + 1) * n];
+          acc[r] += a;
+        }
+      }
+    }
+  }
+  long long node = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+    if (r < rcount) G[(size_t)(r0 + r) * M + node] = acc[r];
+}
+
+template <int D>
+static void launch_scatter(dski_plan p, int R, const float* V, int ldv, double* G,
+                           hipStream_t st) {
+  GeoK g = geo_of(p);
+  dim3 grid;
+  if (D == 1) grid = dim3((g.m[0] + 255) / 256);
+  if (D == 2) grid = dim3((g.m[1] + 15) / 16, (g.m[0] + 15) / 16);
+  if (D == 3) grid = dim3((g.m[2] + 7) / 8, ((g.m[1] + 7) / 8) * ((g.m[0] + 3) / 4));
+  constexpr int RB = 8;
+  for (int r0 = 0; r0 < R; r0 += RB) {
+    int rc = R - r0 < RB ? R - r0 : RB;
+    k_scatter<D, RB><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv, r0,
+                                           rc, G, p->M);
+  }
+}
+
+dski_status scatter(dski_plan p, int R, const float* V, int ldv, double* G, hipStream_t st) {
+  if (R <= 0) return DSKI_OK;
+  switch (p->d) {
+    case 1: launch_scatter<1>(p, R, V, ldv, G, st); break;
+    case 2: launch_scatter<2>(p, R, V, ldv, G, st); break;
+    case 3: launch_scatter<3>(p, R, V, ldv, G, st); break;
+    default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
+  }
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+// ------------------------------------------------------------------ K_UU by FFT
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// One Stockham pass (radix 4 or 2) over a length-L sequence handled by `tpp`
+// threads (lane = 0..tpp-1); dir = +1 forward (e^{-2 pi i/L}), -1 inverse.
+__device__ __forceinline__ void stockham_pass(const double2* __restrict__ in,
+                                              double2* __restrict__ out, int L, int Ns,
+                                              int radix, const double2* __restrict__ tw,
+                                              int lane, int tpp, int dir) {
+  if (radix == 4) {
+    int q = L >> 2;
+    int tstep = L / (4 * Ns);
+    for (int jj = lane; jj < q; jj += tpp) {
+      double2 v0 = in[jj], v1 = in[jj + q], v2 = in[jj + 2 * q], v3 = in[jj + 3 * q];
+      int k = jj & (Ns - 1);
+      if (Ns > 1) {
+        double2 w1 = tw[k * tstep], w2 = tw[2 * k * tstep], w3 = tw[3 * k * tstep];
+        if (dir > 0) {
+          v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
+        } else {
+          v1 = cmulc(v1, w1); v2 = cmulc(v2, w2); v3 = cmulc(v3, w3);
+        }
+      }
+      double2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), a3 = csub(v1, v3);
+      // -i * a3 = (a3.y, -a3.x); +i * a3 = (-a3.y, a3.x)
+      double2 ma3 = dir > 0 ? make_double2(a3.y, -a3.x) : make_double2(-a3.y, a3.x);
+      int o = (jj / Ns) * 4 * Ns + k;
+      out[o] = cadd(a0, a2);
+      out[o + Ns] = cadd(a1, ma3);
+      out[o + 2 * Ns] = csub(a0, a2);
+      out[o + 3 * Ns] = csub(a1, ma3);
+    }
+  } else {
+    int q = L >> 1;
+    int tstep = L / (2 * Ns);
+    for (int jj = lane; jj < q; jj += tpp) {
+      double2 v0 = in[jj], v1 = in[jj + q];
+      int k = jj & (Ns - 1);
+      if (Ns > 1) v1 = dir > 0 ? cmul(v1, tw[k * tstep]) : cmulc(v1, tw[k * tstep]);
+      int o = (jj / Ns) * 2 * Ns + k;
+      out[o] = cadd(v0, v1);
+      out[o + Ns] = csub(v0, v1);
+    }
+  }
+}
+
+// Toeplitz product along one axis for all grid lines of R columns.  Each line
+// (m values at stride `inner`) is zero-padded to L, transformed, multiplied by the
+// circulant eigenvalues `spec` (already scaled by 1/L) and transformed back; two
+// lines share one complex FFT (real and imaginary parts), which is exact because
+// the spectrum is real and even.
+template <int PPB>
+__global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long long nlines, int m,
+                                                  int L, long long inner,
+                                                  const double2* __restrict__ tw,
+                                                  const double* __restrict__ spec) {
+  extern __shared__ double2 smem[];
+  constexpr int TPP = 256 / PPB;
+  const int pr = threadIdx.x / TPP;
+  const int lane = threadIdx.x % TPP;
+  double2* bufA = smem;                  // PPB * L
+  double2* bufB = smem + (size_t)PPB * L;  // PPB * L
+  const long long line0 = (long long)blockIdx.x * (2 * PPB);
+  const long long linestride = (long long)m * inner;
+  // cooperative load (zero padding beyond m)
+  for (int f = threadIdx.x; f < PPB * L; f += 256) bufA[f] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const int nl = 2 * PPB;
+  if (inner > 1) {
+    for (int f = threadIdx.x; f < nl * m; f += 256) {
+      int l = f % nl, jj = f / nl;
+      long long line = line0 + l;
+      if (line < nlines) {
+        double v = G[(line / inner) * linestride + line % inner + (long long)jj * inner];
+        double* dst = reinterpret_cast<double*>(&bufA[(size_t)(l >> 1) * L + jj]);
+        dst[l & 1] = v;
+      }
+    }
+  } else {
+    for (int f = threadIdx.x; f < nl * m; f += 256) {
+      int jj = f % m, l = f / m;
+      long long line = line0 + l;
+      if (line < nlines) {
+        double v = G[line * m + jj];
+        double* dst = reinterpret_cast<double*>(&bufA[(size_t)(l >> 1) * L + jj]);
+        dst[l & 1] = v;
+      }
+    }
+  }
+  __syncthreads();
+  double2* a = bufA + (size_t)pr * L;
+  double2* b = bufB + (size_t)pr * L;
+  // forward
+  int Ns = 1;
+  while (Ns < L) {
+    int radix = ((L / Ns) % 4 == 0) ? 4 : 2;
+    stockham_pass(a, b, L, Ns, radix, tw, lane, TPP, +1);
+    __syncthreads();
+    double2* t = a; a = b; b = t;
+    Ns *= radix;
+  }
+  for (int kk = lane; kk < L; kk += TPP) {
+    double s = spec[kk];
+    a[kk] = make_double2(a[kk].x * s, a[kk].y * s);
+  }
+  __syncthreads();
+  Ns = 1;
+  while (Ns < L) {
+    int radix = ((L / Ns) % 4 == 0) ? 4 : 2;
+    stockham_pass(a, b, L, Ns, radix, tw, lane, TPP, -1);
+    __syncthreads();
+    double2* t = a; a = b; b = t;
+    Ns *= radix;
+  }
+  // `a` now holds the result for this pair; the final buffer is the same for all pairs
+  double2* res = a - (size_t)pr * L;  // base of the result buffer (A or B)
+  if (inner > 1) {
+    for (int f = threadIdx.x; f < nl * m; f += 256) {
+      int l = f % nl, jj = f / nl;
+      long long line = line0 + l;
+      if (line < nlines) {
+        const double* src = reinterpret_cast<const double*>(&res[(size_t)(l >> 1) * L + jj]);
+        G[(line / inner) * linestride + line % inner + (long long)jj * inner] = src[l & 1];
+      }
+    }
+  } else {
+    for (int f = threadIdx.x; f < nl * m; f += 256) {
+      int jj = f % m, l = f / m;
+      long long line = line0 + l;
+      if (line < nlines) {
+        const double* src = reinterpret_cast<const double*>(&res[(size_t)(l >> 1) * L + jj]);
+        G[line * m + jj] = src[l & 1];
+      }
+    }
+  }
+}
+
+// G <- K_UU G for R columns; dwhich = p (0..d-1) uses d T_p / dlog ell_p on axis p.
+dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich) {
+  if (R <= 0) return DSKI_OK;
+  long long inner = p->M;
+  for (int a = 0; a < p->d; ++a) {
+    const Axis& A = p->ax[a];
+    inner /= A.m;
+    long long nlines = (long long)R * (p->M / A.m);
+    const double* spec = (a == dwhich) ? A.dspec : A.spec;
+    const double2* tw = reinterpret_cast<const double2*>(A.twiddle);
+    int L = A.L;
+    if (L <= 512) {
+      constexpr int PPB = 4;
+      size_t sh = sizeof(double2) * 2 * PPB * L;
+      long long blocks = (nlines + 2 * PPB - 1) / (2 * PPB);
+      k_toeplitz<PPB><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
+    } else if (L <= 1024) {
+      constexpr int PPB = 2;
+      size_t sh = sizeof(double2) * 2 * PPB * L;
+      long long blocks = (nlines + 2 * PPB - 1) / (2 * PPB);
+      k_toeplitz<PPB><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
+    } else if (L <= 2048) {
+      constexpr int PPB = 1;
+      size_t sh = sizeof(double2) * 2 * PPB * L;
+      long long blocks = (nlines + 2 * PPB - 1) / (2 * PPB);
+      k_toeplitz<PPB><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
+    } else {
+      set_error("FFT length %d not supported (grid size per axis <= 1024)", L);
+      return DSKI_ENOTSUP;
+    }
+    DSKI_HIP(hipGetLastError());
+  }
+  return DSKI_OK;
+}
+
+// ------------------------------------------------------------------ gather + noise
+template <int D, int RB>
+__global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
+                                                const float* __restrict__ toff, int n, GeoK g,
+                                                const double* __restrict__ G, long long M,
+                                                const float* __restrict__ V, int ldv,
+                                                float* __restrict__ Y, int ldy, int r0,
+                                                int rcount, double nv, double ng,
+                                                double* __restrict__ pq_partial, int R) {
+  int k = blockIdx.x * 256 + threadIdx.x;
+  double pq[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) pq[r] = 0.0;
+  if (k < n) {
+    int cl = cell[k];
+    int c[D];
+    {
+      int rem = cl;
+#pragma unroll
+      for (int a = D - 1; a >= 0; --a) {
+        c[a] = rem % g.nc[a] + 1;
+        rem /= g.nc[a];
+      }
+    }
+    double w[D][4], dw[D][4];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      keys_weights((double)toff[(size_t)a * n + k], w[a], dw[a]);
+#pragma unroll
+      for (int o = 0; o < 4; ++o) dw[a][o] *= g.invh[a];
+    }
+    long long base = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) base = base * g.m[a] + (c[a] - 1);
+    long long stride[D];
+    stride[D - 1] = 1;
+#pragma unroll
+    for (int a = D - 2; a >= 0; --a) stride[a] = stride[a + 1] * g.m[a + 1];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (r < rcount) {
+        const double* Gr = G + (size_t)(r0 + r) * M + base;
+        double acc[D + 1];
+#pragma unroll
+        for (int q = 0; q <= D; ++q) acc[q] = 0.0;
+        if (D == 1) {
+#pragma unroll
+          for (int o0 = 0; o0 < 4; ++o0) {
+            double gv = Gr[o0];
+            acc[0] += w[0][o0] * gv;
+            acc[1] += dw[0][o0] * gv;
+          }
+        } else if (D == 2) {
+#pragma unroll
+          for (int o0 = 0; o0 < 4; ++o0) {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int o1 = 0; o1 < 4; ++o1) {
+              double gv = Gr[o0 * stride[0] + o1];
+              s0 += w[D - 1][o1] * gv;
+              s1 += dw[D - 1][o1] * gv;
+            }
+            acc[0] += w[0][o0] * s0;
+            acc[1] += dw[0][o0] * s0;
+            acc[2] += w[0][o0] * s1;
+          }
+        } else {
+#pragma unroll
+          for (int o0 = 0; o0 < 4; ++o0) {
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0;  // value, d/dx1, d/dx2 over axes 1,2
+#pragma unroll
+            for (int o1 = 0; o1 < 4; ++o1) {
+              double s0 = 0.0, s2 = 0.0;
+#pragma unroll
+              for (int o2 = 0; o2 < 4; ++o2) {
+                double gv = Gr[o0 * stride[0] + o1 * stride[1] + o2];
+                s0 += w[D - 1][o2] * gv;
+                s2 += dw[D - 1][o2] * gv;
+              }
+              t0 += w[1][o1] * s0;
+              t1 += dw[1][o1] * s0;
+              t2 += w[1][o1] * s2;
+            }
+            acc[0] += w[0][o0] * t0;
+            acc[1] += dw[0][o0] * t0;
+            acc[2] += w[0][o0] * t1;
+            acc[3] += w[0][o0] * t2;
+          }
+        }
+        const float* vv = V + (size_t)(r0 + r) * ldv + k;
+        float* yy = Y + (size_t)(r0 + r) * ldy + k;
+        double dot = 0.0;
+#pragma unroll
+        for (int q = 0; q <= D; ++q) {
+          double vin = (double)vv[(size_t)q * n];
+          float out = (float)(acc[q] + (q == 0 ? nv : ng) * vin);
+          yy[(size_t)q * n] = out;
+          dot += vin * (double)out;
+        }
+        pq[r] = dot;
+      }
+    }
+  }
+  if (pq_partial) {
+    __shared__ double red[RB][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      double v = pq[r];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) red[r][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < RB && threadIdx.x < rcount) {
+      int r = threadIdx.x;
+      pq_partial[(size_t)blockIdx.x * R + r0 + r] = red[r][0] + red[r][1] + red[r][2] + red[r][3];
+    }
+  }
+}
+
+int gather_blocks(dski_plan p) { return (p->n + 255) / 256; }
+
+template <int D>
+static void launch_gather(dski_plan p, int R, const double* G, const float* V, int ldv, float* Y,
+                          int ldy, double nv, double ng, double* pq_partial, hipStream_t st) {
+  GeoK g = geo_of(p);
+  constexpr int RB = 8;
+  int blocks = gather_blocks(p);
+  for (int r0 = 0; r0 < R; r0 += RB) {
+    int rc = R - r0 < RB ? R - r0 : RB;
+    k_gather<D, RB><<<blocks, 256, 0, st>>>(p->cell, p->toff, p->n, g, G, p->M, V, ldv, Y, ldy, r0,
+                                            rc, nv, ng, pq_partial, R);
+  }
+}
+
+dski_status gather(dski_plan p, int R, const double* G, const float* V, int ldv, float* Y,
+                           int ldy, double nv, double ng, double* pq_partial, hipStream_t st) {
+  if (R <= 0 || p->n == 0) return DSKI_OK;
+  switch (p->d) {
+    case 1: launch_gather<1>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 2: launch_gather<2>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 3: launch_gather<3>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
+  }
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+dski_status mvm_tiled(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
+                      double* pq_partial, hipStream_t st) {
+  if (R <= 0) return DSKI_OK;
+  DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
+  double* G = p->grid.as<double>();
+  DSKI_TRY(scatter(p, R, V, ldv, G, st));
+  DSKI_TRY(apply_kuu(p, R, G, st));
+  return gather(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, pq_partial, st);
+}
+
+__global__ void k_noise_deriv(const float* __restrict__ V, int ldv, float* __restrict__ Y,
+                              int ldy, int n, int N, int R, double cv, double cg) {
+  size_t tot = (size_t)N * R;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int i = (int)(e % N);
+    int r = (int)(e / N);
+    double c = i < n ? cv : cg;
+    Y[(size_t)r * ldy + i] = (float)(c * (double)V[(size_t)r * ldv + i]);
+  }
+}
+
+static dski_status mvm_dtheta_tiled(dski_plan p, int which, int R, const float* V, int ldv,
+                                    float* Y, int ldy, hipStream_t st) {
+  if (R <= 0) return DSKI_OK;
+  int d = p->d;
+  if (which <= d) {
+    DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
+    double* G = p->grid.as<double>();
+    DSKI_TRY(scatter(p, R, V, ldv, G, st));
+    DSKI_TRY(apply_kuu(p, R, G, st, which < d ? which : -1));
+    // d K_UU / d log s = 2 K_UU: fold the factor 2 into the gather via a second pass
+    DSKI_TRY(gather(p, R, G, V, ldv, Y, ldy, 0.0, 0.0, nullptr, st));
+    if (which == d) {
+      size_t tot = (size_t)p->N * R;
+      int blocks = (int)std::min<size_t>((tot + 255) / 256, 65535 * 8);
+      k_noise_deriv<<<blocks, 256, 0, st>>>(Y, ldy, Y, ldy, p->N, p->N, R, 2.0, 2.0);
+      DSKI_HIP(hipGetLastError());
+    }
+    return DSKI_OK;
+  }
+  double cv = which == d + 1 ? 2.0 * p->sf * p->sf : 0.0;
+  double cg = which == d + 2 ? 2.0 * p->sg * p->sg : 0.0;
+  size_t tot = (size_t)p->N * R;
+  int blocks = (int)std::min<size_t>((tot + 255) / 256, 65535 * 8);
+  k_noise_deriv<<<blocks, 256, 0, st>>>(V, ldv, Y, ldy, p->n, p->N, R, cv, cg);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+dski_status mvm_dtheta(dski_plan p, int which, int R, const float* V, int ldv, float* Y, int ldy,
+                       hipStream_t st) {
+  return mvm_dtheta_tiled(p, which, R, V, ldv, Y, ldy, st);
+}
+
+}  // namespace dski
+
+using namespace dski;
+
+static dski_status check_mvm_args(dski_plan p, int R, const void* V, int ldv, const void* Y,
+                                  int ldy) {
+  if (!p || R < 0 || (R > 0 && (!V || !Y)) || ldv < p->N || ldy < p->N) {
+    set_error("bad MVM arguments (R=%d, ldv=%d, ldy=%d, N=%d)", R, ldv, ldy, p ? p->N : -1);
+    return DSKI_EINVAL;
+  }
+  return DSKI_OK;
+}
+
+extern "C" {
+
+dski_status dski_mvm_tiled(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
+                           dski_stream stream) {
+  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
+  return mvm_tiled(p, R, V, ldv, Y, ldy, nullptr, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_mvm(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
+                     dski_stream stream) {
+  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
+  if (R == 0 || p->N == 0) return DSKI_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  size_t nr = (size_t)p->N * R;
+  DSKI_TRY(p->vin.reserve(sizeof(float) * nr));
+  DSKI_TRY(p->vout.reserve(sizeof(float) * nr));
+  float* vi = p->vin.as<float>();
+  float* vo = p->vout.as<float>();
+  DSKI_TRY(permute(p, +1, R, V, ldv, vi, p->N, st));
+  DSKI_TRY(mvm_tiled(p, R, vi, p->N, vo, p->N, nullptr, st));
+  return permute(p, -1, R, vo, p->N, Y, ldy, st);
+}
+
+dski_status dski_mvm_dtheta(dski_plan p, int which, int R, const float* V, int ldv, float* Y,
+                            int ldy, dski_stream stream) {
+  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
+  if (which < 0 || which > p->d + 2) {
+    set_error("which=%d out of range 0..%d", which, p->d + 2);
+    return DSKI_EINVAL;
+  }
+  if (R == 0 || p->N == 0) return DSKI_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  size_t nr = (size_t)p->N * R;
+  DSKI_TRY(p->vin.reserve(sizeof(float) * nr));
+  DSKI_TRY(p->vout.reserve(sizeof(float) * nr));
+  float* vi = p->vin.as<float>();
+  float* vo = p->vout.as<float>();
+  DSKI_TRY(permute(p, +1, R, V, ldv, vi, p->N, st));
+  DSKI_TRY(mvm_dtheta(p, which, R, vi, p->N, vo, p->N, st));
+  return permute(p, -1, R, vo, p->N, Y, ldy, st);
+}
+
+}  // extern "C"

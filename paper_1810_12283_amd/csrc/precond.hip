@@ -1,0 +1,698 @@
+// Truncated pivoted Cholesky of the noise-free D-SKI matrix and the
+// preconditioner M = D + L L^T (Sec. 3.3).
+//
+// Diagonal and rows use the separable form of the D-SKI entries (the D-SKI
+// matrix of a product kernel is a Hadamard product of 1-D SKI factors,
+// Sec. 3.2):  K[(a,i),(b,j)] = s^2 prod_p  w_p^{(a)}(x_ip)^T T_p w_p^{(b)}(x_jp),
+// where w_p^{(a)} are the 4 value weights, or derivative weights when block a
+// is the derivative along axis p.  A row costs O(N d 4 + sum_p m_p), the
+// diagonal O(N d 16).
+//
+// Greedy pivoting on the largest residual diagonal entry, lowest index among
+// exact ties; every step runs on the device (no host round trip per pivot).
+//
+// The preconditioner is kept in square-root form: with G = D^{-1/2} L = U S V^T,
+//   M^{-1} = D^{-1/2} B B D^{-1/2},  B = I - U diag(c) U^T,  c = 1 - (1 + s^2)^{-1/2},
+// which stays positive definite when U is stored in FP32 (B is applied twice),
+// and C = D^{1/2} (I + U diag(sqrt(1 + s^2) - 1) U^T) satisfies C C^T = M.
+// log det M = sum log D_ii + sum log(1 + s_i^2).
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace dski {
+
+struct GeoP {
+  int d, n, N;
+  int m[DSKI_MAXD];
+  int nc[DSKI_MAXD];
+  double invh[DSKI_MAXD];
+  const double* col[DSKI_MAXD];  // first column of T_p (unscaled)
+  double s2;
+};
+
+static GeoP geop_of(dski_plan p) {
+  GeoP g{};
+  g.d = p->d;
+  g.n = p->n;
+  g.N = p->N;
+  for (int a = 0; a < p->d; ++a) {
+    g.m[a] = p->ax[a].m;
+    g.nc[a] = p->ax[a].ncell;
+    g.invh[a] = 1.0 / p->ax[a].h;
+    g.col[a] = p->ax[a].col;
+  }
+  g.s2 = p->s * p->s;
+  return g;
+}
+
+__device__ __forceinline__ void kw(double t, bool deriv, double invh, double w[4]) {
+  double t2 = t * t, t3 = t2 * t;
+  if (!deriv) {
+    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+  } else {
+    w[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0) * invh;
+    w[1] = 0.5 * (9.0 * t2 - 10.0 * t) * invh;
+    w[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0) * invh;
+    w[3] = 0.5 * (3.0 * t2 - 2.0 * t) * invh;
+  }
+}
+
+__device__ __forceinline__ void cell_coords(int cl, const GeoP& g, int c[DSKI_MAXD]) {
+  for (int a = g.d - 1; a >= 0; --a) {
+    c[a] = cl % g.nc[a] + 1;
+    cl /= g.nc[a];
+  }
+}
+
+// diag[e] for e = blk * n + k (tile order)
+__global__ void k_pc_diag(GeoP g, const int* __restrict__ cell, const float* __restrict__ toff,
+                          double* __restrict__ diag) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.N) return;
+  int blk = e / g.n, k = e % g.n;
+  double v = g.s2;
+  for (int a = 0; a < g.d; ++a) {
+    double w[4];
+    kw((double)toff[(size_t)a * g.n + k], blk == a + 1, g.invh[a], w);
+    double q = 0.0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) q += w[i] * g.col[a][i > j ? i - j : j - i] * w[j];
+    v *= q;
+  }
+  diag[e] = v;
+}
+
+struct PivState {
+  int piv;        // chosen tile-order N-index
+  int stop;       // 1 once the factorisation has stopped
+  int rank;       // columns produced
+  double dpiv;    // residual diagonal at the pivot
+  double dmax0;   // largest initial diagonal
+};
+
+// Block-wise arg-max of the residual diagonal (ties -> lowest index).
+__global__ void k_argmax_partial(const double* __restrict__ dres, int N, double* __restrict__ pv,
+                                 int* __restrict__ pi) {
+  __shared__ double sv[kBlock];
+  __shared__ int si[kBlock];
+  double best = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x) {
+    double v = dres[e];
+    if (v > best || (v == best && e < bi)) {
+      best = v;
+      bi = e;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      double v = sv[threadIdx.x + off];
+      int i = si[threadIdx.x + off];
+      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
+        sv[threadIdx.x] = v;
+        si[threadIdx.x] = i;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = sv[0];
+    pi[blockIdx.x] = si[0];
+  }
+}
+
+// Final arg-max, stop test, pivot bookkeeping, pivot-row factors a_p and the
+// pivot's row of L.  One work-group.
+__global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int* __restrict__ pi,
+                               int nblk, int j, double rel_tol, PivState* __restrict__ ps,
+                               int* __restrict__ piv_list, const double* __restrict__ dres,
+                               const int* __restrict__ cell, const float* __restrict__ toff,
+                               double* __restrict__ arow, const double* __restrict__ L,
+                               double* __restrict__ lrow) {
+  __shared__ double sv[kBlock];
+  __shared__ int si[kBlock];
+  double best = -INFINITY;
+  int bi = 0x7fffffff;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    double v = pv[b];
+    int i = pi[b];
+    if (v > best || (v == best && i < bi)) {
+      best = v;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      double v = sv[threadIdx.x + off];
+      int i = si[threadIdx.x + off];
+      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
+        sv[threadIdx.x] = v;
+        si[threadIdx.x] = i;
+      }
+    }
+    __syncthreads();
+  }
+  __shared__ int s_stop;
+  __shared__ int s_piv;
+  if (threadIdx.x == 0) {
+    if (j == 0) {
+      ps->dmax0 = sv[0];
+      ps->stop = 0;
+      ps->rank = 0;
+    }
+    int stop = ps->stop;
+    if (!stop && !(sv[0] > rel_tol * ps->dmax0 && sv[0] > 0.0)) stop = 1;
+    ps->stop = stop;
+    s_stop = stop;
+    s_piv = si[0];
+    if (!stop) {
+      ps->piv = si[0];
+      ps->dpiv = sv[0];
+      piv_list[j] = si[0];
+      ps->rank = j + 1;
+    }
+  }
+  __syncthreads();
+  if (s_stop) return;
+  int e = s_piv;
+  int blk = e / g.n, k = e % g.n;
+  int c[DSKI_MAXD];
+  cell_coords(cell[k], g, c);
+  // a_p[u] = sum_o T_p[u, c_p - 1 + o] w_p^{(blk)}(x_kp)[o], u < m_p
+  int off = 0;
+  for (int a = 0; a < g.d; ++a) {
+    double w[4];
+    kw((double)toff[(size_t)a * g.n + k], blk == a + 1, g.invh[a], w);
+    for (int u = threadIdx.x; u < g.m[a]; u += blockDim.x) {
+      double acc = 0.0;
+      for (int o = 0; o < 4; ++o) {
+        int v = c[a] - 1 + o;
+        acc += g.col[a][u > v ? u - v : v - u] * w[o];
+      }
+      arow[off + u] = acc;
+    }
+    off += g.m[a];
+  }
+  for (int l = threadIdx.x; l < j; l += blockDim.x) lrow[l] = L[(size_t)l * g.N + e];
+}
+
+// Column j of L and the residual-diagonal update.
+__global__ void k_pc_column(GeoP g, int j, const PivState* __restrict__ ps,
+                            const int* __restrict__ cell, const float* __restrict__ toff,
+                            const double* __restrict__ arow, const double* __restrict__ lrow,
+                            double* __restrict__ L, double* __restrict__ dres) {
+  if (ps->stop) return;
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.N) return;
+  int blk = e / g.n, k = e % g.n;
+  int c[DSKI_MAXD];
+  cell_coords(cell[k], g, c);
+  double row = g.s2;
+  int off = 0;
+  for (int a = 0; a < g.d; ++a) {
+    double w[4];
+    kw((double)toff[(size_t)a * g.n + k], blk == a + 1, g.invh[a], w);
+    double q = 0.0;
+    for (int o = 0; o < 4; ++o) q += w[o] * arow[off + c[a] - 1 + o];
+    row *= q;
+    off += g.m[a];
+  }
+  double acc = row;
+  for (int l = 0; l < j; ++l) acc -= L[(size_t)l * g.N + e] * lrow[l];
+  double lj = acc / sqrt(ps->dpiv);
+  L[(size_t)j * g.N + e] = lj;
+  double dn = dres[e] - lj * lj;
+  if (e == ps->piv) dn = -INFINITY;
+  dres[e] = dn;
+}
+
+// Gram partials of G = D^{-1/2} L: pairs (i <= j) over a chunk of rows.
+__global__ void k_gram_partial(const double* __restrict__ L, int N, int n, int k, int rows,
+                               double isf, double isg, double* __restrict__ partial) {
+  extern __shared__ double sG[];  // rows x k
+  int r0 = blockIdx.x * rows;
+  int rn = min(rows, N - r0);
+  for (int f = threadIdx.x; f < rows * k; f += blockDim.x) {
+    int i = f / rows, r = f % rows;
+    double v = 0.0;
+    if (r < rn) {
+      int e = r0 + r;
+      v = L[(size_t)i * N + e] * (e < n ? isf : isg);
+    }
+    sG[(size_t)i * rows + r] = v;
+  }
+  __syncthreads();
+  int npair = k * (k + 1) / 2;
+  for (int pidx = threadIdx.x; pidx < npair; pidx += blockDim.x) {
+    // decode pidx -> (i, j), j >= i
+    int i = 0, rem = pidx;
+    while (rem >= k - i) {
+      rem -= k - i;
+      ++i;
+    }
+    int jj = i + rem;
+    double acc = 0.0;
+    for (int r = 0; r < rn; ++r) acc += sG[(size_t)i * rows + r] * sG[(size_t)jj * rows + r];
+    partial[(size_t)blockIdx.x * npair + pidx] = acc;
+  }
+}
+
+// U[:, i] = G V[:, i] / sigma_i  (components with sigma_i = 0 are dropped).
+// (Vs holds V with column i divided by sigma_i; read through the cache, it is
+// the same for every thread.)
+__global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, double isf, double isg,
+                         const double* __restrict__ sV, float* __restrict__ U) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  double sc = e < n ? isf : isg;
+  for (int i = 0; i < k; ++i) {
+    double acc = 0.0;
+    for (int l = 0; l < k; ++l) acc += L[(size_t)l * N + e] * sV[l * k + i];
+    U[(size_t)i * N + e] = (float)(acc * sc);
+  }
+}
+
+// ------------------------------------------------------------------ apply
+// Partials of U^T v over a chunk of rows, with
+//   v = pre_e * X_e - sum_i U[e, i] coef[i, r]   (coef may be NULL).
+constexpr int kProjRC = 16;  // columns per launch
+
+__global__ void k_proj(const float* __restrict__ U, int N, int n, int k, int rows,
+                       const float* __restrict__ X, int ld, int r0, int rc, double pre_v,
+                       double pre_g, const double* __restrict__ coef, int R,
+                       double* __restrict__ partial) {
+  extern __shared__ double sm[];
+  float* sU = reinterpret_cast<float*>(sm);                         // k x rows
+  double* sval = sm + ((size_t)k * rows + 1) / 2;                    // rows x kProjRC
+  double* sco = sval + (size_t)rows * kProjRC;                      // k x kProjRC
+  int e0 = blockIdx.x * rows;
+  int rn = min(rows, N - e0);
+  for (int f = threadIdx.x; f < k * rows; f += blockDim.x) {
+    int i = f / rows, r = f % rows;
+    sU[(size_t)i * rows + r] = r < rn ? U[(size_t)i * N + e0 + r] : 0.0f;
+  }
+  if (coef)
+    for (int f = threadIdx.x; f < k * rc; f += blockDim.x) {
+      int i = f / rc, c = f % rc;
+      sco[i * kProjRC + c] = coef[(size_t)i * R + r0 + c];
+    }
+  __syncthreads();
+  for (int f = threadIdx.x; f < rows * rc; f += blockDim.x) {
+    int r = f % rows, c = f / rows;
+    double v = 0.0;
+    if (r < rn) {
+      int e = e0 + r;
+      v = (e < n ? pre_v : pre_g) * (double)X[(size_t)(r0 + c) * ld + e];
+      if (coef)
+        for (int i = 0; i < k; ++i) v -= (double)sU[(size_t)i * rows + r] * sco[i * kProjRC + c];
+    }
+    sval[(size_t)r * kProjRC + c] = v;
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < k * rc; f += blockDim.x) {
+    int i = f / rc, c = f % rc;
+    double acc = 0.0;
+    for (int r = 0; r < rn; ++r) acc += (double)sU[(size_t)i * rows + r] * sval[(size_t)r * kProjRC + c];
+    partial[(size_t)blockIdx.x * k * R + (size_t)i * R + r0 + c] = acc;
+  }
+}
+
+// out_e = post_e * (pre_e * X_e - sum_i U[e, i] coef[i, r]); optional partials of X.out.
+__global__ void k_pc_final(const float* __restrict__ U, int N, int n, int k, const float* __restrict__ X,
+                           int ld, int R, double pre_v, double pre_g, double post_v, double post_g,
+                           const double* __restrict__ coef, float* __restrict__ out, int ldo,
+                           double* __restrict__ dot_partial) {
+  extern __shared__ double sco[];  // k x R
+  for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
+  __syncthreads();
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  double dot = 0.0;
+  if (e < N) {
+    double pre = e < n ? pre_v : pre_g;
+    double post = e < n ? post_v : post_g;
+    double x = (double)X[(size_t)r * ld + e];
+    double v = pre * x;
+    for (int i = 0; i < k; ++i) v -= (double)U[(size_t)i * N + e] * sco[i * R + r];
+    float o = (float)(post * v);
+    out[(size_t)r * ldo + e] = o;
+    dot = x * (double)o;
+  }
+  if (dot_partial) {
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) dot_partial[(size_t)blockIdx.x * R + r] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+// coef[i, r] = c_i * (t1[i, r] + t2[i, r])  (t2 may be NULL); sign applied by `sgn`.
+__global__ void k_coef(const double* __restrict__ c, const double* __restrict__ t1,
+                       const double* __restrict__ t2, int k, int R, double sgn,
+                       double* __restrict__ coef) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= k * R) return;
+  int i = f / R;
+  double t = t1[f] + (t2 ? t2[f] : 0.0);
+  coef[f] = sgn * c[i] * t;
+}
+
+static int proj_rows(int k) { return k <= 64 ? 128 : 64; }
+
+static size_t proj_lds(int k, int rows) {
+  return sizeof(double) * (((size_t)k * rows + 1) / 2 + (size_t)rows * kProjRC + (size_t)k * kProjRC);
+}
+
+int vec_blocks(int N) { return (N + kBlock - 1) / kBlock; }
+
+// t[k x R] = U^T (pre .* X - U coef)
+static dski_status project(dski_precond pc, int R, const float* X, int ld, double pre_v, double pre_g,
+                           const double* coef, double* partial, double* t, hipStream_t st) {
+  dski_plan p = pc->plan;
+  int k = pc->k, N = p->N;
+  int rows = proj_rows(k);
+  int nblk = (N + rows - 1) / rows;
+  size_t lds = proj_lds(k, rows);
+  for (int r0 = 0; r0 < R; r0 += kProjRC) {
+    int rc = std::min(kProjRC, R - r0);
+    k_proj<<<nblk, kBlock, lds, st>>>(pc->U, N, p->n, k, rows, X, ld, r0, rc, pre_v, pre_g, coef, R,
+                                      partial);
+  }
+  DSKI_HIP(hipGetLastError());
+  return reduce_partials(partial, nblk, k * R, t, st);
+}
+
+static dski_status ensure_work(dski_precond pc, int R, double** partial, double** t1, double** t2,
+                               double** coef) {
+  dski_plan p = pc->plan;
+  int k = pc->k;
+  int rows = proj_rows(k);
+  int nblk = (p->N + rows - 1) / rows;
+  size_t np = std::max((size_t)nblk * k * R, (size_t)vec_blocks(p->N) * R);
+  size_t want = sizeof(double) * (np + 3 * (size_t)k * R + 64);
+  DSKI_TRY(pc->work.reserve(want));
+  double* base = pc->work.as<double>();
+  *partial = base;
+  *t1 = base + np;
+  *t2 = *t1 + (size_t)k * R;
+  *coef = *t2 + (size_t)k * R;
+  return DSKI_OK;
+}
+
+dski_status precond_apply_tiled(dski_precond pc, int R, const float* Rm, int ld, float* Z, int ldz,
+                                double* rz_partial, int* nblk_out, hipStream_t st) {
+  dski_plan p = pc->plan;
+  int k = pc->k, N = p->N;
+  double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
+  if (nblk_out) *nblk_out = vec_blocks(N);
+  if (R <= 0) return DSKI_OK;
+  dim3 fgrid(vec_blocks(N), R);
+  if (k == 0) {
+    k_pc_final<<<fgrid, kBlock, 0, st>>>(pc->U, N, p->n, 0, Rm, ld, R, isf, isg, isf, isg, nullptr, Z,
+                                         ldz, rz_partial);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  }
+  double *partial, *t1, *t2, *coef;
+  DSKI_TRY(ensure_work(pc, R, &partial, &t1, &t2, &coef));
+  int cb = (k * R + kBlock - 1) / kBlock;
+  // t1 = U^T r',  r' = D^{-1/2} Rm
+  DSKI_TRY(project(pc, R, Rm, ld, isf, isg, nullptr, partial, t1, st));
+  k_coef<<<cb, kBlock, 0, st>>>(pc->c, t1, nullptr, k, R, 1.0, coef);
+  // t2 = U^T w,  w = r' - U (c .* t1)
+  DSKI_TRY(project(pc, R, Rm, ld, isf, isg, coef, partial, t2, st));
+  k_coef<<<cb, kBlock, 0, st>>>(pc->c, t1, t2, k, R, 1.0, coef);
+  // Z = D^{-1/2} (r' - U (c .* (t1 + t2)))
+  k_pc_final<<<fgrid, kBlock, sizeof(double) * k * R, st>>>(pc->U, N, p->n, k, Rm, ld, R, isf, isg, isf,
+                                                            isg, coef, Z, ldz, rz_partial);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+dski_status precond_factor_apply_tiled(dski_precond pc, int R, const float* W, int ld, float* Z, int ldz,
+                                       hipStream_t st) {
+  dski_plan p = pc->plan;
+  int k = pc->k, N = p->N;
+  if (R <= 0) return DSKI_OK;
+  dim3 fgrid(vec_blocks(N), R);
+  if (k == 0) {
+    k_pc_final<<<fgrid, kBlock, 0, st>>>(pc->U, N, p->n, 0, W, ld, R, 1.0, 1.0, p->sf, p->sg, nullptr, Z,
+                                         ldz, nullptr);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  }
+  double *partial, *t1, *t2, *coef;
+  DSKI_TRY(ensure_work(pc, R, &partial, &t1, &t2, &coef));
+  int cb = (k * R + kBlock - 1) / kBlock;
+  DSKI_TRY(project(pc, R, W, ld, 1.0, 1.0, nullptr, partial, t1, st));
+  k_coef<<<cb, kBlock, 0, st>>>(pc->rootc, t1, nullptr, k, R, -1.0, coef);
+  k_pc_final<<<fgrid, kBlock, sizeof(double) * k * R, st>>>(pc->U, N, p->n, k, W, ld, R, 1.0, 1.0, p->sf,
+                                                            p->sg, coef, Z, ldz, nullptr);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+static void destroy_pc(dski_precond pc) {
+  if (!pc) return;
+  (void)hipFree(pc->piv_tile);
+  (void)hipFree(pc->L);
+  (void)hipFree(pc->U);
+  (void)hipFree(pc->c);
+  (void)hipFree(pc->rootc);
+  pc->work.release();
+  delete pc;
+}
+
+static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_host, int* piv_host,
+                              hipStream_t st) {
+  int N = p->N, n = p->n;
+  GeoP g = geop_of(p);
+  DSKI_HIP(hipMalloc(&pc->piv_tile, sizeof(int) * std::max(k, 1)));
+  DSKI_HIP(hipMalloc(&pc->L, sizeof(double) * (size_t)N * std::max(k, 1)));
+  // scratch: dres (N), argmax partials, PivState, arow (sum m), lrow (k)
+  int nblk = std::min(1024, std::max(1, (N + kBlock - 1) / kBlock));
+  int msum = 0;
+  for (int a = 0; a < p->d; ++a) msum += p->ax[a].m;
+  size_t bytes = sizeof(double) * ((size_t)N + nblk + msum + k + 8) + sizeof(int) * (nblk + 8) +
+                 sizeof(PivState) + 256;
+  char* scratch = nullptr;
+  DSKI_HIP(hipMalloc(&scratch, bytes));
+  double* dres = reinterpret_cast<double*>(scratch);
+  double* pv = dres + N;
+  double* arow = pv + nblk;
+  double* lrow = arow + msum;
+  PivState* ps = reinterpret_cast<PivState*>(lrow + k + 8);
+  int* pi = reinterpret_cast<int*>(ps + 1);
+  dski_status rc = DSKI_OK;
+  do {
+    int vb = (N + kBlock - 1) / kBlock;
+    k_pc_diag<<<vb, kBlock, 0, st>>>(g, p->cell, p->toff, dres);
+    const double rel_tol = 1e-12;
+    for (int j = 0; j < k; ++j) {
+      k_argmax_partial<<<nblk, kBlock, 0, st>>>(dres, N, pv, pi);
+      k_pivot_select<<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, pc->piv_tile, dres, p->cell,
+                                           p->toff, arow, pc->L, lrow);
+      k_pc_column<<<vb, kBlock, 0, st>>>(g, j, ps, p->cell, p->toff, arow, lrow, pc->L, dres);
+    }
+    if (hipGetLastError() != hipSuccess) {
+      set_error("pivoted Cholesky kernel launch failed");
+      rc = DSKI_EHIP;
+      break;
+    }
+    PivState hps{};
+    if (k > 0) {
+      if (hipMemcpyAsync(&hps, ps, sizeof(PivState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        set_error("pivoted Cholesky synchronisation failed");
+        rc = DSKI_EHIP;
+        break;
+      }
+    }
+    int r = k > 0 ? hps.rank : 0;
+    pc->k = r;
+    if (rank_host) *rank_host = r;
+    if (piv_host && r > 0) {
+      std::vector<int> pt(r), perm(n);
+      if (hipMemcpy(pt.data(), pc->piv_tile, sizeof(int) * r, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(perm.data(), p->perm, sizeof(int) * n, hipMemcpyDeviceToHost) != hipSuccess) {
+        set_error("pivot copy failed");
+        rc = DSKI_EHIP;
+        break;
+      }
+      for (int j = 0; j < r; ++j) {
+        int e = pt[j];
+        piv_host[j] = (e / n) * n + perm[e % n];
+      }
+      for (int j = r; j < k; ++j) piv_host[j] = -1;
+    }
+    // preconditioner: Gram of G = D^{-1/2} L, eigen-decomposition on the host
+    double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
+    double logdetD = (double)n * 2.0 * std::log(p->sf) + (double)(N - n) * 2.0 * std::log(p->sg);
+    DSKI_HIP(hipMalloc(&pc->U, sizeof(float) * (size_t)N * std::max(r, 1)));
+    DSKI_HIP(hipMalloc(&pc->c, sizeof(double) * std::max(r, 1)));
+    DSKI_HIP(hipMalloc(&pc->rootc, sizeof(double) * std::max(r, 1)));
+    if (r == 0) {
+      pc->logdet = logdetD;
+      break;
+    }
+    int rows = std::max(1, 6144 / r);
+    int gb = (N + rows - 1) / rows;
+    int npair = r * (r + 1) / 2;
+    double* gpart = nullptr;
+    DSKI_HIP(hipMalloc(&gpart, sizeof(double) * ((size_t)gb * npair + npair)));
+    k_gram_partial<<<gb, kBlock, sizeof(double) * rows * r, st>>>(pc->L, N, n, r, rows, isf, isg, gpart);
+    dski_status rr = reduce_partials(gpart, gb, npair, gpart + (size_t)gb * npair, st);
+    std::vector<double> gram(npair);
+    if (rr == DSKI_OK) {
+      if (hipMemcpyAsync(gram.data(), gpart + (size_t)gb * npair, sizeof(double) * npair,
+                         hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        rr = DSKI_EHIP;
+    }
+    (void)hipFree(gpart);
+    if (rr != DSKI_OK) {
+      set_error("Gram matrix of the preconditioner failed");
+      rc = DSKI_EHIP;
+      break;
+    }
+    std::vector<double> A((size_t)r * r), V((size_t)r * r), w(r);
+    for (int i = 0, pidx = 0; i < r; ++i)
+      for (int jj = i; jj < r; ++jj, ++pidx) A[(size_t)i * r + jj] = A[(size_t)jj * r + i] = gram[pidx];
+    sym_eig_jacobi(r, A.data(), V.data(), w.data());
+    std::vector<double> Vs((size_t)r * r), c(r), rootc(r);
+    double wmax = 0.0;
+    for (int i = 0; i < r; ++i) wmax = std::max(wmax, w[i]);
+    double ld = logdetD;
+    for (int i = 0; i < r; ++i) {
+      double s2 = w[i] > 1e-13 * wmax ? w[i] : 0.0;
+      double inv = s2 > 0.0 ? 1.0 / std::sqrt(s2) : 0.0;
+      for (int l = 0; l < r; ++l) Vs[(size_t)l * r + i] = V[(size_t)l * r + i] * inv;
+      c[i] = 1.0 - 1.0 / std::sqrt(1.0 + s2);
+      rootc[i] = std::sqrt(1.0 + s2) - 1.0;
+      ld += std::log1p(s2);
+    }
+    pc->logdet = ld;
+    double* dV = nullptr;
+    DSKI_HIP(hipMalloc(&dV, sizeof(double) * (size_t)r * r));
+    if (hipMemcpyAsync(dV, Vs.data(), sizeof(double) * r * r, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(pc->c, c.data(), sizeof(double) * r, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(pc->rootc, rootc.data(), sizeof(double) * r, hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+      (void)hipFree(dV);
+      set_error("preconditioner upload failed");
+      rc = DSKI_EHIP;
+      break;
+    }
+    k_make_u<<<(N + kBlock - 1) / kBlock, kBlock, 0, st>>>(pc->L, N, n, r, isf, isg,
+                                                                                dV, pc->U);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(dV);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      set_error("preconditioner factor kernel failed");
+      rc = DSKI_EHIP;
+      break;
+    }
+    if (r < k) rc = DSKI_RANK_TRUNCATED;
+  } while (0);
+  (void)hipFree(scratch);
+  return rc;
+}
+
+}  // namespace dski
+
+using namespace dski;
+
+extern "C" {
+
+dski_status pivchol_build(dski_plan p, int k, dski_precond* out, int* rank_host, int* piv_host,
+                          dski_stream stream) {
+  if (!p || !out || k < 0 || k > p->N || k > 1024) {
+    set_error("pivchol_build: bad arguments (k=%d)", k);
+    return DSKI_EINVAL;
+  }
+  if ((size_t)k * proj_rows(k) / 2 + (size_t)proj_rows(k) * kProjRC + (size_t)k * kProjRC >
+      65536 / sizeof(double)) {
+    set_error("pivchol_build: rank %d too large for this build (max 150)", k);
+    return DSKI_ENOTSUP;
+  }
+  *out = nullptr;
+  dski_precond pc = new dski_precond_s();
+  pc->plan = p;
+  dski_status rc = build_impl(p, k, pc, rank_host, piv_host, static_cast<hipStream_t>(stream));
+  if (rc < 0) {
+    destroy_pc(pc);
+    return rc;
+  }
+  *out = pc;
+  return rc;
+}
+
+dski_status dski_precond_destroy(dski_precond pc) {
+  destroy_pc(pc);
+  return DSKI_OK;
+}
+
+dski_status dski_precond_logdet(dski_precond pc, double* out_host) {
+  if (!pc || !out_host) {
+    set_error("dski_precond_logdet: NULL argument");
+    return DSKI_EINVAL;
+  }
+  *out_host = pc->logdet;
+  return DSKI_OK;
+}
+
+dski_status dski_precond_apply(dski_precond pc, int R, const float* Rm, int ld, float* Z, int ldz,
+                               dski_stream stream) {
+  if (!pc || R < 0 || ld < pc->plan->N || ldz < pc->plan->N || (R > 0 && (!Rm || !Z))) {
+    set_error("dski_precond_apply: bad arguments");
+    return DSKI_EINVAL;
+  }
+  dski_plan p = pc->plan;
+  if (R == 0) return DSKI_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  size_t nr = (size_t)p->N * R;
+  DSKI_TRY(p->vin.reserve(sizeof(float) * nr));
+  DSKI_TRY(p->vout.reserve(sizeof(float) * nr));
+  DSKI_TRY(permute(p, +1, R, Rm, ld, p->vin.as<float>(), p->N, st));
+  DSKI_TRY(precond_apply_tiled(pc, R, p->vin.as<float>(), p->N, p->vout.as<float>(), p->N, nullptr,
+                               nullptr, st));
+  return permute(p, -1, R, p->vout.as<float>(), p->N, Z, ldz, st);
+}
+
+__global__ void k_factor_out(const double* __restrict__ L, int N, int n, int k,
+                             const int* __restrict__ perm, double* __restrict__ out, int ld) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (e >= N || j >= k) return;
+  int u = (e / n) * n + perm[e % n];
+  out[(size_t)j * ld + u] = L[(size_t)j * N + e];
+}
+
+dski_status dski_precond_factor(dski_precond pc, double* Lout, int ld, dski_stream stream) {
+  if (!pc || !Lout || ld < pc->plan->N) {
+    set_error("dski_precond_factor: bad arguments");
+    return DSKI_EINVAL;
+  }
+  if (pc->k == 0) return DSKI_OK;
+  dski_plan p = pc->plan;
+  dim3 grid((p->N + kBlock - 1) / kBlock, pc->k);
+  k_factor_out<<<grid, kBlock, 0, static_cast<hipStream_t>(stream)>>>(pc->L, p->N, p->n, pc->k, p->perm,
+                                                                       Lout, ld);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+}  // extern "C"

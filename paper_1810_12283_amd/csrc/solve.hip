@@ -1,0 +1,329 @@
+// Stochastic Lanczos quadrature for log det K~ and the log marginal likelihood
+// eq. (1) with its hyper-parameter gradient.
+//
+// One block PCG carries the data solve alpha = K~^{-1} y and the probe solves
+// u_i = K~^{-1} z_i, z_i = C w_i (C C^T = M, w_i Rademacher).  From the same run:
+//   log det K~ ~ log det M + (1/t) sum_i (z_i^T M^{-1} z_i) e_1^T log(T_i) e_1,
+// with T_i the Lanczos tridiagonal of probe i from its CG coefficients (Sec. 2);
+//   d mll / d theta = 1/2 alpha^T K' alpha - 1/2 (1/t) sum_i u_i^T K' v_i,  v_i = M^{-1} z_i,
+// where K' = dK~/dtheta is the derivative of the approximate kernel (Sec. 3):
+// for ell_p and s it is S K_UU' S^T with K_UU' the Kronecker-Toeplitz matrix with
+// the derivative spectrum on axis p (or 2 K_UU), so the products reduce to dot
+// products of scattered grids; for the noise levels it is diagonal.
+#include <cmath>
+
+#include "internal.h"
+
+namespace dski {
+
+// partial[b, q] = sum over a chunk of a[pa[q]] . b[pb[q]] (columns of length len, offset lo)
+template <typename T>
+__global__ void k_pair_dots(const T* __restrict__ A, long long lda, const T* __restrict__ Bm,
+                            long long ldb, const int* __restrict__ pairs, int npairs, long long lo,
+                            long long len, double* __restrict__ partial) {
+  int q = blockIdx.y;
+  int ca = pairs[2 * q], cb = pairs[2 * q + 1];
+  const T* a = A + (size_t)ca * lda + lo;
+  const T* b = Bm + (size_t)cb * ldb + lo;
+  double acc = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (long long)gridDim.x * blockDim.x)
+    acc += (double)a[e] * (double)b[e];
+  __shared__ double red[4];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * npairs + q] = red[0] + red[1] + red[2] + red[3];
+}
+
+struct DotCtx {
+  DevBuf buf;  // pairs (int) + partials + results
+};
+
+template <typename T>
+static dski_status pair_dots(const T* A, long long lda, const T* B, long long ldb,
+                             const std::vector<int>& pairs, long long lo, long long len,
+                             std::vector<double>& out, DevBuf& buf, hipStream_t st) {
+  int np = (int)pairs.size() / 2;
+  out.assign(np, 0.0);
+  if (np == 0 || len <= 0) return DSKI_OK;
+  int nblk = (int)std::min<long long>(256, (len + kBlock - 1) / kBlock);
+  size_t bytes = sizeof(int) * pairs.size() + 64 + sizeof(double) * ((size_t)nblk * np + np);
+  DSKI_TRY(buf.reserve(bytes));
+  int* dp = buf.as<int>();
+  double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(dp) + ((sizeof(int) * pairs.size() + 63) / 64) * 64);
+  double* res = part + (size_t)nblk * np;
+  DSKI_HIP(hipMemcpyAsync(dp, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice, st));
+  k_pair_dots<T><<<dim3(nblk, np), kBlock, 0, st>>>(A, lda, B, ldb, dp, np, lo, len, part);
+  DSKI_HIP(hipGetLastError());
+  DSKI_TRY(reduce_partials(part, nblk, np, res, st));
+  DSKI_HIP(hipMemcpyAsync(out.data(), res, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+  DSKI_HIP(hipStreamSynchronize(st));
+  return DSKI_OK;
+}
+
+__global__ void k_copy_cols_d(const double* __restrict__ src, double* __restrict__ dst, long long M,
+                              const int* __restrict__ cols, int nc) {
+  int c = blockIdx.y;
+  const double* s = src + (size_t)cols[c] * M;
+  double* d = dst + (size_t)c * M;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < M;
+       e += (long long)gridDim.x * blockDim.x)
+    d[e] = s[e];
+}
+
+struct ProbeRun {
+  std::vector<double> quad, weight;
+  double logdet = 0, stderr_ = 0;
+  bool ok = true;
+};
+
+static void slq_combine(const std::vector<double>& ab, int max_iter, int R, int col0, int t,
+                        const PcgResult& res, double logdetM, ProbeRun& out) {
+  out.quad.assign(t, 0.0);
+  out.weight.assign(t, 0.0);
+  double mean = 0.0;
+  std::vector<double> vals(t);
+  for (int i = 0; i < t; ++i) {
+    int c = col0 + i;
+    int J = std::min(res.iters[c], max_iter);
+    int ok = 0;
+    double q = gauss_quad_log(ab.data() + (size_t)c * max_iter, ab.data() + (size_t)R * max_iter + (size_t)c * max_iter,
+                              J, &ok);
+    if (!ok) out.ok = false;
+    out.quad[i] = q;
+    out.weight[i] = res.rz0[c];
+    vals[i] = q * res.rz0[c];
+    mean += vals[i];
+  }
+  mean /= std::max(t, 1);
+  double var = 0.0;
+  for (int i = 0; i < t; ++i) var += (vals[i] - mean) * (vals[i] - mean);
+  out.logdet = logdetM + mean;
+  out.stderr_ = t > 1 ? std::sqrt(var / (t - 1) / t) : NAN;
+}
+
+}  // namespace dski
+
+using namespace dski;
+
+extern "C" {
+
+dski_status slq_logdet(dski_plan p, dski_precond pc, int t, int lanczos_steps, double tol, int max_iter,
+                       uint64_t seed, double* logdet_host, double* stderr_host, dski_stream stream) {
+  if (!p || t <= 0 || lanczos_steps < 0 || (lanczos_steps == 0 && (tol <= 0 || max_iter <= 0)) ||
+      (pc && pc->plan != p) || !logdet_host) {
+    set_error("slq_logdet: bad arguments");
+    return DSKI_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int N = p->N;
+  int steps = lanczos_steps > 0 ? lanczos_steps : max_iter;
+  size_t nr = (size_t)N * t;
+  DevBuf tmp;
+  DSKI_TRY(tmp.reserve(sizeof(float) * nr * 3 + sizeof(double) * 2 * (size_t)steps * t + 1024));
+  float* W = tmp.as<float>();
+  float* Z = W + nr;
+  float* X = Z + nr;
+  double* ab = reinterpret_cast<double*>(X + nr);
+  dski_status rc = DSKI_OK;
+  do {
+    // probes in user order -> tile order -> z = C w
+    rc = rademacher(seed, 0, t, N, X, N, st);
+    if (rc < 0) break;
+    rc = permute(p, +1, t, X, N, W, N, st);
+    if (rc < 0) break;
+    if (pc)
+      rc = precond_factor_apply_tiled(pc, t, W, N, Z, N, st);
+    else
+      rc = hipMemcpyAsync(Z, W, sizeof(float) * nr, hipMemcpyDeviceToDevice, st) == hipSuccess ? DSKI_OK
+                                                                                                 : DSKI_EHIP;
+    if (rc < 0) break;
+    std::vector<double> tols(t, lanczos_steps > 0 ? 0.0 : tol);
+    PcgResult res;
+    rc = pcg_tiled(p, pc, t, Z, N, X, N, tols.data(), steps, lanczos_steps, ab, res, st);
+    if (rc < 0) break;
+    std::vector<double> hab(2 * (size_t)steps * t);
+    if (hipMemcpyAsync(hab.data(), ab, sizeof(double) * hab.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("SLQ copy failed");
+      rc = DSKI_EHIP;
+      break;
+    }
+    ProbeRun pr;
+    slq_combine(hab, steps, t, 0, t, res, pc ? pc->logdet : 0.0, pr);
+    if (!pr.ok) {
+      set_error("SLQ: non-positive Ritz value or quadrature failure");
+      rc = DSKI_EBREAKDOWN;
+      break;
+    }
+    *logdet_host = pr.logdet;
+    if (stderr_host) *stderr_host = pr.stderr_;
+  } while (0);
+  tmp.release();
+  return rc;
+}
+
+dski_status mll_and_grad(dski_plan p, dski_precond pc_in, int k, const float* y, int t, uint64_t seed,
+                         double tol, int max_iter, double* mll_host, double* grad_host,
+                         double* logdet_host, int* iters_host, dski_stream stream) {
+  if (!p || !y || t <= 0 || tol <= 0 || max_iter <= 0 || (!pc_in && k < 0) ||
+      (pc_in && pc_in->plan != p)) {
+    set_error("mll_and_grad: bad arguments");
+    return DSKI_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int N = p->N, n = p->n, d = p->d;
+  long long M = p->M;
+  dski_precond pc = pc_in;
+  dski_status rc = DSKI_OK;
+  if (!pc) {
+    int rank = 0;
+    rc = pivchol_build(p, k, &pc, &rank, nullptr, stream);
+    if (rc < 0) return rc;
+  }
+  int R = 1 + t;
+  size_t nr = (size_t)N * R;
+  DevBuf tmp, dotbuf;
+  do {
+    // buffers: B (R cols), X (R cols), Vv (t cols), W (t cols), history
+    size_t fl = nr * 2 + (size_t)N * t * 2;
+    rc = tmp.reserve(sizeof(float) * fl + sizeof(double) * 2 * (size_t)max_iter * R + 1024);
+    if (rc < 0) break;
+    float* B = tmp.as<float>();
+    float* X = B + nr;
+    float* Vv = X + nr;
+    float* W = Vv + (size_t)N * t;
+    double* ab = reinterpret_cast<double*>(W + (size_t)N * t);
+    rc = permute(p, +1, 1, y, N, B, N, st);
+    if (rc < 0) break;
+    rc = rademacher(seed, 0, t, N, Vv, N, st);
+    if (rc < 0) break;
+    rc = permute(p, +1, t, Vv, N, W, N, st);
+    if (rc < 0) break;
+    rc = precond_factor_apply_tiled(pc, t, W, N, B + N, N, st);
+    if (rc < 0) break;
+    std::vector<double> tols(R, tol);
+    PcgResult res;
+    rc = pcg_tiled(p, pc, R, B, N, X, N, tols.data(), max_iter, 0, ab, res, st);
+    if (rc < 0) break;
+    dski_status pcg_rc = rc;
+    // v_i = M^{-1} z_i
+    rc = precond_apply_tiled(pc, t, B + N, N, Vv, N, nullptr, nullptr, st);
+    if (rc < 0) break;
+    // log det by SLQ from the same run
+    std::vector<double> hab(2 * (size_t)max_iter * R);
+    if (hipMemcpyAsync(hab.data(), ab, sizeof(double) * hab.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("mll_and_grad: copy failed");
+      rc = DSKI_EHIP;
+      break;
+    }
+    ProbeRun pr;
+    slq_combine(hab, max_iter, R, 1, t, res, pc->logdet, pr);
+    if (!pr.ok) {
+      set_error("mll_and_grad: SLQ quadrature failed");
+      rc = DSKI_EBREAKDOWN;
+      break;
+    }
+    // data fit y^T alpha and the noise-gradient dots (value rows, gradient rows)
+    std::vector<int> pairs = {0, 0};
+    std::vector<double> yal;
+    rc = pair_dots<float>(B, N, X, N, pairs, 0, N, yal, dotbuf, st);
+    if (rc < 0) break;
+    std::vector<int> np;
+    np.push_back(0);
+    np.push_back(0);  // alpha.alpha (X col 0 with itself)
+    for (int i = 0; i < t; ++i) {
+      np.push_back(1 + i);
+      np.push_back(i);
+    }
+    // pairs index X (cols) against: first pair X0.X0 handled with A=X,B=X below
+    std::vector<double> aa_v, aa_g;
+    std::vector<int> p00 = {0, 0};
+    rc = pair_dots<float>(X, N, X, N, p00, 0, n, aa_v, dotbuf, st);
+    if (rc < 0) break;
+    rc = pair_dots<float>(X, N, X, N, p00, n, N - n, aa_g, dotbuf, st);
+    if (rc < 0) break;
+    std::vector<int> puv;
+    for (int i = 0; i < t; ++i) {
+      puv.push_back(1 + i);
+      puv.push_back(i);
+    }
+    std::vector<double> uv_v, uv_g;
+    rc = pair_dots<float>(X, N, Vv, N, puv, 0, n, uv_v, dotbuf, st);
+    if (rc < 0) break;
+    rc = pair_dots<float>(X, N, Vv, N, puv, n, N - n, uv_g, dotbuf, st);
+    if (rc < 0) break;
+    // grids: [S^T alpha, S^T u_1..u_t, S^T v_1..v_t]
+    int Rg = 1 + 2 * t;
+    rc = p->grid.reserve(sizeof(double) * (size_t)M * (Rg + 1 + t));
+    if (rc < 0) break;
+    double* G = p->grid.as<double>();
+    double* H = G + (size_t)M * Rg;  // K' applied to [alpha, v_1..v_t]
+    rc = scatter(p, R, X, N, G, st);
+    if (rc < 0) break;
+    rc = scatter(p, t, Vv, N, G + (size_t)M * R, st);
+    if (rc < 0) break;
+    std::vector<int> cols;
+    cols.push_back(0);
+    for (int i = 0; i < t; ++i) cols.push_back(R + i);
+    std::vector<int> gp;  // (H col, G col) pairs
+    gp.push_back(0);
+    gp.push_back(0);
+    for (int i = 0; i < t; ++i) {
+      gp.push_back(1 + i);
+      gp.push_back(1 + i);
+    }
+    int* dcols = nullptr;
+    if (hipMalloc(&dcols, sizeof(int) * cols.size()) != hipSuccess) {
+      set_error("allocation failed");
+      rc = DSKI_ENOMEM;
+      break;
+    }
+    std::vector<double> g(d + 3, 0.0);
+    for (int which = 0; which <= d && rc >= 0; ++which) {
+      if (hipMemcpyAsync(dcols, cols.data(), sizeof(int) * cols.size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+        rc = DSKI_EHIP;
+        break;
+      }
+      int nb = (int)std::min<long long>(1024, (M + kBlock - 1) / kBlock);
+      k_copy_cols_d<<<dim3(nb, 1 + t), kBlock, 0, st>>>(G, H, M, dcols, 1 + t);
+      rc = apply_kuu(p, 1 + t, H, st, which < d ? which : -1);
+      if (rc < 0) break;
+      std::vector<double> dots;
+      rc = pair_dots<double>(H, M, G, M, gp, 0, M, dots, dotbuf, st);
+      if (rc < 0) break;
+      double scale = which < d ? 1.0 : 2.0;
+      double tr = 0.0;
+      for (int i = 0; i < t; ++i) tr += dots[1 + i];
+      tr /= t;
+      g[which] = scale * (0.5 * dots[0] - 0.5 * tr);
+    }
+    (void)hipFree(dcols);
+    if (rc < 0) break;
+    double sf2 = p->sf * p->sf, sg2 = p->sg * p->sg;
+    double trv = 0.0, trg = 0.0;
+    for (int i = 0; i < t; ++i) {
+      trv += uv_v[i];
+      trg += uv_g[i];
+    }
+    g[d + 1] = sf2 * (aa_v[0] - trv / t);
+    g[d + 2] = sg2 * (aa_g[0] - trg / t);
+    const double log2pi = 1.8378770664093453;
+    double mll = -0.5 * (yal[0] + pr.logdet + (double)N * log2pi);
+    if (mll_host) *mll_host = mll;
+    if (grad_host)
+      for (int j = 0; j < d + 3; ++j) grad_host[j] = g[j];
+    if (logdet_host) *logdet_host = pr.logdet;
+    if (iters_host)
+      for (int r = 0; r < R; ++r) iters_host[r] = res.iters[r];
+    rc = pcg_rc;
+  } while (0);
+  tmp.release();
+  dotbuf.release();
+  if (!pc_in) dski_precond_destroy(pc);
+  return rc;
+}
+
+}  // extern "C"

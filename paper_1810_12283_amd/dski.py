@@ -1,0 +1,316 @@
+"""Python binding of libdski.so (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library.  PyTorch supplies device memory
+(tensor data pointers) and the current HIP stream, nothing else.  Blocks of R
+N-vectors are torch tensors of shape (R, N), contiguous: row r is vector r,
+i.e. the column-major N x R layout of the C ABI with ld = N.
+
+If the library is missing or cannot be loaded every call raises: there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdski.so")
+
+OK, NOT_CONVERGED, RANK_TRUNCATED = 0, 1, 2
+_STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "RANK_TRUNCATED", -1: "EINVAL", -2: "ENOMEM",
+           -3: "EHIP", -4: "EBREAKDOWN", -5: "ENOTSUP"}
+
+
+class DSKIError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+vp = C.c_void_p
+ip = C.POINTER(C.c_int)
+dp = C.POINTER(C.c_double)
+_SIGS = {
+    "dski_last_error": (C.c_char_p, []),
+    "dski_version": (C.c_char_p, []),
+    "dski_plan_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, vp, ip, dp, dp, vp]),
+    "dski_plan_destroy": (C.c_int, [vp]),
+    "dski_plan_info": (C.c_int, [vp, ip, ip, ip, C.POINTER(C.c_longlong), ip, ip, dp, dp]),
+    "dski_set_hypers": (C.c_int, [vp, dp, C.c_double, C.c_double, C.c_double, vp]),
+    "dski_mvm": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_mvm_dtheta": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_permute": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_tile_order": (C.c_int, [vp, ip]),
+    "dski_mvm_tiled": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "pivchol_build": (C.c_int, [vp, C.c_int, C.POINTER(vp), ip, ip, vp]),
+    "dski_precond_destroy": (C.c_int, [vp]),
+    "dski_precond_apply": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_precond_logdet": (C.c_int, [vp, dp]),
+    "dski_precond_factor": (C.c_int, [vp, vp, C.c_int, vp]),
+    "pcg_solve": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, vp, C.c_int, dp, C.c_int, ip, dp, vp, vp]),
+    "slq_logdet": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_uint64, dp, dp, vp]),
+    "mll_and_grad": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, C.c_uint64, C.c_double, C.c_int,
+                               dp, dp, dp, ip, vp]),
+    "dski_rademacher": (C.c_int, [C.c_uint64, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]),
+    "dski_lanczos_quad_log": (C.c_double, [dp, dp, C.c_int, ip]),
+}
+
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load libdski.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1810_12283_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().dski_last_error().decode()
+
+
+def _check(status, what):
+    if status < 0:
+        raise DSKIError(status, f"{what}: {last_error()}")
+    return status
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return vp(stream.cuda_stream)
+
+
+def _dptr(t: torch.Tensor):
+    return vp(t.data_ptr())
+
+
+def _arr(vals, ctype):
+    a = (ctype * len(vals))(*vals)
+    return a
+
+
+def _block(V: torch.Tensor, N: int, name: str) -> torch.Tensor:
+    if not V.is_cuda or V.dtype != torch.float32:
+        raise TypeError(f"{name} must be a CUDA float32 tensor")
+    if V.dim() == 1:
+        V = V[None, :]
+    if V.shape[-1] != N or not V.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with shape (R, {N})")
+    return V
+
+
+class Plan:
+    """A D-SKI operator on fixed points and grid (owns a dski_plan)."""
+
+    def __init__(self, X: torch.Tensor, grid_m: Sequence[int], lo=None, hi=None, stream=None):
+        L = lib()
+        if not X.is_cuda or X.dtype != torch.float64 or X.dim() != 2:
+            raise TypeError("X must be a CUDA float64 tensor of shape (n, d)")
+        X = X.contiguous()
+        n, d = X.shape
+        self.n, self.d, self.N = n, d, n * (d + 1)
+        h = vp()
+        m = _arr([int(v) for v in grid_m], C.c_int)
+        lo_a = _arr([float(v) for v in lo], C.c_double) if lo is not None else None
+        hi_a = _arr([float(v) for v in hi], C.c_double) if hi is not None else None
+        _check(L.dski_plan_create(C.byref(h), n, d, _dptr(X), m, lo_a, hi_a, _stream(stream)),
+               "dski_plan_create")
+        self._h = h
+        self._info()
+
+    def _info(self):
+        L = lib()
+        n, d, N = C.c_int(), C.c_int(), C.c_int()
+        M = C.c_longlong()
+        m = (C.c_int * 3)()
+        Lf = (C.c_int * 3)()
+        h = (C.c_double * 3)()
+        lo = (C.c_double * 3)()
+        _check(L.dski_plan_info(self._h, C.byref(n), C.byref(d), C.byref(N), C.byref(M), m, Lf, h, lo),
+               "dski_plan_info")
+        self.grid_nodes = M.value
+        self.grid_m = [m[i] for i in range(self.d)]
+        self.fft_len = [Lf[i] for i in range(self.d)]
+        self.h = [h[i] for i in range(self.d)]
+        self.grid_lo = [lo[i] for i in range(self.d)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dski_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_hypers(self, log_ell, log_s, log_sigma_f, log_sigma_g, stream=None):
+        le = np.broadcast_to(np.asarray(log_ell, dtype=np.float64), (self.d,))
+        a = _arr([float(v) for v in le], C.c_double)
+        _check(lib().dski_set_hypers(self._h, a, float(log_s), float(log_sigma_f), float(log_sigma_g),
+                                     _stream(stream)), "dski_set_hypers")
+
+    def mvm(self, V: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        V = _block(V, self.N, "V")
+        Y = torch.empty_like(V) if out is None else out
+        _check(lib().dski_mvm(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N, _stream(stream)),
+               "dski_mvm")
+        return Y
+
+    def mvm_tiled(self, V: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        V = _block(V, self.N, "V")
+        Y = torch.empty_like(V) if out is None else out
+        _check(lib().dski_mvm_tiled(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
+                                    _stream(stream)), "dski_mvm_tiled")
+        return Y
+
+    def mvm_dtheta(self, which: int, V: torch.Tensor, stream=None) -> torch.Tensor:
+        V = _block(V, self.N, "V")
+        Y = torch.empty_like(V)
+        _check(lib().dski_mvm_dtheta(self._h, int(which), V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
+                                     _stream(stream)), "dski_mvm_dtheta")
+        return Y
+
+    def permute(self, V: torch.Tensor, direction: int, stream=None) -> torch.Tensor:
+        V = _block(V, self.N, "V")
+        Y = torch.empty_like(V)
+        _check(lib().dski_permute(self._h, int(direction), V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
+                                  _stream(stream)), "dski_permute")
+        return Y
+
+    def tile_order(self) -> np.ndarray:
+        perm = (C.c_int * self.n)()
+        _check(lib().dski_tile_order(self._h, perm), "dski_tile_order")
+        return np.frombuffer(perm, dtype=np.int32).copy()
+
+    def pivchol(self, k: int, stream=None) -> "Precond":
+        return Precond(self, k, stream)
+
+    def pcg(self, B: torch.Tensor, precond: Optional["Precond"] = None, tol=1e-4, max_iter=10000,
+            history=False, stream=None):
+        """Returns (X, iters, relres, status, alpha_beta or None)."""
+        B = _block(B, self.N, "B")
+        R = B.shape[0]
+        X = torch.empty_like(B)
+        tols = _arr([float(t) for t in np.broadcast_to(np.asarray(tol, dtype=np.float64), (R,))], C.c_double)
+        iters = (C.c_int * R)()
+        relres = (C.c_double * R)()
+        ab = torch.zeros(2 * max_iter * R, dtype=torch.float64, device=B.device) if history else None
+        st = _check(lib().pcg_solve(self._h, precond.handle if precond else None, R, _dptr(B), self.N,
+                                    _dptr(X), self.N, tols, int(max_iter), iters, relres,
+                                    _dptr(ab) if ab is not None else None, _stream(stream)), "pcg_solve")
+        return X, list(iters), list(relres), st, ab
+
+    def slq_logdet(self, precond: Optional["Precond"], num_probes: int, lanczos_steps: int = 0,
+                   tol: float = 1e-4, max_iter: int = 10000, seed: int = 0x181012283, stream=None):
+        ld, se = C.c_double(), C.c_double()
+        _check(lib().slq_logdet(self._h, precond.handle if precond else None, int(num_probes),
+                                int(lanczos_steps), float(tol), int(max_iter), C.c_uint64(seed),
+                                C.byref(ld), C.byref(se), _stream(stream)), "slq_logdet")
+        return ld.value, se.value
+
+    def mll_and_grad(self, y: torch.Tensor, precond: Optional["Precond"] = None, k: int = 50,
+                     num_probes: int = 16, seed: int = 0x181012283, tol: float = 1e-4,
+                     max_iter: int = 10000, stream=None):
+        y = _block(y, self.N, "y")
+        mll, ld = C.c_double(), C.c_double()
+        grad = (C.c_double * (self.d + 3))()
+        iters = (C.c_int * (1 + num_probes))()
+        st = _check(lib().mll_and_grad(self._h, precond.handle if precond else None, int(k), _dptr(y),
+                                       int(num_probes), C.c_uint64(seed), float(tol), int(max_iter),
+                                       C.byref(mll), grad, C.byref(ld), iters, _stream(stream)),
+                    "mll_and_grad")
+        return dict(mll=mll.value, grad=np.array(list(grad)), logdet=ld.value, iters=list(iters),
+                    status=st)
+
+
+class Precond:
+    """Pivoted-Cholesky preconditioner (owns a dski_precond)."""
+
+    def __init__(self, plan: Plan, k: int, stream=None):
+        self.plan = plan
+        h = vp()
+        rank = C.c_int()
+        piv = (C.c_int * max(k, 1))()
+        self.status = _check(lib().pivchol_build(plan.handle, int(k), C.byref(h), C.byref(rank), piv,
+                                                 _stream(stream)), "pivchol_build")
+        self._h = h
+        self.rank = rank.value
+        self.pivots = np.array([piv[i] for i in range(self.rank)], dtype=np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dski_precond_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def logdet(self) -> float:
+        v = C.c_double()
+        _check(lib().dski_precond_logdet(self._h, C.byref(v)), "dski_precond_logdet")
+        return v.value
+
+    def apply(self, Rm: torch.Tensor, stream=None) -> torch.Tensor:
+        Rm = _block(Rm, self.plan.N, "R")
+        Z = torch.empty_like(Rm)
+        _check(lib().dski_precond_apply(self._h, Rm.shape[0], _dptr(Rm), self.plan.N, _dptr(Z), self.plan.N,
+                                        _stream(stream)), "dski_precond_apply")
+        return Z
+
+    def factor(self, stream=None) -> torch.Tensor:
+        """L as a (rank, N) float64 tensor (row j = column j of L, user order)."""
+        out = torch.zeros((max(self.rank, 1), self.plan.N), dtype=torch.float64, device="cuda")
+        _check(lib().dski_precond_factor(self._h, _dptr(out), self.plan.N, _stream(stream)),
+               "dski_precond_factor")
+        return out[: self.rank]
+
+
+def rademacher(seed: int, col0: int, ncols: int, N: int, device="cuda", stream=None) -> torch.Tensor:
+    out = torch.empty((ncols, N), dtype=torch.float32, device=device)
+    _check(lib().dski_rademacher(C.c_uint64(seed), int(col0), int(ncols), int(N), _dptr(out), N,
+                                 _stream(stream)), "dski_rademacher")
+    return out
+
+
+def lanczos_quad_log(alpha: Sequence[float], beta: Sequence[float]) -> float:
+    J = len(alpha)
+    a = _arr([float(v) for v in alpha], C.c_double)
+    b = _arr([float(v) for v in beta] + [0.0], C.c_double)
+    ok = C.c_int()
+    v = lib().dski_lanczos_quad_log(a, b, J, C.byref(ok))
+    if not ok.value:
+        raise DSKIError(-4, "quadrature failed (non-positive Ritz value)")
+    return v
+
+
+def version() -> str:
+    return lib().dski_version().decode()

@@ -1,0 +1,111 @@
+"""GPU parity of the D-SKI MVM (Sec. 3.1) against the FP64 oracle.
+
+Bar: 1e-5 relative (2-norm per column) on the MVM, with inputs rounded to
+FP32 on both sides; bitwise reproducibility of reruns; bit-exact probes."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import rng as orng
+from tests.gpu_common import SEED, from_gpu, make, need_gpu, rel_cols, say, small_workloads, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL_MVM = 1e-5
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_mvm_matches_oracle(idx):
+    name, W = small_workloads()[idx]
+    say("mvm", name, W.n, W.grid_m)
+    plan, op = make(W)
+    r = np.random.default_rng(idx)
+    for R in (1, 3, 17):
+        V = r.standard_normal((op.N, R)).astype(np.float32).astype(np.float64)
+        V[:, 0] = W.y.astype(np.float32)          # a smooth data column
+        Y = from_gpu(plan.mvm(to_gpu(V)))
+        ref = op.matvec(V)
+        err = rel_cols(Y, ref)
+        say("  R", R, "max rel err", err.max())
+        assert err.max() < TOL_MVM
+
+
+def test_mvm_dtheta_matches_oracle():
+    W = workloads.small2d(n=400, grid=40)
+    say("mvm_dtheta", W.n)
+    plan, op = make(W)
+    V = np.random.default_rng(5).standard_normal((op.N, 2)).astype(np.float32).astype(np.float64)
+    for which in range(op.d + 3):
+        Y = from_gpu(plan.mvm_dtheta(which, to_gpu(V)))
+        ref = op.matvec_dtheta(which, V)
+        err = rel_cols(Y, ref)
+        say("  which", which, err.max())
+        assert err.max() < TOL_MVM
+
+
+def test_tiled_order_and_determinism():
+    W = workloads.terrain(n=2000, grid=40)
+    say("tiled", W.n)
+    plan, op = make(W)
+    V = to_gpu(np.random.default_rng(1).standard_normal((op.N, 5)))
+    Y1 = plan.mvm(V)
+    Y2 = plan.mvm(V)
+    assert torch.equal(Y1, Y2)                      # fixed summation order, no atomics
+    Vt = plan.permute(V, +1)
+    Yt = plan.mvm_tiled(Vt)
+    assert torch.equal(plan.permute(Yt, -1), Y1)
+    perm = plan.tile_order()
+    assert sorted(perm.tolist()) == list(range(W.n))
+    # the back permutation inverts the forward one exactly
+    assert torch.equal(plan.permute(Vt, -1), V)
+
+
+def test_mvm_full_size_terrain():
+    """The terrain workload at full size (n=20,000, 200x200 grid, 17 columns)."""
+    W = workloads.terrain()
+    say("mvm full terrain", W.n, W.grid_m)
+    plan, op = make(W)
+    r = np.random.default_rng(7)
+    V = np.sign(r.standard_normal((op.N, 17))).astype(np.float64)
+    V[:, 0] = W.y.astype(np.float32)
+    Y = from_gpu(plan.mvm(to_gpu(V)))
+    err = rel_cols(Y, op.matvec(V))
+    say("  max rel err", err.max())
+    assert err.max() < TOL_MVM
+
+
+def test_mvm_edge_cases():
+    dski = need_gpu()
+    say("edge cases")
+    # points exactly on the box corners, a 1-D problem and the smallest grid
+    X = np.array([[0.0, 0.0], [1.0, 1.0], [0.0, 1.0], [0.5, 0.25]])
+    for m in ([4, 4], [5, 9]):
+        plan = dski.Plan(torch.tensor(X, device="cuda"), m, [0, 0], [1, 1])
+        plan.set_hypers(np.log([0.4, 0.3]), 0.1, np.log(0.05), np.log(0.1))
+        from oracle import dski as odski
+        op = odski.DSKI(X, m, [0, 0], [1, 1], np.log([0.4, 0.3]), 0.1, np.log(0.05), np.log(0.1))
+        V = np.random.default_rng(0).standard_normal((op.N, 2)).astype(np.float32).astype(np.float64)
+        assert rel_cols(from_gpu(plan.mvm(to_gpu(V))), op.matvec(V)).max() < TOL_MVM
+    X1 = np.random.default_rng(2).random((50, 1))
+    plan = dski.Plan(torch.tensor(X1, device="cuda"), [25], [0], [1])
+    plan.set_hypers([np.log(0.1)], 0.0, np.log(0.05), np.log(0.1))
+    from oracle import dski as odski
+    op = odski.DSKI(X1, [25], [0], [1], [np.log(0.1)], 0.0, np.log(0.05), np.log(0.1))
+    V = np.random.default_rng(3).standard_normal((op.N, 3)).astype(np.float32).astype(np.float64)
+    assert rel_cols(from_gpu(plan.mvm(to_gpu(V))), op.matvec(V)).max() < TOL_MVM
+    # a point outside the box is rejected
+    with pytest.raises(dski.DSKIError):
+        dski.Plan(torch.tensor([[0.0, 1.5]], device="cuda", dtype=torch.float64), [8, 8], [0, 0], [1, 1])
+    # empty block of vectors
+    plan = dski.Plan(torch.tensor(X, device="cuda"), [6, 6], [0, 0], [1, 1])
+    out = plan.mvm(torch.zeros((0, 12), device="cuda"))
+    assert out.shape == (0, 12)
+
+
+def test_rademacher_matches_oracle_stream():
+    dski = need_gpu()
+    say("rademacher")
+    for (seed, col0, nc, N) in ((SEED, 0, 3, 1000), (12345, 5, 2, 777)):
+        g = dski.rademacher(seed, col0, nc, N).cpu().numpy().T.astype(np.float64)
+        assert np.array_equal(g, orng.rademacher(seed, col0, nc, N))

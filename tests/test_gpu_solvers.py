@@ -1,0 +1,138 @@
+"""GPU parity of pivoted Cholesky, preconditioner, PCG, SLQ and the marginal
+likelihood with its gradient against the FP64 oracle (same probes, same
+pivots).  Bars: pivot order equal except at near-ties (the GPU pick is within
+tau = 1e-4 x max initial diagonal of the oracle's best); factor 1e-4; log det
+M 1e-5; solves 1e-4 true relative residual (oracle's FP64 operator); log det
+1e-3; mll gradient 1e-3 relative to its norm."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import krylov, mll as omll, pivchol, precond, rng as orng, slq
+from tests.gpu_common import SEED, from_gpu, make, need_gpu, rel_cols, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+TAU = 1e-4
+
+
+def _pivchol_pair(W, k):
+    plan, op = make(W)
+    pc = plan.pivchol(k)
+    piv = pc.pivots
+    dg = op.diag_K()
+    L, opiv, gaps = pivchol.pivoted_cholesky(dg, op.row_K, len(piv), forced=piv)
+    return plan, op, pc, L, gaps
+
+
+@pytest.mark.parametrize("name,k", [("small2d", 20), ("terrain_small", 50), ("torus_small", 30)])
+def test_pivchol_matches_oracle(name, k):
+    W = {"small2d": workloads.small2d(), "terrain_small": workloads.terrain(n=3000, grid=60),
+         "torus_small": workloads.torus(n=700, grid=14)}[name]
+    say("pivchol", name, k)
+    plan, op, pc, L, gaps = _pivchol_pair(W, k)
+    assert pc.rank == k
+    say("  max gap", gaps.max())
+    assert gaps.max() <= TAU
+    Lg = pc.factor().cpu().numpy().T
+    err = np.linalg.norm(Lg - L) / np.linalg.norm(L)
+    say("  factor rel err", err)
+    assert err < 1e-4
+    P = precond.Precond(L, op.Dn)
+    assert pc.logdet() == pytest.approx(P.logdet(), rel=1e-5)
+    # preconditioner application
+    B = np.random.default_rng(1).standard_normal((op.N, 3)).astype(np.float32).astype(np.float64)
+    Z = from_gpu(pc.apply(to_gpu(B)))
+    e2 = rel_cols(Z, P.solve(B)).max()
+    say("  apply rel err", e2)
+    assert e2 < 1e-4
+
+
+def test_pivchol_exact_low_rank_and_truncation():
+    """rank(K) <= grid size: asking for more columns stops early (rank
+    truncated) and then M = K~, so PCG converges in one step."""
+    dski = need_gpu()
+    say("pivchol low rank")
+    r = np.random.default_rng(3)
+    X = r.random((20, 2))
+    plan = dski.Plan(torch.tensor(X, device="cuda"), [6, 6], [0, 0], [1, 1])
+    plan.set_hypers(np.log([0.3, 0.3]), 0.0, np.log(0.05), np.log(0.1))
+    pc = plan.pivchol(60)
+    assert pc.status == dski.RANK_TRUNCATED
+    assert pc.rank <= 36
+    B = to_gpu(r.standard_normal((60, 2)))
+    X_, iters, relres, st, _ = plan.pcg(B, pc, tol=1e-3, max_iter=50)
+    say("  iters", iters, relres)
+    assert max(iters) <= 2
+
+
+@pytest.mark.parametrize("name", ["small2d", "terrain_small"])
+def test_pcg_true_residual(name):
+    W = {"small2d": workloads.small2d(), "terrain_small": workloads.terrain(n=3000, grid=60)}[name]
+    say("pcg", name)
+    plan, op = make(W)
+    pc = plan.pivchol(W.rank)
+    Wr = orng.rademacher(SEED, 0, 2, op.N)
+    B = np.concatenate([W.y[:, None], Wr], axis=1).astype(np.float32).astype(np.float64)
+    X, iters, relres, st, _ = plan.pcg(to_gpu(B), pc, tol=1e-4, max_iter=20000)
+    say("  iters", iters, "relres", relres, "status", st)
+    assert st == 0
+    tr = krylov.true_relres(op.matvec, B, from_gpu(X))
+    say("  true relres (oracle FP64 operator)", tr)
+    assert tr.max() <= 1e-4
+    # unpreconditioned CG on the same system needs many more iterations
+    X2, it2, rr2, st2, _ = plan.pcg(to_gpu(B[:, :1]), None, tol=1e-4, max_iter=max(iters) * 5)
+    say("  CG iters", it2, rr2)
+    assert it2[0] > 3 * iters[0]
+
+
+def test_pcg_not_converged_status():
+    W = workloads.small2d()
+    say("pcg max_iter")
+    plan, op = make(W)
+    X, iters, relres, st, _ = plan.pcg(to_gpu(W.y), None, tol=1e-8, max_iter=5)
+    assert st == 1 and iters == [5] and relres[0] > 1e-8
+
+
+def test_slq_fixed_steps_matches_oracle():
+    """small2d: 10 probes x 30 Lanczos steps (explicit Lanczos in the oracle,
+    PCG-derived tridiagonals on the GPU, same probes and preconditioner)."""
+    W = workloads.small2d()
+    say("slq small2d")
+    plan, op, pc, L, gaps = _pivchol_pair(W, W.rank)
+    ld_gpu, se_gpu = plan.slq_logdet(pc, W.num_probes, W.lanczos_steps, seed=SEED)
+    P = precond.Precond(L, op.Dn)
+    Z = P.factor_apply(orng.rademacher(SEED, 0, W.num_probes, op.N))
+    q, w = [], []
+    for i in range(W.num_probes):
+        dg, of, nrm2 = krylov.lanczos(op.matvec, Z[:, i], W.lanczos_steps, P.solve)
+        q.append(slq.quad_from_tridiag(dg, of))
+        w.append(nrm2)
+    ld_or, se_or = slq.estimate(q, w, P.logdet())
+    exact = np.linalg.slogdet(op.dense())[1]
+    say("  gpu", ld_gpu, se_gpu, "oracle", ld_or, se_or, "exact", exact)
+    assert ld_gpu == pytest.approx(ld_or, rel=1e-3)
+    assert abs(ld_gpu - exact) < 4 * se_gpu + 1e-3 * abs(exact)
+
+
+def test_mll_and_grad_matches_oracle_small():
+    W = workloads.small2d(n=400, grid=40)
+    say("mll small2d")
+    plan, op, pc, L, gaps = _pivchol_pair(W, 30)
+    t = 16
+    res = plan.mll_and_grad(to_gpu(W.y.astype(np.float32)), pc, num_probes=t, seed=SEED, tol=1e-6,
+                            max_iter=5000)
+    ref = omll.stochastic(op, W.y.astype(np.float32).astype(np.float64), L, t, SEED, 1e-6)
+    say("  gpu", res["mll"], res["logdet"], res["grad"])
+    say("  orc", ref["mll"], ref["logdet"], ref["grad"])
+    assert res["logdet"] == pytest.approx(ref["logdet"], rel=1e-3)
+    assert res["mll"] == pytest.approx(ref["mll"], rel=1e-3, abs=1e-3 * abs(ref["logdet"]))
+    g, gr = res["grad"], ref["grad"]
+    assert np.linalg.norm(g - gr) / np.linalg.norm(gr) < 1e-3
+    # and against the dense exact gradient within the stochastic error
+    ex = omll.exact(op, W.y.astype(np.float32).astype(np.float64))
+    say("  exact", ex["mll"], ex["grad"])
+    assert abs(res["logdet"] - ex["logdet"]) < 5e-2 * abs(ex["logdet"])
