@@ -35,7 +35,9 @@
  *  - Hyper-parameters are natural logs: log ell_1..log ell_d, log s,
  *    log sigma_f, log sigma_g (this order wherever a gradient is returned).
  *  - Arithmetic: N-vectors are stored in FP32; interpolation, K_UU, dot
- *    products and all scalars are computed in FP64.
+ *    products and all scalars are computed in FP64.  Every call that takes
+ *    N-vectors has an *_f64 twin with FP64 storage (same semantics), for
+ *    problems whose conditioning needs it.
  */
 #ifndef DSKI_H
 #define DSKI_H
@@ -97,22 +99,34 @@ dski_status dski_set_hypers(dski_plan plan, const double* log_ell_host, double l
 /* Y = K~ V for R vectors (user order).  V and Y must not overlap. */
 dski_status dski_mvm(dski_plan plan, int R, const float* V, int ldv, float* Y, int ldy,
                      dski_stream stream);
+dski_status dski_mvm_f64(dski_plan plan, int R, const double* V, int ldv, double* Y, int ldy,
+                         dski_stream stream);
 
 /* Y = (d K~ / d theta_which) V, which = 0..d+2 in hyper-parameter order
  * (derivative of the approximate kernel, Sec. 3: weights fixed). */
 dski_status dski_mvm_dtheta(dski_plan plan, int which, int R, const float* V, int ldv,
                             float* Y, int ldy, dski_stream stream);
+dski_status dski_mvm_dtheta_f64(dski_plan plan, int which, int R, const double* V, int ldv,
+                                double* Y, int ldy, dski_stream stream);
 
 /* Tile order: the internal point order (sorted by interpolation cell) that the
  * solvers use.  dir = +1: user -> tile, dir = -1: tile -> user.  perm_host (n
  * ints, may be NULL) receives, for tile position k, the user index. */
 dski_status dski_permute(dski_plan plan, int dir, int R, const float* in, int ldi, float* out,
                          int ldo, dski_stream stream);
+dski_status dski_permute_f64(dski_plan plan, int dir, int R, const double* in, int ldi,
+                             double* out, int ldo, dski_stream stream);
 dski_status dski_tile_order(dski_plan plan, int* perm_host);
 
 /* Y = K~ V on tile-ordered vectors (the product the PCG iterations run). */
 dski_status dski_mvm_tiled(dski_plan plan, int R, const float* V, int ldv, float* Y, int ldy,
                            dski_stream stream);
+dski_status dski_mvm_tiled_f64(dski_plan plan, int R, const double* V, int ldv, double* Y,
+                               int ldy, dski_stream stream);
+
+/* Storage precision (32 or 64 bits) of the N-vectors that slq_logdet creates
+ * internally (probes, Krylov vectors).  Default 32. */
+dski_status dski_plan_set_precision(dski_plan plan, int bits);
 
 /* Truncated pivoted Cholesky of the noise-free K (Sec. 3.3; greedy largest
  * residual diagonal, lowest index among exact ties) and the preconditioner
@@ -127,6 +141,8 @@ dski_status dski_precond_destroy(dski_precond pc);
 /* Z = M^{-1} R for R vectors (user order), stable form of Sec. 3.3. */
 dski_status dski_precond_apply(dski_precond pc, int R, const float* Rm, int ld, float* Z,
                                int ldz, dski_stream stream);
+dski_status dski_precond_apply_f64(dski_precond pc, int R, const double* Rm, int ld, double* Z,
+                                   int ldz, dski_stream stream);
 
 /* log det M (host FP64). */
 dski_status dski_precond_logdet(dski_precond pc, double* out_host);
@@ -137,7 +153,10 @@ dski_status dski_precond_factor(dski_precond pc, double* Lout, int ld, dski_stre
 
 /* Preconditioned CG on the R columns of B independently (they share every
  * MVM, not their Krylov spaces), x_0 = 0 (Sec. 2, Sec. 3.3).  Column c stops
- * when ||r||_2 <= tol_host[c] ||b_c||_2 (recurrence residual).
+ * when ||r||_2 <= tol_host[c] ||b_c||_2 (recurrence residual).  The iterate is
+ * accumulated and returned in FP64 (X, N x R, ld >= N): at the conditioning of
+ * these systems an FP32-rounded solution alone would carry a true residual
+ * well above 1e-4.
  *   pc        : NULL = no preconditioner.
  *   iters_host, relres_host : R entries each (may be NULL).
  *   alpha_beta: NULL or a device FP64 buffer of 2*max_iter*R entries that
@@ -145,9 +164,13 @@ dski_status dski_precond_factor(dski_precond pc, double* Lout, int ld, dski_stre
  *               [R*max_iter + c*max_iter + j]) for the Lanczos tridiagonal.
  * Returns DSKI_NOT_CONVERGED if a column reached max_iter. */
 dski_status pcg_solve(dski_plan plan, dski_precond pc, int R, const float* B, int ldb,
-                      float* X, int ldx, const double* tol_host, int max_iter,
+                      double* X, int ldx, const double* tol_host, int max_iter,
                       int* iters_host, double* relres_host, double* alpha_beta,
                       dski_stream stream);
+dski_status pcg_solve_f64(dski_plan plan, dski_precond pc, int R, const double* B, int ldb,
+                          double* X, int ldx, const double* tol_host, int max_iter,
+                          int* iters_host, double* relres_host, double* alpha_beta,
+                          dski_stream stream);
 
 /* Stochastic Lanczos quadrature estimate of log det K~ (Sec. 2).  Probe i is
  * z_i = C w_i with w_i the Rademacher column i of the SplitMix64 stream
@@ -167,6 +190,10 @@ dski_status mll_and_grad(dski_plan plan, dski_precond pc, int k, const float* y,
                          int num_probes, uint64_t seed, double tol, int max_iter,
                          double* mll_host, double* grad_host, double* logdet_host,
                          int* iters_host, dski_stream stream);
+dski_status mll_and_grad_f64(dski_plan plan, dski_precond pc, int k, const double* y,
+                             int num_probes, uint64_t seed, double tol, int max_iter,
+                             double* mll_host, double* grad_host, double* logdet_host,
+                             int* iters_host, dski_stream stream);
 
 /* out[c*ld + i] = +-1 (FP32): Rademacher column col0+c of the counter-based
  * SplitMix64 stream `seed` (Steele et al. 2014): entry i of column c is -1

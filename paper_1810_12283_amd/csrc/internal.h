@@ -77,6 +77,7 @@ struct dski_plan_s {
   dski::DevBuf vin, vout;      // tile-ordered FP32 vectors
   dski::DevBuf partial;        // FP64 block partials
   dski::DevBuf scal;           // FP64 small scalars
+  int precision = 32;          // storage of N-vectors inside slq_logdet (32 or 64)
 };
 
 struct dski_precond_s {
@@ -86,6 +87,7 @@ struct dski_precond_s {
   int* piv_tile = nullptr;     // device, k pivots (tile-order N-index)
   double* L = nullptr;         // device, N x k FP64 (tile order, column-major)
   float* U = nullptr;          // device, N x k FP32 left singular vectors of D^{-1/2} L
+  double* Ud = nullptr;        // device, the same in FP64 (for the FP64-storage path)
   double* c = nullptr;         // device, k: 1 - (1 + sigma_i^2)^{-1/2}
   double* rootc = nullptr;     // device, k: sqrt(1 + sigma_i^2) - 1
   dski::DevBuf work;
@@ -96,25 +98,34 @@ namespace dski {
 constexpr int kBlock = 256;
 
 // --- plan / grid ------------------------------------------------------------------
+// T is the storage type of N-vectors (float or double); grids are FP64.
 dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich = -1);
-dski_status scatter(dski_plan p, int R, const float* V, int ldv, double* G, hipStream_t st);
-dski_status gather(dski_plan p, int R, const double* G, const float* V, int ldv, float* Y,
-                   int ldy, double nv, double ng, double* pq_partial, hipStream_t st);
-dski_status mvm_dtheta(dski_plan p, int which, int R, const float* V, int ldv, float* Y, int ldy,
+template <typename T>
+dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st);
+template <typename T>
+dski_status gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
+                   double nv, double ng, double* pq_partial, hipStream_t st);
+template <typename T>
+dski_status mvm_dtheta(dski_plan p, int which, int R, const T* V, int ldv, T* Y, int ldy,
                        hipStream_t st);
 int gather_blocks(dski_plan p);
-dski_status mvm_tiled(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
-                      double* pq_partial, hipStream_t st);
+template <typename T>
+dski_status mvm_tiled(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double* pq_partial,
+                      hipStream_t st);
 dski_status permute(dski_plan p, int dir, int R, const float* in, int ldi, float* out, int ldo,
+                    hipStream_t st);
+dski_status permute(dski_plan p, int dir, int R, const double* in, int ldi, double* out, int ldo,
                     hipStream_t st);
 
 // --- preconditioner -----------------------------------------------------------------
 // Z = M^{-1} Rm (tile order).  rz_partial (optional): block partials of sum Rm*Z per column.
-dski_status precond_apply_tiled(dski_precond pc, int R, const float* Rm, int ld, float* Z,
-                                int ldz, double* rz_partial, int* nblk_out, hipStream_t st);
+template <typename T>
+dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* Z, int ldz,
+                                double* rz_partial, int* nblk_out, hipStream_t st);
 // Z = C W with C C^T = M (tile order).
-dski_status precond_factor_apply_tiled(dski_precond pc, int R, const float* W, int ld, float* Z,
-                                       int ldz, hipStream_t st);
+template <typename T>
+dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int ld, T* Z, int ldz,
+                                       hipStream_t st);
 int vec_blocks(int N);
 
 // --- PCG core (tile order) -----------------------------------------------------------
@@ -124,17 +135,19 @@ struct PcgResult {
   std::vector<double> rz0;     // r_0^T M^{-1} r_0 per column
   bool breakdown = false;
 };
-dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int ldb, float* X,
-                      int ldx, const double* tol_host, int max_iter, int fixed_iters,
-                      double* alpha_beta, PcgResult& res, hipStream_t st);
+// X (storage type, may be NULL) and/or X64 (FP64, may be NULL) receive the iterate.
+template <typename T>
+dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
+                      const double* tol_host, int max_iter, int fixed_iters, double* alpha_beta,
+                      PcgResult& res, hipStream_t st, double* X64 = nullptr);
 
 // --- host numerics ---------------------------------------------------------------------
 double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok);
 int sym_eig_jacobi(int k, double* A, double* V, double* w);
 
 // --- rng ---------------------------------------------------------------------------------
-dski_status rademacher(uint64_t seed, int col0, int ncols, int N, float* out, int ld,
-                       hipStream_t st);
+template <typename T>
+dski_status rademacher(uint64_t seed, int col0, int ncols, int N, T* out, int ld, hipStream_t st);
 
 // deterministic reductions
 dski_status reduce_partials(const double* partial, int nblk, int ncol, double* out,

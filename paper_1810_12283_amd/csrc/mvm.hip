@@ -71,13 +71,13 @@ static GeoK geo_of(dski_plan p) {
 //   w(x_k)_j V_0[k] + sum_q d_q w(x_k)_j V_q[k].
 // Cell c (1-based per axis) covers nodes c-1..c+2, so node j is touched by
 // cells j-2..j+1 (clipped to 1..m-3); its stencil position in cell c is j-c+1.
-template <int D, int RB>
+// One launch handles all R columns, RB at a time.
+template <int D, int RB, typename T>
 __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ cell,
                                                  const float* __restrict__ toff,
                                                  const int* __restrict__ cstart, int n, GeoK g,
-                                                 const float* __restrict__ V, int ldv, int r0,
-                                                 int rcount, double* __restrict__ G,
-                                                 long long M) {
+                                                 const T* __restrict__ V, int ldv, int R,
+                                                 double* __restrict__ G, long long M) {
   int j[D];
   if (D == 1) {
     j[0] = blockIdx.x * 256 + threadIdx.x;
@@ -92,9 +92,6 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ cell,
     j[0] = (blockIdx.y / ((g.m[1] + 7) / 8)) * 4 + (threadIdx.x >> 6);
     if (j[0] >= g.m[0] || j[1] >= g.m[1] || j[2] >= g.m[2]) return;
   }
-  double acc[RB];
-#pragma unroll
-  for (int r = 0; r < RB; ++r) acc[r] = 0.0;
   int lo[D], hi[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -102,96 +99,100 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ cell,
     hi[a] = min(g.nc[a], j[a] + 1);
   }
   const int last = D - 1;
-  const float* Vr = V + (size_t)r0 * ldv;
-  // iterate over the outer cell coordinates; the innermost axis is a contiguous run
-  int outer_cnt = 1;
-#pragma unroll
-  for (int a = 0; a < last; ++a) outer_cnt *= (hi[a] >= lo[a] ? hi[a] - lo[a] + 1 : 0);
-  for (int oc = 0; oc < outer_cnt; ++oc) {
-    int c[D];
-    int rem = oc;
-    int base = 0;
-#pragma unroll
-    for (int a = last - 1; a >= 0; --a) {
-      int span = hi[a] - lo[a] + 1;
-      c[a] = lo[a] + rem % span;
-      rem /= span;
-    }
-#pragma unroll
-    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
-    base *= g.nc[last];
-    int kb = cstart[base + lo[last] - 1];
-    int ke = cstart[base + hi[last]];
-    for (int k = kb; k < ke; ++k) {
-      int cl = cell[k];
-      int clast = cl % g.nc[last] + 1;
-      double wv[D], wd[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        int ca = (a == last) ? clast : c[a];
-        int o = j[a] - ca + 1;
-        double t = (double)toff[(size_t)a * n + k];
-        wv[a] = keys_w1(o, t);
-        wd[a] = keys_dw1(o, t) * g.invh[a];
-      }
-      double wprod = 1.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) wprod *= wv[a];
-      double dprod[D];
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        double v = 1.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) v *= (a == q) ? wd[a] : wv[a];
-        dprod[q] = v;
-      }
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        if (r < rcount) {
-          const float* vv = Vr + (size_t)r * ldv + k;
-          double a = wprod * (double)vv[0];
-#pragma unroll
-          for (int q = 0; q < D; ++q) a += dprod[q] * (double)vv[(size_t)(q + 1) * n];
-          acc[r] += a;
-        }
-      }
-    }
-  }
   long long node = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
+  // the innermost cell axis is a contiguous run of points in tile order
+  int outer_cnt = 1;
 #pragma unroll
-  for (int r = 0; r < RB; ++r)
-    if (r < rcount) G[(size_t)(r0 + r) * M + node] = acc[r];
+  for (int a = 0; a < last; ++a) outer_cnt *= hi[a] - lo[a] + 1;
+  for (int r0 = 0; r0 < R; r0 += RB) {
+    const int rcount = min(RB, R - r0);
+    double acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+    const T* Vr = V + (size_t)r0 * ldv;
+    for (int oc = 0; oc < outer_cnt; ++oc) {
+      int c[D];
+      int rem = oc;
+      int base = 0;
+#pragma unroll
+      for (int a = last - 1; a >= 0; --a) {
+        int span = hi[a] - lo[a] + 1;
+        c[a] = lo[a] + rem % span;
+        rem /= span;
+      }
+#pragma unroll
+      for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+      base *= g.nc[last];
+      int kb = cstart[base + lo[last] - 1];
+      int ke = cstart[base + hi[last]];
+      for (int k = kb; k < ke; ++k) {
+        int cl = cell[k];
+        int clast = cl % g.nc[last] + 1;
+        double wv[D], wd[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          int ca = (a == last) ? clast : c[a];
+          int o = j[a] - ca + 1;
+          double t = (double)toff[(size_t)a * n + k];
+          wv[a] = keys_w1(o, t);
+          wd[a] = keys_dw1(o, t) * g.invh[a];
+        }
+        double wprod = 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) wprod *= wv[a];
+        double dprod[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          double v = 1.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) v *= (a == q) ? wd[a] : wv[a];
+          dprod[q] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          if (r < rcount) {
+            const T* vv = Vr + (size_t)r * ldv + k;
+            double a = wprod * (double)vv[0];
+#pragma unroll
+            for (int q = 0; q < D; ++q) a += dprod[q] * (double)vv[(size_t)(q + 1) * n];
+            acc[r] += a;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < rcount) G[(size_t)(r0 + r) * M + node] = acc[r];
+  }
 }
 
-template <int D>
-static void launch_scatter(dski_plan p, int R, const float* V, int ldv, double* G,
-                           hipStream_t st) {
+template <int D, typename T>
+static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
   GeoK g = geo_of(p);
   dim3 grid;
   if (D == 1) grid = dim3((g.m[0] + 255) / 256);
   if (D == 2) grid = dim3((g.m[1] + 15) / 16, (g.m[0] + 15) / 16);
   if (D == 3) grid = dim3((g.m[2] + 7) / 8, ((g.m[1] + 7) / 8) * ((g.m[0] + 3) / 4));
-  constexpr int RB = 8;
-  for (int r0 = 0; r0 < R; r0 += RB) {
-    int rc = R - r0 < RB ? R - r0 : RB;
-    k_scatter<D, RB><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv, r0,
-                                           rc, G, p->M);
-  }
+  k_scatter<D, 8, T><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv, R, G,
+                                           p->M);
 }
 
-dski_status scatter(dski_plan p, int R, const float* V, int ldv, double* G, hipStream_t st) {
+template <typename T>
+dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
   if (R <= 0) return DSKI_OK;
   switch (p->d) {
-    case 1: launch_scatter<1>(p, R, V, ldv, G, st); break;
-    case 2: launch_scatter<2>(p, R, V, ldv, G, st); break;
-    case 3: launch_scatter<3>(p, R, V, ldv, G, st); break;
+    case 1: launch_scatter<1, T>(p, R, V, ldv, G, st); break;
+    case 2: launch_scatter<2, T>(p, R, V, ldv, G, st); break;
+    case 3: launch_scatter<3, T>(p, R, V, ldv, G, st); break;
     default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
   }
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
+template dski_status scatter<float>(dski_plan, int, const float*, int, double*, hipStream_t);
+template dski_status scatter<double>(dski_plan, int, const double*, int, double*, hipStream_t);
 
 // ------------------------------------------------------------------ K_UU by FFT
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -373,207 +374,222 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
 }
 
 // ------------------------------------------------------------------ gather + noise
-template <int D, int RB>
+// One thread per point, all R columns in one launch (RB at a time): the 4^d
+// grid values of each column are read once and give the value and all d
+// derivative rows.  Y = S G + D V with FP64 accumulation; optional per-block
+// partials of V.Y per column (the p^T q of CG).
+template <int D, int RB, typename T>
 __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
                                                 const float* __restrict__ toff, int n, GeoK g,
                                                 const double* __restrict__ G, long long M,
-                                                const float* __restrict__ V, int ldv,
-                                                float* __restrict__ Y, int ldy, int r0,
-                                                int rcount, double nv, double ng,
-                                                double* __restrict__ pq_partial, int R) {
+                                                const T* __restrict__ V, int ldv,
+                                                T* __restrict__ Y, int ldy, int R, double nv,
+                                                double ng, double* __restrict__ pq_partial) {
   int k = blockIdx.x * 256 + threadIdx.x;
-  double pq[RB];
+  const bool live = k < n;
+  double w[D][4], dw[D][4];
+  long long base = 0;
+  long long stride[D];
+  stride[D - 1] = 1;
 #pragma unroll
-  for (int r = 0; r < RB; ++r) pq[r] = 0.0;
-  if (k < n) {
-    int cl = cell[k];
+  for (int a = D - 2; a >= 0; --a) stride[a] = stride[a + 1] * g.m[a + 1];
+  if (live) {
     int c[D];
-    {
-      int rem = cl;
+    int rem = cell[k];
 #pragma unroll
-      for (int a = D - 1; a >= 0; --a) {
-        c[a] = rem % g.nc[a] + 1;
-        rem /= g.nc[a];
-      }
+    for (int a = D - 1; a >= 0; --a) {
+      c[a] = rem % g.nc[a] + 1;
+      rem /= g.nc[a];
     }
-    double w[D][4], dw[D][4];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       keys_weights((double)toff[(size_t)a * n + k], w[a], dw[a]);
 #pragma unroll
       for (int o = 0; o < 4; ++o) dw[a][o] *= g.invh[a];
     }
-    long long base = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) base = base * g.m[a] + (c[a] - 1);
-    long long stride[D];
-    stride[D - 1] = 1;
+  }
+  __shared__ double red[RB][4];
+  for (int r0 = 0; r0 < R; r0 += RB) {
+    const int rcount = min(RB, R - r0);
+    double pq[RB];
 #pragma unroll
-    for (int a = D - 2; a >= 0; --a) stride[a] = stride[a + 1] * g.m[a + 1];
+    for (int r = 0; r < RB; ++r) pq[r] = 0.0;
+    if (live) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      if (r < rcount) {
-        const double* Gr = G + (size_t)(r0 + r) * M + base;
-        double acc[D + 1];
+      for (int r = 0; r < RB; ++r) {
+        if (r < rcount) {
+          const double* Gr = G + (size_t)(r0 + r) * M + base;
+          double acc[D + 1];
 #pragma unroll
-        for (int q = 0; q <= D; ++q) acc[q] = 0.0;
-        if (D == 1) {
+          for (int q = 0; q <= D; ++q) acc[q] = 0.0;
+          if (D == 1) {
 #pragma unroll
-          for (int o0 = 0; o0 < 4; ++o0) {
-            double gv = Gr[o0];
-            acc[0] += w[0][o0] * gv;
-            acc[1] += dw[0][o0] * gv;
-          }
-        } else if (D == 2) {
-#pragma unroll
-          for (int o0 = 0; o0 < 4; ++o0) {
-            double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-            for (int o1 = 0; o1 < 4; ++o1) {
-              double gv = Gr[o0 * stride[0] + o1];
-              s0 += w[D - 1][o1] * gv;
-              s1 += dw[D - 1][o1] * gv;
+            for (int o0 = 0; o0 < 4; ++o0) {
+              double gv = Gr[o0];
+              acc[0] += w[0][o0] * gv;
+              acc[1] += dw[0][o0] * gv;
             }
-            acc[0] += w[0][o0] * s0;
-            acc[1] += dw[0][o0] * s0;
-            acc[2] += w[0][o0] * s1;
-          }
-        } else {
+          } else if (D == 2) {
 #pragma unroll
-          for (int o0 = 0; o0 < 4; ++o0) {
-            double t0 = 0.0, t1 = 0.0, t2 = 0.0;  // value, d/dx1, d/dx2 over axes 1,2
+            for (int o0 = 0; o0 < 4; ++o0) {
+              double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int o1 = 0; o1 < 4; ++o1) {
-              double s0 = 0.0, s2 = 0.0;
-#pragma unroll
-              for (int o2 = 0; o2 < 4; ++o2) {
-                double gv = Gr[o0 * stride[0] + o1 * stride[1] + o2];
-                s0 += w[D - 1][o2] * gv;
-                s2 += dw[D - 1][o2] * gv;
+              for (int o1 = 0; o1 < 4; ++o1) {
+                double gv = Gr[o0 * stride[0] + o1];
+                s0 += w[D - 1][o1] * gv;
+                s1 += dw[D - 1][o1] * gv;
               }
-              t0 += w[1][o1] * s0;
-              t1 += dw[1][o1] * s0;
-              t2 += w[1][o1] * s2;
+              acc[0] += w[0][o0] * s0;
+              acc[1] += dw[0][o0] * s0;
+              acc[2] += w[0][o0] * s1;
             }
-            acc[0] += w[0][o0] * t0;
-            acc[1] += dw[0][o0] * t0;
-            acc[2] += w[0][o0] * t1;
-            acc[3] += w[0][o0] * t2;
-          }
-        }
-        const float* vv = V + (size_t)(r0 + r) * ldv + k;
-        float* yy = Y + (size_t)(r0 + r) * ldy + k;
-        double dot = 0.0;
+          } else {
 #pragma unroll
-        for (int q = 0; q <= D; ++q) {
-          double vin = (double)vv[(size_t)q * n];
-          float out = (float)(acc[q] + (q == 0 ? nv : ng) * vin);
-          yy[(size_t)q * n] = out;
-          dot += vin * (double)out;
+            for (int o0 = 0; o0 < 4; ++o0) {
+              double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+              for (int o1 = 0; o1 < 4; ++o1) {
+                double s0 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int o2 = 0; o2 < 4; ++o2) {
+                  double gv = Gr[o0 * stride[0] + o1 * stride[1] + o2];
+                  s0 += w[D - 1][o2] * gv;
+                  s2 += dw[D - 1][o2] * gv;
+                }
+                t0 += w[1][o1] * s0;
+                t1 += dw[1][o1] * s0;
+                t2 += w[1][o1] * s2;
+              }
+              acc[0] += w[0][o0] * t0;
+              acc[1] += dw[0][o0] * t0;
+              acc[2] += w[0][o0] * t1;
+              acc[3] += w[0][o0] * t2;
+            }
+          }
+          const T* vv = V + (size_t)(r0 + r) * ldv + k;
+          T* yy = Y + (size_t)(r0 + r) * ldy + k;
+          double dot = 0.0;
+#pragma unroll
+          for (int q = 0; q <= D; ++q) {
+            double vin = (double)vv[(size_t)q * n];
+            T out = (T)(acc[q] + (q == 0 ? nv : ng) * vin);
+            yy[(size_t)q * n] = out;
+            dot += vin * (double)out;
+          }
+          pq[r] = dot;
         }
-        pq[r] = dot;
       }
     }
-  }
-  if (pq_partial) {
-    __shared__ double red[RB][4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (pq_partial) {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      double v = pq[r];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) red[r][wv] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < RB && threadIdx.x < rcount) {
-      int r = threadIdx.x;
-      pq_partial[(size_t)blockIdx.x * R + r0 + r] = red[r][0] + red[r][1] + red[r][2] + red[r][3];
+      for (int r = 0; r < RB; ++r) {
+        double v = pq[r];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[r][wv] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < rcount) {
+        int r = threadIdx.x;
+        pq_partial[(size_t)blockIdx.x * R + r0 + r] = red[r][0] + red[r][1] + red[r][2] + red[r][3];
+      }
+      __syncthreads();
     }
   }
 }
 
 int gather_blocks(dski_plan p) { return (p->n + 255) / 256; }
 
-template <int D>
-static void launch_gather(dski_plan p, int R, const double* G, const float* V, int ldv, float* Y,
-                          int ldy, double nv, double ng, double* pq_partial, hipStream_t st) {
+template <int D, typename T>
+static void launch_gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
+                          double nv, double ng, double* pq_partial, hipStream_t st) {
   GeoK g = geo_of(p);
-  constexpr int RB = 8;
-  int blocks = gather_blocks(p);
-  for (int r0 = 0; r0 < R; r0 += RB) {
-    int rc = R - r0 < RB ? R - r0 : RB;
-    k_gather<D, RB><<<blocks, 256, 0, st>>>(p->cell, p->toff, p->n, g, G, p->M, V, ldv, Y, ldy, r0,
-                                            rc, nv, ng, pq_partial, R);
-  }
+  k_gather<D, 8, T><<<gather_blocks(p), 256, 0, st>>>(p->cell, p->toff, p->n, g, G, p->M, V, ldv, Y,
+                                                      ldy, R, nv, ng, pq_partial);
 }
 
-dski_status gather(dski_plan p, int R, const double* G, const float* V, int ldv, float* Y,
-                           int ldy, double nv, double ng, double* pq_partial, hipStream_t st) {
+template <typename T>
+dski_status gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy, double nv,
+                   double ng, double* pq_partial, hipStream_t st) {
   if (R <= 0 || p->n == 0) return DSKI_OK;
   switch (p->d) {
-    case 1: launch_gather<1>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
-    case 2: launch_gather<2>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
-    case 3: launch_gather<3>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 1: launch_gather<1, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 2: launch_gather<2, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 3: launch_gather<3, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
     default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
   }
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
 
-dski_status mvm_tiled(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
-                      double* pq_partial, hipStream_t st) {
+template dski_status gather<float>(dski_plan, int, const double*, const float*, int, float*, int,
+                                   double, double, double*, hipStream_t);
+template dski_status gather<double>(dski_plan, int, const double*, const double*, int, double*, int,
+                                    double, double, double*, hipStream_t);
+
+template <typename T>
+dski_status mvm_tiled(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double* pq_partial,
+                      hipStream_t st) {
   if (R <= 0) return DSKI_OK;
   DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
   double* G = p->grid.as<double>();
-  DSKI_TRY(scatter(p, R, V, ldv, G, st));
+  DSKI_TRY(scatter<T>(p, R, V, ldv, G, st));
   DSKI_TRY(apply_kuu(p, R, G, st));
-  return gather(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, pq_partial, st);
+  return gather<T>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, pq_partial, st);
 }
+template dski_status mvm_tiled<float>(dski_plan, int, const float*, int, float*, int, double*,
+                                      hipStream_t);
+template dski_status mvm_tiled<double>(dski_plan, int, const double*, int, double*, int, double*,
+                                       hipStream_t);
 
-__global__ void k_noise_deriv(const float* __restrict__ V, int ldv, float* __restrict__ Y,
-                              int ldy, int n, int N, int R, double cv, double cg) {
+template <typename T>
+__global__ void k_noise_deriv(const T* __restrict__ V, int ldv, T* __restrict__ Y, int ldy, int n,
+                              int N, int R, double cv, double cg) {
   size_t tot = (size_t)N * R;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
     int i = (int)(e % N);
     int r = (int)(e / N);
     double c = i < n ? cv : cg;
-    Y[(size_t)r * ldy + i] = (float)(c * (double)V[(size_t)r * ldv + i]);
+    Y[(size_t)r * ldy + i] = (T)(c * (double)V[(size_t)r * ldv + i]);
   }
 }
 
-static dski_status mvm_dtheta_tiled(dski_plan p, int which, int R, const float* V, int ldv,
-                                    float* Y, int ldy, hipStream_t st) {
+// Y = dK~/dtheta_which V on tile-ordered vectors: for ell_p the derivative
+// spectrum on axis p, for s the factor 2 of K_UU, for the noise levels the
+// diagonal 2 sigma^2 on the value or gradient rows.
+template <typename T>
+dski_status mvm_dtheta(dski_plan p, int which, int R, const T* V, int ldv, T* Y, int ldy,
+                       hipStream_t st) {
   if (R <= 0) return DSKI_OK;
   int d = p->d;
+  size_t tot = (size_t)p->N * R;
+  int blocks = (int)std::min<size_t>((tot + 255) / 256, 65535 * 8);
   if (which <= d) {
     DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
     double* G = p->grid.as<double>();
-    DSKI_TRY(scatter(p, R, V, ldv, G, st));
+    DSKI_TRY(scatter<T>(p, R, V, ldv, G, st));
     DSKI_TRY(apply_kuu(p, R, G, st, which < d ? which : -1));
-    // d K_UU / d log s = 2 K_UU: fold the factor 2 into the gather via a second pass
-    DSKI_TRY(gather(p, R, G, V, ldv, Y, ldy, 0.0, 0.0, nullptr, st));
+    DSKI_TRY(gather<T>(p, R, G, V, ldv, Y, ldy, 0.0, 0.0, nullptr, st));
     if (which == d) {
-      size_t tot = (size_t)p->N * R;
-      int blocks = (int)std::min<size_t>((tot + 255) / 256, 65535 * 8);
-      k_noise_deriv<<<blocks, 256, 0, st>>>(Y, ldy, Y, ldy, p->N, p->N, R, 2.0, 2.0);
+      k_noise_deriv<T><<<blocks, 256, 0, st>>>(Y, ldy, Y, ldy, p->N, p->N, R, 2.0, 2.0);
       DSKI_HIP(hipGetLastError());
     }
     return DSKI_OK;
   }
   double cv = which == d + 1 ? 2.0 * p->sf * p->sf : 0.0;
   double cg = which == d + 2 ? 2.0 * p->sg * p->sg : 0.0;
-  size_t tot = (size_t)p->N * R;
-  int blocks = (int)std::min<size_t>((tot + 255) / 256, 65535 * 8);
-  k_noise_deriv<<<blocks, 256, 0, st>>>(V, ldv, Y, ldy, p->n, p->N, R, cv, cg);
+  k_noise_deriv<T><<<blocks, 256, 0, st>>>(V, ldv, Y, ldy, p->n, p->N, R, cv, cg);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
 
-dski_status mvm_dtheta(dski_plan p, int which, int R, const float* V, int ldv, float* Y, int ldy,
-                       hipStream_t st) {
-  return mvm_dtheta_tiled(p, which, R, V, ldv, Y, ldy, st);
-}
+template dski_status mvm_dtheta<float>(dski_plan, int, int, const float*, int, float*, int,
+                                       hipStream_t);
+template dski_status mvm_dtheta<double>(dski_plan, int, int, const double*, int, double*, int,
+                                        hipStream_t);
 
 }  // namespace dski
 
@@ -588,46 +604,68 @@ static dski_status check_mvm_args(dski_plan p, int R, const void* V, int ldv, co
   return DSKI_OK;
 }
 
+template <typename T>
+static dski_status mvm_user(dski_plan p, int which, int R, const T* V, int ldv, T* Y, int ldy,
+                            hipStream_t st) {
+  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
+  if (which < -1 || which > p->d + 2) {
+    set_error("which=%d out of range 0..%d", which, p->d + 2);
+    return DSKI_EINVAL;
+  }
+  if (R == 0 || p->N == 0) return DSKI_OK;
+  size_t nr = (size_t)p->N * R;
+  DSKI_TRY(p->vin.reserve(sizeof(T) * nr));
+  DSKI_TRY(p->vout.reserve(sizeof(T) * nr));
+  T* vi = p->vin.as<T>();
+  T* vo = p->vout.as<T>();
+  DSKI_TRY(permute(p, +1, R, V, ldv, vi, p->N, st));
+  if (which < 0)
+    DSKI_TRY(mvm_tiled<T>(p, R, vi, p->N, vo, p->N, nullptr, st));
+  else
+    DSKI_TRY(mvm_dtheta<T>(p, which, R, vi, p->N, vo, p->N, st));
+  return permute(p, -1, R, vo, p->N, Y, ldy, st);
+}
+
 extern "C" {
 
 dski_status dski_mvm_tiled(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
                            dski_stream stream) {
   DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
-  return mvm_tiled(p, R, V, ldv, Y, ldy, nullptr, static_cast<hipStream_t>(stream));
+  return mvm_tiled<float>(p, R, V, ldv, Y, ldy, nullptr, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_mvm_tiled_f64(dski_plan p, int R, const double* V, int ldv, double* Y, int ldy,
+                               dski_stream stream) {
+  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
+  return mvm_tiled<double>(p, R, V, ldv, Y, ldy, nullptr, static_cast<hipStream_t>(stream));
 }
 
 dski_status dski_mvm(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
                      dski_stream stream) {
-  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
-  if (R == 0 || p->N == 0) return DSKI_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  size_t nr = (size_t)p->N * R;
-  DSKI_TRY(p->vin.reserve(sizeof(float) * nr));
-  DSKI_TRY(p->vout.reserve(sizeof(float) * nr));
-  float* vi = p->vin.as<float>();
-  float* vo = p->vout.as<float>();
-  DSKI_TRY(permute(p, +1, R, V, ldv, vi, p->N, st));
-  DSKI_TRY(mvm_tiled(p, R, vi, p->N, vo, p->N, nullptr, st));
-  return permute(p, -1, R, vo, p->N, Y, ldy, st);
+  return mvm_user<float>(p, -1, R, V, ldv, Y, ldy, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_mvm_f64(dski_plan p, int R, const double* V, int ldv, double* Y, int ldy,
+                         dski_stream stream) {
+  return mvm_user<double>(p, -1, R, V, ldv, Y, ldy, static_cast<hipStream_t>(stream));
 }
 
 dski_status dski_mvm_dtheta(dski_plan p, int which, int R, const float* V, int ldv, float* Y,
                             int ldy, dski_stream stream) {
-  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
-  if (which < 0 || which > p->d + 2) {
-    set_error("which=%d out of range 0..%d", which, p->d + 2);
+  if (which < 0) {
+    set_error("which=%d out of range", which);
     return DSKI_EINVAL;
   }
-  if (R == 0 || p->N == 0) return DSKI_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  size_t nr = (size_t)p->N * R;
-  DSKI_TRY(p->vin.reserve(sizeof(float) * nr));
-  DSKI_TRY(p->vout.reserve(sizeof(float) * nr));
-  float* vi = p->vin.as<float>();
-  float* vo = p->vout.as<float>();
-  DSKI_TRY(permute(p, +1, R, V, ldv, vi, p->N, st));
-  DSKI_TRY(mvm_dtheta(p, which, R, vi, p->N, vo, p->N, st));
-  return permute(p, -1, R, vo, p->N, Y, ldy, st);
+  return mvm_user<float>(p, which, R, V, ldv, Y, ldy, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_mvm_dtheta_f64(dski_plan p, int which, int R, const double* V, int ldv, double* Y,
+                                int ldy, dski_stream stream) {
+  if (which < 0) {
+    set_error("which=%d out of range", which);
+    return DSKI_EINVAL;
+  }
+  return mvm_user<double>(p, which, R, V, ldv, Y, ldy, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

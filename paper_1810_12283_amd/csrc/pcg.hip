@@ -1,7 +1,7 @@
 // Preconditioned conjugate gradients on a block of R right-hand sides (Sec. 2,
 // Sec. 3.3).  The columns are independent CG runs that share every MVM (the
 // block is not a block-Krylov method, so each column keeps its own Lanczos
-// tridiagonal for quadrature).  Vectors are FP32 in tile order, the iterate x
+// tridiagonal for quadrature).  Vectors are FP32 (or FP64) in tile order, the iterate x
 // is accumulated in FP64, all inner products and scalars are FP64 and live on
 // the device; the host only polls the number of active columns every few
 // iterations.
@@ -28,13 +28,14 @@ constexpr int kVecChunk = 1024;  // elements per work-group in the vector kernel
 static int nchunks(int N) { return (N + kVecChunk - 1) / kVecChunk; }
 
 // R = B, X = 0, partials of b.b
-__global__ void k_pcg_init(const float* __restrict__ B, int ldb, float* __restrict__ Rr,
+template <typename T>
+__global__ void k_pcg_init(const T* __restrict__ B, int ldb, T* __restrict__ Rr,
                            double* __restrict__ Xd, int N, int R, double* __restrict__ partial) {
   int r = blockIdx.y;
   int e0 = blockIdx.x * kVecChunk;
   double acc = 0.0;
   for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
-    float b = B[(size_t)r * ldb + e];
+    T b = B[(size_t)r * ldb + e];
     Rr[(size_t)r * N + e] = b;
     Xd[(size_t)r * N + e] = 0.0;
     acc += (double)b * (double)b;
@@ -100,8 +101,9 @@ __global__ void k_pcg_alpha(const double* __restrict__ pq_part, int nblk, int R,
 }
 
 // x += alpha p (FP64), r -= alpha q; partials of r.r
-__global__ void k_pcg_update_xr(const float* __restrict__ P, const float* __restrict__ Q,
-                                float* __restrict__ Rr, double* __restrict__ Xd, int N, int R,
+template <typename T>
+__global__ void k_pcg_update_xr(const T* __restrict__ P, const T* __restrict__ Q,
+                                T* __restrict__ Rr, double* __restrict__ Xd, int N, int R,
                                 PcgScal s, double* __restrict__ partial) {
   int r = blockIdx.y;
   int e0 = blockIdx.x * kVecChunk;
@@ -111,7 +113,7 @@ __global__ void k_pcg_update_xr(const float* __restrict__ P, const float* __rest
     for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
       size_t i = (size_t)r * N + e;
       Xd[i] += a * (double)P[i];
-      float rn = (float)((double)Rr[i] - a * (double)Q[i]);
+      T rn = (T)((double)Rr[i] - a * (double)Q[i]);
       Rr[i] = rn;
       acc += (double)rn * (double)rn;
     }
@@ -154,34 +156,38 @@ __global__ void k_pcg_beta(const double* __restrict__ rz_part, int nblk, int R, 
   }
 }
 
-__global__ void k_pcg_update_p(const float* __restrict__ Z, float* __restrict__ P, int N, PcgScal s) {
+template <typename T>
+__global__ void k_pcg_update_p(const T* __restrict__ Z, T* __restrict__ P, int N, PcgScal s) {
   int r = blockIdx.y;
   if (!s.active[r]) return;
   double b = s.beta[r];
   int e0 = blockIdx.x * kVecChunk;
   for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
     size_t i = (size_t)r * N + e;
-    P[i] = (float)((double)Z[i] + b * (double)P[i]);
+    P[i] = (T)((double)Z[i] + b * (double)P[i]);
   }
 }
 
-__global__ void k_copy_f(const float* __restrict__ a, float* __restrict__ b, int N, int R) {
+template <typename T>
+__global__ void k_copy_f(const T* __restrict__ a, T* __restrict__ b, int N, int R) {
   int r = blockIdx.y;
   int e0 = blockIdx.x * kVecChunk;
   for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x)
     b[(size_t)r * N + e] = a[(size_t)r * N + e];
 }
 
-__global__ void k_x_out(const double* __restrict__ Xd, int N, float* __restrict__ X, int ldx) {
+template <typename TO>
+__global__ void k_x_out(const double* __restrict__ Xd, int N, TO* __restrict__ X, int ldx) {
   int r = blockIdx.y;
   int e0 = blockIdx.x * kVecChunk;
   for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x)
-    X[(size_t)r * ldx + e] = (float)Xd[(size_t)r * N + e];
+    X[(size_t)r * ldx + e] = (TO)Xd[(size_t)r * N + e];
 }
 
-dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int ldb, float* X, int ldx,
+template <typename T>
+dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
                       const double* tol_host, int max_iter, int fixed_iters, double* alpha_beta,
-                      PcgResult& res, hipStream_t st) {
+                      PcgResult& res, hipStream_t st, double* X64) {
   int N = p->N;
   res.iters.assign(R, 0);
   res.relres.assign(R, 0.0);
@@ -193,16 +199,16 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int l
   int nbg = gather_blocks(p);
   int nbz = vec_blocks(N);
   int npart = std::max(nbv, std::max(nbg, nbz));
-  size_t fbytes = sizeof(float) * nr * 4;
+  size_t fbytes = sizeof(T) * nr * 4;
   size_t dbytes = sizeof(double) * (nr + (size_t)npart * R * 2 + 8 * (size_t)R + 8);
   size_t ibytes = sizeof(int) * (2 * (size_t)R + 8);
   DevBuf& wb = p->vin;  // shares the plan's vector workspace
   DSKI_TRY(wb.reserve(fbytes + dbytes + ibytes + 512));
   char* base = wb.as<char>();
-  float* Rr = reinterpret_cast<float*>(base);
-  float* Z = Rr + nr;
-  float* P = Z + nr;
-  float* Q = P + nr;
+  T* Rr = reinterpret_cast<T*>(base);
+  T* Z = Rr + nr;
+  T* P = Z + nr;
+  T* Q = P + nr;
   double* Xd = reinterpret_cast<double*>(Q + nr);
   double* part1 = Xd + nr;
   double* part2 = part1 + (size_t)npart * R;
@@ -222,17 +228,17 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int l
   DSKI_HIP(hipMemcpyAsync(s.tol2, tol2.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
   DSKI_HIP(hipMemsetAsync(s.flags, 0, sizeof(int) * 2, st));
   dim3 vg(nbv, R);
-  k_pcg_init<<<vg, kBlock, 0, st>>>(B, ldb, Rr, Xd, N, R, part1);
+  k_pcg_init<T><<<vg, kBlock, 0, st>>>(B, ldb, Rr, Xd, N, R, part1);
   // z = M^{-1} r, p = z
   const double* rzp = nullptr;
-  float* Zuse = Rr;
+  T* Zuse = Rr;
   int nbzz = 0;
   if (pc) {
-    DSKI_TRY(precond_apply_tiled(pc, R, Rr, N, Z, N, part2, &nbzz, st));
+    DSKI_TRY(precond_apply_tiled<T>(pc, R, Rr, N, Z, N, part2, &nbzz, st));
     rzp = part2;
     Zuse = Z;
   }
-  k_copy_f<<<vg, kBlock, 0, st>>>(Zuse, P, N, R);
+  k_copy_f<T><<<vg, kBlock, 0, st>>>(Zuse, P, N, R);
   k_pcg_init_scal<<<R, kBlock, 0, st>>>(part1, nbv, rzp, nbzz, R, fixed_iters, s, rz0);
   DSKI_HIP(hipGetLastError());
   int* hflags = nullptr;
@@ -244,19 +250,19 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int l
   while (it < limit) {
     int burst = std::min(check, limit - it);
     for (int b = 0; b < burst; ++b) {
-      rc = mvm_tiled(p, R, P, N, Q, N, part1, st);
+      rc = mvm_tiled<T>(p, R, P, N, Q, N, part1, st);
       if (rc < 0) break;
       k_pcg_alpha<<<R, kBlock, 0, st>>>(part1, nbg, R, s, alpha_beta, max_iter);
-      k_pcg_update_xr<<<vg, kBlock, 0, st>>>(P, Q, Rr, Xd, N, R, s, part2);
+      k_pcg_update_xr<T><<<vg, kBlock, 0, st>>>(P, Q, Rr, Xd, N, R, s, part2);
       k_pcg_rr<<<R, kBlock, 0, st>>>(part2, nbv, R, s);
       if (pc) {
-        rc = precond_apply_tiled(pc, R, Rr, N, Z, N, part1, &nbzz, st);
+        rc = precond_apply_tiled<T>(pc, R, Rr, N, Z, N, part1, &nbzz, st);
         if (rc < 0) break;
         k_pcg_beta<<<R, kBlock, 0, st>>>(part1, nbzz, R, s, alpha_beta, max_iter, fixed_iters);
-        k_pcg_update_p<<<vg, kBlock, 0, st>>>(Z, P, N, s);
+        k_pcg_update_p<T><<<vg, kBlock, 0, st>>>(Z, P, N, s);
       } else {
         k_pcg_beta<<<R, kBlock, 0, st>>>(nullptr, 0, R, s, alpha_beta, max_iter, fixed_iters);
-        k_pcg_update_p<<<vg, kBlock, 0, st>>>(Rr, P, N, s);
+        k_pcg_update_p<T><<<vg, kBlock, 0, st>>>(Rr, P, N, s);
       }
     }
     if (rc < 0) break;
@@ -282,7 +288,8 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int l
   }
   (void)hipHostFree(hflags);
   if (rc < 0 && rc != DSKI_EBREAKDOWN) return rc;
-  k_x_out<<<vg, kBlock, 0, st>>>(Xd, N, X, ldx);
+  if (X) k_x_out<T><<<vg, kBlock, 0, st>>>(Xd, N, X, ldx);
+  if (X64) k_x_out<double><<<vg, kBlock, 0, st>>>(Xd, N, X64, ldx);
   DSKI_HIP(hipGetLastError());
   std::vector<double> hrr(R), hbb(R), hrz0(R);
   DSKI_HIP(hipMemcpyAsync(res.iters.data(), s.iters, sizeof(int) * R, hipMemcpyDeviceToHost, st));
@@ -302,30 +309,35 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const float* B, int l
   return notconv ? DSKI_NOT_CONVERGED : DSKI_OK;
 }
 
+template dski_status pcg_tiled<float>(dski_plan, dski_precond, int, const float*, int, float*, int,
+                                      const double*, int, int, double*, PcgResult&, hipStream_t, double*);
+template dski_status pcg_tiled<double>(dski_plan, dski_precond, int, const double*, int, double*, int,
+                                       const double*, int, int, double*, PcgResult&, hipStream_t,
+                                       double*);
+
 }  // namespace dski
 
 using namespace dski;
 
-extern "C" {
-
-dski_status pcg_solve(dski_plan p, dski_precond pc, int R, const float* B, int ldb, float* X, int ldx,
-                      const double* tol_host, int max_iter, int* iters_host, double* relres_host,
-                      double* alpha_beta, dski_stream stream) {
+template <typename T>
+static dski_status pcg_user(dski_plan p, dski_precond pc, int R, const T* B, int ldb, double* X, int ldx,
+                            const double* tol_host, int max_iter, int* iters_host, double* relres_host,
+                            double* alpha_beta, hipStream_t st) {
   if (!p || R < 0 || ldb < p->N || ldx < p->N || (R > 0 && (!B || !X || !tol_host)) || max_iter < 0 ||
       (pc && pc->plan != p)) {
     set_error("pcg_solve: bad arguments");
     return DSKI_EINVAL;
   }
-  if (R == 0) return DSKI_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (R == 0 || p->N == 0) return DSKI_OK;
   size_t nr = (size_t)p->N * R;
-  // user -> tile order (B into vout; the PCG uses vin as workspace)
-  DSKI_TRY(p->vout.reserve(sizeof(float) * nr * 2));
-  float* Bt = p->vout.as<float>();
-  float* Xt = Bt + nr;
+  // user -> tile order (B and X in vout; the PCG itself uses vin as workspace)
+  DSKI_TRY(p->vout.reserve(sizeof(T) * nr + sizeof(double) * nr + 64));
+  T* Bt = p->vout.as<T>();
+  double* Xt = reinterpret_cast<double*>(p->vout.as<char>() + ((sizeof(T) * nr + 63) / 64) * 64);
   DSKI_TRY(permute(p, +1, R, B, ldb, Bt, p->N, st));
   PcgResult res;
-  dski_status rc = pcg_tiled(p, pc, R, Bt, p->N, Xt, p->N, tol_host, max_iter, 0, alpha_beta, res, st);
+  dski_status rc =
+      pcg_tiled<T>(p, pc, R, Bt, p->N, nullptr, p->N, tol_host, max_iter, 0, alpha_beta, res, st, Xt);
   if (rc < 0 && rc != DSKI_EBREAKDOWN) return rc;
   DSKI_TRY(permute(p, -1, R, Xt, p->N, X, ldx, st));
   DSKI_HIP(hipStreamSynchronize(st));
@@ -334,6 +346,22 @@ dski_status pcg_solve(dski_plan p, dski_precond pc, int R, const float* B, int l
     if (relres_host) relres_host[r] = res.relres[r];
   }
   return rc;
+}
+
+extern "C" {
+
+dski_status pcg_solve(dski_plan p, dski_precond pc, int R, const float* B, int ldb, double* X, int ldx,
+                      const double* tol_host, int max_iter, int* iters_host, double* relres_host,
+                      double* alpha_beta, dski_stream stream) {
+  return pcg_user<float>(p, pc, R, B, ldb, X, ldx, tol_host, max_iter, iters_host, relres_host, alpha_beta,
+                         static_cast<hipStream_t>(stream));
+}
+
+dski_status pcg_solve_f64(dski_plan p, dski_precond pc, int R, const double* B, int ldb, double* X,
+                          int ldx, const double* tol_host, int max_iter, int* iters_host,
+                          double* relres_host, double* alpha_beta, dski_stream stream) {
+  return pcg_user<double>(p, pc, R, B, ldb, X, ldx, tol_host, max_iter, iters_host, relres_host,
+                          alpha_beta, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

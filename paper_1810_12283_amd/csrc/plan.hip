@@ -174,9 +174,9 @@ __global__ void k_spectrum(int m, int L, double h, double ell, double scale,
 }
 
 // Permutation between user order and tile order for R vectors of N = n(d+1).
+template <typename T>
 __global__ void k_permute(const int* __restrict__ perm, int n, int nb, int R, int dir,
-                          const float* __restrict__ in, int ldi, float* __restrict__ out,
-                          int ldo) {
+                          const T* __restrict__ in, int ldi, T* __restrict__ out, int ldo) {
   size_t tot = (size_t)n * nb * R;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -199,8 +199,8 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_rademacher(uint64_t seed, int col0, int ncols, int N, float* __restrict__ out,
-                             int ld) {
+template <typename T>
+__global__ void k_rademacher(uint64_t seed, int col0, int ncols, int N, T* __restrict__ out, int ld) {
   size_t tot = (size_t)N * ncols;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -208,7 +208,7 @@ __global__ void k_rademacher(uint64_t seed, int col0, int ncols, int N, float* _
     int c = (int)(e / N);
     uint64_t ctr = (uint64_t)(col0 + c) * (uint64_t)N + (uint64_t)i;
     uint64_t z = mix64(seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull);
-    out[(size_t)c * ld + i] = (z >> 63) ? -1.0f : 1.0f;
+    out[(size_t)c * ld + i] = (z >> 63) ? (T)-1 : (T)1;
   }
 }
 
@@ -242,23 +242,36 @@ static int grid1d(size_t work, int block = kBlock) {
   return (int)(g == 0 ? 1 : g);
 }
 
-dski_status permute(dski_plan p, int dir, int R, const float* in, int ldi, float* out, int ldo,
-                    hipStream_t st) {
+template <typename T>
+static dski_status permute_t(dski_plan p, int dir, int R, const T* in, int ldi, T* out, int ldo,
+                             hipStream_t st) {
   size_t tot = (size_t)p->N * R;
   if (tot == 0) return DSKI_OK;
-  k_permute<<<grid1d(tot), kBlock, 0, st>>>(p->perm, p->n, p->d + 1, R, dir, in, ldi, out, ldo);
+  k_permute<T><<<grid1d(tot), kBlock, 0, st>>>(p->perm, p->n, p->d + 1, R, dir, in, ldi, out, ldo);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
 
-dski_status rademacher(uint64_t seed, int col0, int ncols, int N, float* out, int ld,
-                       hipStream_t st) {
+dski_status permute(dski_plan p, int dir, int R, const float* in, int ldi, float* out, int ldo,
+                    hipStream_t st) {
+  return permute_t<float>(p, dir, R, in, ldi, out, ldo, st);
+}
+
+dski_status permute(dski_plan p, int dir, int R, const double* in, int ldi, double* out, int ldo,
+                    hipStream_t st) {
+  return permute_t<double>(p, dir, R, in, ldi, out, ldo, st);
+}
+
+template <typename T>
+dski_status rademacher(uint64_t seed, int col0, int ncols, int N, T* out, int ld, hipStream_t st) {
   size_t tot = (size_t)N * ncols;
   if (tot == 0) return DSKI_OK;
-  k_rademacher<<<grid1d(tot), kBlock, 0, st>>>(seed, col0, ncols, N, out, ld);
+  k_rademacher<T><<<grid1d(tot), kBlock, 0, st>>>(seed, col0, ncols, N, out, ld);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
+template dski_status rademacher<float>(uint64_t, int, int, int, float*, int, hipStream_t);
+template dski_status rademacher<double>(uint64_t, int, int, int, double*, int, hipStream_t);
 
 static int fft_len(int m) {
   int L = 4;
@@ -517,6 +530,25 @@ dski_status dski_permute(dski_plan p, int dir, int R, const float* in, int ldi, 
   return permute(p, dir, R, in, ldi, out, ldo, static_cast<hipStream_t>(stream));
 }
 
+dski_status dski_permute_f64(dski_plan p, int dir, int R, const double* in, int ldi, double* out,
+                             int ldo, dski_stream stream) {
+  if (!p || (dir != 1 && dir != -1) || R < 0 || (R > 0 && (!in || !out)) || ldi < p->N ||
+      ldo < p->N) {
+    set_error("dski_permute_f64: bad arguments");
+    return DSKI_EINVAL;
+  }
+  return permute(p, dir, R, in, ldi, out, ldo, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_plan_set_precision(dski_plan p, int bits) {
+  if (!p || (bits != 32 && bits != 64)) {
+    set_error("dski_plan_set_precision: bits must be 32 or 64");
+    return DSKI_EINVAL;
+  }
+  p->precision = bits;
+  return DSKI_OK;
+}
+
 dski_status dski_tile_order(dski_plan p, int* perm_host) {
   if (!p || !perm_host) {
     set_error("dski_tile_order: NULL argument");
@@ -532,7 +564,7 @@ dski_status dski_rademacher(uint64_t seed, int col0, int ncols, int N, float* ou
     set_error("dski_rademacher: bad arguments");
     return DSKI_EINVAL;
   }
-  return rademacher(seed, col0, ncols, N, out, ld, static_cast<hipStream_t>(stream));
+  return rademacher<float>(seed, col0, ncols, N, out, ld, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

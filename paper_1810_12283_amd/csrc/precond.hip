@@ -272,7 +272,8 @@ __global__ void k_gram_partial(const double* __restrict__ L, int N, int n, int k
 // (Vs holds V with column i divided by sigma_i; read through the cache, it is
 // the same for every thread.)
 __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, double isf, double isg,
-                         const double* __restrict__ sV, float* __restrict__ U) {
+                         const double* __restrict__ sV, float* __restrict__ U,
+                         double* __restrict__ Ud) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   double sc = e < n ? isf : isg;
@@ -280,6 +281,7 @@ __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, doub
     double acc = 0.0;
     for (int l = 0; l < k; ++l) acc += L[(size_t)l * N + e] * sV[l * k + i];
     U[(size_t)i * N + e] = (float)(acc * sc);
+    Ud[(size_t)i * N + e] = acc * sc;
   }
 }
 
@@ -288,19 +290,19 @@ __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, doub
 //   v = pre_e * X_e - sum_i U[e, i] coef[i, r]   (coef may be NULL).
 constexpr int kProjRC = 16;  // columns per launch
 
-__global__ void k_proj(const float* __restrict__ U, int N, int n, int k, int rows,
-                       const float* __restrict__ X, int ld, int r0, int rc, double pre_v,
-                       double pre_g, const double* __restrict__ coef, int R,
-                       double* __restrict__ partial) {
+template <typename T>
+__global__ void k_proj(const T* __restrict__ U, int N, int n, int k, int rows, const T* __restrict__ X,
+                       int ld, int r0, int rc, double pre_v, double pre_g,
+                       const double* __restrict__ coef, int R, double* __restrict__ partial) {
   extern __shared__ double sm[];
-  float* sU = reinterpret_cast<float*>(sm);                         // k x rows
-  double* sval = sm + ((size_t)k * rows + 1) / 2;                    // rows x kProjRC
-  double* sco = sval + (size_t)rows * kProjRC;                      // k x kProjRC
+  T* sU = reinterpret_cast<T*>(sm);                                             // k x rows
+  double* sval = sm + ((size_t)k * rows * sizeof(T) + sizeof(double) - 1) / sizeof(double);  // rows x RC
+  double* sco = sval + (size_t)rows * kProjRC;                                  // k x RC
   int e0 = blockIdx.x * rows;
   int rn = min(rows, N - e0);
   for (int f = threadIdx.x; f < k * rows; f += blockDim.x) {
     int i = f / rows, r = f % rows;
-    sU[(size_t)i * rows + r] = r < rn ? U[(size_t)i * N + e0 + r] : 0.0f;
+    sU[(size_t)i * rows + r] = r < rn ? U[(size_t)i * N + e0 + r] : (T)0;
   }
   if (coef)
     for (int f = threadIdx.x; f < k * rc; f += blockDim.x) {
@@ -329,9 +331,10 @@ __global__ void k_proj(const float* __restrict__ U, int N, int n, int k, int row
 }
 
 // out_e = post_e * (pre_e * X_e - sum_i U[e, i] coef[i, r]); optional partials of X.out.
-__global__ void k_pc_final(const float* __restrict__ U, int N, int n, int k, const float* __restrict__ X,
+template <typename T>
+__global__ void k_pc_final(const T* __restrict__ U, int N, int n, int k, const T* __restrict__ X,
                            int ld, int R, double pre_v, double pre_g, double post_v, double post_g,
-                           const double* __restrict__ coef, float* __restrict__ out, int ldo,
+                           const double* __restrict__ coef, T* __restrict__ out, int ldo,
                            double* __restrict__ dot_partial) {
   extern __shared__ double sco[];  // k x R
   for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
@@ -345,7 +348,7 @@ __global__ void k_pc_final(const float* __restrict__ U, int N, int n, int k, con
     double x = (double)X[(size_t)r * ld + e];
     double v = pre * x;
     for (int i = 0; i < k; ++i) v -= (double)U[(size_t)i * N + e] * sco[i * R + r];
-    float o = (float)(post * v);
+    T o = (T)(post * v);
     out[(size_t)r * ldo + e] = o;
     dot = x * (double)o;
   }
@@ -358,7 +361,7 @@ __global__ void k_pc_final(const float* __restrict__ U, int N, int n, int k, con
   }
 }
 
-// coef[i, r] = c_i * (t1[i, r] + t2[i, r])  (t2 may be NULL); sign applied by `sgn`.
+// coef[i, r] = sgn * c_i * (t1[i, r] + t2[i, r])  (t2 may be NULL).
 __global__ void k_coef(const double* __restrict__ c, const double* __restrict__ t1,
                        const double* __restrict__ t2, int k, int R, double sgn,
                        double* __restrict__ coef) {
@@ -369,26 +372,42 @@ __global__ void k_coef(const double* __restrict__ c, const double* __restrict__ 
   coef[f] = sgn * c[i] * t;
 }
 
-static int proj_rows(int k) { return k <= 64 ? 128 : 64; }
+// rows per projection block so that the LDS tile stays within 60 KiB
+static int proj_rows(int k, size_t tsize) {
+  int rows = 128;
+  while (rows > 8 && (size_t)k * rows * tsize + sizeof(double) * ((size_t)rows * kProjRC + (size_t)k * kProjRC) >
+                         61440)
+    rows /= 2;
+  return rows;
+}
 
-static size_t proj_lds(int k, int rows) {
-  return sizeof(double) * (((size_t)k * rows + 1) / 2 + (size_t)rows * kProjRC + (size_t)k * kProjRC);
+static size_t proj_lds(int k, int rows, size_t tsize) {
+  return ((size_t)k * rows * tsize + sizeof(double) - 1) / sizeof(double) * sizeof(double) +
+         sizeof(double) * ((size_t)rows * kProjRC + (size_t)k * kProjRC);
 }
 
 int vec_blocks(int N) { return (N + kBlock - 1) / kBlock; }
 
+template <typename T>
+static const T* u_of(dski_precond pc);
+template <>
+const float* u_of<float>(dski_precond pc) { return pc->U; }
+template <>
+const double* u_of<double>(dski_precond pc) { return pc->Ud; }
+
 // t[k x R] = U^T (pre .* X - U coef)
-static dski_status project(dski_precond pc, int R, const float* X, int ld, double pre_v, double pre_g,
+template <typename T>
+static dski_status project(dski_precond pc, int R, const T* X, int ld, double pre_v, double pre_g,
                            const double* coef, double* partial, double* t, hipStream_t st) {
   dski_plan p = pc->plan;
   int k = pc->k, N = p->N;
-  int rows = proj_rows(k);
+  int rows = proj_rows(k, sizeof(T));
   int nblk = (N + rows - 1) / rows;
-  size_t lds = proj_lds(k, rows);
+  size_t lds = proj_lds(k, rows, sizeof(T));
   for (int r0 = 0; r0 < R; r0 += kProjRC) {
     int rc = std::min(kProjRC, R - r0);
-    k_proj<<<nblk, kBlock, lds, st>>>(pc->U, N, p->n, k, rows, X, ld, r0, rc, pre_v, pre_g, coef, R,
-                                      partial);
+    k_proj<T><<<nblk, kBlock, lds, st>>>(u_of<T>(pc), N, p->n, k, rows, X, ld, r0, rc, pre_v, pre_g, coef,
+                                         R, partial);
   }
   DSKI_HIP(hipGetLastError());
   return reduce_partials(partial, nblk, k * R, t, st);
@@ -398,7 +417,7 @@ static dski_status ensure_work(dski_precond pc, int R, double** partial, double*
                                double** coef) {
   dski_plan p = pc->plan;
   int k = pc->k;
-  int rows = proj_rows(k);
+  int rows = proj_rows(k, sizeof(double));
   int nblk = (p->N + rows - 1) / rows;
   size_t np = std::max((size_t)nblk * k * R, (size_t)vec_blocks(p->N) * R);
   size_t want = sizeof(double) * (np + 3 * (size_t)k * R + 64);
@@ -411,7 +430,8 @@ static dski_status ensure_work(dski_precond pc, int R, double** partial, double*
   return DSKI_OK;
 }
 
-dski_status precond_apply_tiled(dski_precond pc, int R, const float* Rm, int ld, float* Z, int ldz,
+template <typename T>
+dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* Z, int ldz,
                                 double* rz_partial, int* nblk_out, hipStream_t st) {
   dski_plan p = pc->plan;
   int k = pc->k, N = p->N;
@@ -420,8 +440,8 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const float* Rm, int ld,
   if (R <= 0) return DSKI_OK;
   dim3 fgrid(vec_blocks(N), R);
   if (k == 0) {
-    k_pc_final<<<fgrid, kBlock, 0, st>>>(pc->U, N, p->n, 0, Rm, ld, R, isf, isg, isf, isg, nullptr, Z,
-                                         ldz, rz_partial);
+    k_pc_final<T><<<fgrid, kBlock, 0, st>>>(u_of<T>(pc), N, p->n, 0, Rm, ld, R, isf, isg, isf, isg, nullptr,
+                                            Z, ldz, rz_partial);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   }
@@ -429,46 +449,56 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const float* Rm, int ld,
   DSKI_TRY(ensure_work(pc, R, &partial, &t1, &t2, &coef));
   int cb = (k * R + kBlock - 1) / kBlock;
   // t1 = U^T r',  r' = D^{-1/2} Rm
-  DSKI_TRY(project(pc, R, Rm, ld, isf, isg, nullptr, partial, t1, st));
+  DSKI_TRY(project<T>(pc, R, Rm, ld, isf, isg, nullptr, partial, t1, st));
   k_coef<<<cb, kBlock, 0, st>>>(pc->c, t1, nullptr, k, R, 1.0, coef);
   // t2 = U^T w,  w = r' - U (c .* t1)
-  DSKI_TRY(project(pc, R, Rm, ld, isf, isg, coef, partial, t2, st));
+  DSKI_TRY(project<T>(pc, R, Rm, ld, isf, isg, coef, partial, t2, st));
   k_coef<<<cb, kBlock, 0, st>>>(pc->c, t1, t2, k, R, 1.0, coef);
   // Z = D^{-1/2} (r' - U (c .* (t1 + t2)))
-  k_pc_final<<<fgrid, kBlock, sizeof(double) * k * R, st>>>(pc->U, N, p->n, k, Rm, ld, R, isf, isg, isf,
-                                                            isg, coef, Z, ldz, rz_partial);
+  k_pc_final<T><<<fgrid, kBlock, sizeof(double) * k * R, st>>>(u_of<T>(pc), N, p->n, k, Rm, ld, R, isf,
+                                                               isg, isf, isg, coef, Z, ldz, rz_partial);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
+template dski_status precond_apply_tiled<float>(dski_precond, int, const float*, int, float*, int,
+                                                double*, int*, hipStream_t);
+template dski_status precond_apply_tiled<double>(dski_precond, int, const double*, int, double*, int,
+                                                 double*, int*, hipStream_t);
 
-dski_status precond_factor_apply_tiled(dski_precond pc, int R, const float* W, int ld, float* Z, int ldz,
+template <typename T>
+dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int ld, T* Z, int ldz,
                                        hipStream_t st) {
   dski_plan p = pc->plan;
   int k = pc->k, N = p->N;
   if (R <= 0) return DSKI_OK;
   dim3 fgrid(vec_blocks(N), R);
   if (k == 0) {
-    k_pc_final<<<fgrid, kBlock, 0, st>>>(pc->U, N, p->n, 0, W, ld, R, 1.0, 1.0, p->sf, p->sg, nullptr, Z,
-                                         ldz, nullptr);
+    k_pc_final<T><<<fgrid, kBlock, 0, st>>>(u_of<T>(pc), N, p->n, 0, W, ld, R, 1.0, 1.0, p->sf, p->sg,
+                                            nullptr, Z, ldz, nullptr);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   }
   double *partial, *t1, *t2, *coef;
   DSKI_TRY(ensure_work(pc, R, &partial, &t1, &t2, &coef));
   int cb = (k * R + kBlock - 1) / kBlock;
-  DSKI_TRY(project(pc, R, W, ld, 1.0, 1.0, nullptr, partial, t1, st));
+  DSKI_TRY(project<T>(pc, R, W, ld, 1.0, 1.0, nullptr, partial, t1, st));
   k_coef<<<cb, kBlock, 0, st>>>(pc->rootc, t1, nullptr, k, R, -1.0, coef);
-  k_pc_final<<<fgrid, kBlock, sizeof(double) * k * R, st>>>(pc->U, N, p->n, k, W, ld, R, 1.0, 1.0, p->sf,
-                                                            p->sg, coef, Z, ldz, nullptr);
+  k_pc_final<T><<<fgrid, kBlock, sizeof(double) * k * R, st>>>(u_of<T>(pc), N, p->n, k, W, ld, R, 1.0, 1.0,
+                                                               p->sf, p->sg, coef, Z, ldz, nullptr);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
+template dski_status precond_factor_apply_tiled<float>(dski_precond, int, const float*, int, float*, int,
+                                                       hipStream_t);
+template dski_status precond_factor_apply_tiled<double>(dski_precond, int, const double*, int, double*,
+                                                        int, hipStream_t);
 
 static void destroy_pc(dski_precond pc) {
   if (!pc) return;
   (void)hipFree(pc->piv_tile);
   (void)hipFree(pc->L);
   (void)hipFree(pc->U);
+  (void)hipFree(pc->Ud);
   (void)hipFree(pc->c);
   (void)hipFree(pc->rootc);
   pc->work.release();
@@ -541,6 +571,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
     double logdetD = (double)n * 2.0 * std::log(p->sf) + (double)(N - n) * 2.0 * std::log(p->sg);
     DSKI_HIP(hipMalloc(&pc->U, sizeof(float) * (size_t)N * std::max(r, 1)));
+    DSKI_HIP(hipMalloc(&pc->Ud, sizeof(double) * (size_t)N * std::max(r, 1)));
     DSKI_HIP(hipMalloc(&pc->c, sizeof(double) * std::max(r, 1)));
     DSKI_HIP(hipMalloc(&pc->rootc, sizeof(double) * std::max(r, 1)));
     if (r == 0) {
@@ -596,7 +627,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
       break;
     }
     k_make_u<<<(N + kBlock - 1) / kBlock, kBlock, 0, st>>>(pc->L, N, n, r, isf, isg,
-                                                                                dV, pc->U);
+                                                                                dV, pc->U, pc->Ud);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(st);
     (void)hipFree(dV);
@@ -623,9 +654,8 @@ dski_status pivchol_build(dski_plan p, int k, dski_precond* out, int* rank_host,
     set_error("pivchol_build: bad arguments (k=%d)", k);
     return DSKI_EINVAL;
   }
-  if ((size_t)k * proj_rows(k) / 2 + (size_t)proj_rows(k) * kProjRC + (size_t)k * kProjRC >
-      65536 / sizeof(double)) {
-    set_error("pivchol_build: rank %d too large for this build (max 150)", k);
+  if (k > 256) {
+    set_error("pivchol_build: rank %d too large for this build (max 256)", k);
     return DSKI_ENOTSUP;
   }
   *out = nullptr;
@@ -654,22 +684,36 @@ dski_status dski_precond_logdet(dski_precond pc, double* out_host) {
   return DSKI_OK;
 }
 
-dski_status dski_precond_apply(dski_precond pc, int R, const float* Rm, int ld, float* Z, int ldz,
-                               dski_stream stream) {
+}  // extern "C"
+
+template <typename T>
+static dski_status precond_apply_user(dski_precond pc, int R, const T* Rm, int ld, T* Z, int ldz,
+                                      hipStream_t st) {
   if (!pc || R < 0 || ld < pc->plan->N || ldz < pc->plan->N || (R > 0 && (!Rm || !Z))) {
     set_error("dski_precond_apply: bad arguments");
     return DSKI_EINVAL;
   }
   dski_plan p = pc->plan;
   if (R == 0) return DSKI_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
   size_t nr = (size_t)p->N * R;
-  DSKI_TRY(p->vin.reserve(sizeof(float) * nr));
-  DSKI_TRY(p->vout.reserve(sizeof(float) * nr));
-  DSKI_TRY(permute(p, +1, R, Rm, ld, p->vin.as<float>(), p->N, st));
-  DSKI_TRY(precond_apply_tiled(pc, R, p->vin.as<float>(), p->N, p->vout.as<float>(), p->N, nullptr,
-                               nullptr, st));
-  return permute(p, -1, R, p->vout.as<float>(), p->N, Z, ldz, st);
+  DSKI_TRY(p->vin.reserve(sizeof(T) * nr));
+  DSKI_TRY(p->vout.reserve(sizeof(T) * nr));
+  DSKI_TRY(permute(p, +1, R, Rm, ld, p->vin.as<T>(), p->N, st));
+  DSKI_TRY(precond_apply_tiled<T>(pc, R, p->vin.as<T>(), p->N, p->vout.as<T>(), p->N, nullptr, nullptr,
+                                  st));
+  return permute(p, -1, R, p->vout.as<T>(), p->N, Z, ldz, st);
+}
+
+extern "C" {
+
+dski_status dski_precond_apply(dski_precond pc, int R, const float* Rm, int ld, float* Z, int ldz,
+                               dski_stream stream) {
+  return precond_apply_user<float>(pc, R, Rm, ld, Z, ldz, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_precond_apply_f64(dski_precond pc, int R, const double* Rm, int ld, double* Z, int ldz,
+                                   dski_stream stream) {
+  return precond_apply_user<double>(pc, R, Rm, ld, Z, ldz, static_cast<hipStream_t>(stream));
 }
 
 __global__ void k_factor_out(const double* __restrict__ L, int N, int n, int k,

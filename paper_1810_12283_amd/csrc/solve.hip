@@ -107,41 +107,34 @@ static void slq_combine(const std::vector<double>& ab, int max_iter, int R, int 
 
 using namespace dski;
 
-extern "C" {
-
-dski_status slq_logdet(dski_plan p, dski_precond pc, int t, int lanczos_steps, double tol, int max_iter,
-                       uint64_t seed, double* logdet_host, double* stderr_host, dski_stream stream) {
-  if (!p || t <= 0 || lanczos_steps < 0 || (lanczos_steps == 0 && (tol <= 0 || max_iter <= 0)) ||
-      (pc && pc->plan != p) || !logdet_host) {
-    set_error("slq_logdet: bad arguments");
-    return DSKI_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
+template <typename T>
+static dski_status slq_impl(dski_plan p, dski_precond pc, int t, int lanczos_steps, double tol, int max_iter,
+                            uint64_t seed, double* logdet_host, double* stderr_host, hipStream_t st) {
   int N = p->N;
   int steps = lanczos_steps > 0 ? lanczos_steps : max_iter;
   size_t nr = (size_t)N * t;
   DevBuf tmp;
-  DSKI_TRY(tmp.reserve(sizeof(float) * nr * 3 + sizeof(double) * 2 * (size_t)steps * t + 1024));
-  float* W = tmp.as<float>();
-  float* Z = W + nr;
-  float* X = Z + nr;
-  double* ab = reinterpret_cast<double*>(X + nr);
+  DSKI_TRY(tmp.reserve(sizeof(T) * nr * 3 + sizeof(double) * 2 * (size_t)steps * t + 1024));
+  T* W = tmp.as<T>();
+  T* Z = W + nr;
+  T* X = Z + nr;
+  double* ab = reinterpret_cast<double*>(tmp.as<char>() + ((sizeof(T) * nr * 3 + 63) / 64) * 64);
   dski_status rc = DSKI_OK;
   do {
     // probes in user order -> tile order -> z = C w
-    rc = rademacher(seed, 0, t, N, X, N, st);
+    rc = rademacher<T>(seed, 0, t, N, X, N, st);
     if (rc < 0) break;
     rc = permute(p, +1, t, X, N, W, N, st);
     if (rc < 0) break;
     if (pc)
-      rc = precond_factor_apply_tiled(pc, t, W, N, Z, N, st);
+      rc = precond_factor_apply_tiled<T>(pc, t, W, N, Z, N, st);
     else
-      rc = hipMemcpyAsync(Z, W, sizeof(float) * nr, hipMemcpyDeviceToDevice, st) == hipSuccess ? DSKI_OK
-                                                                                                 : DSKI_EHIP;
+      rc = hipMemcpyAsync(Z, W, sizeof(T) * nr, hipMemcpyDeviceToDevice, st) == hipSuccess ? DSKI_OK
+                                                                                             : DSKI_EHIP;
     if (rc < 0) break;
     std::vector<double> tols(t, lanczos_steps > 0 ? 0.0 : tol);
     PcgResult res;
-    rc = pcg_tiled(p, pc, t, Z, N, X, N, tols.data(), steps, lanczos_steps, ab, res, st);
+    rc = pcg_tiled<T>(p, pc, t, Z, N, X, N, tols.data(), steps, lanczos_steps, ab, res, st);
     if (rc < 0) break;
     std::vector<double> hab(2 * (size_t)steps * t);
     if (hipMemcpyAsync(hab.data(), ab, sizeof(double) * hab.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -164,52 +157,42 @@ dski_status slq_logdet(dski_plan p, dski_precond pc, int t, int lanczos_steps, d
   return rc;
 }
 
-dski_status mll_and_grad(dski_plan p, dski_precond pc_in, int k, const float* y, int t, uint64_t seed,
-                         double tol, int max_iter, double* mll_host, double* grad_host,
-                         double* logdet_host, int* iters_host, dski_stream stream) {
-  if (!p || !y || t <= 0 || tol <= 0 || max_iter <= 0 || (!pc_in && k < 0) ||
-      (pc_in && pc_in->plan != p)) {
-    set_error("mll_and_grad: bad arguments");
-    return DSKI_EINVAL;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
+template <typename T>
+static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uint64_t seed, double tol,
+                            int max_iter, double* mll_host, double* grad_host, double* logdet_host,
+                            int* iters_host, hipStream_t st) {
   int N = p->N, n = p->n, d = p->d;
   long long M = p->M;
-  dski_precond pc = pc_in;
   dski_status rc = DSKI_OK;
-  if (!pc) {
-    int rank = 0;
-    rc = pivchol_build(p, k, &pc, &rank, nullptr, stream);
-    if (rc < 0) return rc;
-  }
   int R = 1 + t;
   size_t nr = (size_t)N * R;
   DevBuf tmp, dotbuf;
+  int* dcols = nullptr;
   do {
-    // buffers: B (R cols), X (R cols), Vv (t cols), W (t cols), history
+    // buffers: B (R cols), X (R cols), Vv (t cols), W (t cols), CG history
     size_t fl = nr * 2 + (size_t)N * t * 2;
-    rc = tmp.reserve(sizeof(float) * fl + sizeof(double) * 2 * (size_t)max_iter * R + 1024);
+    rc = tmp.reserve(sizeof(T) * fl + sizeof(double) * 2 * (size_t)max_iter * R + 1024);
     if (rc < 0) break;
-    float* B = tmp.as<float>();
-    float* X = B + nr;
-    float* Vv = X + nr;
-    float* W = Vv + (size_t)N * t;
-    double* ab = reinterpret_cast<double*>(W + (size_t)N * t);
+    T* B = tmp.as<T>();
+    T* X = B + nr;
+    T* Vv = X + nr;
+    T* W = Vv + (size_t)N * t;
+    double* ab = reinterpret_cast<double*>(tmp.as<char>() + ((sizeof(T) * fl + 63) / 64) * 64);
     rc = permute(p, +1, 1, y, N, B, N, st);
     if (rc < 0) break;
-    rc = rademacher(seed, 0, t, N, Vv, N, st);
+    rc = rademacher<T>(seed, 0, t, N, Vv, N, st);
     if (rc < 0) break;
     rc = permute(p, +1, t, Vv, N, W, N, st);
     if (rc < 0) break;
-    rc = precond_factor_apply_tiled(pc, t, W, N, B + N, N, st);
+    rc = precond_factor_apply_tiled<T>(pc, t, W, N, B + N, N, st);
     if (rc < 0) break;
     std::vector<double> tols(R, tol);
     PcgResult res;
-    rc = pcg_tiled(p, pc, R, B, N, X, N, tols.data(), max_iter, 0, ab, res, st);
+    rc = pcg_tiled<T>(p, pc, R, B, N, X, N, tols.data(), max_iter, 0, ab, res, st);
     if (rc < 0) break;
     dski_status pcg_rc = rc;
     // v_i = M^{-1} z_i
-    rc = precond_apply_tiled(pc, t, B + N, N, Vv, N, nullptr, nullptr, st);
+    rc = precond_apply_tiled<T>(pc, t, B + N, N, Vv, N, nullptr, nullptr, st);
     if (rc < 0) break;
     // log det by SLQ from the same run
     std::vector<double> hab(2 * (size_t)max_iter * R);
@@ -226,67 +209,55 @@ dski_status mll_and_grad(dski_plan p, dski_precond pc_in, int k, const float* y,
       rc = DSKI_EBREAKDOWN;
       break;
     }
-    // data fit y^T alpha and the noise-gradient dots (value rows, gradient rows)
-    std::vector<int> pairs = {0, 0};
-    std::vector<double> yal;
-    rc = pair_dots<float>(B, N, X, N, pairs, 0, N, yal, dotbuf, st);
-    if (rc < 0) break;
-    std::vector<int> np;
-    np.push_back(0);
-    np.push_back(0);  // alpha.alpha (X col 0 with itself)
-    for (int i = 0; i < t; ++i) {
-      np.push_back(1 + i);
-      np.push_back(i);
-    }
-    // pairs index X (cols) against: first pair X0.X0 handled with A=X,B=X below
-    std::vector<double> aa_v, aa_g;
+    // data fit y^T alpha; alpha^T alpha and u_i^T v_i on value rows and on gradient rows
+    std::vector<double> yal, aa_v, aa_g, uv_v, uv_g;
     std::vector<int> p00 = {0, 0};
-    rc = pair_dots<float>(X, N, X, N, p00, 0, n, aa_v, dotbuf, st);
+    rc = pair_dots<T>(B, N, X, N, p00, 0, N, yal, dotbuf, st);
     if (rc < 0) break;
-    rc = pair_dots<float>(X, N, X, N, p00, n, N - n, aa_g, dotbuf, st);
+    rc = pair_dots<T>(X, N, X, N, p00, 0, n, aa_v, dotbuf, st);
+    if (rc < 0) break;
+    rc = pair_dots<T>(X, N, X, N, p00, n, N - n, aa_g, dotbuf, st);
     if (rc < 0) break;
     std::vector<int> puv;
     for (int i = 0; i < t; ++i) {
       puv.push_back(1 + i);
       puv.push_back(i);
     }
-    std::vector<double> uv_v, uv_g;
-    rc = pair_dots<float>(X, N, Vv, N, puv, 0, n, uv_v, dotbuf, st);
+    rc = pair_dots<T>(X, N, Vv, N, puv, 0, n, uv_v, dotbuf, st);
     if (rc < 0) break;
-    rc = pair_dots<float>(X, N, Vv, N, puv, n, N - n, uv_g, dotbuf, st);
+    rc = pair_dots<T>(X, N, Vv, N, puv, n, N - n, uv_g, dotbuf, st);
     if (rc < 0) break;
-    // grids: [S^T alpha, S^T u_1..u_t, S^T v_1..v_t]
+    // grids G = [S^T alpha, S^T u_1..u_t, S^T v_1..v_t]; H = K' [S^T alpha, S^T v_i]
     int Rg = 1 + 2 * t;
     rc = p->grid.reserve(sizeof(double) * (size_t)M * (Rg + 1 + t));
     if (rc < 0) break;
     double* G = p->grid.as<double>();
-    double* H = G + (size_t)M * Rg;  // K' applied to [alpha, v_1..v_t]
-    rc = scatter(p, R, X, N, G, st);
+    double* H = G + (size_t)M * Rg;
+    rc = scatter<T>(p, R, X, N, G, st);
     if (rc < 0) break;
-    rc = scatter(p, t, Vv, N, G + (size_t)M * R, st);
+    rc = scatter<T>(p, t, Vv, N, G + (size_t)M * R, st);
     if (rc < 0) break;
     std::vector<int> cols;
     cols.push_back(0);
     for (int i = 0; i < t; ++i) cols.push_back(R + i);
-    std::vector<int> gp;  // (H col, G col) pairs
-    gp.push_back(0);
-    gp.push_back(0);
+    std::vector<int> gp = {0, 0};  // (H col, G col) pairs
     for (int i = 0; i < t; ++i) {
       gp.push_back(1 + i);
       gp.push_back(1 + i);
     }
-    int* dcols = nullptr;
     if (hipMalloc(&dcols, sizeof(int) * cols.size()) != hipSuccess) {
+      dcols = nullptr;
       set_error("allocation failed");
       rc = DSKI_ENOMEM;
       break;
     }
+    if (hipMemcpyAsync(dcols, cols.data(), sizeof(int) * cols.size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+      set_error("copy failed");
+      rc = DSKI_EHIP;
+      break;
+    }
     std::vector<double> g(d + 3, 0.0);
     for (int which = 0; which <= d && rc >= 0; ++which) {
-      if (hipMemcpyAsync(dcols, cols.data(), sizeof(int) * cols.size(), hipMemcpyHostToDevice, st) != hipSuccess) {
-        rc = DSKI_EHIP;
-        break;
-      }
       int nb = (int)std::min<long long>(1024, (M + kBlock - 1) / kBlock);
       k_copy_cols_d<<<dim3(nb, 1 + t), kBlock, 0, st>>>(G, H, M, dcols, 1 + t);
       rc = apply_kuu(p, 1 + t, H, st, which < d ? which : -1);
@@ -294,13 +265,12 @@ dski_status mll_and_grad(dski_plan p, dski_precond pc_in, int k, const float* y,
       std::vector<double> dots;
       rc = pair_dots<double>(H, M, G, M, gp, 0, M, dots, dotbuf, st);
       if (rc < 0) break;
-      double scale = which < d ? 1.0 : 2.0;
+      double scale = which < d ? 1.0 : 2.0;  // d K_UU / d log s = 2 K_UU
       double tr = 0.0;
       for (int i = 0; i < t; ++i) tr += dots[1 + i];
       tr /= t;
       g[which] = scale * (0.5 * dots[0] - 0.5 * tr);
     }
-    (void)hipFree(dcols);
     if (rc < 0) break;
     double sf2 = p->sf * p->sf, sg2 = p->sg * p->sg;
     double trv = 0.0, trg = 0.0;
@@ -308,6 +278,7 @@ dski_status mll_and_grad(dski_plan p, dski_precond pc_in, int k, const float* y,
       trv += uv_v[i];
       trg += uv_g[i];
     }
+    // dK~/dlog sigma = 2 sigma^2 on the value (gradient) rows
     g[d + 1] = sf2 * (aa_v[0] - trv / t);
     g[d + 2] = sg2 * (aa_g[0] - trg / t);
     const double log2pi = 1.8378770664093453;
@@ -320,10 +291,60 @@ dski_status mll_and_grad(dski_plan p, dski_precond pc_in, int k, const float* y,
       for (int r = 0; r < R; ++r) iters_host[r] = res.iters[r];
     rc = pcg_rc;
   } while (0);
+  if (dcols) (void)hipFree(dcols);
   tmp.release();
   dotbuf.release();
+  return rc;
+}
+
+template <typename T>
+static dski_status mll_user(dski_plan p, dski_precond pc_in, int k, const T* y, int t, uint64_t seed,
+                            double tol, int max_iter, double* mll_host, double* grad_host,
+                            double* logdet_host, int* iters_host, hipStream_t st) {
+  if (!p || !y || t <= 0 || tol <= 0 || max_iter <= 0 || (!pc_in && k < 0) ||
+      (pc_in && pc_in->plan != p) || p->N == 0) {
+    set_error("mll_and_grad: bad arguments");
+    return DSKI_EINVAL;
+  }
+  dski_precond pc = pc_in;
+  if (!pc) {
+    int rank = 0;
+    dski_status rc = pivchol_build(p, k, &pc, &rank, nullptr, st);
+    if (rc < 0) return rc;
+  }
+  dski_status rc = mll_impl<T>(p, pc, y, t, seed, tol, max_iter, mll_host, grad_host, logdet_host,
+                               iters_host, st);
   if (!pc_in) dski_precond_destroy(pc);
   return rc;
+}
+
+extern "C" {
+
+dski_status slq_logdet(dski_plan p, dski_precond pc, int t, int lanczos_steps, double tol, int max_iter,
+                       uint64_t seed, double* logdet_host, double* stderr_host, dski_stream stream) {
+  if (!p || t <= 0 || lanczos_steps < 0 || (lanczos_steps == 0 && (tol <= 0 || max_iter <= 0)) ||
+      (pc && pc->plan != p) || !logdet_host || p->N == 0) {
+    set_error("slq_logdet: bad arguments");
+    return DSKI_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->precision == 64)
+    return slq_impl<double>(p, pc, t, lanczos_steps, tol, max_iter, seed, logdet_host, stderr_host, st);
+  return slq_impl<float>(p, pc, t, lanczos_steps, tol, max_iter, seed, logdet_host, stderr_host, st);
+}
+
+dski_status mll_and_grad(dski_plan p, dski_precond pc, int k, const float* y, int t, uint64_t seed,
+                         double tol, int max_iter, double* mll_host, double* grad_host,
+                         double* logdet_host, int* iters_host, dski_stream stream) {
+  return mll_user<float>(p, pc, k, y, t, seed, tol, max_iter, mll_host, grad_host, logdet_host,
+                         iters_host, static_cast<hipStream_t>(stream));
+}
+
+dski_status mll_and_grad_f64(dski_plan p, dski_precond pc, int k, const double* y, int t, uint64_t seed,
+                             double tol, int max_iter, double* mll_host, double* grad_host,
+                             double* logdet_host, int* iters_host, dski_stream stream) {
+  return mll_user<double>(p, pc, k, y, t, seed, tol, max_iter, mll_host, grad_host, logdet_host,
+                          iters_host, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -60,6 +60,15 @@ _SIGS = {
                                dp, dp, dp, ip, vp]),
     "dski_rademacher": (C.c_int, [C.c_uint64, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]),
     "dski_lanczos_quad_log": (C.c_double, [dp, dp, C.c_int, ip]),
+    "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
+    "dski_mvm_f64": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_mvm_dtheta_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_permute_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_mvm_tiled_f64": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_precond_apply_f64": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "pcg_solve_f64": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, vp, C.c_int, dp, C.c_int, ip, dp, vp, vp]),
+    "mll_and_grad_f64": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, C.c_uint64, C.c_double, C.c_int,
+                                   dp, dp, dp, ip, vp]),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -100,14 +109,19 @@ def _dptr(t: torch.Tensor):
     return vp(t.data_ptr())
 
 
+def _fn(name, V):
+    """The FP32 entry point or its *_f64 twin, by the tensor's dtype."""
+    return getattr(lib(), name + ("_f64" if V.dtype == torch.float64 else ""))
+
+
 def _arr(vals, ctype):
     a = (ctype * len(vals))(*vals)
     return a
 
 
 def _block(V: torch.Tensor, N: int, name: str) -> torch.Tensor:
-    if not V.is_cuda or V.dtype != torch.float32:
-        raise TypeError(f"{name} must be a CUDA float32 tensor")
+    if not V.is_cuda or V.dtype not in (torch.float32, torch.float64):
+        raise TypeError(f"{name} must be a CUDA float32 or float64 tensor")
     if V.dim() == 1:
         V = V[None, :]
     if V.shape[-1] != N or not V.is_contiguous():
@@ -174,30 +188,34 @@ class Plan:
     def mvm(self, V: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         V = _block(V, self.N, "V")
         Y = torch.empty_like(V) if out is None else out
-        _check(lib().dski_mvm(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N, _stream(stream)),
+        _check(_fn("dski_mvm", V)(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N, _stream(stream)),
                "dski_mvm")
         return Y
 
     def mvm_tiled(self, V: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         V = _block(V, self.N, "V")
         Y = torch.empty_like(V) if out is None else out
-        _check(lib().dski_mvm_tiled(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
+        _check(_fn("dski_mvm_tiled", V)(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
                                     _stream(stream)), "dski_mvm_tiled")
         return Y
 
     def mvm_dtheta(self, which: int, V: torch.Tensor, stream=None) -> torch.Tensor:
         V = _block(V, self.N, "V")
         Y = torch.empty_like(V)
-        _check(lib().dski_mvm_dtheta(self._h, int(which), V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
+        _check(_fn("dski_mvm_dtheta", V)(self._h, int(which), V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
                                      _stream(stream)), "dski_mvm_dtheta")
         return Y
 
     def permute(self, V: torch.Tensor, direction: int, stream=None) -> torch.Tensor:
         V = _block(V, self.N, "V")
         Y = torch.empty_like(V)
-        _check(lib().dski_permute(self._h, int(direction), V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
+        _check(_fn("dski_permute", V)(self._h, int(direction), V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
                                   _stream(stream)), "dski_permute")
         return Y
+
+    def set_precision(self, bits: int):
+        """Storage precision of the vectors slq_logdet creates (32 or 64)."""
+        _check(lib().dski_plan_set_precision(self._h, int(bits)), "dski_plan_set_precision")
 
     def tile_order(self) -> np.ndarray:
         perm = (C.c_int * self.n)()
@@ -212,12 +230,12 @@ class Plan:
         """Returns (X, iters, relres, status, alpha_beta or None)."""
         B = _block(B, self.N, "B")
         R = B.shape[0]
-        X = torch.empty_like(B)
+        X = torch.empty(B.shape, dtype=torch.float64, device=B.device)
         tols = _arr([float(t) for t in np.broadcast_to(np.asarray(tol, dtype=np.float64), (R,))], C.c_double)
         iters = (C.c_int * R)()
         relres = (C.c_double * R)()
         ab = torch.zeros(2 * max_iter * R, dtype=torch.float64, device=B.device) if history else None
-        st = _check(lib().pcg_solve(self._h, precond.handle if precond else None, R, _dptr(B), self.N,
+        st = _check(_fn("pcg_solve", B)(self._h, precond.handle if precond else None, R, _dptr(B), self.N,
                                     _dptr(X), self.N, tols, int(max_iter), iters, relres,
                                     _dptr(ab) if ab is not None else None, _stream(stream)), "pcg_solve")
         return X, list(iters), list(relres), st, ab
@@ -237,7 +255,7 @@ class Plan:
         mll, ld = C.c_double(), C.c_double()
         grad = (C.c_double * (self.d + 3))()
         iters = (C.c_int * (1 + num_probes))()
-        st = _check(lib().mll_and_grad(self._h, precond.handle if precond else None, int(k), _dptr(y),
+        st = _check(_fn("mll_and_grad", y)(self._h, precond.handle if precond else None, int(k), _dptr(y),
                                        int(num_probes), C.c_uint64(seed), float(tol), int(max_iter),
                                        C.byref(mll), grad, C.byref(ld), iters, _stream(stream)),
                     "mll_and_grad")
@@ -282,7 +300,7 @@ class Precond:
     def apply(self, Rm: torch.Tensor, stream=None) -> torch.Tensor:
         Rm = _block(Rm, self.plan.N, "R")
         Z = torch.empty_like(Rm)
-        _check(lib().dski_precond_apply(self._h, Rm.shape[0], _dptr(Rm), self.plan.N, _dptr(Z), self.plan.N,
+        _check(_fn("dski_precond_apply", Rm)(self._h, Rm.shape[0], _dptr(Rm), self.plan.N, _dptr(Z), self.plan.N,
                                         _stream(stream)), "dski_precond_apply")
         return Z
 

@@ -31,6 +31,20 @@ def test_mvm_matches_oracle(idx):
         assert err.max() < TOL_MVM
 
 
+@pytest.mark.parametrize("idx", [0, 3])
+def test_mvm_fp64_matches_oracle(idx):
+    name, W = small_workloads()[idx]
+    say("mvm fp64", name)
+    plan, op = make(W)
+    V = np.random.default_rng(11).standard_normal((op.N, 5))
+    Y = plan.mvm(to_gpu(V).double() * 0 + torch.tensor(V.T.copy(), device="cuda"))
+    err = rel_cols(Y.cpu().numpy().T, op.matvec(V))
+    say("  max rel err", err.max())
+    assert err.max() < 1e-12
+    Yd = plan.mvm_dtheta(0, torch.tensor(V.T.copy(), device="cuda"))
+    assert rel_cols(Yd.cpu().numpy().T, op.matvec_dtheta(0, V)).max() < 1e-12
+
+
 def test_mvm_dtheta_matches_oracle():
     W = workloads.small2d(n=400, grid=40)
     say("mvm_dtheta", W.n)
