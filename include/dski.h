@@ -124,6 +124,14 @@ dski_status dski_mvm_tiled(dski_plan plan, int R, const float* V, int ldv, float
 dski_status dski_mvm_tiled_f64(dski_plan plan, int R, const double* V, int ldv, double* Y,
                                int ldy, dski_stream stream);
 
+/* One stage of dski_mvm_tiled, for profiling and custom pipelines: stage 0 =
+ * scatter G = S^T V into the plan's FP64 grid workspace (M x R), stage 1 =
+ * G <- K_UU G in place (FFT, one launch per axis), stage 2 = gather
+ * Y = S G + D V.  Stages 1 and 2 use the grid left by the last stage 0 of at
+ * least R columns on this plan; any other call may overwrite it. */
+dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int ldv, float* Y,
+                           int ldy, dski_stream stream);
+
 /* Storage precision (32 or 64 bits) of the N-vectors that slq_logdet creates
  * internally (probes, Krylov vectors).  Default 32. */
 dski_status dski_plan_set_precision(dski_plan plan, int bits);

@@ -640,6 +640,26 @@ dski_status dski_mvm_tiled_f64(dski_plan p, int R, const double* V, int ldv, dou
   return mvm_tiled<double>(p, R, V, ldv, Y, ldy, nullptr, static_cast<hipStream_t>(stream));
 }
 
+dski_status dski_mvm_stage(dski_plan p, int stage, int R, const float* V, int ldv, float* Y, int ldy,
+                           dski_stream stream) {
+  if (!p || R < 0 || stage < 0 || stage > 2 || (stage != 1 && (!V || ldv < p->N)) ||
+      (stage == 2 && (!Y || ldy < p->N))) {
+    set_error("dski_mvm_stage: bad arguments");
+    return DSKI_EINVAL;
+  }
+  if (R == 0) return DSKI_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (stage == 0) DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
+  if (p->grid.bytes < sizeof(double) * (size_t)p->M * R) {
+    set_error("dski_mvm_stage: run stage 0 with at least R columns first");
+    return DSKI_EINVAL;
+  }
+  double* G = p->grid.as<double>();
+  if (stage == 0) return scatter<float>(p, R, V, ldv, G, st);
+  if (stage == 1) return apply_kuu(p, R, G, st);
+  return gather<float>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, nullptr, st);
+}
+
 dski_status dski_mvm(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
                      dski_stream stream) {
   return mvm_user<float>(p, -1, R, V, ldv, Y, ldy, static_cast<hipStream_t>(stream));

@@ -61,6 +61,7 @@ _SIGS = {
     "dski_rademacher": (C.c_int, [C.c_uint64, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]),
     "dski_lanczos_quad_log": (C.c_double, [dp, dp, C.c_int, ip]),
     "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
+    "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_mvm_f64": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_mvm_dtheta_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_permute_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -197,6 +198,14 @@ class Plan:
         Y = torch.empty_like(V) if out is None else out
         _check(_fn("dski_mvm_tiled", V)(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
                                     _stream(stream)), "dski_mvm_tiled")
+        return Y
+
+    def mvm_stage(self, stage: int, V: torch.Tensor, Y: Optional[torch.Tensor] = None, stream=None):
+        """One stage of the tile-ordered MVM (0 scatter, 1 K_UU, 2 gather into Y)."""
+        V = _block(V, self.N, "V")
+        yp = _dptr(Y) if Y is not None else None
+        _check(lib().dski_mvm_stage(self._h, int(stage), V.shape[0], _dptr(V), self.N, yp, self.N,
+                                    _stream(stream)), "dski_mvm_stage")
         return Y
 
     def mvm_dtheta(self, which: int, V: torch.Tensor, stream=None) -> torch.Tensor:
