@@ -70,7 +70,7 @@ struct dski_plan_s {
   // point data in tile order (device)
   int* perm = nullptr;         // tile position -> user index
   int* cell = nullptr;         // linear cell id per tile position
-  float* toff = nullptr;       // d x n offsets in [0, 1] (SoA)
+  double* toff = nullptr;      // d x n offsets in [0, 1] (SoA, FP64)
   int* cell_start = nullptr;   // ncells + 1
   // workspaces
   dski::DevBuf grid;           // FP64 grid buffer, M * Rmax

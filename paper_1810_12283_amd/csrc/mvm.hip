@@ -71,71 +71,212 @@ static GeoK geo_of(dski_plan p) {
 //   w(x_k)_j V_0[k] + sum_q d_q w(x_k)_j V_q[k].
 // Cell c (1-based per axis) covers nodes c-1..c+2, so node j is touched by
 // cells j-2..j+1 (clipped to 1..m-3); its stencil position in cell c is j-c+1.
-// One launch handles all R columns, RB at a time.
-template <int D, int RB, typename T>
-__global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ cell,
-                                                 const float* __restrict__ toff,
-                                                 const int* __restrict__ cstart, int n, GeoK g,
-                                                 const T* __restrict__ V, int ldv, int R,
-                                                 double* __restrict__ G, long long M) {
-  int j[D];
-  if (D == 1) {
-    j[0] = blockIdx.x * 256 + threadIdx.x;
-    if (j[0] >= g.m[0]) return;
-  } else if (D == 2) {
-    j[1] = blockIdx.x * 16 + (threadIdx.x & 15);
-    j[0] = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (j[0] >= g.m[0] || j[1] >= g.m[1]) return;
-  } else {
-    j[2] = blockIdx.x * 8 + (threadIdx.x & 7);
-    j[1] = (blockIdx.y % ((g.m[1] + 7) / 8)) * 8 + ((threadIdx.x >> 3) & 7);
-    j[0] = (blockIdx.y / ((g.m[1] + 7) / 8)) * 4 + (threadIdx.x >> 6);
-    if (j[0] >= g.m[0] || j[1] >= g.m[1] || j[2] >= g.m[2]) return;
+// LDS-staged version: a work-group owns a tile of grid nodes and one chunk of
+// CR columns.  It copies into LDS the offsets and the CR column values of every
+// point in the cells whose stencils reach the tile (the tile's cells plus a
+// halo of 2 below / 1 above), with a table of each cell's range, then every
+// thread sums its node's contributions from LDS in the same fixed order as
+// above.  Regions with more than PMAX points fall back to reading through the
+// cache (same order, same result).
+template <int D>
+struct TileShape {
+  static constexpr int e0 = D == 1 ? 256 : (D == 2 ? 16 : 4);
+  static constexpr int e1 = D == 2 ? 16 : 8;
+  static constexpr int e2 = 8;
+  static __host__ __device__ constexpr int ext(int a) { return a == 0 ? e0 : (a == 1 ? e1 : e2); }
+  static constexpr int max_cells = D == 1 ? (e0 + 3) : (D == 2 ? (e0 + 3) * (e1 + 3) : (e0 + 3) * (e1 + 3) * (e2 + 3));
+  static constexpr int max_rows = D == 1 ? 1 : (D == 2 ? (e0 + 3) : (e0 + 3) * (e1 + 3));
+};
+
+template <int D, int CR, typename T, int PMAX>
+__global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cell,
+                                                     const double* __restrict__ toff,
+                                                     const int* __restrict__ cstart, int n, GeoK g,
+                                                     const T* __restrict__ V, int ldv, int R,
+                                                     double* __restrict__ G, long long M) {
+  using TS = TileShape<D>;
+  __shared__ double s_t[D][PMAX];
+  __shared__ T s_v[PMAX * CR * (D + 1)];
+  __shared__ int s_lcs[TS::max_cells + 1];
+  __shared__ int s_rcnt[TS::max_rows];
+  __shared__ int s_roff[TS::max_rows + 1];
+  __shared__ int s_rg0[TS::max_rows];
+  const int last = D - 1;
+  // tile origin and this thread's node
+  int origin[D], span[D], rlo[D], jl[D];
+  {
+    int rem = blockIdx.x;
+    for (int a = D - 1; a >= 0; --a) {
+      int nt = (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
+      origin[a] = (rem % nt) * TS::ext(a);
+      rem /= nt;
+    }
   }
+  if (D == 1) {
+    jl[0] = threadIdx.x;
+  } else if (D == 2) {
+    jl[0] = threadIdx.x / TS::e1;
+    jl[1] = threadIdx.x % TS::e1;
+  } else {
+    jl[0] = threadIdx.x / (TS::e1 * TS::e2);
+    jl[1] = (threadIdx.x / TS::e2) % TS::e1;
+    jl[2] = threadIdx.x % TS::e2;
+  }
+  int nrows = 1, ncells_r = 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int tlast = min(origin[a] + TS::ext(a) - 1, g.m[a] - 1);
+    rlo[a] = max(1, origin[a] - 2);
+    int rhi = min(g.nc[a], tlast + 1);
+    span[a] = rhi - rlo[a] + 1;
+    ncells_r *= span[a];
+    if (a < last) nrows *= span[a];
+  }
+  const int r0 = blockIdx.y * CR;
+  const int rc = min(CR, R - r0);
+  // per-row global ranges (rows = all region axes but the last; cells of a row are contiguous)
+  for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
+    int rem = row, base = 0, mul = 1;
+    int c[D];
+    for (int a = last - 1; a >= 0; --a) {
+      c[a] = rlo[a] + rem % span[a];
+      rem /= span[a];
+    }
+    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+    base *= g.nc[last];
+    (void)mul;
+    int g0 = cstart[base + rlo[last] - 1];
+    int g1 = cstart[base + rlo[last] - 1 + span[last]];
+    s_rg0[row] = g0;
+    s_rcnt[row] = g1 - g0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int row = 0; row < nrows; ++row) {
+      s_roff[row] = acc;
+      acc += s_rcnt[row];
+    }
+    s_roff[nrows] = acc;
+  }
+  __syncthreads();
+  const int total = s_roff[nrows];
+  const bool lds_ok = total <= PMAX;
+  if (lds_ok) {
+    // cell table (region-local, row-major) -> LDS point ranges
+    for (int f = threadIdx.x; f < ncells_r; f += blockDim.x) {
+      int row = f / span[last], cl = f % span[last];
+      int rem = row, base = 0;
+      int c[D];
+      for (int a = last - 1; a >= 0; --a) {
+        c[a] = rlo[a] + rem % span[a];
+        rem /= span[a];
+      }
+      for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+      base *= g.nc[last];
+      s_lcs[f] = cstart[base + rlo[last] - 1 + cl] - s_rg0[row] + s_roff[row];
+    }
+    if (threadIdx.x == 0) s_lcs[ncells_r] = total;
+    // point offsets and column values
+    for (int row = 0; row < nrows; ++row) {
+      int cnt = s_rcnt[row], g0 = s_rg0[row], off = s_roff[row];
+      for (int f = threadIdx.x; f < cnt * D; f += blockDim.x) {
+        int i = f % cnt, a = f / cnt;
+        s_t[a][off + i] = toff[(size_t)a * n + g0 + i];
+      }
+      int tot = cnt * rc * (D + 1);
+      for (int f = threadIdx.x; f < tot; f += blockDim.x) {
+        int i = f % cnt, rest = f / cnt;
+        int b = rest % (D + 1), r = rest / (D + 1);
+        s_v[((off + i) * CR + r) * (D + 1) + b] = V[(size_t)(r0 + r) * ldv + (size_t)b * n + g0 + i];
+      }
+    }
+  }
+  __syncthreads();
+  int j[D];
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    j[a] = origin[a] + jl[a];
+    inside = inside && j[a] < g.m[a];
+  }
+  if (!inside) return;
+  double acc[CR];
+#pragma unroll
+  for (int r = 0; r < CR; ++r) acc[r] = 0.0;
   int lo[D], hi[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     lo[a] = max(1, j[a] - 2);
     hi[a] = min(g.nc[a], j[a] + 1);
   }
-  const int last = D - 1;
-  long long node = 0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
-  // the innermost cell axis is a contiguous run of points in tile order
   int outer_cnt = 1;
 #pragma unroll
   for (int a = 0; a < last; ++a) outer_cnt *= hi[a] - lo[a] + 1;
-  for (int r0 = 0; r0 < R; r0 += RB) {
-    const int rcount = min(RB, R - r0);
-    double acc[RB];
+  for (int oc = 0; oc < outer_cnt; ++oc) {
+    int c[D];
+    int rem = oc;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = 0.0;
-    const T* Vr = V + (size_t)r0 * ldv;
-    for (int oc = 0; oc < outer_cnt; ++oc) {
-      int c[D];
-      int rem = oc;
-      int base = 0;
+    for (int a = last - 1; a >= 0; --a) {
+      int sp = hi[a] - lo[a] + 1;
+      c[a] = lo[a] + rem % sp;
+      rem /= sp;
+    }
+    if (lds_ok) {
+      int lrow = 0;
 #pragma unroll
-      for (int a = last - 1; a >= 0; --a) {
-        int span = hi[a] - lo[a] + 1;
-        c[a] = lo[a] + rem % span;
-        rem /= span;
+      for (int a = 0; a < last; ++a) lrow = lrow * span[a] + (c[a] - rlo[a]);
+      for (int cl = lo[last]; cl <= hi[last]; ++cl) {
+        int lc = lrow * span[last] + (cl - rlo[last]);
+        int q0 = s_lcs[lc], q1 = s_lcs[lc + 1];
+        for (int q = q0; q < q1; ++q) {
+          double wv[D], wd[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            int ca = (a == last) ? cl : c[a];
+            int o = j[a] - ca + 1;
+            double t = s_t[a][q];
+            wv[a] = keys_w1(o, t);
+            wd[a] = keys_dw1(o, t) * g.invh[a];
+          }
+          double wprod = 1.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) wprod *= wv[a];
+          double dprod[D];
+#pragma unroll
+          for (int qq = 0; qq < D; ++qq) {
+            double v = 1.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
+            dprod[qq] = v;
+          }
+          const T* sv = s_v + (size_t)q * CR * (D + 1);
+#pragma unroll
+          for (int r = 0; r < CR; ++r) {
+            if (r < rc) {
+              double a = wprod * (double)sv[r * (D + 1)];
+#pragma unroll
+              for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)sv[r * (D + 1) + qq + 1];
+              acc[r] += a;
+            }
+          }
+        }
       }
+    } else {
+      int base = 0;
 #pragma unroll
       for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
       base *= g.nc[last];
       int kb = cstart[base + lo[last] - 1];
       int ke = cstart[base + hi[last]];
       for (int k = kb; k < ke; ++k) {
-        int cl = cell[k];
-        int clast = cl % g.nc[last] + 1;
+        int clast = cell[k] % g.nc[last] + 1;
         double wv[D], wd[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           int ca = (a == last) ? clast : c[a];
           int o = j[a] - ca + 1;
-          double t = (double)toff[(size_t)a * n + k];
+          double t = toff[(size_t)a * n + k];
           wv[a] = keys_w1(o, t);
           wd[a] = keys_dw1(o, t) * g.invh[a];
         }
@@ -144,39 +285,43 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ cell,
         for (int a = 0; a < D; ++a) wprod *= wv[a];
         double dprod[D];
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
+        for (int qq = 0; qq < D; ++qq) {
           double v = 1.0;
 #pragma unroll
-          for (int a = 0; a < D; ++a) v *= (a == q) ? wd[a] : wv[a];
-          dprod[q] = v;
+          for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
+          dprod[qq] = v;
         }
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          if (r < rcount) {
-            const T* vv = Vr + (size_t)r * ldv + k;
+        for (int r = 0; r < CR; ++r) {
+          if (r < rc) {
+            const T* vv = V + (size_t)(r0 + r) * ldv + k;
             double a = wprod * (double)vv[0];
 #pragma unroll
-            for (int q = 0; q < D; ++q) a += dprod[q] * (double)vv[(size_t)(q + 1) * n];
+            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)vv[(size_t)(qq + 1) * n];
             acc[r] += a;
           }
         }
       }
     }
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-      if (r < rcount) G[(size_t)(r0 + r) * M + node] = acc[r];
   }
+  long long node = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
+#pragma unroll
+  for (int r = 0; r < CR; ++r)
+    if (r < rc) G[(size_t)(r0 + r) * M + node] = acc[r];
 }
 
 template <int D, typename T>
 static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
   GeoK g = geo_of(p);
-  dim3 grid;
-  if (D == 1) grid = dim3((g.m[0] + 255) / 256);
-  if (D == 2) grid = dim3((g.m[1] + 15) / 16, (g.m[0] + 15) / 16);
-  if (D == 3) grid = dim3((g.m[2] + 7) / 8, ((g.m[1] + 7) / 8) * ((g.m[0] + 3) / 4));
-  k_scatter<D, 8, T><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv, R, G,
-                                           p->M);
+  using TS = TileShape<D>;
+  long long tiles = 1;
+  for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
+  constexpr int CR = sizeof(T) == 4 ? (D == 3 ? 4 : 8) : (D == 3 ? 2 : 4);
+  dim3 grid((unsigned)tiles, (R + CR - 1) / CR);
+  k_scatter_lds<D, CR, T, 512><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv,
+                                                      R, G, p->M);
 }
 
 template <typename T>
@@ -374,26 +519,21 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
 }
 
 // ------------------------------------------------------------------ gather + noise
-// One thread per point, all R columns in one launch (RB at a time): the 4^d
-// grid values of each column are read once and give the value and all d
-// derivative rows.  Y = S G + D V with FP64 accumulation; optional per-block
-// partials of V.Y per column (the p^T q of CG).
-template <int D, int RB, typename T>
+// One thread per (point, column): the 4^d grid values of the column are read
+// once and give the value and all d derivative rows.  Y = S G + D V with FP64
+// accumulation; optional per-block partials of V.Y per column (p^T q of CG).
+template <int D, typename T>
 __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
-                                                const float* __restrict__ toff, int n, GeoK g,
+                                                const double* __restrict__ toff, int n, GeoK g,
                                                 const double* __restrict__ G, long long M,
                                                 const T* __restrict__ V, int ldv,
                                                 T* __restrict__ Y, int ldy, int R, double nv,
                                                 double ng, double* __restrict__ pq_partial) {
-  int k = blockIdx.x * 256 + threadIdx.x;
-  const bool live = k < n;
-  double w[D][4], dw[D][4];
-  long long base = 0;
-  long long stride[D];
-  stride[D - 1] = 1;
-#pragma unroll
-  for (int a = D - 2; a >= 0; --a) stride[a] = stride[a + 1] * g.m[a + 1];
-  if (live) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y;
+  double dot = 0.0;
+  if (k < n) {
+    double w[D][4], dw[D][4];
     int c[D];
     int rem = cell[k];
 #pragma unroll
@@ -403,100 +543,81 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      keys_weights((double)toff[(size_t)a * n + k], w[a], dw[a]);
+      keys_weights(toff[(size_t)a * n + k], w[a], dw[a]);
 #pragma unroll
       for (int o = 0; o < 4; ++o) dw[a][o] *= g.invh[a];
     }
+    long long base = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) base = base * g.m[a] + (c[a] - 1);
-  }
-  __shared__ double red[RB][4];
-  for (int r0 = 0; r0 < R; r0 += RB) {
-    const int rcount = min(RB, R - r0);
-    double pq[RB];
+    long long stride[D];
+    stride[D - 1] = 1;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) pq[r] = 0.0;
-    if (live) {
+    for (int a = D - 2; a >= 0; --a) stride[a] = stride[a + 1] * g.m[a + 1];
+    const double* Gr = G + (size_t)r * M + base;
+    double acc[D + 1];
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        if (r < rcount) {
-          const double* Gr = G + (size_t)(r0 + r) * M + base;
-          double acc[D + 1];
+    for (int q = 0; q <= D; ++q) acc[q] = 0.0;
+    if (D == 1) {
 #pragma unroll
-          for (int q = 0; q <= D; ++q) acc[q] = 0.0;
-          if (D == 1) {
+      for (int o0 = 0; o0 < 4; ++o0) {
+        double gv = Gr[o0];
+        acc[0] += w[0][o0] * gv;
+        acc[1] += dw[0][o0] * gv;
+      }
+    } else if (D == 2) {
 #pragma unroll
-            for (int o0 = 0; o0 < 4; ++o0) {
-              double gv = Gr[o0];
-              acc[0] += w[0][o0] * gv;
-              acc[1] += dw[0][o0] * gv;
-            }
-          } else if (D == 2) {
+      for (int o0 = 0; o0 < 4; ++o0) {
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int o0 = 0; o0 < 4; ++o0) {
-              double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-              for (int o1 = 0; o1 < 4; ++o1) {
-                double gv = Gr[o0 * stride[0] + o1];
-                s0 += w[D - 1][o1] * gv;
-                s1 += dw[D - 1][o1] * gv;
-              }
-              acc[0] += w[0][o0] * s0;
-              acc[1] += dw[0][o0] * s0;
-              acc[2] += w[0][o0] * s1;
-            }
-          } else {
-#pragma unroll
-            for (int o0 = 0; o0 < 4; ++o0) {
-              double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-#pragma unroll
-              for (int o1 = 0; o1 < 4; ++o1) {
-                double s0 = 0.0, s2 = 0.0;
-#pragma unroll
-                for (int o2 = 0; o2 < 4; ++o2) {
-                  double gv = Gr[o0 * stride[0] + o1 * stride[1] + o2];
-                  s0 += w[D - 1][o2] * gv;
-                  s2 += dw[D - 1][o2] * gv;
-                }
-                t0 += w[1][o1] * s0;
-                t1 += dw[1][o1] * s0;
-                t2 += w[1][o1] * s2;
-              }
-              acc[0] += w[0][o0] * t0;
-              acc[1] += dw[0][o0] * t0;
-              acc[2] += w[0][o0] * t1;
-              acc[3] += w[0][o0] * t2;
-            }
-          }
-          const T* vv = V + (size_t)(r0 + r) * ldv + k;
-          T* yy = Y + (size_t)(r0 + r) * ldy + k;
-          double dot = 0.0;
-#pragma unroll
-          for (int q = 0; q <= D; ++q) {
-            double vin = (double)vv[(size_t)q * n];
-            T out = (T)(acc[q] + (q == 0 ? nv : ng) * vin);
-            yy[(size_t)q * n] = out;
-            dot += vin * (double)out;
-          }
-          pq[r] = dot;
+        for (int o1 = 0; o1 < 4; ++o1) {
+          double gv = Gr[o0 * stride[0] + o1];
+          s0 += w[D - 1][o1] * gv;
+          s1 += dw[D - 1][o1] * gv;
         }
+        acc[0] += w[0][o0] * s0;
+        acc[1] += dw[0][o0] * s0;
+        acc[2] += w[0][o0] * s1;
       }
-    }
-    if (pq_partial) {
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    } else {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        double v = pq[r];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) red[r][wv] = v;
+      for (int o0 = 0; o0 < 4; ++o0) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+        for (int o1 = 0; o1 < 4; ++o1) {
+          double s0 = 0.0, s2 = 0.0;
+#pragma unroll
+          for (int o2 = 0; o2 < 4; ++o2) {
+            double gv = Gr[o0 * stride[0] + o1 * stride[1] + o2];
+            s0 += w[D - 1][o2] * gv;
+            s2 += dw[D - 1][o2] * gv;
+          }
+          t0 += w[1][o1] * s0;
+          t1 += dw[1][o1] * s0;
+          t2 += w[1][o1] * s2;
+        }
+        acc[0] += w[0][o0] * t0;
+        acc[1] += dw[0][o0] * t0;
+        acc[2] += w[0][o0] * t1;
+        acc[3] += w[0][o0] * t2;
       }
-      __syncthreads();
-      if (threadIdx.x < rcount) {
-        int r = threadIdx.x;
-        pq_partial[(size_t)blockIdx.x * R + r0 + r] = red[r][0] + red[r][1] + red[r][2] + red[r][3];
-      }
-      __syncthreads();
     }
+    const T* vv = V + (size_t)r * ldv + k;
+    T* yy = Y + (size_t)r * ldy + k;
+#pragma unroll
+    for (int q = 0; q <= D; ++q) {
+      double vin = (double)vv[(size_t)q * n];
+      T out = (T)(acc[q] + (q == 0 ? nv : ng) * vin);
+      yy[(size_t)q * n] = out;
+      dot += vin * (double)out;
+    }
+  }
+  if (pq_partial) {
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) pq_partial[(size_t)blockIdx.x * R + r] = red[0] + red[1] + red[2] + red[3];
   }
 }
 
@@ -506,8 +627,8 @@ template <int D, typename T>
 static void launch_gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
                           double nv, double ng, double* pq_partial, hipStream_t st) {
   GeoK g = geo_of(p);
-  k_gather<D, 8, T><<<gather_blocks(p), 256, 0, st>>>(p->cell, p->toff, p->n, g, G, p->M, V, ldv, Y,
-                                                      ldy, R, nv, ng, pq_partial);
+  k_gather<D, T><<<dim3(gather_blocks(p), R), 256, 0, st>>>(p->cell, p->toff, p->n, g, G, p->M, V, ldv, Y,
+                                                            ldy, R, nv, ng, pq_partial);
 }
 
 template <typename T>
@@ -523,7 +644,6 @@ dski_status gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* 
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
-
 template dski_status gather<float>(dski_plan, int, const double*, const float*, int, float*, int,
                                    double, double, double*, hipStream_t);
 template dski_status gather<double>(dski_plan, int, const double*, const double*, int, double*, int,

@@ -53,7 +53,7 @@ struct Geo {
 // Cell i_p = clamp(floor(s_p), 1, m_p - 3) with s_p = (x_p - lo_p) / h_p, so
 // the stencil nodes i_p - 1 .. i_p + 2 lie in the grid; t_p = s_p - i_p.
 __global__ void k_cells(const double* __restrict__ X, int n, Geo g, int* __restrict__ cell_u,
-                        float* __restrict__ t_u, int* __restrict__ counts, int* __restrict__ err) {
+                        double* __restrict__ t_u, int* __restrict__ counts, int* __restrict__ err) {
   int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
   int lin = 0;
@@ -68,7 +68,7 @@ __global__ void k_cells(const double* __restrict__ X, int n, Geo g, int* __restr
     i = i < 1 ? 1 : (i > g.m[p] - 3 ? g.m[p] - 3 : i);
     double t = s - (double)i;
     t = fmin(fmax(t, 0.0), 1.0);
-    t_u[(size_t)p * n + u] = (float)t;
+    t_u[(size_t)p * n + u] = t;
     lin = lin * g.nc[p] + (i - 1);
   }
   cell_u[u] = lin;
@@ -126,8 +126,8 @@ __global__ void k_sort_cells(const int* __restrict__ start, int ncells, int* __r
 }
 
 __global__ void k_gather_points(const int* __restrict__ perm, int n, int d,
-                                const int* __restrict__ cell_u, const float* __restrict__ t_u,
-                                int* __restrict__ cell, float* __restrict__ toff) {
+                                const int* __restrict__ cell_u, const double* __restrict__ t_u,
+                                int* __restrict__ cell, double* __restrict__ toff) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int u = perm[k];
@@ -372,7 +372,7 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
   p->ncells = (int)nc;
   DSKI_HIP(hipMalloc(&p->perm, sizeof(int) * (size_t)std::max(n, 1)));
   DSKI_HIP(hipMalloc(&p->cell, sizeof(int) * (size_t)std::max(n, 1)));
-  DSKI_HIP(hipMalloc(&p->toff, sizeof(float) * (size_t)std::max(n, 1) * d));
+  DSKI_HIP(hipMalloc(&p->toff, sizeof(double) * (size_t)std::max(n, 1) * d));
   DSKI_HIP(hipMalloc(&p->cell_start, sizeof(int) * (size_t)(nc + 1)));
   for (int a = 0; a < d; ++a) {
     Axis& A = p->ax[a];
@@ -385,14 +385,14 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
   }
   // temporaries
   int *cell_u = nullptr, *counts = nullptr, *err = nullptr;
-  float* t_u = nullptr;
-  size_t tmp_bytes = sizeof(int) * (size_t)std::max(n, 1) * 1 + sizeof(float) * (size_t)std::max(n, 1) * d +
+  double* t_u = nullptr;
+  size_t tmp_bytes = sizeof(double) * (size_t)std::max(n, 1) * d + sizeof(int) * (size_t)std::max(n, 1) +
                      sizeof(int) * (size_t)(2 * nc + 2) + 64;
   char* tmp = nullptr;
   DSKI_HIP(hipMalloc(&tmp, tmp_bytes));
-  cell_u = reinterpret_cast<int*>(tmp);
-  t_u = reinterpret_cast<float*>(cell_u + std::max(n, 1));
-  counts = reinterpret_cast<int*>(t_u + (size_t)std::max(n, 1) * d);
+  t_u = reinterpret_cast<double*>(tmp);
+  cell_u = reinterpret_cast<int*>(t_u + (size_t)std::max(n, 1) * d);
+  counts = cell_u + std::max(n, 1);
   int* fill = counts + nc + 1;
   err = fill + nc + 1;
   dski_status rc = DSKI_OK;

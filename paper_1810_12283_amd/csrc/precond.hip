@@ -70,7 +70,7 @@ __device__ __forceinline__ void cell_coords(int cl, const GeoP& g, int c[DSKI_MA
 }
 
 // diag[e] for e = blk * n + k (tile order)
-__global__ void k_pc_diag(GeoP g, const int* __restrict__ cell, const float* __restrict__ toff,
+__global__ void k_pc_diag(GeoP g, const int* __restrict__ cell, const double* __restrict__ toff,
                           double* __restrict__ diag) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.N) return;
@@ -134,7 +134,7 @@ __global__ void k_argmax_partial(const double* __restrict__ dres, int N, double*
 __global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int* __restrict__ pi,
                                int nblk, int j, double rel_tol, PivState* __restrict__ ps,
                                int* __restrict__ piv_list, const double* __restrict__ dres,
-                               const int* __restrict__ cell, const float* __restrict__ toff,
+                               const int* __restrict__ cell, const double* __restrict__ toff,
                                double* __restrict__ arow, const double* __restrict__ L,
                                double* __restrict__ lrow) {
   __shared__ double sv[kBlock];
@@ -209,7 +209,7 @@ __global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int*
 
 // Column j of L and the residual-diagonal update.
 __global__ void k_pc_column(GeoP g, int j, const PivState* __restrict__ ps,
-                            const int* __restrict__ cell, const float* __restrict__ toff,
+                            const int* __restrict__ cell, const double* __restrict__ toff,
                             const double* __restrict__ arow, const double* __restrict__ lrow,
                             double* __restrict__ L, double* __restrict__ dres) {
   if (ps->stop) return;
