@@ -210,6 +210,7 @@ def main(argv=None):
         "pcg_true_relres": float(max(r["true_rel"] for r in recs)),
         "pivchol_s": round(float(np.mean([r["pivchol_s"] for r in recs])), 4),
         "mll_and_grad_s": round(float(np.mean([r["mll_s"] for r in recs])), 4),
+        "mll_pcg_iters": int(max(r["mll_iters"] for r in recs)),
         "mll": recs[-1]["mll"],
         "logdet": recs[-1]["logdet"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,

@@ -101,6 +101,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   __shared__ int s_rcnt[TS::max_rows];
   __shared__ int s_roff[TS::max_rows + 1];
   __shared__ int s_rg0[TS::max_rows];
+  __shared__ int s_qk[PMAX];
   const int last = D - 1;
   // tile origin and this thread's node
   int origin[D], span[D], rlo[D], jl[D];
@@ -163,7 +164,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   const int total = s_roff[nrows];
   const bool lds_ok = total <= PMAX;
   if (lds_ok) {
-    // cell table (region-local, row-major) -> LDS point ranges
+    // cell table (region-local, row-major) -> LDS point ranges; and for every LDS
+    // slot the global (tile-order) index of its point
     for (int f = threadIdx.x; f < ncells_r; f += blockDim.x) {
       int row = f / span[last], cl = f % span[last];
       int rem = row, base = 0;
@@ -177,19 +179,24 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
       s_lcs[f] = cstart[base + rlo[last] - 1 + cl] - s_rg0[row] + s_roff[row];
     }
     if (threadIdx.x == 0) s_lcs[ncells_r] = total;
-    // point offsets and column values
-    for (int row = 0; row < nrows; ++row) {
-      int cnt = s_rcnt[row], g0 = s_rg0[row], off = s_roff[row];
-      for (int f = threadIdx.x; f < cnt * D; f += blockDim.x) {
-        int i = f % cnt, a = f / cnt;
-        s_t[a][off + i] = toff[(size_t)a * n + g0 + i];
-      }
-      int tot = cnt * rc * (D + 1);
-      for (int f = threadIdx.x; f < tot; f += blockDim.x) {
-        int i = f % cnt, rest = f / cnt;
-        int b = rest % (D + 1), r = rest / (D + 1);
-        s_v[((off + i) * CR + r) * (D + 1) + b] = V[(size_t)(r0 + r) * ldv + (size_t)b * n + g0 + i];
-      }
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      int row = 0;
+      while (s_roff[row + 1] <= q) ++row;
+      s_qk[q] = s_rg0[row] + q - s_roff[row];
+    }
+  }
+  __syncthreads();
+  if (lds_ok) {
+    // all loads of the region in flat loops (no per-row serialisation)
+    for (int f = threadIdx.x; f < total * D; f += blockDim.x) {
+      int q = f % total, a = f / total;
+      s_t[a][q] = toff[(size_t)a * n + s_qk[q]];
+    }
+    const int tot = total * rc * (D + 1);
+    for (int f = threadIdx.x; f < tot; f += blockDim.x) {
+      int q = f % total, rest = f / total;
+      int b = rest % (D + 1), r = rest / (D + 1);
+      s_v[(q * CR + r) * (D + 1) + b] = V[(size_t)(r0 + r) * ldv + (size_t)b * n + s_qk[q]];
     }
   }
   __syncthreads();
@@ -318,7 +325,7 @@ static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, h
   using TS = TileShape<D>;
   long long tiles = 1;
   for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
-  constexpr int CR = sizeof(T) == 4 ? (D == 3 ? 4 : 8) : (D == 3 ? 2 : 4);
+  constexpr int CR = sizeof(T) == 4 ? 4 : 2;
   dim3 grid((unsigned)tiles, (R + CR - 1) / CR);
   k_scatter_lds<D, CR, T, 512><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv,
                                                       R, G, p->M);
@@ -349,45 +356,107 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-// One Stockham pass (radix 4 or 2) over a length-L sequence handled by `tpp`
-// threads (lane = 0..tpp-1); dir = +1 forward (e^{-2 pi i/L}), -1 inverse.
-__device__ __forceinline__ void stockham_pass(const double2* __restrict__ in,
-                                              double2* __restrict__ out, int L, int Ns,
-                                              int radix, const double2* __restrict__ tw,
-                                              int lane, int tpp, int dir) {
-  if (radix == 4) {
-    int q = L >> 2;
-    int tstep = L / (4 * Ns);
-    for (int jj = lane; jj < q; jj += tpp) {
-      double2 v0 = in[jj], v1 = in[jj + q], v2 = in[jj + 2 * q], v3 = in[jj + 3 * q];
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+__device__ __forceinline__ double2 cmi(double2 a, int dir) {
+  return dir > 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+}
+
+// 4-point DFT in registers (dir = +1: e^{-2 pi i/4}, -1: inverse).
+__device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2& d, int dir) {
+  double2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = cmi(csub(b, d), dir);
+  a = cadd(t0, t2);
+  c = csub(t0, t2);
+  b = cadd(t1, t3);
+  d = csub(t1, t3);
+}
+
+// 8-point DFT in registers: two 4-point DFTs on even / odd inputs, then the
+// twiddles e^{-+2 pi i k/8}.
+__device__ __forceinline__ void dft8(double2 v[8], int dir) {
+  const double h = 0.70710678118654752440;
+  double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3, dir);
+  dft4(o0, o1, o2, o3, dir);
+  // W^1 = (1 -+ i)/sqrt2, W^2 = -+i, W^3 = (-1 -+ i)/sqrt2
+  double2 w1o1 = cscale(cadd(o1, cmi(o1, dir)), h);
+  double2 w2o2 = cmi(o2, dir);
+  double2 w3o3 = cscale(csub(cmi(o3, dir), o3), h);
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, w1o1);
+  v[5] = csub(e1, w1o1);
+  v[2] = cadd(e2, w2o2);
+  v[6] = csub(e2, w2o2);
+  v[3] = cadd(e3, w3o3);
+  v[7] = csub(e3, w3o3);
+}
+
+// One in-place Stockham pass of radix RAD over a length-L sequence in LDS,
+// handled by `tpp` threads: each butterfly reads its RAD inputs into
+// registers, the work-group synchronises, then writes the RAD outputs.
+template <int RAD>
+__device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int L, int Ns,
+                                              const double2* __restrict__ tw, int lane, int tpp,
+                                              int dir) {
+  constexpr int PER = 8 / RAD;  // butterflies per thread when tpp = L / 8
+  const int q = L / RAD;
+  const int tstep = L / (RAD * Ns);
+  double2 v[PER][RAD];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    int jj = lane + b * tpp;
+    if (jj < q) {
       int k = jj & (Ns - 1);
-      if (Ns > 1) {
-        double2 w1 = tw[k * tstep], w2 = tw[2 * k * tstep], w3 = tw[3 * k * tstep];
-        if (dir > 0) {
-          v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
-        } else {
-          v1 = cmulc(v1, w1); v2 = cmulc(v2, w2); v3 = cmulc(v3, w3);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        double2 x = buf[jj + r * q];
+        if (r > 0 && Ns > 1) {
+          double2 w = tw[r * k * tstep];
+          x = dir > 0 ? cmul(x, w) : cmulc(x, w);
         }
+        v[b][r] = x;
       }
-      double2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), a3 = csub(v1, v3);
-      // -i * a3 = (a3.y, -a3.x); +i * a3 = (-a3.y, a3.x)
-      double2 ma3 = dir > 0 ? make_double2(a3.y, -a3.x) : make_double2(-a3.y, a3.x);
-      int o = (jj / Ns) * 4 * Ns + k;
-      out[o] = cadd(a0, a2);
-      out[o + Ns] = cadd(a1, ma3);
-      out[o + 2 * Ns] = csub(a0, a2);
-      out[o + 3 * Ns] = csub(a1, ma3);
+      if (RAD == 8) {
+        dft8(v[b], dir);
+      } else if (RAD == 4) {
+        dft4(v[b][0], v[b][1], v[b][2], v[b][3], dir);
+      } else {
+        double2 a0 = v[b][0], a1 = v[b][1];
+        v[b][0] = cadd(a0, a1);
+        v[b][1] = csub(a0, a1);
+      }
     }
-  } else {
-    int q = L >> 1;
-    int tstep = L / (2 * Ns);
-    for (int jj = lane; jj < q; jj += tpp) {
-      double2 v0 = in[jj], v1 = in[jj + q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    int jj = lane + b * tpp;
+    if (jj < q) {
       int k = jj & (Ns - 1);
-      if (Ns > 1) v1 = dir > 0 ? cmul(v1, tw[k * tstep]) : cmulc(v1, tw[k * tstep]);
-      int o = (jj / Ns) * 2 * Ns + k;
-      out[o] = cadd(v0, v1);
-      out[o + Ns] = csub(v0, v1);
+      int o = (jj / Ns) * RAD * Ns + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[o + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void fft_inplace(double2* buf, int L, const double2* tw, int lane, int tpp,
+                                            int dir) {
+  int Ns = 1;
+  while (Ns < L) {
+    int left = L / Ns;
+    if (left % 8 == 0) {
+      stockham_pass<8>(buf, L, Ns, tw, lane, tpp, dir);
+      Ns *= 8;
+    } else if (left % 4 == 0) {
+      stockham_pass<4>(buf, L, Ns, tw, lane, tpp, dir);
+      Ns *= 4;
+    } else {
+      stockham_pass<2>(buf, L, Ns, tw, lane, tpp, dir);
+      Ns *= 2;
     }
   }
 }
@@ -396,32 +465,29 @@ __device__ __forceinline__ void stockham_pass(const double2* __restrict__ in,
 // (m values at stride `inner`) is zero-padded to L, transformed, multiplied by the
 // circulant eigenvalues `spec` (already scaled by 1/L) and transformed back; two
 // lines share one complex FFT (real and imaginary parts), which is exact because
-// the spectrum is real and even.
-template <int PPB>
+// the spectrum is real and even.  TPP = L/8 threads per line pair, 256/TPP pairs
+// per work-group, 32 KiB of LDS.
 __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long long nlines, int m,
                                                   int L, long long inner,
                                                   const double2* __restrict__ tw,
                                                   const double* __restrict__ spec) {
   extern __shared__ double2 smem[];
-  constexpr int TPP = 256 / PPB;
-  const int pr = threadIdx.x / TPP;
-  const int lane = threadIdx.x % TPP;
-  double2* bufA = smem;                  // PPB * L
-  double2* bufB = smem + (size_t)PPB * L;  // PPB * L
-  const long long line0 = (long long)blockIdx.x * (2 * PPB);
+  const int tpp = L / 8;
+  const int ppb = 256 / tpp;
+  const int pr = threadIdx.x / tpp;
+  const int lane = threadIdx.x % tpp;
+  const long long line0 = (long long)blockIdx.x * (2 * ppb);
   const long long linestride = (long long)m * inner;
-  // cooperative load (zero padding beyond m)
-  for (int f = threadIdx.x; f < PPB * L; f += 256) bufA[f] = make_double2(0.0, 0.0);
+  for (int f = threadIdx.x; f < ppb * L; f += 256) smem[f] = make_double2(0.0, 0.0);
   __syncthreads();
-  const int nl = 2 * PPB;
+  const int nl = 2 * ppb;
   if (inner > 1) {
     for (int f = threadIdx.x; f < nl * m; f += 256) {
       int l = f % nl, jj = f / nl;
       long long line = line0 + l;
       if (line < nlines) {
         double v = G[(line / inner) * linestride + line % inner + (long long)jj * inner];
-        double* dst = reinterpret_cast<double*>(&bufA[(size_t)(l >> 1) * L + jj]);
-        dst[l & 1] = v;
+        reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v;
       }
     }
   } else {
@@ -430,55 +496,30 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
       long long line = line0 + l;
       if (line < nlines) {
         double v = G[line * m + jj];
-        double* dst = reinterpret_cast<double*>(&bufA[(size_t)(l >> 1) * L + jj]);
-        dst[l & 1] = v;
+        reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v;
       }
     }
   }
   __syncthreads();
-  double2* a = bufA + (size_t)pr * L;
-  double2* b = bufB + (size_t)pr * L;
-  // forward
-  int Ns = 1;
-  while (Ns < L) {
-    int radix = ((L / Ns) % 4 == 0) ? 4 : 2;
-    stockham_pass(a, b, L, Ns, radix, tw, lane, TPP, +1);
-    __syncthreads();
-    double2* t = a; a = b; b = t;
-    Ns *= radix;
-  }
-  for (int kk = lane; kk < L; kk += TPP) {
-    double s = spec[kk];
-    a[kk] = make_double2(a[kk].x * s, a[kk].y * s);
-  }
+  double2* buf = smem + (size_t)pr * L;
+  fft_inplace(buf, L, tw, lane, tpp, +1);
+  for (int kk = lane; kk < L; kk += tpp) buf[kk] = cscale(buf[kk], spec[kk]);
   __syncthreads();
-  Ns = 1;
-  while (Ns < L) {
-    int radix = ((L / Ns) % 4 == 0) ? 4 : 2;
-    stockham_pass(a, b, L, Ns, radix, tw, lane, TPP, -1);
-    __syncthreads();
-    double2* t = a; a = b; b = t;
-    Ns *= radix;
-  }
-  // `a` now holds the result for this pair; the final buffer is the same for all pairs
-  double2* res = a - (size_t)pr * L;  // base of the result buffer (A or B)
+  fft_inplace(buf, L, tw, lane, tpp, -1);
   if (inner > 1) {
     for (int f = threadIdx.x; f < nl * m; f += 256) {
       int l = f % nl, jj = f / nl;
       long long line = line0 + l;
-      if (line < nlines) {
-        const double* src = reinterpret_cast<const double*>(&res[(size_t)(l >> 1) * L + jj]);
-        G[(line / inner) * linestride + line % inner + (long long)jj * inner] = src[l & 1];
-      }
+      if (line < nlines)
+        G[(line / inner) * linestride + line % inner + (long long)jj * inner] =
+            reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
     }
   } else {
     for (int f = threadIdx.x; f < nl * m; f += 256) {
       int jj = f % m, l = f / m;
       long long line = line0 + l;
-      if (line < nlines) {
-        const double* src = reinterpret_cast<const double*>(&res[(size_t)(l >> 1) * L + jj]);
-        G[line * m + jj] = src[l & 1];
-      }
+      if (line < nlines)
+        G[line * m + jj] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
     }
   }
 }
@@ -494,25 +535,14 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
     const double* spec = (a == dwhich) ? A.dspec : A.spec;
     const double2* tw = reinterpret_cast<const double2*>(A.twiddle);
     int L = A.L;
-    if (L <= 512) {
-      constexpr int PPB = 4;
-      size_t sh = sizeof(double2) * 2 * PPB * L;
-      long long blocks = (nlines + 2 * PPB - 1) / (2 * PPB);
-      k_toeplitz<PPB><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
-    } else if (L <= 1024) {
-      constexpr int PPB = 2;
-      size_t sh = sizeof(double2) * 2 * PPB * L;
-      long long blocks = (nlines + 2 * PPB - 1) / (2 * PPB);
-      k_toeplitz<PPB><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
-    } else if (L <= 2048) {
-      constexpr int PPB = 1;
-      size_t sh = sizeof(double2) * 2 * PPB * L;
-      long long blocks = (nlines + 2 * PPB - 1) / (2 * PPB);
-      k_toeplitz<PPB><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
-    } else {
-      set_error("FFT length %d not supported (grid size per axis <= 1024)", L);
+    if (L < 8 || L > 2048) {
+      set_error("FFT length %d not supported (grid size per axis 4..1024)", L);
       return DSKI_ENOTSUP;
     }
+    int ppb = 256 / (L / 8);
+    size_t sh = sizeof(double2) * (size_t)ppb * L;
+    long long blocks = (nlines + 2 * ppb - 1) / (2 * ppb);
+    k_toeplitz<<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
     DSKI_HIP(hipGetLastError());
   }
   return DSKI_OK;

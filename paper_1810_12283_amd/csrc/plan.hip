@@ -274,7 +274,7 @@ template dski_status rademacher<float>(uint64_t, int, int, int, float*, int, hip
 template dski_status rademacher<double>(uint64_t, int, int, int, double*, int, hipStream_t);
 
 static int fft_len(int m) {
-  int L = 4;
+  int L = 8;
   while (L < 2 * m - 1) L <<= 1;
   return L;
 }
