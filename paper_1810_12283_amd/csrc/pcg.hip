@@ -1,269 +1,329 @@
 // Preconditioned conjugate gradients on a block of R right-hand sides (Sec. 2,
 // Sec. 3.3).  The columns are independent CG runs that share every MVM (the
 // block is not a block-Krylov method, so each column keeps its own Lanczos
-// tridiagonal for quadrature).  Vectors are FP32 (or FP64) in tile order, the iterate x
-// is accumulated in FP64, all inner products and scalars are FP64 and live on
-// the device; the host only polls the number of active columns every few
-// iterations.
+// tridiagonal for quadrature).  Vectors are FP32 (or FP64) in tile order, the
+// iterate x is accumulated in FP64, all inner products and scalars are FP64 and
+// live on the device; the host only polls the number of active columns.
+//
+// One iteration is 9 launches (10 with the FFT of a 3-D grid):
+//   scatter | K_UU per axis | gather (+ partials of p.q)
+//   update:  alpha (every block reduces the p.q partials itself, same order),
+//            x += alpha p, r -= alpha q, partials of r.r and of U^T D^{-1/2} r
+//   reduce:  t1 = U^T r', coef1 = c .* t1; r.r
+//   project: t2 = U^T (r' - U coef1)
+//   reduce:  coef2 = c .* (t1 + t2)
+//   final:   z = D^{-1/2}(r' - U coef2) (+ partials of r.z)
+//   beta:    beta (every block reduces the r.z partials), convergence test,
+//            p = z + beta p.
+// Scalars that one kernel both reads in every block and updates (rz, the
+// active flags) are double-buffered by iteration parity.
 #include <cmath>
 
 #include "internal.h"
+#include "tskinny.h"
 
 namespace dski {
 
+constexpr int kPcgMaxR = 32;  // columns per fused PCG (larger blocks run in groups)
+
 struct PcgScal {
-  double* rz;     // r^T M^{-1} r
-  double* rr;     // r^T r
-  double* bb;     // b^T b
-  double* alpha;
-  double* beta;
-  double* tol2;
-  int* active;
-  int* iters;
-  int* flags;     // [0] number of active columns, [1] breakdown
+  double* rz;     // [2][R] r^T M^{-1} r, by parity
+  double* rr;     // [R] r^T r (current)
+  double* bb;     // [R] b^T b
+  double* alpha;  // [R]
+  double* tol2;   // [R]
+  int* active;    // [2][R] by parity
+  int* iters;     // [R]
+  int* flags;     // [0] active columns, [1] breakdown
 };
 
-constexpr int kVecChunk = 1024;  // elements per work-group in the vector kernels
+constexpr int kVecChunk = 1024;  // rows per work-group in the streaming vector kernels
 
 static int nchunks(int N) { return (N + kVecChunk - 1) / kVecChunk; }
 
-// R = B, X = 0, partials of b.b
-template <typename T>
-__global__ void k_pcg_init(const T* __restrict__ B, int ldb, T* __restrict__ Rr,
-                           double* __restrict__ Xd, int N, int R, double* __restrict__ partial) {
-  int r = blockIdx.y;
-  int e0 = blockIdx.x * kVecChunk;
-  double acc = 0.0;
-  for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
-    T b = B[(size_t)r * ldb + e];
-    Rr[(size_t)r * N + e] = b;
-    Xd[(size_t)r * N + e] = 0.0;
-    acc += (double)b * (double)b;
-  }
-  __shared__ double red[4];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * R + r] = red[0] + red[1] + red[2] + red[3];
-}
-
-__device__ double block_sum_col(const double* __restrict__ partial, int nblk, int R, int r) {
-  __shared__ double buf[kBlock];
-  double a = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) a += partial[(size_t)b * R + r];
-  buf[threadIdx.x] = a;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) buf[threadIdx.x] += buf[threadIdx.x + off];
-    __syncthreads();
-  }
-  double v = buf[0];
-  __syncthreads();
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-// After the initial preconditioner application: rz, bb, rr, active flags.
-__global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b,
-                                const double* __restrict__ rz_part, int nb_z, int R,
-                                int fixed_iters, PcgScal s, double* __restrict__ rz0) {
-  int r = blockIdx.x;
-  double bb = block_sum_col(bb_part, nb_b, R, r);
-  double rz = rz_part ? block_sum_col(rz_part, nb_z, R, r) : bb;
-  if (threadIdx.x == 0) {
-    s.bb[r] = bb;
-    s.rr[r] = bb;
-    s.rz[r] = rz;
-    rz0[r] = rz;
-    s.iters[r] = 0;
-    int act = bb > 0.0 && (fixed_iters > 0 || bb > s.tol2[r] * bb);
-    s.active[r] = act;
-    if (act) atomicAdd(&s.flags[0], 1);
-  }
-}
-
-// alpha = r^T z / p^T q
-__global__ void k_pcg_alpha(const double* __restrict__ pq_part, int nblk, int R, PcgScal s,
-                            double* __restrict__ hist, int max_iter) {
-  int r = blockIdx.x;
-  double pq = block_sum_col(pq_part, nblk, R, r);
-  if (threadIdx.x == 0) {
-    double a = 0.0;
-    if (s.active[r]) {
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        s.flags[1] = 1;
-      } else {
-        a = s.rz[r] / pq;
-      }
-      if (hist && s.iters[r] < max_iter) hist[(size_t)r * max_iter + s.iters[r]] = a;
-    }
-    s.alpha[r] = a;
-  }
-}
-
-// x += alpha p (FP64), r -= alpha q; partials of r.r
+// R = B, X = 0, partials of b.b (block = kVecChunk rows, all columns)
 template <typename T>
-__global__ void k_pcg_update_xr(const T* __restrict__ P, const T* __restrict__ Q,
-                                T* __restrict__ Rr, double* __restrict__ Xd, int N, int R,
-                                PcgScal s, double* __restrict__ partial) {
-  int r = blockIdx.y;
-  int e0 = blockIdx.x * kVecChunk;
-  double acc = 0.0;
-  if (s.active[r]) {
-    double a = s.alpha[r];
-    for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
-      size_t i = (size_t)r * N + e;
-      Xd[i] += a * (double)P[i];
-      T rn = (T)((double)Rr[i] - a * (double)Q[i]);
-      Rr[i] = rn;
-      acc += (double)rn * (double)rn;
-    }
-  }
+__global__ void k_pcg_init(const T* __restrict__ B, int ldb, T* __restrict__ Rr, double* __restrict__ Xd,
+                           int N, int R, double* __restrict__ partial) {
   __shared__ double red[4];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  const int e0 = blockIdx.x * kVecChunk;
+  for (int c = 0; c < R; ++c) {
+    double acc = 0.0;
+    for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
+      T b = B[(size_t)c * ldb + e];
+      Rr[(size_t)c * N + e] = b;
+      Xd[(size_t)c * N + e] = 0.0;
+      acc += (double)b * (double)b;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * R + c] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+// fixed-order sum of column c of per-block partials (nblk x R); called by one thread
+__device__ __forceinline__ double col_sum(const double* __restrict__ part, int nblk, int R, int c) {
+  double a = 0.0;
+  for (int b = 0; b < nblk; ++b) a += part[(size_t)b * R + c];
+  return a;
+}
+
+// After the initial preconditioner application (parity 0): rz, bb, rr, active.
+__global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, const double* __restrict__ rz_part,
+                                int nb_z, int R, int fixed_iters, PcgScal s, double* __restrict__ rz0) {
+  int c = threadIdx.x;
+  if (c >= R) return;
+  double bb = col_sum(bb_part, nb_b, R, c);
+  double rz = rz_part ? col_sum(rz_part, nb_z, R, c) : bb;
+  s.bb[c] = bb;
+  s.rr[c] = bb;
+  s.rz[c] = rz;
+  s.rz[R + c] = rz;
+  rz0[c] = rz;
+  s.iters[c] = 0;
+  int act = bb > 0.0 && (fixed_iters > 0 || bb > s.tol2[c] * bb);
+  s.active[c] = act;
+  s.active[R + c] = act;
+  if (act) atomicAdd(&s.flags[0], 1);
+}
+
+// alpha, x and r updates, partials of r.r and of U^T D^{-1/2} r (row tile of RT rows).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, const T* __restrict__ Q,
+                                                    T* __restrict__ Rr, double* __restrict__ Xd, int N, int n,
+                                                    int R, PcgScal s, int par, const double* __restrict__ pq_part,
+                                                    int nb_pq, double* __restrict__ rr_part,
+                                                    const T* __restrict__ U, int k, double isf, double isg,
+                                                    int RT, ProjLds L, double* __restrict__ t_part,
+                                                    double* __restrict__ hist, int max_iter) {
+  extern __shared__ __align__(16) char smem[];
+  T* sU = reinterpret_cast<T*>(smem + L.oU);
+  double* sx = reinterpret_cast<double*>(smem + L.ox);
+  double* sred = reinterpret_cast<double*>(smem + L.ored);
+  __shared__ double s_alpha[kPcgMaxR];
+  __shared__ int s_act[kPcgMaxR];
+  const int* act = s.active + par * R;
+  if (threadIdx.x < R) {
+    int c = threadIdx.x;
+    double a = 0.0;
+    int on = act[c];
+    if (on) {
+      double pq = col_sum(pq_part, nb_pq, R, c);
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0) s.flags[1] = 1;
+      } else {
+        a = s.rz[par * R + c] / pq;
+      }
+      if (blockIdx.x == 0 && hist && s.iters[c] < max_iter) hist[(size_t)c * max_iter + s.iters[c]] = a;
+    }
+    if (blockIdx.x == 0) s.alpha[c] = a;
+    s_alpha[c] = a;
+    s_act[c] = on;
+  }
+  const int e0 = blockIdx.x * RT;
+  const int rn = min(RT, N - e0);
+  if (k > 0) tile_load_u<T>(U, N, k, e0, rn, RT, sU);
   __syncthreads();
-  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * R + r] = red[0] + red[1] + red[2] + red[3];
+  for (int f = threadIdx.x; f < RT * R; f += blockDim.x) {
+    int r = f % RT, c = f / RT;
+    double v = 0.0;
+    if (r < rn) {
+      size_t i = (size_t)c * N + e0 + r;
+      double rv = (double)Rr[i];
+      if (s_act[c]) {
+        double a = s_alpha[c];
+        Xd[i] += a * (double)P[i];
+        T rnew = (T)(rv - a * (double)Q[i]);
+        Rr[i] = rnew;
+        rv = (double)rnew;
+      }
+      v = rv;
+    }
+    sx[r * R + c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < R) {
+    int c = threadIdx.x;
+    double acc = 0.0;
+    for (int r = 0; r < rn; ++r) {
+      double v = sx[r * R + c];
+      acc += v * v;
+    }
+    rr_part[(size_t)blockIdx.x * R + c] = acc;
+  }
+  if (k == 0) return;
+  __syncthreads();
+  for (int f = threadIdx.x; f < rn * R; f += blockDim.x) {
+    int r = f / R;
+    sx[f] *= (e0 + r < n ? isf : isg);
+  }
+  __syncthreads();
+  tile_proj<T>(sU, sx, rn, RT, k, R, sred, t_part + (size_t)blockIdx.x * k * R);
 }
 
-__global__ void k_pcg_rr(const double* __restrict__ part, int nblk, int R, PcgScal s) {
-  int r = blockIdx.x;
-  double v = block_sum_col(part, nblk, R, r);
-  if (threadIdx.x == 0 && s.active[r]) s.rr[r] = v;
-}
-
-// beta = r'^T z' / r^T z, history, convergence test, active count
-__global__ void k_pcg_beta(const double* __restrict__ rz_part, int nblk, int R, PcgScal s,
-                           double* __restrict__ hist, int max_iter, int fixed_iters) {
-  int r = blockIdx.x;
-  double rzn = rz_part ? block_sum_col(rz_part, nblk, R, r) : 0.0;
-  if (threadIdx.x == 0) {
-    if (!rz_part) rzn = s.rr[r];
+// beta, history, convergence test (block 0 writes the next parity), p = z + beta p.
+template <typename T>
+__global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, int R, PcgScal s, int par,
+                           const double* __restrict__ rz_part, int nb_rz, double* __restrict__ hist,
+                           int max_iter, int fixed_iters) {
+  __shared__ double s_beta[kPcgMaxR];
+  __shared__ int s_act[kPcgMaxR];
+  if (threadIdx.x < R) {
+    int c = threadIdx.x;
+    int on = s.active[par * R + c];
+    double rz_old = s.rz[par * R + c];
     double b = 0.0;
-    if (s.active[r]) {
-      if (!(rzn >= 0.0) || !isfinite(rzn)) s.flags[1] = 1;
-      b = s.rz[r] > 0.0 ? rzn / s.rz[r] : 0.0;
-      int it = s.iters[r];
-      if (hist && it < max_iter) hist[(size_t)R * max_iter + (size_t)r * max_iter + it] = b;
-      s.iters[r] = it + 1;
-      s.rz[r] = rzn;
-      bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (s.rr[r] <= s.tol2[r] * s.bb[r]);
-      if (done) {
-        s.active[r] = 0;
-        atomicSub(&s.flags[0], 1);
+    double rzn = rz_old;
+    int on_next = on;
+    if (on) {
+      rzn = rz_part ? col_sum(rz_part, nb_rz, R, c) : s.rr[c];
+      if (!(rzn >= 0.0) || !isfinite(rzn)) {
+        if (blockIdx.x == 0) s.flags[1] = 1;
+      }
+      b = rz_old > 0.0 ? rzn / rz_old : 0.0;
+      int it = s.iters[c];
+      bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (s.rr[c] <= s.tol2[c] * s.bb[c]);
+      on_next = done ? 0 : 1;
+      if (blockIdx.x == 0) {
+        if (hist && it < max_iter) hist[(size_t)R * max_iter + (size_t)c * max_iter + it] = b;
+        s.iters[c] = it + 1;
+        if (done) atomicSub(&s.flags[0], 1);
       }
     }
-    s.beta[r] = b;
+    if (blockIdx.x == 0) {
+      s.rz[(1 - par) * R + c] = rzn;
+      s.active[(1 - par) * R + c] = on_next;
+    }
+    s_beta[c] = b;
+    s_act[c] = on;
+  }
+  __syncthreads();
+  const int e0 = blockIdx.x * kVecChunk;
+  const int e1 = min(N, e0 + kVecChunk);
+  for (int c = 0; c < R; ++c) {
+    if (!s_act[c]) continue;
+    double b = s_beta[c];
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      size_t i = (size_t)c * N + e;
+      P[i] = (T)((double)Z[i] + b * (double)P[i]);
+    }
   }
 }
 
 template <typename T>
-__global__ void k_pcg_update_p(const T* __restrict__ Z, T* __restrict__ P, int N, PcgScal s) {
-  int r = blockIdx.y;
-  if (!s.active[r]) return;
-  double b = s.beta[r];
-  int e0 = blockIdx.x * kVecChunk;
-  for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
-    size_t i = (size_t)r * N + e;
-    P[i] = (T)((double)Z[i] + b * (double)P[i]);
-  }
-}
-
-template <typename T>
-__global__ void k_copy_f(const T* __restrict__ a, T* __restrict__ b, int N, int R) {
-  int r = blockIdx.y;
-  int e0 = blockIdx.x * kVecChunk;
-  for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x)
-    b[(size_t)r * N + e] = a[(size_t)r * N + e];
+__global__ void k_copy_cols(const T* __restrict__ a, T* __restrict__ b, int N, int R) {
+  const int e0 = blockIdx.x * kVecChunk;
+  for (int c = 0; c < R; ++c)
+    for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x)
+      b[(size_t)c * N + e] = a[(size_t)c * N + e];
 }
 
 template <typename TO>
-__global__ void k_x_out(const double* __restrict__ Xd, int N, TO* __restrict__ X, int ldx) {
-  int r = blockIdx.y;
-  int e0 = blockIdx.x * kVecChunk;
-  for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x)
-    X[(size_t)r * ldx + e] = (TO)Xd[(size_t)r * N + e];
+__global__ void k_x_out(const double* __restrict__ Xd, int N, int R, TO* __restrict__ X, int ldx) {
+  const int e0 = blockIdx.x * kVecChunk;
+  for (int c = 0; c < R; ++c)
+    for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x)
+      X[(size_t)c * ldx + e] = (TO)Xd[(size_t)c * N + e];
 }
 
+// One PCG on R <= kPcgMaxR columns (history layout [alpha: R x max_iter][beta: R x max_iter]).
 template <typename T>
-dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
-                      const double* tol_host, int max_iter, int fixed_iters, double* alpha_beta,
-                      PcgResult& res, hipStream_t st, double* X64) {
-  int N = p->N;
-  res.iters.assign(R, 0);
-  res.relres.assign(R, 0.0);
-  res.rz0.assign(R, 0.0);
-  if (R <= 0) return DSKI_OK;
-  // workspace: Rr, Z, P, Q (FP32), Xd (FP64), partials, scalars
-  size_t nr = (size_t)N * R;
-  int nbv = nchunks(N);
-  int nbg = gather_blocks(p);
-  int nbz = vec_blocks(N);
-  int npart = std::max(nbv, std::max(nbg, nbz));
-  size_t fbytes = sizeof(T) * nr * 4;
-  size_t dbytes = sizeof(double) * (nr + (size_t)npart * R * 2 + 8 * (size_t)R + 8);
-  size_t ibytes = sizeof(int) * (2 * (size_t)R + 8);
-  DevBuf& wb = p->vin;  // shares the plan's vector workspace
-  DSKI_TRY(wb.reserve(fbytes + dbytes + ibytes + 512));
-  char* base = wb.as<char>();
+static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
+                             const double* tol_host, int max_iter, int fixed_iters, double* hist,
+                             PcgResult& res, int res_c0, hipStream_t st, double* X64, int ldx64) {
+  const int N = p->N, n = p->n;
+  const int k = pc ? pc->k : 0;
+  const size_t nr = (size_t)N * R;
+  const int nbv = nchunks(N), nbg = gather_blocks(p), nbz = vec_blocks(N);
+  ProjLds L = proj_lds(k, R, sizeof(T));
+  const int nbt = (N + L.RT - 1) / L.RT;
+  const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, nbt)) * R;
+  const size_t ntp = (size_t)nbt * std::max(k, 1) * R;
+  // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, t2, coef, scalars
+  size_t tb = ((sizeof(T) * nr * 4) + 63) / 64 * 64;
+  size_t db = sizeof(double) * (nr + 3 * npart + ntp + 3 * (size_t)k * R + 12 * (size_t)R + 16);
+  size_t ib = sizeof(int) * (4 * (size_t)R + 8);
+  DSKI_TRY(p->vin.reserve(tb + db + ib + 512));
+  char* base = p->vin.as<char>();
   T* Rr = reinterpret_cast<T*>(base);
   T* Z = Rr + nr;
   T* P = Z + nr;
   T* Q = P + nr;
-  double* Xd = reinterpret_cast<double*>(Q + nr);
-  double* part1 = Xd + nr;
-  double* part2 = part1 + (size_t)npart * R;
+  double* Xd = reinterpret_cast<double*>(base + tb);
+  double* pq_part = Xd + nr;
+  double* rr_part = pq_part + npart;
+  double* rz_part = rr_part + npart;
+  double* t_part = rz_part + npart;
+  double* t1 = t_part + ntp;
+  double* t2 = t1 + (size_t)k * R;
+  double* coef = t2 + (size_t)k * R;
   PcgScal s;
-  s.rz = part2 + (size_t)npart * R;
-  s.rr = s.rz + R;
+  s.rz = coef + (size_t)k * R;
+  s.rr = s.rz + 2 * R;
   s.bb = s.rr + R;
   s.alpha = s.bb + R;
-  s.beta = s.alpha + R;
-  s.tol2 = s.beta + R;
+  s.tol2 = s.alpha + R;
   double* rz0 = s.tol2 + R;
-  s.active = reinterpret_cast<int*>(rz0 + R + 1);
-  s.iters = s.active + R;
+  s.active = reinterpret_cast<int*>(rz0 + R + 2);
+  s.iters = s.active + 2 * R;
   s.flags = s.iters + R;
   std::vector<double> tol2(R);
   for (int r = 0; r < R; ++r) tol2[r] = tol_host ? tol_host[r] * tol_host[r] : 0.0;
   DSKI_HIP(hipMemcpyAsync(s.tol2, tol2.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
   DSKI_HIP(hipMemsetAsync(s.flags, 0, sizeof(int) * 2, st));
-  dim3 vg(nbv, R);
-  k_pcg_init<T><<<vg, kBlock, 0, st>>>(B, ldb, Rr, Xd, N, R, part1);
-  // z = M^{-1} r, p = z
+  k_pcg_init<T><<<nbv, kBlock, 0, st>>>(B, ldb, Rr, Xd, N, R, rr_part);
   const double* rzp = nullptr;
-  T* Zuse = Rr;
-  int nbzz = 0;
+  const T* Zuse = Rr;
   if (pc) {
-    DSKI_TRY(precond_apply_tiled<T>(pc, R, Rr, N, Z, N, part2, &nbzz, st));
-    rzp = part2;
+    DSKI_TRY(precond_apply_tiled<T>(pc, R, Rr, N, Z, N, rz_part, nullptr, st));
+    rzp = rz_part;
     Zuse = Z;
   }
-  k_copy_f<T><<<vg, kBlock, 0, st>>>(Zuse, P, N, R);
-  k_pcg_init_scal<<<R, kBlock, 0, st>>>(part1, nbv, rzp, nbzz, R, fixed_iters, s, rz0);
+  k_copy_cols<T><<<nbv, kBlock, 0, st>>>(Zuse, P, N, R);
+  k_pcg_init_scal<<<1, 64, 0, st>>>(rr_part, nbv, rzp, nbz, R, fixed_iters, s, rz0);
   DSKI_HIP(hipGetLastError());
   int* hflags = nullptr;
   DSKI_HIP(hipHostMalloc(&hflags, sizeof(int) * 2, hipHostMallocDefault));
+  const T* U = pc ? u_of<T>(pc) : nullptr;
+  const double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
   dski_status rc = DSKI_OK;
-  int limit = fixed_iters > 0 ? fixed_iters : max_iter;
-  int it = 0;
-  int check = 1;
+  const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
+  int it = 0, check = 1;
   while (it < limit) {
     int burst = std::min(check, limit - it);
     for (int b = 0; b < burst; ++b) {
-      rc = mvm_tiled<T>(p, R, P, N, Q, N, part1, st);
+      const int par = (it + b) & 1;
+      rc = mvm_tiled<T>(p, R, P, N, Q, N, pq_part, st);
       if (rc < 0) break;
-      k_pcg_alpha<<<R, kBlock, 0, st>>>(part1, nbg, R, s, alpha_beta, max_iter);
-      k_pcg_update_xr<T><<<vg, kBlock, 0, st>>>(P, Q, Rr, Xd, N, R, s, part2);
-      k_pcg_rr<<<R, kBlock, 0, st>>>(part2, nbv, R, s);
-      if (pc) {
-        rc = precond_apply_tiled<T>(pc, R, Rr, N, Z, N, part1, &nbzz, st);
+      k_pcg_update<T><<<nbt, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U, k,
+                                                     isf, isg, L.RT, L, t_part, hist, max_iter);
+      RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
+      if (pc && k > 0) {
+        RedJob jt{t_part, nbt, k * R, R, t1, pc->c, nullptr, 1.0, coef, nullptr};
+        rc = launch_reduce(jt, &jr, st);
         if (rc < 0) break;
-        k_pcg_beta<<<R, kBlock, 0, st>>>(part1, nbzz, R, s, alpha_beta, max_iter, fixed_iters);
-        k_pcg_update_p<T><<<vg, kBlock, 0, st>>>(Z, P, N, s);
+        k_ts_proj<T><<<nbt, kBlock, L.bytes, st>>>(Rr, N, N, n, R, isf, isg, U, k, coef, L.RT, L, t_part);
+        RedJob j2{t_part, nbt, k * R, R, t2, pc->c, t1, 1.0, coef, nullptr};
+        rc = launch_reduce(j2, nullptr, st);
+        if (rc < 0) break;
+        k_ts_final<T><<<nbz, kBlock, sizeof(double) * k * R, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, k,
+                                                                   coef, Z, N, rz_part);
       } else {
-        k_pcg_beta<<<R, kBlock, 0, st>>>(nullptr, 0, R, s, alpha_beta, max_iter, fixed_iters);
-        k_pcg_update_p<T><<<vg, kBlock, 0, st>>>(Rr, P, N, s);
+        rc = launch_reduce(jr, nullptr, st);
+        if (rc < 0) break;
+        if (pc)  // rank-0 preconditioner: M = D
+          k_ts_final<T><<<nbz, kBlock, 0, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N,
+                                               rz_part);
       }
+      k_pcg_beta<T><<<nbv, kBlock, 0, st>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist,
+                                            max_iter, fixed_iters);
     }
     if (rc < 0) break;
     it += burst;
@@ -288,19 +348,22 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, 
   }
   (void)hipHostFree(hflags);
   if (rc < 0 && rc != DSKI_EBREAKDOWN) return rc;
-  if (X) k_x_out<T><<<vg, kBlock, 0, st>>>(Xd, N, X, ldx);
-  if (X64) k_x_out<double><<<vg, kBlock, 0, st>>>(Xd, N, X64, ldx);
+  if (X) k_x_out<T><<<nbv, kBlock, 0, st>>>(Xd, N, R, X, ldx);
+  if (X64) k_x_out<double><<<nbv, kBlock, 0, st>>>(Xd, N, R, X64, ldx64);
   DSKI_HIP(hipGetLastError());
   std::vector<double> hrr(R), hbb(R), hrz0(R);
-  DSKI_HIP(hipMemcpyAsync(res.iters.data(), s.iters, sizeof(int) * R, hipMemcpyDeviceToHost, st));
+  std::vector<int> hit(R);
+  DSKI_HIP(hipMemcpyAsync(hit.data(), s.iters, sizeof(int) * R, hipMemcpyDeviceToHost, st));
   DSKI_HIP(hipMemcpyAsync(hrr.data(), s.rr, sizeof(double) * R, hipMemcpyDeviceToHost, st));
   DSKI_HIP(hipMemcpyAsync(hbb.data(), s.bb, sizeof(double) * R, hipMemcpyDeviceToHost, st));
-  DSKI_HIP(hipMemcpyAsync(res.rz0.data(), rz0, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+  DSKI_HIP(hipMemcpyAsync(hrz0.data(), rz0, sizeof(double) * R, hipMemcpyDeviceToHost, st));
   DSKI_HIP(hipStreamSynchronize(st));
   bool notconv = false;
   for (int r = 0; r < R; ++r) {
-    res.relres[r] = hbb[r] > 0 ? std::sqrt(std::max(hrr[r], 0.0) / hbb[r]) : 0.0;
-    if (fixed_iters <= 0 && tol_host && res.relres[r] > tol_host[r]) notconv = true;
+    res.iters[res_c0 + r] = hit[r];
+    res.rz0[res_c0 + r] = hrz0[r];
+    res.relres[res_c0 + r] = hbb[r] > 0 ? std::sqrt(std::max(hrr[r], 0.0) / hbb[r]) : 0.0;
+    if (fixed_iters <= 0 && tol_host && res.relres[res_c0 + r] > tol_host[r]) notconv = true;
   }
   if (rc == DSKI_EBREAKDOWN) {
     res.breakdown = true;
@@ -309,6 +372,29 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, 
   return notconv ? DSKI_NOT_CONVERGED : DSKI_OK;
 }
 
+template <typename T>
+dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
+                      const double* tol_host, int max_iter, int fixed_iters, double* alpha_beta,
+                      PcgResult& res, hipStream_t st, double* X64) {
+  res.iters.assign(R, 0);
+  res.relres.assign(R, 0.0);
+  res.rz0.assign(R, 0.0);
+  if (R <= 0) return DSKI_OK;
+  if (R > kPcgMaxR && alpha_beta) {
+    set_error("PCG with a CG-coefficient history supports at most %d columns per call", kPcgMaxR);
+    return DSKI_ENOTSUP;
+  }
+  dski_status worst = DSKI_OK;
+  for (int c0 = 0; c0 < R; c0 += kPcgMaxR) {
+    int rg = std::min(kPcgMaxR, R - c0);
+    dski_status rc = pcg_group<T>(p, pc, rg, B + (size_t)c0 * ldb, ldb, X ? X + (size_t)c0 * ldx : nullptr, ldx,
+                                  tol_host + c0, max_iter, fixed_iters, alpha_beta, res, c0, st,
+                                  X64 ? X64 + (size_t)c0 * ldx : nullptr, ldx);
+    if (rc < 0) return rc;
+    if (rc > worst) worst = rc;
+  }
+  return worst;
+}
 template dski_status pcg_tiled<float>(dski_plan, dski_precond, int, const float*, int, float*, int,
                                       const double*, int, int, double*, PcgResult&, hipStream_t, double*);
 template dski_status pcg_tiled<double>(dski_plan, dski_precond, int, const double*, int, double*, int,

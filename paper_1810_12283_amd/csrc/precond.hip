@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "tskinny.h"
 
 namespace dski {
 
@@ -286,147 +287,48 @@ __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, doub
 }
 
 // ------------------------------------------------------------------ apply
-// Partials of U^T v over a chunk of rows, with
-//   v = pre_e * X_e - sum_i U[e, i] coef[i, r]   (coef may be NULL).
-constexpr int kProjRC = 16;  // columns per launch
-
-template <typename T>
-__global__ void k_proj(const T* __restrict__ U, int N, int n, int k, int rows, const T* __restrict__ X,
-                       int ld, int r0, int rc, double pre_v, double pre_g,
-                       const double* __restrict__ coef, int R, double* __restrict__ partial) {
-  extern __shared__ double sm[];
-  T* sU = reinterpret_cast<T*>(sm);                                             // k x rows
-  double* sval = sm + ((size_t)k * rows * sizeof(T) + sizeof(double) - 1) / sizeof(double);  // rows x RC
-  double* sco = sval + (size_t)rows * kProjRC;                                  // k x RC
-  int e0 = blockIdx.x * rows;
-  int rn = min(rows, N - e0);
-  for (int f = threadIdx.x; f < k * rows; f += blockDim.x) {
-    int i = f / rows, r = f % rows;
-    sU[(size_t)i * rows + r] = r < rn ? U[(size_t)i * N + e0 + r] : (T)0;
-  }
-  if (coef)
-    for (int f = threadIdx.x; f < k * rc; f += blockDim.x) {
-      int i = f / rc, c = f % rc;
-      sco[i * kProjRC + c] = coef[(size_t)i * R + r0 + c];
-    }
-  __syncthreads();
-  for (int f = threadIdx.x; f < rows * rc; f += blockDim.x) {
-    int r = f % rows, c = f / rows;
-    double v = 0.0;
-    if (r < rn) {
-      int e = e0 + r;
-      v = (e < n ? pre_v : pre_g) * (double)X[(size_t)(r0 + c) * ld + e];
-      if (coef)
-        for (int i = 0; i < k; ++i) v -= (double)sU[(size_t)i * rows + r] * sco[i * kProjRC + c];
-    }
-    sval[(size_t)r * kProjRC + c] = v;
-  }
-  __syncthreads();
-  for (int f = threadIdx.x; f < k * rc; f += blockDim.x) {
-    int i = f / rc, c = f % rc;
-    double acc = 0.0;
-    for (int r = 0; r < rn; ++r) acc += (double)sU[(size_t)i * rows + r] * sval[(size_t)r * kProjRC + c];
-    partial[(size_t)blockIdx.x * k * R + (size_t)i * R + r0 + c] = acc;
-  }
-}
-
-// out_e = post_e * (pre_e * X_e - sum_i U[e, i] coef[i, r]); optional partials of X.out.
-template <typename T>
-__global__ void k_pc_final(const T* __restrict__ U, int N, int n, int k, const T* __restrict__ X,
-                           int ld, int R, double pre_v, double pre_g, double post_v, double post_g,
-                           const double* __restrict__ coef, T* __restrict__ out, int ldo,
-                           double* __restrict__ dot_partial) {
-  extern __shared__ double sco[];  // k x R
-  for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
-  __syncthreads();
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  int r = blockIdx.y;
-  double dot = 0.0;
-  if (e < N) {
-    double pre = e < n ? pre_v : pre_g;
-    double post = e < n ? post_v : post_g;
-    double x = (double)X[(size_t)r * ld + e];
-    double v = pre * x;
-    for (int i = 0; i < k; ++i) v -= (double)U[(size_t)i * N + e] * sco[i * R + r];
-    T o = (T)(post * v);
-    out[(size_t)r * ldo + e] = o;
-    dot = x * (double)o;
-  }
-  if (dot_partial) {
-    __shared__ double red[4];
-    for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
-    __syncthreads();
-    if (threadIdx.x == 0) dot_partial[(size_t)blockIdx.x * R + r] = red[0] + red[1] + red[2] + red[3];
-  }
-}
-
-// coef[i, r] = sgn * c_i * (t1[i, r] + t2[i, r])  (t2 may be NULL).
-__global__ void k_coef(const double* __restrict__ c, const double* __restrict__ t1,
-                       const double* __restrict__ t2, int k, int R, double sgn,
-                       double* __restrict__ coef) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= k * R) return;
-  int i = f / R;
-  double t = t1[f] + (t2 ? t2[f] : 0.0);
-  coef[f] = sgn * c[i] * t;
-}
-
-// rows per projection block so that the LDS tile stays within 60 KiB
-static int proj_rows(int k, size_t tsize) {
-  int rows = 128;
-  while (rows > 8 && (size_t)k * rows * tsize + sizeof(double) * ((size_t)rows * kProjRC + (size_t)k * kProjRC) >
-                         61440)
-    rows /= 2;
-  return rows;
-}
-
-static size_t proj_lds(int k, int rows, size_t tsize) {
-  return ((size_t)k * rows * tsize + sizeof(double) - 1) / sizeof(double) * sizeof(double) +
-         sizeof(double) * ((size_t)rows * kProjRC + (size_t)k * kProjRC);
-}
+// Tall-skinny products with the N x k factor U (column-major):
+//   projection  t = U^T v      (k x R; split over row tiles, register-blocked 2 x 4
+//                               outputs per thread from an LDS tile of U and v,
+//                               per-tile partials reduced in a fixed order),
+//   correction  z = post .* (pre .* x - U coef)   (one thread per row, all R
+//                               columns in registers, U read once).
+// With R = 17 columns these products do ~6 flops per byte, below the vector-ALU
+// ridge, so they stay on the vector units.
 
 int vec_blocks(int N) { return (N + kBlock - 1) / kBlock; }
 
-template <typename T>
-static const T* u_of(dski_precond pc);
-template <>
-const float* u_of<float>(dski_precond pc) { return pc->U; }
-template <>
-const double* u_of<double>(dski_precond pc) { return pc->Ud; }
+struct PcWork {
+  double* partial;  // nblk x k x R
+  double* t1;
+  double* t2;
+  double* coef;
+  int nblk;
+  ProjLds L;
+};
 
-// t[k x R] = U^T (pre .* X - U coef)
 template <typename T>
-static dski_status project(dski_precond pc, int R, const T* X, int ld, double pre_v, double pre_g,
-                           const double* coef, double* partial, double* t, hipStream_t st) {
-  dski_plan p = pc->plan;
-  int k = pc->k, N = p->N;
-  int rows = proj_rows(k, sizeof(T));
-  int nblk = (N + rows - 1) / rows;
-  size_t lds = proj_lds(k, rows, sizeof(T));
-  for (int r0 = 0; r0 < R; r0 += kProjRC) {
-    int rc = std::min(kProjRC, R - r0);
-    k_proj<T><<<nblk, kBlock, lds, st>>>(u_of<T>(pc), N, p->n, k, rows, X, ld, r0, rc, pre_v, pre_g, coef,
-                                         R, partial);
-  }
-  DSKI_HIP(hipGetLastError());
-  return reduce_partials(partial, nblk, k * R, t, st);
-}
-
-static dski_status ensure_work(dski_precond pc, int R, double** partial, double** t1, double** t2,
-                               double** coef) {
+static dski_status pc_work(dski_precond pc, int R, PcWork& w) {
   dski_plan p = pc->plan;
   int k = pc->k;
-  int rows = proj_rows(k, sizeof(double));
-  int nblk = (p->N + rows - 1) / rows;
-  size_t np = std::max((size_t)nblk * k * R, (size_t)vec_blocks(p->N) * R);
-  size_t want = sizeof(double) * (np + 3 * (size_t)k * R + 64);
-  DSKI_TRY(pc->work.reserve(want));
+  w.L = proj_lds(k, R, sizeof(T));
+  w.nblk = (p->N + w.L.RT - 1) / w.L.RT;
+  size_t np = std::max((size_t)w.nblk * k * R, (size_t)vec_blocks(p->N) * R);
+  DSKI_TRY(pc->work.reserve(sizeof(double) * (np + 3 * (size_t)k * R + 64)));
   double* base = pc->work.as<double>();
-  *partial = base;
-  *t1 = base + np;
-  *t2 = *t1 + (size_t)k * R;
-  *coef = *t2 + (size_t)k * R;
+  w.partial = base;
+  w.t1 = base + np;
+  w.t2 = w.t1 + (size_t)k * R;
+  w.coef = w.t2 + (size_t)k * R;
+  return DSKI_OK;
+}
+
+template <typename T>
+static dski_status check_cols(int R) {
+  if (R > kFinalMaxR) {
+    set_error("at most %d columns per preconditioner application", kFinalMaxR);
+    return DSKI_ENOTSUP;
+  }
   return DSKI_OK;
 }
 
@@ -438,25 +340,38 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
   double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
   if (nblk_out) *nblk_out = vec_blocks(N);
   if (R <= 0) return DSKI_OK;
-  dim3 fgrid(vec_blocks(N), R);
+  if (R > kFinalMaxR) {  // independent columns: apply in groups
+    for (int c0 = 0; c0 < R; c0 += kFinalMaxR) {
+      int rc = std::min(kFinalMaxR, R - c0);
+      DSKI_TRY(precond_apply_tiled<T>(pc, rc, Rm + (size_t)c0 * ld, ld, Z + (size_t)c0 * ldz, ldz, nullptr,
+                                      nullptr, st));
+    }
+    return DSKI_OK;
+  }
+  const T* U = u_of<T>(pc);
   if (k == 0) {
-    k_pc_final<T><<<fgrid, kBlock, 0, st>>>(u_of<T>(pc), N, p->n, 0, Rm, ld, R, isf, isg, isf, isg, nullptr,
-                                            Z, ldz, rz_partial);
+    k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(Rm, ld, N, p->n, R, isf, isg, isf, isg, U, 0, nullptr, Z,
+                                                   ldz, rz_partial);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   }
-  double *partial, *t1, *t2, *coef;
-  DSKI_TRY(ensure_work(pc, R, &partial, &t1, &t2, &coef));
-  int cb = (k * R + kBlock - 1) / kBlock;
-  // t1 = U^T r',  r' = D^{-1/2} Rm
-  DSKI_TRY(project<T>(pc, R, Rm, ld, isf, isg, nullptr, partial, t1, st));
-  k_coef<<<cb, kBlock, 0, st>>>(pc->c, t1, nullptr, k, R, 1.0, coef);
-  // t2 = U^T w,  w = r' - U (c .* t1)
-  DSKI_TRY(project<T>(pc, R, Rm, ld, isf, isg, coef, partial, t2, st));
-  k_coef<<<cb, kBlock, 0, st>>>(pc->c, t1, t2, k, R, 1.0, coef);
-  // Z = D^{-1/2} (r' - U (c .* (t1 + t2)))
-  k_pc_final<T><<<fgrid, kBlock, sizeof(double) * k * R, st>>>(u_of<T>(pc), N, p->n, k, Rm, ld, R, isf,
-                                                               isg, isf, isg, coef, Z, ldz, rz_partial);
+  PcWork w;
+  DSKI_TRY(pc_work<T>(pc, R, w));
+  // t1 = U^T r',  r' = D^{-1/2} Rm;  coef1 = c .* t1
+  k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, nullptr, w.L.RT, w.L,
+                                                  w.partial);
+  DSKI_HIP(hipGetLastError());
+  RedJob j1{w.partial, w.nblk, k * R, R, w.t1, pc->c, nullptr, 1.0, w.coef, nullptr};
+  DSKI_TRY(launch_reduce(j1, nullptr, st));
+  // t2 = U^T (r' - U coef1);  coef2 = c .* (t1 + t2)
+  k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, w.coef, w.L.RT, w.L,
+                                                  w.partial);
+  DSKI_HIP(hipGetLastError());
+  RedJob j2{w.partial, w.nblk, k * R, R, w.t2, pc->c, w.t1, 1.0, w.coef, nullptr};
+  DSKI_TRY(launch_reduce(j2, nullptr, st));
+  // Z = D^{-1/2} (r' - U coef2)
+  k_ts_final<T><<<vec_blocks(N), kBlock, sizeof(double) * k * R, st>>>(Rm, ld, N, p->n, R, isf, isg, isf, isg,
+                                                                      U, k, w.coef, Z, ldz, rz_partial);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
@@ -471,20 +386,29 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
   dski_plan p = pc->plan;
   int k = pc->k, N = p->N;
   if (R <= 0) return DSKI_OK;
-  dim3 fgrid(vec_blocks(N), R);
+  if (R > kFinalMaxR) {
+    for (int c0 = 0; c0 < R; c0 += kFinalMaxR) {
+      int rc = std::min(kFinalMaxR, R - c0);
+      DSKI_TRY(precond_factor_apply_tiled<T>(pc, rc, W + (size_t)c0 * ld, ld, Z + (size_t)c0 * ldz, ldz, st));
+    }
+    return DSKI_OK;
+  }
+  const T* U = u_of<T>(pc);
   if (k == 0) {
-    k_pc_final<T><<<fgrid, kBlock, 0, st>>>(u_of<T>(pc), N, p->n, 0, W, ld, R, 1.0, 1.0, p->sf, p->sg,
-                                            nullptr, Z, ldz, nullptr);
+    k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, U, 0, nullptr,
+                                                   Z, ldz, nullptr);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   }
-  double *partial, *t1, *t2, *coef;
-  DSKI_TRY(ensure_work(pc, R, &partial, &t1, &t2, &coef));
-  int cb = (k * R + kBlock - 1) / kBlock;
-  DSKI_TRY(project<T>(pc, R, W, ld, 1.0, 1.0, nullptr, partial, t1, st));
-  k_coef<<<cb, kBlock, 0, st>>>(pc->rootc, t1, nullptr, k, R, -1.0, coef);
-  k_pc_final<T><<<fgrid, kBlock, sizeof(double) * k * R, st>>>(u_of<T>(pc), N, p->n, k, W, ld, R, 1.0, 1.0,
-                                                               p->sf, p->sg, coef, Z, ldz, nullptr);
+  PcWork w;
+  DSKI_TRY(pc_work<T>(pc, R, w));
+  k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(W, ld, N, p->n, R, 1.0, 1.0, U, k, nullptr, w.L.RT, w.L,
+                                                  w.partial);
+  DSKI_HIP(hipGetLastError());
+  RedJob j1{w.partial, w.nblk, k * R, R, w.t1, pc->rootc, nullptr, -1.0, w.coef, nullptr};
+  DSKI_TRY(launch_reduce(j1, nullptr, st));
+  k_ts_final<T><<<vec_blocks(N), kBlock, sizeof(double) * k * R, st>>>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg,
+                                                                      U, k, w.coef, Z, ldz, nullptr);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }

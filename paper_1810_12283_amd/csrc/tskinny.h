@@ -1,0 +1,218 @@
+// Tall-skinny products with the N x k preconditioner factor U, shared by the
+// preconditioner and the fused PCG iteration (device helpers and kernels that
+// each translation unit instantiates for itself).
+#pragma once
+
+#include "internal.h"
+
+namespace dski {
+
+template <typename T>
+inline const T* u_of(dski_precond pc);
+template <>
+inline const float* u_of<float>(dski_precond pc) { return pc->U; }
+template <>
+inline const double* u_of<double>(dski_precond pc) { return pc->Ud; }
+
+// LDS plan of a projection tile: U tile (RT x (k+1), T), v tile (RT x R, FP64),
+// coefficients (k x R, FP64), two row-split partial sums (2 x k x R, FP64).
+struct ProjLds {
+  int RT = 128;
+  size_t oU = 0, ox = 0, ocoef = 0, ored = 0, bytes = 0;
+};
+
+inline ProjLds proj_lds(int k, int R, size_t tsize) {
+  ProjLds L;
+  for (L.RT = 128; L.RT >= 8; L.RT /= 2) {
+    size_t u = ((size_t)L.RT * (k + 1) * tsize + 15) / 16 * 16;
+    L.oU = 0;
+    L.ox = u;
+    L.ocoef = L.ox + sizeof(double) * (size_t)L.RT * R;
+    L.ored = L.ocoef + sizeof(double) * (size_t)k * R;
+    L.bytes = L.ored + sizeof(double) * 2 * (size_t)k * R;
+    if (L.bytes <= 61440) break;
+  }
+  return L;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_load_u(const T* __restrict__ U, int N, int k, int e0, int rn, int RT,
+                                            T* __restrict__ sU) {
+  for (int f = threadIdx.x; f < k * RT; f += blockDim.x) {
+    int i = f / RT, r = f % RT;
+    sU[r * (k + 1) + i] = r < rn ? U[(size_t)i * N + e0 + r] : (T)0;
+  }
+}
+
+// partial[i, c] of sum over the tile rows of sU[r, i] * sx[r, c]; 2 x 4 outputs per
+// task, rows split in two halves whose sums are added in a fixed order.
+template <typename T>
+__device__ __forceinline__ void tile_proj(const T* __restrict__ sU, const double* __restrict__ sx,
+                                          int rn, int RT, int k, int R, double* __restrict__ sred,
+                                          double* __restrict__ out) {
+  const int ni = (k + 1) / 2, nc = (R + 3) / 4;
+  const int ntask = ni * nc * 2;
+  const int half = RT / 2;
+  for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+    int rs = task & 1, rest = task >> 1;
+    int cb = rest % nc, ib = rest / nc;
+    int i0 = 2 * ib, c0 = 4 * cb;
+    double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int rb = rs * half, re = min(rn, rb + half);
+    for (int r = rb; r < re; ++r) {
+      const T* ur = sU + r * (k + 1);
+      double u0 = (double)ur[i0];
+      double u1 = i0 + 1 < k ? (double)ur[i0 + 1] : 0.0;
+      const double* xr = sx + r * R;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double x = c0 + j < R ? xr[c0 + j] : 0.0;
+        acc[0][j] += u0 * x;
+        acc[1][j] += u1 * x;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (i0 + a < k && c0 + j < R) sred[((size_t)rs * k + i0 + a) * R + c0 + j] = acc[a][j];
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < k * R; f += blockDim.x) out[f] = sred[f] + sred[(size_t)k * R + f];
+}
+
+// Fixed-order reduction of per-tile partials (nblk x nout) in up to two jobs (blockIdx.y):
+//   out[o] = sum_b partial[b, o];  optional t_out = out, and
+//   coef[o] = sgn * c[o / R] * (out[o] + t_prev[o]).
+struct RedJob {
+  const double* partial;
+  int nblk, nout, R;
+  double* out;             // may be NULL
+  const double* c;         // may be NULL (no coefficients)
+  const double* t_prev;    // may be NULL
+  double sgn;
+  double* coef;            // may be NULL
+  const int* mask;         // optional: only write out[o] when mask[o % R] (per-column flag)
+};
+
+static __global__ void k_ts_reduce(RedJob j0, RedJob j1) {
+  const RedJob& J = blockIdx.y == 0 ? j0 : j1;
+  __shared__ double red[4][64];
+  int o = blockIdx.x * 64 + (threadIdx.x & 63);
+  int q = threadIdx.x >> 6;
+  double a = 0.0;
+  if (o < J.nout)
+    for (int b = q; b < J.nblk; b += 4) a += J.partial[(size_t)b * J.nout + o];
+  red[q][threadIdx.x & 63] = a;
+  __syncthreads();
+  if (q == 0 && o < J.nout) {
+    double t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    bool write = !J.mask || J.mask[o % J.R];
+    if (J.out && write) J.out[o] = t;
+    if (J.coef) J.coef[o] = J.sgn * J.c[o / J.R] * (t + (J.t_prev ? J.t_prev[o] : 0.0));
+  }
+}
+
+static inline dski_status launch_reduce(const RedJob& a, const RedJob* b, hipStream_t st) {
+  int nout = std::max(a.nout, b ? b->nout : 0);
+  dim3 grid((nout + 63) / 64, b ? 2 : 1);
+  RedJob bb = b ? *b : a;
+  k_ts_reduce<<<grid, 256, 0, st>>>(a, bb);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+constexpr int kFinalMaxR = 32;
+
+// z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]); per-block partials of X.z
+template <typename T>
+static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X, int ld, int N, int n, int R,
+                                                  double pre_v, double pre_g, double post_v, double post_g,
+                                                  const T* __restrict__ U, int k,
+                                                  const double* __restrict__ coef, T* __restrict__ Z, int ldz,
+                                                  double* __restrict__ dot_partial) {
+  extern __shared__ __align__(16) char smem[];
+  double* sco = reinterpret_cast<double*>(smem);  // k x R
+  for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
+  __syncthreads();
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[kFinalMaxR];
+#pragma unroll
+  for (int c = 0; c < kFinalMaxR; ++c) acc[c] = 0.0;
+  if (e < N) {
+    for (int i = 0; i < k; ++i) {
+      double u = (double)U[(size_t)i * N + e];
+      const double* cr = sco + i * R;
+#pragma unroll
+      for (int c = 0; c < kFinalMaxR; ++c)
+        if (c < R) acc[c] += u * cr[c];
+    }
+  }
+  const double pre = e < n ? pre_v : pre_g, post = e < n ? post_v : post_g;
+  __shared__ double red[4];
+#pragma unroll
+  for (int c = 0; c < kFinalMaxR; ++c) {
+    if (c < R) {
+      double dot = 0.0;
+      if (e < N) {
+        double x = (double)X[(size_t)c * ld + e];
+        T z = (T)(post * (pre * x - acc[c]));
+        Z[(size_t)c * ldz + e] = z;
+        dot = x * (double)z;
+      }
+      if (dot_partial) {
+        for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+        __syncthreads();
+        if (threadIdx.x == 0) dot_partial[(size_t)blockIdx.x * R + c] = red[0] + red[1] + red[2] + red[3];
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// partial t over a row tile of  v = pre .* X - U coef  (coef may be NULL)
+template <typename T>
+static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X, int ld, int N, int n, int R,
+                                                 double pre_v, double pre_g, const T* __restrict__ U, int k,
+                                                 const double* __restrict__ coef, int RT, ProjLds L,
+                                                 double* __restrict__ partial) {
+  extern __shared__ __align__(16) char smem[];
+  T* sU = reinterpret_cast<T*>(smem + L.oU);
+  double* sx = reinterpret_cast<double*>(smem + L.ox);
+  double* sco = reinterpret_cast<double*>(smem + L.ocoef);
+  double* sred = reinterpret_cast<double*>(smem + L.ored);
+  const int e0 = blockIdx.x * RT;
+  const int rn = min(RT, N - e0);
+  tile_load_u<T>(U, N, k, e0, rn, RT, sU);
+  for (int f = threadIdx.x; f < RT * R; f += blockDim.x) {
+    int r = f % RT, c = f / RT;
+    int e = e0 + r;
+    sx[r * R + c] = r < rn ? (e < n ? pre_v : pre_g) * (double)X[(size_t)c * ld + e] : 0.0;
+  }
+  if (coef)
+    for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
+  __syncthreads();
+  if (coef) {
+    // sx[r, c] -= sum_i sU[r, i] coef[i, c]   (tasks: one row x 4 columns)
+    const int nc = (R + 3) / 4;
+    for (int task = threadIdx.x; task < rn * nc; task += blockDim.x) {
+      int r = task % rn, c0 = (task / rn) * 4;
+      double acc[4] = {0, 0, 0, 0};
+      const T* ur = sU + r * (k + 1);
+      for (int i = 0; i < k; ++i) {
+        double u = (double)ur[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c0 + j < R) acc[j] += u * sco[i * R + c0 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (c0 + j < R) sx[r * R + c0 + j] -= acc[j];
+    }
+    __syncthreads();
+  }
+  tile_proj<T>(sU, sx, rn, RT, k, R, sred, partial + (size_t)blockIdx.x * k * R);
+}
+
+}  // namespace dski
