@@ -136,10 +136,14 @@ struct PcgResult {
   bool breakdown = false;
 };
 // X (storage type, may be NULL) and/or X64 (FP64, may be NULL) receive the iterate.
+// verify_mask (host, R flags, may be NULL): columns whose convergence is confirmed
+// with the true residual b - K~ x (and resumed if needed; their CG history then
+// no longer describes a single Krylov run).
 template <typename T>
 dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
                       const double* tol_host, int max_iter, int fixed_iters, double* alpha_beta,
-                      PcgResult& res, hipStream_t st, double* X64 = nullptr);
+                      PcgResult& res, hipStream_t st, double* X64 = nullptr,
+                      const int* verify_mask = nullptr);
 
 // --- host numerics ---------------------------------------------------------------------
 double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok);

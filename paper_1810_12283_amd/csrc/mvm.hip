@@ -551,7 +551,8 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
 // ------------------------------------------------------------------ gather + noise
 // One thread per (point, column): the 4^d grid values of the column are read
 // once and give the value and all d derivative rows.  Y = S G + D V with FP64
-// accumulation; optional per-block partials of V.Y per column (p^T q of CG).
+// accumulation; optional per-block partials of V.Y per column (p^T q of CG),
+// stored output-major: pq_partial[column * blocks + block].
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
                                                 const double* __restrict__ toff, int n, GeoK g,
@@ -647,7 +648,7 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
     for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
     __syncthreads();
-    if (threadIdx.x == 0) pq_partial[(size_t)blockIdx.x * R + r] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) pq_partial[(size_t)r * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
   }
 }
 

@@ -41,10 +41,6 @@ constexpr int kVecChunk = 1024;  // rows per work-group in the streaming vector 
 
 static int nchunks(int N) { return (N + kVecChunk - 1) / kVecChunk; }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // R = B, X = 0, partials of b.b (block = kVecChunk rows, all columns)
 template <typename T>
@@ -60,28 +56,23 @@ __global__ void k_pcg_init(const T* __restrict__ B, int ldb, T* __restrict__ Rr,
       Xd[(size_t)c * N + e] = 0.0;
       acc += (double)b * (double)b;
     }
-    acc = wave_sum(acc);
+    acc = wave_sum64(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * R + c] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) partial[(size_t)c * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
     __syncthreads();
   }
 }
 
-// fixed-order sum of column c of per-block partials (nblk x R); called by one thread
-__device__ __forceinline__ double col_sum(const double* __restrict__ part, int nblk, int R, int c) {
-  double a = 0.0;
-  for (int b = 0; b < nblk; ++b) a += part[(size_t)b * R + c];
-  return a;
-}
-
 // After the initial preconditioner application (parity 0): rz, bb, rr, active.
+// One wavefront per column (partials are output-major).
 __global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, const double* __restrict__ rz_part,
                                 int nb_z, int R, int fixed_iters, PcgScal s, double* __restrict__ rz0) {
-  int c = threadIdx.x;
-  if (c >= R) return;
-  double bb = col_sum(bb_part, nb_b, R, c);
-  double rz = rz_part ? col_sum(rz_part, nb_z, R, c) : bb;
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wv; c < R; c += nw) {
+    double bb = wave_out_sum(bb_part, nb_b, c);
+    double rz = rz_part ? wave_out_sum(rz_part, nb_z, c) : bb;
+    if ((threadIdx.x & 63) != 0) continue;
   s.bb[c] = bb;
   s.rr[c] = bb;
   s.rz[c] = rz;
@@ -92,6 +83,7 @@ __global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, co
   s.active[c] = act;
   s.active[R + c] = act;
   if (act) atomicAdd(&s.flags[0], 1);
+  }
 }
 
 // alpha, x and r updates, partials of r.r and of U^T D^{-1/2} r (row tile of RT rows).
@@ -110,22 +102,24 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
   __shared__ double s_alpha[kPcgMaxR];
   __shared__ int s_act[kPcgMaxR];
   const int* act = s.active + par * R;
-  if (threadIdx.x < R) {
-    int c = threadIdx.x;
-    double a = 0.0;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = wv; c < R; c += 4) {  // one wavefront per column
     int on = act[c];
-    if (on) {
-      double pq = col_sum(pq_part, nb_pq, R, c);
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        if (blockIdx.x == 0) s.flags[1] = 1;
-      } else {
-        a = s.rz[par * R + c] / pq;
+    double pq = on ? wave_out_sum(pq_part, nb_pq, c) : 0.0;
+    if (lane == 0) {
+      double a = 0.0;
+      if (on) {
+        if (!(pq > 0.0) || !isfinite(pq)) {
+          if (blockIdx.x == 0) s.flags[1] = 1;
+        } else {
+          a = s.rz[par * R + c] / pq;
+        }
+        if (blockIdx.x == 0 && hist && s.iters[c] < max_iter) hist[(size_t)c * max_iter + s.iters[c]] = a;
       }
-      if (blockIdx.x == 0 && hist && s.iters[c] < max_iter) hist[(size_t)c * max_iter + s.iters[c]] = a;
+      if (blockIdx.x == 0) s.alpha[c] = a;
+      s_alpha[c] = a;
+      s_act[c] = on;
     }
-    if (blockIdx.x == 0) s.alpha[c] = a;
-    s_alpha[c] = a;
-    s_act[c] = on;
   }
   const int e0 = blockIdx.x * RT;
   const int rn = min(RT, N - e0);
@@ -149,14 +143,14 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
     sx[r * R + c] = v;
   }
   __syncthreads();
-  if (threadIdx.x < R) {
-    int c = threadIdx.x;
+  for (int c = wv; c < R; c += 4) {
     double acc = 0.0;
-    for (int r = 0; r < rn; ++r) {
+    for (int r = lane; r < rn; r += 64) {
       double v = sx[r * R + c];
       acc += v * v;
     }
-    rr_part[(size_t)blockIdx.x * R + c] = acc;
+    acc = wave_sum64(acc);
+    if (lane == 0) rr_part[(size_t)c * gridDim.x + blockIdx.x] = acc;
   }
   if (k == 0) return;
   __syncthreads();
@@ -165,7 +159,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
     sx[f] *= (e0 + r < n ? isf : isg);
   }
   __syncthreads();
-  tile_proj<T>(sU, sx, rn, RT, k, R, sred, t_part + (size_t)blockIdx.x * k * R);
+  tile_proj<T>(sU, sx, rn, RT, k, R, sred, t_part);
 }
 
 // beta, history, convergence test (block 0 writes the next parity), p = z + beta p.
@@ -175,15 +169,17 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
                            int max_iter, int fixed_iters) {
   __shared__ double s_beta[kPcgMaxR];
   __shared__ int s_act[kPcgMaxR];
-  if (threadIdx.x < R) {
-    int c = threadIdx.x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = wv; c < R; c += 4) {  // one wavefront per column
     int on = s.active[par * R + c];
+    double rzs = (on && rz_part) ? wave_out_sum(rz_part, nb_rz, c) : 0.0;
+    if (lane != 0) continue;
     double rz_old = s.rz[par * R + c];
     double b = 0.0;
     double rzn = rz_old;
     int on_next = on;
     if (on) {
-      rzn = rz_part ? col_sum(rz_part, nb_rz, R, c) : s.rr[c];
+      rzn = rz_part ? rzs : s.rr[c];
       if (!(rzn >= 0.0) || !isfinite(rzn)) {
         if (blockIdx.x == 0) s.flags[1] = 1;
       }
@@ -217,6 +213,59 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
   }
 }
 
+// True residual r = b - y (y = K~ x from the FP64-storage operator): stored into Rr
+// for the columns flagged in `verify`, partials of |r|^2 (output-major).
+template <typename T>
+__global__ void k_true_resid(const T* __restrict__ B, int ldb, const double* __restrict__ Y, T* __restrict__ Rr,
+                             int N, int R, const int* __restrict__ verify, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int e0 = blockIdx.x * kVecChunk;
+  for (int c = 0; c < R; ++c) {
+    double acc = 0.0;
+    const bool ver = verify[c] != 0;
+    for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x) {
+      double r = (double)B[(size_t)c * ldb + e] - Y[(size_t)c * N + e];
+      if (ver) Rr[(size_t)c * N + e] = (T)r;
+      acc += r * r;
+    }
+    acc = wave_sum64(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(size_t)c * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+// Restart of the columns in `restart`: rz from the new M^{-1} r, active again.
+__global__ void k_pcg_restart_scal(const double* __restrict__ rr_part, int nb_r, const double* __restrict__ rz_part,
+                                   int nb_z, int R, const int* __restrict__ restart, PcgScal s) {
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wv; c < R; c += nw) {
+    double rr = wave_out_sum(rr_part, nb_r, c);
+    double rz = rz_part ? wave_out_sum(rz_part, nb_z, c) : rr;
+    if ((threadIdx.x & 63) != 0) continue;
+    s.rr[c] = rr;
+    if (restart[c]) {
+      s.rz[c] = rz;
+      s.rz[R + c] = rz;
+      s.active[c] = 1;
+      s.active[R + c] = 1;
+      atomicAdd(&s.flags[0], 1);
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_copy_cols_masked(const T* __restrict__ a, T* __restrict__ b, int N, int R,
+                                   const int* __restrict__ mask) {
+  const int e0 = blockIdx.x * kVecChunk;
+  for (int c = 0; c < R; ++c) {
+    if (!mask[c]) continue;
+    for (int e = e0 + threadIdx.x; e < min(N, e0 + kVecChunk); e += blockDim.x)
+      b[(size_t)c * N + e] = a[(size_t)c * N + e];
+  }
+}
+
 template <typename T>
 __global__ void k_copy_cols(const T* __restrict__ a, T* __restrict__ b, int N, int R) {
   const int e0 = blockIdx.x * kVecChunk;
@@ -237,7 +286,8 @@ __global__ void k_x_out(const double* __restrict__ Xd, int N, int R, TO* __restr
 template <typename T>
 static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
                              const double* tol_host, int max_iter, int fixed_iters, double* hist,
-                             PcgResult& res, int res_c0, hipStream_t st, double* X64, int ldx64) {
+                             PcgResult& res, int res_c0, hipStream_t st, double* X64, int ldx64,
+                             const int* verify_mask) {
   const int N = p->N, n = p->n;
   const int k = pc ? pc->k : 0;
   const size_t nr = (size_t)N * R;
@@ -287,7 +337,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
     Zuse = Z;
   }
   k_copy_cols<T><<<nbv, kBlock, 0, st>>>(Zuse, P, N, R);
-  k_pcg_init_scal<<<1, 64, 0, st>>>(rr_part, nbv, rzp, nbz, R, fixed_iters, s, rz0);
+  k_pcg_init_scal<<<1, 256, 0, st>>>(rr_part, nbv, rzp, nbz, R, fixed_iters, s, rz0);
   DSKI_HIP(hipGetLastError());
   int* hflags = nullptr;
   DSKI_HIP(hipHostMalloc(&hflags, sizeof(int) * 2, hipHostMallocDefault));
@@ -295,56 +345,105 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   const double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
   dski_status rc = DSKI_OK;
   const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
-  int it = 0, check = 1;
-  while (it < limit) {
-    int burst = std::min(check, limit - it);
-    for (int b = 0; b < burst; ++b) {
-      const int par = (it + b) & 1;
-      rc = mvm_tiled<T>(p, R, P, N, Q, N, pq_part, st);
-      if (rc < 0) break;
-      k_pcg_update<T><<<nbt, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U, k,
-                                                     isf, isg, L.RT, L, t_part, hist, max_iter);
-      RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
-      if (pc && k > 0) {
-        RedJob jt{t_part, nbt, k * R, R, t1, pc->c, nullptr, 1.0, coef, nullptr};
-        rc = launch_reduce(jt, &jr, st);
-        if (rc < 0) break;
-        k_ts_proj<T><<<nbt, kBlock, L.bytes, st>>>(Rr, N, N, n, R, isf, isg, U, k, coef, L.RT, L, t_part);
-        RedJob j2{t_part, nbt, k * R, R, t2, pc->c, t1, 1.0, coef, nullptr};
-        rc = launch_reduce(j2, nullptr, st);
-        if (rc < 0) break;
-        k_ts_final<T><<<nbz, kBlock, sizeof(double) * k * R, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, k,
-                                                                   coef, Z, N, rz_part);
-      } else {
-        rc = launch_reduce(jr, nullptr, st);
-        if (rc < 0) break;
-        if (pc)  // rank-0 preconditioner: M = D
-          k_ts_final<T><<<nbz, kBlock, 0, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N,
-                                               rz_part);
+  int it = 0;
+  auto run = [&]() -> dski_status {
+    int check = 1;
+    while (it < limit) {
+      int burst = std::min(check, limit - it);
+      for (int b = 0; b < burst; ++b) {
+        const int par = (it + b) & 1;
+        DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, st));
+        k_pcg_update<T><<<nbt, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U,
+                                                       k, isf, isg, L.RT, L, t_part, hist, max_iter);
+        RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
+        if (pc && k > 0) {
+          RedJob jt{t_part, nbt, k * R, R, t1, pc->c, nullptr, 1.0, coef, nullptr};
+          DSKI_TRY(launch_reduce(jt, &jr, st));
+          k_ts_proj<T><<<nbt, kBlock, L.bytes, st>>>(Rr, N, N, n, R, isf, isg, U, k, coef, L.RT, L, t_part);
+          RedJob j2{t_part, nbt, k * R, R, t2, pc->c, t1, 1.0, coef, nullptr};
+          DSKI_TRY(launch_reduce(j2, nullptr, st));
+          k_ts_final<T><<<nbz, kBlock, 0, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part);
+        } else {
+          DSKI_TRY(launch_reduce(jr, nullptr, st));
+          if (pc)  // rank-0 preconditioner: M = D
+            k_ts_final<T><<<nbz, kBlock, 0, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N,
+                                                 rz_part);
+        }
+        k_pcg_beta<T><<<nbv, kBlock, 0, st>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist,
+                                              max_iter, fixed_iters);
       }
-      k_pcg_beta<T><<<nbv, kBlock, 0, st>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist,
-                                            max_iter, fixed_iters);
+      it += burst;
+      DSKI_HIP(hipGetLastError());
+      DSKI_HIP(hipMemcpyAsync(hflags, s.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+      DSKI_HIP(hipStreamSynchronize(st));
+      if (hflags[1]) {
+        set_error("PCG breakdown: p^T K p <= 0 or r^T M^{-1} r < 0");
+        return DSKI_EBREAKDOWN;
+      }
+      if (hflags[0] <= 0) break;
+      check = std::min(check * 2, 32);
     }
-    if (rc < 0) break;
-    it += burst;
-    if (hipGetLastError() != hipSuccess) {
-      set_error("PCG kernel launch failed");
-      rc = DSKI_EHIP;
-      break;
+    return DSKI_OK;
+  };
+  rc = run();
+  // True-residual verification: columns that met the tolerance on the recurrence
+  // residual are checked with b - K~ x (FP64 iterate, FP64-storage operator) and
+  // resumed from x if still above it (at most 3 rounds).
+  std::vector<int> ver(R, 0);
+  bool any_ver = false;
+  for (int r = 0; r < R; ++r) {
+    ver[r] = verify_mask ? verify_mask[r] : 0;
+    any_ver = any_ver || ver[r];
+  }
+  std::vector<double> true_rr;
+  if (rc == DSKI_OK && fixed_iters <= 0 && any_ver) {
+    DevBuf ybuf;
+    int* dmask = nullptr;
+    for (int round = 0; round < 3 && rc == DSKI_OK; ++round) {
+      if (ybuf.reserve(sizeof(double) * nr + sizeof(int) * 2 * (size_t)R + 64) < 0) {
+        rc = DSKI_ENOMEM;
+        break;
+      }
+      double* Y = ybuf.as<double>();
+      dmask = reinterpret_cast<int*>(Y + nr);
+      int* drestart = dmask + R;
+      rc = mvm_tiled<double>(p, R, Xd, N, Y, N, nullptr, st);
+      if (rc < 0) break;
+      DSKI_HIP(hipMemcpyAsync(dmask, ver.data(), sizeof(int) * R, hipMemcpyHostToDevice, st));
+      k_true_resid<T><<<nbv, kBlock, 0, st>>>(B, ldb, Y, Rr, N, R, dmask, rr_part);
+      std::vector<double> hrt(R), hbb(R);
+      RedJob jq{rr_part, nbv, R, R, t2, nullptr, nullptr, 0.0, nullptr, nullptr};
+      DSKI_TRY(launch_reduce(jq, nullptr, st));
+      DSKI_HIP(hipMemcpyAsync(hrt.data(), t2, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+      DSKI_HIP(hipMemcpyAsync(hbb.data(), s.bb, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+      DSKI_HIP(hipStreamSynchronize(st));
+      true_rr = hrt;
+      std::vector<int> restart(R, 0);
+      int nre = 0;
+      for (int r = 0; r < R; ++r) {
+        if (ver[r] && hrt[r] > tol2[r] * hbb[r] * (1.0 + 1e-12)) {
+          restart[r] = 1;
+          ++nre;
+        }
+      }
+      if (nre == 0 || it >= limit) break;
+      DSKI_HIP(hipMemcpyAsync(drestart, restart.data(), sizeof(int) * R, hipMemcpyHostToDevice, st));
+      // r (true, already in Rr for verified columns), z = M^{-1} r, p = z for the restarted columns
+      const double* rzp2 = nullptr;
+      const T* Zuse2 = Rr;
+      if (pc) {
+        rc = precond_apply_tiled<T>(pc, R, Rr, N, Z, N, rz_part, nullptr, st);
+        if (rc < 0) break;
+        rzp2 = rz_part;
+        Zuse2 = Z;
+      }
+      k_copy_cols_masked<T><<<nbv, kBlock, 0, st>>>(Zuse2, P, N, R, drestart);
+      DSKI_HIP(hipMemsetAsync(s.flags, 0, sizeof(int) * 2, st));
+      k_pcg_restart_scal<<<1, 256, 0, st>>>(rr_part, nbv, rzp2, nbz, R, drestart, s);
+      DSKI_HIP(hipGetLastError());
+      rc = run();
     }
-    if (hipMemcpyAsync(hflags, s.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-      set_error("PCG synchronisation failed");
-      rc = DSKI_EHIP;
-      break;
-    }
-    if (hflags[1]) {
-      set_error("PCG breakdown: p^T K p <= 0 or r^T M^{-1} r < 0");
-      rc = DSKI_EBREAKDOWN;
-      break;
-    }
-    if (hflags[0] <= 0) break;
-    check = std::min(check * 2, 32);
+    ybuf.release();
   }
   (void)hipHostFree(hflags);
   if (rc < 0 && rc != DSKI_EBREAKDOWN) return rc;
@@ -362,7 +461,8 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   for (int r = 0; r < R; ++r) {
     res.iters[res_c0 + r] = hit[r];
     res.rz0[res_c0 + r] = hrz0[r];
-    res.relres[res_c0 + r] = hbb[r] > 0 ? std::sqrt(std::max(hrr[r], 0.0) / hbb[r]) : 0.0;
+    double rr = (!true_rr.empty() && ver[r]) ? true_rr[r] : hrr[r];
+    res.relres[res_c0 + r] = hbb[r] > 0 ? std::sqrt(std::max(rr, 0.0) / hbb[r]) : 0.0;
     if (fixed_iters <= 0 && tol_host && res.relres[res_c0 + r] > tol_host[r]) notconv = true;
   }
   if (rc == DSKI_EBREAKDOWN) {
@@ -375,7 +475,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
 template <typename T>
 dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
                       const double* tol_host, int max_iter, int fixed_iters, double* alpha_beta,
-                      PcgResult& res, hipStream_t st, double* X64) {
+                      PcgResult& res, hipStream_t st, double* X64, const int* verify_mask) {
   res.iters.assign(R, 0);
   res.relres.assign(R, 0.0);
   res.rz0.assign(R, 0.0);
@@ -389,17 +489,19 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, 
     int rg = std::min(kPcgMaxR, R - c0);
     dski_status rc = pcg_group<T>(p, pc, rg, B + (size_t)c0 * ldb, ldb, X ? X + (size_t)c0 * ldx : nullptr, ldx,
                                   tol_host + c0, max_iter, fixed_iters, alpha_beta, res, c0, st,
-                                  X64 ? X64 + (size_t)c0 * ldx : nullptr, ldx);
+                                  X64 ? X64 + (size_t)c0 * ldx : nullptr, ldx,
+                                  verify_mask ? verify_mask + c0 : nullptr);
     if (rc < 0) return rc;
     if (rc > worst) worst = rc;
   }
   return worst;
 }
 template dski_status pcg_tiled<float>(dski_plan, dski_precond, int, const float*, int, float*, int,
-                                      const double*, int, int, double*, PcgResult&, hipStream_t, double*);
+                                      const double*, int, int, double*, PcgResult&, hipStream_t, double*,
+                                      const int*);
 template dski_status pcg_tiled<double>(dski_plan, dski_precond, int, const double*, int, double*, int,
                                        const double*, int, int, double*, PcgResult&, hipStream_t,
-                                       double*);
+                                       double*, const int*);
 
 }  // namespace dski
 
@@ -422,8 +524,10 @@ static dski_status pcg_user(dski_plan p, dski_precond pc, int R, const T* B, int
   double* Xt = reinterpret_cast<double*>(p->vout.as<char>() + ((sizeof(T) * nr + 63) / 64) * 64);
   DSKI_TRY(permute(p, +1, R, B, ldb, Bt, p->N, st));
   PcgResult res;
-  dski_status rc =
-      pcg_tiled<T>(p, pc, R, Bt, p->N, nullptr, p->N, tol_host, max_iter, 0, alpha_beta, res, st, Xt);
+  // without a CG-coefficient history every column gets the true-residual check
+  std::vector<int> verify(R, alpha_beta ? 0 : 1);
+  dski_status rc = pcg_tiled<T>(p, pc, R, Bt, p->N, nullptr, p->N, tol_host, max_iter, 0, alpha_beta, res, st,
+                                Xt, verify.data());
   if (rc < 0 && rc != DSKI_EBREAKDOWN) return rc;
   DSKI_TRY(permute(p, -1, R, Xt, p->N, X, ldx, st));
   DSKI_HIP(hipStreamSynchronize(st));

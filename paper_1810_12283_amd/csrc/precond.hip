@@ -370,7 +370,7 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
   RedJob j2{w.partial, w.nblk, k * R, R, w.t2, pc->c, w.t1, 1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j2, nullptr, st));
   // Z = D^{-1/2} (r' - U coef2)
-  k_ts_final<T><<<vec_blocks(N), kBlock, sizeof(double) * k * R, st>>>(Rm, ld, N, p->n, R, isf, isg, isf, isg,
+  k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(Rm, ld, N, p->n, R, isf, isg, isf, isg,
                                                                       U, k, w.coef, Z, ldz, rz_partial);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
@@ -407,7 +407,7 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
   DSKI_HIP(hipGetLastError());
   RedJob j1{w.partial, w.nblk, k * R, R, w.t1, pc->rootc, nullptr, -1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j1, nullptr, st));
-  k_ts_final<T><<<vec_blocks(N), kBlock, sizeof(double) * k * R, st>>>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg,
+  k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg,
                                                                       U, k, w.coef, Z, ldz, nullptr);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;

@@ -188,7 +188,9 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
     if (rc < 0) break;
     std::vector<double> tols(R, tol);
     PcgResult res;
-    rc = pcg_tiled<T>(p, pc, R, B, N, X, N, tols.data(), max_iter, 0, ab, res, st);
+    std::vector<int> verify(R, 0);
+    verify[0] = 1;  // the data solve alpha; probe columns keep a single Krylov run for SLQ
+    rc = pcg_tiled<T>(p, pc, R, B, N, X, N, tols.data(), max_iter, 0, ab, res, st, nullptr, verify.data());
     if (rc < 0) break;
     dski_status pcg_rc = rc;
     // v_i = M^{-1} z_i

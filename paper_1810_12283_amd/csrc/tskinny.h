@@ -7,6 +7,8 @@
 
 namespace dski {
 
+constexpr int kFinalMaxR = 32;  // columns per tall-skinny launch
+
 template <typename T>
 inline const T* u_of(dski_precond pc);
 template <>
@@ -15,7 +17,7 @@ template <>
 inline const double* u_of<double>(dski_precond pc) { return pc->Ud; }
 
 // LDS plan of a projection tile: U tile (RT x (k+1), T), v tile (RT x R, FP64),
-// coefficients (k x R, FP64), two row-split partial sums (2 x k x R, FP64).
+// two row-split partial sums (2 x k x R, FP64).
 struct ProjLds {
   int RT = 128;
   size_t oU = 0, ox = 0, ocoef = 0, ored = 0, bytes = 0;
@@ -28,7 +30,7 @@ inline ProjLds proj_lds(int k, int R, size_t tsize) {
     L.oU = 0;
     L.ox = u;
     L.ocoef = L.ox + sizeof(double) * (size_t)L.RT * R;
-    L.ored = L.ocoef + sizeof(double) * (size_t)k * R;
+    L.ored = L.ocoef;
     L.bytes = L.ored + sizeof(double) * 2 * (size_t)k * R;
     if (L.bytes <= 61440) break;
   }
@@ -49,7 +51,7 @@ __device__ __forceinline__ void tile_load_u(const T* __restrict__ U, int N, int 
 template <typename T>
 __device__ __forceinline__ void tile_proj(const T* __restrict__ sU, const double* __restrict__ sx,
                                           int rn, int RT, int k, int R, double* __restrict__ sred,
-                                          double* __restrict__ out) {
+                                          double* __restrict__ partial) {
   const int ni = (k + 1) / 2, nc = (R + 3) / 4;
   const int ntask = ni * nc * 2;
   const int half = RT / 2;
@@ -78,14 +80,31 @@ __device__ __forceinline__ void tile_proj(const T* __restrict__ sU, const double
         if (i0 + a < k && c0 + j < R) sred[((size_t)rs * k + i0 + a) * R + c0 + j] = acc[a][j];
   }
   __syncthreads();
-  for (int f = threadIdx.x; f < k * R; f += blockDim.x) out[f] = sred[f] + sred[(size_t)k * R + f];
+  // output-major partials: partial[f * blocks + block]
+  for (int f = threadIdx.x; f < k * R; f += blockDim.x)
+    partial[(size_t)f * gridDim.x + blockIdx.x] = sred[f] + sred[(size_t)k * R + f];
 }
 
-// Fixed-order reduction of per-tile partials (nblk x nout) in up to two jobs (blockIdx.y):
-//   out[o] = sum_b partial[b, o];  optional t_out = out, and
+__device__ __forceinline__ double wave_sum64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Fixed-order sum of the nblk partials of one output (output-major layout),
+// by one wavefront: lane l adds blocks l, l + 64, ..., then a shuffle tree.
+__device__ __forceinline__ double wave_out_sum(const double* __restrict__ part, int nblk, int o) {
+  const int lane = threadIdx.x & 63;
+  double a = 0.0;
+  const double* p = part + (size_t)o * nblk;
+  for (int b = lane; b < nblk; b += 64) a += p[b];
+  return wave_sum64(a);
+}
+
+// Reduction of per-tile partials in up to two jobs (blockIdx.y), one wavefront
+// per output:  out[o] = sum_b partial[o, b];  optional t_out = out, and
 //   coef[o] = sgn * c[o / R] * (out[o] + t_prev[o]).
 struct RedJob {
-  const double* partial;
+  const double* partial;   // output-major: nout x nblk
   int nblk, nout, R;
   double* out;             // may be NULL
   const double* c;         // may be NULL (no coefficients)
@@ -97,16 +116,10 @@ struct RedJob {
 
 static __global__ void k_ts_reduce(RedJob j0, RedJob j1) {
   const RedJob& J = blockIdx.y == 0 ? j0 : j1;
-  __shared__ double red[4][64];
-  int o = blockIdx.x * 64 + (threadIdx.x & 63);
-  int q = threadIdx.x >> 6;
-  double a = 0.0;
-  if (o < J.nout)
-    for (int b = q; b < J.nblk; b += 4) a += J.partial[(size_t)b * J.nout + o];
-  red[q][threadIdx.x & 63] = a;
-  __syncthreads();
-  if (q == 0 && o < J.nout) {
-    double t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  int o = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (o >= J.nout) return;
+  double t = wave_out_sum(J.partial, J.nblk, o);
+  if ((threadIdx.x & 63) == 0) {
     bool write = !J.mask || J.mask[o % J.R];
     if (J.out && write) J.out[o] = t;
     if (J.coef) J.coef[o] = J.sgn * J.c[o / J.R] * (t + (J.t_prev ? J.t_prev[o] : 0.0));
@@ -115,26 +128,23 @@ static __global__ void k_ts_reduce(RedJob j0, RedJob j1) {
 
 static inline dski_status launch_reduce(const RedJob& a, const RedJob* b, hipStream_t st) {
   int nout = std::max(a.nout, b ? b->nout : 0);
-  dim3 grid((nout + 63) / 64, b ? 2 : 1);
+  dim3 grid((nout + 3) / 4, b ? 2 : 1);
   RedJob bb = b ? *b : a;
   k_ts_reduce<<<grid, 256, 0, st>>>(a, bb);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
 
-constexpr int kFinalMaxR = 32;
-
-// z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]); per-block partials of X.z
+// z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]); per-block partials
+// of X.z stored output-major (dot_partial[c * blocks + block]).  coef[i, c] is the
+// same for all threads (scalar loads).
 template <typename T>
 static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X, int ld, int N, int n, int R,
-                                                  double pre_v, double pre_g, double post_v, double post_g,
-                                                  const T* __restrict__ U, int k,
-                                                  const double* __restrict__ coef, T* __restrict__ Z, int ldz,
-                                                  double* __restrict__ dot_partial) {
-  extern __shared__ __align__(16) char smem[];
-  double* sco = reinterpret_cast<double*>(smem);  // k x R
-  for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
-  __syncthreads();
+                                                         double pre_v, double pre_g, double post_v, double post_g,
+                                                         const T* __restrict__ U, int k,
+                                                         const double* __restrict__ coef, T* __restrict__ Z,
+                                                         int ldz, double* __restrict__ dot_partial) {
+  __shared__ double red[4][kFinalMaxR];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   double acc[kFinalMaxR];
 #pragma unroll
@@ -142,14 +152,13 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
   if (e < N) {
     for (int i = 0; i < k; ++i) {
       double u = (double)U[(size_t)i * N + e];
-      const double* cr = sco + i * R;
+      const double* cr = coef + i * R;
 #pragma unroll
       for (int c = 0; c < kFinalMaxR; ++c)
         if (c < R) acc[c] += u * cr[c];
     }
   }
   const double pre = e < n ? pre_v : pre_g, post = e < n ? post_v : post_g;
-  __shared__ double red[4];
 #pragma unroll
   for (int c = 0; c < kFinalMaxR; ++c) {
     if (c < R) {
@@ -160,13 +169,21 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
         Z[(size_t)c * ldz + e] = z;
         dot = x * (double)z;
       }
-      if (dot_partial) {
-        for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
-        __syncthreads();
-        if (threadIdx.x == 0) dot_partial[(size_t)blockIdx.x * R + c] = red[0] + red[1] + red[2] + red[3];
-        __syncthreads();
+      acc[c] = dot;
+    }
+  }
+  if (dot_partial) {
+#pragma unroll
+    for (int c = 0; c < kFinalMaxR; ++c) {
+      if (c < R) {
+        double v = wave_sum64(acc[c]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
       }
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+      int c = threadIdx.x;
+      dot_partial[(size_t)c * gridDim.x + blockIdx.x] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
     }
   }
 }
@@ -180,7 +197,6 @@ static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X,
   extern __shared__ __align__(16) char smem[];
   T* sU = reinterpret_cast<T*>(smem + L.oU);
   double* sx = reinterpret_cast<double*>(smem + L.ox);
-  double* sco = reinterpret_cast<double*>(smem + L.ocoef);
   double* sred = reinterpret_cast<double*>(smem + L.ored);
   const int e0 = blockIdx.x * RT;
   const int rn = min(RT, N - e0);
@@ -190,29 +206,28 @@ static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X,
     int e = e0 + r;
     sx[r * R + c] = r < rn ? (e < n ? pre_v : pre_g) * (double)X[(size_t)c * ld + e] : 0.0;
   }
-  if (coef)
-    for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
   __syncthreads();
   if (coef) {
-    // sx[r, c] -= sum_i sU[r, i] coef[i, c]   (tasks: one row x 4 columns)
-    const int nc = (R + 3) / 4;
-    for (int task = threadIdx.x; task < rn * nc; task += blockDim.x) {
-      int r = task % rn, c0 = (task / rn) * 4;
-      double acc[4] = {0, 0, 0, 0};
+    // sx[r, c] -= sum_i sU[r, i] coef[i, c]: one thread per row, all columns in
+    // registers; coef[i, c] is the same for every thread (scalar loads)
+    for (int r = threadIdx.x; r < rn; r += blockDim.x) {
+      double acc[kFinalMaxR];
+#pragma unroll
+      for (int c = 0; c < kFinalMaxR; ++c) acc[c] = 0.0;
       const T* ur = sU + r * (k + 1);
       for (int i = 0; i < k; ++i) {
         double u = (double)ur[i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (c0 + j < R) acc[j] += u * sco[i * R + c0 + j];
+        for (int c = 0; c < kFinalMaxR; ++c)
+          if (c < R) acc[c] += u * coef[i * R + c];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (c0 + j < R) sx[r * R + c0 + j] -= acc[j];
+      for (int c = 0; c < kFinalMaxR; ++c)
+        if (c < R) sx[r * R + c] -= acc[c];
     }
     __syncthreads();
   }
-  tile_proj<T>(sU, sx, rn, RT, k, R, sred, partial + (size_t)blockIdx.x * k * R);
+  tile_proj<T>(sU, sx, rn, RT, k, R, sred, partial);
 }
 
 }  // namespace dski
