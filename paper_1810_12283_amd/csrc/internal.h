@@ -71,6 +71,7 @@ struct dski_plan_s {
   int* perm = nullptr;         // tile position -> user index
   int* cell = nullptr;         // linear cell id per tile position
   double* toff = nullptr;      // d x n offsets in [0, 1] (SoA, FP64)
+  double* wts = nullptr;       // d x 8 x n: Keys weights w_0..w_3 and dw_0..dw_3 / h per axis (FP64)
   int* cell_start = nullptr;   // ncells + 1
   // workspaces
   dski::DevBuf grid;           // FP64 grid buffer, M * Rmax

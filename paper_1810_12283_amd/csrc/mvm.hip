@@ -1,6 +1,9 @@
 // The D-SKI matrix-vector product (Sec. 3.1):
 //     Y = [W; dW_1..dW_d] K_UU [W; dW_1..dW_d]^T V + D V
 // in three stages over tile-ordered vectors:
+// The Keys cubic-convolution weights of every point are precomputed at plan
+// set-up (FP64); both stages read the same table, so the operator is exactly
+// symmetric.
 //   scatter  G = S^T V      owner-computes: one thread per grid node pulls the
 //                           contributions of the points whose 4^d stencil covers
 //                           it, in a fixed order (no atomics, bitwise
@@ -15,40 +18,6 @@
 #include "internal.h"
 
 namespace dski {
-
-// Keys cubic convolution (a = -1/2) weights of the stencil nodes i-1..i+2 for
-// offset t in [0, 1], and their derivatives with respect to t (divide by h for x).
-__device__ __forceinline__ void keys_weights(double t, double w[4], double dw[4]) {
-  double t2 = t * t, t3 = t2 * t;
-  w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
-  w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-  w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-  w[3] = 0.5 * (t3 - t2);
-  dw[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0);
-  dw[1] = 0.5 * (9.0 * t2 - 10.0 * t);
-  dw[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0);
-  dw[3] = 0.5 * (3.0 * t2 - 2.0 * t);
-}
-
-__device__ __forceinline__ double keys_w1(int o, double t) {
-  double t2 = t * t, t3 = t2 * t;
-  switch (o) {
-    case 0: return 0.5 * (-t3 + 2.0 * t2 - t);
-    case 1: return 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-    case 2: return 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-    default: return 0.5 * (t3 - t2);
-  }
-}
-
-__device__ __forceinline__ double keys_dw1(int o, double t) {
-  double t2 = t * t;
-  switch (o) {
-    case 0: return 0.5 * (-3.0 * t2 + 4.0 * t - 1.0);
-    case 1: return 0.5 * (9.0 * t2 - 10.0 * t);
-    case 2: return 0.5 * (-9.0 * t2 + 8.0 * t + 1.0);
-    default: return 0.5 * (3.0 * t2 - 2.0 * t);
-  }
-}
 
 struct GeoK {
   int m[DSKI_MAXD];
@@ -90,12 +59,12 @@ struct TileShape {
 
 template <int D, int CR, typename T, int PMAX>
 __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cell,
-                                                     const double* __restrict__ toff,
+                                                     const double* __restrict__ wts,
                                                      const int* __restrict__ cstart, int n, GeoK g,
-                                                     const T* __restrict__ V, int ldv, int R,
+                                                     const T* __restrict__ V, int ldv, int R, int cr,
                                                      double* __restrict__ G, long long M) {
   using TS = TileShape<D>;
-  __shared__ double s_t[D][PMAX];
+  __shared__ double s_w[D * 8][PMAX];
   __shared__ T s_v[PMAX * CR * (D + 1)];
   __shared__ int s_lcs[TS::max_cells + 1];
   __shared__ int s_rcnt[TS::max_rows];
@@ -133,8 +102,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     ncells_r *= span[a];
     if (a < last) nrows *= span[a];
   }
-  const int r0 = blockIdx.y * CR;
-  const int rc = min(CR, R - r0);
+  const int r0 = blockIdx.y * cr;
+  const int rc = min(cr, R - r0);
   // per-row global ranges (rows = all region axes but the last; cells of a row are contiguous)
   for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
     int rem = row, base = 0, mul = 1;
@@ -188,9 +157,9 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   __syncthreads();
   if (lds_ok) {
     // all loads of the region in flat loops (no per-row serialisation)
-    for (int f = threadIdx.x; f < total * D; f += blockDim.x) {
-      int q = f % total, a = f / total;
-      s_t[a][q] = toff[(size_t)a * n + s_qk[q]];
+    for (int f = threadIdx.x; f < total * D * 8; f += blockDim.x) {
+      int q = f % total, j = f / total;
+      s_w[j][q] = wts[(size_t)j * n + s_qk[q]];
     }
     const int tot = total * rc * (D + 1);
     for (int f = threadIdx.x; f < tot; f += blockDim.x) {
@@ -242,9 +211,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
           for (int a = 0; a < D; ++a) {
             int ca = (a == last) ? cl : c[a];
             int o = j[a] - ca + 1;
-            double t = s_t[a][q];
-            wv[a] = keys_w1(o, t);
-            wd[a] = keys_dw1(o, t) * g.invh[a];
+            wv[a] = s_w[a * 8 + o][q];
+            wd[a] = s_w[a * 8 + 4 + o][q];
           }
           double wprod = 1.0;
 #pragma unroll
@@ -283,9 +251,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
         for (int a = 0; a < D; ++a) {
           int ca = (a == last) ? clast : c[a];
           int o = j[a] - ca + 1;
-          double t = toff[(size_t)a * n + k];
-          wv[a] = keys_w1(o, t);
-          wd[a] = keys_dw1(o, t) * g.invh[a];
+          wv[a] = wts[(size_t)(a * 8 + o) * n + k];
+          wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
         }
         double wprod = 1.0;
 #pragma unroll
@@ -325,10 +292,13 @@ static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, h
   using TS = TileShape<D>;
   long long tiles = 1;
   for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
-  constexpr int CR = sizeof(T) == 4 ? 4 : 2;
-  dim3 grid((unsigned)tiles, (R + CR - 1) / CR);
-  k_scatter_lds<D, CR, T, 512><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv,
-                                                      R, G, p->M);
+  // columns per work-group: at most CR, chunks balanced (17 columns -> 5 x {4,4,3,3,3})
+  constexpr int CR = (sizeof(T) == 4 && D <= 2) ? 4 : (D <= 2 ? 2 : (sizeof(T) == 4 ? 2 : 1));
+  const int nch = (R + CR - 1) / CR;
+  const int cr = (R + nch - 1) / nch;
+  dim3 grid((unsigned)tiles, nch);
+  k_scatter_lds<D, CR, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv,
+                                                      R, cr, G, p->M);
 }
 
 template <typename T>
@@ -466,7 +436,7 @@ __device__ __forceinline__ void fft_inplace(double2* buf, int L, const double2* 
 // circulant eigenvalues `spec` (already scaled by 1/L) and transformed back; two
 // lines share one complex FFT (real and imaginary parts), which is exact because
 // the spectrum is real and even.  TPP = L/8 threads per line pair, 256/TPP pairs
-// per work-group, 32 KiB of LDS.
+// per work-group, 32 KiB of LDS plus the twiddle table.
 __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long long nlines, int m,
                                                   int L, long long inner,
                                                   const double2* __restrict__ tw,
@@ -478,6 +448,8 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   const int lane = threadIdx.x % tpp;
   const long long line0 = (long long)blockIdx.x * (2 * ppb);
   const long long linestride = (long long)m * inner;
+  double2* stw = smem + (size_t)ppb * L;  // twiddle table staged in LDS
+  for (int f = threadIdx.x; f < L; f += 256) stw[f] = tw[f];
   for (int f = threadIdx.x; f < ppb * L; f += 256) smem[f] = make_double2(0.0, 0.0);
   __syncthreads();
   const int nl = 2 * ppb;
@@ -502,10 +474,10 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   }
   __syncthreads();
   double2* buf = smem + (size_t)pr * L;
-  fft_inplace(buf, L, tw, lane, tpp, +1);
+  fft_inplace(buf, L, stw, lane, tpp, +1);
   for (int kk = lane; kk < L; kk += tpp) buf[kk] = cscale(buf[kk], spec[kk]);
   __syncthreads();
-  fft_inplace(buf, L, tw, lane, tpp, -1);
+  fft_inplace(buf, L, stw, lane, tpp, -1);
   if (inner > 1) {
     for (int f = threadIdx.x; f < nl * m; f += 256) {
       int l = f % nl, jj = f / nl;
@@ -540,7 +512,7 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
       return DSKI_ENOTSUP;
     }
     int ppb = 256 / (L / 8);
-    size_t sh = sizeof(double2) * (size_t)ppb * L;
+    size_t sh = sizeof(double2) * ((size_t)ppb * L + L);
     long long blocks = (nlines + 2 * ppb - 1) / (2 * ppb);
     k_toeplitz<<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
     DSKI_HIP(hipGetLastError());
@@ -555,7 +527,7 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
 // stored output-major: pq_partial[column * blocks + block].
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
-                                                const double* __restrict__ toff, int n, GeoK g,
+                                                const double* __restrict__ wts, int n, GeoK g,
                                                 const double* __restrict__ G, long long M,
                                                 const T* __restrict__ V, int ldv,
                                                 T* __restrict__ Y, int ldy, int R, double nv,
@@ -573,11 +545,12 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
       rem /= g.nc[a];
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      keys_weights(toff[(size_t)a * n + k], w[a], dw[a]);
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int o = 0; o < 4; ++o) dw[a][o] *= g.invh[a];
-    }
+      for (int o = 0; o < 4; ++o) {
+        w[a][o] = wts[(size_t)(a * 8 + o) * n + k];
+        dw[a][o] = wts[(size_t)(a * 8 + 4 + o) * n + k];
+      }
     long long base = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) base = base * g.m[a] + (c[a] - 1);
@@ -658,7 +631,7 @@ template <int D, typename T>
 static void launch_gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
                           double nv, double ng, double* pq_partial, hipStream_t st) {
   GeoK g = geo_of(p);
-  k_gather<D, T><<<dim3(gather_blocks(p), R), 256, 0, st>>>(p->cell, p->toff, p->n, g, G, p->M, V, ldv, Y,
+  k_gather<D, T><<<dim3(gather_blocks(p), R), 256, 0, st>>>(p->cell, p->wts, p->n, g, G, p->M, V, ldv, Y,
                                                             ldy, R, nv, ng, pq_partial);
 }
 

@@ -162,54 +162,50 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
   tile_proj<T>(sU, sx, rn, RT, k, R, sred, t_part);
 }
 
-// beta, history, convergence test (block 0 writes the next parity), p = z + beta p.
+// beta, history, convergence test, p = z + beta p.  Grid (row chunks of 256, R):
+// every block recomputes its column's beta from the r.z partials (same order);
+// block (0, c) writes the column's next-parity state.
 template <typename T>
 __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, int R, PcgScal s, int par,
                            const double* __restrict__ rz_part, int nb_rz, double* __restrict__ hist,
                            int max_iter, int fixed_iters) {
-  __shared__ double s_beta[kPcgMaxR];
-  __shared__ int s_act[kPcgMaxR];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int c = wv; c < R; c += 4) {  // one wavefront per column
-    int on = s.active[par * R + c];
-    double rzs = (on && rz_part) ? wave_out_sum(rz_part, nb_rz, c) : 0.0;
-    if (lane != 0) continue;
-    double rz_old = s.rz[par * R + c];
-    double b = 0.0;
-    double rzn = rz_old;
-    int on_next = on;
-    if (on) {
-      rzn = rz_part ? rzs : s.rr[c];
+  __shared__ double s_beta;
+  __shared__ int s_on;
+  const int c = blockIdx.y;
+  const int on = s.active[par * R + c];
+  if (!on) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      s.rz[(1 - par) * R + c] = s.rz[par * R + c];
+      s.active[(1 - par) * R + c] = 0;
+    }
+    return;
+  }
+  if (threadIdx.x < 64) {
+    double rzs = rz_part ? wave_out_sum(rz_part, nb_rz, c) : 0.0;
+    if (threadIdx.x == 0) {
+      double rz_old = s.rz[par * R + c];
+      double rzn = rz_part ? rzs : s.rr[c];
       if (!(rzn >= 0.0) || !isfinite(rzn)) {
         if (blockIdx.x == 0) s.flags[1] = 1;
       }
-      b = rz_old > 0.0 ? rzn / rz_old : 0.0;
-      int it = s.iters[c];
-      bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (s.rr[c] <= s.tol2[c] * s.bb[c]);
-      on_next = done ? 0 : 1;
+      double b = rz_old > 0.0 ? rzn / rz_old : 0.0;
       if (blockIdx.x == 0) {
+        int it = s.iters[c];
+        bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (s.rr[c] <= s.tol2[c] * s.bb[c]);
         if (hist && it < max_iter) hist[(size_t)R * max_iter + (size_t)c * max_iter + it] = b;
         s.iters[c] = it + 1;
         if (done) atomicSub(&s.flags[0], 1);
+        s.rz[(1 - par) * R + c] = rzn;
+        s.active[(1 - par) * R + c] = done ? 0 : 1;
       }
+      s_beta = b;
     }
-    if (blockIdx.x == 0) {
-      s.rz[(1 - par) * R + c] = rzn;
-      s.active[(1 - par) * R + c] = on_next;
-    }
-    s_beta[c] = b;
-    s_act[c] = on;
   }
   __syncthreads();
-  const int e0 = blockIdx.x * kVecChunk;
-  const int e1 = min(N, e0 + kVecChunk);
-  for (int c = 0; c < R; ++c) {
-    if (!s_act[c]) continue;
-    double b = s_beta[c];
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      size_t i = (size_t)c * N + e;
-      P[i] = (T)((double)Z[i] + b * (double)P[i]);
-    }
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < N) {
+    size_t i = (size_t)c * N + e;
+    P[i] = (T)((double)Z[i] + s_beta * (double)P[i]);
   }
 }
 
@@ -362,15 +358,15 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
           k_ts_proj<T><<<nbt, kBlock, L.bytes, st>>>(Rr, N, N, n, R, isf, isg, U, k, coef, L.RT, L, t_part);
           RedJob j2{t_part, nbt, k * R, R, t2, pc->c, t1, 1.0, coef, nullptr};
           DSKI_TRY(launch_reduce(j2, nullptr, st));
-          k_ts_final<T><<<nbz, kBlock, 0, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part);
+          launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part, st);
         } else {
           DSKI_TRY(launch_reduce(jr, nullptr, st));
           if (pc)  // rank-0 preconditioner: M = D
-            k_ts_final<T><<<nbz, kBlock, 0, st>>>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N,
-                                                 rz_part);
+            launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N,
+                                                 rz_part, st);
         }
-        k_pcg_beta<T><<<nbv, kBlock, 0, st>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist,
-                                              max_iter, fixed_iters);
+        k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, st>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr,
+                                                       nbz, hist, max_iter, fixed_iters);
       }
       it += burst;
       DSKI_HIP(hipGetLastError());

@@ -135,6 +135,29 @@ __global__ void k_gather_points(const int* __restrict__ perm, int n, int d,
   for (int p = 0; p < d; ++p) toff[(size_t)p * n + k] = t_u[(size_t)p * n + u];
 }
 
+// Interpolation weights of every point, computed once per plan (they depend only
+// on the point offsets): for axis a, Keys cubic convolution (a = -1/2) weights
+// w_0..w_3 of the stencil nodes i-1..i+2 at offset t, and their derivatives
+// dw_0..dw_3 with respect to x (d/dt divided by h).  Layout wts[(a * 8 + j) * n + k].
+__global__ void k_weights(const double* __restrict__ toff, int n, int d, const double* __restrict__ invh,
+                          double* __restrict__ wts) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  for (int a = 0; a < d; ++a) {
+    double t = toff[(size_t)a * n + k];
+    double t2 = t * t, t3 = t2 * t, ih = invh[a];
+    double* w = wts + (size_t)a * 8 * n + k;
+    w[0 * (size_t)n] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1 * (size_t)n] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2 * (size_t)n] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3 * (size_t)n] = 0.5 * (t3 - t2);
+    w[4 * (size_t)n] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0) * ih;
+    w[5 * (size_t)n] = 0.5 * (9.0 * t2 - 10.0 * t) * ih;
+    w[6 * (size_t)n] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0) * ih;
+    w[7 * (size_t)n] = 0.5 * (3.0 * t2 - 2.0 * t) * ih;
+  }
+}
+
 // Forward twiddles e^{-2 pi i t / L} stored as (cos, -sin) pairs.
 __global__ void k_twiddle(int L, double* __restrict__ tw) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -294,6 +317,7 @@ dski_status dski_plan_destroy(dski_plan p) {
   (void)hipFree(p->perm);
   (void)hipFree(p->cell);
   (void)hipFree(p->toff);
+  (void)hipFree(p->wts);
   (void)hipFree(p->cell_start);
   for (int a = 0; a < p->d; ++a) {
     (void)hipFree(p->ax[a].twiddle);
@@ -373,6 +397,7 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
   DSKI_HIP(hipMalloc(&p->perm, sizeof(int) * (size_t)std::max(n, 1)));
   DSKI_HIP(hipMalloc(&p->cell, sizeof(int) * (size_t)std::max(n, 1)));
   DSKI_HIP(hipMalloc(&p->toff, sizeof(double) * (size_t)std::max(n, 1) * d));
+  DSKI_HIP(hipMalloc(&p->wts, sizeof(double) * (size_t)std::max(n, 1) * d * 8));
   DSKI_HIP(hipMalloc(&p->cell_start, sizeof(int) * (size_t)(nc + 1)));
   for (int a = 0; a < d; ++a) {
     Axis& A = p->ax[a];
@@ -387,7 +412,7 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
   int *cell_u = nullptr, *counts = nullptr, *err = nullptr;
   double* t_u = nullptr;
   size_t tmp_bytes = sizeof(double) * (size_t)std::max(n, 1) * d + sizeof(int) * (size_t)std::max(n, 1) +
-                     sizeof(int) * (size_t)(2 * nc + 2) + 64;
+                     sizeof(int) * (size_t)(2 * nc + 2) + 128;
   char* tmp = nullptr;
   DSKI_HIP(hipMalloc(&tmp, tmp_bytes));
   t_u = reinterpret_cast<double*>(tmp);
@@ -412,6 +437,18 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
       k_sort_cells<<<(int)((nc + kBlock - 1) / kBlock), kBlock, 0, st>>>(p->cell_start, (int)nc, p->perm);
       k_gather_points<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(p->perm, n, d, cell_u, t_u, p->cell,
                                                                    p->toff);
+    }
+    if (n > 0) {
+      double invh[DSKI_MAXD];
+      for (int a = 0; a < d; ++a) invh[a] = 1.0 / p->ax[a].h;
+      double* dinvh = reinterpret_cast<double*>(err + 2);  // scratch after the error flag (aligned)
+      dinvh = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(dinvh) + 7) & ~uintptr_t(7));
+      if (hipMemcpyAsync(dinvh, invh, sizeof(double) * d, hipMemcpyHostToDevice, st) != hipSuccess) {
+        set_error("set-up copy failed");
+        rc = DSKI_EHIP;
+        break;
+      }
+      k_weights<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(p->toff, n, d, dinvh, p->wts);
     }
     if (hipGetLastError() != hipSuccess) {
       set_error("set-up kernel launch failed");

@@ -350,8 +350,8 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
   }
   const T* U = u_of<T>(pc);
   if (k == 0) {
-    k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(Rm, ld, N, p->n, R, isf, isg, isf, isg, U, 0, nullptr, Z,
-                                                   ldz, rz_partial);
+    launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, U, 0, nullptr, Z,
+                                                   ldz, rz_partial, st);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   }
@@ -370,8 +370,8 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
   RedJob j2{w.partial, w.nblk, k * R, R, w.t2, pc->c, w.t1, 1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j2, nullptr, st));
   // Z = D^{-1/2} (r' - U coef2)
-  k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(Rm, ld, N, p->n, R, isf, isg, isf, isg,
-                                                                      U, k, w.coef, Z, ldz, rz_partial);
+  launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg,
+                                                                      U, k, w.coef, Z, ldz, rz_partial, st);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
@@ -395,8 +395,8 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
   }
   const T* U = u_of<T>(pc);
   if (k == 0) {
-    k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, U, 0, nullptr,
-                                                   Z, ldz, nullptr);
+    launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, U, 0, nullptr,
+                                                   Z, ldz, nullptr, st);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   }
@@ -407,8 +407,8 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
   DSKI_HIP(hipGetLastError());
   RedJob j1{w.partial, w.nblk, k * R, R, w.t1, pc->rootc, nullptr, -1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j1, nullptr, st));
-  k_ts_final<T><<<vec_blocks(N), kBlock, 0, st>>>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg,
-                                                                      U, k, w.coef, Z, ldz, nullptr);
+  launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg,
+                                                                      U, k, w.coef, Z, ldz, nullptr, st);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }

@@ -17,7 +17,8 @@ template <>
 inline const double* u_of<double>(dski_precond pc) { return pc->Ud; }
 
 // LDS plan of a projection tile: U tile (RT x (k+1), T), v tile (RT x R, FP64),
-// two row-split partial sums (2 x k x R, FP64).
+// coefficients (k x R, FP64), two row-split partial sums (2 x k x R, FP64); at
+// most 48 KiB so that several work-groups share a CU.
 struct ProjLds {
   int RT = 128;
   size_t oU = 0, ox = 0, ocoef = 0, ored = 0, bytes = 0;
@@ -30,9 +31,9 @@ inline ProjLds proj_lds(int k, int R, size_t tsize) {
     L.oU = 0;
     L.ox = u;
     L.ocoef = L.ox + sizeof(double) * (size_t)L.RT * R;
-    L.ored = L.ocoef;
+    L.ored = L.ocoef + sizeof(double) * (size_t)k * R;
     L.bytes = L.ored + sizeof(double) * 2 * (size_t)k * R;
-    if (L.bytes <= 61440) break;
+    if (L.bytes <= 49152) break;
   }
   return L;
 }
@@ -135,38 +136,57 @@ static inline dski_status launch_reduce(const RedJob& a, const RedJob* b, hipStr
   return DSKI_OK;
 }
 
-// z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]); per-block partials
-// of X.z stored output-major (dot_partial[c * blocks + block]).  coef[i, c] is the
-// same for all threads (scalar loads).
+// z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]) for a group of
+// `cg` columns per blockIdx.y (one thread per row, the group's columns in
+// registers, U loads issued 8 at a time); per-block partials of X.z stored
+// output-major (dot_partial[c * blocks + block]).  coef[i, c] is the same for all
+// threads of a group (scalar loads).
+constexpr int kFinalGroup = 8;
+
 template <typename T>
 static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X, int ld, int N, int n, int R,
                                                          double pre_v, double pre_g, double post_v, double post_g,
                                                          const T* __restrict__ U, int k,
                                                          const double* __restrict__ coef, T* __restrict__ Z,
-                                                         int ldz, double* __restrict__ dot_partial) {
-  __shared__ double red[4][kFinalMaxR];
+                                                         int ldz, double* __restrict__ dot_partial, int cgs) {
+  __shared__ double red[4][kFinalGroup];
+  const int c0 = blockIdx.y * cgs;
+  const int cg = min(cgs, R - c0);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc[kFinalMaxR];
+  double acc[kFinalGroup];
 #pragma unroll
-  for (int c = 0; c < kFinalMaxR; ++c) acc[c] = 0.0;
+  for (int c = 0; c < kFinalGroup; ++c) acc[c] = 0.0;
   if (e < N) {
-    for (int i = 0; i < k; ++i) {
-      double u = (double)U[(size_t)i * N + e];
-      const double* cr = coef + i * R;
+    int i = 0;
+    for (; i + 8 <= k; i += 8) {
+      double u[8];
 #pragma unroll
-      for (int c = 0; c < kFinalMaxR; ++c)
-        if (c < R) acc[c] += u * cr[c];
+      for (int j = 0; j < 8; ++j) u[j] = (double)U[(size_t)(i + j) * N + e];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double* cr = coef + (i + j) * R + c0;
+#pragma unroll
+        for (int c = 0; c < kFinalGroup; ++c)
+          if (c < cg) acc[c] += u[j] * cr[c];
+      }
+    }
+    for (; i < k; ++i) {
+      double u = (double)U[(size_t)i * N + e];
+      const double* cr = coef + i * R + c0;
+#pragma unroll
+      for (int c = 0; c < kFinalGroup; ++c)
+        if (c < cg) acc[c] += u * cr[c];
     }
   }
   const double pre = e < n ? pre_v : pre_g, post = e < n ? post_v : post_g;
 #pragma unroll
-  for (int c = 0; c < kFinalMaxR; ++c) {
-    if (c < R) {
+  for (int c = 0; c < kFinalGroup; ++c) {
+    if (c < cg) {
       double dot = 0.0;
       if (e < N) {
-        double x = (double)X[(size_t)c * ld + e];
+        double x = (double)X[(size_t)(c0 + c) * ld + e];
         T z = (T)(post * (pre * x - acc[c]));
-        Z[(size_t)c * ldz + e] = z;
+        Z[(size_t)(c0 + c) * ldz + e] = z;
         dot = x * (double)z;
       }
       acc[c] = dot;
@@ -174,18 +194,30 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
   }
   if (dot_partial) {
 #pragma unroll
-    for (int c = 0; c < kFinalMaxR; ++c) {
-      if (c < R) {
+    for (int c = 0; c < kFinalGroup; ++c) {
+      if (c < cg) {
         double v = wave_sum64(acc[c]);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
       }
     }
     __syncthreads();
-    if (threadIdx.x < R) {
+    if (threadIdx.x < cg) {
       int c = threadIdx.x;
-      dot_partial[(size_t)c * gridDim.x + blockIdx.x] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+      dot_partial[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
     }
   }
+}
+
+// launch helper: balanced column groups of at most kFinalGroup columns
+template <typename T>
+static inline void launch_final(const T* X, int ld, int N, int n, int R, double pre_v, double pre_g,
+                                double post_v, double post_g, const T* U, int k, const double* coef, T* Z,
+                                int ldz, double* dot_partial, hipStream_t st) {
+  const int ng = (R + kFinalGroup - 1) / kFinalGroup;
+  const int cgs = (R + ng - 1) / ng;
+  dim3 grid((N + 255) / 256, ng);
+  k_ts_final<T><<<grid, 256, 0, st>>>(X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
+                                      dot_partial, cgs);
 }
 
 // partial t over a row tile of  v = pre .* X - U coef  (coef may be NULL)
@@ -206,24 +238,33 @@ static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X,
     int e = e0 + r;
     sx[r * R + c] = r < rn ? (e < n ? pre_v : pre_g) * (double)X[(size_t)c * ld + e] : 0.0;
   }
+  if (coef) {
+    double* sco = reinterpret_cast<double*>(smem + L.ocoef);
+    for (int f = threadIdx.x; f < k * R; f += blockDim.x) sco[f] = coef[f];
+  }
   __syncthreads();
   if (coef) {
-    // sx[r, c] -= sum_i sU[r, i] coef[i, c]: one thread per row, all columns in
-    // registers; coef[i, c] is the same for every thread (scalar loads)
-    for (int r = threadIdx.x; r < rn; r += blockDim.x) {
-      double acc[kFinalMaxR];
+    // sx[r, c] -= sum_i sU[r, i] coef[i, c]: 4 threads per row, each a quarter of
+    // the columns in registers; U and coef read from LDS
+    double* sco = reinterpret_cast<double*>(smem + L.ocoef);
+    const int cq = (R + 3) / 4;
+    for (int task = threadIdx.x; task < rn * 4; task += blockDim.x) {
+      const int r = task >> 2, c0 = (task & 3) * cq;
+      const int cn = min(cq, R - c0);
+      double acc[kFinalMaxR / 4];
 #pragma unroll
-      for (int c = 0; c < kFinalMaxR; ++c) acc[c] = 0.0;
+      for (int c = 0; c < kFinalMaxR / 4; ++c) acc[c] = 0.0;
       const T* ur = sU + r * (k + 1);
       for (int i = 0; i < k; ++i) {
         double u = (double)ur[i];
+        const double* cr = sco + i * R + c0;
 #pragma unroll
-        for (int c = 0; c < kFinalMaxR; ++c)
-          if (c < R) acc[c] += u * coef[i * R + c];
+        for (int c = 0; c < kFinalMaxR / 4; ++c)
+          if (c < cn) acc[c] += u * cr[c];
       }
 #pragma unroll
-      for (int c = 0; c < kFinalMaxR; ++c)
-        if (c < R) sx[r * R + c] -= acc[c];
+      for (int c = 0; c < kFinalMaxR / 4; ++c)
+        if (c < cn) sx[r * R + c0 + c] -= acc[c];
     }
     __syncthreads();
   }
