@@ -132,6 +132,18 @@ dski_status dski_mvm_tiled_f64(dski_plan plan, int R, const double* V, int ldv, 
 dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int ldv, float* Y,
                            int ldy, dski_stream stream);
 
+/* Times the interchangeable kernel variants for R right-hand sides and
+ * preconditioner rank k on this plan's shape (scatter: LDS node tiles / direct
+ * one column per thread / direct two columns per thread; preconditioner
+ * projections: LDS row tiles / wavefront shuffles) and keeps the fastest of
+ * each.  All variants give bitwise-identical scatters and equal projections up
+ * to summation order.  times_host (5 entries, may be NULL) receives the
+ * measured microseconds in that order.  1 <= R <= 32, 0 <= k <= 256. */
+dski_status dski_autotune(dski_plan plan, int R, int k, double* times_host, dski_stream stream);
+
+/* Select the variants directly (scatter 0..2, projection 0..1). */
+dski_status dski_set_variants(dski_plan plan, int scatter_variant, int proj_variant);
+
 /* Storage precision (32 or 64 bits) of the N-vectors that slq_logdet creates
  * internally (probes, Krylov vectors).  Default 32. */
 dski_status dski_plan_set_precision(dski_plan plan, int bits);

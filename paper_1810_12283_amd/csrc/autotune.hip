@@ -1,0 +1,118 @@
+// Per-shape autotuning of kernel variants.  The scatter (W^T) and the
+// preconditioner projections (U^T v) each have an LDS-tiled and a cache-direct
+// form with identical results; which is faster depends on the grid size, the
+// number of points per cell, the rank and the number of right-hand sides.  The
+// tuner times each candidate with HIP events on the caller's stream and keeps
+// the fastest in the plan.
+#include <cmath>
+
+#include "internal.h"
+#include "tskinny.h"
+
+namespace dski {
+
+__global__ void k_fill_pm1(float* __restrict__ out, size_t len, uint64_t seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[i] = (z >> 63) ? -0.5f : 0.5f;
+  }
+}
+
+template <class F>
+static dski_status time_us(F&& fn, int reps, hipStream_t st, double* us) {
+  hipEvent_t a, b;
+  DSKI_HIP(hipEventCreate(&a));
+  DSKI_HIP(hipEventCreate(&b));
+  dski_status rc = fn();  // warm-up
+  if (rc < 0) return rc;
+  DSKI_HIP(hipEventRecord(a, st));
+  for (int i = 0; i < reps; ++i) {
+    rc = fn();
+    if (rc < 0) return rc;
+  }
+  DSKI_HIP(hipEventRecord(b, st));
+  DSKI_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  DSKI_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *us = 1e3 * ms / reps;
+  return DSKI_OK;
+}
+
+}  // namespace dski
+
+using namespace dski;
+
+extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_host, dski_stream stream) {
+  if (!p || R <= 0 || R > 32 || k < 0 || k > 256) {
+    set_error("dski_autotune: bad arguments (1 <= R <= 32, 0 <= k <= 256)");
+    return DSKI_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int N = p->N;
+  const int reps = 10;
+  DevBuf buf;
+  size_t nv = (size_t)N * R, nu = (size_t)N * std::max(k, 1);
+  DSKI_TRY(buf.reserve(sizeof(float) * (nv + nu) + sizeof(double) * (2 * (size_t)std::max(k, 1) * R +
+                                                                      (size_t)std::max(k, 1) * R *
+                                                                          ((N + 7) / 8 + 1)) + 1024));
+  float* V = buf.as<float>();
+  float* U = V + nv;
+  double* coef = reinterpret_cast<double*>(buf.as<char>() + ((sizeof(float) * (nv + nu) + 63) / 64) * 64);
+  double* part = coef + (size_t)std::max(k, 1) * R;
+  k_fill_pm1<<<1024, 256, 0, st>>>(V, nv + nu, 12345);
+  DSKI_HIP(hipMemsetAsync(coef, 0, sizeof(double) * (size_t)std::max(k, 1) * R, st));
+  DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
+  double* G = p->grid.as<double>();
+  double t[5] = {0, 0, 0, 0, 0};
+  // scatter variants
+  int best_s = 0;
+  for (int v = 0; v < 3; ++v) {
+    p->scatter_variant = v;
+    DSKI_TRY(time_us([&]() { return scatter<float>(p, R, V, N, G, st); }, reps, st, &t[v]));
+    if (t[v] < t[best_s]) best_s = v;
+  }
+  p->scatter_variant = best_s;
+  // projection variants (with the correction term, as in the PCG)
+  int best_p = 0;
+  if (k > 0) {
+    ProjLds L = proj_lds(k, R, sizeof(float));
+    const int nblk = (N + L.RT - 1) / L.RT;
+    DSKI_TRY(time_us(
+        [&]() -> dski_status {
+          k_ts_proj<float><<<nblk, kBlock, L.bytes, st>>>(V, N, N, p->n, R, 1.0, 1.0, U, k, coef, L.RT, L, part);
+          DSKI_HIP(hipGetLastError());
+          return DSKI_OK;
+        },
+        reps, st, &t[3]));
+    DSKI_TRY(time_us(
+        [&]() -> dski_status {
+          int nb = 0;
+          launch_proj_shfl<float>(V, N, N, p->n, R, 1.0, 1.0, U, k, coef, part, &nb, st);
+          DSKI_HIP(hipGetLastError());
+          return DSKI_OK;
+        },
+        reps, st, &t[4]));
+    best_p = t[4] < t[3] ? 1 : 0;
+  }
+  p->proj_variant = best_p;
+  DSKI_HIP(hipStreamSynchronize(st));
+  buf.release();
+  if (times_host)
+    for (int i = 0; i < 5; ++i) times_host[i] = t[i];
+  return DSKI_OK;
+}
+
+extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant, int proj_variant) {
+  if (!p || scatter_variant < 0 || scatter_variant > 2 || proj_variant < 0 || proj_variant > 1) {
+    set_error("dski_set_variants: bad arguments");
+    return DSKI_EINVAL;
+  }
+  p->scatter_variant = scatter_variant;
+  p->proj_variant = proj_variant;
+  return DSKI_OK;
+}

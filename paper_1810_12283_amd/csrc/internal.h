@@ -79,6 +79,9 @@ struct dski_plan_s {
   dski::DevBuf partial;        // FP64 block partials
   dski::DevBuf scal;           // FP64 small scalars
   int precision = 32;          // storage of N-vectors inside slq_logdet (32 or 64)
+  // kernel variants chosen by dski_autotune (defaults: the LDS-tiled kernels)
+  int scatter_variant = 0;     // 0 LDS node tiles, 1 direct 1 column/thread, 2 direct 2 columns/thread
+  int proj_variant = 0;        // 0 LDS row tiles, 1 wavefront-shuffle row blocks
 };
 
 struct dski_precond_s {

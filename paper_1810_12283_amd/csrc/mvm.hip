@@ -301,13 +301,119 @@ static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, h
                                                       R, cr, G, p->M);
 }
 
+// Direct variant: one thread per (grid node, CRD columns), no LDS; cell ranges,
+// weights and column values are read through the caches (neighbouring nodes share
+// points).  Same summation order as the tiled kernel, hence the same result.
+template <int D, int CRD, typename T>
+__global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ cell,
+                                                        const double* __restrict__ wts,
+                                                        const int* __restrict__ cstart, int n, GeoK g,
+                                                        const T* __restrict__ V, int ldv, int R,
+                                                        double* __restrict__ G, long long M) {
+  const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= M) return;
+  const int r0 = blockIdx.y * CRD;
+  const int rc = min(CRD, R - r0);
+  const int last = D - 1;
+  int j[D];
+  {
+    long long rem = node;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+      j[a] = (int)(rem % g.m[a]);
+      rem /= g.m[a];
+    }
+  }
+  int lo[D], hi[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = max(1, j[a] - 2);
+    hi[a] = min(g.nc[a], j[a] + 1);
+  }
+  int outer_cnt = 1;
+#pragma unroll
+  for (int a = 0; a < last; ++a) outer_cnt *= hi[a] - lo[a] + 1;
+  double acc[CRD];
+#pragma unroll
+  for (int r = 0; r < CRD; ++r) acc[r] = 0.0;
+  for (int oc = 0; oc < outer_cnt; ++oc) {
+    int c[D];
+    int rem = oc, base = 0;
+#pragma unroll
+    for (int a = last - 1; a >= 0; --a) {
+      int sp = hi[a] - lo[a] + 1;
+      c[a] = lo[a] + rem % sp;
+      rem /= sp;
+    }
+#pragma unroll
+    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+    base *= g.nc[last];
+    // the cells lo..hi of the last axis are one contiguous run of points; the
+    // stencil position on the last axis changes at each cell boundary
+    for (int cl = lo[last]; cl <= hi[last]; ++cl) {
+      const int kb = cstart[base + cl - 1], ke = cstart[base + cl];
+      for (int k = kb; k < ke; ++k) {
+        double wv[D], wd[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          int ca = (a == last) ? cl : c[a];
+          int o = j[a] - ca + 1;
+          wv[a] = wts[(size_t)(a * 8 + o) * n + k];
+          wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
+        }
+        double wprod = 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) wprod *= wv[a];
+        double dprod[D];
+#pragma unroll
+        for (int qq = 0; qq < D; ++qq) {
+          double v = 1.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
+          dprod[qq] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < CRD; ++r) {
+          if (r < rc) {
+            const T* vv = V + (size_t)(r0 + r) * ldv + k;
+            double a = wprod * (double)vv[0];
+#pragma unroll
+            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)vv[(size_t)(qq + 1) * n];
+            acc[r] += a;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < CRD; ++r)
+    if (r < rc) G[(size_t)(r0 + r) * M + node] = acc[r];
+}
+
+template <int D, int CRD, typename T>
+static void launch_scatter_direct(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
+  GeoK g = geo_of(p);
+  dim3 grid((unsigned)((p->M + 255) / 256), (R + CRD - 1) / CRD);
+  k_scatter_direct<D, CRD, T><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv, R, G, p->M);
+}
+
+template <int D, typename T>
+static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
+  if (p->scatter_variant == 1)
+    launch_scatter_direct<D, 1, T>(p, R, V, ldv, G, st);
+  else if (p->scatter_variant == 2)
+    launch_scatter_direct<D, 2, T>(p, R, V, ldv, G, st);
+  else
+    launch_scatter<D, T>(p, R, V, ldv, G, st);
+}
+
 template <typename T>
 dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
   if (R <= 0) return DSKI_OK;
   switch (p->d) {
-    case 1: launch_scatter<1, T>(p, R, V, ldv, G, st); break;
-    case 2: launch_scatter<2, T>(p, R, V, ldv, G, st); break;
-    case 3: launch_scatter<3, T>(p, R, V, ldv, G, st); break;
+    case 1: scatter_dispatch<1, T>(p, R, V, ldv, G, st); break;
+    case 2: scatter_dispatch<2, T>(p, R, V, ldv, G, st); break;
+    case 3: scatter_dispatch<3, T>(p, R, V, ldv, G, st); break;
     default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
   }
   DSKI_HIP(hipGetLastError());

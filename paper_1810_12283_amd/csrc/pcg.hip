@@ -162,6 +162,85 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
   tile_proj<T>(sU, sx, rn, RT, k, R, sred, t_part);
 }
 
+// Wavefront-shuffle variant of the update: grid (row blocks of 256, column
+// groups of cgs); one thread per row for its group's columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update_shfl(const T* __restrict__ P, const T* __restrict__ Q,
+                                                         T* __restrict__ Rr, double* __restrict__ Xd, int N, int n,
+                                                         int R, PcgScal s, int par,
+                                                         const double* __restrict__ pq_part, int nb_pq,
+                                                         double* __restrict__ rr_part, const T* __restrict__ U,
+                                                         int k, double isf, double isg, int cgs,
+                                                         double* __restrict__ t_part, double* __restrict__ hist,
+                                                         int max_iter) {
+  __shared__ double red[4][kShflChunk][kShflGroup];
+  __shared__ double s_alpha[kShflGroup];
+  __shared__ int s_act[kShflGroup];
+  const int c0 = blockIdx.y * cgs;
+  const int cg = min(cgs, R - c0);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wv < cg) {  // one wavefront per column of the group
+    const int c = c0 + wv;
+    int on = s.active[par * R + c];
+    double pq = on ? wave_out_sum(pq_part, nb_pq, c) : 0.0;
+    if (lane == 0) {
+      double a = 0.0;
+      if (on) {
+        if (!(pq > 0.0) || !isfinite(pq)) {
+          if (blockIdx.x == 0) s.flags[1] = 1;
+        } else {
+          a = s.rz[par * R + c] / pq;
+        }
+        if (blockIdx.x == 0 && hist && s.iters[c] < max_iter) hist[(size_t)c * max_iter + s.iters[c]] = a;
+      }
+      if (blockIdx.x == 0) s.alpha[c] = a;
+      s_alpha[wv] = a;
+      s_act[wv] = on;
+    }
+  }
+  __syncthreads();
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[kShflGroup];
+#pragma unroll
+  for (int c = 0; c < kShflGroup; ++c) v[c] = 0.0;
+  if (e < N) {
+#pragma unroll
+    for (int c = 0; c < kShflGroup; ++c) {
+      if (c < cg) {
+        size_t i = (size_t)(c0 + c) * N + e;
+        double rv = (double)Rr[i];
+        if (s_act[c]) {
+          double a = s_alpha[c];
+          Xd[i] += a * (double)P[i];
+          T rnew = (T)(rv - a * (double)Q[i]);
+          Rr[i] = rnew;
+          rv = (double)rnew;
+        }
+        v[c] = rv;
+      }
+    }
+  }
+  // partials of r.r
+#pragma unroll
+  for (int c = 0; c < kShflGroup; ++c) {
+    if (c < cg) {
+      double sm = wave_sum64(v[c] * v[c]);
+      if (lane == 0) red[wv][0][c] = sm;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < cg) {
+    int c = threadIdx.x;
+    rr_part[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = red[0][0][c] + red[1][0][c] + red[2][0][c] + red[3][0][c];
+  }
+  __syncthreads();
+  if (k == 0) return;
+  const double pre = e < n ? isf : isg;
+#pragma unroll
+  for (int c = 0; c < kShflGroup; ++c) v[c] *= pre;
+  shfl_project<T>(U, N, e, k, R, c0, cg, v, red, t_part);
+}
+
 // beta, history, convergence test, p = z + beta p.  Grid (row chunks of 256, R):
 // every block recomputes its column's beta from the r.z partials (same order);
 // block (0, c) writes the column's next-parity state.
@@ -289,7 +368,10 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   const size_t nr = (size_t)N * R;
   const int nbv = nchunks(N), nbg = gather_blocks(p), nbz = vec_blocks(N);
   ProjLds L = proj_lds(k, R, sizeof(T));
-  const int nbt = (N + L.RT - 1) / L.RT;
+  const bool shfl = p->proj_variant == 1;
+  const int ngs = (R + kShflGroup - 1) / kShflGroup;
+  const int cgs = (R + ngs - 1) / ngs;
+  const int nbt = shfl ? (N + 255) / 256 : (N + L.RT - 1) / L.RT;
   const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, nbt)) * R;
   const size_t ntp = (size_t)nbt * std::max(k, 1) * R;
   // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, t2, coef, scalars
@@ -349,13 +431,23 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
       for (int b = 0; b < burst; ++b) {
         const int par = (it + b) & 1;
         DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, st));
-        k_pcg_update<T><<<nbt, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U,
-                                                       k, isf, isg, L.RT, L, t_part, hist, max_iter);
+        if (shfl)
+          k_pcg_update_shfl<T><<<dim3(nbt, ngs), kBlock, 0, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg,
+                                                                  rr_part, U, k, isf, isg, cgs, t_part, hist,
+                                                                  max_iter);
+        else
+          k_pcg_update<T><<<nbt, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U,
+                                                         k, isf, isg, L.RT, L, t_part, hist, max_iter);
         RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
         if (pc && k > 0) {
           RedJob jt{t_part, nbt, k * R, R, t1, pc->c, nullptr, 1.0, coef, nullptr};
           DSKI_TRY(launch_reduce(jt, &jr, st));
-          k_ts_proj<T><<<nbt, kBlock, L.bytes, st>>>(Rr, N, N, n, R, isf, isg, U, k, coef, L.RT, L, t_part);
+          if (shfl) {
+            int nbx = 0;
+            launch_proj_shfl<T>(Rr, N, N, n, R, isf, isg, U, k, coef, t_part, &nbx, st);
+          } else {
+            k_ts_proj<T><<<nbt, kBlock, L.bytes, st>>>(Rr, N, N, n, R, isf, isg, U, k, coef, L.RT, L, t_part);
+          }
           RedJob j2{t_part, nbt, k * R, R, t2, pc->c, t1, 1.0, coef, nullptr};
           DSKI_TRY(launch_reduce(j2, nullptr, st));
           launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part, st);

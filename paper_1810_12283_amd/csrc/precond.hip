@@ -313,7 +313,7 @@ static dski_status pc_work(dski_precond pc, int R, PcWork& w) {
   int k = pc->k;
   w.L = proj_lds(k, R, sizeof(T));
   w.nblk = (p->N + w.L.RT - 1) / w.L.RT;
-  size_t np = std::max((size_t)w.nblk * k * R, (size_t)vec_blocks(p->N) * R);
+  size_t np = std::max((size_t)std::max(w.nblk, vec_blocks(p->N)) * k * R, (size_t)vec_blocks(p->N) * R);
   DSKI_TRY(pc->work.reserve(sizeof(double) * (np + 3 * (size_t)k * R + 64)));
   double* base = pc->work.as<double>();
   w.partial = base;
@@ -357,21 +357,27 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
   }
   PcWork w;
   DSKI_TRY(pc_work<T>(pc, R, w));
+  int nb = w.nblk;
   // t1 = U^T r',  r' = D^{-1/2} Rm;  coef1 = c .* t1
-  k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, nullptr, w.L.RT, w.L,
-                                                  w.partial);
+  if (p->proj_variant == 1)
+    launch_proj_shfl<T>(Rm, ld, N, p->n, R, isf, isg, U, k, nullptr, w.partial, &nb, st);
+  else
+    k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, nullptr, w.L.RT, w.L,
+                                                    w.partial);
   DSKI_HIP(hipGetLastError());
-  RedJob j1{w.partial, w.nblk, k * R, R, w.t1, pc->c, nullptr, 1.0, w.coef, nullptr};
+  RedJob j1{w.partial, nb, k * R, R, w.t1, pc->c, nullptr, 1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j1, nullptr, st));
   // t2 = U^T (r' - U coef1);  coef2 = c .* (t1 + t2)
-  k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, w.coef, w.L.RT, w.L,
-                                                  w.partial);
+  if (p->proj_variant == 1)
+    launch_proj_shfl<T>(Rm, ld, N, p->n, R, isf, isg, U, k, w.coef, w.partial, &nb, st);
+  else
+    k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, w.coef, w.L.RT, w.L,
+                                                    w.partial);
   DSKI_HIP(hipGetLastError());
-  RedJob j2{w.partial, w.nblk, k * R, R, w.t2, pc->c, w.t1, 1.0, w.coef, nullptr};
+  RedJob j2{w.partial, nb, k * R, R, w.t2, pc->c, w.t1, 1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j2, nullptr, st));
   // Z = D^{-1/2} (r' - U coef2)
-  launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg,
-                                                                      U, k, w.coef, Z, ldz, rz_partial, st);
+  launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, U, k, w.coef, Z, ldz, rz_partial, st);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
@@ -402,13 +408,16 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
   }
   PcWork w;
   DSKI_TRY(pc_work<T>(pc, R, w));
-  k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(W, ld, N, p->n, R, 1.0, 1.0, U, k, nullptr, w.L.RT, w.L,
-                                                  w.partial);
+  int nb = w.nblk;
+  if (p->proj_variant == 1)
+    launch_proj_shfl<T>(W, ld, N, p->n, R, 1.0, 1.0, U, k, nullptr, w.partial, &nb, st);
+  else
+    k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(W, ld, N, p->n, R, 1.0, 1.0, U, k, nullptr, w.L.RT, w.L,
+                                                    w.partial);
   DSKI_HIP(hipGetLastError());
-  RedJob j1{w.partial, w.nblk, k * R, R, w.t1, pc->rootc, nullptr, -1.0, w.coef, nullptr};
+  RedJob j1{w.partial, nb, k * R, R, w.t1, pc->rootc, nullptr, -1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j1, nullptr, st));
-  launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg,
-                                                                      U, k, w.coef, Z, ldz, nullptr, st);
+  launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, U, k, w.coef, Z, ldz, nullptr, st);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }

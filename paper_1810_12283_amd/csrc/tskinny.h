@@ -271,4 +271,81 @@ static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X,
   tile_proj<T>(sU, sx, rn, RT, k, R, sred, partial);
 }
 
+// Wavefront-shuffle variant of the projection: grid (row blocks of 256, column
+// groups of `cgs`); each thread owns one row and its group's columns,
+//   v = pre .* X - U coef   (coef may be NULL),
+// and every output (i, c) is a wavefront shuffle-tree sum over the block's rows,
+// combined over the 4 wavefronts in a fixed order.  No LDS tiles, many blocks.
+constexpr int kShflGroup = 4;
+constexpr int kShflChunk = 32;
+
+template <typename T>
+__device__ __forceinline__ void shfl_project(const T* __restrict__ U, int N, int e, int k, int R, int c0,
+                                             int cg, const double v[kShflGroup],
+                                             double (*red)[kShflChunk][kShflGroup],
+                                             double* __restrict__ partial) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i0 = 0; i0 < k; i0 += kShflChunk) {
+    const int ni = min(kShflChunk, k - i0);
+    for (int ii = 0; ii < ni; ++ii) {
+      double u = e < N ? (double)U[(size_t)(i0 + ii) * N + e] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kShflGroup; ++c) {
+        if (c < cg) {
+          double sm = wave_sum64(u * v[c]);
+          if (lane == 0) red[wv][ii][c] = sm;
+        }
+      }
+    }
+    __syncthreads();
+    for (int f = threadIdx.x; f < ni * cg; f += blockDim.x) {
+      int ii = f / cg, c = f % cg;
+      double t = red[0][ii][c] + red[1][ii][c] + red[2][ii][c] + red[3][ii][c];
+      partial[((size_t)(i0 + ii) * R + c0 + c) * gridDim.x + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+static __global__ __launch_bounds__(256) void k_ts_proj_shfl(const T* __restrict__ X, int ld, int N, int n, int R,
+                                                             double pre_v, double pre_g, const T* __restrict__ U,
+                                                             int k, const double* __restrict__ coef, int cgs,
+                                                             double* __restrict__ partial) {
+  __shared__ double red[4][kShflChunk][kShflGroup];
+  const int c0 = blockIdx.y * cgs;
+  const int cg = min(cgs, R - c0);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[kShflGroup];
+#pragma unroll
+  for (int c = 0; c < kShflGroup; ++c) v[c] = 0.0;
+  if (e < N) {
+    const double pre = e < n ? pre_v : pre_g;
+#pragma unroll
+    for (int c = 0; c < kShflGroup; ++c)
+      if (c < cg) v[c] = pre * (double)X[(size_t)(c0 + c) * ld + e];
+    if (coef) {
+      for (int i = 0; i < k; ++i) {
+        double u = (double)U[(size_t)i * N + e];
+        const double* cr = coef + i * R + c0;
+#pragma unroll
+        for (int c = 0; c < kShflGroup; ++c)
+          if (c < cg) v[c] -= u * cr[c];
+      }
+    }
+  }
+  shfl_project<T>(U, N, e, k, R, c0, cg, v, red, partial);
+}
+
+template <typename T>
+static inline void launch_proj_shfl(const T* X, int ld, int N, int n, int R, double pre_v, double pre_g,
+                                    const T* U, int k, const double* coef, double* partial, int* nblk,
+                                    hipStream_t st) {
+  const int ng = (R + kShflGroup - 1) / kShflGroup;
+  const int cgs = (R + ng - 1) / ng;
+  dim3 grid((N + 255) / 256, ng);
+  *nblk = grid.x;
+  k_ts_proj_shfl<T><<<grid, 256, 0, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, coef, cgs, partial);
+}
+
 }  // namespace dski

@@ -62,6 +62,8 @@ _SIGS = {
     "dski_lanczos_quad_log": (C.c_double, [dp, dp, C.c_int, ip]),
     "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
     "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_autotune": (C.c_int, [vp, C.c_int, C.c_int, dp, vp]),
+    "dski_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
     "dski_mvm_f64": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_mvm_dtheta_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_permute_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -221,6 +223,15 @@ class Plan:
         _check(_fn("dski_permute", V)(self._h, int(direction), V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
                                   _stream(stream)), "dski_permute")
         return Y
+
+    def autotune(self, R: int, k: int, stream=None) -> dict:
+        """Time the kernel variants for this shape and keep the fastest."""
+        t = (C.c_double * 5)()
+        _check(lib().dski_autotune(self._h, int(R), int(k), t, _stream(stream)), "dski_autotune")
+        return {"scatter_us": [t[0], t[1], t[2]], "proj_us": [t[3], t[4]]}
+
+    def set_variants(self, scatter: int, proj: int):
+        _check(lib().dski_set_variants(self._h, int(scatter), int(proj)), "dski_set_variants")
 
     def set_precision(self, bits: int):
         """Storage precision of the vectors slq_logdet creates (32 or 64)."""

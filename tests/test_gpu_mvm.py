@@ -123,3 +123,20 @@ def test_rademacher_matches_oracle_stream():
     for (seed, col0, nc, N) in ((SEED, 0, 3, 1000), (12345, 5, 2, 777)):
         g = dski.rademacher(seed, col0, nc, N).cpu().numpy().T.astype(np.float64)
         assert np.array_equal(g, orng.rademacher(seed, col0, nc, N))
+
+
+@pytest.mark.parametrize("name", ["terrain_small", "torus_small"])
+def test_kernel_variants_agree(name):
+    """Every scatter variant gives the same bits; the autotuner's choice is one of them."""
+    W = dict(small_workloads())[name]
+    say("variants", name)
+    plan, op = make(W)
+    V = to_gpu(np.random.default_rng(4).standard_normal((op.N, 17)))
+    outs = []
+    for v in range(3):
+        plan.set_variants(v, 0)
+        outs.append(plan.mvm(V))
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    t = plan.autotune(17, 30)
+    say("  autotune us", t)
+    assert torch.equal(plan.mvm(V), outs[0])
