@@ -86,6 +86,33 @@ dski_status dski_plan_create(dski_plan* out, int n, int d, const double* X,
                              const double* hi_host, dski_stream stream);
 dski_status dski_plan_destroy(dski_plan plan);
 
+/* D-SKIP operator (Sec. 3.2) for higher d: the kernel matrix of the product SE
+ * kernel with derivatives as the Hadamard product over axes of the 1-D D-SKI
+ * factors Khat_p (grid of m_1d nodes on [lo_p, hi_p]; the (a, b) block uses
+ * derivative weights on the side whose block is the derivative along p), each
+ * compressed by rank_r Lanczos steps with full re-orthogonalisation from the
+ * normalised Rademacher column `node` of `seed` (leaves 0..d-1), combined by a
+ * binary tree (pairs (0,1), (2,3), ..., internal nodes recompressed by rank_r
+ * Lanczos steps and numbered on from d; the root is the exact Hadamard product of
+ * its two children), applied by the SKIP reduction (A o B) v = rowsum((Qa Ta) o
+ * ((Qb Tb) C^T)), C = Qa^T diag(v) Qb.
+ * X: device, n x d row-major FP64 (copied); 2 <= d <= 64; m_1d >= 4;
+ * 1 <= rank_r <= 64; lo_host/hi_host: d entries each, or both NULL for the
+ * bounding box; log_ell_host: d length scales (the factors depend on them; the
+ * build runs here and again in dski_set_hypers when a length scale changes).
+ * The plan works with every solver call (pivchol_build, pcg_solve, slq_logdet,
+ * dski_mvm*); dski_mvm_dtheta supports s and the noise levels; mll_and_grad and
+ * dski_mvm_stage return DSKI_ENOTSUP.  Tile order is the identity.
+ * Errors: DSKI_EINVAL on bad arguments or points outside the box. */
+dski_status dskip_plan_create(dski_plan* out, int n, int d, const double* X, int m_1d,
+                              int rank_r, uint64_t seed, const double* lo_host,
+                              const double* hi_host, const double* log_ell_host,
+                              dski_stream stream);
+
+/* D-SKIP plan facts: grid size, requested rank, and the number of Lanczos
+ * vectors kept in the two root factors (< rank_r after an early breakdown). */
+dski_status dskip_plan_info(dski_plan plan, int* m_1d, int* rank_r, int* k_a, int* k_b);
+
 /* Plan geometry: n, d, N, total grid nodes, and per axis (d entries each)
  * the grid size, circulant FFT length, grid spacing and first node. */
 dski_status dski_plan_info(dski_plan plan, int* n, int* d, int* N, long long* grid_nodes,

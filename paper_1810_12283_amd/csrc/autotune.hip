@@ -66,12 +66,12 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
   double* part = coef + (size_t)std::max(k, 1) * R;
   k_fill_pm1<<<1024, 256, 0, st>>>(V, nv + nu, 12345);
   DSKI_HIP(hipMemsetAsync(coef, 0, sizeof(double) * (size_t)std::max(k, 1) * R, st));
-  DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
-  double* G = p->grid.as<double>();
   double t[5] = {0, 0, 0, 0, 0};
-  // scatter variants
+  // scatter variants (D-SKI plans only)
   int best_s = 0;
-  for (int v = 0; v < 3; ++v) {
+  if (p->kind == 0) DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
+  double* G = p->grid.as<double>();
+  for (int v = 0; v < (p->kind == 0 ? 3 : 0); ++v) {
     p->scatter_variant = v;
     DSKI_TRY(time_us([&]() { return scatter<float>(p, R, V, N, G, st); }, reps, st, &t[v]));
     if (t[v] < t[best_s]) best_s = v;

@@ -9,7 +9,8 @@
 
 #include "../../include/dski.h"
 
-#define DSKI_MAXD 3
+#define DSKI_MAXD 3     // D-SKI grid dimensions
+#define DSKIP_MAXD 64   // D-SKIP input dimensions
 
 namespace dski {
 
@@ -57,9 +58,22 @@ struct Axis {
   double* col = nullptr;      // m first column of T_p (device)
 };
 
+struct DskipData;  // D-SKIP factors (dskip.hip)
+
+// State of the device-side pivoted Cholesky.
+struct PivState {
+  int piv;        // chosen tile-order N-index
+  int stop;       // 1 once the factorisation has stopped
+  int rank;       // columns produced
+  double dpiv;    // residual diagonal at the pivot
+  double dmax0;   // largest initial diagonal
+};
+
 }  // namespace dski
 
 struct dski_plan_s {
+  int kind = 0;                // 0 D-SKI (grid), 1 D-SKIP (Hadamard of 1-D factors)
+  dski::DskipData* ds = nullptr;
   int n = 0, d = 0, N = 0;
   long long M = 0;             // grid nodes
   int ncells = 0;              // total interpolation cells
@@ -148,6 +162,21 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, 
                       const double* tol_host, int max_iter, int fixed_iters, double* alpha_beta,
                       PcgResult& res, hipStream_t st, double* X64 = nullptr,
                       const int* verify_mask = nullptr);
+
+// --- D-SKIP ----------------------------------------------------------------------------
+// Y = ks K V + diag(nv on value rows, ng on gradient rows) V (D-SKIP, identity tile order)
+template <typename T>
+dski_status dskip_apply(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double ks, double nv, double ng,
+                        double* pq_partial, hipStream_t st);
+template <typename T>
+dski_status dskip_mvm(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double* pq_partial,
+                      hipStream_t st);
+dski_status dskip_set_hypers(dski_plan p, const double* log_ell, hipStream_t st);
+dski_status dskip_diag(dski_plan p, double* diag, hipStream_t st);
+// one pivoted-Cholesky step j (after the arg-max partials pv/pi of nblk blocks)
+dski_status dskip_pc_step(dski_plan p, int j, const double* pv, const int* pi, int nblk, double rel_tol,
+                          PivState* ps, int* piv_list, double* L, double* lrow, double* dres, hipStream_t st);
+void dskip_destroy(dski_plan p);
 
 // --- host numerics ---------------------------------------------------------------------
 double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok);

@@ -731,7 +731,7 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
   }
 }
 
-int gather_blocks(dski_plan p) { return (p->n + 255) / 256; }
+int gather_blocks(dski_plan p) { return p->kind == 1 ? (p->N + 255) / 256 : (p->n + 255) / 256; }
 
 template <int D, typename T>
 static void launch_gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
@@ -763,6 +763,7 @@ template <typename T>
 dski_status mvm_tiled(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double* pq_partial,
                       hipStream_t st) {
   if (R <= 0) return DSKI_OK;
+  if (p->kind == 1) return dskip_mvm<T>(p, R, V, ldv, Y, ldy, pq_partial, st);
   DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
   double* G = p->grid.as<double>();
   DSKI_TRY(scatter<T>(p, R, V, ldv, G, st));
@@ -797,6 +798,12 @@ dski_status mvm_dtheta(dski_plan p, int which, int R, const T* V, int ldv, T* Y,
   int d = p->d;
   size_t tot = (size_t)p->N * R;
   int blocks = (int)std::min<size_t>((tot + 255) / 256, 65535 * 8);
+  if (p->kind == 1 && which < d) {
+    set_error("D-SKIP: length-scale derivatives of the Lanczos factors are not available");
+    return DSKI_ENOTSUP;
+  }
+  if (p->kind == 1 && which == d)  // dK~/dlog s = 2 K
+    return dskip_apply<T>(p, R, V, ldv, Y, ldy, 2.0 * p->s * p->s, 0.0, 0.0, nullptr, st);
   if (which <= d) {
     DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
     double* G = p->grid.as<double>();
@@ -878,6 +885,10 @@ dski_status dski_mvm_stage(dski_plan p, int stage, int R, const float* V, int ld
     return DSKI_EINVAL;
   }
   if (R == 0) return DSKI_OK;
+  if (p->kind != 0) {
+    set_error("dski_mvm_stage: a D-SKIP plan has no grid stages");
+    return DSKI_ENOTSUP;
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (stage == 0) DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
   if (p->grid.bytes < sizeof(double) * (size_t)p->M * R) {

@@ -314,12 +314,13 @@ const char* dski_version(void) { return "dski-gfx950 " __DATE__; }
 
 dski_status dski_plan_destroy(dski_plan p) {
   if (!p) return DSKI_OK;
+  if (p->kind == 1) dskip_destroy(p);
   (void)hipFree(p->perm);
   (void)hipFree(p->cell);
   (void)hipFree(p->toff);
   (void)hipFree(p->wts);
   (void)hipFree(p->cell_start);
-  for (int a = 0; a < p->d; ++a) {
+  for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     (void)hipFree(p->ax[a].twiddle);
     (void)hipFree(p->ax[a].spec);
     (void)hipFree(p->ax[a].dspec);
@@ -517,7 +518,7 @@ dski_status dski_plan_info(dski_plan p, int* n, int* d, int* N, long long* grid_
   if (d) *d = p->d;
   if (N) *N = p->N;
   if (grid_nodes) *grid_nodes = p->M;
-  for (int a = 0; a < p->d; ++a) {
+  for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     if (m_host) m_host[a] = p->ax[a].m;
     if (fft_len_host) fft_len_host[a] = p->ax[a].L;
     if (h_host) h_host[a] = p->ax[a].h;
@@ -545,6 +546,7 @@ dski_status dski_set_hypers(dski_plan p, const double* log_ell_host, double log_
   p->s = std::exp(log_s);
   p->sf = std::exp(log_sigma_f);
   p->sg = std::exp(log_sigma_g);
+  if (p->kind == 1) return dskip_set_hypers(p, log_ell_host, st);  // rebuilds the factors when ell moves
   for (int a = 0; a < p->d; ++a) {
     Axis& A = p->ax[a];
     p->ell[a] = std::exp(log_ell_host[a]);

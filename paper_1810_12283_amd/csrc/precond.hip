@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "pivot.h"
 #include "tskinny.h"
 
 namespace dski {
@@ -88,14 +89,6 @@ __global__ void k_pc_diag(GeoP g, const int* __restrict__ cell, const double* __
   diag[e] = v;
 }
 
-struct PivState {
-  int piv;        // chosen tile-order N-index
-  int stop;       // 1 once the factorisation has stopped
-  int rank;       // columns produced
-  double dpiv;    // residual diagonal at the pivot
-  double dmax0;   // largest initial diagonal
-};
-
 // Block-wise arg-max of the residual diagonal (ties -> lowest index).
 __global__ void k_argmax_partial(const double* __restrict__ dres, int N, double* __restrict__ pv,
                                  int* __restrict__ pi) {
@@ -134,59 +127,11 @@ __global__ void k_argmax_partial(const double* __restrict__ dres, int N, double*
 // pivot's row of L.  One work-group.
 __global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int* __restrict__ pi,
                                int nblk, int j, double rel_tol, PivState* __restrict__ ps,
-                               int* __restrict__ piv_list, const double* __restrict__ dres,
-                               const int* __restrict__ cell, const double* __restrict__ toff,
-                               double* __restrict__ arow, const double* __restrict__ L,
-                               double* __restrict__ lrow) {
-  __shared__ double sv[kBlock];
-  __shared__ int si[kBlock];
-  double best = -INFINITY;
-  int bi = 0x7fffffff;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    double v = pv[b];
-    int i = pi[b];
-    if (v > best || (v == best && i < bi)) {
-      best = v;
-      bi = i;
-    }
-  }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
-      double v = sv[threadIdx.x + off];
-      int i = si[threadIdx.x + off];
-      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && i < si[threadIdx.x])) {
-        sv[threadIdx.x] = v;
-        si[threadIdx.x] = i;
-      }
-    }
-    __syncthreads();
-  }
-  __shared__ int s_stop;
-  __shared__ int s_piv;
-  if (threadIdx.x == 0) {
-    if (j == 0) {
-      ps->dmax0 = sv[0];
-      ps->stop = 0;
-      ps->rank = 0;
-    }
-    int stop = ps->stop;
-    if (!stop && !(sv[0] > rel_tol * ps->dmax0 && sv[0] > 0.0)) stop = 1;
-    ps->stop = stop;
-    s_stop = stop;
-    s_piv = si[0];
-    if (!stop) {
-      ps->piv = si[0];
-      ps->dpiv = sv[0];
-      piv_list[j] = si[0];
-      ps->rank = j + 1;
-    }
-  }
-  __syncthreads();
-  if (s_stop) return;
-  int e = s_piv;
+                               int* __restrict__ piv_list, const int* __restrict__ cell,
+                               const double* __restrict__ toff, double* __restrict__ arow,
+                               const double* __restrict__ L, double* __restrict__ lrow) {
+  const int e = pivot_select_block(pv, pi, nblk, j, rel_tol, ps, piv_list);
+  if (e < 0) return;
   int blk = e / g.n, k = e % g.n;
   int c[DSKI_MAXD];
   cell_coords(cell[k], g, c);
@@ -441,13 +386,14 @@ static void destroy_pc(dski_precond pc) {
 static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_host, int* piv_host,
                               hipStream_t st) {
   int N = p->N, n = p->n;
-  GeoP g = geop_of(p);
+  GeoP g = p->kind == 0 ? geop_of(p) : GeoP{};
   DSKI_HIP(hipMalloc(&pc->piv_tile, sizeof(int) * std::max(k, 1)));
   DSKI_HIP(hipMalloc(&pc->L, sizeof(double) * (size_t)N * std::max(k, 1)));
   // scratch: dres (N), argmax partials, PivState, arow (sum m), lrow (k)
   int nblk = std::min(1024, std::max(1, (N + kBlock - 1) / kBlock));
   int msum = 0;
-  for (int a = 0; a < p->d; ++a) msum += p->ax[a].m;
+  if (p->kind == 0)
+    for (int a = 0; a < p->d; ++a) msum += p->ax[a].m;
   size_t bytes = sizeof(double) * ((size_t)N + nblk + msum + k + 8) + sizeof(int) * (nblk + 8) +
                  sizeof(PivState) + 256;
   char* scratch = nullptr;
@@ -461,14 +407,25 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
   dski_status rc = DSKI_OK;
   do {
     int vb = (N + kBlock - 1) / kBlock;
-    k_pc_diag<<<vb, kBlock, 0, st>>>(g, p->cell, p->toff, dres);
+    if (p->kind == 1) {
+      rc = dskip_diag(p, dres, st);
+      if (rc < 0) break;
+    } else {
+      k_pc_diag<<<vb, kBlock, 0, st>>>(g, p->cell, p->toff, dres);
+    }
     const double rel_tol = 1e-12;
     for (int j = 0; j < k; ++j) {
       k_argmax_partial<<<nblk, kBlock, 0, st>>>(dres, N, pv, pi);
-      k_pivot_select<<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, pc->piv_tile, dres, p->cell,
-                                           p->toff, arow, pc->L, lrow);
+      if (p->kind == 1) {
+        rc = dskip_pc_step(p, j, pv, pi, nblk, rel_tol, ps, pc->piv_tile, pc->L, lrow, dres, st);
+        if (rc < 0) break;
+        continue;
+      }
+      k_pivot_select<<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, pc->piv_tile, p->cell, p->toff,
+                                           arow, pc->L, lrow);
       k_pc_column<<<vb, kBlock, 0, st>>>(g, j, ps, p->cell, p->toff, arow, lrow, pc->L, dres);
     }
+    if (rc < 0) break;
     if (hipGetLastError() != hipSuccess) {
       set_error("pivoted Cholesky kernel launch failed");
       rc = DSKI_EHIP;

@@ -308,6 +308,11 @@ static dski_status mll_user(dski_plan p, dski_precond pc_in, int k, const T* y, 
     set_error("mll_and_grad: bad arguments");
     return DSKI_EINVAL;
   }
+  if (p->kind != 0) {
+    set_error("mll_and_grad: the length-scale gradient needs a D-SKI plan (D-SKIP factors are not "
+              "differentiated)");
+    return DSKI_ENOTSUP;
+  }
   dski_precond pc = pc_in;
   if (!pc) {
     int rank = 0;

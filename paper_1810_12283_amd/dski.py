@@ -42,6 +42,9 @@ _SIGS = {
     "dski_version": (C.c_char_p, []),
     "dski_plan_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, vp, ip, dp, dp, vp]),
     "dski_plan_destroy": (C.c_int, [vp]),
+    "dskip_plan_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, vp, C.c_int, C.c_int, C.c_uint64,
+                                    dp, dp, dp, vp]),
+    "dskip_plan_info": (C.c_int, [vp, ip, ip, ip, ip]),
     "dski_plan_info": (C.c_int, [vp, ip, ip, ip, C.POINTER(C.c_longlong), ip, ip, dp, dp]),
     "dski_set_hypers": (C.c_int, [vp, dp, C.c_double, C.c_double, C.c_double, vp]),
     "dski_mvm": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -153,6 +156,13 @@ class Plan:
 
     def _info(self):
         L = lib()
+        if getattr(self, "kind", "dski") == "dskip":
+            m1, r, ka, kb = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+            _check(L.dskip_plan_info(self._h, C.byref(m1), C.byref(r), C.byref(ka), C.byref(kb)),
+                   "dskip_plan_info")
+            self.m_1d, self.rank_r, self.root_ranks = m1.value, r.value, (ka.value, kb.value)
+            self.grid_nodes = 0
+            return
         n, d, N = C.c_int(), C.c_int(), C.c_int()
         M = C.c_longlong()
         m = (C.c_int * 3)()
@@ -181,6 +191,8 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    kind = "dski"
 
     def set_hypers(self, log_ell, log_s, log_sigma_f, log_sigma_g, stream=None):
         le = np.broadcast_to(np.asarray(log_ell, dtype=np.float64), (self.d,))
@@ -281,6 +293,31 @@ class Plan:
                     "mll_and_grad")
         return dict(mll=mll.value, grad=np.array(list(grad)), logdet=ld.value, iters=list(iters),
                     status=st)
+
+
+class DskipPlan(Plan):
+    """A D-SKIP operator (Hadamard product of Lanczos-compressed 1-D D-SKI
+    factors, Sec. 3.2) on fixed points; works with the same solver calls."""
+
+    kind = "dskip"
+
+    def __init__(self, X: torch.Tensor, m_1d: int, rank_r: int, seed: int, log_ell, lo=None, hi=None,
+                 stream=None):
+        L = lib()
+        if not X.is_cuda or X.dtype != torch.float64 or X.dim() != 2:
+            raise TypeError("X must be a CUDA float64 tensor of shape (n, d)")
+        X = X.contiguous()
+        n, d = X.shape
+        self.n, self.d, self.N = n, d, n * (d + 1)
+        h = vp()
+        le = np.broadcast_to(np.asarray(log_ell, dtype=np.float64), (d,))
+        le_a = _arr([float(v) for v in le], C.c_double)
+        lo_a = _arr([float(v) for v in lo], C.c_double) if lo is not None else None
+        hi_a = _arr([float(v) for v in hi], C.c_double) if hi is not None else None
+        _check(L.dskip_plan_create(C.byref(h), n, d, _dptr(X), int(m_1d), int(rank_r), int(seed) & (2**64 - 1),
+                                   lo_a, hi_a, le_a, _stream(stream)), "dskip_plan_create")
+        self._h = h
+        self._info()
 
 
 class Precond:

@@ -60,6 +60,8 @@ class Workload:
     num_probes: int          # Hutchinson probes
     lanczos_steps: int       # 0 = derive the quadrature from PCG to tolerance
     seed: int
+    skip_m: int = 0          # D-SKIP: 1-D grid nodes per axis (0: not a D-SKIP workload)
+    skip_rank: int = 0       # D-SKIP: Lanczos rank of every factor
 
     @property
     def n(self) -> int:
@@ -200,9 +202,10 @@ def torus(seed: int = 2, n: int = 30000, grid: int = 48) -> Workload:
                     50, 1e-4, 16, 0, seed)
 
 
-def ridge8d(seed: int = 3, n: int = 4000, d: int = 8) -> Workload:
+def ridge8d(seed: int = 3, n: int = 4000, d: int = 8, skip_m: int = 100, skip_rank: int = 32) -> Workload:
     """f = sum_{j=1}^{16} tanh(a_j.x + b_j), |a_j|~U[0.5,2] along a uniform
-    direction, b_j~U[-1,1]; X~U[-1,1]^d."""
+    direction, b_j~U[-1,1]; X~U[-1,1]^d.  D-SKIP operator: 1-D grids of
+    ``skip_m`` nodes, Lanczos rank ``skip_rank``; pivoted-Cholesky rank 100."""
     rng = np.random.default_rng(seed)
     J = 16
     dirs = rng.standard_normal((J, d))
@@ -217,7 +220,7 @@ def ridge8d(seed: int = 3, n: int = 4000, d: int = 8) -> Workload:
     y = _noisy(rng, f, grad, sf, sg)
     return Workload("ridge8d", X, f, grad, y, np.log(np.full(d, 0.5)), 0.0,
                     math.log(sf), math.log(sg), None, -np.ones(d), np.ones(d),
-                    100, 1e-4, 16, 0, seed)
+                    100, 1e-4, 16, 0, seed, skip_m, skip_rank)
 
 
 def by_name(name: str, **kw) -> Workload:
