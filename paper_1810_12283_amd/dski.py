@@ -320,6 +320,33 @@ class DskipPlan(Plan):
         self._info()
 
 
+class MarginalLikelihood(torch.autograd.Function):
+    """mll(theta) with theta = (log ell_1..log ell_d, log s, log sigma_f,
+    log sigma_g) as a float64 tensor; the forward pass sets the hyper-parameters
+    of `plan`, builds a rank-k preconditioner and calls mll_and_grad (adjoint
+    MVMs on the device); the backward pass returns grad_output times the
+    gradient computed there (eq. (1) and its derivatives).
+
+        mll = MarginalLikelihood.apply(theta, plan, y, k, num_probes, seed, tol, max_iter)
+    """
+
+    @staticmethod
+    def forward(ctx, theta, plan, y, k=50, num_probes=16, seed=0x181012283, tol=1e-4, max_iter=10000):
+        th = theta.detach().double().cpu().numpy()
+        d = plan.d
+        if th.shape != (d + 3,):
+            raise ValueError(f"theta must have d + 3 = {d + 3} entries")
+        plan.set_hypers(th[:d], th[d], th[d + 1], th[d + 2])
+        res = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=max_iter)
+        ctx.save_for_backward(torch.tensor(res["grad"], dtype=theta.dtype, device=theta.device))
+        return torch.tensor(res["mll"], dtype=theta.dtype, device=theta.device)
+
+    @staticmethod
+    def backward(ctx, grad_output):
+        (g,) = ctx.saved_tensors
+        return (grad_output * g,) + (None,) * 7
+
+
 class Precond:
     """Pivoted-Cholesky preconditioner (owns a dski_precond)."""
 
