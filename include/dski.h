@@ -162,14 +162,20 @@ dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int
 /* Times the interchangeable kernel variants for R right-hand sides and
  * preconditioner rank k on this plan's shape (scatter: LDS node tiles / direct
  * one column per thread / direct two columns per thread; preconditioner
- * projections: LDS row tiles / wavefront shuffles) and keeps the fastest of
- * each.  All variants give bitwise-identical scatters and equal projections up
- * to summation order.  times_host (5 entries, may be NULL) receives the
- * measured microseconds in that order.  1 <= R <= 32, 0 <= k <= 256. */
+ * projection: row tiles of 128 / 64 / 256 rows per work-group) and keeps the
+ * fastest of each.  All scatter variants give bitwise-identical results; the
+ * projections are equal up to summation order.  times_host (6 entries, may be
+ * NULL) receives the measured microseconds in that order (scatter entries are
+ * 0 for a D-SKIP plan).  1 <= R <= 32, 0 <= k <= 256. */
 dski_status dski_autotune(dski_plan plan, int R, int k, double* times_host, dski_stream stream);
 
-/* Select the variants directly (scatter 0..2, projection 0..1). */
+/* Select the variants directly (scatter 0..2, projection 0..2). */
 dski_status dski_set_variants(dski_plan plan, int scatter_variant, int proj_variant);
+
+/* PCG launch mode: 1 (default) replays bursts of 8 iterations from a HIP graph
+ * captured once per solve on a side stream (ordered with the caller's stream
+ * by events); 0 launches every kernel directly.  Results are bitwise equal. */
+dski_status dski_set_graph(dski_plan plan, int on);
 
 /* Storage precision (32 or 64 bits) of the N-vectors that slq_logdet creates
  * internally (probes, Krylov vectors).  Default 32. */
@@ -177,7 +183,9 @@ dski_status dski_plan_set_precision(dski_plan plan, int bits);
 
 /* Truncated pivoted Cholesky of the noise-free K (Sec. 3.3; greedy largest
  * residual diagonal, lowest index among exact ties) and the preconditioner
- * M = D + L L^T in square-root form.  rank_host receives the rank reached
+ * M = D + L L^T, kept as G = D^{-1/2} L = U S V^T (U FP64, orthonormal
+ * columns): M^{-1} = D^{-1/2}(I - U diag(s^2/(1+s^2)) U^T) D^{-1/2}.  rank_host
+ * receives the rank reached
  * (< k when the largest residual diagonal fell below 1e-12 x the largest
  * initial one: DSKI_RANK_TRUNCATED).  piv_host (k ints, user-order indices
  * into the N-vector, may be NULL) receives the pivots. */
@@ -185,7 +193,8 @@ dski_status pivchol_build(dski_plan plan, int k, dski_precond* out, int* rank_ho
                           int* piv_host, dski_stream stream);
 dski_status dski_precond_destroy(dski_precond pc);
 
-/* Z = M^{-1} R for R vectors (user order), stable form of Sec. 3.3. */
+/* Z = M^{-1} R for R vectors (user order); the Woodbury identity of Sec. 3.3
+ * with two noise levels (one projection onto U, one correction). */
 dski_status dski_precond_apply(dski_precond pc, int R, const float* Rm, int ld, float* Z,
                                int ldz, dski_stream stream);
 dski_status dski_precond_apply_f64(dski_precond pc, int R, const double* Rm, int ld, double* Z,

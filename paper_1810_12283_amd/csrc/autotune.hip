@@ -1,9 +1,10 @@
-// Per-shape autotuning of kernel variants.  The scatter (W^T) and the
-// preconditioner projections (U^T v) each have an LDS-tiled and a cache-direct
-// form with identical results; which is faster depends on the grid size, the
-// number of points per cell, the rank and the number of right-hand sides.  The
-// tuner times each candidate with HIP events on the caller's stream and keeps
-// the fastest in the plan.
+// Per-shape autotuning of kernel variants.  The scatter (W^T) has an LDS-tiled
+// and two cache-direct forms with identical results; the preconditioner
+// projection (U^T v) has three row-tile heights (partials differ, reduced in a
+// fixed order).  Which is faster depends on the grid size, the number of points
+// per cell, the rank and the number of right-hand sides.  The tuner times each
+// candidate with HIP events on the caller's stream and keeps the fastest in the
+// plan.
 #include <cmath>
 
 #include "internal.h"
@@ -61,12 +62,11 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
                                                                       (size_t)std::max(k, 1) * R *
                                                                           ((N + 7) / 8 + 1)) + 1024));
   float* V = buf.as<float>();
-  float* U = V + nv;
   double* coef = reinterpret_cast<double*>(buf.as<char>() + ((sizeof(float) * (nv + nu) + 63) / 64) * 64);
   double* part = coef + (size_t)std::max(k, 1) * R;
-  k_fill_pm1<<<1024, 256, 0, st>>>(V, nv + nu, 12345);
+  k_fill_pm1<<<1024, 256, 0, st>>>(V, nv, 12345);
   DSKI_HIP(hipMemsetAsync(coef, 0, sizeof(double) * (size_t)std::max(k, 1) * R, st));
-  double t[5] = {0, 0, 0, 0, 0};
+  double t[6] = {0, 0, 0, 0, 0, 0};
   // scatter variants (D-SKI plans only)
   int best_s = 0;
   if (p->kind == 0) DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
@@ -77,42 +77,46 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
     if (t[v] < t[best_s]) best_s = v;
   }
   p->scatter_variant = best_s;
-  // projection variants (with the correction term, as in the PCG)
+  // projection row tiles (128, 64, 256 rows per work-group) on a dummy FP64 factor
   int best_p = 0;
   if (k > 0) {
-    ProjLds L = proj_lds(k, R, sizeof(float));
-    const int nblk = (N + L.RT - 1) / L.RT;
-    DSKI_TRY(time_us(
-        [&]() -> dski_status {
-          k_ts_proj<float><<<nblk, kBlock, L.bytes, st>>>(V, N, N, p->n, R, 1.0, 1.0, U, k, coef, L.RT, L, part);
-          DSKI_HIP(hipGetLastError());
-          return DSKI_OK;
-        },
-        reps, st, &t[3]));
-    DSKI_TRY(time_us(
-        [&]() -> dski_status {
-          int nb = 0;
-          launch_proj_shfl<float>(V, N, N, p->n, R, 1.0, 1.0, U, k, coef, part, &nb, st);
-          DSKI_HIP(hipGetLastError());
-          return DSKI_OK;
-        },
-        reps, st, &t[4]));
-    best_p = t[4] < t[3] ? 1 : 0;
+    DevBuf ubuf;
+    DSKI_TRY(ubuf.reserve(sizeof(double) * nu));
+    double* Ud = ubuf.as<double>();
+    DSKI_HIP(hipMemsetAsync(Ud, 0, sizeof(double) * nu, st));
+    for (int v = 0; v < 3; ++v) {
+      p->proj_variant = v;
+      ProjPlan L = proj_plan(k, R, proj_rows(p));
+      DSKI_TRY(time_us([&]() { return launch_proj<float>(V, N, N, p->n, R, 1.0, 1.0, Ud, k, L, part, st); }, reps,
+                       st, &t[3 + v]));
+      if (t[3 + v] < t[3 + best_p]) best_p = v;
+    }
+    DSKI_HIP(hipStreamSynchronize(st));
+    ubuf.release();
   }
   p->proj_variant = best_p;
   DSKI_HIP(hipStreamSynchronize(st));
   buf.release();
   if (times_host)
-    for (int i = 0; i < 5; ++i) times_host[i] = t[i];
+    for (int i = 0; i < 6; ++i) times_host[i] = t[i];
   return DSKI_OK;
 }
 
 extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant, int proj_variant) {
-  if (!p || scatter_variant < 0 || scatter_variant > 2 || proj_variant < 0 || proj_variant > 1) {
+  if (!p || scatter_variant < 0 || scatter_variant > 2 || proj_variant < 0 || proj_variant > 2) {
     set_error("dski_set_variants: bad arguments");
     return DSKI_EINVAL;
   }
   p->scatter_variant = scatter_variant;
   p->proj_variant = proj_variant;
+  return DSKI_OK;
+}
+
+extern "C" dski_status dski_set_graph(dski_plan p, int on) {
+  if (!p || (on != 0 && on != 1)) {
+    set_error("dski_set_graph: bad arguments");
+    return DSKI_EINVAL;
+  }
+  p->use_graph = on;
   return DSKI_OK;
 }

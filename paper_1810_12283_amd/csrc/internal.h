@@ -95,7 +95,8 @@ struct dski_plan_s {
   int precision = 32;          // storage of N-vectors inside slq_logdet (32 or 64)
   // kernel variants chosen by dski_autotune (defaults: the LDS-tiled kernels)
   int scatter_variant = 0;     // 0 LDS node tiles, 1 direct 1 column/thread, 2 direct 2 columns/thread
-  int proj_variant = 0;        // 0 LDS row tiles, 1 wavefront-shuffle row blocks
+  int proj_variant = 0;        // rows per projection tile: 0 -> 128, 1 -> 64, 2 -> 256
+  int use_graph = 1;           // PCG bursts replayed from a captured HIP graph
 };
 
 struct dski_precond_s {
@@ -104,9 +105,8 @@ struct dski_precond_s {
   double logdet = 0;
   int* piv_tile = nullptr;     // device, k pivots (tile-order N-index)
   double* L = nullptr;         // device, N x k FP64 (tile order, column-major)
-  float* U = nullptr;          // device, N x k FP32 left singular vectors of D^{-1/2} L
-  double* Ud = nullptr;        // device, the same in FP64 (for the FP64-storage path)
-  double* c = nullptr;         // device, k: 1 - (1 + sigma_i^2)^{-1/2}
+  double* U = nullptr;         // device, N x k FP64 left singular vectors of D^{-1/2} L
+  double* w = nullptr;         // device, k: sigma_i^2 / (1 + sigma_i^2)
   double* rootc = nullptr;     // device, k: sqrt(1 + sigma_i^2) - 1
   dski::DevBuf work;
 };
@@ -145,6 +145,7 @@ template <typename T>
 dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int ld, T* Z, int ldz,
                                        hipStream_t st);
 int vec_blocks(int N);
+int proj_rows(dski_plan p);  // rows per projection tile of the chosen variant
 
 // --- PCG core (tile order) -----------------------------------------------------------
 struct PcgResult {

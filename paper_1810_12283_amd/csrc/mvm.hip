@@ -121,20 +121,29 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     s_rcnt[row] = g1 - g0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int row = 0; row < nrows; ++row) {
-      s_roff[row] = acc;
-      acc += s_rcnt[row];
+  // exclusive prefix of the row counts (wavefront 0, 64 rows per step)
+  if (threadIdx.x < 64) {
+    int carry = 0;
+    for (int r0 = 0; r0 < nrows; r0 += 64) {
+      const int row = r0 + threadIdx.x;
+      const int v = row < nrows ? s_rcnt[row] : 0;
+      int incl = v;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if ((int)threadIdx.x >= off) incl += o;
+      }
+      if (row < nrows) s_roff[row] = carry + incl - v;
+      carry += __shfl(incl, 63, 64);
     }
-    s_roff[nrows] = acc;
+    if (threadIdx.x == 0) s_roff[nrows] = carry;
   }
   __syncthreads();
   const int total = s_roff[nrows];
   const bool lds_ok = total <= PMAX;
   if (lds_ok) {
     // cell table (region-local, row-major) -> LDS point ranges; and for every LDS
-    // slot the global (tile-order) index of its point
+    // slot the global (tile-order) index of its point (binary search of the row)
     for (int f = threadIdx.x; f < ncells_r; f += blockDim.x) {
       int row = f / span[last], cl = f % span[last];
       int rem = row, base = 0;
@@ -149,23 +158,51 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     }
     if (threadIdx.x == 0) s_lcs[ncells_r] = total;
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
-      int row = 0;
-      while (s_roff[row + 1] <= q) ++row;
-      s_qk[q] = s_rg0[row] + q - s_roff[row];
+      int lo_r = 0, hi_r = nrows - 1;  // last row with s_roff[row] <= q
+      while (lo_r < hi_r) {
+        const int mid = (lo_r + hi_r + 1) >> 1;
+        if (s_roff[mid] <= q) lo_r = mid; else hi_r = mid - 1;
+      }
+      s_qk[q] = s_rg0[lo_r] + q - s_roff[lo_r];
     }
   }
   __syncthreads();
   if (lds_ok) {
-    // all loads of the region in flat loops (no per-row serialisation)
-    for (int f = threadIdx.x; f < total * D * 8; f += blockDim.x) {
-      int q = f % total, j = f / total;
-      s_w[j][q] = wts[(size_t)j * n + s_qk[q]];
+    // loads of the region issued four per thread at a time; the value slots of
+    // columns beyond this chunk are zero so the accumulation needs no branches
+    const int totw = total * D * 8;
+    for (int f0 = threadIdx.x; f0 < totw; f0 += 1024) {
+      double w4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        w4[u] = f < totw ? wts[(size_t)(f / total) * n + s_qk[f % total]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        if (f < totw) s_w[f / total][f % total] = w4[u];
+      }
     }
-    const int tot = total * rc * (D + 1);
-    for (int f = threadIdx.x; f < tot; f += blockDim.x) {
-      int q = f % total, rest = f / total;
-      int b = rest % (D + 1), r = rest / (D + 1);
-      s_v[(q * CR + r) * (D + 1) + b] = V[(size_t)(r0 + r) * ldv + (size_t)b * n + s_qk[q]];
+    const int tot = total * CR * (D + 1);
+    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
+      T v4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        const int q = f % total, rest = f / total;
+        const int b = rest % (D + 1), r = rest / (D + 1);
+        v4[u] = (f < tot && r < rc) ? V[(size_t)(r0 + r) * ldv + (size_t)b * n + s_qk[q]] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        if (f < tot) {
+          const int q = f % total, rest = f / total;
+          const int b = rest % (D + 1), r = rest / (D + 1);
+          s_v[(q * CR + r) * (D + 1) + b] = v4[u];
+        }
+      }
     }
   }
   __syncthreads();
@@ -227,13 +264,11 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
           }
           const T* sv = s_v + (size_t)q * CR * (D + 1);
 #pragma unroll
-          for (int r = 0; r < CR; ++r) {
-            if (r < rc) {
-              double a = wprod * (double)sv[r * (D + 1)];
+          for (int r = 0; r < CR; ++r) {  // columns beyond rc hold zeros
+            double a = wprod * (double)sv[r * (D + 1)];
 #pragma unroll
-              for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)sv[r * (D + 1) + qq + 1];
-              acc[r] += a;
-            }
+            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)sv[r * (D + 1) + qq + 1];
+            acc[r] += a;
           }
         }
       }
@@ -542,62 +577,96 @@ __device__ __forceinline__ void fft_inplace(double2* buf, int L, const double2* 
 // circulant eigenvalues `spec` (already scaled by 1/L) and transformed back; two
 // lines share one complex FFT (real and imaginary parts), which is exact because
 // the spectrum is real and even.  TPP = L/8 threads per line pair, 256/TPP pairs
-// per work-group, 32 KiB of LDS plus the twiddle table.
+// per work-group; LDS holds the line pairs, the twiddles, the spectrum and the
+// base offset of every line.  Grid loads and stores are issued four per thread
+// at a time.
 __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long long nlines, int m,
                                                   int L, long long inner,
                                                   const double2* __restrict__ tw,
                                                   const double* __restrict__ spec) {
   extern __shared__ double2 smem[];
+  __shared__ long long s_base[512];
   const int tpp = L / 8;
   const int ppb = 256 / tpp;
   const int pr = threadIdx.x / tpp;
   const int lane = threadIdx.x % tpp;
-  const long long line0 = (long long)blockIdx.x * (2 * ppb);
-  const long long linestride = (long long)m * inner;
-  double2* stw = smem + (size_t)ppb * L;  // twiddle table staged in LDS
-  for (int f = threadIdx.x; f < L; f += 256) stw[f] = tw[f];
-  for (int f = threadIdx.x; f < ppb * L; f += 256) smem[f] = make_double2(0.0, 0.0);
-  __syncthreads();
   const int nl = 2 * ppb;
+  const long long line0 = (long long)blockIdx.x * nl;
+  double2* stw = smem + (size_t)ppb * L;  // twiddle table
+  // spectrum in LDS up to L = 1024 (64 KiB in all), else read through the cache
+  const bool stage_spec = L <= 1024;
+  double* sspec = stage_spec ? reinterpret_cast<double*>(stw + L) : nullptr;
+  for (int f = threadIdx.x; f < L; f += 256) {
+    stw[f] = tw[f];
+    if (stage_spec) sspec[f] = spec[f];
+  }
+  for (int l = threadIdx.x; l < nl; l += 256) {
+    const long long line = line0 + l;
+    s_base[l] = line < nlines ? (line / inner) * ((long long)m * inner) + line % inner : -1;
+  }
+  // zero padding of every line pair (entries m .. L-1)
+  for (int f = threadIdx.x; f < ppb * (L - m); f += 256) {
+    const int pp = f / (L - m), jj = m + f % (L - m);
+    smem[(size_t)pp * L + jj] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int tot = nl * m;
   if (inner > 1) {
-    for (int f = threadIdx.x; f < nl * m; f += 256) {
-      int l = f % nl, jj = f / nl;
-      long long line = line0 + l;
-      if (line < nlines) {
-        double v = G[(line / inner) * linestride + line % inner + (long long)jj * inner];
-        reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v;
+    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        const int l = f % nl, jj = f / nl;
+        const long long b = f < tot ? s_base[l] : -1;
+        v[u] = b >= 0 ? G[b + (long long)jj * inner] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        if (f < tot) {
+          const int l = f % nl, jj = f / nl;
+          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v[u];
+        }
       }
     }
   } else {
-    for (int f = threadIdx.x; f < nl * m; f += 256) {
-      int jj = f % m, l = f / m;
-      long long line = line0 + l;
-      if (line < nlines) {
-        double v = G[line * m + jj];
-        reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v;
+    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        const int jj = f % m, l = f / m;
+        const long long b = f < tot ? s_base[l] : -1;
+        v[u] = b >= 0 ? G[b + jj] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        if (f < tot) {
+          const int jj = f % m, l = f / m;
+          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v[u];
+        }
       }
     }
   }
   __syncthreads();
   double2* buf = smem + (size_t)pr * L;
   fft_inplace(buf, L, stw, lane, tpp, +1);
-  for (int kk = lane; kk < L; kk += tpp) buf[kk] = cscale(buf[kk], spec[kk]);
+  for (int kk = lane; kk < L; kk += tpp) buf[kk] = cscale(buf[kk], stage_spec ? sspec[kk] : spec[kk]);
   __syncthreads();
   fft_inplace(buf, L, stw, lane, tpp, -1);
   if (inner > 1) {
-    for (int f = threadIdx.x; f < nl * m; f += 256) {
-      int l = f % nl, jj = f / nl;
-      long long line = line0 + l;
-      if (line < nlines)
-        G[(line / inner) * linestride + line % inner + (long long)jj * inner] =
-            reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
+    for (int f = threadIdx.x; f < tot; f += 256) {
+      const int l = f % nl, jj = f / nl;
+      const long long b = s_base[l];
+      if (b >= 0) G[b + (long long)jj * inner] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
     }
   } else {
-    for (int f = threadIdx.x; f < nl * m; f += 256) {
-      int jj = f % m, l = f / m;
-      long long line = line0 + l;
-      if (line < nlines)
-        G[line * m + jj] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
+    for (int f = threadIdx.x; f < tot; f += 256) {
+      const int jj = f % m, l = f / m;
+      const long long b = s_base[l];
+      if (b >= 0) G[b + jj] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
     }
   }
 }
@@ -618,7 +687,7 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
       return DSKI_ENOTSUP;
     }
     int ppb = 256 / (L / 8);
-    size_t sh = sizeof(double2) * ((size_t)ppb * L + L);
+    size_t sh = sizeof(double2) * ((size_t)ppb * L + L) + (L <= 1024 ? sizeof(double) * L : 0);
     long long blocks = (nlines + 2 * ppb - 1) / (2 * ppb);
     k_toeplitz<<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
     DSKI_HIP(hipGetLastError());

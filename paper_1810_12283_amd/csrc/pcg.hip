@@ -5,14 +5,12 @@
 // iterate x is accumulated in FP64, all inner products and scalars are FP64 and
 // live on the device; the host only polls the number of active columns.
 //
-// One iteration is 9 launches (10 with the FFT of a 3-D grid):
+// One iteration is 8 launches (9 with the FFT of a 3-D grid):
 //   scatter | K_UU per axis | gather (+ partials of p.q)
 //   update:  alpha (every block reduces the p.q partials itself, same order),
 //            x += alpha p, r -= alpha q, partials of r.r and of U^T D^{-1/2} r
-//   reduce:  t1 = U^T r', coef1 = c .* t1; r.r
-//   project: t2 = U^T (r' - U coef1)
-//   reduce:  coef2 = c .* (t1 + t2)
-//   final:   z = D^{-1/2}(r' - U coef2) (+ partials of r.z)
+//   reduce:  t = U^T r', coef = w .* t; r.r
+//   final:   z = D^{-1/2}(r' - U coef) (+ partials of r.z)
 //   beta:    beta (every block reduces the r.z partials), convergence test,
 //            p = z + beta p.
 // Scalars that one kernel both reads in every block and updates (rz, the
@@ -38,6 +36,30 @@ struct PcgScal {
 };
 
 constexpr int kVecChunk = 1024;  // rows per work-group in the streaming vector kernels
+constexpr int kGraphIters = 8;   // PCG iterations per captured HIP graph
+
+// Captured iterations of one solve (side stream, ordering events, graph).
+struct PcgGraph {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int par0 = -1;
+  void reset_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    par0 = -1;
+  }
+  ~PcgGraph() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    reset_graph();
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
 
 static int nchunks(int N) { return (N + kVecChunk - 1) / kVecChunk; }
 
@@ -86,18 +108,19 @@ __global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, co
   }
 }
 
-// alpha, x and r updates, partials of r.r and of U^T D^{-1/2} r (row tile of RT rows).
-template <typename T>
+// alpha, x and r updates, partials of r.r and of U^T D^{-1/2} r (row tile of
+// L.RT rows; the new r of the tile is kept in LDS for the projection).
+template <typename T, int TPT>
 __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, const T* __restrict__ Q,
                                                     T* __restrict__ Rr, double* __restrict__ Xd, int N, int n,
                                                     int R, PcgScal s, int par, const double* __restrict__ pq_part,
                                                     int nb_pq, double* __restrict__ rr_part,
-                                                    const T* __restrict__ U, int k, double isf, double isg,
-                                                    int RT, ProjLds L, double* __restrict__ t_part,
+                                                    const double* __restrict__ U, int k, double isf, double isg,
+                                                    ProjPlan L, double* __restrict__ t_part,
                                                     double* __restrict__ hist, int max_iter) {
   extern __shared__ __align__(16) char smem[];
-  T* sU = reinterpret_cast<T*>(smem + L.oU);
-  double* sx = reinterpret_cast<double*>(smem + L.ox);
+  double* sx = reinterpret_cast<double*>(smem);
+  double* sU = reinterpret_cast<double*>(smem + L.oU);
   double* sred = reinterpret_cast<double*>(smem + L.ored);
   __shared__ double s_alpha[kPcgMaxR];
   __shared__ int s_act[kPcgMaxR];
@@ -121,32 +144,45 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
       s_act[c] = on;
     }
   }
+  __syncthreads();
+  const int RT = L.RT, RP = L.RP;
   const int e0 = blockIdx.x * RT;
   const int rn = min(RT, N - e0);
-  if (k > 0) tile_load_u<T>(U, N, k, e0, rn, RT, sU);
-  __syncthreads();
-  for (int f = threadIdx.x; f < RT * R; f += blockDim.x) {
-    int r = f % RT, c = f / RT;
-    double v = 0.0;
-    if (r < rn) {
-      size_t i = (size_t)c * N + e0 + r;
-      double rv = (double)Rr[i];
-      if (s_act[c]) {
-        double a = s_alpha[c];
-        Xd[i] += a * (double)P[i];
-        T rnew = (T)(rv - a * (double)Q[i]);
-        Rr[i] = rnew;
-        rv = (double)rnew;
-      }
-      v = rv;
+  const int tot = RT * RP;
+  for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
+    double rv[4], pv[4], qv[4], xv[4];
+    bool ok[4], on[4];
+    size_t idx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = f0 + 256 * u;
+      const int c = f / RT, r = f % RT;
+      ok[u] = f < tot && c < R && r < rn;
+      on[u] = ok[u] && s_act[c];
+      idx[u] = (size_t)(ok[u] ? c : 0) * N + e0 + (ok[u] ? r : 0);
+      rv[u] = ok[u] ? (double)Rr[idx[u]] : 0.0;
+      pv[u] = on[u] ? (double)P[idx[u]] : 0.0;
+      qv[u] = on[u] ? (double)Q[idx[u]] : 0.0;
+      xv[u] = on[u] ? Xd[idx[u]] : 0.0;
     }
-    sx[r * R + c] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = f0 + 256 * u;
+      if (on[u]) {
+        const double a = s_alpha[f / RT];
+        Xd[idx[u]] = xv[u] + a * pv[u];
+        const T rnew = (T)(rv[u] - a * qv[u]);
+        Rr[idx[u]] = rnew;
+        rv[u] = (double)rnew;
+      }
+      if (f < tot) sx[(f % RT) * RP + f / RT] = rv[u];
+    }
   }
   __syncthreads();
   for (int c = wv; c < R; c += 4) {
     double acc = 0.0;
     for (int r = lane; r < rn; r += 64) {
-      double v = sx[r * R + c];
+      const double v = sx[r * RP + c];
       acc += v * v;
     }
     acc = wave_sum64(acc);
@@ -154,91 +190,27 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
   }
   if (k == 0) return;
   __syncthreads();
-  for (int f = threadIdx.x; f < rn * R; f += blockDim.x) {
-    int r = f / R;
-    sx[f] *= (e0 + r < n ? isf : isg);
-  }
-  __syncthreads();
-  tile_proj<T>(sU, sx, rn, RT, k, R, sred, t_part);
+  for (int f = threadIdx.x; f < rn * RP; f += 256) sx[f] *= (e0 + f / RP < n ? isf : isg);
+  tile_project<TPT>(U, N, k, R, e0, rn, L, sx, sU, sred, t_part);
 }
 
-// Wavefront-shuffle variant of the update: grid (row blocks of 256, column
-// groups of cgs); one thread per row for its group's columns.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_update_shfl(const T* __restrict__ P, const T* __restrict__ Q,
-                                                         T* __restrict__ Rr, double* __restrict__ Xd, int N, int n,
-                                                         int R, PcgScal s, int par,
-                                                         const double* __restrict__ pq_part, int nb_pq,
-                                                         double* __restrict__ rr_part, const T* __restrict__ U,
-                                                         int k, double isf, double isg, int cgs,
-                                                         double* __restrict__ t_part, double* __restrict__ hist,
-                                                         int max_iter) {
-  __shared__ double red[4][kShflChunk][kShflGroup];
-  __shared__ double s_alpha[kShflGroup];
-  __shared__ int s_act[kShflGroup];
-  const int c0 = blockIdx.y * cgs;
-  const int cg = min(cgs, R - c0);
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wv < cg) {  // one wavefront per column of the group
-    const int c = c0 + wv;
-    int on = s.active[par * R + c];
-    double pq = on ? wave_out_sum(pq_part, nb_pq, c) : 0.0;
-    if (lane == 0) {
-      double a = 0.0;
-      if (on) {
-        if (!(pq > 0.0) || !isfinite(pq)) {
-          if (blockIdx.x == 0) s.flags[1] = 1;
-        } else {
-          a = s.rz[par * R + c] / pq;
-        }
-        if (blockIdx.x == 0 && hist && s.iters[c] < max_iter) hist[(size_t)c * max_iter + s.iters[c]] = a;
-      }
-      if (blockIdx.x == 0) s.alpha[c] = a;
-      s_alpha[wv] = a;
-      s_act[wv] = on;
-    }
+static dski_status launch_update(const ProjPlan& L, int nb, const T* P, const T* Q, T* Rr, double* Xd, int N,
+                                 int n, int R, const PcgScal& s, int par, const double* pq_part, int nb_pq,
+                                 double* rr_part, const double* U, int k, double isf, double isg, double* t_part,
+                                 double* hist, int max_iter, hipStream_t st) {
+#define DSKI_UPD(TPT)                                                                                        \
+  k_pcg_update<T, TPT><<<nb, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nb_pq, rr_part, U, \
+                                                    k, isf, isg, L, t_part, hist, max_iter)
+  switch (L.tpt) {
+    case 1: DSKI_UPD(1); break;
+    case 2: DSKI_UPD(2); break;
+    case 4: DSKI_UPD(4); break;
+    default: DSKI_UPD(8); break;
   }
-  __syncthreads();
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[kShflGroup];
-#pragma unroll
-  for (int c = 0; c < kShflGroup; ++c) v[c] = 0.0;
-  if (e < N) {
-#pragma unroll
-    for (int c = 0; c < kShflGroup; ++c) {
-      if (c < cg) {
-        size_t i = (size_t)(c0 + c) * N + e;
-        double rv = (double)Rr[i];
-        if (s_act[c]) {
-          double a = s_alpha[c];
-          Xd[i] += a * (double)P[i];
-          T rnew = (T)(rv - a * (double)Q[i]);
-          Rr[i] = rnew;
-          rv = (double)rnew;
-        }
-        v[c] = rv;
-      }
-    }
-  }
-  // partials of r.r
-#pragma unroll
-  for (int c = 0; c < kShflGroup; ++c) {
-    if (c < cg) {
-      double sm = wave_sum64(v[c] * v[c]);
-      if (lane == 0) red[wv][0][c] = sm;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < cg) {
-    int c = threadIdx.x;
-    rr_part[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = red[0][0][c] + red[1][0][c] + red[2][0][c] + red[3][0][c];
-  }
-  __syncthreads();
-  if (k == 0) return;
-  const double pre = e < n ? isf : isg;
-#pragma unroll
-  for (int c = 0; c < kShflGroup; ++c) v[c] *= pre;
-  shfl_project<T>(U, N, e, k, R, c0, cg, v, red, t_part);
+#undef DSKI_UPD
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
 }
 
 // beta, history, convergence test, p = z + beta p.  Grid (row chunks of 256, R):
@@ -367,16 +339,14 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   const int k = pc ? pc->k : 0;
   const size_t nr = (size_t)N * R;
   const int nbv = nchunks(N), nbg = gather_blocks(p), nbz = vec_blocks(N);
-  ProjLds L = proj_lds(k, R, sizeof(T));
-  const bool shfl = p->proj_variant == 1;
-  const int ngs = (R + kShflGroup - 1) / kShflGroup;
-  const int cgs = (R + ngs - 1) / ngs;
-  const int nbt = shfl ? (N + 255) / 256 : (N + L.RT - 1) / L.RT;
+  const ProjPlan L = proj_plan(k, R, proj_rows(p));
+  const int nbt = L.nblk(N);
   const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, nbt)) * R;
   const size_t ntp = (size_t)nbt * std::max(k, 1) * R;
-  // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, t2, coef, scalars
+  // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, scratch (R), coef, scalars
+  const size_t kr = (size_t)std::max(k, 1) * R;
   size_t tb = ((sizeof(T) * nr * 4) + 63) / 64 * 64;
-  size_t db = sizeof(double) * (nr + 3 * npart + ntp + 3 * (size_t)k * R + 12 * (size_t)R + 16);
+  size_t db = sizeof(double) * (nr + 3 * npart + ntp + 3 * kr + 12 * (size_t)R + 16);
   size_t ib = sizeof(int) * (4 * (size_t)R + 8);
   DSKI_TRY(p->vin.reserve(tb + db + ib + 512));
   char* base = p->vin.as<char>();
@@ -390,10 +360,10 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   double* rz_part = rr_part + npart;
   double* t_part = rz_part + npart;
   double* t1 = t_part + ntp;
-  double* t2 = t1 + (size_t)k * R;
-  double* coef = t2 + (size_t)k * R;
+  double* t2 = t1 + kr;  // R doubles of scratch (true-residual norms)
+  double* coef = t2 + kr;
   PcgScal s;
-  s.rz = coef + (size_t)k * R;
+  s.rz = coef + kr;
   s.rr = s.rz + 2 * R;
   s.bb = s.rr + R;
   s.alpha = s.bb + R;
@@ -419,47 +389,79 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   DSKI_HIP(hipGetLastError());
   int* hflags = nullptr;
   DSKI_HIP(hipHostMalloc(&hflags, sizeof(int) * 2, hipHostMallocDefault));
-  const T* U = pc ? u_of<T>(pc) : nullptr;
+  const double* U = pc ? pc->U : nullptr;
   const double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
   dski_status rc = DSKI_OK;
   const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
   int it = 0;
+  // one iteration, all launches on stream `q`
+  auto iterate = [&](int par, hipStream_t q) -> dski_status {
+    DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, q));
+    DSKI_TRY(launch_update<T>(L, nbt, P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U, pc ? k : 0, isf,
+                              isg, t_part, hist, max_iter, q));
+    RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
+    if (pc && k > 0) {
+      RedJob jt{t_part, nbt, k * R, R, t1, pc->w, nullptr, 1.0, coef, nullptr};
+      DSKI_TRY(launch_reduce(jt, &jr, q));
+      DSKI_TRY(launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part, q));
+    } else {
+      DSKI_TRY(launch_reduce(jr, nullptr, q));
+      if (pc)  // rank-0 preconditioner: M = D
+        DSKI_TRY(launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N, rz_part, q));
+    }
+    k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist,
+                                                  max_iter, fixed_iters);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  };
+  // Bursts of kGraphIters iterations are replayed from a HIP graph captured once
+  // per solve on a side stream (ordered after and before `st` by events); the
+  // first iterations run eagerly, which also sizes every workspace.
+  PcgGraph gr;
+  auto graph_burst = [&](int nrep) -> dski_status {
+    const int par0 = it & 1;
+    if (!gr.exec || gr.par0 != par0) {
+      if (!gr.stream) {
+        DSKI_HIP(hipStreamCreateWithFlags(&gr.stream, hipStreamNonBlocking));
+        DSKI_HIP(hipEventCreateWithFlags(&gr.ev0, hipEventDisableTiming));
+        DSKI_HIP(hipEventCreateWithFlags(&gr.ev1, hipEventDisableTiming));
+      }
+      gr.reset_graph();
+      DSKI_HIP(hipStreamBeginCapture(gr.stream, hipStreamCaptureModeRelaxed));
+      dski_status cr = DSKI_OK;
+      for (int j = 0; j < kGraphIters && cr == DSKI_OK; ++j) cr = iterate((par0 + j) & 1, gr.stream);
+      hipGraph_t g = nullptr;
+      hipError_t ec = hipStreamEndCapture(gr.stream, &g);
+      if (cr < 0) {
+        if (g) (void)hipGraphDestroy(g);
+        return cr;
+      }
+      if (ec != hipSuccess) {
+        set_error("PCG graph capture failed: %s", hipGetErrorString(ec));
+        return DSKI_EHIP;
+      }
+      gr.graph = g;
+      DSKI_HIP(hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0));
+      gr.par0 = par0;
+    }
+    DSKI_HIP(hipEventRecord(gr.ev0, st));
+    DSKI_HIP(hipStreamWaitEvent(gr.stream, gr.ev0, 0));
+    for (int j = 0; j < nrep; ++j) DSKI_HIP(hipGraphLaunch(gr.exec, gr.stream));
+    DSKI_HIP(hipEventRecord(gr.ev1, gr.stream));
+    DSKI_HIP(hipStreamWaitEvent(st, gr.ev1, 0));
+    return DSKI_OK;
+  };
   auto run = [&]() -> dski_status {
     int check = 1;
     while (it < limit) {
       int burst = std::min(check, limit - it);
-      for (int b = 0; b < burst; ++b) {
-        const int par = (it + b) & 1;
-        DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, st));
-        if (shfl)
-          k_pcg_update_shfl<T><<<dim3(nbt, ngs), kBlock, 0, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg,
-                                                                  rr_part, U, k, isf, isg, cgs, t_part, hist,
-                                                                  max_iter);
-        else
-          k_pcg_update<T><<<nbt, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U,
-                                                         k, isf, isg, L.RT, L, t_part, hist, max_iter);
-        RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
-        if (pc && k > 0) {
-          RedJob jt{t_part, nbt, k * R, R, t1, pc->c, nullptr, 1.0, coef, nullptr};
-          DSKI_TRY(launch_reduce(jt, &jr, st));
-          if (shfl) {
-            int nbx = 0;
-            launch_proj_shfl<T>(Rr, N, N, n, R, isf, isg, U, k, coef, t_part, &nbx, st);
-          } else {
-            k_ts_proj<T><<<nbt, kBlock, L.bytes, st>>>(Rr, N, N, n, R, isf, isg, U, k, coef, L.RT, L, t_part);
-          }
-          RedJob j2{t_part, nbt, k * R, R, t2, pc->c, t1, 1.0, coef, nullptr};
-          DSKI_TRY(launch_reduce(j2, nullptr, st));
-          launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part, st);
-        } else {
-          DSKI_TRY(launch_reduce(jr, nullptr, st));
-          if (pc)  // rank-0 preconditioner: M = D
-            launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N,
-                                                 rz_part, st);
-        }
-        k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, st>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr,
-                                                       nbz, hist, max_iter, fixed_iters);
+      int b = 0;
+      if (p->use_graph && burst >= kGraphIters) {
+        const int nrep = burst / kGraphIters;
+        DSKI_TRY(graph_burst(nrep));
+        b = nrep * kGraphIters;
       }
+      for (; b < burst; ++b) DSKI_TRY(iterate((it + b) & 1, st));
       it += burst;
       DSKI_HIP(hipGetLastError());
       DSKI_HIP(hipMemcpyAsync(hflags, s.flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st));

@@ -11,11 +11,11 @@
 // Greedy pivoting on the largest residual diagonal entry, lowest index among
 // exact ties; every step runs on the device (no host round trip per pivot).
 //
-// The preconditioner is kept in square-root form: with G = D^{-1/2} L = U S V^T,
-//   M^{-1} = D^{-1/2} B B D^{-1/2},  B = I - U diag(c) U^T,  c = 1 - (1 + s^2)^{-1/2},
-// which stays positive definite when U is stored in FP32 (B is applied twice),
-// and C = D^{1/2} (I + U diag(sqrt(1 + s^2) - 1) U^T) satisfies C C^T = M.
-// log det M = sum log D_ii + sum log(1 + s_i^2).
+// With G = D^{-1/2} L = U S V^T (Gram matrix of G and its eigen-decomposition),
+//   M^{-1} = D^{-1/2} (I - U diag(s^2 / (1 + s^2)) U^T) D^{-1/2}   (Woodbury),
+//   C = D^{1/2} (I + U diag(sqrt(1 + s^2) - 1) U^T),  C C^T = M,
+//   log det M = sum log D_ii + sum log(1 + s_i^2);
+// U is kept in FP64 so that the applied M^{-1} stays symmetric positive definite.
 #include <cmath>
 #include <cstring>
 
@@ -215,65 +215,63 @@ __global__ void k_gram_partial(const double* __restrict__ L, int N, int n, int k
 }
 
 // U[:, i] = G V[:, i] / sigma_i  (components with sigma_i = 0 are dropped).
-// (Vs holds V with column i divided by sigma_i; read through the cache, it is
-// the same for every thread.)
+// (Vs holds V with column i divided by sigma_i.)  One thread per row, outputs in
+// groups of 16 so that each L entry is read k/16 times.
 __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, double isf, double isg,
-                         const double* __restrict__ sV, float* __restrict__ U,
-                         double* __restrict__ Ud) {
+                         const double* __restrict__ sV, double* __restrict__ U) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   double sc = e < n ? isf : isg;
-  for (int i = 0; i < k; ++i) {
-    double acc = 0.0;
-    for (int l = 0; l < k; ++l) acc += L[(size_t)l * N + e] * sV[l * k + i];
-    U[(size_t)i * N + e] = (float)(acc * sc);
-    Ud[(size_t)i * N + e] = acc * sc;
+  for (int i0 = 0; i0 < k; i0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (int l = 0; l < k; ++l) {
+      const double lv = L[(size_t)l * N + e];
+      const double* vr = sV + (size_t)l * k + i0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i0 + i < k) acc[i] += lv * vr[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i0 + i < k) U[(size_t)(i0 + i) * N + e] = acc[i] * sc;
   }
 }
 
 // ------------------------------------------------------------------ apply
-// Tall-skinny products with the N x k factor U (column-major):
-//   projection  t = U^T v      (k x R; split over row tiles, register-blocked 2 x 4
-//                               outputs per thread from an LDS tile of U and v,
-//                               per-tile partials reduced in a fixed order),
-//   correction  z = post .* (pre .* x - U coef)   (one thread per row, all R
-//                               columns in registers, U read once).
-// With R = 17 columns these products do ~6 flops per byte, below the vector-ALU
-// ridge, so they stay on the vector units.
+// M^{-1} = D^{-1/2} (I - U diag(w) U^T) D^{-1/2},  w = s^2 / (1 + s^2)   (Woodbury,
+// U with orthonormal columns, kept in FP64 so that the operator stays SPD);
+// C = D^{1/2} (I + U diag(sqrt(1 + s^2) - 1) U^T) with C C^T = M.
+// Each application is one projection (row tiles, fixed-order partials), one
+// reduction that forms the coefficients, and one correction pass.
 
 int vec_blocks(int N) { return (N + kBlock - 1) / kBlock; }
 
+int proj_rows(dski_plan p) {
+  static const int rt[3] = {128, 64, 256};
+  return rt[std::min(std::max(p->proj_variant, 0), 2)];
+}
+
 struct PcWork {
   double* partial;  // nblk x k x R
-  double* t1;
-  double* t2;
+  double* t;
   double* coef;
   int nblk;
-  ProjLds L;
+  ProjPlan L;
 };
 
-template <typename T>
 static dski_status pc_work(dski_precond pc, int R, PcWork& w) {
   dski_plan p = pc->plan;
   int k = pc->k;
-  w.L = proj_lds(k, R, sizeof(T));
-  w.nblk = (p->N + w.L.RT - 1) / w.L.RT;
-  size_t np = std::max((size_t)std::max(w.nblk, vec_blocks(p->N)) * k * R, (size_t)vec_blocks(p->N) * R);
-  DSKI_TRY(pc->work.reserve(sizeof(double) * (np + 3 * (size_t)k * R + 64)));
+  w.L = proj_plan(k, R, proj_rows(p));
+  w.nblk = w.L.nblk(p->N);
+  size_t np = std::max((size_t)w.nblk * k * R, (size_t)vec_blocks(p->N) * R);
+  DSKI_TRY(pc->work.reserve(sizeof(double) * (np + 2 * (size_t)k * R + 64)));
   double* base = pc->work.as<double>();
   w.partial = base;
-  w.t1 = base + np;
-  w.t2 = w.t1 + (size_t)k * R;
-  w.coef = w.t2 + (size_t)k * R;
-  return DSKI_OK;
-}
-
-template <typename T>
-static dski_status check_cols(int R) {
-  if (R > kFinalMaxR) {
-    set_error("at most %d columns per preconditioner application", kFinalMaxR);
-    return DSKI_ENOTSUP;
-  }
+  w.t = base + np;
+  w.coef = w.t + (size_t)k * R;
   return DSKI_OK;
 }
 
@@ -293,38 +291,14 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
     }
     return DSKI_OK;
   }
-  const T* U = u_of<T>(pc);
-  if (k == 0) {
-    launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, U, 0, nullptr, Z,
-                                                   ldz, rz_partial, st);
-    DSKI_HIP(hipGetLastError());
-    return DSKI_OK;
-  }
+  if (k == 0)
+    return launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, pc->U, 0, nullptr, Z, ldz, rz_partial, st);
   PcWork w;
-  DSKI_TRY(pc_work<T>(pc, R, w));
-  int nb = w.nblk;
-  // t1 = U^T r',  r' = D^{-1/2} Rm;  coef1 = c .* t1
-  if (p->proj_variant == 1)
-    launch_proj_shfl<T>(Rm, ld, N, p->n, R, isf, isg, U, k, nullptr, w.partial, &nb, st);
-  else
-    k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, nullptr, w.L.RT, w.L,
-                                                    w.partial);
-  DSKI_HIP(hipGetLastError());
-  RedJob j1{w.partial, nb, k * R, R, w.t1, pc->c, nullptr, 1.0, w.coef, nullptr};
-  DSKI_TRY(launch_reduce(j1, nullptr, st));
-  // t2 = U^T (r' - U coef1);  coef2 = c .* (t1 + t2)
-  if (p->proj_variant == 1)
-    launch_proj_shfl<T>(Rm, ld, N, p->n, R, isf, isg, U, k, w.coef, w.partial, &nb, st);
-  else
-    k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(Rm, ld, N, p->n, R, isf, isg, U, k, w.coef, w.L.RT, w.L,
-                                                    w.partial);
-  DSKI_HIP(hipGetLastError());
-  RedJob j2{w.partial, nb, k * R, R, w.t2, pc->c, w.t1, 1.0, w.coef, nullptr};
-  DSKI_TRY(launch_reduce(j2, nullptr, st));
-  // Z = D^{-1/2} (r' - U coef2)
-  launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, U, k, w.coef, Z, ldz, rz_partial, st);
-  DSKI_HIP(hipGetLastError());
-  return DSKI_OK;
+  DSKI_TRY(pc_work(pc, R, w));
+  DSKI_TRY(launch_proj<T>(Rm, ld, N, p->n, R, isf, isg, pc->U, k, w.L, w.partial, st));
+  RedJob j{w.partial, w.nblk, k * R, R, w.t, pc->w, nullptr, 1.0, w.coef, nullptr};
+  DSKI_TRY(launch_reduce(j, nullptr, st));
+  return launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, pc->U, k, w.coef, Z, ldz, rz_partial, st);
 }
 template dski_status precond_apply_tiled<float>(dski_precond, int, const float*, int, float*, int,
                                                 double*, int*, hipStream_t);
@@ -344,27 +318,14 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
     }
     return DSKI_OK;
   }
-  const T* U = u_of<T>(pc);
-  if (k == 0) {
-    launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, U, 0, nullptr,
-                                                   Z, ldz, nullptr, st);
-    DSKI_HIP(hipGetLastError());
-    return DSKI_OK;
-  }
+  if (k == 0)
+    return launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, pc->U, 0, nullptr, Z, ldz, nullptr, st);
   PcWork w;
-  DSKI_TRY(pc_work<T>(pc, R, w));
-  int nb = w.nblk;
-  if (p->proj_variant == 1)
-    launch_proj_shfl<T>(W, ld, N, p->n, R, 1.0, 1.0, U, k, nullptr, w.partial, &nb, st);
-  else
-    k_ts_proj<T><<<w.nblk, kBlock, w.L.bytes, st>>>(W, ld, N, p->n, R, 1.0, 1.0, U, k, nullptr, w.L.RT, w.L,
-                                                    w.partial);
-  DSKI_HIP(hipGetLastError());
-  RedJob j1{w.partial, nb, k * R, R, w.t1, pc->rootc, nullptr, -1.0, w.coef, nullptr};
-  DSKI_TRY(launch_reduce(j1, nullptr, st));
-  launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, U, k, w.coef, Z, ldz, nullptr, st);
-  DSKI_HIP(hipGetLastError());
-  return DSKI_OK;
+  DSKI_TRY(pc_work(pc, R, w));
+  DSKI_TRY(launch_proj<T>(W, ld, N, p->n, R, 1.0, 1.0, pc->U, k, w.L, w.partial, st));
+  RedJob j{w.partial, w.nblk, k * R, R, w.t, pc->rootc, nullptr, -1.0, w.coef, nullptr};
+  DSKI_TRY(launch_reduce(j, nullptr, st));
+  return launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, pc->U, k, w.coef, Z, ldz, nullptr, st);
 }
 template dski_status precond_factor_apply_tiled<float>(dski_precond, int, const float*, int, float*, int,
                                                        hipStream_t);
@@ -376,8 +337,7 @@ static void destroy_pc(dski_precond pc) {
   (void)hipFree(pc->piv_tile);
   (void)hipFree(pc->L);
   (void)hipFree(pc->U);
-  (void)hipFree(pc->Ud);
-  (void)hipFree(pc->c);
+  (void)hipFree(pc->w);
   (void)hipFree(pc->rootc);
   pc->work.release();
   delete pc;
@@ -460,9 +420,8 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     // preconditioner: Gram of G = D^{-1/2} L, eigen-decomposition on the host
     double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
     double logdetD = (double)n * 2.0 * std::log(p->sf) + (double)(N - n) * 2.0 * std::log(p->sg);
-    DSKI_HIP(hipMalloc(&pc->U, sizeof(float) * (size_t)N * std::max(r, 1)));
-    DSKI_HIP(hipMalloc(&pc->Ud, sizeof(double) * (size_t)N * std::max(r, 1)));
-    DSKI_HIP(hipMalloc(&pc->c, sizeof(double) * std::max(r, 1)));
+    DSKI_HIP(hipMalloc(&pc->U, sizeof(double) * (size_t)N * std::max(r, 1)));
+    DSKI_HIP(hipMalloc(&pc->w, sizeof(double) * std::max(r, 1)));
     DSKI_HIP(hipMalloc(&pc->rootc, sizeof(double) * std::max(r, 1)));
     if (r == 0) {
       pc->logdet = logdetD;
@@ -492,7 +451,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     for (int i = 0, pidx = 0; i < r; ++i)
       for (int jj = i; jj < r; ++jj, ++pidx) A[(size_t)i * r + jj] = A[(size_t)jj * r + i] = gram[pidx];
     sym_eig_jacobi(r, A.data(), V.data(), w.data());
-    std::vector<double> Vs((size_t)r * r), c(r), rootc(r);
+    std::vector<double> Vs((size_t)r * r), wd(r), rootc(r);
     double wmax = 0.0;
     for (int i = 0; i < r; ++i) wmax = std::max(wmax, w[i]);
     double ld = logdetD;
@@ -500,7 +459,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
       double s2 = w[i] > 1e-13 * wmax ? w[i] : 0.0;
       double inv = s2 > 0.0 ? 1.0 / std::sqrt(s2) : 0.0;
       for (int l = 0; l < r; ++l) Vs[(size_t)l * r + i] = V[(size_t)l * r + i] * inv;
-      c[i] = 1.0 - 1.0 / std::sqrt(1.0 + s2);
+      wd[i] = s2 / (1.0 + s2);
       rootc[i] = std::sqrt(1.0 + s2) - 1.0;
       ld += std::log1p(s2);
     }
@@ -508,7 +467,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     double* dV = nullptr;
     DSKI_HIP(hipMalloc(&dV, sizeof(double) * (size_t)r * r));
     if (hipMemcpyAsync(dV, Vs.data(), sizeof(double) * r * r, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(pc->c, c.data(), sizeof(double) * r, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(pc->w, wd.data(), sizeof(double) * r, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(pc->rootc, rootc.data(), sizeof(double) * r, hipMemcpyHostToDevice, st) !=
             hipSuccess) {
       (void)hipFree(dV);
@@ -517,7 +476,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
       break;
     }
     k_make_u<<<(N + kBlock - 1) / kBlock, kBlock, 0, st>>>(pc->L, N, n, r, isf, isg,
-                                                                                dV, pc->U, pc->Ud);
+                                                                                dV, pc->U);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(st);
     (void)hipFree(dV);

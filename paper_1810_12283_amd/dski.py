@@ -67,6 +67,7 @@ _SIGS = {
     "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_autotune": (C.c_int, [vp, C.c_int, C.c_int, dp, vp]),
     "dski_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
+    "dski_set_graph": (C.c_int, [vp, C.c_int]),
     "dski_mvm_f64": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_mvm_dtheta_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_permute_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -238,12 +239,16 @@ class Plan:
 
     def autotune(self, R: int, k: int, stream=None) -> dict:
         """Time the kernel variants for this shape and keep the fastest."""
-        t = (C.c_double * 5)()
+        t = (C.c_double * 6)()
         _check(lib().dski_autotune(self._h, int(R), int(k), t, _stream(stream)), "dski_autotune")
-        return {"scatter_us": [t[0], t[1], t[2]], "proj_us": [t[3], t[4]]}
+        return {"scatter_us": [t[0], t[1], t[2]], "proj_us": [t[3], t[4], t[5]]}
 
     def set_variants(self, scatter: int, proj: int):
         _check(lib().dski_set_variants(self._h, int(scatter), int(proj)), "dski_set_variants")
+
+    def set_graph(self, on: bool):
+        """Replay PCG iterations from a captured HIP graph (default) or launch directly."""
+        _check(lib().dski_set_graph(self._h, int(bool(on))), "dski_set_graph")
 
     def set_precision(self, bits: int):
         """Storage precision of the vectors slq_logdet creates (32 or 64)."""

