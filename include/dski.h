@@ -241,7 +241,9 @@ dski_status slq_logdet(dski_plan plan, dski_precond pc, int num_probes, int lanc
  * parameter order) at the plan's current hyper-parameters.  One PCG on
  * [y, z_1..z_t]; log det by SLQ from the same run; the trace terms
  * tr(K~^{-1} dK~) by E[(K~^{-1} z)^T dK~ (M^{-1} z)].  pc NULL: build rank k.
- * y is an N-vector in user order. */
+ * y is an N-vector in user order.  num_probes = 0 gives the data-fit part only
+ * (-y^T alpha / 2 - N log(2 pi) / 2 and its gradient, log det reported as 0),
+ * which a caller combines with its own log det model. */
 dski_status mll_and_grad(dski_plan plan, dski_precond pc, int k, const float* y,
                          int num_probes, uint64_t seed, double tol, int max_iter,
                          double* mll_host, double* grad_host, double* logdet_host,
@@ -263,6 +265,34 @@ dski_status dski_rademacher(uint64_t seed, int col0, int ncols, int N, float* ou
  * (Gauss quadrature of Sec. 2's Lanczos connection).  *ok = 0 if a Ritz value
  * is not positive or the eigen-iteration fails. */
 double dski_lanczos_quad_log(const double* alpha_host, const double* beta_host, int J, int* ok);
+
+/* ---------------------------------------------------------------------------------
+ * Learned log-determinant surrogate (a network of this project, not of the paper):
+ * y = w3 . gelu(W2 gelu(W1 x + b1) + b2) + b3 with the exact GELU, FP32, F inputs,
+ * H units per hidden layer (H <= 128, F <= 16), and forward-mode tangents along
+ * the first J inputs (J <= min(F, 8)).  Parameters are packed row-major:
+ * W1 (H x F), b1 (H), W2 (H x H), b2 (H), w3 (H), b3 (1); H F + H^2 + 3 H + 1 floats.
+ * X is a device B x F row-major batch; y (B), dy (B x J) are device outputs.
+ * Training loss: (1/B) sum_b [(y_b - t_b)^2 + lam sum_j (dy_bj - g_bj)^2]. */
+typedef struct dski_mlp_s* dski_mlp;
+
+/* params_host: the packed parameters (copied).  Errors: DSKI_EINVAL. */
+dski_status mlp_create(dski_mlp* out, int F, int H, int J, const float* params_host, dski_stream stream);
+dski_status mlp_destroy(dski_mlp net);
+dski_status mlp_num_params(dski_mlp net, int* n);
+/* Copies the current parameters and/or the gradient of the last mlp_backward (host, may be NULL). */
+dski_status mlp_get_params(dski_mlp net, float* params_host, float* grad_host);
+/* y = network(X). */
+dski_status mlp_forward(dski_mlp net, int B, const float* X, float* y, dski_stream stream);
+/* y and dy[b, j] = d y_b / d x_bj for j < J (tangent propagation). */
+dski_status mlp_jvp(dski_mlp net, int B, const float* X, float* y, float* dy, dski_stream stream);
+/* Gradient of the training loss with respect to every parameter (kept in the
+ * network for mlp_step); t (B) and g (B x J) are device targets; loss_host may
+ * be NULL.  Deterministic: batch sums in FP64 in a fixed order. */
+dski_status mlp_backward(dski_mlp net, int B, const float* X, const float* t, const float* g, float lam,
+                         double* loss_host, dski_stream stream);
+/* One Adam step (Kingma & Ba 2015) with the gradient of the last mlp_backward. */
+dski_status mlp_step(dski_mlp net, float lr, float beta1, float beta2, float eps, dski_stream stream);
 
 #ifdef __cplusplus
 }

@@ -3,5 +3,5 @@
 The product is ``libdski.so`` (HIP kernels behind the C ABI in
 ``include/dski.h``); ``paper_1810_12283_amd.dski`` is its ctypes binding.
 """
-from .dski import (DSKIError, DskipPlan, MarginalLikelihood, Plan, Precond, lanczos_quad_log, lib, rademacher,  # noqa: F401
+from .dski import (DSKIError, DskipPlan, MarginalLikelihood, Mlp, Plan, Precond, lanczos_quad_log, lib, rademacher,  # noqa: F401
                    version)

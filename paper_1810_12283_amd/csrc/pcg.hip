@@ -213,7 +213,7 @@ static dski_status launch_update(const ProjPlan& L, int nb, const T* P, const T*
   return DSKI_OK;
 }
 
-// beta, history, convergence test, p = z + beta p.  Grid (row chunks of 256, R):
+// beta, history (hist = the beta rows), convergence test, p = z + beta p.  Grid (row chunks of 256, R):
 // every block recomputes its column's beta from the r.z partials (same order);
 // block (0, c) writes the column's next-parity state.
 template <typename T>
@@ -243,7 +243,7 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
       if (blockIdx.x == 0) {
         int it = s.iters[c];
         bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (s.rr[c] <= s.tol2[c] * s.bb[c]);
-        if (hist && it < max_iter) hist[(size_t)R * max_iter + (size_t)c * max_iter + it] = b;
+        if (hist && it < max_iter) hist[(size_t)c * max_iter + it] = b;
         s.iters[c] = it + 1;
         if (done) atomicSub(&s.flags[0], 1);
         s.rz[(1 - par) * R + c] = rzn;
@@ -329,10 +329,11 @@ __global__ void k_x_out(const double* __restrict__ Xd, int N, int R, TO* __restr
       X[(size_t)c * ldx + e] = (TO)Xd[(size_t)c * N + e];
 }
 
-// One PCG on R <= kPcgMaxR columns (history layout [alpha: R x max_iter][beta: R x max_iter]).
+// One PCG on R <= kPcgMaxR columns; alpha of column c at hist[c max_iter + j], beta at
+// hist_b[c max_iter + j] (both may be NULL).
 template <typename T>
 static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, int ldb, T* X, int ldx,
-                             const double* tol_host, int max_iter, int fixed_iters, double* hist,
+                             const double* tol_host, int max_iter, int fixed_iters, double* hist, double* hist_b,
                              PcgResult& res, int res_c0, hipStream_t st, double* X64, int ldx64,
                              const int* verify_mask) {
   const int N = p->N, n = p->n;
@@ -409,7 +410,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
       if (pc)  // rank-0 preconditioner: M = D
         DSKI_TRY(launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N, rz_part, q));
     }
-    k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist,
+    k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist_b,
                                                   max_iter, fixed_iters);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
@@ -570,15 +571,15 @@ dski_status pcg_tiled(dski_plan p, dski_precond pc, int R, const T* B, int ldb, 
   res.relres.assign(R, 0.0);
   res.rz0.assign(R, 0.0);
   if (R <= 0) return DSKI_OK;
-  if (R > kPcgMaxR && alpha_beta) {
-    set_error("PCG with a CG-coefficient history supports at most %d columns per call", kPcgMaxR);
-    return DSKI_ENOTSUP;
-  }
   dski_status worst = DSKI_OK;
+  // columns run in independent groups of at most kPcgMaxR; history layout
+  // [alpha: R x max_iter][beta: R x max_iter] over all R columns
   for (int c0 = 0; c0 < R; c0 += kPcgMaxR) {
     int rg = std::min(kPcgMaxR, R - c0);
+    double* ha = alpha_beta ? alpha_beta + (size_t)c0 * max_iter : nullptr;
+    double* hb = alpha_beta ? alpha_beta + ((size_t)R + c0) * max_iter : nullptr;
     dski_status rc = pcg_group<T>(p, pc, rg, B + (size_t)c0 * ldb, ldb, X ? X + (size_t)c0 * ldx : nullptr, ldx,
-                                  tol_host + c0, max_iter, fixed_iters, alpha_beta, res, c0, st,
+                                  tol_host + c0, max_iter, fixed_iters, ha, hb, res, c0, st,
                                   X64 ? X64 + (size_t)c0 * ldx : nullptr, ldx,
                                   verify_mask ? verify_mask + c0 : nullptr);
     if (rc < 0) return rc;

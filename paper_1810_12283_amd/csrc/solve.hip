@@ -205,11 +205,16 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
       break;
     }
     ProbeRun pr;
-    slq_combine(hab, max_iter, R, 1, t, res, pc->logdet, pr);
-    if (!pr.ok) {
-      set_error("mll_and_grad: SLQ quadrature failed");
-      rc = DSKI_EBREAKDOWN;
-      break;
+    if (t > 0) {
+      slq_combine(hab, max_iter, R, 1, t, res, pc->logdet, pr);
+      if (!pr.ok) {
+        set_error("mll_and_grad: SLQ quadrature failed");
+        rc = DSKI_EBREAKDOWN;
+        break;
+      }
+    } else {  // data-fit part only: no log det term
+      pr.ok = true;
+      pr.logdet = 0.0;
     }
     // data fit y^T alpha; alpha^T alpha and u_i^T v_i on value rows and on gradient rows
     std::vector<double> yal, aa_v, aa_g, uv_v, uv_g;
@@ -270,7 +275,7 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
       double scale = which < d ? 1.0 : 2.0;  // d K_UU / d log s = 2 K_UU
       double tr = 0.0;
       for (int i = 0; i < t; ++i) tr += dots[1 + i];
-      tr /= t;
+      if (t > 0) tr /= t;
       g[which] = scale * (0.5 * dots[0] - 0.5 * tr);
     }
     if (rc < 0) break;
@@ -281,8 +286,8 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
       trg += uv_g[i];
     }
     // dK~/dlog sigma = 2 sigma^2 on the value (gradient) rows
-    g[d + 1] = sf2 * (aa_v[0] - trv / t);
-    g[d + 2] = sg2 * (aa_g[0] - trg / t);
+    g[d + 1] = sf2 * (aa_v[0] - (t > 0 ? trv / t : 0.0));
+    g[d + 2] = sg2 * (aa_g[0] - (t > 0 ? trg / t : 0.0));
     const double log2pi = 1.8378770664093453;
     double mll = -0.5 * (yal[0] + pr.logdet + (double)N * log2pi);
     if (mll_host) *mll_host = mll;
@@ -303,7 +308,7 @@ template <typename T>
 static dski_status mll_user(dski_plan p, dski_precond pc_in, int k, const T* y, int t, uint64_t seed,
                             double tol, int max_iter, double* mll_host, double* grad_host,
                             double* logdet_host, int* iters_host, hipStream_t st) {
-  if (!p || !y || t <= 0 || tol <= 0 || max_iter <= 0 || (!pc_in && k < 0) ||
+  if (!p || !y || t < 0 || tol <= 0 || max_iter <= 0 || (!pc_in && k < 0) ||
       (pc_in && pc_in->plan != p) || p->N == 0) {
     set_error("mll_and_grad: bad arguments");
     return DSKI_EINVAL;

@@ -68,6 +68,14 @@ _SIGS = {
     "dski_autotune": (C.c_int, [vp, C.c_int, C.c_int, dp, vp]),
     "dski_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
     "dski_set_graph": (C.c_int, [vp, C.c_int]),
+    "mlp_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp, vp]),
+    "mlp_destroy": (C.c_int, [vp]),
+    "mlp_num_params": (C.c_int, [vp, ip]),
+    "mlp_get_params": (C.c_int, [vp, vp, vp]),
+    "mlp_forward": (C.c_int, [vp, C.c_int, vp, vp, vp]),
+    "mlp_jvp": (C.c_int, [vp, C.c_int, vp, vp, vp, vp]),
+    "mlp_backward": (C.c_int, [vp, C.c_int, vp, vp, vp, C.c_float, dp, vp]),
+    "mlp_step": (C.c_int, [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
     "dski_mvm_f64": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_mvm_dtheta_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_permute_f64": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -399,6 +407,70 @@ class Precond:
         _check(lib().dski_precond_factor(self._h, _dptr(out), self.plan.N, _stream(stream)),
                "dski_precond_factor")
         return out[: self.rank]
+
+
+class Mlp:
+    """The surrogate network on the device (owns a dski_mlp); parameters packed
+    row-major as W1, b1, W2, b2, w3, b3 (FP32)."""
+
+    def __init__(self, params: np.ndarray, F: int = 8, H: int = 128, J: int = 5, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != H * F + H * H + 3 * H + 1:
+            raise ValueError("packed parameter vector has the wrong length")
+        h = vp()
+        _check(lib().mlp_create(C.byref(h), int(F), int(H), int(J), p.ctypes.data_as(vp), _stream(stream)),
+               "mlp_create")
+        self._h, self.F, self.H, self.J, self.n = h, F, H, J, p.size
+
+    @staticmethod
+    def pack(W1, b1, W2, b2, w3, b3) -> np.ndarray:
+        return np.concatenate([np.ravel(W1), np.ravel(b1), np.ravel(W2), np.ravel(b2), np.ravel(w3),
+                               np.ravel(b3)]).astype(np.float32)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.float32)
+        _check(lib().mlp_get_params(self._h, out.ctypes.data_as(vp), None), "mlp_get_params")
+        return out
+
+    def grad(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.float32)
+        _check(lib().mlp_get_params(self._h, None, out.ctypes.data_as(vp)), "mlp_get_params")
+        return out
+
+    def forward(self, X: torch.Tensor, stream=None) -> torch.Tensor:
+        X = X.contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(lib().mlp_forward(self._h, X.shape[0], _dptr(X), _dptr(y), _stream(stream)), "mlp_forward")
+        return y
+
+    def jvp(self, X: torch.Tensor, stream=None):
+        X = X.contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        dy = torch.empty((X.shape[0], self.J), dtype=torch.float32, device=X.device)
+        _check(lib().mlp_jvp(self._h, X.shape[0], _dptr(X), _dptr(y), _dptr(dy), _stream(stream)), "mlp_jvp")
+        return y, dy
+
+    def backward(self, X: torch.Tensor, t: torch.Tensor, g: torch.Tensor, lam: float = 1.0, stream=None) -> float:
+        X, t, g = X.contiguous(), t.contiguous(), g.contiguous()
+        loss = C.c_double()
+        _check(lib().mlp_backward(self._h, X.shape[0], _dptr(X), _dptr(t), _dptr(g), float(lam), C.byref(loss),
+                                  _stream(stream)), "mlp_backward")
+        return loss.value
+
+    def step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().mlp_step(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),
+               "mlp_step")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def rademacher(seed: int, col0: int, ncols: int, N: int, device="cuda", stream=None) -> torch.Tensor:

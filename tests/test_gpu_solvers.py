@@ -196,7 +196,7 @@ def test_autograd_mll_on_the_implicit_surface():
     y = to_gpu(W.y.astype(np.float32))
     le, ls, lf, lg = W.hypers()
     theta = torch.tensor(np.concatenate([le, [ls, lf, lg]]), dtype=torch.float64, requires_grad=True)
-    mll = dski.MarginalLikelihood.apply(theta, plan, y, 60, 64, SEED, 1e-6, 5000)
+    mll = dski.MarginalLikelihood.apply(theta, plan, y, 60, 64, SEED, 1e-6, 5000)  # 65 columns: 3 PCG groups
     (g,) = torch.autograd.grad(mll, theta)
     direct = plan.mll_and_grad(y, None, k=60, num_probes=64, seed=SEED, tol=1e-6, max_iter=5000)
     assert mll.item() == direct["mll"]
