@@ -1,0 +1,183 @@
+"""Learned log-determinant surrogate and the hyper-parameter fit that uses it.
+
+The network (``dski.Mlp``, FP32, trained and evaluated by the device kernels
+behind ``mlp_*``) maps standardised features
+    [log ell_1 .. log ell_d, log s, log sigma_f, log sigma_g, log n, log h_1 .. log h_d]
+to the standardised value of log det(K~) / n, and its input tangents give the
+gradient with respect to the d + 3 log hyper-parameters.  Training targets come
+from the method itself: the SLQ log determinant and its stochastic trace
+gradient (``mll_and_grad`` with a zero data vector, so only the log det terms
+remain).  During a fit the data-fit part (one PCG column, ``mll_and_grad``
+with zero probes) is exact and the log det comes from the network; every
+``recheck`` evaluations SLQ re-computes the log det, and when the relative
+error exceeds ``fallback_tol`` the fit continues with plain SLQ.
+
+This module only orchestrates device calls (and the 5-parameter L-BFGS on the
+host); every numerical step of the method runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import dski
+
+LOG2PI = math.log(2.0 * math.pi)
+
+
+def logdet_and_grad(plan: dski.Plan, theta: np.ndarray, k: int, num_probes: int, seed: int, tol: float,
+                    max_iter: int = 20000):
+    """SLQ log det K~ and its gradient (d + 3 log hyper-parameters) at theta."""
+    d = plan.d
+    plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
+    zero = torch.zeros((1, plan.N), dtype=torch.float32, device="cuda")
+    res = plan.mll_and_grad(zero, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=max_iter)
+    # with y = 0: mll = -(log det + N log 2 pi) / 2, grad = -(d log det) / 2
+    return res["logdet"], -2.0 * np.asarray(res["grad"])
+
+
+def data_fit_and_grad(plan: dski.Plan, theta: np.ndarray, y: torch.Tensor, k: int, tol: float,
+                      max_iter: int = 20000):
+    """-y^T K~^{-1} y / 2 - N log(2 pi) / 2 and its gradient (one PCG column)."""
+    d = plan.d
+    plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
+    res = plan.mll_and_grad(y, None, k=k, num_probes=0, tol=tol, max_iter=max_iter)
+    return res["mll"], np.asarray(res["grad"])
+
+
+@dataclass
+class Surrogate:
+    net: dski.Mlp
+    mu_x: np.ndarray
+    sd_x: np.ndarray
+    mu_t: float
+    sd_t: float
+    n: int
+    const_feats: np.ndarray          # log n, log h_1 .. log h_d
+    history: list = field(default_factory=list)
+
+    def features(self, theta: np.ndarray) -> np.ndarray:
+        return np.concatenate([np.asarray(theta, dtype=np.float64), self.const_feats])
+
+    def __call__(self, theta: np.ndarray):
+        """(log det, d log det / d theta) from the network."""
+        x = (self.features(theta) - self.mu_x) / self.sd_x
+        X = torch.tensor(x[None, :], dtype=torch.float32, device="cuda")
+        y, dy = self.net.jvp(X)
+        J = len(theta)
+        val = self.n * (self.mu_t + self.sd_t * float(y[0]))
+        grad = self.n * self.sd_t * dy[0, :J].double().cpu().numpy() / self.sd_x[:J]
+        return val, grad
+
+
+def sobol_design(theta_star: np.ndarray, m: int, radius: float, seed: int, ell_min: Optional[np.ndarray] = None):
+    from scipy.stats import qmc
+    u = qmc.Sobol(d=len(theta_star), scramble=True, seed=seed).random(m)
+    th = theta_star[None, :] + radius * (2.0 * u - 1.0)
+    if ell_min is not None:
+        d = len(ell_min)
+        th[:, :d] = np.maximum(th[:, :d], np.log(ell_min)[None, :])
+    return th
+
+
+def training_data(plan: dski.Plan, thetas: np.ndarray, k: int, num_probes: int, seed: int, tol: float,
+                  max_iter: int = 20000, progress=None):
+    T = np.empty(len(thetas))
+    G = np.empty_like(thetas)
+    for i, th in enumerate(thetas):
+        T[i], G[i] = logdet_and_grad(plan, th, k, num_probes, seed, tol, max_iter)
+        if progress:
+            progress(i, T[i])
+    return T, G
+
+
+def train(thetas: np.ndarray, logdets: np.ndarray, grads: np.ndarray, n: int, h: np.ndarray, steps: int = 2000,
+          lr: float = 2e-3, lam: float = 1.0, hidden: int = 128, seed: int = 0) -> Surrogate:
+    """Fit the network to log det / n and its gradient with full-batch Adam on the device."""
+    J = thetas.shape[1]
+    const = np.concatenate([[math.log(n)], np.log(h)])
+    Xf = np.concatenate([thetas, np.repeat(const[None, :], len(thetas), axis=0)], axis=1)
+    F = Xf.shape[1]
+    mu_x = Xf.mean(axis=0)
+    sd_x = Xf.std(axis=0)
+    sd_x[sd_x == 0] = 1.0
+    t = logdets / n
+    mu_t, sd_t = float(t.mean()), float(t.std() or 1.0)
+    X = (Xf - mu_x) / sd_x
+    ts = (t - mu_t) / sd_t
+    gs = (grads / n) * sd_x[None, :J] / sd_t
+    r = np.random.default_rng(seed)
+    W1 = r.standard_normal((hidden, F)) * math.sqrt(2.0 / F)
+    W2 = r.standard_normal((hidden, hidden)) * math.sqrt(2.0 / hidden)
+    w3 = r.standard_normal(hidden) * math.sqrt(1.0 / hidden)
+    net = dski.Mlp(dski.Mlp.pack(W1, np.zeros(hidden), W2, np.zeros(hidden), w3, np.zeros(1)), F=F, H=hidden, J=J)
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    td = torch.tensor(ts, dtype=torch.float32, device="cuda")
+    gd = torch.tensor(gs, dtype=torch.float32, device="cuda")
+    hist = []
+    for s in range(steps):
+        loss = net.backward(Xd, td, gd, lam)
+        net.step(lr=lr)
+        if s % 100 == 0 or s == steps - 1:
+            hist.append((s, loss))
+    return Surrogate(net, mu_x, sd_x, mu_t, sd_t, n, const, hist)
+
+
+@dataclass
+class FitResult:
+    theta: np.ndarray
+    mll: float
+    evals: int
+    seconds: float
+    fell_back: bool
+    rechecks: list
+
+
+def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes: int, seed: int, tol: float,
+        surrogate: Optional[Surrogate] = None, recheck: int = 10, fallback_tol: float = 1e-3,
+        max_evals: int = 60, gtol: float = 1e-5) -> FitResult:
+    """Maximise the marginal likelihood over the log hyper-parameters with L-BFGS.
+
+    With a surrogate: mll = data-fit part (exact) - log det (network) / 2, with
+    SLQ re-checks every `recheck` evaluations and a fall-back to plain SLQ when
+    the relative log det error exceeds `fallback_tol`."""
+    from scipy.optimize import minimize
+
+    state = {"evals": 0, "fallback": surrogate is None, "rechecks": []}
+    t0 = time.perf_counter()
+
+    def objective(theta):
+        state["evals"] += 1
+        if state["fallback"]:
+            d = plan.d
+            plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
+            res = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=20000)
+            return -res["mll"], -np.asarray(res["grad"])
+        dfit, dgrad = data_fit_and_grad(plan, theta, y, k, tol)
+        ld, ldg = surrogate(theta)
+        if state["evals"] % recheck == 0:
+            ld_slq, _ = logdet_and_grad(plan, theta, k, num_probes, seed, tol)
+            err = abs(ld - ld_slq) / abs(ld_slq)
+            state["rechecks"].append((state["evals"], ld, ld_slq, err))
+            if err > fallback_tol:
+                state["fallback"] = True
+                ld, ldg = logdet_and_grad(plan, theta, k, num_probes, seed, tol)
+        mll = dfit - 0.5 * ld
+        grad = dgrad - 0.5 * ldg
+        return -mll, -grad
+
+    res = minimize(objective, np.asarray(theta0, dtype=np.float64), jac=True, method="L-BFGS-B",
+                   options={"maxfun": max_evals, "gtol": gtol})
+    # final value with the full method at the optimum
+    d = plan.d
+    th = res.x
+    plan.set_hypers(th[:d], th[d], th[d + 1], th[d + 2])
+    final = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=20000)
+    torch.cuda.synchronize()
+    return FitResult(th, final["mll"], state["evals"], time.perf_counter() - t0, state["fallback"],
+                     state["rechecks"])
