@@ -162,15 +162,21 @@ dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int
 /* Times the interchangeable kernel variants for R right-hand sides and
  * preconditioner rank k on this plan's shape (scatter: LDS node tiles / direct
  * one column per thread / direct two columns per thread; preconditioner
- * projection: row tiles of 128 / 64 / 256 rows per work-group) and keeps the
- * fastest of each.  All scatter variants give bitwise-identical results; the
- * projections are equal up to summation order.  times_host (6 entries, may be
- * NULL) receives the measured microseconds in that order (scatter entries are
- * 0 for a D-SKIP plan).  1 <= R <= 32, 0 <= k <= 256. */
+ * projection: row tiles of 128 / 64 / 256 rows per work-group; K_UU factor of
+ * each axis: circulant FFT / dense Toeplitz product on the FP64 matrix cores)
+ * and keeps the fastest of each.  All scatter variants give bitwise-identical
+ * results; projections and K_UU variants agree up to rounding.  times_host
+ * (12 entries, may be NULL) receives the measured microseconds: scatter (3),
+ * projection (3), then FFT and dense for axes 0, 1, 2 (scatter and K_UU
+ * entries are 0 for a D-SKIP plan).  1 <= R <= 32, 0 <= k <= 256. */
 dski_status dski_autotune(dski_plan plan, int R, int k, double* times_host, dski_stream stream);
 
 /* Select the variants directly (scatter 0..2, projection 0..2). */
 dski_status dski_set_variants(dski_plan plan, int scatter_variant, int proj_variant);
+
+/* K_UU factor of one axis: 0 circulant FFT, 1 dense Toeplitz product on the
+ * matrix cores (grid size <= 448 on that axis; larger axes keep the FFT). */
+dski_status dski_set_kuu_variant(dski_plan plan, int axis, int variant);
 
 /* PCG launch mode: 1 (default) replays bursts of 8 iterations from a HIP graph
  * captured once per solve on a side stream (ordered with the caller's stream

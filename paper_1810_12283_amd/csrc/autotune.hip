@@ -12,6 +12,8 @@
 
 namespace dski {
 
+constexpr int kTuneTimes = 6 + 2 * DSKI_MAXD;
+
 __global__ void k_fill_pm1(float* __restrict__ out, size_t len, uint64_t seed) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
     uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
@@ -66,7 +68,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
   double* part = coef + (size_t)std::max(k, 1) * R;
   k_fill_pm1<<<1024, 256, 0, st>>>(V, nv, 12345);
   DSKI_HIP(hipMemsetAsync(coef, 0, sizeof(double) * (size_t)std::max(k, 1) * R, st));
-  double t[6] = {0, 0, 0, 0, 0, 0};
+  double t[kTuneTimes] = {0};
   // scatter variants (D-SKI plans only)
   int best_s = 0;
   if (p->kind == 0) DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
@@ -77,6 +79,15 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
     if (t[v] < t[best_s]) best_s = v;
   }
   p->scatter_variant = best_s;
+  // K_UU per axis: FFT or dense matrix-core product (on the scattered grid)
+  for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
+    int best = 0;
+    for (int v = 0; v < 2; ++v) {
+      DSKI_TRY(time_us([&]() { return kuu_axis(p, R, G, st, -1, a, v); }, reps, st, &t[6 + 2 * a + v]));
+      if (t[6 + 2 * a + v] < t[6 + 2 * a + best]) best = v;
+    }
+    p->kuu_variant[a] = best;
+  }
   // projection row tiles (128, 64, 256 rows per work-group) on a dummy FP64 factor
   int best_p = 0;
   if (k > 0) {
@@ -98,7 +109,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
   DSKI_HIP(hipStreamSynchronize(st));
   buf.release();
   if (times_host)
-    for (int i = 0; i < 6; ++i) times_host[i] = t[i];
+    for (int i = 0; i < kTuneTimes; ++i) times_host[i] = t[i];
   return DSKI_OK;
 }
 
@@ -118,5 +129,14 @@ extern "C" dski_status dski_set_graph(dski_plan p, int on) {
     return DSKI_EINVAL;
   }
   p->use_graph = on;
+  return DSKI_OK;
+}
+
+extern "C" dski_status dski_set_kuu_variant(dski_plan p, int axis, int variant) {
+  if (!p || p->kind != 0 || axis < 0 || axis >= p->d || variant < 0 || variant > 1) {
+    set_error("dski_set_kuu_variant: bad arguments");
+    return DSKI_EINVAL;
+  }
+  p->kuu_variant[axis] = variant;
   return DSKI_OK;
 }

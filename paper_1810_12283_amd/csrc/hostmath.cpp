@@ -58,6 +58,13 @@ int sym_eig_jacobi(int k, double* A, double* V, double* w) {
 // accumulates only the first row of the eigenvector matrix (Golub-Welsch):
 // the Ritz values theta_k and weights z_k^2 give sum_k z_k^2 log theta_k.
 // *ok = 0 if a Ritz value is not positive or the iteration fails.
+// sqrt(a^2 + b^2) without the cost of std::hypot where no overflow can occur
+static inline double fast_hypot(double a, double b) {
+  const double m = std::fmax(std::fabs(a), std::fabs(b));
+  if (m > 1e150 || m < 1e-150) return std::hypot(a, b);
+  return std::sqrt(a * a + b * b);
+}
+
 double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok) {
   *ok = 1;
   if (J <= 0) {
@@ -85,7 +92,7 @@ double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok) {
         return 0.0;
       }
       double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
+      double r = fast_hypot(g, 1.0);
       g = d[m] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
       double s = 1.0, c = 1.0, p = 0.0;
       int i;
@@ -93,7 +100,7 @@ double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok) {
       for (i = m - 1; i >= l; --i) {
         double f = s * e[i];
         double b = c * e[i];
-        r = std::hypot(f, g);
+        r = fast_hypot(f, g);
         e[i + 1] = r;
         if (r == 0.0) {
           d[i + 1] -= p;

@@ -97,6 +97,7 @@ struct dski_plan_s {
   int scatter_variant = 0;     // 0 LDS node tiles, 1 direct 1 column/thread, 2 direct 2 columns/thread
   int proj_variant = 0;        // rows per projection tile: 0 -> 128, 1 -> 64, 2 -> 256
   int use_graph = 1;           // PCG bursts replayed from a captured HIP graph
+  int kuu_variant[DSKI_MAXD] = {0, 0, 0};  // per axis: 0 FFT, 1 dense matrix-core product
 };
 
 struct dski_precond_s {
@@ -118,6 +119,7 @@ constexpr int kBlock = 256;
 // --- plan / grid ------------------------------------------------------------------
 // T is the storage type of N-vectors (float or double); grids are FP64.
 dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich = -1);
+dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, int a, int variant);
 template <typename T>
 dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st);
 template <typename T>

@@ -671,27 +671,156 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   }
 }
 
+// Dense Toeplitz product along one axis on the FP64 matrix cores: for 16 grid
+// lines at a time,  Y (m x 16) = T (m x m) X,  T[a][b] = c(|a - b|) with
+// c(k) = scale * col[k] (and, for the length-scale derivative, times (k h / ell)^2).
+// The 16 lines are staged in LDS (rows padded to a multiple of 4 with zeros);
+// each wavefront owns row tiles of 16 and accumulates over b in steps of 4 with
+// v_mfma_f64_16x16x4f64 (operands: lane l holds T[a0 + l%16][b0 + l/16] and
+// X[b0 + l/16][l%16]; the 16 x 16 result sits in 4 doubles per lane,
+// row 4 (l/16) + r, column l%16), two accumulators over alternating steps.
+// Results go back through LDS so that the stores follow the memory layout.
+// Exact up to rounding; O(m^2) per line against O(L log L) for the FFT, which
+// the per-axis tuner weighs.  m <= kDenseMaxM.
+typedef double dski_dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kDenseMaxM = 448;
+constexpr int kDenseMaxTiles = (kDenseMaxM + 63) / 64;  // row tiles per wavefront
+
+__global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, long long nlines, int m,
+                                                       long long inner, const double* __restrict__ col,
+                                                       double scale, int deriv, double h_over_ell) {
+  extern __shared__ double smem_d[];
+  __shared__ long long s_base[16];
+  const int mp = (m + 3) & ~3;
+  double* sX = smem_d;               // mp x 16
+  double* scol = smem_d + (size_t)mp * 16;  // m
+  const long long line0 = (long long)blockIdx.x * 16;
+  for (int k = threadIdx.x; k < m; k += 256) {
+    double v = col[k] * scale;
+    if (deriv) {
+      const double t = (double)k * h_over_ell;
+      v *= t * t;
+    }
+    scol[k] = v;
+  }
+  if (threadIdx.x < 16) {
+    const long long line = line0 + threadIdx.x;
+    s_base[threadIdx.x] = line < nlines ? (line / inner) * ((long long)m * inner) + line % inner : -1;
+  }
+  __syncthreads();
+  const int tot = mp * 16;
+  for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = f0 + 256 * u;
+      int l, bb;
+      if (inner > 1) {
+        l = f % 16;
+        bb = f / 16;
+      } else {
+        bb = f % mp;
+        l = f / mp;
+      }
+      const long long base = f < tot ? s_base[l] : -1;
+      v[u] = (base >= 0 && bb < m) ? G[base + (long long)bb * inner] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = f0 + 256 * u;
+      if (f < tot) {
+        const int l = inner > 1 ? f % 16 : f / mp;
+        const int bb = inner > 1 ? f / 16 : f % mp;
+        sX[bb * 16 + l] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ntiles = (m + 15) / 16;
+  dski_dbl4 res[kDenseMaxTiles];
+#pragma unroll
+  for (int q = 0; q < kDenseMaxTiles; ++q) {
+    const int tile = wv + 4 * q;
+    dski_dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    if (tile < ntiles) {
+      const int a = tile * 16 + r16;
+      int k0 = 0;
+      for (; k0 + 8 <= mp; k0 += 8) {
+        const int b0 = k0 + kq, b1 = k0 + 4 + kq;
+        const double a0v = (a < m && b0 < m) ? scol[a > b0 ? a - b0 : b0 - a] : 0.0;
+        const double a1v = (a < m && b1 < m) ? scol[a > b1 ? a - b1 : b1 - a] : 0.0;
+        const double x0 = sX[b0 * 16 + r16];
+        const double x1 = sX[b1 * 16 + r16];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0v, x0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1v, x1, acc1, 0, 0, 0);
+      }
+      if (k0 < mp) {
+        const int b0 = k0 + kq;
+        const double a0v = (a < m && b0 < m) ? scol[a > b0 ? a - b0 : b0 - a] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0v, sX[b0 * 16 + r16], acc0, 0, 0, 0);
+      }
+    }
+    res[q] = acc0 + acc1;
+  }
+  __syncthreads();  // every wavefront has read sX
+#pragma unroll
+  for (int q = 0; q < kDenseMaxTiles; ++q) {
+    const int tile = wv + 4 * q;
+    if (tile < ntiles) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = tile * 16 + 4 * kq + r;
+        if (a < m) sX[a * 16 + r16] = res[q][r];
+      }
+    }
+  }
+  __syncthreads();
+  const int totm = m * 16;
+  for (int f = threadIdx.x; f < totm; f += 256) {
+    const int l = inner > 1 ? f % 16 : f / m;
+    const int bb = inner > 1 ? f / 16 : f % m;
+    const long long base = s_base[l];
+    if (base >= 0) G[base + (long long)bb * inner] = sX[bb * 16 + l];
+  }
+}
+
+// K_UU factor of one axis (stride `inner`) for R columns, FFT (variant 0) or
+// dense matrix-core product (variant 1, m <= kDenseMaxM).
+dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, int a, int variant) {
+  const Axis& A = p->ax[a];
+  long long inner = 1;
+  for (int b = a + 1; b < p->d; ++b) inner *= p->ax[b].m;
+  const long long nlines = (long long)R * (p->M / A.m);
+  if (variant == 1 && A.m <= kDenseMaxM) {
+    const int mp = (A.m + 3) & ~3;
+    const size_t sh = sizeof(double) * ((size_t)mp * 16 + A.m);
+    const double scale = a == 0 ? p->s * p->s : 1.0;
+    k_toeplitz_mfma<<<(unsigned)((nlines + 15) / 16), 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale,
+                                                                     a == dwhich ? 1 : 0, A.h / p->ell[a]);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  }
+  const double* spec = (a == dwhich) ? A.dspec : A.spec;
+  const double2* tw = reinterpret_cast<const double2*>(A.twiddle);
+  const int L = A.L;
+  if (L < 8 || L > 2048) {
+    set_error("FFT length %d not supported (grid size per axis 4..1024)", L);
+    return DSKI_ENOTSUP;
+  }
+  const int ppb = 256 / (L / 8);
+  const size_t sh = sizeof(double2) * ((size_t)ppb * L + L) + (L <= 1024 ? sizeof(double) * L : 0);
+  const long long blocks = (nlines + 2 * ppb - 1) / (2 * ppb);
+  k_toeplitz<<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
 // G <- K_UU G for R columns; dwhich = p (0..d-1) uses d T_p / dlog ell_p on axis p.
 dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich) {
   if (R <= 0) return DSKI_OK;
-  long long inner = p->M;
-  for (int a = 0; a < p->d; ++a) {
-    const Axis& A = p->ax[a];
-    inner /= A.m;
-    long long nlines = (long long)R * (p->M / A.m);
-    const double* spec = (a == dwhich) ? A.dspec : A.spec;
-    const double2* tw = reinterpret_cast<const double2*>(A.twiddle);
-    int L = A.L;
-    if (L < 8 || L > 2048) {
-      set_error("FFT length %d not supported (grid size per axis 4..1024)", L);
-      return DSKI_ENOTSUP;
-    }
-    int ppb = 256 / (L / 8);
-    size_t sh = sizeof(double2) * ((size_t)ppb * L + L) + (L <= 1024 ? sizeof(double) * L : 0);
-    long long blocks = (nlines + 2 * ppb - 1) / (2 * ppb);
-    k_toeplitz<<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
-    DSKI_HIP(hipGetLastError());
-  }
+  for (int a = 0; a < p->d; ++a) DSKI_TRY(kuu_axis(p, R, G, st, dwhich, a, p->kuu_variant[a]));
   return DSKI_OK;
 }
 

@@ -11,6 +11,7 @@
 // the derivative spectrum on axis p (or 2 K_UU), so the products reduce to dot
 // products of scattered grids; for the noise levels it is diagonal.
 #include <cmath>
+#include <thread>
 
 #include "internal.h"
 
@@ -82,18 +83,34 @@ static void slq_combine(const std::vector<double>& ab, int max_iter, int R, int 
                         const PcgResult& res, double logdetM, ProbeRun& out) {
   out.quad.assign(t, 0.0);
   out.weight.assign(t, 0.0);
-  double mean = 0.0;
   std::vector<double> vals(t);
-  for (int i = 0; i < t; ++i) {
-    int c = col0 + i;
-    int J = std::min(res.iters[c], max_iter);
+  std::vector<int> okv(t, 1);
+  // one Gauss quadrature per probe (O(J^2) each): probes spread over host threads
+  auto work = [&](int i) {
+    const int c = col0 + i;
+    const int J = std::min(res.iters[c], max_iter);
     int ok = 0;
-    double q = gauss_quad_log(ab.data() + (size_t)c * max_iter, ab.data() + (size_t)R * max_iter + (size_t)c * max_iter,
-                              J, &ok);
-    if (!ok) out.ok = false;
+    const double q = gauss_quad_log(ab.data() + (size_t)c * max_iter,
+                                    ab.data() + (size_t)R * max_iter + (size_t)c * max_iter, J, &ok);
+    okv[i] = ok;
     out.quad[i] = q;
     out.weight[i] = res.rz0[c];
     vals[i] = q * res.rz0[c];
+  };
+  const int nth = std::max(1, std::min(t, (int)std::thread::hardware_concurrency()));
+  if (nth <= 1) {
+    for (int i = 0; i < t; ++i) work(i);
+  } else {
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nth; ++w)
+      pool.emplace_back([&, w]() {
+        for (int i = w; i < t; i += nth) work(i);
+      });
+    for (auto& th : pool) th.join();
+  }
+  double mean = 0.0;
+  for (int i = 0; i < t; ++i) {
+    if (!okv[i]) out.ok = false;
     mean += vals[i];
   }
   mean /= std::max(t, 1);

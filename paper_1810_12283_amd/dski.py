@@ -68,6 +68,7 @@ _SIGS = {
     "dski_autotune": (C.c_int, [vp, C.c_int, C.c_int, dp, vp]),
     "dski_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
     "dski_set_graph": (C.c_int, [vp, C.c_int]),
+    "dski_set_kuu_variant": (C.c_int, [vp, C.c_int, C.c_int]),
     "mlp_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp, vp]),
     "mlp_destroy": (C.c_int, [vp]),
     "mlp_num_params": (C.c_int, [vp, ip]),
@@ -247,12 +248,17 @@ class Plan:
 
     def autotune(self, R: int, k: int, stream=None) -> dict:
         """Time the kernel variants for this shape and keep the fastest."""
-        t = (C.c_double * 6)()
+        t = (C.c_double * 12)()
         _check(lib().dski_autotune(self._h, int(R), int(k), t, _stream(stream)), "dski_autotune")
-        return {"scatter_us": [t[0], t[1], t[2]], "proj_us": [t[3], t[4], t[5]]}
+        return {"scatter_us": [t[0], t[1], t[2]], "proj_us": [t[3], t[4], t[5]],
+                "kuu_us": [[t[6 + 2 * a], t[7 + 2 * a]] for a in range(min(self.d, 3))]}
 
     def set_variants(self, scatter: int, proj: int):
         _check(lib().dski_set_variants(self._h, int(scatter), int(proj)), "dski_set_variants")
+
+    def set_kuu_variant(self, axis: int, variant: int):
+        """K_UU factor of one axis: 0 FFT, 1 dense matrix-core product."""
+        _check(lib().dski_set_kuu_variant(self._h, int(axis), int(variant)), "dski_set_kuu_variant")
 
     def set_graph(self, on: bool):
         """Replay PCG iterations from a captured HIP graph (default) or launch directly."""

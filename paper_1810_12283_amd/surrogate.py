@@ -140,12 +140,14 @@ class FitResult:
 
 def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes: int, seed: int, tol: float,
         surrogate: Optional[Surrogate] = None, recheck: int = 10, fallback_tol: float = 1e-3,
-        max_evals: int = 60, gtol: float = 1e-5) -> FitResult:
+        max_evals: int = 60, gtol: float = 1e-5, bounds=None) -> FitResult:
     """Maximise the marginal likelihood over the log hyper-parameters with L-BFGS.
 
     With a surrogate: mll = data-fit part (exact) - log det (network) / 2, with
     SLQ re-checks every `recheck` evaluations and a fall-back to plain SLQ when
-    the relative log det error exceeds `fallback_tol`."""
+    the relative log det error exceeds `fallback_tol`.  `bounds` (a list of
+    (lo, hi) per log hyper-parameter) keeps the search inside the region the
+    surrogate was trained on."""
     from scipy.optimize import minimize
 
     state = {"evals": 0, "fallback": surrogate is None, "rechecks": []}
@@ -171,7 +173,7 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
         grad = dgrad - 0.5 * ldg
         return -mll, -grad
 
-    res = minimize(objective, np.asarray(theta0, dtype=np.float64), jac=True, method="L-BFGS-B",
+    res = minimize(objective, np.asarray(theta0, dtype=np.float64), jac=True, method="L-BFGS-B", bounds=bounds,
                    options={"maxfun": max_evals, "gtol": gtol})
     # final value with the full method at the optimum
     d = plan.d

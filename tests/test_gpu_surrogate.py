@@ -1,8 +1,8 @@
 """The learned log-det surrogate end to end on a reduced terrain problem
 (n = 2,000, 60 x 60 grid, 64 training points within 0.5 log-units): training targets from the device SLQ, training with
 the device Adam kernels, accuracy on fresh Sobol points, and an L-BFGS fit
-with the surrogate (SLQ re-check every 10 evaluations, fall-back above 1e-3)
-against the same fit with plain SLQ: equal final marginal likelihood within
+with the surrogate (SLQ re-check every 10 evaluations, fall-back above 1e-3),
+bounded to the trained region, against the same fit with plain SLQ: equal final marginal likelihood within
 1e-3 relative, and what the surrogate saves per evaluation."""
 import time
 
@@ -48,9 +48,10 @@ def test_surrogate_trains_and_drives_the_fit():
     # fits from the same start
     y = torch.tensor(W.y.astype(np.float32), device="cuda")[None, :].contiguous()
     theta0 = th_star + 0.2
-    plain = sg.fit(plan, y, theta0, k, t, SEED, tol, surrogate=None, max_evals=20)
+    box = [(a - 0.45, a + 0.45) for a in th_star]  # inside the trained region
+    plain = sg.fit(plan, y, theta0, k, t, SEED, tol, surrogate=None, max_evals=40, bounds=box)
     say("  plain fit done", round(plain.seconds, 2))
-    withs = sg.fit(plan, y, theta0, k, t, SEED, tol, surrogate=S, max_evals=20)
+    withs = sg.fit(plan, y, theta0, k, t, SEED, tol, surrogate=S, max_evals=40, bounds=box)
     say("  plain: mll", plain.mll, "evals", plain.evals, "s", round(plain.seconds, 2))
     say("  surrogate: mll", withs.mll, "evals", withs.evals, "s", round(withs.seconds, 2), "fell back", withs.fell_back,
         "rechecks", withs.rechecks)
