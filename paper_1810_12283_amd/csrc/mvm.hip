@@ -677,8 +677,9 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
 // The 16 lines are staged in LDS (rows padded to a multiple of 4 with zeros);
 // each wavefront owns row tiles of 16 and accumulates over b in steps of 4 with
 // v_mfma_f64_16x16x4f64 (operands: lane l holds T[a0 + l%16][b0 + l/16] and
-// X[b0 + l/16][l%16]; the 16 x 16 result sits in 4 doubles per lane,
-// row 4 (l/16) + r, column l%16), two accumulators over alternating steps.
+// X[b0 + l/16][l%16]; the 16 x 16 result sits in 4 doubles per lane: register r
+// of lane l is row l/16 + 4 r, column l%16), two accumulators over alternating
+// steps.
 // Results go back through LDS so that the stores follow the memory layout.
 // Exact up to rounding; O(m^2) per line against O(L log L) for the FFT, which
 // the per-axis tuner weighs.  m <= kDenseMaxM.
@@ -771,7 +772,7 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
     if (tile < ntiles) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = tile * 16 + 4 * kq + r;
+        const int a = tile * 16 + kq + 4 * r;
         if (a < m) sX[a * 16 + r16] = res[q][r];
       }
     }
