@@ -748,19 +748,25 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
     if (tile < ntiles) {
       const int a = tile * 16 + r16;
       int k0 = 0;
-      for (; k0 + 8 <= mp; k0 += 8) {
-        const int b0 = k0 + kq, b1 = k0 + 4 + kq;
-        const double a0v = (a < m && b0 < m) ? scol[a > b0 ? a - b0 : b0 - a] : 0.0;
-        const double a1v = (a < m && b1 < m) ? scol[a > b1 ? a - b1 : b1 - a] : 0.0;
-        const double x0 = sX[b0 * 16 + r16];
-        const double x1 = sX[b1 * 16 + r16];
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0v, x0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1v, x1, acc1, 0, 0, 0);
+      // operands of 8 steps read from LDS before the first of their 8 products
+      for (; k0 + 32 <= mp; k0 += 32) {
+        double av[8], xv[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int b = k0 + 4 * s + kq;
+          av[s] = (a < m && b < m) ? scol[a > b ? a - b : b - a] : 0.0;
+          xv[s] = sX[b * 16 + r16];
+        }
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], xv[s], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], xv[s + 1], acc1, 0, 0, 0);
+        }
       }
-      if (k0 < mp) {
-        const int b0 = k0 + kq;
-        const double a0v = (a < m && b0 < m) ? scol[a > b0 ? a - b0 : b0 - a] : 0.0;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0v, sX[b0 * 16 + r16], acc0, 0, 0, 0);
+      for (; k0 < mp; k0 += 4) {
+        const int b = k0 + kq;
+        const double av = (a < m && b < m) ? scol[a > b ? a - b : b - a] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sX[b * 16 + r16], acc0, 0, 0, 0);
       }
     }
     res[q] = acc0 + acc1;
