@@ -678,8 +678,8 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
 // each wavefront owns row tiles of 16 and accumulates over b in steps of 4 with
 // v_mfma_f64_16x16x4f64 (operands: lane l holds T[a0 + l%16][b0 + l/16] and
 // X[b0 + l/16][l%16]; the 16 x 16 result sits in 4 doubles per lane: register r
-// of lane l is row l/16 + 4 r, column l%16), two accumulators over alternating
-// steps.
+// of lane l is row l/16 + 4 r, column l%16); the row tiles of a wavefront run
+// as independent accumulator chains.
 // Results go back through LDS so that the stores follow the memory layout.
 // Exact up to rounding; O(m^2) per line against O(L log L) for the FFT, which
 // the per-axis tuner weighs.  m <= kDenseMaxM.
@@ -740,36 +740,27 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r16 = lane & 15, kq = lane >> 4;
   const int ntiles = (m + 15) / 16;
+  // all row tiles of this wavefront advance together: independent accumulator
+  // chains that share the X operand of each step
   dski_dbl4 res[kDenseMaxTiles];
+  int arow[kDenseMaxTiles];
 #pragma unroll
   for (int q = 0; q < kDenseMaxTiles; ++q) {
-    const int tile = wv + 4 * q;
-    dski_dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    if (tile < ntiles) {
-      const int a = tile * 16 + r16;
-      int k0 = 0;
-      // operands of 8 steps read from LDS before the first of their 8 products
-      for (; k0 + 32 <= mp; k0 += 32) {
-        double av[8], xv[8];
+    res[q] = dski_dbl4{0.0, 0.0, 0.0, 0.0};
+    arow[q] = (wv + 4 * q) * 16 + r16;  // row of T (>= m for padding or absent tiles)
+  }
+  const int nq = (ntiles - wv + 3) / 4;  // tiles of this wavefront
+  for (int k0 = 0; k0 < mp; k0 += 4) {
+    const int b = k0 + kq;
+    const double xv = sX[b * 16 + r16];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int b = k0 + 4 * s + kq;
-          av[s] = (a < m && b < m) ? scol[a > b ? a - b : b - a] : 0.0;
-          xv[s] = sX[b * 16 + r16];
-        }
-#pragma unroll
-        for (int s = 0; s < 8; s += 2) {
-          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], xv[s], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], xv[s + 1], acc1, 0, 0, 0);
-        }
-      }
-      for (; k0 < mp; k0 += 4) {
-        const int b = k0 + kq;
+    for (int q = 0; q < kDenseMaxTiles; ++q) {
+      if (q < nq) {
+        const int a = arow[q];
         const double av = (a < m && b < m) ? scol[a > b ? a - b : b - a] : 0.0;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sX[b * 16 + r16], acc0, 0, 0, 0);
+        res[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, res[q], 0, 0, 0);
       }
     }
-    res[q] = acc0 + acc1;
   }
   __syncthreads();  // every wavefront has read sX
 #pragma unroll

@@ -106,24 +106,28 @@ __device__ __forceinline__ void tile_project(const double* __restrict__ U, int N
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[q][a][j] = 0.0;
   }
-  for (int s0 = 0; s0 < rn; s0 += SUBR) {
-    const int sn = min(SUBR, rn - s0);
-    __syncthreads();  // previous sub-tile consumed
-    const int tot = SUBR * KP;
-    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-      double v[4];
+  // U sub-tiles: each thread holds its share (<= 16 values, SUBR KP <= 4096) of
+  // the next sub-tile in registers while the current one is used from LDS
+  const int tot = SUBR * KP;
+  double cur[16], nxt[16];
+  auto load_sub = [&](int s0, double (&v)[16]) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        const int i = f / SUBR, r = f % SUBR;
-        v[u] = (f < tot && i < k && r < sn) ? U[(size_t)i * N + e0 + s0 + r] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        if (f < tot) sU[(f % SUBR) * KP + f / SUBR] = v[u];
-      }
+    for (int u = 0; u < 16; ++u) {
+      const int f = threadIdx.x + 256 * u;
+      const int i = f / SUBR, r = f % SUBR;
+      v[u] = (f < tot && i < k && s0 + r < rn) ? U[(size_t)i * N + e0 + s0 + r] : 0.0;
     }
+  };
+  load_sub(0, cur);
+  for (int s0 = 0; s0 < rn; s0 += SUBR) {
+    __syncthreads();  // previous sub-tile consumed
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int f = threadIdx.x + 256 * u;
+      if (f < tot) sU[(f % SUBR) * KP + f / SUBR] = cur[u];
+    }
+    const bool more = s0 + SUBR < rn;
+    if (more) load_sub(s0 + SUBR, nxt);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
@@ -149,6 +153,10 @@ __device__ __forceinline__ void tile_project(const double* __restrict__ U, int N
           acc[q][1][3] += u[j].y * x23[j].y;
         }
       }
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
     }
   }
   const int nblk = gridDim.x;
@@ -283,6 +291,10 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
   double acc[RB];
 #pragma unroll
   for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+  // X first: its loads overlap the U stream below
+  double xv[RB];
+#pragma unroll
+  for (int c = 0; c < RB; ++c) xv[c] = (in && c < R) ? (double)X[(size_t)c * ld + e] : 0.0;
   for (int i0 = 0; i0 < k; i0 += kc) {
     const int kn = min(kc, k - i0);
     if (i0 > 0) __syncthreads();
@@ -291,11 +303,19 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
       sco[f] = c < R ? coef[(i0 + i) * R + c] : 0.0;
     }
     __syncthreads();
+    // U rows in blocks of 8, the next block loaded while the current one is used
+    double u[8], un[8];
     int i = 0;
-    for (; i + 8 <= kn; i += 8) {
-      double u[8];
+    if (kn >= 8) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) u[j] = U[(size_t)(i0 + i + j) * N + ec];
+      for (int j = 0; j < 8; ++j) u[j] = U[(size_t)(i0 + j) * N + ec];
+    }
+    for (; i + 8 <= kn; i += 8) {
+      const bool more = i + 16 <= kn;
+      if (more) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) un[j] = U[(size_t)(i0 + i + 8 + j) * N + ec];
+      }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const double* cr = sco + (i + j) * RB;
@@ -306,22 +326,23 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
           acc[c + 1] += u[j] * cc.y;
         }
       }
+      if (more) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = un[j];
+      }
     }
     for (; i < kn; ++i) {
-      const double u = U[(size_t)(i0 + i) * N + ec];
+      const double uu = U[(size_t)(i0 + i) * N + ec];
       const double* cr = sco + i * RB;
 #pragma unroll
       for (int c = 0; c < RB; c += 2) {
         const double2 cc = *reinterpret_cast<const double2*>(cr + c);
-        acc[c] += u * cc.x;
-        acc[c + 1] += u * cc.y;
+        acc[c] += uu * cc.x;
+        acc[c + 1] += uu * cc.y;
       }
     }
   }
   const double pre = e < n ? pre_v : pre_g, post = e < n ? post_v : post_g;
-  double xv[RB];
-#pragma unroll
-  for (int c = 0; c < RB; ++c) xv[c] = (in && c < R) ? (double)X[(size_t)c * ld + e] : 0.0;
 #pragma unroll
   for (int c = 0; c < RB; ++c) {
     double dot = 0.0;
