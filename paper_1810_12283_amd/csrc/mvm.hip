@@ -468,14 +468,16 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-// multiply by -i (forward) or +i (inverse)
-__device__ __forceinline__ double2 cmi(double2 a, int dir) {
-  return dir > 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+// multiply by -i (forward, DIR = +1) or +i (inverse, DIR = -1)
+template <int DIR>
+__device__ __forceinline__ double2 cmi(double2 a) {
+  return DIR > 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
 }
 
-// 4-point DFT in registers (dir = +1: e^{-2 pi i/4}, -1: inverse).
-__device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2& d, int dir) {
-  double2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = cmi(csub(b, d), dir);
+// 4-point DFT in registers (DIR = +1: e^{-2 pi i/4}, -1: inverse).
+template <int DIR>
+__device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2& d) {
+  double2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = cmi<DIR>(csub(b, d));
   a = cadd(t0, t2);
   c = csub(t0, t2);
   b = cadd(t1, t3);
@@ -484,16 +486,17 @@ __device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2
 
 // 8-point DFT in registers: two 4-point DFTs on even / odd inputs, then the
 // twiddles e^{-+2 pi i k/8}.
-__device__ __forceinline__ void dft8(double2 v[8], int dir) {
+template <int DIR>
+__device__ __forceinline__ void dft8(double2 v[8]) {
   const double h = 0.70710678118654752440;
   double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
   double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-  dft4(e0, e1, e2, e3, dir);
-  dft4(o0, o1, o2, o3, dir);
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
   // W^1 = (1 -+ i)/sqrt2, W^2 = -+i, W^3 = (-1 -+ i)/sqrt2
-  double2 w1o1 = cscale(cadd(o1, cmi(o1, dir)), h);
-  double2 w2o2 = cmi(o2, dir);
-  double2 w3o3 = cscale(csub(cmi(o3, dir), o3), h);
+  double2 w1o1 = cscale(cadd(o1, cmi<DIR>(o1)), h);
+  double2 w2o2 = cmi<DIR>(o2);
+  double2 w3o3 = cscale(csub(cmi<DIR>(o3), o3), h);
   v[0] = cadd(e0, o0);
   v[4] = csub(e0, o0);
   v[1] = cadd(e1, w1o1);
@@ -507,10 +510,9 @@ __device__ __forceinline__ void dft8(double2 v[8], int dir) {
 // One in-place Stockham pass of radix RAD over a length-L sequence in LDS,
 // handled by `tpp` threads: each butterfly reads its RAD inputs into
 // registers, the work-group synchronises, then writes the RAD outputs.
-template <int RAD>
+template <int RAD, int DIR>
 __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int L, int Ns,
-                                              const double2* __restrict__ tw, int lane, int tpp,
-                                              int dir) {
+                                              const double2* __restrict__ tw, int lane, int tpp) {
   constexpr int PER = 8 / RAD;  // butterflies per thread when tpp = L / 8
   const int q = L / RAD;
   const int tstep = L / (RAD * Ns);
@@ -525,14 +527,14 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int L, 
         double2 x = buf[jj + r * q];
         if (r > 0 && Ns > 1) {
           double2 w = tw[r * k * tstep];
-          x = dir > 0 ? cmul(x, w) : cmulc(x, w);
+          x = DIR > 0 ? cmul(x, w) : cmulc(x, w);
         }
         v[b][r] = x;
       }
       if (RAD == 8) {
-        dft8(v[b], dir);
+        dft8<DIR>(v[b]);
       } else if (RAD == 4) {
-        dft4(v[b][0], v[b][1], v[b][2], v[b][3], dir);
+        dft4<DIR>(v[b][0], v[b][1], v[b][2], v[b][3]);
       } else {
         double2 a0 = v[b][0], a1 = v[b][1];
         v[b][0] = cadd(a0, a1);
@@ -554,19 +556,19 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int L, 
   __syncthreads();
 }
 
-__device__ __forceinline__ void fft_inplace(double2* buf, int L, const double2* tw, int lane, int tpp,
-                                            int dir) {
+template <int DIR>
+__device__ __forceinline__ void fft_inplace(double2* buf, int L, const double2* tw, int lane, int tpp) {
   int Ns = 1;
   while (Ns < L) {
     int left = L / Ns;
     if (left % 8 == 0) {
-      stockham_pass<8>(buf, L, Ns, tw, lane, tpp, dir);
+      stockham_pass<8, DIR>(buf, L, Ns, tw, lane, tpp);
       Ns *= 8;
     } else if (left % 4 == 0) {
-      stockham_pass<4>(buf, L, Ns, tw, lane, tpp, dir);
+      stockham_pass<4, DIR>(buf, L, Ns, tw, lane, tpp);
       Ns *= 4;
     } else {
-      stockham_pass<2>(buf, L, Ns, tw, lane, tpp, dir);
+      stockham_pass<2, DIR>(buf, L, Ns, tw, lane, tpp);
       Ns *= 2;
     }
   }
@@ -652,10 +654,10 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   }
   __syncthreads();
   double2* buf = smem + (size_t)pr * L;
-  fft_inplace(buf, L, stw, lane, tpp, +1);
+  fft_inplace<+1>(buf, L, stw, lane, tpp);
   for (int kk = lane; kk < L; kk += tpp) buf[kk] = cscale(buf[kk], stage_spec ? sspec[kk] : spec[kk]);
   __syncthreads();
-  fft_inplace(buf, L, stw, lane, tpp, -1);
+  fft_inplace<-1>(buf, L, stw, lane, tpp);
   if (inner > 1) {
     for (int f = threadIdx.x; f < tot; f += 256) {
       const int l = f % nl, jj = f / nl;
@@ -685,8 +687,8 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
 // the per-axis tuner weighs.  m <= kDenseMaxM.
 typedef double dski_dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kDenseMaxM = 448;
-constexpr int kDenseMaxTiles = (kDenseMaxM + 63) / 64;  // row tiles per wavefront
 
+template <int NT>  // row tiles per wavefront: 4 NT >= ceil(m / 16)
 __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, long long nlines, int m,
                                                        long long inner, const double* __restrict__ col,
                                                        double scale, int deriv, double h_over_ell) {
@@ -741,30 +743,32 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
   const int r16 = lane & 15, kq = lane >> 4;
   const int ntiles = (m + 15) / 16;
   // all row tiles of this wavefront advance together: independent accumulator
-  // chains that share the X operand of each step
-  dski_dbl4 res[kDenseMaxTiles];
-  int arow[kDenseMaxTiles];
+  // chains that share the X operand of each step.  No branches: rows of X at or
+  // beyond m are zero and output rows at or beyond m are discarded, so the
+  // Toeplitz index only needs clamping to stay inside the column.
+  dski_dbl4 res[NT];
+  int arow[NT];
 #pragma unroll
-  for (int q = 0; q < kDenseMaxTiles; ++q) {
+  for (int q = 0; q < NT; ++q) {
     res[q] = dski_dbl4{0.0, 0.0, 0.0, 0.0};
-    arow[q] = (wv + 4 * q) * 16 + r16;  // row of T (>= m for padding or absent tiles)
+    arow[q] = (wv + 4 * q) * 16 + r16;
   }
-  const int nq = (ntiles - wv + 3) / 4;  // tiles of this wavefront
+#pragma unroll 2
   for (int k0 = 0; k0 < mp; k0 += 4) {
     const int b = k0 + kq;
     const double xv = sX[b * 16 + r16];
+    double av[NT];
 #pragma unroll
-    for (int q = 0; q < kDenseMaxTiles; ++q) {
-      if (q < nq) {
-        const int a = arow[q];
-        const double av = (a < m && b < m) ? scol[a > b ? a - b : b - a] : 0.0;
-        res[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, res[q], 0, 0, 0);
-      }
+    for (int q = 0; q < NT; ++q) {
+      const int dd = arow[q] > b ? arow[q] - b : b - arow[q];
+      av[q] = scol[dd < m ? dd : m - 1];
     }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) res[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], xv, res[q], 0, 0, 0);
   }
   __syncthreads();  // every wavefront has read sX
 #pragma unroll
-  for (int q = 0; q < kDenseMaxTiles; ++q) {
+  for (int q = 0; q < NT; ++q) {
     const int tile = wv + 4 * q;
     if (tile < ntiles) {
 #pragma unroll
@@ -795,8 +799,19 @@ dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, 
     const int mp = (A.m + 3) & ~3;
     const size_t sh = sizeof(double) * ((size_t)mp * 16 + A.m);
     const double scale = a == 0 ? p->s * p->s : 1.0;
-    k_toeplitz_mfma<<<(unsigned)((nlines + 15) / 16), 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale,
-                                                                     a == dwhich ? 1 : 0, A.h / p->ell[a]);
+    const unsigned nb = (unsigned)((nlines + 15) / 16);
+    const int nt = ((A.m + 15) / 16 + 3) / 4;
+    const int dv = a == dwhich ? 1 : 0;
+    const double hl = A.h / p->ell[a];
+    switch (nt) {
+      case 1: k_toeplitz_mfma<1><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 2: k_toeplitz_mfma<2><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 3: k_toeplitz_mfma<3><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 4: k_toeplitz_mfma<4><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 5: k_toeplitz_mfma<5><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 6: k_toeplitz_mfma<6><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      default: k_toeplitz_mfma<7><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+    }
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   }
