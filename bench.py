@@ -162,6 +162,13 @@ def main(argv=None):
             plan.mvm_stage(0, Vt)
             plan.mvm_stage(1, Vt)
             plan.mvm_stage(2, Vt, Yt)
+        tuned = plan.autotune(R, W.rank)
+        chosen = [0 if kk[0] <= kk[1] else 1 for kk in tuned["kuu_us"]]
+        for v in (1 - chosen[0], chosen[0]):  # the other K_UU variant too, then the tuned one
+            for ax in range(d):
+                plan.set_kuu_variant(ax, v)
+            for _ in range(3):
+                plan.mvm_stage(1, Vt)
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):

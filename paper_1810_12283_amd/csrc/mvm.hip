@@ -507,6 +507,10 @@ __device__ __forceinline__ void dft8(double2 v[8]) {
   v[7] = csub(e3, w3o3);
 }
 
+// LDS position of element i of a line buffer: one pad element per 8, so that
+// the stride-8 accesses of the Stockham passes spread over the banks.
+__device__ __forceinline__ int padi(int i) { return i + (i >> 3); }
+
 // One in-place Stockham pass of radix RAD over a length-L sequence in LDS,
 // handled by `tpp` threads: each butterfly reads its RAD inputs into
 // registers, the work-group synchronises, then writes the RAD outputs.
@@ -524,7 +528,7 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int L, 
       int k = jj & (Ns - 1);
 #pragma unroll
       for (int r = 0; r < RAD; ++r) {
-        double2 x = buf[jj + r * q];
+        double2 x = buf[padi(jj + r * q)];
         if (r > 0 && Ns > 1) {
           double2 w = tw[r * k * tstep];
           x = DIR > 0 ? cmul(x, w) : cmulc(x, w);
@@ -550,7 +554,7 @@ __device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int L, 
       int k = jj & (Ns - 1);
       int o = (jj / Ns) * RAD * Ns + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) buf[o + r * Ns] = v[b][r];
+      for (int r = 0; r < RAD; ++r) buf[padi(o + r * Ns)] = v[b][r];
     }
   }
   __syncthreads();
@@ -594,14 +598,17 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   const int lane = threadIdx.x % tpp;
   const int nl = 2 * ppb;
   const long long line0 = (long long)blockIdx.x * nl;
-  double2* stw = smem + (size_t)ppb * L;  // twiddle table
-  // spectrum in LDS up to L = 1024 (64 KiB in all), else read through the cache
-  const bool stage_spec = L <= 1024;
-  double* sspec = stage_spec ? reinterpret_cast<double*>(stw + L) : nullptr;
-  for (int f = threadIdx.x; f < L; f += 256) {
-    stw[f] = tw[f];
-    if (stage_spec) sspec[f] = spec[f];
-  }
+  const int LP = L + (L >> 3);  // padded line-pair buffer
+  // twiddles and spectrum in LDS up to L = 1024 (below 64 KiB in all), else
+  // read through the cache
+  const bool stage = L <= 1024;
+  double2* stw = stage ? smem + (size_t)ppb * LP : const_cast<double2*>(tw);
+  double* sspec = stage ? reinterpret_cast<double*>(smem + (size_t)ppb * LP + L) : const_cast<double*>(spec);
+  if (stage)
+    for (int f = threadIdx.x; f < L; f += 256) {
+      stw[f] = tw[f];
+      sspec[f] = spec[f];
+    }
   for (int l = threadIdx.x; l < nl; l += 256) {
     const long long line = line0 + l;
     s_base[l] = line < nlines ? (line / inner) * ((long long)m * inner) + line % inner : -1;
@@ -609,7 +616,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   // zero padding of every line pair (entries m .. L-1)
   for (int f = threadIdx.x; f < ppb * (L - m); f += 256) {
     const int pp = f / (L - m), jj = m + f % (L - m);
-    smem[(size_t)pp * L + jj] = make_double2(0.0, 0.0);
+    smem[(size_t)pp * LP + padi(jj)] = make_double2(0.0, 0.0);
   }
   __syncthreads();
   const int tot = nl * m;
@@ -628,7 +635,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
         const int f = f0 + 256 * u;
         if (f < tot) {
           const int l = f % nl, jj = f / nl;
-          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v[u];
+          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1] = v[u];
         }
       }
     }
@@ -647,28 +654,28 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
         const int f = f0 + 256 * u;
         if (f < tot) {
           const int jj = f % m, l = f / m;
-          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1] = v[u];
+          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1] = v[u];
         }
       }
     }
   }
   __syncthreads();
-  double2* buf = smem + (size_t)pr * L;
+  double2* buf = smem + (size_t)pr * LP;
   fft_inplace<+1>(buf, L, stw, lane, tpp);
-  for (int kk = lane; kk < L; kk += tpp) buf[kk] = cscale(buf[kk], stage_spec ? sspec[kk] : spec[kk]);
+  for (int kk = lane; kk < L; kk += tpp) buf[padi(kk)] = cscale(buf[padi(kk)], sspec[kk]);
   __syncthreads();
   fft_inplace<-1>(buf, L, stw, lane, tpp);
   if (inner > 1) {
     for (int f = threadIdx.x; f < tot; f += 256) {
       const int l = f % nl, jj = f / nl;
       const long long b = s_base[l];
-      if (b >= 0) G[b + (long long)jj * inner] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
+      if (b >= 0) G[b + (long long)jj * inner] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1];
     }
   } else {
     for (int f = threadIdx.x; f < tot; f += 256) {
       const int jj = f % m, l = f / m;
       const long long b = s_base[l];
-      if (b >= 0) G[b + jj] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * L + jj])[l & 1];
+      if (b >= 0) G[b + jj] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1];
     }
   }
 }
@@ -695,8 +702,8 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
   extern __shared__ double smem_d[];
   __shared__ long long s_base[16];
   const int mp = (m + 3) & ~3;
-  double* sX = smem_d;               // mp x 16
-  double* scol = smem_d + (size_t)mp * 16;  // m
+  double* sX = smem_d;               // mp rows of 16 lines, row stride 17 (banks)
+  double* scol = smem_d + (size_t)mp * 17;  // m
   const long long line0 = (long long)blockIdx.x * 16;
   for (int k = threadIdx.x; k < m; k += 256) {
     double v = col[k] * scale;
@@ -734,7 +741,7 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
       if (f < tot) {
         const int l = inner > 1 ? f % 16 : f / mp;
         const int bb = inner > 1 ? f / 16 : f % mp;
-        sX[bb * 16 + l] = v[u];
+        sX[bb * 17 + l] = v[u];
       }
     }
   }
@@ -756,7 +763,7 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
 #pragma unroll 2
   for (int k0 = 0; k0 < mp; k0 += 4) {
     const int b = k0 + kq;
-    const double xv = sX[b * 16 + r16];
+    const double xv = sX[b * 17 + r16];
     double av[NT];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
@@ -774,7 +781,7 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = tile * 16 + kq + 4 * r;
-        if (a < m) sX[a * 16 + r16] = res[q][r];
+        if (a < m) sX[a * 17 + r16] = res[q][r];
       }
     }
   }
@@ -784,7 +791,7 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
     const int l = inner > 1 ? f % 16 : f / m;
     const int bb = inner > 1 ? f / 16 : f % m;
     const long long base = s_base[l];
-    if (base >= 0) G[base + (long long)bb * inner] = sX[bb * 16 + l];
+    if (base >= 0) G[base + (long long)bb * inner] = sX[bb * 17 + l];
   }
 }
 
@@ -797,7 +804,7 @@ dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, 
   const long long nlines = (long long)R * (p->M / A.m);
   if (variant == 1 && A.m <= kDenseMaxM) {
     const int mp = (A.m + 3) & ~3;
-    const size_t sh = sizeof(double) * ((size_t)mp * 16 + A.m);
+    const size_t sh = sizeof(double) * ((size_t)mp * 17 + A.m);
     const double scale = a == 0 ? p->s * p->s : 1.0;
     const unsigned nb = (unsigned)((nlines + 15) / 16);
     const int nt = ((A.m + 15) / 16 + 3) / 4;
@@ -823,7 +830,7 @@ dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, 
     return DSKI_ENOTSUP;
   }
   const int ppb = 256 / (L / 8);
-  const size_t sh = sizeof(double2) * ((size_t)ppb * L + L) + (L <= 1024 ? sizeof(double) * L : 0);
+  const size_t sh = sizeof(double2) * (size_t)ppb * (L + L / 8) + (L <= 1024 ? (sizeof(double2) + sizeof(double)) * L : 0);
   const long long blocks = (nlines + 2 * ppb - 1) / (2 * ppb);
   k_toeplitz<<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
   DSKI_HIP(hipGetLastError());
