@@ -102,9 +102,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     ncells_r *= span[a];
     if (a < last) nrows *= span[a];
   }
-  // this work-group's columns [rs0, rse), processed CR at a time
-  const int rs0 = blockIdx.y * cr;
-  const int rse = min(R, rs0 + cr);
+  const int r0 = blockIdx.y * cr;
+  const int rc = min(cr, R - r0);
   // per-row global ranges (rows = all region axes but the last; cells of a row are contiguous)
   for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
     int rem = row, base = 0, mul = 1;
@@ -185,6 +184,26 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
         if (f < totw) s_w[f / total][f % total] = w4[u];
       }
     }
+    const int tot = total * CR * (D + 1);
+    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
+      T v4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        const int q = f % total, rest = f / total;
+        const int b = rest % (D + 1), r = rest / (D + 1);
+        v4[u] = (f < tot && r < rc) ? V[(size_t)(r0 + r) * ldv + (size_t)b * n + s_qk[q]] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = f0 + 256 * u;
+        if (f < tot) {
+          const int q = f % total, rest = f / total;
+          const int b = rest % (D + 1), r = rest / (D + 1);
+          s_v[(q * CR + r) * (D + 1) + b] = v4[u];
+        }
+      }
+    }
   }
   __syncthreads();
   int j[D];
@@ -194,6 +213,10 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     j[a] = origin[a] + jl[a];
     inside = inside && j[a] < g.m[a];
   }
+  if (!inside) return;
+  double acc[CR];
+#pragma unroll
+  for (int r = 0; r < CR; ++r) acc[r] = 0.0;
   int lo[D], hi[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -203,131 +226,99 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   int outer_cnt = 1;
 #pragma unroll
   for (int a = 0; a < last; ++a) outer_cnt *= hi[a] - lo[a] + 1;
+  for (int oc = 0; oc < outer_cnt; ++oc) {
+    int c[D];
+    int rem = oc;
+#pragma unroll
+    for (int a = last - 1; a >= 0; --a) {
+      int sp = hi[a] - lo[a] + 1;
+      c[a] = lo[a] + rem % sp;
+      rem /= sp;
+    }
+    if (lds_ok) {
+      int lrow = 0;
+#pragma unroll
+      for (int a = 0; a < last; ++a) lrow = lrow * span[a] + (c[a] - rlo[a]);
+      for (int cl = lo[last]; cl <= hi[last]; ++cl) {
+        int lc = lrow * span[last] + (cl - rlo[last]);
+        int q0 = s_lcs[lc], q1 = s_lcs[lc + 1];
+        for (int q = q0; q < q1; ++q) {
+          double wv[D], wd[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            int ca = (a == last) ? cl : c[a];
+            int o = j[a] - ca + 1;
+            wv[a] = s_w[a * 8 + o][q];
+            wd[a] = s_w[a * 8 + 4 + o][q];
+          }
+          double wprod = 1.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) wprod *= wv[a];
+          double dprod[D];
+#pragma unroll
+          for (int qq = 0; qq < D; ++qq) {
+            double v = 1.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
+            dprod[qq] = v;
+          }
+          const T* sv = s_v + (size_t)q * CR * (D + 1);
+#pragma unroll
+          for (int r = 0; r < CR; ++r) {  // columns beyond rc hold zeros
+            double a = wprod * (double)sv[r * (D + 1)];
+#pragma unroll
+            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)sv[r * (D + 1) + qq + 1];
+            acc[r] += a;
+          }
+        }
+      }
+    } else {
+      int base = 0;
+#pragma unroll
+      for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+      base *= g.nc[last];
+      int kb = cstart[base + lo[last] - 1];
+      int ke = cstart[base + hi[last]];
+      for (int k = kb; k < ke; ++k) {
+        int clast = cell[k] % g.nc[last] + 1;
+        double wv[D], wd[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          int ca = (a == last) ? clast : c[a];
+          int o = j[a] - ca + 1;
+          wv[a] = wts[(size_t)(a * 8 + o) * n + k];
+          wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
+        }
+        double wprod = 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) wprod *= wv[a];
+        double dprod[D];
+#pragma unroll
+        for (int qq = 0; qq < D; ++qq) {
+          double v = 1.0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
+          dprod[qq] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+          if (r < rc) {
+            const T* vv = V + (size_t)(r0 + r) * ldv + k;
+            double a = wprod * (double)vv[0];
+#pragma unroll
+            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)vv[(size_t)(qq + 1) * n];
+            acc[r] += a;
+          }
+        }
+      }
+    }
+  }
   long long node = 0;
 #pragma unroll
-  for (int a = 0; a < D; ++a) node = node * g.m[a] + (inside ? j[a] : 0);
-  for (int r0 = rs0; r0 < rse; r0 += CR) {
-    const int rc = min(CR, rse - r0);
-    if (lds_ok) {
-      const int tot = total * CR * (D + 1);
-      for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-        T v4[4];
+  for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int f = f0 + 256 * u;
-          const int q = f % total, rest = f / total;
-          const int b = rest % (D + 1), r = rest / (D + 1);
-          v4[u] = (f < tot && r < rc) ? V[(size_t)(r0 + r) * ldv + (size_t)b * n + s_qk[q]] : (T)0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int f = f0 + 256 * u;
-          if (f < tot) {
-            const int q = f % total, rest = f / total;
-            const int b = rest % (D + 1), r = rest / (D + 1);
-            s_v[(q * CR + r) * (D + 1) + b] = v4[u];
-          }
-        }
-      }
-    }
-    __syncthreads();
-    double acc[CR];
-#pragma unroll
-    for (int r = 0; r < CR; ++r) acc[r] = 0.0;
-    if (inside) {
-      for (int oc = 0; oc < outer_cnt; ++oc) {
-        int c[D];
-        int rem = oc;
-  #pragma unroll
-        for (int a = last - 1; a >= 0; --a) {
-          int sp = hi[a] - lo[a] + 1;
-          c[a] = lo[a] + rem % sp;
-          rem /= sp;
-        }
-        if (lds_ok) {
-          int lrow = 0;
-  #pragma unroll
-          for (int a = 0; a < last; ++a) lrow = lrow * span[a] + (c[a] - rlo[a]);
-          for (int cl = lo[last]; cl <= hi[last]; ++cl) {
-            int lc = lrow * span[last] + (cl - rlo[last]);
-            int q0 = s_lcs[lc], q1 = s_lcs[lc + 1];
-            for (int q = q0; q < q1; ++q) {
-              double wv[D], wd[D];
-  #pragma unroll
-              for (int a = 0; a < D; ++a) {
-                int ca = (a == last) ? cl : c[a];
-                int o = j[a] - ca + 1;
-                wv[a] = s_w[a * 8 + o][q];
-                wd[a] = s_w[a * 8 + 4 + o][q];
-              }
-              double wprod = 1.0;
-  #pragma unroll
-              for (int a = 0; a < D; ++a) wprod *= wv[a];
-              double dprod[D];
-  #pragma unroll
-              for (int qq = 0; qq < D; ++qq) {
-                double v = 1.0;
-  #pragma unroll
-                for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
-                dprod[qq] = v;
-              }
-              const T* sv = s_v + (size_t)q * CR * (D + 1);
-  #pragma unroll
-              for (int r = 0; r < CR; ++r) {  // columns beyond rc hold zeros
-                double a = wprod * (double)sv[r * (D + 1)];
-  #pragma unroll
-                for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)sv[r * (D + 1) + qq + 1];
-                acc[r] += a;
-              }
-            }
-          }
-        } else {
-          int base = 0;
-  #pragma unroll
-          for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
-          base *= g.nc[last];
-          int kb = cstart[base + lo[last] - 1];
-          int ke = cstart[base + hi[last]];
-          for (int k = kb; k < ke; ++k) {
-            int clast = cell[k] % g.nc[last] + 1;
-            double wv[D], wd[D];
-  #pragma unroll
-            for (int a = 0; a < D; ++a) {
-              int ca = (a == last) ? clast : c[a];
-              int o = j[a] - ca + 1;
-              wv[a] = wts[(size_t)(a * 8 + o) * n + k];
-              wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
-            }
-            double wprod = 1.0;
-  #pragma unroll
-            for (int a = 0; a < D; ++a) wprod *= wv[a];
-            double dprod[D];
-  #pragma unroll
-            for (int qq = 0; qq < D; ++qq) {
-              double v = 1.0;
-  #pragma unroll
-              for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
-              dprod[qq] = v;
-            }
-  #pragma unroll
-            for (int r = 0; r < CR; ++r) {
-              if (r < rc) {
-                const T* vv = V + (size_t)(r0 + r) * ldv + k;
-                double a = wprod * (double)vv[0];
-  #pragma unroll
-                for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)vv[(size_t)(qq + 1) * n];
-                acc[r] += a;
-              }
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < CR; ++r)
-        if (r < rc) G[(size_t)(r0 + r) * M + node] = acc[r];
-    }
-    __syncthreads();  // s_v is rewritten by the next column chunk
-  }
+  for (int r = 0; r < CR; ++r)
+    if (r < rc) G[(size_t)(r0 + r) * M + node] = acc[r];
 }
 
 template <int D, typename T>
@@ -336,14 +327,11 @@ static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, h
   using TS = TileShape<D>;
   long long tiles = 1;
   for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
-  // columns: chunks of CR per pass; a work-group takes a run of chunks (its
-  // tile's weights and point index staged once), with enough work-groups to
-  // cover the CUs: 17 columns on 169 tiles -> 2 runs of 12 and 5 columns
+  // columns per work-group: at most CR, chunks balanced (17 columns -> 5 x {4,4,3,3,3})
   constexpr int CR = (sizeof(T) == 4 && D <= 2) ? 4 : (D <= 2 ? 2 : (sizeof(T) == 4 ? 2 : 1));
   const int nch = (R + CR - 1) / CR;
-  const int nrun = (int)std::min<long long>(nch, std::max<long long>(1, (256 + tiles - 1) / tiles));
-  const int cr = CR * ((nch + nrun - 1) / nrun);
-  dim3 grid((unsigned)tiles, (R + cr - 1) / cr);
+  const int cr = (R + nch - 1) / nch;
+  dim3 grid((unsigned)tiles, nch);
   k_scatter_lds<D, CR, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv,
                                                       R, cr, G, p->M);
 }
