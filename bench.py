@@ -169,10 +169,11 @@ def main(argv=None):
                 plan.set_kuu_variant(ax, v)
             for _ in range(3):
                 plan.mvm_stage(1, Vt)
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            dst.copy_(src)                   # runtime copy kernel: 256 MiB read, 256 MiB written
+            torch.mul(src, 1.0, out=dst)     # elementwise kernel: the same bytes
         torch.cuda.synchronize()
         print(json.dumps({"pmc_mvm": "done", "copy_bytes": src.numel() * 4, "source": source_digest()}), flush=True)
         return 0
