@@ -46,13 +46,40 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// Radix plan of the length-2^lg FFT along a grid axis: passes of radix 8
+// while three or more factors of two remain, then one pass of radix 4 or 2.
+// The inverse transform runs the same radices in reverse order.  Pass s of a
+// direction has stride Ns = product of the radices before it; its twiddles
+// e^{-+2 pi i r k / (radix Ns)} (r = 1..radix-1, k < Ns) are stored at
+// fft_tw_offset + (r - 1) Ns + k, forward passes first, then the inverse ones
+// (already conjugated).
+__host__ __device__ constexpr int fft_npass(int lg) { return lg / 3 + (lg % 3 != 0 ? 1 : 0); }
+__host__ __device__ constexpr int fft_radix_dir(int lg, int s, int dir) {
+  const int t = dir > 0 ? s : fft_npass(lg) - 1 - s;
+  return t < lg / 3 ? 8 : (lg % 3 == 2 ? 4 : 2);
+}
+__host__ __device__ constexpr int fft_ns(int lg, int s, int dir) {
+  int ns = 1;
+  for (int t = 0; t < s; ++t) ns *= fft_radix_dir(lg, t, dir);
+  return ns;
+}
+__host__ __device__ constexpr int fft_tw_offset(int lg, int s, int dir) {
+  int off = 0;
+  if (dir < 0)
+    for (int t = 0; t < fft_npass(lg); ++t) off += (fft_radix_dir(lg, t, +1) - 1) * fft_ns(lg, t, +1);
+  for (int t = 0; t < s; ++t) off += (fft_radix_dir(lg, t, dir) - 1) * fft_ns(lg, t, dir);
+  return off;
+}
+__host__ __device__ constexpr int fft_tw_size(int lg) { return fft_tw_offset(lg, fft_npass(lg), -1); }
+constexpr int kFftMaxLog2 = 11;  // L <= 2048, m <= 1024 per axis
+
 // Per-axis geometry of the grid and its circulant embedding.
 struct Axis {
   int m = 0;          // grid nodes
   int ncell = 0;      // interpolation cells = m - 3
   int L = 0;          // circulant length (power of two >= 2m - 1)
   double lo = 0, h = 0;
-  double* twiddle = nullptr;  // L complex e^{-2 pi i t / L} (device, interleaved cos, -sin)
+  double* twiddle = nullptr;  // fft_tw_size(log2 L) complex pass twiddles (device, interleaved re, im)
   double* spec = nullptr;     // L circulant eigenvalues of T_p, scaled (device)
   double* dspec = nullptr;    // L eigenvalues of dT_p / dlog ell_p, scaled (device)
   double* col = nullptr;      // m first column of T_p (device)

@@ -507,177 +507,249 @@ __device__ __forceinline__ void dft8(double2 v[8]) {
   v[7] = csub(e3, w3o3);
 }
 
-// LDS position of element i of a line buffer: one pad element per 8, so that
-// the stride-8 accesses of the Stockham passes spread over the banks.
+// LDS position of element i of a line-pair buffer: one pad element per 8, so
+// that the stride-8 accesses of the radix-8 passes spread over the banks.
 __device__ __forceinline__ int padi(int i) { return i + (i >> 3); }
 
-// One in-place Stockham pass of radix RAD over a length-L sequence in LDS,
-// handled by `tpp` threads: each butterfly reads its RAD inputs into
-// registers, the work-group synchronises, then writes the RAD outputs.
-template <int RAD, int DIR>
-__device__ __forceinline__ void stockham_pass(double2* __restrict__ buf, int L, int Ns,
-                                              const double2* __restrict__ tw, int lane, int tpp) {
-  constexpr int PER = 8 / RAD;  // butterflies per thread when tpp = L / 8
-  const int q = L / RAD;
-  const int tstep = L / (RAD * Ns);
-  double2 v[PER][RAD];
-#pragma unroll
-  for (int b = 0; b < PER; ++b) {
-    int jj = lane + b * tpp;
-    if (jj < q) {
-      int k = jj & (Ns - 1);
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) {
-        double2 x = buf[padi(jj + r * q)];
-        if (r > 0 && Ns > 1) {
-          double2 w = tw[r * k * tstep];
-          x = DIR > 0 ? cmul(x, w) : cmulc(x, w);
-        }
-        v[b][r] = x;
-      }
-      if (RAD == 8) {
-        dft8<DIR>(v[b]);
-      } else if (RAD == 4) {
-        dft4<DIR>(v[b][0], v[b][1], v[b][2], v[b][3]);
-      } else {
-        double2 a0 = v[b][0], a1 = v[b][1];
-        v[b][0] = cadd(a0, a1);
-        v[b][1] = csub(a0, a1);
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int b = 0; b < PER; ++b) {
-    int jj = lane + b * tpp;
-    if (jj < q) {
-      int k = jj & (Ns - 1);
-      int o = (jj / Ns) * RAD * Ns + k;
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) buf[padi(o + r * Ns)] = v[b][r];
-    }
-  }
-  __syncthreads();
+// Orders the LDS accesses of one wavefront: lanes exchange values through LDS,
+// and the LDS operations of a wavefront complete in issue order, so only the
+// compiler has to be kept from moving loads and stores across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int DIR>
-__device__ __forceinline__ void fft_inplace(double2* buf, int L, const double2* tw, int lane, int tpp) {
-  int Ns = 1;
-  while (Ns < L) {
-    int left = L / Ns;
-    if (left % 8 == 0) {
-      stockham_pass<8, DIR>(buf, L, Ns, tw, lane, tpp);
-      Ns *= 8;
-    } else if (left % 4 == 0) {
-      stockham_pass<4, DIR>(buf, L, Ns, tw, lane, tpp);
-      Ns *= 4;
-    } else {
-      stockham_pass<2, DIR>(buf, L, Ns, tw, lane, tpp);
-      Ns *= 2;
+// Work-group index remapped so that consecutive logical blocks run on the same
+// XCD (the hardware deals work-groups to the 8 XCDs in turn): blocks that share
+// cache lines then share one L2.  A bijection on [0, nb).
+__device__ __forceinline__ long long xcd_block(unsigned bid, unsigned nb) {
+  const unsigned full = nb & ~7u;
+  if (bid >= full) return bid;
+  return (long long)(bid & 7u) * (full >> 3) + (bid >> 3);
+}
+
+// Shape of the line-pair FFT for L = 2^LG: TPL lanes hold one pair of real grid
+// lines as one complex sequence (E values per lane), PW pairs per wavefront,
+// four wavefronts per work-group.
+template <int LG>
+struct FftShape {
+  static constexpr int L = 1 << LG;
+  static constexpr int TPL = L / 8 < 64 ? L / 8 : 64;
+  static constexpr int PW = 64 / TPL;
+  static constexpr int E = L / TPL;
+  static constexpr int NP = fft_npass(LG);
+  static constexpr int PAIRS = 4 * PW;
+  static constexpr int NL = 2 * PAIRS;                      // lines per work-group
+  static constexpr int LGNL = LG <= 9 ? 12 - LG : 3;        // log2(NL)
+  static constexpr int LP = L + L / 8 + 1;                  // odd: pair buffers start on different banks
+  static constexpr bool STAGE = L <= 1024;                  // twiddles and spectrum in LDS
+  static constexpr int TW = fft_tw_size(LG);
+  static constexpr size_t lds_bytes() {
+    return sizeof(double2) * (size_t)PAIRS * LP + (STAGE ? sizeof(double2) * TW + sizeof(double) * L : 0);
+  }
+};
+
+// Radix-RAD butterflies of one pass (stride NS, direction DIR) on the values a
+// lane holds: v[b RAD + r] is input r of butterfly jj = lane + b TPL, i.e. the
+// sequence element jj + r L / RAD.  Inputs r >= 1 take the pass twiddle of
+// k = jj mod NS first (none when NS = 1).
+template <int LG, int RAD, int NS, int DIR>
+__device__ __forceinline__ void fft_butterflies(double2* v, const double2* __restrict__ tw, int lp) {
+  using S = FftShape<LG>;
+  constexpr int NB = S::L / RAD / S::TPL;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    double2* u = v + b * RAD;
+    if (NS > 1) {
+      const int k = (lp + b * S::TPL) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) u[r] = cmul(u[r], tw[(r - 1) * NS + k]);
     }
+    if (RAD == 8) {
+      dft8<DIR>(u);
+    } else if (RAD == 4) {
+      dft4<DIR>(u[0], u[1], u[2], u[3]);
+    } else {
+      const double2 a0 = u[0], a1 = u[1];
+      u[0] = cadd(a0, a1);
+      u[1] = csub(a0, a1);
+    }
+  }
+}
+
+// Stockham hand-over between two passes through the pair's LDS buffer: the
+// outputs of pass (RA, NSA) go to (jj / NSA) RA NSA + jj mod NSA + r NSA, and the
+// next pass (RB) reads its inputs jj + r L / RB.
+template <int LG, int RA, int NSA, int RB>
+__device__ __forceinline__ void fft_exchange(double2* v, double2* __restrict__ buf, int lp) {
+  using S = FftShape<LG>;
+  constexpr int NBA = S::L / RA / S::TPL, NBB = S::L / RB / S::TPL;
+#pragma unroll
+  for (int b = 0; b < NBA; ++b) {
+    const int jj = lp + b * S::TPL;
+    const int o = (jj / NSA) * RA * NSA + (jj & (NSA - 1));
+#pragma unroll
+    for (int r = 0; r < RA; ++r) buf[padi(o + r * NSA)] = v[b * RA + r];
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int b = 0; b < NBB; ++b)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) v[b * RB + r] = buf[padi(lp + b * S::TPL + r * (S::L / RB))];
+  wave_lds_sync();
+}
+
+// Passes S0.. of one direction; v enters holding the inputs of pass S0.
+template <int LG, int DIR, int S0>
+__device__ __forceinline__ void fft_run(double2* v, double2* __restrict__ buf, const double2* __restrict__ tw,
+                                        int lp) {
+  constexpr int NP = fft_npass(LG);
+  constexpr int RAD = fft_radix_dir(LG, S0, DIR), NS = fft_ns(LG, S0, DIR);
+  fft_butterflies<LG, RAD, NS, DIR>(v, tw + fft_tw_offset(LG, S0, DIR), lp);
+  if constexpr (S0 + 1 < NP) {
+    fft_exchange<LG, RAD, NS, fft_radix_dir(LG, S0 + 1, DIR)>(v, buf, lp);
+    fft_run<LG, DIR, S0 + 1>(v, buf, tw, lp);
   }
 }
 
 // Toeplitz product along one axis for all grid lines of R columns.  Each line
-// (m values at stride `inner`) is zero-padded to L, transformed, multiplied by the
-// circulant eigenvalues `spec` (already scaled by 1/L) and transformed back; two
+// (m values at stride `inner`) is zero-padded to L, transformed, multiplied by
+// the circulant eigenvalues `spec` (scaled by 1/L) and transformed back; two
 // lines share one complex FFT (real and imaginary parts), which is exact because
-// the spectrum is real and even.  TPP = L/8 threads per line pair, 256/TPP pairs
-// per work-group; LDS holds the line pairs, the twiddles, the spectrum and the
-// base offset of every line.  Grid loads and stores are issued four per thread
-// at a time.
+// the spectrum is real and even.  One pair per TPL lanes, all exchanges inside
+// the wavefront.  The last forward pass leaves element jj + r L / RAD in the
+// lane that the first inverse pass (same radix, NS = 1) needs it in, so the
+// spectrum is applied in registers between the two; the first forward pass and
+// the last inverse pass touch the elements lane + r L / 8, which contiguous
+// lines (inner = 1) load and store straight from and to the grid.  Strided
+// lines go through LDS with work-group-wide coalesced loads and stores.
+template <int LG>
 __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long long nlines, int m,
-                                                  int L, long long inner,
-                                                  const double2* __restrict__ tw,
+                                                  long long inner, const double2* __restrict__ tw,
                                                   const double* __restrict__ spec) {
+  using S = FftShape<LG>;
+  constexpr int L = S::L, E = S::E, TPL = S::TPL;
+  constexpr int R0 = fft_radix_dir(LG, 0, +1);                 // 8
+  constexpr int RL = fft_radix_dir(LG, S::NP - 1, +1);         // radix of the last forward pass
   extern __shared__ double2 smem[];
-  __shared__ long long s_base[512];
-  const int tpp = L / 8;
-  const int ppb = 256 / tpp;
-  const int pr = threadIdx.x / tpp;
-  const int lane = threadIdx.x % tpp;
-  const int nl = 2 * ppb;
-  const long long line0 = (long long)blockIdx.x * nl;
-  const int LP = L + (L >> 3);  // padded line-pair buffer
-  // twiddles and spectrum in LDS up to L = 1024 (below 64 KiB in all), else
-  // read through the cache
-  const bool stage = L <= 1024;
-  double2* stw = stage ? smem + (size_t)ppb * LP : const_cast<double2*>(tw);
-  double* sspec = stage ? reinterpret_cast<double*>(smem + (size_t)ppb * LP + L) : const_cast<double*>(spec);
-  if (stage)
-    for (int f = threadIdx.x; f < L; f += 256) {
-      stw[f] = tw[f];
-      sspec[f] = spec[f];
+  __shared__ long long s_base[S::NL];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lp = lane % TPL;
+  const int pair = wave * S::PW + lane / TPL;
+  const long long line0 = xcd_block(blockIdx.x, gridDim.x) * S::NL;
+  double2* buf = smem + (size_t)pair * S::LP;
+  const double2* stw = tw;
+  const double* sspec = spec;
+  if constexpr (S::STAGE) {
+    double2* t = smem + (size_t)S::PAIRS * S::LP;
+    double* sp = reinterpret_cast<double*>(t + S::TW);
+    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
+    for (int f = threadIdx.x; f < L; f += 256) sp[f] = spec[f];
+    stw = t;
+    sspec = sp;
+  }
+  double2 v[E];
+  const long long la = line0 + 2 * pair;
+  if (inner == 1) {
+    const double* A = G + la * m;
+    const bool va = la < nlines, vb = la + 1 < nlines;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
+      const bool in = pos < m;
+      v[e] = make_double2(in && va ? A[pos] : 0.0, in && vb ? A[m + pos] : 0.0);
     }
-  for (int l = threadIdx.x; l < nl; l += 256) {
-    const long long line = line0 + l;
-    s_base[l] = line < nlines ? (line / inner) * ((long long)m * inner) + line % inner : -1;
-  }
-  // zero padding of every line pair (entries m .. L-1)
-  for (int f = threadIdx.x; f < ppb * (L - m); f += 256) {
-    const int pp = f / (L - m), jj = m + f % (L - m);
-    smem[(size_t)pp * LP + padi(jj)] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int tot = nl * m;
-  if (inner > 1) {
+    if constexpr (S::STAGE) __syncthreads();
+  } else {
+    // line bases of the block: line = q inner + r  ->  q m inner + r
+    {
+      const long long q0 = line0 / inner;
+      const unsigned in = (unsigned)inner, r0 = (unsigned)(line0 - q0 * inner);
+      for (int l = threadIdx.x; l < S::NL; l += 256) {  // NL is up to 512
+        const unsigned rr = r0 + (unsigned)l;
+        s_base[l] = line0 + l < nlines ? (q0 + rr / in) * m * inner + rr % in : -1;
+      }
+    }
+    __syncthreads();
+    const int tot = S::NL * m;
     for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-      double v[4];
+      double x[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int f = f0 + 256 * u;
-        const int l = f % nl, jj = f / nl;
-        const long long b = f < tot ? s_base[l] : -1;
-        v[u] = b >= 0 ? G[b + (long long)jj * inner] : 0.0;
+        const long long b = f < tot ? s_base[f & (S::NL - 1)] : -1;
+        x[u] = b >= 0 ? G[b + (long long)(f >> S::LGNL) * inner] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int f = f0 + 256 * u;
         if (f < tot) {
-          const int l = f % nl, jj = f / nl;
-          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1] = v[u];
+          const int l = f & (S::NL - 1);
+          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * S::LP + padi(f >> S::LGNL)])[l & 1] = x[u];
         }
       }
     }
-  } else {
-    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-      double v[4];
+    __syncthreads();
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        const int jj = f % m, l = f / m;
-        const long long b = f < tot ? s_base[l] : -1;
-        v[u] = b >= 0 ? G[b + jj] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        if (f < tot) {
-          const int jj = f % m, l = f / m;
-          reinterpret_cast<double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1] = v[u];
-        }
-      }
+    for (int e = 0; e < E; ++e) {
+      const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
+      v[e] = pos < m ? buf[padi(pos)] : make_double2(0.0, 0.0);
     }
+    wave_lds_sync();
   }
-  __syncthreads();
-  double2* buf = smem + (size_t)pr * LP;
-  fft_inplace<+1>(buf, L, stw, lane, tpp);
-  for (int kk = lane; kk < L; kk += tpp) buf[padi(kk)] = cscale(buf[padi(kk)], sspec[kk]);
-  __syncthreads();
-  fft_inplace<-1>(buf, L, stw, lane, tpp);
-  if (inner > 1) {
-    for (int f = threadIdx.x; f < tot; f += 256) {
-      const int l = f % nl, jj = f / nl;
-      const long long b = s_base[l];
-      if (b >= 0) G[b + (long long)jj * inner] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1];
+  fft_run<LG, +1, 0>(v, buf, stw, lp);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sspec[lp + (e / RL) * TPL + (e % RL) * (L / RL)]);
+  fft_run<LG, -1, 0>(v, buf, stw, lp);
+  if (inner == 1) {
+    double* A = G + la * m;
+    const bool va = la < nlines, vb = la + 1 < nlines;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
+      if (pos < m) {
+        if (va) A[pos] = v[e].x;
+        if (vb) A[m + pos] = v[e].y;
+      }
     }
   } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
+      if (pos < m) buf[padi(pos)] = v[e];
+    }
+    __syncthreads();
+    const int tot = S::NL * m;
     for (int f = threadIdx.x; f < tot; f += 256) {
-      const int jj = f % m, l = f / m;
+      const int l = f & (S::NL - 1);
       const long long b = s_base[l];
-      if (b >= 0) G[b + jj] = reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * LP + padi(jj)])[l & 1];
+      if (b >= 0)
+        G[b + (long long)(f >> S::LGNL) * inner] =
+            reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * S::LP + padi(f >> S::LGNL)])[l & 1];
     }
   }
+}
+
+template <int LG>
+static dski_status launch_toeplitz(double* G, long long nlines, int m, long long inner, const double2* tw,
+                                   const double* spec, hipStream_t st) {
+  using S = FftShape<LG>;
+  static_assert(S::lds_bytes() <= 160 * 1024, "LDS");
+  static_assert(S::NL == 1 << S::LGNL, "lines per block");
+  const size_t sh = S::lds_bytes();
+  if (sh > 64 * 1024) {
+    static bool done = false;
+    if (!done) {
+      DSKI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_toeplitz<LG>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+      done = true;
+    }
+  }
+  const long long blocks = (nlines + S::NL - 1) / S::NL;
+  k_toeplitz<LG><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, m, inner, tw, spec);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
 }
 
 // Dense Toeplitz product along one axis on the FP64 matrix cores: for 16 grid
@@ -824,17 +896,20 @@ dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, 
   }
   const double* spec = (a == dwhich) ? A.dspec : A.spec;
   const double2* tw = reinterpret_cast<const double2*>(A.twiddle);
-  const int L = A.L;
-  if (L < 8 || L > 2048) {
-    set_error("FFT length %d not supported (grid size per axis 4..1024)", L);
-    return DSKI_ENOTSUP;
+  switch (A.L) {
+    case 8: return launch_toeplitz<3>(G, nlines, A.m, inner, tw, spec, st);
+    case 16: return launch_toeplitz<4>(G, nlines, A.m, inner, tw, spec, st);
+    case 32: return launch_toeplitz<5>(G, nlines, A.m, inner, tw, spec, st);
+    case 64: return launch_toeplitz<6>(G, nlines, A.m, inner, tw, spec, st);
+    case 128: return launch_toeplitz<7>(G, nlines, A.m, inner, tw, spec, st);
+    case 256: return launch_toeplitz<8>(G, nlines, A.m, inner, tw, spec, st);
+    case 512: return launch_toeplitz<9>(G, nlines, A.m, inner, tw, spec, st);
+    case 1024: return launch_toeplitz<10>(G, nlines, A.m, inner, tw, spec, st);
+    case 2048: return launch_toeplitz<11>(G, nlines, A.m, inner, tw, spec, st);
+    default:
+      set_error("FFT length %d not supported (grid size per axis 4..1024)", A.L);
+      return DSKI_ENOTSUP;
   }
-  const int ppb = 256 / (L / 8);
-  const size_t sh = sizeof(double2) * (size_t)ppb * (L + L / 8) + (L <= 1024 ? (sizeof(double2) + sizeof(double)) * L : 0);
-  const long long blocks = (nlines + 2 * ppb - 1) / (2 * ppb);
-  k_toeplitz<<<(unsigned)blocks, 256, sh, st>>>(G, nlines, A.m, L, inner, tw, spec);
-  DSKI_HIP(hipGetLastError());
-  return DSKI_OK;
 }
 
 // G <- K_UU G for R columns; dwhich = p (0..d-1) uses d T_p / dlog ell_p on axis p.

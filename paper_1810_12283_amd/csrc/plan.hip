@@ -158,14 +158,22 @@ __global__ void k_weights(const double* __restrict__ toff, int n, int d, const d
   }
 }
 
-// Forward twiddles e^{-2 pi i t / L} stored as (cos, -sin) pairs.
-__global__ void k_twiddle(int L, double* __restrict__ tw) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= L) return;
-  double sn, cs;
-  sincospi(2.0 * (double)t / (double)L, &sn, &cs);
-  tw[2 * t] = cs;
-  tw[2 * t + 1] = -sn;
+// Pass twiddles of the length-2^lg FFT in the layout of the radix plan
+// (forward passes e^{-2 pi i r k / (radix Ns)}, then inverse passes with +).
+__global__ void k_twiddle(int lg, double* __restrict__ tw) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= fft_tw_size(lg)) return;
+  const int np = fft_npass(lg);
+  for (int dir = 1; dir >= -1; dir -= 2)
+    for (int s = 0; s < np; ++s) {
+      const int off = fft_tw_offset(lg, s, dir), rad = fft_radix_dir(lg, s, dir), ns = fft_ns(lg, s, dir);
+      if (e < off || e >= off + (rad - 1) * ns) continue;
+      const int r = 1 + (e - off) / ns, k = (e - off) % ns;
+      double sn, cs;
+      sincospi(2.0 * (double)(r * k) / (double)(rad * ns), &sn, &cs);
+      tw[2 * e] = cs;
+      tw[2 * e + 1] = dir > 0 ? -sn : sn;
+    }
 }
 
 // Circulant eigenvalues of the embedding [c_0..c_{m-1}, 0.., c_{m-1}..c_1] of the
@@ -378,8 +386,8 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
     A.h = (bhi[a] - blo[a]) / (double)(A.m - 3);
     A.lo = blo[a] - A.h;
     A.L = fft_len(A.m);
-    if (A.L > 4096) {
-      set_error("grid size %d on axis %d exceeds the FFT limit (m <= 2048)", A.m, a);
+    if (A.L > (1 << kFftMaxLog2)) {
+      set_error("grid size %d on axis %d exceeds the FFT limit (m <= 1024)", A.m, a);
       return DSKI_ENOTSUP;
     }
     g.m[a] = A.m;
@@ -402,11 +410,13 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
   DSKI_HIP(hipMalloc(&p->cell_start, sizeof(int) * (size_t)(nc + 1)));
   for (int a = 0; a < d; ++a) {
     Axis& A = p->ax[a];
-    DSKI_HIP(hipMalloc(&A.twiddle, sizeof(double) * 2 * A.L));
+    int lg = 0;
+    while ((1 << lg) < A.L) ++lg;
+    DSKI_HIP(hipMalloc(&A.twiddle, sizeof(double) * 2 * fft_tw_size(lg)));
     DSKI_HIP(hipMalloc(&A.spec, sizeof(double) * A.L));
     DSKI_HIP(hipMalloc(&A.dspec, sizeof(double) * A.L));
     DSKI_HIP(hipMalloc(&A.col, sizeof(double) * A.m));
-    k_twiddle<<<(A.L + kBlock - 1) / kBlock, kBlock, 0, st>>>(A.L, A.twiddle);
+    k_twiddle<<<(fft_tw_size(lg) + kBlock - 1) / kBlock, kBlock, 0, st>>>(lg, A.twiddle);
     DSKI_HIP(hipGetLastError());
   }
   // temporaries

@@ -170,3 +170,27 @@ def test_dense_kuu_variant_matches_oracle(idx):
     times = plan.autotune(5, 10)
     say("  tuner K_UU us", times["kuu_us"])
     assert rel_cols(plan.mvm(Vd).cpu().numpy().T, op.matvec(V)).max() < 1e-12
+
+
+@pytest.mark.parametrize("m", [[600, 12], [12, 300], [1000]])
+def test_mvm_long_axes_match_oracle(m):
+    """Grid axes whose circulant length is 1024 or 2048 (the largest FFT), as the
+    strided and as the contiguous axis, in FP64 to 1e-12 and FP32 storage to 1e-5."""
+    dski = need_gpu()
+    from oracle import dski as odski
+    say("long axes", m)
+    d = len(m)
+    X = np.random.default_rng(21).random((300, d))
+    ell = np.log(np.full(d, 0.05))
+    plan = dski.Plan(torch.tensor(X, device="cuda"), m, [0] * d, [1] * d)
+    plan.set_hypers(ell, 0.1, np.log(0.05), np.log(0.1))
+    op = odski.DSKI(X, m, [0] * d, [1] * d, ell, 0.1, np.log(0.05), np.log(0.1))
+    V = np.random.default_rng(22).standard_normal((op.N, 3))
+    Y = plan.mvm(torch.tensor(V.T.copy(), device="cuda")).cpu().numpy().T
+    err = rel_cols(Y, op.matvec(V)).max()
+    say("  fp64 max rel err", err)
+    assert err < 1e-12
+    Yd = plan.mvm_dtheta(0, torch.tensor(V.T.copy(), device="cuda")).cpu().numpy().T
+    assert rel_cols(Yd, op.matvec_dtheta(0, V)).max() < 1e-12
+    Vf = V.astype(np.float32).astype(np.float64)
+    assert rel_cols(from_gpu(plan.mvm(to_gpu(Vf))), op.matvec(Vf)).max() < TOL_MVM
