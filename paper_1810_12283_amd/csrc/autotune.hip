@@ -1,5 +1,6 @@
-// Per-shape autotuning of kernel variants.  The scatter (W^T) has an LDS-tiled
-// and two cache-direct forms with identical results; the preconditioner
+// Per-shape autotuning of kernel variants.  The scatter (W^T) has two LDS-tiled
+// forms (column values held in LDS in the input type or in FP64) and two
+// cache-direct forms, all with identical results; the preconditioner
 // projection (U^T v) has three row-tile heights (partials differ, reduced in a
 // fixed order).  Which is faster depends on the grid size, the number of points
 // per cell, the rank and the number of right-hand sides.  The tuner times each
@@ -12,7 +13,8 @@
 
 namespace dski {
 
-constexpr int kTuneTimes = 6 + 2 * DSKI_MAXD;
+constexpr int kScatterVariants = 4;
+constexpr int kTuneTimes = kScatterVariants + 3 + 2 * DSKI_MAXD;
 
 __global__ void k_fill_pm1(float* __restrict__ out, size_t len, uint64_t seed) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
@@ -73,7 +75,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
   int best_s = 0;
   if (p->kind == 0) DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
   double* G = p->grid.as<double>();
-  for (int v = 0; v < (p->kind == 0 ? 3 : 0); ++v) {
+  for (int v = 0; v < (p->kind == 0 ? kScatterVariants : 0); ++v) {
     p->scatter_variant = v;
     DSKI_TRY(time_us([&]() { return scatter<float>(p, R, V, N, G, st); }, reps, st, &t[v]));
     if (t[v] < t[best_s]) best_s = v;
@@ -83,8 +85,9 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
   for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     int best = 0;
     for (int v = 0; v < 2; ++v) {
-      DSKI_TRY(time_us([&]() { return kuu_axis(p, R, G, st, -1, a, v); }, reps, st, &t[6 + 2 * a + v]));
-      if (t[6 + 2 * a + v] < t[6 + 2 * a + best]) best = v;
+      double* ta = t + kScatterVariants + 3 + 2 * a;
+      DSKI_TRY(time_us([&]() { return kuu_axis(p, R, G, st, -1, a, v); }, reps, st, &ta[v]));
+      if (ta[v] < ta[best]) best = v;
     }
     p->kuu_variant[a] = best;
   }
@@ -99,8 +102,8 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
       p->proj_variant = v;
       ProjPlan L = proj_plan(k, R, proj_rows(p));
       DSKI_TRY(time_us([&]() { return launch_proj<float>(V, N, N, p->n, R, 1.0, 1.0, Ud, k, L, part, st); }, reps,
-                       st, &t[3 + v]));
-      if (t[3 + v] < t[3 + best_p]) best_p = v;
+                       st, &t[kScatterVariants + v]));
+      if (t[kScatterVariants + v] < t[kScatterVariants + best_p]) best_p = v;
     }
     DSKI_HIP(hipStreamSynchronize(st));
     ubuf.release();
@@ -114,7 +117,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
 }
 
 extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant, int proj_variant) {
-  if (!p || scatter_variant < 0 || scatter_variant > 2 || proj_variant < 0 || proj_variant > 2) {
+  if (!p || scatter_variant < 0 || scatter_variant >= kScatterVariants || proj_variant < 0 || proj_variant > 2) {
     set_error("dski_set_variants: bad arguments");
     return DSKI_EINVAL;
   }

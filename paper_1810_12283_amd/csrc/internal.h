@@ -121,7 +121,8 @@ struct dski_plan_s {
   dski::DevBuf scal;           // FP64 small scalars
   int precision = 32;          // storage of N-vectors inside slq_logdet (32 or 64)
   // kernel variants chosen by dski_autotune (defaults: the LDS-tiled kernels)
-  int scatter_variant = 0;     // 0 LDS node tiles, 1 direct 1 column/thread, 2 direct 2 columns/thread
+  int scatter_variant = 0;     // 0 LDS node tiles, 1 direct 1 column/thread, 2 direct 2 columns/thread,
+                               // 3 LDS node tiles with FP64 column values
   int proj_variant = 0;        // rows per projection tile: 0 -> 128, 1 -> 64, 2 -> 256
   int use_graph = 1;           // PCG bursts replayed from a captured HIP graph
   int kuu_variant[DSKI_MAXD] = {0, 0, 0};  // per axis: 0 FFT, 1 dense matrix-core product

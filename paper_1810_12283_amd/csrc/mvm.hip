@@ -41,12 +41,14 @@ static GeoK geo_of(dski_plan p) {
 // Cell c (1-based per axis) covers nodes c-1..c+2, so node j is touched by
 // cells j-2..j+1 (clipped to 1..m-3); its stencil position in cell c is j-c+1.
 // LDS-staged version: a work-group owns a tile of grid nodes and one chunk of
-// CR columns.  It copies into LDS the offsets and the CR column values of every
+// CR columns.  It copies into LDS the weights and the CR column values of every
 // point in the cells whose stencils reach the tile (the tile's cells plus a
 // halo of 2 below / 1 above), with a table of each cell's range, then every
 // thread sums its node's contributions from LDS in the same fixed order as
-// above.  Regions with more than PMAX points fall back to reading through the
-// cache (same order, same result).
+// above.  Up to PMAX = 256 region points one thread stages one point; regions
+// with more points fall back to reading through the cache (same order, same
+// result).  VS is the type the column values are held in LDS (the input type,
+// or FP64 to convert once at staging).
 template <int D>
 struct TileShape {
   static constexpr int e0 = D == 1 ? 256 : (D == 2 ? 16 : 4);
@@ -55,22 +57,24 @@ struct TileShape {
   static __host__ __device__ constexpr int ext(int a) { return a == 0 ? e0 : (a == 1 ? e1 : e2); }
   static constexpr int max_cells = D == 1 ? (e0 + 3) : (D == 2 ? (e0 + 3) * (e1 + 3) : (e0 + 3) * (e1 + 3) * (e2 + 3));
   static constexpr int max_rows = D == 1 ? 1 : (D == 2 ? (e0 + 3) : (e0 + 3) * (e1 + 3));
+  static constexpr int last_span = ext(D - 1) + 3;
 };
 
-template <int D, int CR, typename T, int PMAX>
+template <int D, int CR, typename T, typename VS, int PMAX>
 __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cell,
                                                      const double* __restrict__ wts,
                                                      const int* __restrict__ cstart, int n, GeoK g,
                                                      const T* __restrict__ V, int ldv, int R, int cr,
                                                      double* __restrict__ G, long long M) {
+  static_assert(PMAX == 256, "one thread stages one region point");
   using TS = TileShape<D>;
   __shared__ double s_w[D * 8][PMAX];
-  __shared__ T s_v[PMAX * CR * (D + 1)];
+  __shared__ VS s_v[PMAX * CR * (D + 1)];
   __shared__ int s_lcs[TS::max_cells + 1];
   __shared__ int s_rcnt[TS::max_rows];
   __shared__ int s_roff[TS::max_rows + 1];
   __shared__ int s_rg0[TS::max_rows];
-  __shared__ int s_qk[PMAX];
+  __shared__ int s_rcb[TS::max_rows];
   const int last = D - 1;
   // tile origin and this thread's node
   int origin[D], span[D], rlo[D], jl[D];
@@ -106,17 +110,17 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   const int rc = min(cr, R - r0);
   // per-row global ranges (rows = all region axes but the last; cells of a row are contiguous)
   for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
-    int rem = row, base = 0, mul = 1;
+    int rem = row, base = 0;
     int c[D];
     for (int a = last - 1; a >= 0; --a) {
       c[a] = rlo[a] + rem % span[a];
       rem /= span[a];
     }
     for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
-    base *= g.nc[last];
-    (void)mul;
-    int g0 = cstart[base + rlo[last] - 1];
-    int g1 = cstart[base + rlo[last] - 1 + span[last]];
+    base = base * g.nc[last] + rlo[last] - 1;
+    const int g0 = cstart[base];
+    const int g1 = cstart[base + span[last]];
+    s_rcb[row] = base;
     s_rg0[row] = g0;
     s_rcnt[row] = g1 - g0;
   }
@@ -124,8 +128,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   // exclusive prefix of the row counts (wavefront 0, 64 rows per step)
   if (threadIdx.x < 64) {
     int carry = 0;
-    for (int r0 = 0; r0 < nrows; r0 += 64) {
-      const int row = r0 + threadIdx.x;
+    for (int rb = 0; rb < nrows; rb += 64) {
+      const int row = rb + threadIdx.x;
       const int v = row < nrows ? s_rcnt[row] : 0;
       int incl = v;
 #pragma unroll
@@ -142,67 +146,36 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   const int total = s_roff[nrows];
   const bool lds_ok = total <= PMAX;
   if (lds_ok) {
-    // cell table (region-local, row-major) -> LDS point ranges; and for every LDS
-    // slot the global (tile-order) index of its point (binary search of the row)
-    for (int f = threadIdx.x; f < ncells_r; f += blockDim.x) {
-      int row = f / span[last], cl = f % span[last];
-      int rem = row, base = 0;
-      int c[D];
-      for (int a = last - 1; a >= 0; --a) {
-        c[a] = rlo[a] + rem % span[a];
-        rem /= span[a];
-      }
-      for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
-      base *= g.nc[last];
-      s_lcs[f] = cstart[base + rlo[last] - 1 + cl] - s_rg0[row] + s_roff[row];
+    // cell table (region-local, row-major) -> LDS point ranges
+    for (int f = threadIdx.x; f < nrows * TS::last_span; f += blockDim.x) {
+      const int row = f / TS::last_span, cl = f % TS::last_span;
+      if (cl < span[last])
+        s_lcs[row * span[last] + cl] = cstart[s_rcb[row] + cl] - s_rg0[row] + s_roff[row];
     }
     if (threadIdx.x == 0) s_lcs[ncells_r] = total;
-    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    // this thread's region point: its row by binary search of the row offsets,
+    // then its weights and column values (zero beyond the chunk)
+    const int q = threadIdx.x;
+    if (q < total) {
       int lo_r = 0, hi_r = nrows - 1;  // last row with s_roff[row] <= q
       while (lo_r < hi_r) {
         const int mid = (lo_r + hi_r + 1) >> 1;
         if (s_roff[mid] <= q) lo_r = mid; else hi_r = mid - 1;
       }
-      s_qk[q] = s_rg0[lo_r] + q - s_roff[lo_r];
-    }
-  }
-  __syncthreads();
-  if (lds_ok) {
-    // loads of the region issued four per thread at a time; the value slots of
-    // columns beyond this chunk are zero so the accumulation needs no branches
-    const int totw = total * D * 8;
-    for (int f0 = threadIdx.x; f0 < totw; f0 += 1024) {
-      double w4[4];
+      const int kq = s_rg0[lo_r] + q - s_roff[lo_r];
+      double w[D * 8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        w4[u] = f < totw ? wts[(size_t)(f / total) * n + s_qk[f % total]] : 0.0;
-      }
+      for (int a8 = 0; a8 < D * 8; ++a8) w[a8] = wts[(size_t)a8 * n + kq];
+      VS x[CR * (D + 1)];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        if (f < totw) s_w[f / total][f % total] = w4[u];
-      }
-    }
-    const int tot = total * CR * (D + 1);
-    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-      T v4[4];
+      for (int r = 0; r < CR; ++r)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        const int q = f % total, rest = f / total;
-        const int b = rest % (D + 1), r = rest / (D + 1);
-        v4[u] = (f < tot && r < rc) ? V[(size_t)(r0 + r) * ldv + (size_t)b * n + s_qk[q]] : (T)0;
-      }
+        for (int b = 0; b <= D; ++b)
+          x[r * (D + 1) + b] = r < rc ? (VS)V[(size_t)(r0 + r) * ldv + (size_t)b * n + kq] : (VS)0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = f0 + 256 * u;
-        if (f < tot) {
-          const int q = f % total, rest = f / total;
-          const int b = rest % (D + 1), r = rest / (D + 1);
-          s_v[(q * CR + r) * (D + 1) + b] = v4[u];
-        }
-      }
+      for (int a8 = 0; a8 < D * 8; ++a8) s_w[a8][q] = w[a8];
+#pragma unroll
+      for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
     }
   }
   __syncthreads();
@@ -262,7 +235,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
             for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
             dprod[qq] = v;
           }
-          const T* sv = s_v + (size_t)q * CR * (D + 1);
+          const VS* sv = s_v + (size_t)q * CR * (D + 1);
 #pragma unroll
           for (int r = 0; r < CR; ++r) {  // columns beyond rc hold zeros
             double a = wprod * (double)sv[r * (D + 1)];
@@ -322,7 +295,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
 }
 
 template <int D, typename T>
-static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
+static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st, bool wide) {
   GeoK g = geo_of(p);
   using TS = TileShape<D>;
   long long tiles = 1;
@@ -332,8 +305,12 @@ static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, h
   const int nch = (R + CR - 1) / CR;
   const int cr = (R + nch - 1) / nch;
   dim3 grid((unsigned)tiles, nch);
-  k_scatter_lds<D, CR, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv,
-                                                      R, cr, G, p->M);
+  if (wide)
+    k_scatter_lds<D, CR, T, double, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V,
+                                                                ldv, R, cr, G, p->M);
+  else
+    k_scatter_lds<D, CR, T, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv,
+                                                           R, cr, G, p->M);
 }
 
 // Direct variant: one thread per (grid node, CRD columns), no LDS; cell ranges,
@@ -439,7 +416,7 @@ static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, double* G,
   else if (p->scatter_variant == 2)
     launch_scatter_direct<D, 2, T>(p, R, V, ldv, G, st);
   else
-    launch_scatter<D, T>(p, R, V, ldv, G, st);
+    launch_scatter<D, T>(p, R, V, ldv, G, st, p->scatter_variant == 3);
 }
 
 template <typename T>

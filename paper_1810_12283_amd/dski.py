@@ -248,10 +248,10 @@ class Plan:
 
     def autotune(self, R: int, k: int, stream=None) -> dict:
         """Time the kernel variants for this shape and keep the fastest."""
-        t = (C.c_double * 12)()
+        t = (C.c_double * 13)()
         _check(lib().dski_autotune(self._h, int(R), int(k), t, _stream(stream)), "dski_autotune")
-        return {"scatter_us": [t[0], t[1], t[2]], "proj_us": [t[3], t[4], t[5]],
-                "kuu_us": [[t[6 + 2 * a], t[7 + 2 * a]] for a in range(min(self.d, 3))]}
+        return {"scatter_us": [t[0], t[1], t[2], t[3]], "proj_us": [t[4], t[5], t[6]],
+                "kuu_us": [[t[7 + 2 * a], t[8 + 2 * a]] for a in range(min(self.d, 3))]}
 
     def set_variants(self, scatter: int, proj: int):
         _check(lib().dski_set_variants(self._h, int(scatter), int(proj)), "dski_set_variants")
