@@ -40,6 +40,35 @@ static GeoK geo_of(dski_plan p) {
 //   w(x_k)_j V_0[k] + sum_q d_q w(x_k)_j V_q[k].
 // Cell c (1-based per axis) covers nodes c-1..c+2, so node j is touched by
 // cells j-2..j+1 (clipped to 1..m-3); its stencil position in cell c is j-c+1.
+// The contribution of one point to one node for CR columns: the stencil
+// weights of the node on every axis (value wv, derivative wd) form
+// w = prod wv and d_q w = wd_q prod_{a != q} wv_a, and each column adds
+// w V_0 + sum_q d_q w V_q as one FMA chain (x holds the CR x (D + 1) values,
+// column-major by column).  Every scatter form calls this, so all give the
+// same bits.
+template <int D, int CR, typename VT>
+__device__ __forceinline__ void scatter_accum(double (&acc)[CR], const double (&wv)[D], const double (&wd)[D],
+                                              const VT* x) {
+  double wprod = wv[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) wprod *= wv[a];
+  double dprod[D];
+#pragma unroll
+  for (int qq = 0; qq < D; ++qq) {
+    double v = qq == 0 ? wd[0] : wv[0];
+#pragma unroll
+    for (int a = 1; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
+    dprod[qq] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < CR; ++r) {
+    double s = fma(wprod, (double)x[r * (D + 1)], acc[r]);
+#pragma unroll
+    for (int qq = 0; qq < D; ++qq) s = fma(dprod[qq], (double)x[r * (D + 1) + qq + 1], s);
+    acc[r] = s;
+  }
+}
+
 // LDS-staged version: a work-group owns a tile of grid nodes and one chunk of
 // CR columns.  It copies into LDS the weights and the CR column values of every
 // point in the cells whose stencils reach the tile (the tile's cells plus a
@@ -75,6 +104,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   __shared__ int s_roff[TS::max_rows + 1];
   __shared__ int s_rg0[TS::max_rows];
   __shared__ int s_rcb[TS::max_rows];
+  __shared__ int s_cl[PMAX];  // last-axis cell (1-based) of every region point
   const int last = D - 1;
   // tile origin and this thread's node
   int origin[D], span[D], rlo[D], jl[D];
@@ -163,6 +193,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
         if (s_roff[mid] <= q) lo_r = mid; else hi_r = mid - 1;
       }
       const int kq = s_rg0[lo_r] + q - s_roff[lo_r];
+      const int ck = cell[kq];
       double w[D * 8];
 #pragma unroll
       for (int a8 = 0; a8 < D * 8; ++a8) w[a8] = wts[(size_t)a8 * n + kq];
@@ -176,6 +207,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
       for (int a8 = 0; a8 < D * 8; ++a8) s_w[a8][q] = w[a8];
 #pragma unroll
       for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
+      s_cl[q] = ck % g.nc[last] + 1;
     }
   }
   __syncthreads();
@@ -190,99 +222,87 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   double acc[CR];
 #pragma unroll
   for (int r = 0; r < CR; ++r) acc[r] = 0.0;
-  int lo[D], hi[D];
+  int lo[D], hi[D], c[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     lo[a] = max(1, j[a] - 2);
     hi[a] = min(g.nc[a], j[a] + 1);
+    c[a] = lo[a];
   }
-  int outer_cnt = 1;
-#pragma unroll
-  for (int a = 0; a < last; ++a) outer_cnt *= hi[a] - lo[a] + 1;
-  for (int oc = 0; oc < outer_cnt; ++oc) {
-    int c[D];
-    int rem = oc;
-#pragma unroll
-    for (int a = last - 1; a >= 0; --a) {
-      int sp = hi[a] - lo[a] + 1;
-      c[a] = lo[a] + rem % sp;
-      rem /= sp;
-    }
-    if (lds_ok) {
+  if (lds_ok) {
+    // The node's points in the fixed order: outer cells c[0..last-1] in
+    // odometer order, and for each the contiguous run of points of cells
+    // lo..hi on the last axis.  All runs are walked as one sequence, so a
+    // wavefront iterates as often as its busiest node has points.
+    auto run = [&](int& q, int& qe) {
       int lrow = 0;
 #pragma unroll
       for (int a = 0; a < last; ++a) lrow = lrow * span[a] + (c[a] - rlo[a]);
-      for (int cl = lo[last]; cl <= hi[last]; ++cl) {
-        int lc = lrow * span[last] + (cl - rlo[last]);
-        int q0 = s_lcs[lc], q1 = s_lcs[lc + 1];
-        for (int q = q0; q < q1; ++q) {
-          double wv[D], wd[D];
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            int ca = (a == last) ? cl : c[a];
-            int o = j[a] - ca + 1;
-            wv[a] = s_w[a * 8 + o][q];
-            wd[a] = s_w[a * 8 + 4 + o][q];
-          }
-          double wprod = 1.0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) wprod *= wv[a];
-          double dprod[D];
-#pragma unroll
-          for (int qq = 0; qq < D; ++qq) {
-            double v = 1.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
-            dprod[qq] = v;
-          }
-          const VS* sv = s_v + (size_t)q * CR * (D + 1);
-#pragma unroll
-          for (int r = 0; r < CR; ++r) {  // columns beyond rc hold zeros
-            double a = wprod * (double)sv[r * (D + 1)];
-#pragma unroll
-            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)sv[r * (D + 1) + qq + 1];
-            acc[r] += a;
-          }
+      q = s_lcs[lrow * span[last] + lo[last] - rlo[last]];
+      qe = s_lcs[lrow * span[last] + hi[last] - rlo[last] + 1];
+    };
+    int q, qe;
+    run(q, qe);
+    while (true) {
+      bool done = false;
+      while (q >= qe) {
+        int a = last - 1;
+        while (a >= 0 && c[a] == hi[a]) {
+          c[a] = lo[a];
+          --a;
         }
+        if (a < 0) {
+          done = true;
+          break;
+        }
+        ++c[a];
+        run(q, qe);
       }
-    } else {
-      int base = 0;
+      if (done) break;
+      double wv[D], wd[D];
+      const int cl = s_cl[q];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int o = j[a] - (a == last ? cl : c[a]) + 1;
+        wv[a] = s_w[a * 8 + o][q];
+        wd[a] = s_w[a * 8 + 4 + o][q];
+      }
+      scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)q * CR * (D + 1));
+      ++q;
+    }
+  } else {
+    int outer_cnt = 1;
+#pragma unroll
+    for (int a = 0; a < last; ++a) outer_cnt *= hi[a] - lo[a] + 1;
+    for (int oc = 0; oc < outer_cnt; ++oc) {
+      int rem = oc, base = 0;
+#pragma unroll
+      for (int a = last - 1; a >= 0; --a) {
+        int sp = hi[a] - lo[a] + 1;
+        c[a] = lo[a] + rem % sp;
+        rem /= sp;
+      }
 #pragma unroll
       for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
       base *= g.nc[last];
-      int kb = cstart[base + lo[last] - 1];
-      int ke = cstart[base + hi[last]];
+      const int kb = cstart[base + lo[last] - 1];
+      const int ke = cstart[base + hi[last]];
       for (int k = kb; k < ke; ++k) {
-        int clast = cell[k] % g.nc[last] + 1;
+        const int clast = cell[k] % g.nc[last] + 1;
         double wv[D], wd[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          int ca = (a == last) ? clast : c[a];
-          int o = j[a] - ca + 1;
+          const int o = j[a] - ((a == last) ? clast : c[a]) + 1;
           wv[a] = wts[(size_t)(a * 8 + o) * n + k];
           wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
         }
-        double wprod = 1.0;
+        T x[CR * (D + 1)];
 #pragma unroll
-        for (int a = 0; a < D; ++a) wprod *= wv[a];
-        double dprod[D];
+        for (int r = 0; r < CR; ++r)
 #pragma unroll
-        for (int qq = 0; qq < D; ++qq) {
-          double v = 1.0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
-          dprod[qq] = v;
-        }
-#pragma unroll
-        for (int r = 0; r < CR; ++r) {
-          if (r < rc) {
-            const T* vv = V + (size_t)(r0 + r) * ldv + k;
-            double a = wprod * (double)vv[0];
-#pragma unroll
-            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)vv[(size_t)(qq + 1) * n];
-            acc[r] += a;
-          }
-        }
+          for (int b2 = 0; b2 <= D; ++b2)
+            x[r * (D + 1) + b2] = r < rc ? V[(size_t)(r0 + r) * ldv + (size_t)b2 * n + k] : (T)0;
+        scatter_accum<D, CR>(acc, wv, wd, x);
       }
     }
   }
@@ -373,27 +393,13 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
           wv[a] = wts[(size_t)(a * 8 + o) * n + k];
           wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
         }
-        double wprod = 1.0;
+        T x[CRD * (D + 1)];
 #pragma unroll
-        for (int a = 0; a < D; ++a) wprod *= wv[a];
-        double dprod[D];
+        for (int r = 0; r < CRD; ++r)
 #pragma unroll
-        for (int qq = 0; qq < D; ++qq) {
-          double v = 1.0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) v *= (a == qq) ? wd[a] : wv[a];
-          dprod[qq] = v;
-        }
-#pragma unroll
-        for (int r = 0; r < CRD; ++r) {
-          if (r < rc) {
-            const T* vv = V + (size_t)(r0 + r) * ldv + k;
-            double a = wprod * (double)vv[0];
-#pragma unroll
-            for (int qq = 0; qq < D; ++qq) a += dprod[qq] * (double)vv[(size_t)(qq + 1) * n];
-            acc[r] += a;
-          }
-        }
+          for (int b2 = 0; b2 <= D; ++b2)
+            x[r * (D + 1) + b2] = r < rc ? V[(size_t)(r0 + r) * ldv + (size_t)b2 * n + k] : (T)0;
+        scatter_accum<D, CRD>(acc, wv, wd, x);
       }
     }
   }
