@@ -159,21 +159,19 @@ dski_status dski_mvm_tiled_f64(dski_plan plan, int R, const double* V, int ldv, 
 dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int ldv, float* Y,
                            int ldy, dski_stream stream);
 
-/* Times the interchangeable kernel variants for R right-hand sides and
- * preconditioner rank k on this plan's shape (scatter: LDS node tiles with the
- * column values in the input type / direct one column per thread / direct two
- * columns per thread / LDS node tiles with FP64 column values; preconditioner
- * projection: row tiles of 128 / 64 / 256 rows per work-group; K_UU factor of
+/* Times the interchangeable kernel variants for R right-hand sides on this
+ * plan's shape (scatter: LDS node tiles with the base number of columns per
+ * work-group / direct one column per thread / direct two columns per thread /
+ * LDS node tiles with 1.5 and with 2 times the base columns; K_UU factor of
  * each axis: circulant FFT / dense Toeplitz product on the FP64 matrix cores)
  * and keeps the fastest of each.  All scatter variants give bitwise-identical
- * results; projections and K_UU variants agree up to rounding.  times_host
- * (13 entries, may be NULL) receives the measured microseconds: scatter (4),
- * projection (3), then FFT and dense for axes 0, 1, 2 (scatter and K_UU
- * entries are 0 for a D-SKIP plan).  1 <= R <= 32, 0 <= k <= 256. */
-dski_status dski_autotune(dski_plan plan, int R, int k, double* times_host, dski_stream stream);
+ * results; the K_UU variants agree up to rounding.  times_host (11 entries,
+ * may be NULL) receives the measured microseconds: scatter (5), then FFT and
+ * dense for axes 0, 1, 2 (all 0 for a D-SKIP plan).  1 <= R <= 32. */
+dski_status dski_autotune(dski_plan plan, int R, double* times_host, dski_stream stream);
 
-/* Select the variants directly (scatter 0..3, projection 0..2). */
-dski_status dski_set_variants(dski_plan plan, int scatter_variant, int proj_variant);
+/* Select the scatter variant directly (0..4). */
+dski_status dski_set_variants(dski_plan plan, int scatter_variant);
 
 /* K_UU factor of one axis: 0 circulant FFT, 1 dense Toeplitz product on the
  * matrix cores (grid size <= 448 on that axis; larger axes keep the FFT). */

@@ -1,20 +1,18 @@
-// Per-shape autotuning of kernel variants.  The scatter (W^T) has two LDS-tiled
-// forms (column values held in LDS in the input type or in FP64) and two
-// cache-direct forms, all with identical results; the preconditioner
-// projection (U^T v) has three row-tile heights (partials differ, reduced in a
-// fixed order).  Which is faster depends on the grid size, the number of points
-// per cell, the rank and the number of right-hand sides.  The tuner times each
-// candidate with HIP events on the caller's stream and keeps the fastest in the
-// plan.
+// Per-shape autotuning of kernel variants.  The scatter (W^T) has three
+// LDS-tiled forms (base, 1.5 and 2 times the base number of columns per
+// work-group) and two cache-direct forms, all with identical results; each K_UU factor has a
+// circulant-FFT and a dense matrix-core form (equal up to rounding).  Which is
+// faster depends on the grid size, the number of points per cell and the
+// number of right-hand sides.  The tuner times each candidate with HIP events
+// on the caller's stream and keeps the fastest in the plan.
 #include <cmath>
 
 #include "internal.h"
-#include "tskinny.h"
 
 namespace dski {
 
-constexpr int kScatterVariants = 4;
-constexpr int kTuneTimes = kScatterVariants + 3 + 2 * DSKI_MAXD;
+constexpr int kScatterVariants = 5;
+constexpr int kTuneTimes = kScatterVariants + 2 * DSKI_MAXD;
 
 __global__ void k_fill_pm1(float* __restrict__ out, size_t len, uint64_t seed) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
@@ -52,24 +50,20 @@ static dski_status time_us(F&& fn, int reps, hipStream_t st, double* us) {
 
 using namespace dski;
 
-extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_host, dski_stream stream) {
-  if (!p || R <= 0 || R > 32 || k < 0 || k > 256) {
-    set_error("dski_autotune: bad arguments (1 <= R <= 32, 0 <= k <= 256)");
+extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dski_stream stream) {
+  if (!p || R <= 0 || R > 32) {
+    set_error("dski_autotune: bad arguments (1 <= R <= 32)");
     return DSKI_EINVAL;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int N = p->N;
   const int reps = 10;
   DevBuf buf;
-  size_t nv = (size_t)N * R, nu = (size_t)N * std::max(k, 1);
-  DSKI_TRY(buf.reserve(sizeof(float) * (nv + nu) + sizeof(double) * (2 * (size_t)std::max(k, 1) * R +
-                                                                      (size_t)std::max(k, 1) * R *
-                                                                          ((N + 7) / 8 + 1)) + 1024));
+  const size_t nv = (size_t)N * R;
+  DSKI_TRY(buf.reserve(sizeof(float) * nv + 64));
   float* V = buf.as<float>();
-  double* coef = reinterpret_cast<double*>(buf.as<char>() + ((sizeof(float) * (nv + nu) + 63) / 64) * 64);
-  double* part = coef + (size_t)std::max(k, 1) * R;
   k_fill_pm1<<<1024, 256, 0, st>>>(V, nv, 12345);
-  DSKI_HIP(hipMemsetAsync(coef, 0, sizeof(double) * (size_t)std::max(k, 1) * R, st));
+  DSKI_HIP(hipGetLastError());
   double t[kTuneTimes] = {0};
   // scatter variants (D-SKI plans only)
   int best_s = 0;
@@ -85,30 +79,12 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
   for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     int best = 0;
     for (int v = 0; v < 2; ++v) {
-      double* ta = t + kScatterVariants + 3 + 2 * a;
+      double* ta = t + kScatterVariants + 2 * a;
       DSKI_TRY(time_us([&]() { return kuu_axis(p, R, G, st, -1, a, v); }, reps, st, &ta[v]));
       if (ta[v] < ta[best]) best = v;
     }
     p->kuu_variant[a] = best;
   }
-  // projection row tiles (128, 64, 256 rows per work-group) on a dummy FP64 factor
-  int best_p = 0;
-  if (k > 0) {
-    DevBuf ubuf;
-    DSKI_TRY(ubuf.reserve(sizeof(double) * nu));
-    double* Ud = ubuf.as<double>();
-    DSKI_HIP(hipMemsetAsync(Ud, 0, sizeof(double) * nu, st));
-    for (int v = 0; v < 3; ++v) {
-      p->proj_variant = v;
-      ProjPlan L = proj_plan(k, R, proj_rows(p));
-      DSKI_TRY(time_us([&]() { return launch_proj<float>(V, N, N, p->n, R, 1.0, 1.0, Ud, k, L, part, st); }, reps,
-                       st, &t[kScatterVariants + v]));
-      if (t[kScatterVariants + v] < t[kScatterVariants + best_p]) best_p = v;
-    }
-    DSKI_HIP(hipStreamSynchronize(st));
-    ubuf.release();
-  }
-  p->proj_variant = best_p;
   DSKI_HIP(hipStreamSynchronize(st));
   buf.release();
   if (times_host)
@@ -116,13 +92,12 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, int k, double* times_ho
   return DSKI_OK;
 }
 
-extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant, int proj_variant) {
-  if (!p || scatter_variant < 0 || scatter_variant >= kScatterVariants || proj_variant < 0 || proj_variant > 2) {
+extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant) {
+  if (!p || scatter_variant < 0 || scatter_variant >= kScatterVariants) {
     set_error("dski_set_variants: bad arguments");
     return DSKI_EINVAL;
   }
   p->scatter_variant = scatter_variant;
-  p->proj_variant = proj_variant;
   return DSKI_OK;
 }
 

@@ -14,6 +14,16 @@
 
 namespace dski {
 
+// p[i] when ok, else zero, without a branch: the load is issued from index i
+// or from the valid index `safe`, and the value selected afterwards, so that
+// neighbouring loads stay in flight together (a load under a branch is waited
+// for inside the branch).
+template <typename T>
+__device__ __forceinline__ T ld_or0(const T* __restrict__ p, size_t i, size_t safe, bool ok) {
+  const T v = p[ok ? i : safe];
+  return ok ? v : (T)0;
+}
+
 void set_error(const char* fmt, ...);
 
 struct HipError {
@@ -122,8 +132,7 @@ struct dski_plan_s {
   int precision = 32;          // storage of N-vectors inside slq_logdet (32 or 64)
   // kernel variants chosen by dski_autotune (defaults: the LDS-tiled kernels)
   int scatter_variant = 0;     // 0 LDS node tiles, 1 direct 1 column/thread, 2 direct 2 columns/thread,
-                               // 3 LDS node tiles with FP64 column values
-  int proj_variant = 0;        // rows per projection tile: 0 -> 128, 1 -> 64, 2 -> 256
+                               // 3 / 4 LDS node tiles with 1.5 / 2 times the columns per work-group
   int use_graph = 1;           // PCG bursts replayed from a captured HIP graph
   int kuu_variant[DSKI_MAXD] = {0, 0, 0};  // per axis: 0 FFT, 1 dense matrix-core product
 };
@@ -175,7 +184,6 @@ template <typename T>
 dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int ld, T* Z, int ldz,
                                        hipStream_t st);
 int vec_blocks(int N);
-int proj_rows(dski_plan p);  // rows per projection tile of the chosen variant
 
 // --- PCG core (tile order) -----------------------------------------------------------
 struct PcgResult {

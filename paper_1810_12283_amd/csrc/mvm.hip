@@ -202,7 +202,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
       for (int r = 0; r < CR; ++r)
 #pragma unroll
         for (int b = 0; b <= D; ++b)
-          x[r * (D + 1) + b] = r < rc ? (VS)V[(size_t)(r0 + r) * ldv + (size_t)b * n + kq] : (VS)0;
+          x[r * (D + 1) + b] = (VS)ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
+                                          (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
 #pragma unroll
       for (int a8 = 0; a8 < D * 8; ++a8) s_w[a8][q] = w[a8];
 #pragma unroll
@@ -301,7 +302,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
         for (int r = 0; r < CR; ++r)
 #pragma unroll
           for (int b2 = 0; b2 <= D; ++b2)
-            x[r * (D + 1) + b2] = r < rc ? V[(size_t)(r0 + r) * ldv + (size_t)b2 * n + k] : (T)0;
+            x[r * (D + 1) + b2] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b2 * n + k,
+                                         (size_t)r0 * ldv + (size_t)b2 * n + k, r < rc);
         scatter_accum<D, CR>(acc, wv, wd, x);
       }
     }
@@ -314,23 +316,29 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     if (r < rc) G[(size_t)(r0 + r) * M + node] = acc[r];
 }
 
-template <int D, typename T>
-static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st, bool wide) {
+// Columns per work-group of the LDS-tiled scatter: a base chunk (4 FP32 or 2
+// FP64 columns in 1-D and 2-D, half that in 3-D) times 1, 1.5 or 2; wider
+// chunks mean fewer work-groups, each staging its region once for more columns.
+template <int D, typename T, int WIDTH>
+constexpr int scatter_cr() {
+  constexpr int base = (sizeof(T) == 4 && D <= 2) ? 4 : (D <= 2 ? 2 : (sizeof(T) == 4 ? 2 : 1));
+  constexpr int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : 2 * base);
+  return D == 3 && cr > 3 ? 3 : cr;  // 3-D: the region tables leave room for 3 columns
+}
+
+template <int D, typename T, int WIDTH>
+static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
   GeoK g = geo_of(p);
   using TS = TileShape<D>;
   long long tiles = 1;
   for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
-  // columns per work-group: at most CR, chunks balanced (17 columns -> 5 x {4,4,3,3,3})
-  constexpr int CR = (sizeof(T) == 4 && D <= 2) ? 4 : (D <= 2 ? 2 : (sizeof(T) == 4 ? 2 : 1));
+  // columns per work-group: at most CR, chunks of equal width but the last
+  constexpr int CR = scatter_cr<D, T, WIDTH>();
   const int nch = (R + CR - 1) / CR;
   const int cr = (R + nch - 1) / nch;
   dim3 grid((unsigned)tiles, nch);
-  if (wide)
-    k_scatter_lds<D, CR, T, double, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V,
-                                                                ldv, R, cr, G, p->M);
-  else
-    k_scatter_lds<D, CR, T, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv,
-                                                           R, cr, G, p->M);
+  k_scatter_lds<D, CR, T, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv, R, cr,
+                                                         G, p->M);
 }
 
 // Direct variant: one thread per (grid node, CRD columns), no LDS; cell ranges,
@@ -398,7 +406,8 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
         for (int r = 0; r < CRD; ++r)
 #pragma unroll
           for (int b2 = 0; b2 <= D; ++b2)
-            x[r * (D + 1) + b2] = r < rc ? V[(size_t)(r0 + r) * ldv + (size_t)b2 * n + k] : (T)0;
+            x[r * (D + 1) + b2] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b2 * n + k,
+                                         (size_t)r0 * ldv + (size_t)b2 * n + k, r < rc);
         scatter_accum<D, CRD>(acc, wv, wd, x);
       }
     }
@@ -417,12 +426,13 @@ static void launch_scatter_direct(dski_plan p, int R, const T* V, int ldv, doubl
 
 template <int D, typename T>
 static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
-  if (p->scatter_variant == 1)
-    launch_scatter_direct<D, 1, T>(p, R, V, ldv, G, st);
-  else if (p->scatter_variant == 2)
-    launch_scatter_direct<D, 2, T>(p, R, V, ldv, G, st);
-  else
-    launch_scatter<D, T>(p, R, V, ldv, G, st, p->scatter_variant == 3);
+  switch (p->scatter_variant) {
+    case 1: launch_scatter_direct<D, 1, T>(p, R, V, ldv, G, st); break;
+    case 2: launch_scatter_direct<D, 2, T>(p, R, V, ldv, G, st); break;
+    case 3: launch_scatter<D, T, 1>(p, R, V, ldv, G, st); break;
+    case 4: launch_scatter<D, T, 2>(p, R, V, ldv, G, st); break;
+    default: launch_scatter<D, T, 0>(p, R, V, ldv, G, st); break;
+  }
 }
 
 template <typename T>

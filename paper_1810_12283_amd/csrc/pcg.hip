@@ -108,34 +108,40 @@ __global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, co
   }
 }
 
-// alpha, x and r updates, partials of r.r and of U^T D^{-1/2} r (row tile of
-// L.RT rows; the new r of the tile is kept in LDS for the projection).
-template <typename T, int TPT>
+// alpha, x and r updates, partials of r.r and of U^T D^{-1/2} r, one partial
+// per wavefront of 64 rows (the new r of those rows is kept in LDS for the
+// projection on the matrix cores).
+template <typename T, int CB>
 __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, const T* __restrict__ Q,
                                                     T* __restrict__ Rr, double* __restrict__ Xd, int N, int n,
                                                     int R, PcgScal s, int par, const double* __restrict__ pq_part,
                                                     int nb_pq, double* __restrict__ rr_part,
                                                     const double* __restrict__ U, int k, double isf, double isg,
-                                                    ProjPlan L, double* __restrict__ t_part,
-                                                    double* __restrict__ hist, int max_iter) {
+                                                    double* __restrict__ t_part, double* __restrict__ hist,
+                                                    int max_iter) {
   extern __shared__ __align__(16) char smem[];
-  double* sx = reinterpret_cast<double*>(smem);
-  double* sU = reinterpret_cast<double*>(smem + L.oU);
-  double* sred = reinterpret_cast<double*>(smem + L.ored);
+  constexpr int XP = ProjLds<CB>::XP, RC = 16 * CB;
   __shared__ double s_alpha[kPcgMaxR];
   __shared__ int s_act[kPcgMaxR];
   const int* act = s.active + par * R;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int c = wv; c < R; c += 4) {  // one wavefront per column
-    int on = act[c];
-    double pq = on ? wave_out_sum(pq_part, nb_pq, c) : 0.0;
-    if (lane == 0) {
+  {  // alpha of every column at once: 8 lanes per column, all loads in flight together
+    const int c = threadIdx.x >> 3, j = threadIdx.x & 7;
+    const bool col = c < R;
+    const int on = col ? act[c] : 0;
+    const double rz = col ? s.rz[par * R + c] : 0.0;
+    double pq = 0.0;
+    for (int b = j; b < nb_pq; b += 8) pq += ld_or0(pq_part, (size_t)(col ? c : 0) * nb_pq + b, 0, col);
+    pq += __shfl_xor(pq, 1, 64);
+    pq += __shfl_xor(pq, 2, 64);
+    pq += __shfl_xor(pq, 4, 64);
+    if (col && j == 0) {
       double a = 0.0;
       if (on) {
         if (!(pq > 0.0) || !isfinite(pq)) {
           if (blockIdx.x == 0) s.flags[1] = 1;
         } else {
-          a = s.rz[par * R + c] / pq;
+          a = rz / pq;
         }
         if (blockIdx.x == 0 && hist && s.iters[c] < max_iter) hist[(size_t)c * max_iter + s.iters[c]] = a;
       }
@@ -145,70 +151,72 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
     }
   }
   __syncthreads();
-  const int RT = L.RT, RP = L.RP;
-  const int e0 = blockIdx.x * RT;
-  const int rn = min(RT, N - e0);
-  const int tot = RT * RP;
-  for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-    double rv[4], pv[4], qv[4], xv[4];
-    bool ok[4], on[4];
-    size_t idx[4];
+  const int w = blockIdx.x * 4 + wv, nw = proj_waves(N);
+  if (w >= nw) return;
+  T* sx = reinterpret_cast<T*>(smem) + (size_t)wv * ProjLds<CB>::per_wave;
+  const int e0 = w * kProjRows, e = e0 + lane;
+  const bool in = e < N;
+  // x += alpha p, r -= alpha q on this thread's row, every column's loads in flight
+  T rv[RC], pv[RC], qv[RC];
+  double xv[RC];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = f0 + 256 * u;
-      const int c = f / RT, r = f % RT;
-      ok[u] = f < tot && c < R && r < rn;
-      on[u] = ok[u] && s_act[c];
-      idx[u] = (size_t)(ok[u] ? c : 0) * N + e0 + (ok[u] ? r : 0);
-      rv[u] = ok[u] ? (double)Rr[idx[u]] : 0.0;
-      pv[u] = on[u] ? (double)P[idx[u]] : 0.0;
-      qv[u] = on[u] ? (double)Q[idx[u]] : 0.0;
-      xv[u] = on[u] ? Xd[idx[u]] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = f0 + 256 * u;
-      if (on[u]) {
-        const double a = s_alpha[f / RT];
-        Xd[idx[u]] = xv[u] + a * pv[u];
-        const T rnew = (T)(rv[u] - a * qv[u]);
-        Rr[idx[u]] = rnew;
-        rv[u] = (double)rnew;
-      }
-      if (f < tot) sx[(f % RT) * RP + f / RT] = rv[u];
-    }
+  for (int c = 0; c < RC; ++c) {
+    const bool ok = in && c < R, on = ok && s_act[c];
+    const size_t idx = (size_t)(ok ? c : 0) * N + (in ? e : 0);
+    rv[c] = ld_or0(Rr, idx, 0, ok);
+    pv[c] = ld_or0(P, idx, 0, on);
+    qv[c] = ld_or0(Q, idx, 0, on);
+    xv[c] = ld_or0(Xd, idx, 0, on);
   }
-  __syncthreads();
-  for (int c = wv; c < R; c += 4) {
+#pragma unroll
+  for (int c = 0; c < RC; ++c) {
+    if (in && c < R && s_act[c]) {
+      const size_t idx = (size_t)c * N + e;
+      const double a = s_alpha[c];
+      Xd[idx] = xv[c] + a * (double)pv[c];
+      const T rnew = (T)((double)rv[c] - a * (double)qv[c]);
+      Rr[idx] = rnew;
+      rv[c] = rnew;
+    }
+    sx[lane * XP + c] = rv[c];
+  }
+  wave_lds_fence();
+  // |r|^2 partial of every column over the 64 rows: lane c + 32 h sums rows 32 h ..
+  {
+    const int c = lane & 31, h = lane >> 5;
     double acc = 0.0;
-    for (int r = lane; r < rn; r += 64) {
-      const double v = sx[r * RP + c];
-      acc += v * v;
+    if (c < RC) {
+#pragma unroll 8
+      for (int j = 0; j < 32; ++j) {
+        const double v = (double)sx[(32 * h + j) * XP + c];
+        acc += v * v;
+      }
     }
-    acc = wave_sum64(acc);
-    if (lane == 0) rr_part[(size_t)c * gridDim.x + blockIdx.x] = acc;
+    acc += __shfl_xor(acc, 32, 64);
+    if (h == 0 && c < R) rr_part[(size_t)c * nw + w] = acc;
   }
-  if (k == 0) return;
-  __syncthreads();
-  for (int f = threadIdx.x; f < rn * RP; f += 256) sx[f] *= (e0 + f / RP < n ? isf : isg);
-  tile_project<TPT>(U, N, k, R, e0, rn, L, sx, sU, sred, t_part);
+  if (k > 0) wave_project<CB>(U, N, n, k, R, e0, sx, isf, isg, t_part, nw, w);
 }
 
 template <typename T>
-static dski_status launch_update(const ProjPlan& L, int nb, const T* P, const T* Q, T* Rr, double* Xd, int N,
-                                 int n, int R, const PcgScal& s, int par, const double* pq_part, int nb_pq,
-                                 double* rr_part, const double* U, int k, double isf, double isg, double* t_part,
-                                 double* hist, int max_iter, hipStream_t st) {
-#define DSKI_UPD(TPT)                                                                                        \
-  k_pcg_update<T, TPT><<<nb, kBlock, L.bytes, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nb_pq, rr_part, U, \
-                                                    k, isf, isg, L, t_part, hist, max_iter)
-  switch (L.tpt) {
-    case 1: DSKI_UPD(1); break;
-    case 2: DSKI_UPD(2); break;
-    case 4: DSKI_UPD(4); break;
-    default: DSKI_UPD(8); break;
+static dski_status launch_update(int nw, const T* P, const T* Q, T* Rr, double* Xd, int N, int n, int R,
+                                 const PcgScal& s, int par, const double* pq_part, int nb_pq, double* rr_part,
+                                 const double* U, int k, double isf, double isg, double* t_part, double* hist,
+                                 int max_iter, hipStream_t st) {
+  const int nb = (nw + 3) / 4;
+  if (R <= 16) {
+    constexpr size_t sh = ProjLds<1>::bytes<T>();
+    static bool done = false;
+    DSKI_TRY(lds_limit(&k_pcg_update<T, 1>, sh, done));
+    k_pcg_update<T, 1><<<nb, kBlock, sh, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf,
+                                               isg, t_part, hist, max_iter);
+  } else {
+    constexpr size_t sh = ProjLds<2>::bytes<T>();
+    static bool done = false;
+    DSKI_TRY(lds_limit(&k_pcg_update<T, 2>, sh, done));
+    k_pcg_update<T, 2><<<nb, kBlock, sh, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf,
+                                               isg, t_part, hist, max_iter);
   }
-#undef DSKI_UPD
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
@@ -221,7 +229,7 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
                            const double* __restrict__ rz_part, int nb_rz, double* __restrict__ hist,
                            int max_iter, int fixed_iters) {
   __shared__ double s_beta;
-  __shared__ int s_on;
+  __shared__ double s_red[4];
   const int c = blockIdx.y;
   const int on = s.active[par * R + c];
   if (!on) {
@@ -231,8 +239,20 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
     }
     return;
   }
-  if (threadIdx.x < 64) {
-    double rzs = rz_part ? wave_out_sum(rz_part, nb_rz, c) : 0.0;
+  // r.z of the column from its partials: every thread of the block takes a
+  // share, a fixed-order tree combines them
+  double rzs = 0.0;
+  if (rz_part) {
+    for (int b = threadIdx.x; b < nb_rz; b += blockDim.x) rzs += rz_part[(size_t)c * nb_rz + b];
+    rzs = wave_sum64(rzs);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = rzs;
+    __syncthreads();
+    rzs = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  }
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t ip = (size_t)c * N + (e < N ? e : 0);
+  const T zv = Z[ip], pv = P[ip];  // in flight while thread 0 forms beta
+  {
     if (threadIdx.x == 0) {
       double rz_old = s.rz[par * R + c];
       double rzn = rz_part ? rzs : s.rr[c];
@@ -253,11 +273,7 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
     }
   }
   __syncthreads();
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < N) {
-    size_t i = (size_t)c * N + e;
-    P[i] = (T)((double)Z[i] + s_beta * (double)P[i]);
-  }
+  if (e < N) P[ip] = (T)((double)zv + s_beta * (double)pv);
 }
 
 // True residual r = b - y (y = K~ x from the FP64-storage operator): stored into Rr
@@ -340,8 +356,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   const int k = pc ? pc->k : 0;
   const size_t nr = (size_t)N * R;
   const int nbv = nchunks(N), nbg = gather_blocks(p), nbz = vec_blocks(N);
-  const ProjPlan L = proj_plan(k, R, proj_rows(p));
-  const int nbt = L.nblk(N);
+  const int nbt = proj_waves(N);
   const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, nbt)) * R;
   const size_t ntp = (size_t)nbt * std::max(k, 1) * R;
   // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, scratch (R), coef, scalars
@@ -398,7 +413,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   // one iteration, all launches on stream `q`
   auto iterate = [&](int par, hipStream_t q) -> dski_status {
     DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, q));
-    DSKI_TRY(launch_update<T>(L, nbt, P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U, pc ? k : 0, isf,
+    DSKI_TRY(launch_update<T>(nbt, P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U, pc ? k : 0, isf,
                               isg, t_part, hist, max_iter, q));
     RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
     if (pc && k > 0) {

@@ -243,29 +243,22 @@ __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, doub
 // M^{-1} = D^{-1/2} (I - U diag(w) U^T) D^{-1/2},  w = s^2 / (1 + s^2)   (Woodbury,
 // U with orthonormal columns, kept in FP64 so that the operator stays SPD);
 // C = D^{1/2} (I + U diag(sqrt(1 + s^2) - 1) U^T) with C C^T = M.
-// Each application is one projection (row tiles, fixed-order partials), one
+// Each application is one projection (wavefront partials, fixed order), one
 // reduction that forms the coefficients, and one correction pass.
 
 int vec_blocks(int N) { return (N + kBlock - 1) / kBlock; }
-
-int proj_rows(dski_plan p) {
-  static const int rt[3] = {128, 64, 256};
-  return rt[std::min(std::max(p->proj_variant, 0), 2)];
-}
 
 struct PcWork {
   double* partial;  // nblk x k x R
   double* t;
   double* coef;
   int nblk;
-  ProjPlan L;
 };
 
 static dski_status pc_work(dski_precond pc, int R, PcWork& w) {
   dski_plan p = pc->plan;
   int k = pc->k;
-  w.L = proj_plan(k, R, proj_rows(p));
-  w.nblk = w.L.nblk(p->N);
+  w.nblk = proj_waves(p->N);
   size_t np = std::max((size_t)w.nblk * k * R, (size_t)vec_blocks(p->N) * R);
   DSKI_TRY(pc->work.reserve(sizeof(double) * (np + 2 * (size_t)k * R + 64)));
   double* base = pc->work.as<double>();
@@ -295,7 +288,7 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
     return launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, pc->U, 0, nullptr, Z, ldz, rz_partial, st);
   PcWork w;
   DSKI_TRY(pc_work(pc, R, w));
-  DSKI_TRY(launch_proj<T>(Rm, ld, N, p->n, R, isf, isg, pc->U, k, w.L, w.partial, st));
+  DSKI_TRY(launch_proj<T>(Rm, ld, N, p->n, R, isf, isg, pc->U, k, w.partial, st));
   RedJob j{w.partial, w.nblk, k * R, R, w.t, pc->w, nullptr, 1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j, nullptr, st));
   return launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, pc->U, k, w.coef, Z, ldz, rz_partial, st);
@@ -322,7 +315,7 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
     return launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, pc->U, 0, nullptr, Z, ldz, nullptr, st);
   PcWork w;
   DSKI_TRY(pc_work(pc, R, w));
-  DSKI_TRY(launch_proj<T>(W, ld, N, p->n, R, 1.0, 1.0, pc->U, k, w.L, w.partial, st));
+  DSKI_TRY(launch_proj<T>(W, ld, N, p->n, R, 1.0, 1.0, pc->U, k, w.partial, st));
   RedJob j{w.partial, w.nblk, k * R, R, w.t, pc->rootc, nullptr, -1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j, nullptr, st));
   return launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, pc->U, k, w.coef, Z, ldz, nullptr, st);

@@ -2,20 +2,18 @@
 // major), shared by the preconditioner and the fused PCG iteration (device
 // helpers and kernels that each translation unit instantiates for itself).
 //
-//   projection  t = U^T v        v = pre .* X staged in LDS (row tile of RT rows,
-//                                columns padded to a multiple of 4 with zeros),
-//                                U staged in sub-tiles of SUBR rows; every thread
-//                                owns 2 x 4 outputs per task and streams the rows
-//                                of the sub-tile from LDS (no branches in the row
-//                                loop); per-tile partials are written
-//                                output-major and reduced in a fixed order.
+//   projection  t = U^T (pre .* X)   one wavefront per 64 rows on the FP64
+//                                matrix cores (v_mfma_f64_16x16x4f64): U is the
+//                                A operand, read straight from memory (16
+//                                columns x 4 consecutive rows per load), the
+//                                64 x R block of X, staged unscaled in LDS, the
+//                                B operand with the row scale applied in
+//                                registers; one partial per wavefront,
+//                                output-major, reduced in a fixed order.
 //   correction  z = post .* (pre .* X - U coef)   one thread per row, all columns
 //                                in registers (padded to a multiple of 4), coef
-//                                in LDS, U loads issued 8 at a time.
-// Global loads into LDS are issued in batches of four per thread so that
-// several are in flight before the first wait.  With R = 17 these products do
-// about 6 flops per byte, below the vector-ALU ridge: they stay on the vector
-// units.
+//                                in LDS, U loads issued 16 at a time with the
+//                                next 16 in flight.
 #pragma once
 
 #include <algorithm>
@@ -25,6 +23,9 @@
 namespace dski {
 
 constexpr int kFinalMaxR = 32;  // columns per tall-skinny launch
+constexpr int kProjRows = 64;   // rows per projection wavefront
+
+typedef double dski_pdbl4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum64(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -42,196 +43,129 @@ __device__ __forceinline__ double wave_out_sum(const double* __restrict__ part, 
 }
 
 inline int pad4(int x) { return (x + 3) & ~3; }
-inline int pad2(int x) { return (x + 1) & ~1; }
+__host__ __device__ inline int proj_waves(int N) { return (N + kProjRows - 1) / kProjRows; }
 
-// Launch plan of a projection: row tile RT, padded widths, U sub-tile rows,
-// task split and the LDS layout  [sx: RT x RP][sU: SUBR x KP][sred: 2 x KP x RP].
-struct ProjPlan {
-  int RT = 128;    // rows per work-group
-  int RP = 4;      // columns, padded to 4
-  int KP = 2;      // rank, padded to 2
-  int SUBR = 64;   // U rows per LDS sub-tile
-  int S = 1;       // row splits of a sub-tile (1 or 2)
-  int tasks = 0;   // (KP/2) (RP/4) S
-  int tpt = 1;     // tasks per thread: 1, 2, 4 or 8
-  size_t oU = 0, ored = 0, bytes = 0;
-  int nblk(int N) const { return (N + RT - 1) / RT; }
+// Row stride (elements) of a wavefront's 64-row block of X in LDS: odd, so
+// that the four rows of one matrix-core step fall on different banks.
+template <int CB>
+struct ProjLds {
+  static constexpr int XP = 16 * CB + 1;
+  static constexpr int per_wave = kProjRows * XP;
+  template <typename S>
+  static constexpr size_t bytes() { return 4 * sizeof(S) * (size_t)per_wave; }  // four wavefronts
 };
 
-inline ProjPlan proj_plan(int k, int R, int RT) {
-  ProjPlan P;
-  P.RT = RT;
-  P.RP = pad4(std::max(R, 1));
-  P.KP = pad2(std::max(k, 1));
-  P.SUBR = 64;
-  while (P.SUBR > 16 && (size_t)P.SUBR * P.KP * sizeof(double) > 32768) P.SUBR /= 2;
-  const int t1 = (P.KP / 2) * (P.RP / 4);
-  P.S = t1 <= 128 ? 2 : 1;
-  P.tasks = t1 * P.S;
-  P.tpt = 1;
-  while (P.tpt * 256 < P.tasks) P.tpt *= 2;
-  for (;;) {  // at most 64 KiB of LDS per work-group
-    P.oU = sizeof(double) * (size_t)P.RT * P.RP;
-    P.ored = P.oU + sizeof(double) * (size_t)P.SUBR * P.KP;
-    P.bytes = P.ored + (P.S == 2 ? sizeof(double) * 2 * (size_t)P.KP * P.RP : 0);
-    if (P.bytes <= 65536 || P.RT <= 64) break;
-    P.RT /= 2;
+// Partials of t = U^T (scale .* X) over rows e0 .. e0 + 63 (rows >= N count as
+// zero): sx holds this wavefront's X rows (row stride XP, columns >= R zero),
+// the row scale is pre_v below row n and pre_g from n on.  Writes
+// partial[(i R + c) nw + w] for i < k, c < R.  CB = column blocks of 16.
+template <int CB, typename S>
+__device__ __forceinline__ void wave_project(const double* __restrict__ U, int N, int n, int k, int R, int e0,
+                                             const S* __restrict__ sx, double pre_v, double pre_g,
+                                             double* __restrict__ partial, int nw, int w) {
+  constexpr int XP = ProjLds<CB>::XP;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  // the B operands of all 16 steps (rows 4 s + kq), scaled, for every column block
+  double bop[16][CB];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int row = 4 * s + kq, e = e0 + row;
+    const double sc = e < n ? pre_v : pre_g;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) bop[s][cb] = sc * (double)sx[row * XP + 16 * cb + r16];
   }
-  return P;
-}
-
-// t-partials of one row tile: sx (RT x RP, FP64, zero-padded) is in LDS; U rows
-// e0 .. e0 + rn - 1 are staged through sU.  Writes partial[(i R + c) nblk + blk]
-// for i < k, c < R.  Called by all 256 threads (contains barriers).
-template <int TPT>
-__device__ __forceinline__ void tile_project(const double* __restrict__ U, int N, int k, int R, int e0, int rn,
-                                             const ProjPlan& L, const double* __restrict__ sx,
-                                             double* __restrict__ sU, double* __restrict__ sred,
-                                             double* __restrict__ partial) {
-  const int KP = L.KP, RP = L.RP, SUBR = L.SUBR, S = L.S;
-  const int ni = KP / 2, nc = RP / 4;
-  const int half = SUBR / S;
-  int ib[TPT], cb[TPT], hs[TPT];
-  double acc[TPT][2][4];
+  for (int i0 = 0; i0 < k; i0 += 64) {  // groups of four 16-column blocks of U
+    dski_pdbl4 acc[4][CB];
 #pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    int task = threadIdx.x + 256 * q;
-    if (task >= L.tasks) task = L.tasks - 1;  // idle duplicate, never written
-    hs[q] = task % S;
-    int rest = task / S;
-    cb[q] = rest % nc;
-    ib[q] = rest / nc;
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+      for (int cb = 0; cb < CB; ++cb) acc[b][cb] = dski_pdbl4{0.0, 0.0, 0.0, 0.0};
+    const double* ub[4];
+    bool ok[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[q][a][j] = 0.0;
-  }
-  // U sub-tiles: each thread holds its share (<= 16 values, SUBR KP <= 4096) of
-  // the next sub-tile in registers while the current one is used from LDS
-  const int tot = SUBR * KP;
-  double cur[16], nxt[16];
-  auto load_sub = [&](int s0, double (&v)[16]) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int f = threadIdx.x + 256 * u;
-      const int i = f / SUBR, r = f % SUBR;
-      v[u] = (f < tot && i < k && s0 + r < rn) ? U[(size_t)i * N + e0 + s0 + r] : 0.0;
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + 16 * b + r16;
+      ok[b] = i < k;
+      ub[b] = U + (size_t)(ok[b] ? i : 0) * N;
     }
-  };
-  load_sub(0, cur);
-  for (int s0 = 0; s0 < rn; s0 += SUBR) {
-    __syncthreads();  // previous sub-tile consumed
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int f = threadIdx.x + 256 * u;
-      if (f < tot) sU[(f % SUBR) * KP + f / SUBR] = cur[u];
-    }
-    const bool more = s0 + SUBR < rn;
-    if (more) load_sub(s0 + SUBR, nxt);
-    __syncthreads();
+    for (int h = 0; h < 2; ++h) {  // two halves of 8 steps: 32 loads in flight
+      double aop[8][4];
 #pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-      const double* up = sU + (size_t)hs[q] * half * KP + 2 * ib[q];
-      const double* xp = sx + (size_t)(s0 + hs[q] * half) * RP + 4 * cb[q];
-      for (int r0 = 0; r0 < half; r0 += 4) {  // half is a multiple of 4
-        double2 u[4], x01[4], x23[4];
+      for (int s = 0; s < 8; ++s) {
+        const int e = e0 + 4 * (8 * h + s) + kq;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // all reads of 4 rows before the first use
-          u[j] = *reinterpret_cast<const double2*>(up + (size_t)(r0 + j) * KP);
-          x01[j] = *reinterpret_cast<const double2*>(xp + (size_t)(r0 + j) * RP);
-          x23[j] = *reinterpret_cast<const double2*>(xp + (size_t)(r0 + j) * RP + 2);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[q][0][0] += u[j].x * x01[j].x;
-          acc[q][0][1] += u[j].x * x01[j].y;
-          acc[q][0][2] += u[j].x * x23[j].x;
-          acc[q][0][3] += u[j].x * x23[j].y;
-          acc[q][1][0] += u[j].y * x01[j].x;
-          acc[q][1][1] += u[j].y * x01[j].y;
-          acc[q][1][2] += u[j].y * x23[j].x;
-          acc[q][1][3] += u[j].y * x23[j].y;
-        }
+        for (int b = 0; b < 4; ++b) aop[s][b] = ld_or0(ub[b], (size_t)e, 0, ok[b] && e < N);
       }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[b][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s][b], bop[8 * h + s][cb], acc[b][cb], 0, 0, 0);
     }
-    if (more) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
-    }
-  }
-  const int nblk = gridDim.x;
-  if (S == 1) {
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-      if (threadIdx.x + 256 * q >= L.tasks) continue;
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int i = 2 * ib[q] + a, c = 4 * cb[q] + j;
-          if (i < k && c < R) partial[((size_t)i * R + c) * nblk + blockIdx.x] = acc[q][a][j];
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + 16 * b + kq + 4 * r, c = 16 * cb + r16;
+          if (i < k && c < R) partial[((size_t)i * R + c) * nw + w] = acc[b][cb][r];
         }
-    }
-    return;
-  }
-  // S == 2: add the two row halves in a fixed order
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    if (threadIdx.x + 256 * q >= L.tasks) continue;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        sred[((size_t)hs[q] * KP + 2 * ib[q] + a) * RP + 4 * cb[q] + j] = acc[q][a][j];
-  }
-  __syncthreads();
-  for (int f = threadIdx.x; f < k * R; f += 256) {
-    const int i = f / R, c = f % R;
-    partial[(size_t)f * nblk + blockIdx.x] = sred[(size_t)i * RP + c] + sred[((size_t)KP + i) * RP + c];
   }
 }
 
-// Standalone projection: partials of t = U^T (pre .* X) over row tiles of L.RT rows.
-template <typename T, int TPT>
+// Sets the dynamic LDS limit of a kernel once (above 64 KiB it must be raised).
+template <typename K>
+static inline dski_status lds_limit(K* kern, size_t bytes, bool& done) {
+  if (!done && bytes > 65536) {
+    DSKI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)bytes));
+  }
+  done = true;
+  return DSKI_OK;
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Standalone projection: partials of t = U^T (pre .* X), one per wavefront.
+template <typename T, int CB>
 static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X, int ld, int N, int n, int R,
                                                         double pre_v, double pre_g, const double* __restrict__ U,
-                                                        int k, ProjPlan L, double* __restrict__ partial) {
+                                                        int k, double* __restrict__ partial) {
   extern __shared__ __align__(16) char smem[];
-  double* sx = reinterpret_cast<double*>(smem);
-  double* sU = reinterpret_cast<double*>(smem + L.oU);
-  double* sred = reinterpret_cast<double*>(smem + L.ored);
-  const int RT = L.RT, RP = L.RP;
-  const int e0 = blockIdx.x * RT;
-  const int rn = min(RT, N - e0);
-  const int tot = RT * RP;
-  for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-    double v[4];
+  constexpr int XP = ProjLds<CB>::XP;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = blockIdx.x * 4 + wv, nw = proj_waves(N);
+  if (w >= nw) return;
+  T* sx = reinterpret_cast<T*>(smem) + (size_t)wv * ProjLds<CB>::per_wave;
+  const int e0 = w * kProjRows, e = e0 + lane;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = f0 + 256 * u;
-      const int c = f / RT, r = f % RT;
-      const int e = e0 + r;
-      v[u] = (f < tot && c < R && r < rn) ? (e < n ? pre_v : pre_g) * (double)X[(size_t)c * ld + e] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = f0 + 256 * u;
-      if (f < tot) sx[(f % RT) * RP + f / RT] = v[u];
-    }
-  }
-  tile_project<TPT>(U, N, k, R, e0, rn, L, sx, sU, sred, partial);
+  for (int c = 0; c < 16 * CB; ++c) sx[lane * XP + c] = ld_or0(X, (size_t)c * ld + e, 0, c < R && e < N);
+  wave_lds_fence();
+  wave_project<CB>(U, N, n, k, R, e0, sx, pre_v, pre_g, partial, nw, w);
 }
 
 template <typename T>
 static inline dski_status launch_proj(const T* X, int ld, int N, int n, int R, double pre_v, double pre_g,
-                                      const double* U, int k, const ProjPlan& L, double* partial,
-                                      hipStream_t st) {
-  const int nb = L.nblk(N);
-  switch (L.tpt) {
-    case 1: k_ts_proj<T, 1><<<nb, 256, L.bytes, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, L, partial); break;
-    case 2: k_ts_proj<T, 2><<<nb, 256, L.bytes, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, L, partial); break;
-    case 4: k_ts_proj<T, 4><<<nb, 256, L.bytes, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, L, partial); break;
-    default: k_ts_proj<T, 8><<<nb, 256, L.bytes, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, L, partial); break;
+                                      const double* U, int k, double* partial, hipStream_t st) {
+  const int nb = (proj_waves(N) + 3) / 4;
+  if (R <= 16) {
+    constexpr size_t sh = ProjLds<1>::bytes<T>();
+    static bool done = false;
+    DSKI_TRY(lds_limit(&k_ts_proj<T, 1>, sh, done));
+    k_ts_proj<T, 1><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, partial);
+  } else {
+    constexpr size_t sh = ProjLds<2>::bytes<T>();
+    static bool done = false;
+    DSKI_TRY(lds_limit(&k_ts_proj<T, 2>, sh, done));
+    k_ts_proj<T, 2><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, partial);
   }
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
@@ -294,7 +228,7 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
   // X first: its loads overlap the U stream below
   double xv[RB];
 #pragma unroll
-  for (int c = 0; c < RB; ++c) xv[c] = (in && c < R) ? (double)X[(size_t)c * ld + e] : 0.0;
+  for (int c = 0; c < RB; ++c) xv[c] = (double)ld_or0(X, (size_t)c * ld + e, 0, in && c < R);
   for (int i0 = 0; i0 < k; i0 += kc) {
     const int kn = min(kc, k - i0);
     if (i0 > 0) __syncthreads();
@@ -303,21 +237,22 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
       sco[f] = c < R ? coef[(i0 + i) * R + c] : 0.0;
     }
     __syncthreads();
-    // U rows in blocks of 8, the next block loaded while the current one is used
-    double u[8], un[8];
+    // U rows in blocks of 16, the next block loaded while the current one is used
+    constexpr int KB = 16;
+    double u[KB], un[KB];
     int i = 0;
-    if (kn >= 8) {
+    if (kn >= KB) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) u[j] = U[(size_t)(i0 + j) * N + ec];
+      for (int j = 0; j < KB; ++j) u[j] = U[(size_t)(i0 + j) * N + ec];
     }
-    for (; i + 8 <= kn; i += 8) {
-      const bool more = i + 16 <= kn;
+    for (; i + KB <= kn; i += KB) {
+      const bool more = i + 2 * KB <= kn;
       if (more) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) un[j] = U[(size_t)(i0 + i + 8 + j) * N + ec];
+        for (int j = 0; j < KB; ++j) un[j] = U[(size_t)(i0 + i + KB + j) * N + ec];
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < KB; ++j) {
         const double* cr = sco + (i + j) * RB;
 #pragma unroll
         for (int c = 0; c < RB; c += 2) {
@@ -328,17 +263,24 @@ static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X
       }
       if (more) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) u[j] = un[j];
+        for (int j = 0; j < KB; ++j) u[j] = un[j];
       }
     }
-    for (; i < kn; ++i) {
-      const double uu = U[(size_t)(i0 + i) * N + ec];
-      const double* cr = sco + i * RB;
+    // the remaining rows (fewer than KB): loads issued together, then used
+    if (i < kn) {
 #pragma unroll
-      for (int c = 0; c < RB; c += 2) {
-        const double2 cc = *reinterpret_cast<const double2*>(cr + c);
-        acc[c] += uu * cc.x;
-        acc[c + 1] += uu * cc.y;
+      for (int j = 0; j < KB; ++j) u[j] = i + j < kn ? U[(size_t)(i0 + i + j) * N + ec] : 0.0;
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        if (i + j < kn) {
+          const double* cr = sco + (i + j) * RB;
+#pragma unroll
+          for (int c = 0; c < RB; c += 2) {
+            const double2 cc = *reinterpret_cast<const double2*>(cr + c);
+            acc[c] += u[j] * cc.x;
+            acc[c + 1] += u[j] * cc.y;
+          }
+        }
       }
     }
   }

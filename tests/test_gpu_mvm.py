@@ -133,12 +133,12 @@ def test_kernel_variants_agree(name):
     plan, op = make(W)
     V = to_gpu(np.random.default_rng(4).standard_normal((op.N, 17)))
     outs = []
-    for v in range(4):
-        plan.set_variants(v, 0)
+    for v in range(5):
+        plan.set_variants(v)
         outs.append(plan.mvm(V))
     for o in outs[1:]:
         assert torch.equal(outs[0], o)
-    t = plan.autotune(17, 30)
+    t = plan.autotune(17)
     say("  autotune us", t)
     assert torch.equal(plan.mvm(V), outs[0])
 
@@ -168,7 +168,7 @@ def test_dense_kuu_variant_matches_oracle(idx):
     # FP32 storage path and the autotuner's choice
     Vf = V.astype(np.float32).astype(np.float64)
     assert rel_cols(from_gpu(plan.mvm(to_gpu(Vf))), op.matvec(Vf)).max() < TOL_MVM
-    times = plan.autotune(5, 10)
+    times = plan.autotune(5)
     say("  tuner K_UU us", times["kuu_us"])
     assert rel_cols(plan.mvm(Vd).cpu().numpy().T, op.matvec(V)).max() < 1e-12
 

@@ -70,14 +70,14 @@ def test_pivchol_exact_low_rank_and_truncation():
     assert max(iters) <= 2
 
 
-@pytest.mark.parametrize("name,bits,variant", [("small2d", 32, 0), ("terrain_small", 32, 0), ("small2d", 64, 0),
-                                              ("terrain_small", 32, 2),
-                                              ("terrain_small", 32, 1), ("small2d", 64, 1)])
+@pytest.mark.parametrize("name,bits,variant", [("small2d", 32, 1), ("terrain_small", 32, 4), ("small2d", 64, 3),
+                                              ("terrain_small", 32, 0),
+                                              ("terrain_small", 32, 2), ("small2d", 64, 4)])
 def test_pcg_true_residual(name, bits, variant):
     W = {"small2d": workloads.small2d(), "terrain_small": workloads.terrain(n=3000, grid=60)}[name]
-    say("pcg", name, bits, "projection variant", variant)
+    say("pcg", name, bits, "scatter variant", variant)
     plan, op = make(W)
-    plan.set_variants((variant + 1) % 3 if bits == 32 else 3, variant)  # every scatter form
+    plan.set_variants(variant)  # every scatter form
     pc = plan.pivchol(W.rank)
     Wr = orng.rademacher(SEED, 0, 2, op.N)
     B = np.concatenate([W.y[:, None], Wr], axis=1).astype(np.float32).astype(np.float64)
