@@ -10,10 +10,10 @@
 //                                B operand with the row scale applied in
 //                                registers; one partial per wavefront,
 //                                output-major, reduced in a fixed order.
-//   correction  z = post .* (pre .* X - U coef)   one thread per row, all columns
-//                                in registers (padded to a multiple of 4), coef
-//                                in LDS, U loads issued 16 at a time with the
-//                                next 16 in flight.
+//   correction  z = post .* (pre .* X - U coef)   one wavefront per 64 rows on
+//                                the FP64 matrix cores (A = U, B = coef), the
+//                                result transposed through LDS so that X and Z
+//                                move one row per lane.
 #pragma once
 
 #include <algorithm>
@@ -206,109 +206,98 @@ static inline dski_status launch_reduce(const RedJob& a, const RedJob* b, hipStr
   return DSKI_OK;
 }
 
-// z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]), one thread per
-// row with all RB (>= R, multiple of 4) columns in registers; coef (k x R) is
-// staged in LDS as chunks of kc x RB with zero padding; per-block partials of X.z stored
-// output-major (dot_partial[c * blocks + block]).
-template <typename T, int RB>
+// z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]), one wavefront
+// per 64 rows: the product U coef on the FP64 matrix cores (A = U, 16 rows x 4
+// of its columns per load; B = coef, 4 x 16), CB blocks of 16 columns; the
+// result goes through LDS so that X is read and Z written one row per lane;
+// per-work-group partials of X.z (fixed order) stored output-major
+// (dot_partial[c * blocks + block]).  Work-groups cover 256 rows.
+template <typename T, int CB>
 static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X, int ld, int N, int n, int R,
                                                          double pre_v, double pre_g, double post_v, double post_g,
                                                          const double* __restrict__ U, int k,
-                                                         const double* __restrict__ coef, int kc, T* __restrict__ Z,
+                                                         const double* __restrict__ coef, T* __restrict__ Z,
                                                          int ldz, double* __restrict__ dot_partial) {
+  constexpr int XP = 16 * CB + 1, SB = 8;  // LDS row stride; matrix-core steps per load batch
   extern __shared__ __align__(16) char smem[];
-  double* sco = reinterpret_cast<double*>(smem);  // kc x RB
-  __shared__ double red[4][RB];
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const bool in = e < N;
-  const int ec = in ? e : N - 1;
-  double acc[RB];
+  __shared__ double red[4][16 * CB];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int w = blockIdx.x * 4 + wv;
+  const bool live = w < proj_waves(N);
+  const int e0 = w * kProjRows;
+  double* sz = reinterpret_cast<double*>(smem) + (size_t)wv * kProjRows * XP;
+  dski_pdbl4 acc[4][CB];
 #pragma unroll
-  for (int c = 0; c < RB; ++c) acc[c] = 0.0;
-  // X first: its loads overlap the U stream below
-  double xv[RB];
+  for (int eb = 0; eb < 4; ++eb)
 #pragma unroll
-  for (int c = 0; c < RB; ++c) xv[c] = (double)ld_or0(X, (size_t)c * ld + e, 0, in && c < R);
-  for (int i0 = 0; i0 < k; i0 += kc) {
-    const int kn = min(kc, k - i0);
-    if (i0 > 0) __syncthreads();
-    for (int f = threadIdx.x; f < kn * RB; f += 256) {
-      const int i = f / RB, c = f % RB;
-      sco[f] = c < R ? coef[(i0 + i) * R + c] : 0.0;
-    }
-    __syncthreads();
-    // U rows in blocks of 16, the next block loaded while the current one is used
-    constexpr int KB = 16;
-    double u[KB], un[KB];
-    int i = 0;
-    if (kn >= KB) {
+    for (int cb = 0; cb < CB; ++cb) acc[eb][cb] = dski_pdbl4{0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    for (int i0 = 0; i0 < k; i0 += 4 * SB) {
+      double av[SB][4], bv[SB][CB];
 #pragma unroll
-      for (int j = 0; j < KB; ++j) u[j] = U[(size_t)(i0 + j) * N + ec];
-    }
-    for (; i + KB <= kn; i += KB) {
-      const bool more = i + 2 * KB <= kn;
-      if (more) {
+      for (int st = 0; st < SB; ++st) {
+        const int i = i0 + 4 * st + kq;
+        const bool oi = i < k;
 #pragma unroll
-        for (int j = 0; j < KB; ++j) un[j] = U[(size_t)(i0 + i + KB + j) * N + ec];
-      }
+        for (int eb = 0; eb < 4; ++eb) {
+          const int e = e0 + 16 * eb + r16;
+          av[st][eb] = ld_or0(U, (size_t)i * N + e, 0, oi && e < N);
+        }
 #pragma unroll
-      for (int j = 0; j < KB; ++j) {
-        const double* cr = sco + (i + j) * RB;
-#pragma unroll
-        for (int c = 0; c < RB; c += 2) {
-          const double2 cc = *reinterpret_cast<const double2*>(cr + c);
-          acc[c] += u[j] * cc.x;
-          acc[c + 1] += u[j] * cc.y;
+        for (int cb = 0; cb < CB; ++cb) {
+          const int c = 16 * cb + r16;
+          bv[st][cb] = ld_or0(coef, (size_t)i * R + c, 0, oi && c < R);
         }
       }
-      if (more) {
 #pragma unroll
-        for (int j = 0; j < KB; ++j) u[j] = un[j];
-      }
-    }
-    // the remaining rows (fewer than KB): loads issued together, then used
-    if (i < kn) {
+      for (int st = 0; st < SB; ++st)
 #pragma unroll
-      for (int j = 0; j < KB; ++j) u[j] = i + j < kn ? U[(size_t)(i0 + i + j) * N + ec] : 0.0;
+        for (int eb = 0; eb < 4; ++eb)
 #pragma unroll
-      for (int j = 0; j < KB; ++j) {
-        if (i + j < kn) {
-          const double* cr = sco + (i + j) * RB;
-#pragma unroll
-          for (int c = 0; c < RB; c += 2) {
-            const double2 cc = *reinterpret_cast<const double2*>(cr + c);
-            acc[c] += u[j] * cc.x;
-            acc[c + 1] += u[j] * cc.y;
-          }
-        }
-      }
+          for (int cb = 0; cb < CB; ++cb)
+            acc[eb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st][eb], bv[st][cb], acc[eb][cb], 0, 0, 0);
     }
   }
-  const double pre = e < n ? pre_v : pre_g, post = e < n ? post_v : post_g;
+  // D register r of lane l: row 16 eb + l / 16 + 4 r, column 16 cb + l % 16
 #pragma unroll
-  for (int c = 0; c < RB; ++c) {
+  for (int eb = 0; eb < 4; ++eb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sz[(16 * eb + kq + 4 * r) * XP + 16 * cb + r16] = acc[eb][cb][r];
+  wave_lds_fence();
+  const int e = e0 + lane;
+  const bool in = live && e < N;
+  const double pre = e < n ? pre_v : pre_g, post = e < n ? post_v : post_g;
+  double xv[16 * CB];
+#pragma unroll
+  for (int c = 0; c < 16 * CB; ++c) xv[c] = (double)ld_or0(X, (size_t)c * ld + e, 0, in && c < R);
+#pragma unroll
+  for (int c = 0; c < 16 * CB; ++c) {
     double dot = 0.0;
     if (in && c < R) {
-      const T z = (T)(post * (pre * xv[c] - acc[c]));
+      const T z = (T)(post * (pre * xv[c] - sz[lane * XP + c]));
       Z[(size_t)c * ldz + e] = z;
       dot = xv[c] * (double)z;
     }
-    acc[c] = dot;
+    sz[lane * XP + c] = dot;
   }
-  if (dot_partial) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < RB; ++c) {
-      if (c < R) {
-        const double v = wave_sum64(acc[c]);
-        if (lane == 0) red[wv][c] = v;
-      }
+  if (!dot_partial) return;
+  wave_lds_fence();
+  {  // column sums over the wavefront's 64 rows: lane c + 32 h sums rows 32 h ..
+    const int c = lane & 31, h = lane >> 5;
+    double a = 0.0;
+    if (c < 16 * CB) {
+#pragma unroll 8
+      for (int j = 0; j < 32; ++j) a += sz[(32 * h + j) * XP + c];
     }
-    __syncthreads();
-    if (threadIdx.x < R) {
-      const int c = threadIdx.x;
-      dot_partial[(size_t)c * gridDim.x + blockIdx.x] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-    }
+    a += __shfl_xor(a, 32, 64);
+    if (h == 0 && c < 16 * CB) red[wv][c] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < R) {
+    const int c = threadIdx.x;
+    dot_partial[(size_t)c * gridDim.x + blockIdx.x] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
   }
 }
 
@@ -317,29 +306,22 @@ static inline dski_status launch_final(const T* X, int ld, int N, int n, int R, 
                                        double post_v, double post_g, const double* U, int k,
                                        const double* coef, T* Z, int ldz, double* dot_partial, hipStream_t st) {
   if (R <= 0) return DSKI_OK;
-  const int nb = (N + 255) / 256;
-  const int RB = pad4(R);
-  const int kc = std::max(1, std::min(std::max(k, 1), 6144 / RB));  // coef rows per LDS chunk (<= 48 KiB)
-  const size_t sh = sizeof(double) * (size_t)kc * RB;
-#define DSKI_FINAL_CASE(V)                                                                                   \
-  case V:                                                                                                    \
-    k_ts_final<T, V><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, kc, Z, \
-                                          ldz, dot_partial);                                                    \
-    break;
-  switch (RB) {
-    DSKI_FINAL_CASE(4)
-    DSKI_FINAL_CASE(8)
-    DSKI_FINAL_CASE(12)
-    DSKI_FINAL_CASE(16)
-    DSKI_FINAL_CASE(20)
-    DSKI_FINAL_CASE(24)
-    DSKI_FINAL_CASE(28)
-    DSKI_FINAL_CASE(32)
-    default:
-      set_error("at most %d columns per tall-skinny launch", kFinalMaxR);
-      return DSKI_ENOTSUP;
+  if (R > kFinalMaxR) {
+    set_error("at most %d columns per tall-skinny launch", kFinalMaxR);
+    return DSKI_ENOTSUP;
   }
-#undef DSKI_FINAL_CASE
+  const int nb = (proj_waves(N) + 3) / 4;  // = ceil(N / 256)
+  if (R <= 16) {
+    constexpr size_t sh = sizeof(double) * 4 * kProjRows * 17;
+    k_ts_final<T, 1><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
+                                          dot_partial);
+  } else {
+    constexpr size_t sh = sizeof(double) * 4 * kProjRows * 33;
+    static bool done = false;
+    DSKI_TRY(lds_limit(&k_ts_final<T, 2>, sh, done));
+    k_ts_final<T, 2><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
+                                          dot_partial);
+  }
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
