@@ -108,23 +108,43 @@ __global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, co
   }
 }
 
-// alpha, x and r updates, partials of r.r and of U^T D^{-1/2} r, one partial
-// per wavefront of 64 rows (the new r of those rows is kept in LDS for the
-// projection on the matrix cores).
-template <typename T, int CB>
-__global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, const T* __restrict__ Q,
-                                                    T* __restrict__ Rr, double* __restrict__ Xd, int N, int n,
+// alpha, the r update, partials of r.r and of U^T D^{-1/2} r.  A wavefront
+// takes 64 rows: it updates them (one row per lane, all columns), keeps the
+// new r in LDS and projects it on the FP64 matrix cores (the first 16 columns,
+// and the next 16 when RB > 20) with up to 4 remaining columns on the vector
+// ALU.  The four wavefronts' partials are added in LDS in a fixed order and
+// written once per work-group, block-major (t_part[b k R + i R + c],
+// rr_part[b R + c]).  RB = R padded to a multiple of 4.
+template <int RB>
+struct UpdShape {
+  static constexpr int MB = RB <= 20 ? 1 : 2;           // matrix-core column blocks
+  static constexpr int VR = RB > 16 && RB <= 20 ? RB - 16 : 0;  // vector-ALU columns
+  static constexpr int CW = RB > 16 * MB ? RB : 16 * MB;  // columns held per row (zeros beyond R)
+  static constexpr int XP = CW + 1;                     // LDS row stride of the new r
+  static constexpr int TB = 64 * CW;                    // one group of 64 outputs i per column
+  template <typename T>
+  static constexpr size_t bytes() {
+    return 4 * sizeof(T) * (size_t)kProjRows * XP + sizeof(double) * 4 * (size_t)TB;
+  }
+};
+
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* __restrict__ Rr, int N, int n,
                                                     int R, PcgScal s, int par, const double* __restrict__ pq_part,
                                                     int nb_pq, double* __restrict__ rr_part,
                                                     const double* __restrict__ U, int k, double isf, double isg,
                                                     double* __restrict__ t_part, double* __restrict__ hist,
                                                     int max_iter) {
+  using S = UpdShape<RB>;
+  constexpr int XP = S::XP, MB = S::MB, VR = S::VR, CW = S::CW;
   extern __shared__ __align__(16) char smem[];
-  constexpr int XP = ProjLds<CB>::XP, RC = 16 * CB;
+  T* sx = reinterpret_cast<T*>(smem) + (size_t)(threadIdx.x >> 6) * kProjRows * XP;
+  double* st = reinterpret_cast<double*>(smem + 4 * sizeof(T) * (size_t)kProjRows * XP);  // 4 x TB
   __shared__ double s_alpha[kPcgMaxR];
   __shared__ int s_act[kPcgMaxR];
+  __shared__ double s_rr[4][RB];
   const int* act = s.active + par * R;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
   {  // alpha of every column at once: 8 lanes per column, all loads in flight together
     const int c = threadIdx.x >> 3, j = threadIdx.x & 7;
     const bool col = c < R;
@@ -151,41 +171,37 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
     }
   }
   __syncthreads();
-  const int w = blockIdx.x * 4 + wv, nw = proj_waves(N);
-  if (w >= nw) return;
-  T* sx = reinterpret_cast<T*>(smem) + (size_t)wv * ProjLds<CB>::per_wave;
+  const int w = blockIdx.x * 4 + wv;
   const int e0 = w * kProjRows, e = e0 + lane;
-  const bool in = e < N;
-  // x += alpha p, r -= alpha q on this thread's row, every column's loads in flight
-  T rv[RC], pv[RC], qv[RC];
-  double xv[RC];
+  const bool in = e < N;  // rows past N (and wavefronts past the last row) act as zeros
+  // r -= alpha q on this lane's row, every column's loads in flight (x += alpha p
+  // is done by the beta kernel, which reads p anyway)
+  {
+    T rv[RB], qv[RB];
 #pragma unroll
-  for (int c = 0; c < RC; ++c) {
-    const bool ok = in && c < R, on = ok && s_act[c];
-    const size_t idx = (size_t)(ok ? c : 0) * N + (in ? e : 0);
-    rv[c] = ld_or0(Rr, idx, 0, ok);
-    pv[c] = ld_or0(P, idx, 0, on);
-    qv[c] = ld_or0(Q, idx, 0, on);
-    xv[c] = ld_or0(Xd, idx, 0, on);
-  }
-#pragma unroll
-  for (int c = 0; c < RC; ++c) {
-    if (in && c < R && s_act[c]) {
-      const size_t idx = (size_t)c * N + e;
-      const double a = s_alpha[c];
-      Xd[idx] = xv[c] + a * (double)pv[c];
-      const T rnew = (T)((double)rv[c] - a * (double)qv[c]);
-      Rr[idx] = rnew;
-      rv[c] = rnew;
+    for (int c = 0; c < RB; ++c) {
+      const bool ok = in && c < R, on = ok && s_act[c];
+      const size_t idx = (size_t)(ok ? c : 0) * N + (in ? e : 0);
+      rv[c] = ld_or0(Rr, idx, 0, ok);
+      qv[c] = ld_or0(Q, idx, 0, on);
     }
-    sx[lane * XP + c] = rv[c];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) {
+      if (in && c < R && s_act[c]) {
+        const T rnew = (T)((double)rv[c] - s_alpha[c] * (double)qv[c]);
+        Rr[(size_t)c * N + e] = rnew;
+        rv[c] = rnew;
+      }
+      sx[lane * XP + c] = rv[c];
+    }
+#pragma unroll
+    for (int c = RB; c < CW; ++c) sx[lane * XP + c] = (T)0;
   }
   wave_lds_fence();
-  // |r|^2 partial of every column over the 64 rows: lane c + 32 h sums rows 32 h ..
-  {
+  {  // |r|^2 of every column over the 64 rows: lane c + 32 h sums rows 32 h ..
     const int c = lane & 31, h = lane >> 5;
     double acc = 0.0;
-    if (c < RC) {
+    if (c < RB) {
 #pragma unroll 8
       for (int j = 0; j < 32; ++j) {
         const double v = (double)sx[(32 * h + j) * XP + c];
@@ -193,39 +209,141 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ P, con
       }
     }
     acc += __shfl_xor(acc, 32, 64);
-    if (h == 0 && c < R) rr_part[(size_t)c * nw + w] = acc;
+    if (h == 0 && c < RB) s_rr[wv][c] = acc;
   }
-  if (k > 0) wave_project<CB>(U, N, n, k, R, e0, sx, isf, isg, t_part, nw, w);
+  // scaled operands of the projection: rows 4 s + kq of the 64
+  double bop[16][MB], vop[16][VR > 0 ? VR : 1];
+#pragma unroll
+  for (int st_ = 0; st_ < 16; ++st_) {
+    const int row = 4 * st_ + kq;
+    const double sc = e0 + row < n ? isf : isg;
+#pragma unroll
+    for (int cb = 0; cb < MB; ++cb) bop[st_][cb] = sc * (double)sx[row * XP + 16 * cb + r16];
+#pragma unroll
+    for (int v = 0; v < VR; ++v) vop[st_][v] = sc * (double)sx[row * XP + 16 + v];
+  }
+  __syncthreads();  // s_rr complete
+  if (threadIdx.x < R)
+    rr_part[(size_t)blockIdx.x * R + threadIdx.x] =
+        (s_rr[0][threadIdx.x] + s_rr[1][threadIdx.x]) + (s_rr[2][threadIdx.x] + s_rr[3][threadIdx.x]);
+  const int KR = k * R;
+  for (int i0 = 0; i0 < k; i0 += 64) {  // groups of four 16-column blocks of U
+    dski_pdbl4 acc[4][MB];
+    double vacc[4][VR > 0 ? VR : 1];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+      for (int cb = 0; cb < MB; ++cb) acc[b][cb] = dski_pdbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int v = 0; v < VR; ++v) vacc[b][v] = 0.0;
+    }
+    const double* ub[4];
+    bool ok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + 16 * b + r16;
+      ok[b] = i < k;
+      ub[b] = U + (size_t)(ok[b] ? i : 0) * N;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // two halves of 8 steps: 32 loads in flight
+      double aop[8][4];
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int er = e0 + 4 * (8 * h + s8) + kq;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) aop[s8][b] = ld_or0(ub[b], (size_t)er, 0, ok[b] && er < N);
+      }
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+          for (int cb = 0; cb < MB; ++cb)
+            acc[b][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s8][b], bop[8 * h + s8][cb], acc[b][cb], 0, 0, 0);
+#pragma unroll
+          for (int v = 0; v < VR; ++v) vacc[b][v] += aop[s8][b] * vop[8 * h + s8][v];
+        }
+    }
+    // this wavefront's 64 x RB block of t: matrix-core part (register r of lane
+    // l: i = 16 b + l / 16 + 4 r, c = 16 cb + l % 16), vector part summed over
+    // the four lanes that share i
+    double* mine = st + (size_t)wv * S::TB;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+      for (int cb = 0; cb < MB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mine[(16 * b + kq + 4 * r) * CW + 16 * cb + r16] = acc[b][cb][r];
+#pragma unroll
+      for (int v = 0; v < VR; ++v) {
+        double x = vacc[b][v];
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 32, 64);
+        if (kq == 0) mine[(16 * b + r16) * CW + 16 + v] = x;
+      }
+    }
+    __syncthreads();
+    // the block's partial, four wavefronts in a fixed order, written coalesced
+    for (int f = threadIdx.x; f < 64 * R; f += 256) {
+      const int il = f / R, c = f - il * R, i = i0 + il;
+      if (i < k) {
+        const int o = il * CW + c;
+        t_part[(size_t)blockIdx.x * KR + (size_t)i * R + c] =
+            (st[o] + st[S::TB + o]) + (st[2 * S::TB + o] + st[3 * S::TB + o]);
+      }
+    }
+    __syncthreads();
+  }
 }
 
-template <typename T>
-static dski_status launch_update(int nw, const T* P, const T* Q, T* Rr, double* Xd, int N, int n, int R,
-                                 const PcgScal& s, int par, const double* pq_part, int nb_pq, double* rr_part,
-                                 const double* U, int k, double isf, double isg, double* t_part, double* hist,
-                                 int max_iter, hipStream_t st) {
-  const int nb = (nw + 3) / 4;
-  if (R <= 16) {
-    constexpr size_t sh = ProjLds<1>::bytes<T>();
-    static bool done = false;
-    DSKI_TRY(lds_limit(&k_pcg_update<T, 1>, sh, done));
-    k_pcg_update<T, 1><<<nb, kBlock, sh, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf,
-                                               isg, t_part, hist, max_iter);
-  } else {
-    constexpr size_t sh = ProjLds<2>::bytes<T>();
-    static bool done = false;
-    DSKI_TRY(lds_limit(&k_pcg_update<T, 2>, sh, done));
-    k_pcg_update<T, 2><<<nb, kBlock, sh, st>>>(P, Q, Rr, Xd, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf,
-                                               isg, t_part, hist, max_iter);
-  }
+template <typename T, int RB>
+static dski_status launch_update_rb(int nb, const T* Q, T* Rr, int N, int n, int R,
+                                    const PcgScal& s, int par, const double* pq_part, int nb_pq, double* rr_part,
+                                    const double* U, int k, double isf, double isg, double* t_part, double* hist,
+                                    int max_iter, hipStream_t st) {
+  constexpr size_t sh = UpdShape<RB>::template bytes<T>();
+  static bool done = false;
+  DSKI_TRY(lds_limit(&k_pcg_update<T, RB>, sh, done));
+  k_pcg_update<T, RB><<<nb, kBlock, sh, st>>>(Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf, isg,
+                                              t_part, hist, max_iter);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
 
-// beta, history (hist = the beta rows), convergence test, p = z + beta p.  Grid (row chunks of 256, R):
+// Partials are per work-group of 256 rows: nb = ceil(N / 256) blocks.
+template <typename T>
+static dski_status launch_update(int nb, const T* Q, T* Rr, int N, int n, int R,
+                                 const PcgScal& s, int par, const double* pq_part, int nb_pq, double* rr_part,
+                                 const double* U, int k, double isf, double isg, double* t_part, double* hist,
+                                 int max_iter, hipStream_t st) {
+#define DSKI_UPD(V)                                                                                          \
+  case V:                                                                                                    \
+    return launch_update_rb<T, V>(nb, Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf, isg, t_part, \
+                                  hist, max_iter, st);
+  switch (pad4(R)) {
+    DSKI_UPD(4)
+    DSKI_UPD(8)
+    DSKI_UPD(12)
+    DSKI_UPD(16)
+    DSKI_UPD(20)
+    DSKI_UPD(24)
+    DSKI_UPD(28)
+    DSKI_UPD(32)
+    default:
+      set_error("at most %d columns per fused PCG", kPcgMaxR);
+      return DSKI_ENOTSUP;
+  }
+#undef DSKI_UPD
+}
+
+// beta, history (hist = the beta rows), convergence test, x += alpha p and then
+// p = z + beta p (p of this iteration is read once for both).  Grid (row chunks of 256, R):
 // every block recomputes its column's beta from the r.z partials (same order);
 // block (0, c) writes the column's next-parity state.
 template <typename T>
-__global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, int R, PcgScal s, int par,
+__global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, double* __restrict__ Xd, int N, int R,
+                           PcgScal s, int par,
                            const double* __restrict__ rz_part, int nb_rz, double* __restrict__ hist,
                            int max_iter, int fixed_iters) {
   __shared__ double s_beta;
@@ -252,6 +370,7 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const size_t ip = (size_t)c * N + (e < N ? e : 0);
   const T zv = Z[ip], pv = P[ip];  // in flight while thread 0 forms beta
+  const double xv = Xd[ip];
   {
     if (threadIdx.x == 0) {
       double rz_old = s.rz[par * R + c];
@@ -273,7 +392,10 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, int N, in
     }
   }
   __syncthreads();
-  if (e < N) P[ip] = (T)((double)zv + s_beta * (double)pv);
+  if (e < N) {
+    Xd[ip] = xv + s.alpha[c] * (double)pv;  // x += alpha p with this iteration's p
+    P[ip] = (T)((double)zv + s_beta * (double)pv);
+  }
 }
 
 // True residual r = b - y (y = K~ x from the FP64-storage operator): stored into Rr
@@ -356,7 +478,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   const int k = pc ? pc->k : 0;
   const size_t nr = (size_t)N * R;
   const int nbv = nchunks(N), nbg = gather_blocks(p), nbz = vec_blocks(N);
-  const int nbt = proj_waves(N);
+  const int nbt = (proj_waves(N) + 3) / 4;  // update work-groups (256 rows each)
   const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, nbt)) * R;
   const size_t ntp = (size_t)nbt * std::max(k, 1) * R;
   // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, scratch (R), coef, scalars
@@ -413,19 +535,19 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   // one iteration, all launches on stream `q`
   auto iterate = [&](int par, hipStream_t q) -> dski_status {
     DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, q));
-    DSKI_TRY(launch_update<T>(nbt, P, Q, Rr, Xd, N, n, R, s, par, pq_part, nbg, rr_part, U, pc ? k : 0, isf,
-                              isg, t_part, hist, max_iter, q));
+    DSKI_TRY(launch_update<T>(nbt, Q, Rr, N, n, R, s, par, pq_part, nbg, rr_part, U, pc ? k : 0, isf, isg, t_part,
+                              hist, max_iter, q));
     RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
     if (pc && k > 0) {
       RedJob jt{t_part, nbt, k * R, R, t1, pc->w, nullptr, 1.0, coef, nullptr};
-      DSKI_TRY(launch_reduce(jt, &jr, q));
+      DSKI_TRY(launch_reduce_bm(jt, &jr, q));
       DSKI_TRY(launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part, q));
     } else {
-      DSKI_TRY(launch_reduce(jr, nullptr, q));
+      DSKI_TRY(launch_reduce_bm(jr, nullptr, q));
       if (pc)  // rank-0 preconditioner: M = D
         DSKI_TRY(launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N, rz_part, q));
     }
-    k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(pc ? Z : Rr, P, N, R, s, par, pc ? rz_part : nullptr, nbz, hist_b,
+    k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(pc ? Z : Rr, P, Xd, N, R, s, par, pc ? rz_part : nullptr, nbz, hist_b,
                                                   max_iter, fixed_iters);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;

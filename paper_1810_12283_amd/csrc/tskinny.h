@@ -206,6 +206,48 @@ static inline dski_status launch_reduce(const RedJob& a, const RedJob* b, hipStr
   return DSKI_OK;
 }
 
+// The same reduction for block-major partials (partial[b nout + o], written
+// coalesced by one work-group each): a work-group takes 64 consecutive outputs,
+// its four wavefronts add contiguous quarters of the blocks in order, and the
+// quarters are combined in a fixed order.
+static __global__ __launch_bounds__(256) void k_ts_reduce_bm(RedJob j0, RedJob j1) {
+  const RedJob& J = blockIdx.y == 0 ? j0 : j1;
+  __shared__ double q[4][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 64 + lane;
+  if (blockIdx.x * 64 >= J.nout) return;
+  const int per = (J.nblk + 3) / 4, b0 = wv * per, b1 = min(J.nblk, b0 + per);
+  double a = 0.0;
+  if (o < J.nout) {
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {  // eight loads in flight, added in order
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = J.partial[(size_t)(b + u) * J.nout + o];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += v[u];
+    }
+    for (; b < b1; ++b) a += J.partial[(size_t)b * J.nout + o];
+  }
+  q[wv][lane] = a;
+  __syncthreads();
+  if (wv == 0 && o < J.nout) {
+    const double t = (q[0][lane] + q[1][lane]) + (q[2][lane] + q[3][lane]);
+    const bool write = !J.mask || J.mask[o % J.R];
+    if (J.out && write) J.out[o] = t;
+    if (J.coef) J.coef[o] = J.sgn * J.c[o / J.R] * (t + (J.t_prev ? J.t_prev[o] : 0.0));
+  }
+}
+
+static inline dski_status launch_reduce_bm(const RedJob& a, const RedJob* b, hipStream_t st) {
+  const int nout = std::max(a.nout, b ? b->nout : 0);
+  dim3 grid((nout + 63) / 64, b ? 2 : 1);
+  RedJob bb = b ? *b : a;
+  k_ts_reduce_bm<<<grid, 256, 0, st>>>(a, bb);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
 // z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]), one wavefront
 // per 64 rows: the product U coef on the FP64 matrix cores (A = U, 16 rows x 4
 // of its columns per load; B = coef, 4 x 16), CB blocks of 16 columns; the
