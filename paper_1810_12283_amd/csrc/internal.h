@@ -124,6 +124,13 @@ struct dski_plan_s {
   double* toff = nullptr;      // d x n offsets in [0, 1] (SoA, FP64)
   double* wts = nullptr;       // d x 8 x n: Keys weights w_0..w_3 and dw_0..dw_3 / h per axis (FP64)
   int* cell_start = nullptr;   // ncells + 1
+  // scatter region tables (per node tile: its region's points, see mvm.hip)
+  int* tile_off = nullptr;     // tiles + 1 slot offsets
+  int* tile_lcs = nullptr;     // tiles x (region cells + 1) local point ranges
+  int* tile_pts = nullptr;     // slots: point (tile order)
+  int* tile_cl = nullptr;      // slots: last-axis cell of the point
+  double* tile_w = nullptr;    // 8 d x slots: the point's weights
+  long long tile_slots = 0;
   // workspaces
   dski::DevBuf grid;           // FP64 grid buffer, M * Rmax
   dski::DevBuf vin, vout;      // tile-ordered FP32 vectors
@@ -159,6 +166,7 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich 
 dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, int a, int variant);
 template <typename T>
 dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st);
+dski_status scatter_tables(dski_plan p, hipStream_t st);  // build the region tables (plan set-up)
 template <typename T>
 dski_status gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
                    double nv, double ng, double* pq_partial, hipStream_t st);

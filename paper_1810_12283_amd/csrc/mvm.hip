@@ -14,6 +14,7 @@
 //   gather   Y = S G + D V  one thread per point, FP64 accumulation, FP32 store,
 //                           optional fused per-block partials of V.Y.
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 
@@ -89,32 +90,150 @@ struct TileShape {
   static constexpr int last_span = ext(D - 1) + 3;
 };
 
-template <int D, int CR, typename T, typename VS, int PMAX>
+// Region of a tile: the cells whose stencils reach its nodes (the tile's cells
+// plus a halo of 2 below / 1 above, clipped), as per-axis first cell rlo and
+// span; rows = all region axes but the last (their cells are contiguous in the
+// sorted order).
+template <int D>
+struct TileRegion {
+  int origin[D], span[D], rlo[D];
+  int nrows, ncells;
+  __device__ TileRegion(int tile, const GeoK& g) {
+    using TS = TileShape<D>;
+    int rem = tile;
+    for (int a = D - 1; a >= 0; --a) {
+      const int nt = (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
+      origin[a] = (rem % nt) * TS::ext(a);
+      rem /= nt;
+    }
+    nrows = 1;
+    ncells = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int tlast = min(origin[a] + TS::ext(a) - 1, g.m[a] - 1);
+      rlo[a] = max(1, origin[a] - 2);
+      const int rhi = min(g.nc[a], tlast + 1);
+      span[a] = rhi - rlo[a] + 1;
+      ncells *= span[a];
+      if (a < D - 1) nrows *= span[a];
+    }
+  }
+};
+
+// Per-row point ranges of a tile's region in LDS (global first point s_rg0, first
+// region cell s_rcb, local offset s_roff, total in s_roff[nrows]); all threads.
+template <int D>
+__device__ void tile_rows(const TileRegion<D>& T, const GeoK& g, const int* __restrict__ cstart, int* s_rg0,
+                          int* s_rcb, int* s_rcnt, int* s_roff) {
+  const int last = D - 1;
+  for (int row = threadIdx.x; row < T.nrows; row += blockDim.x) {
+    int rem = row, base = 0;
+    int c[D];
+    for (int a = last - 1; a >= 0; --a) {
+      c[a] = T.rlo[a] + rem % T.span[a];
+      rem /= T.span[a];
+    }
+    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+    base = base * g.nc[last] + T.rlo[last] - 1;
+    const int g0 = cstart[base];
+    const int g1 = cstart[base + T.span[last]];
+    s_rcb[row] = base;
+    s_rg0[row] = g0;
+    s_rcnt[row] = g1 - g0;
+  }
+  __syncthreads();
+  // exclusive prefix of the row counts (wavefront 0, 64 rows per step)
+  if (threadIdx.x < 64) {
+    int carry = 0;
+    for (int rb = 0; rb < T.nrows; rb += 64) {
+      const int row = rb + threadIdx.x;
+      const int v = row < T.nrows ? s_rcnt[row] : 0;
+      int incl = v;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if ((int)threadIdx.x >= off) incl += o;
+      }
+      if (row < T.nrows) s_roff[row] = carry + incl - v;
+      carry += __shfl(incl, 63, 64);
+    }
+    if (threadIdx.x == 0) s_roff[T.nrows] = carry;
+  }
+  __syncthreads();
+}
+
+// Plan set-up, pass 1: the number of points in every tile's region.
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_count(const int* __restrict__ cstart, GeoK g,
+                                                    int* __restrict__ total) {
+  using TS = TileShape<D>;
+  __shared__ int s_rg0[TS::max_rows], s_rcb[TS::max_rows], s_rcnt[TS::max_rows], s_roff[TS::max_rows + 1];
+  const TileRegion<D> T(blockIdx.x, g);
+  tile_rows<D>(T, g, cstart, s_rg0, s_rcb, s_rcnt, s_roff);
+  if (threadIdx.x == 0) total[blockIdx.x] = s_roff[T.nrows];
+}
+
+// Plan set-up, pass 2: every tile's region tables (fixed by the points alone):
+// the local point range of each region cell (row-major, last axis fastest), and
+// for each local slot q (tile_off[t] + q) the point, its last-axis cell and its
+// 8 D interpolation weights (SoA with stride `slots`).
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_fill(const int* __restrict__ cell, const double* __restrict__ wts,
+                                                   const int* __restrict__ cstart, int n, GeoK g,
+                                                   const int* __restrict__ tile_off, int* __restrict__ tile_lcs,
+                                                   int* __restrict__ tile_pts, int* __restrict__ tile_cl,
+                                                   double* __restrict__ tile_w, long long slots) {
+  using TS = TileShape<D>;
+  __shared__ int s_rg0[TS::max_rows], s_rcb[TS::max_rows], s_rcnt[TS::max_rows], s_roff[TS::max_rows + 1];
+  const int last = D - 1;
+  const TileRegion<D> T(blockIdx.x, g);
+  tile_rows<D>(T, g, cstart, s_rg0, s_rcb, s_rcnt, s_roff);
+  const int total = s_roff[T.nrows];
+  int* lcs = tile_lcs + (size_t)blockIdx.x * (TS::max_cells + 1);
+  for (int f = threadIdx.x; f < T.nrows * TS::last_span; f += blockDim.x) {
+    const int row = f / TS::last_span, cl = f % TS::last_span;
+    if (cl < T.span[last]) lcs[row * T.span[last] + cl] = cstart[s_rcb[row] + cl] - s_rg0[row] + s_roff[row];
+  }
+  if (threadIdx.x == 0) lcs[T.ncells] = total;
+  const long long off = tile_off[blockIdx.x];
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    int lo_r = 0, hi_r = T.nrows - 1;  // last row with s_roff[row] <= q
+    while (lo_r < hi_r) {
+      const int mid = (lo_r + hi_r + 1) >> 1;
+      if (s_roff[mid] <= q) lo_r = mid; else hi_r = mid - 1;
+    }
+    const int kq = s_rg0[lo_r] + q - s_roff[lo_r];
+    tile_pts[off + q] = kq;
+    tile_cl[off + q] = cell[kq] % g.nc[last] + 1;
+    for (int a8 = 0; a8 < D * 8; ++a8) tile_w[a8 * slots + off + q] = wts[(size_t)a8 * n + kq];
+  }
+}
+
+template <int D, int CR, typename T, int PMAX>
 __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cell,
                                                      const double* __restrict__ wts,
                                                      const int* __restrict__ cstart, int n, GeoK g,
+                                                     const int* __restrict__ tile_off,
+                                                     const int* __restrict__ tile_lcs,
+                                                     const int* __restrict__ tile_pts,
+                                                     const int* __restrict__ tile_cl,
+                                                     const double* __restrict__ tile_w, long long slots,
                                                      const T* __restrict__ V, int ldv, int R, int cr,
                                                      double* __restrict__ G, long long M) {
   static_assert(PMAX == 256, "one thread stages one region point");
   using TS = TileShape<D>;
   __shared__ double s_w[D * 8][PMAX];
-  __shared__ VS s_v[PMAX * CR * (D + 1)];
+  __shared__ T s_v[PMAX * CR * (D + 1)];
   __shared__ int s_lcs[TS::max_cells + 1];
-  __shared__ int s_rcnt[TS::max_rows];
-  __shared__ int s_roff[TS::max_rows + 1];
-  __shared__ int s_rg0[TS::max_rows];
-  __shared__ int s_rcb[TS::max_rows];
   __shared__ int s_cl[PMAX];  // last-axis cell (1-based) of every region point
   const int last = D - 1;
-  // tile origin and this thread's node
+  const TileRegion<D> TR(blockIdx.x, g);
   int origin[D], span[D], rlo[D], jl[D];
-  {
-    int rem = blockIdx.x;
-    for (int a = D - 1; a >= 0; --a) {
-      int nt = (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
-      origin[a] = (rem % nt) * TS::ext(a);
-      rem /= nt;
-    }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    origin[a] = TR.origin[a];
+    span[a] = TR.span[a];
+    rlo[a] = TR.rlo[a];
   }
   if (D == 1) {
     jl[0] = threadIdx.x;
@@ -126,89 +245,35 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     jl[1] = (threadIdx.x / TS::e2) % TS::e1;
     jl[2] = threadIdx.x % TS::e2;
   }
-  int nrows = 1, ncells_r = 1;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    int tlast = min(origin[a] + TS::ext(a) - 1, g.m[a] - 1);
-    rlo[a] = max(1, origin[a] - 2);
-    int rhi = min(g.nc[a], tlast + 1);
-    span[a] = rhi - rlo[a] + 1;
-    ncells_r *= span[a];
-    if (a < last) nrows *= span[a];
-  }
   const int r0 = blockIdx.y * cr;
   const int rc = min(cr, R - r0);
-  // per-row global ranges (rows = all region axes but the last; cells of a row are contiguous)
-  for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
-    int rem = row, base = 0;
-    int c[D];
-    for (int a = last - 1; a >= 0; --a) {
-      c[a] = rlo[a] + rem % span[a];
-      rem /= span[a];
-    }
-    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
-    base = base * g.nc[last] + rlo[last] - 1;
-    const int g0 = cstart[base];
-    const int g1 = cstart[base + span[last]];
-    s_rcb[row] = base;
-    s_rg0[row] = g0;
-    s_rcnt[row] = g1 - g0;
-  }
-  __syncthreads();
-  // exclusive prefix of the row counts (wavefront 0, 64 rows per step)
-  if (threadIdx.x < 64) {
-    int carry = 0;
-    for (int rb = 0; rb < nrows; rb += 64) {
-      const int row = rb + threadIdx.x;
-      const int v = row < nrows ? s_rcnt[row] : 0;
-      int incl = v;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off, 64);
-        if ((int)threadIdx.x >= off) incl += o;
-      }
-      if (row < nrows) s_roff[row] = carry + incl - v;
-      carry += __shfl(incl, 63, 64);
-    }
-    if (threadIdx.x == 0) s_roff[nrows] = carry;
-  }
-  __syncthreads();
-  const int total = s_roff[nrows];
+  const long long off = tile_off[blockIdx.x];
+  const int total = (int)(tile_off[blockIdx.x + 1] - off);
   const bool lds_ok = total <= PMAX;
   if (lds_ok) {
-    // cell table (region-local, row-major) -> LDS point ranges
-    for (int f = threadIdx.x; f < nrows * TS::last_span; f += blockDim.x) {
-      const int row = f / TS::last_span, cl = f % TS::last_span;
-      if (cl < span[last])
-        s_lcs[row * span[last] + cl] = cstart[s_rcb[row] + cl] - s_rg0[row] + s_roff[row];
-    }
-    if (threadIdx.x == 0) s_lcs[ncells_r] = total;
-    // this thread's region point: its row by binary search of the row offsets,
-    // then its weights and column values (zero beyond the chunk)
+    // the region tables of the plan: cell ranges, and for this thread's slot the
+    // point, its last-axis cell and weights; then the point's column values
+    const int* lcs = tile_lcs + (size_t)blockIdx.x * (TS::max_cells + 1);
+    for (int f = threadIdx.x; f <= TR.ncells; f += blockDim.x) s_lcs[f] = lcs[f];
     const int q = threadIdx.x;
     if (q < total) {
-      int lo_r = 0, hi_r = nrows - 1;  // last row with s_roff[row] <= q
-      while (lo_r < hi_r) {
-        const int mid = (lo_r + hi_r + 1) >> 1;
-        if (s_roff[mid] <= q) lo_r = mid; else hi_r = mid - 1;
-      }
-      const int kq = s_rg0[lo_r] + q - s_roff[lo_r];
-      const int ck = cell[kq];
+      const int kq = tile_pts[off + q];
+      const int cq = tile_cl[off + q];
       double w[D * 8];
 #pragma unroll
-      for (int a8 = 0; a8 < D * 8; ++a8) w[a8] = wts[(size_t)a8 * n + kq];
-      VS x[CR * (D + 1)];
+      for (int a8 = 0; a8 < D * 8; ++a8) w[a8] = tile_w[a8 * slots + off + q];
+      T x[CR * (D + 1)];
 #pragma unroll
       for (int r = 0; r < CR; ++r)
 #pragma unroll
         for (int b = 0; b <= D; ++b)
-          x[r * (D + 1) + b] = (VS)ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
-                                          (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
+          x[r * (D + 1) + b] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
+                                      (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
 #pragma unroll
       for (int a8 = 0; a8 < D * 8; ++a8) s_w[a8][q] = w[a8];
 #pragma unroll
       for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
-      s_cl[q] = ck % g.nc[last] + 1;
+      s_cl[q] = cq;
     }
   }
   __syncthreads();
@@ -337,8 +402,9 @@ static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, h
   const int nch = (R + CR - 1) / CR;
   const int cr = (R + nch - 1) / nch;
   dim3 grid((unsigned)tiles, nch);
-  k_scatter_lds<D, CR, T, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv, R, cr,
-                                                         G, p->M);
+  k_scatter_lds<D, CR, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, p->tile_off,
+                                                      p->tile_lcs, p->tile_pts, p->tile_cl, p->tile_w,
+                                                      p->tile_slots, V, ldv, R, cr, G, p->M);
 }
 
 // Direct variant: one thread per (grid node, CRD columns), no LDS; cell ranges,
@@ -449,6 +515,57 @@ dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStrea
 }
 template dski_status scatter<float>(dski_plan, int, const float*, int, double*, hipStream_t);
 template dski_status scatter<double>(dski_plan, int, const double*, int, double*, hipStream_t);
+
+// Region tables of the LDS-tiled scatter, built once per plan: pass 1 counts
+// every tile's region points, the host forms the offsets, pass 2 fills the
+// tables (see k_tile_fill).
+template <int D>
+static dski_status build_tiles(dski_plan p, hipStream_t st) {
+  using TS = TileShape<D>;
+  GeoK g = geo_of(p);
+  long long tiles = 1;
+  for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
+  std::vector<int> tot((size_t)tiles), off((size_t)tiles + 1);
+  int* d_tot = nullptr;
+  DSKI_HIP(hipMalloc(&d_tot, sizeof(int) * (size_t)tiles));
+  k_tile_count<D><<<(unsigned)tiles, 256, 0, st>>>(p->cell_start, g, d_tot);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(tot.data(), d_tot, sizeof(int) * (size_t)tiles, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_tot);
+  DSKI_HIP(e);
+  long long slots = 0;
+  for (long long t = 0; t < tiles; ++t) {
+    off[(size_t)t] = (int)slots;
+    slots += tot[(size_t)t];
+  }
+  if (slots > (1ll << 31) - 1) {
+    set_error("scatter region tables too large");
+    return DSKI_ENOTSUP;
+  }
+  off[(size_t)tiles] = (int)slots;
+  p->tile_slots = slots;
+  DSKI_HIP(hipMalloc(&p->tile_off, sizeof(int) * (size_t)(tiles + 1)));
+  DSKI_HIP(hipMalloc(&p->tile_lcs, sizeof(int) * (size_t)tiles * (TS::max_cells + 1)));
+  DSKI_HIP(hipMalloc(&p->tile_pts, sizeof(int) * (size_t)std::max(slots, 1ll)));
+  DSKI_HIP(hipMalloc(&p->tile_cl, sizeof(int) * (size_t)std::max(slots, 1ll)));
+  DSKI_HIP(hipMalloc(&p->tile_w, sizeof(double) * 8 * D * (size_t)std::max(slots, 1ll)));
+  DSKI_HIP(hipMemcpyAsync(p->tile_off, off.data(), sizeof(int) * (size_t)(tiles + 1), hipMemcpyHostToDevice, st));
+  k_tile_fill<D><<<(unsigned)tiles, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, p->tile_off,
+                                                  p->tile_lcs, p->tile_pts, p->tile_cl, p->tile_w, slots);
+  DSKI_HIP(hipGetLastError());
+  DSKI_HIP(hipStreamSynchronize(st));
+  return DSKI_OK;
+}
+
+dski_status scatter_tables(dski_plan p, hipStream_t st) {
+  switch (p->d) {
+    case 1: return build_tiles<1>(p, st);
+    case 2: return build_tiles<2>(p, st);
+    case 3: return build_tiles<3>(p, st);
+    default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
+  }
+}
 
 // ------------------------------------------------------------------ K_UU by FFT
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {

@@ -328,6 +328,11 @@ dski_status dski_plan_destroy(dski_plan p) {
   (void)hipFree(p->toff);
   (void)hipFree(p->wts);
   (void)hipFree(p->cell_start);
+  (void)hipFree(p->tile_off);
+  (void)hipFree(p->tile_lcs);
+  (void)hipFree(p->tile_pts);
+  (void)hipFree(p->tile_cl);
+  (void)hipFree(p->tile_w);
   for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     (void)hipFree(p->ax[a].twiddle);
     (void)hipFree(p->ax[a].spec);
@@ -475,7 +480,9 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
     if (herr) {
       set_error("a point lies outside the interpolation box (or is not finite)");
       rc = DSKI_EINVAL;
+      break;
     }
+    rc = scatter_tables(p, st);
   } while (0);
   (void)hipFree(tmp);
   return rc;
