@@ -1,6 +1,7 @@
 // Per-shape autotuning of kernel variants.  The scatter (W^T) has three
 // LDS-tiled forms (base, 1.5 and 2 times the base number of columns per
-// work-group) and two cache-direct forms, all with identical results; each K_UU factor has a
+// work-group) and two cache-direct forms, all with identical results; the
+// gather (W) takes 2, 1 or 4 columns per thread (identical results); each K_UU factor has a
 // circulant-FFT and a dense matrix-core form (equal up to rounding).  Which is
 // faster depends on the grid size, the number of points per cell and the
 // number of right-hand sides.  The tuner times each candidate with HIP events
@@ -12,7 +13,8 @@
 namespace dski {
 
 constexpr int kScatterVariants = 5;
-constexpr int kTuneTimes = kScatterVariants + 2 * DSKI_MAXD;
+constexpr int kGatherVariants = 3;
+constexpr int kTuneTimes = kScatterVariants + kGatherVariants + 2 * DSKI_MAXD;
 
 __global__ void k_fill_pm1(float* __restrict__ out, size_t len, uint64_t seed) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
@@ -75,11 +77,28 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
     if (t[v] < t[best_s]) best_s = v;
   }
   p->scatter_variant = best_s;
+  // gather: columns per thread (on the scattered grid; writes into the second half of V)
+  int best_g = 0;
+  if (p->kind == 0) {
+    DevBuf ybuf;
+    DSKI_TRY(ybuf.reserve(sizeof(float) * nv + 64));
+    float* Y = ybuf.as<float>();
+    for (int v = 0; v < kGatherVariants; ++v) {
+      p->gather_variant = v;
+      double* tg = t + kScatterVariants;
+      DSKI_TRY(time_us([&]() { return gather<float>(p, R, G, V, N, Y, N, 1.0, 1.0, nullptr, st); }, reps, st,
+                       &tg[v]));
+      if (tg[v] < tg[best_g]) best_g = v;
+    }
+    DSKI_HIP(hipStreamSynchronize(st));
+    ybuf.release();
+  }
+  p->gather_variant = best_g;
   // K_UU per axis: FFT or dense matrix-core product (on the scattered grid)
   for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     int best = 0;
     for (int v = 0; v < 2; ++v) {
-      double* ta = t + kScatterVariants + 2 * a;
+      double* ta = t + kScatterVariants + kGatherVariants + 2 * a;
       DSKI_TRY(time_us([&]() { return kuu_axis(p, R, G, st, -1, a, v); }, reps, st, &ta[v]));
       if (ta[v] < ta[best]) best = v;
     }
@@ -92,12 +111,14 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
   return DSKI_OK;
 }
 
-extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant) {
-  if (!p || scatter_variant < 0 || scatter_variant >= kScatterVariants) {
+extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant, int gather_variant) {
+  if (!p || scatter_variant < 0 || scatter_variant >= kScatterVariants || gather_variant < 0 ||
+      gather_variant >= kGatherVariants) {
     set_error("dski_set_variants: bad arguments");
     return DSKI_EINVAL;
   }
   p->scatter_variant = scatter_variant;
+  p->gather_variant = gather_variant;
   return DSKI_OK;
 }
 

@@ -1030,20 +1030,30 @@ dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich)
 }
 
 // ------------------------------------------------------------------ gather + noise
-// One thread per (point, column): the 4^d grid values of the column are read
-// once and give the value and all d derivative rows.  Y = S G + D V with FP64
-// accumulation; optional per-block partials of V.Y per column (p^T q of CG),
-// stored output-major: pq_partial[column * blocks + block].
-template <int D, typename T>
+// One thread per (point, group of CG columns): the point's weights are read
+// once for the group, the 4^d grid values of each column give the value and
+// all d derivative rows.  Y = S G + D V with FP64 accumulation; optional
+// per-block partials of V.Y per column (p^T q of CG), stored output-major:
+// pq_partial[column * blocks + block].  The 1-D grid is laid out so that all
+// column groups of one block of points run on the same XCD (the hardware deals
+// work-groups to the 8 XCDs in turn): the points' weights are fetched into one
+// L2.  The number of point blocks is padded to a multiple of 8; padded blocks
+// write zero partials.
+template <int D, int CG, typename T>
 __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
                                                 const double* __restrict__ wts, int n, GeoK g,
                                                 const double* __restrict__ G, long long M,
                                                 const T* __restrict__ V, int ldv,
-                                                T* __restrict__ Y, int ldy, int R, double nv,
+                                                T* __restrict__ Y, int ldy, int R, int ngy, double nv,
                                                 double ng, double* __restrict__ pq_partial) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  const int r = blockIdx.y;
-  double dot = 0.0;
+  const unsigned bid = blockIdx.x, xcd = bid & 7u, sq = bid >> 3;
+  const int bx = (int)(xcd + 8u * (sq / (unsigned)ngy));   // point block
+  const int r0 = (int)(sq % (unsigned)ngy) * CG;          // first column of the group
+  const int nbx = (int)(gridDim.x / (unsigned)ngy);       // point blocks (multiple of 8)
+  const int k = bx * 256 + threadIdx.x;
+  double dot[CG];
+#pragma unroll
+  for (int j = 0; j < CG; ++j) dot[j] = 0.0;
   if (k < n) {
     double w[D][4], dw[D][4];
     int c[D];
@@ -1067,81 +1077,130 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
     stride[D - 1] = 1;
 #pragma unroll
     for (int a = D - 2; a >= 0; --a) stride[a] = stride[a + 1] * g.m[a + 1];
-    const double* Gr = G + (size_t)r * M + base;
-    double acc[D + 1];
+    // the grid values of every column of the group, loaded together
+    constexpr int NG = D == 1 ? 4 : (D == 2 ? 16 : 64);
+    double gv[CG][NG];
 #pragma unroll
-    for (int q = 0; q <= D; ++q) acc[q] = 0.0;
-    if (D == 1) {
+    for (int j = 0; j < CG; ++j) {
+      const bool ok = r0 + j < R;
+      const double* Gr = G + (size_t)(ok ? r0 + j : r0) * M + base;
 #pragma unroll
-      for (int o0 = 0; o0 < 4; ++o0) {
-        double gv = Gr[o0];
-        acc[0] += w[0][o0] * gv;
-        acc[1] += dw[0][o0] * gv;
-      }
-    } else if (D == 2) {
-#pragma unroll
-      for (int o0 = 0; o0 < 4; ++o0) {
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int o1 = 0; o1 < 4; ++o1) {
-          double gv = Gr[o0 * stride[0] + o1];
-          s0 += w[D - 1][o1] * gv;
-          s1 += dw[D - 1][o1] * gv;
-        }
-        acc[0] += w[0][o0] * s0;
-        acc[1] += dw[0][o0] * s0;
-        acc[2] += w[0][o0] * s1;
-      }
-    } else {
-#pragma unroll
-      for (int o0 = 0; o0 < 4; ++o0) {
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-#pragma unroll
-        for (int o1 = 0; o1 < 4; ++o1) {
-          double s0 = 0.0, s2 = 0.0;
-#pragma unroll
-          for (int o2 = 0; o2 < 4; ++o2) {
-            double gv = Gr[o0 * stride[0] + o1 * stride[1] + o2];
-            s0 += w[D - 1][o2] * gv;
-            s2 += dw[D - 1][o2] * gv;
-          }
-          t0 += w[1][o1] * s0;
-          t1 += dw[1][o1] * s0;
-          t2 += w[1][o1] * s2;
-        }
-        acc[0] += w[0][o0] * t0;
-        acc[1] += dw[0][o0] * t0;
-        acc[2] += w[0][o0] * t1;
-        acc[3] += w[0][o0] * t2;
+      for (int f = 0; f < NG; ++f) {
+        long long off;
+        if (D == 1) off = f;
+        else if (D == 2) off = (f >> 2) * stride[0] + (f & 3);
+        else off = (f >> 4) * stride[0] + ((f >> 2) & 3) * stride[1] + (f & 3);
+        gv[j][f] = ok ? Gr[off] : 0.0;
       }
     }
-    const T* vv = V + (size_t)r * ldv + k;
-    T* yy = Y + (size_t)r * ldy + k;
+    T vin_t[CG][D + 1];
 #pragma unroll
-    for (int q = 0; q <= D; ++q) {
-      double vin = (double)vv[(size_t)q * n];
-      T out = (T)(acc[q] + (q == 0 ? nv : ng) * vin);
-      yy[(size_t)q * n] = out;
-      dot += vin * (double)out;
+    for (int j = 0; j < CG; ++j)
+#pragma unroll
+      for (int q = 0; q <= D; ++q)
+        vin_t[j][q] = ld_or0(V, (size_t)(r0 + j) * ldv + (size_t)q * n + k, (size_t)r0 * ldv + (size_t)q * n + k,
+                             r0 + j < R);
+#pragma unroll
+    for (int j = 0; j < CG; ++j) {
+      double acc[D + 1];
+#pragma unroll
+      for (int q = 0; q <= D; ++q) acc[q] = 0.0;
+      if (D == 1) {
+#pragma unroll
+        for (int o0 = 0; o0 < 4; ++o0) {
+          acc[0] += w[0][o0] * gv[j][o0];
+          acc[1] += dw[0][o0] * gv[j][o0];
+        }
+      } else if (D == 2) {
+#pragma unroll
+        for (int o0 = 0; o0 < 4; ++o0) {
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int o1 = 0; o1 < 4; ++o1) {
+            const double x = gv[j][o0 * 4 + o1];
+            s0 += w[D - 1][o1] * x;
+            s1 += dw[D - 1][o1] * x;
+          }
+          acc[0] += w[0][o0] * s0;
+          acc[1] += dw[0][o0] * s0;
+          acc[2] += w[0][o0] * s1;
+        }
+      } else {
+#pragma unroll
+        for (int o0 = 0; o0 < 4; ++o0) {
+          double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+          for (int o1 = 0; o1 < 4; ++o1) {
+            double s0 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int o2 = 0; o2 < 4; ++o2) {
+              const double x = gv[j][o0 * 16 + o1 * 4 + o2];
+              s0 += w[D - 1][o2] * x;
+              s2 += dw[D - 1][o2] * x;
+            }
+            t0 += w[1][o1] * s0;
+            t1 += dw[1][o1] * s0;
+            t2 += w[1][o1] * s2;
+          }
+          acc[0] += w[0][o0] * t0;
+          acc[1] += dw[0][o0] * t0;
+          acc[2] += w[0][o0] * t1;
+          acc[3] += w[0][o0] * t2;
+        }
+      }
+      if (r0 + j < R) {
+        T* yy = Y + (size_t)(r0 + j) * ldy + k;
+#pragma unroll
+        for (int q = 0; q <= D; ++q) {
+          const double vin = (double)vin_t[j][q];
+          const T out = (T)(acc[q] + (q == 0 ? nv : ng) * vin);
+          yy[(size_t)q * n] = out;
+          dot[j] += vin * (double)out;
+        }
+      }
     }
   }
   if (pq_partial) {
-    __shared__ double red[4];
-    for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dot;
+    __shared__ double red[CG][4];
+#pragma unroll
+    for (int j = 0; j < CG; ++j) {
+      double d = dot[j];
+      for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+      if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = d;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) pq_partial[(size_t)r * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x < CG && r0 + (int)threadIdx.x < R) {
+      const int j = threadIdx.x;
+      pq_partial[(size_t)(r0 + j) * nbx + bx] = red[j][0] + red[j][1] + red[j][2] + red[j][3];
+    }
   }
 }
 
-int gather_blocks(dski_plan p) { return p->kind == 1 ? (p->N + 255) / 256 : (p->n + 255) / 256; }
+static int gather_point_blocks(dski_plan p) { return (((p->n + 255) / 256) + 7) & ~7; }
+int gather_blocks(dski_plan p) { return p->kind == 1 ? (p->N + 255) / 256 : gather_point_blocks(p); }
+
+template <int D, int CG, typename T>
+static void launch_gather_cg(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy, double nv,
+                             double ng, double* pq_partial, hipStream_t st) {
+  GeoK g = geo_of(p);
+  const int ngy = (R + CG - 1) / CG;
+  const unsigned nb = (unsigned)(gather_point_blocks(p) * ngy);
+  k_gather<D, CG, T><<<nb, 256, 0, st>>>(p->cell, p->wts, p->n, g, G, p->M, V, ldv, Y, ldy, R, ngy, nv, ng,
+                                         pq_partial);
+}
 
 template <int D, typename T>
 static void launch_gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
                           double nv, double ng, double* pq_partial, hipStream_t st) {
-  GeoK g = geo_of(p);
-  k_gather<D, T><<<dim3(gather_blocks(p), R), 256, 0, st>>>(p->cell, p->wts, p->n, g, G, p->M, V, ldv, Y,
-                                                            ldy, R, nv, ng, pq_partial);
+  if constexpr (D == 3) {  // 64 grid values per column: one column per thread
+    launch_gather_cg<D, 1, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st);
+  } else {
+    switch (p->gather_variant) {
+      case 1: launch_gather_cg<D, 1, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+      case 2: launch_gather_cg<D, 4, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+      default: launch_gather_cg<D, 2, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    }
+  }
 }
 
 template <typename T>

@@ -66,7 +66,7 @@ _SIGS = {
     "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
     "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_autotune": (C.c_int, [vp, C.c_int, dp, vp]),
-    "dski_set_variants": (C.c_int, [vp, C.c_int]),
+    "dski_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
     "dski_set_graph": (C.c_int, [vp, C.c_int]),
     "dski_set_kuu_variant": (C.c_int, [vp, C.c_int, C.c_int]),
     "mlp_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, C.c_int, vp, vp]),
@@ -248,13 +248,13 @@ class Plan:
 
     def autotune(self, R: int, stream=None) -> dict:
         """Time the kernel variants for this shape and keep the fastest."""
-        t = (C.c_double * 11)()
+        t = (C.c_double * 14)()
         _check(lib().dski_autotune(self._h, int(R), t, _stream(stream)), "dski_autotune")
-        return {"scatter_us": [t[0], t[1], t[2], t[3], t[4]],
-                "kuu_us": [[t[5 + 2 * a], t[6 + 2 * a]] for a in range(min(self.d, 3))]}
+        return {"scatter_us": [t[0], t[1], t[2], t[3], t[4]], "gather_us": [t[5], t[6], t[7]],
+                "kuu_us": [[t[8 + 2 * a], t[9 + 2 * a]] for a in range(min(self.d, 3))]}
 
-    def set_variants(self, scatter: int):
-        _check(lib().dski_set_variants(self._h, int(scatter)), "dski_set_variants")
+    def set_variants(self, scatter: int, gather: int = 0):
+        _check(lib().dski_set_variants(self._h, int(scatter), int(gather)), "dski_set_variants")
 
     def set_kuu_variant(self, axis: int, variant: int):
         """K_UU factor of one axis: 0 FFT, 1 dense matrix-core product."""

@@ -127,14 +127,18 @@ def test_rademacher_matches_oracle_stream():
 
 @pytest.mark.parametrize("name", ["terrain_small", "torus_small"])
 def test_kernel_variants_agree(name):
-    """Every scatter variant gives the same bits; the autotuner's choice is one of them."""
+    """Every scatter variant gives the same bits, and so does every gather
+    variant; the autotuner's choice is one of them."""
     W = dict(small_workloads())[name]
     say("variants", name)
     plan, op = make(W)
     V = to_gpu(np.random.default_rng(4).standard_normal((op.N, 17)))
     outs = []
     for v in range(5):
-        plan.set_variants(v)
+        plan.set_variants(v, 0)
+        outs.append(plan.mvm(V))
+    for gv in range(3):
+        plan.set_variants(0, gv)
         outs.append(plan.mvm(V))
     for o in outs[1:]:
         assert torch.equal(outs[0], o)

@@ -77,7 +77,7 @@ def test_pcg_true_residual(name, bits, variant):
     W = {"small2d": workloads.small2d(), "terrain_small": workloads.terrain(n=3000, grid=60)}[name]
     say("pcg", name, bits, "scatter variant", variant)
     plan, op = make(W)
-    plan.set_variants(variant)  # every scatter form
+    plan.set_variants(variant, variant % 3)  # every scatter and gather form
     pc = plan.pivchol(W.rank)
     Wr = orng.rademacher(SEED, 0, 2, op.N)
     B = np.concatenate([W.y[:, None], Wr], axis=1).astype(np.float32).astype(np.float64)
