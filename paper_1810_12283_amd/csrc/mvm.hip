@@ -783,16 +783,16 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
     }
     __syncthreads();
     const int tot = S::NL * m;
-    for (int f0 = threadIdx.x; f0 < tot; f0 += 1024) {
-      double x[4];
+    for (int f0 = threadIdx.x; f0 < tot; f0 += 2048) {  // eight branch-free loads in flight per thread
+      double x[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int f = f0 + 256 * u;
         const long long b = f < tot ? s_base[f & (S::NL - 1)] : -1;
-        x[u] = b >= 0 ? G[b + (long long)(f >> S::LGNL) * inner] : 0.0;
+        x[u] = ld_or0(G, (size_t)(b + (long long)(f >> S::LGNL) * inner), 0, b >= 0);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int f = f0 + 256 * u;
         if (f < tot) {
           const int l = f & (S::NL - 1);

@@ -207,16 +207,16 @@ static inline dski_status launch_reduce(const RedJob& a, const RedJob* b, hipStr
 }
 
 // The same reduction for block-major partials (partial[b nout + o], written
-// coalesced by one work-group each): a work-group takes 64 consecutive outputs,
-// its four wavefronts add contiguous quarters of the blocks in order, and the
-// quarters are combined in a fixed order.
+// coalesced by one work-group each): a work-group takes 16 consecutive outputs;
+// its 256 threads split the blocks into 16 contiguous parts (thread = output +
+// 16 part), each part added in order, the parts combined in a fixed order.
 static __global__ __launch_bounds__(256) void k_ts_reduce_bm(RedJob j0, RedJob j1) {
   const RedJob& J = blockIdx.y == 0 ? j0 : j1;
-  __shared__ double q[4][64];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int o = blockIdx.x * 64 + lane;
-  if (blockIdx.x * 64 >= J.nout) return;
-  const int per = (J.nblk + 3) / 4, b0 = wv * per, b1 = min(J.nblk, b0 + per);
+  __shared__ double q[16][17];
+  const int ol = threadIdx.x & 15, part = threadIdx.x >> 4;
+  const int o = blockIdx.x * 16 + ol;
+  if (blockIdx.x * 16 >= J.nout) return;
+  const int per = (J.nblk + 15) / 16, b0 = part * per, b1 = min(J.nblk, b0 + per);
   double a = 0.0;
   if (o < J.nout) {
     int b = b0;
@@ -229,10 +229,12 @@ static __global__ __launch_bounds__(256) void k_ts_reduce_bm(RedJob j0, RedJob j
     }
     for (; b < b1; ++b) a += J.partial[(size_t)b * J.nout + o];
   }
-  q[wv][lane] = a;
+  q[part][ol] = a;
   __syncthreads();
-  if (wv == 0 && o < J.nout) {
-    const double t = (q[0][lane] + q[1][lane]) + (q[2][lane] + q[3][lane]);
+  if (part == 0 && o < J.nout) {
+    double t = 0.0;
+#pragma unroll
+    for (int pp = 0; pp < 16; ++pp) t += q[pp][ol];
     const bool write = !J.mask || J.mask[o % J.R];
     if (J.out && write) J.out[o] = t;
     if (J.coef) J.coef[o] = J.sgn * J.c[o / J.R] * (t + (J.t_prev ? J.t_prev[o] : 0.0));
@@ -241,7 +243,7 @@ static __global__ __launch_bounds__(256) void k_ts_reduce_bm(RedJob j0, RedJob j
 
 static inline dski_status launch_reduce_bm(const RedJob& a, const RedJob* b, hipStream_t st) {
   const int nout = std::max(a.nout, b ? b->nout : 0);
-  dim3 grid((nout + 63) / 64, b ? 2 : 1);
+  dim3 grid((nout + 15) / 16, b ? 2 : 1);
   RedJob bb = b ? *b : a;
   k_ts_reduce_bm<<<grid, 256, 0, st>>>(a, bb);
   DSKI_HIP(hipGetLastError());
