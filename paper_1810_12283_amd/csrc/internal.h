@@ -151,7 +151,8 @@ struct dski_precond_s {
   double logdet = 0;
   int* piv_tile = nullptr;     // device, k pivots (tile-order N-index)
   double* L = nullptr;         // device, N x k FP64 (tile order, column-major)
-  double* U = nullptr;         // device, N x k FP64 left singular vectors of D^{-1/2} L
+  double* U = nullptr;         // device, N x k FP64 left singular vectors of D^{-1/2} L (column-major)
+  double* Ur = nullptr;        // device, the same N x k row-major (row e at Ur + e k)
   double* w = nullptr;         // device, k: sigma_i^2 / (1 + sigma_i^2)
   double* rootc = nullptr;     // device, k: sqrt(1 + sigma_i^2) - 1
   dski::DevBuf work;

@@ -132,7 +132,7 @@ template <typename T, int RB>
 __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* __restrict__ Rr, int N, int n,
                                                     int R, PcgScal s, int par, const double* __restrict__ pq_part,
                                                     int nb_pq, double* __restrict__ rr_part,
-                                                    const double* __restrict__ U, int k, double isf, double isg,
+                                                    const double* __restrict__ Ur, int k, double isf, double isg,
                                                     double* __restrict__ t_part, double* __restrict__ hist,
                                                     int max_iter) {
   using S = UpdShape<RB>;
@@ -145,6 +145,24 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* 
   __shared__ double s_rr[4][RB];
   const int* act = s.active + par * R;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int w = blockIdx.x * 4 + wv;
+  const int e0 = w * kProjRows, e = e0 + lane;
+  // A operands of the projection (U rows 4 s + kq of the 64, columns i0 + 16 b + l % 16),
+  // for the first group of 64 columns issued before anything else: their latency
+  // overlaps alpha and the r update
+  double aop[16][4];
+  auto load_u = [&](int i0) {  // row-major U: 4 rows x 16 consecutive columns per load
+#pragma unroll
+    for (int s16 = 0; s16 < 16; ++s16) {
+      const int er = e0 + 4 * s16 + kq;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + 16 * b + r16;
+        aop[s16][b] = ld_or0(Ur, (size_t)er * k + i, 0, i < k && er < N);
+      }
+    }
+  };
+  if (k > 0) load_u(0);
   {  // alpha of every column at once: 8 lanes per column, all loads in flight together
     const int c = threadIdx.x >> 3, j = threadIdx.x & 7;
     const bool col = c < R;
@@ -171,8 +189,6 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* 
     }
   }
   __syncthreads();
-  const int w = blockIdx.x * 4 + wv;
-  const int e0 = w * kProjRows, e = e0 + lane;
   const bool in = e < N;  // rows past N (and wavefronts past the last row) act as zeros
   // r -= alpha q on this lane's row, every column's loads in flight (x += alpha p
   // is done by the beta kernel, which reads p anyway)
@@ -211,16 +227,14 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* 
     acc += __shfl_xor(acc, 32, 64);
     if (h == 0 && c < RB) s_rr[wv][c] = acc;
   }
-  // scaled operands of the projection: rows 4 s + kq of the 64
-  double bop[16][MB], vop[16][VR > 0 ? VR : 1];
+  // scaled B operands of the projection: rows 4 s + kq of the 64
+  double bop[16][MB], rsc[16];
 #pragma unroll
   for (int st_ = 0; st_ < 16; ++st_) {
     const int row = 4 * st_ + kq;
-    const double sc = e0 + row < n ? isf : isg;
+    rsc[st_] = e0 + row < n ? isf : isg;
 #pragma unroll
-    for (int cb = 0; cb < MB; ++cb) bop[st_][cb] = sc * (double)sx[row * XP + 16 * cb + r16];
-#pragma unroll
-    for (int v = 0; v < VR; ++v) vop[st_][v] = sc * (double)sx[row * XP + 16 + v];
+    for (int cb = 0; cb < MB; ++cb) bop[st_][cb] = rsc[st_] * (double)sx[row * XP + 16 * cb + r16];
   }
   __syncthreads();  // s_rr complete
   if (threadIdx.x < R)
@@ -237,33 +251,20 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* 
 #pragma unroll
       for (int v = 0; v < VR; ++v) vacc[b][v] = 0.0;
     }
-    const double* ub[4];
-    bool ok[4];
+    if (i0 > 0) load_u(i0);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = i0 + 16 * b + r16;
-      ok[b] = i < k;
-      ub[b] = U + (size_t)(ok[b] ? i : 0) * N;
-    }
+    for (int s16 = 0; s16 < 16; ++s16) {
+      double vop[VR > 0 ? VR : 1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {  // two halves of 8 steps: 32 loads in flight
-      double aop[8][4];
+      for (int v = 0; v < VR; ++v) vop[v] = rsc[s16] * (double)sx[(4 * s16 + kq) * XP + 16 + v];
 #pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8) {
-        const int er = e0 + 4 * (8 * h + s8) + kq;
+      for (int b = 0; b < 4; ++b) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) aop[s8][b] = ld_or0(ub[b], (size_t)er, 0, ok[b] && er < N);
+        for (int cb = 0; cb < MB; ++cb)
+          acc[b][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s16][b], bop[s16][cb], acc[b][cb], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < VR; ++v) vacc[b][v] += aop[s16][b] * vop[v];
       }
-#pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-#pragma unroll
-          for (int cb = 0; cb < MB; ++cb)
-            acc[b][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s8][b], bop[8 * h + s8][cb], acc[b][cb], 0, 0, 0);
-#pragma unroll
-          for (int v = 0; v < VR; ++v) vacc[b][v] += aop[s8][b] * vop[8 * h + s8][v];
-        }
     }
     // this wavefront's 64 x RB block of t: matrix-core part (register r of lane
     // l: i = 16 b + l / 16 + 4 r, c = 16 cb + l % 16), vector part summed over
@@ -300,12 +301,12 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* 
 template <typename T, int RB>
 static dski_status launch_update_rb(int nb, const T* Q, T* Rr, int N, int n, int R,
                                     const PcgScal& s, int par, const double* pq_part, int nb_pq, double* rr_part,
-                                    const double* U, int k, double isf, double isg, double* t_part, double* hist,
+                                    const double* Ur, int k, double isf, double isg, double* t_part, double* hist,
                                     int max_iter, hipStream_t st) {
   constexpr size_t sh = UpdShape<RB>::template bytes<T>();
   static bool done = false;
   DSKI_TRY(lds_limit(&k_pcg_update<T, RB>, sh, done));
-  k_pcg_update<T, RB><<<nb, kBlock, sh, st>>>(Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf, isg,
+  k_pcg_update<T, RB><<<nb, kBlock, sh, st>>>(Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, Ur, k, isf, isg,
                                               t_part, hist, max_iter);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
@@ -315,11 +316,11 @@ static dski_status launch_update_rb(int nb, const T* Q, T* Rr, int N, int n, int
 template <typename T>
 static dski_status launch_update(int nb, const T* Q, T* Rr, int N, int n, int R,
                                  const PcgScal& s, int par, const double* pq_part, int nb_pq, double* rr_part,
-                                 const double* U, int k, double isf, double isg, double* t_part, double* hist,
+                                 const double* Ur, int k, double isf, double isg, double* t_part, double* hist,
                                  int max_iter, hipStream_t st) {
 #define DSKI_UPD(V)                                                                                          \
   case V:                                                                                                    \
-    return launch_update_rb<T, V>(nb, Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, U, k, isf, isg, t_part, \
+    return launch_update_rb<T, V>(nb, Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, Ur, k, isf, isg, t_part, \
                                   hist, max_iter, st);
   switch (pad4(R)) {
     DSKI_UPD(4)
@@ -528,6 +529,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   int* hflags = nullptr;
   DSKI_HIP(hipHostMalloc(&hflags, sizeof(int) * 2, hipHostMallocDefault));
   const double* U = pc ? pc->U : nullptr;
+  const double* Ur = pc ? pc->Ur : nullptr;
   const double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
   dski_status rc = DSKI_OK;
   const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
@@ -535,7 +537,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   // one iteration, all launches on stream `q`
   auto iterate = [&](int par, hipStream_t q) -> dski_status {
     DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, q));
-    DSKI_TRY(launch_update<T>(nbt, Q, Rr, N, n, R, s, par, pq_part, nbg, rr_part, U, pc ? k : 0, isf, isg, t_part,
+    DSKI_TRY(launch_update<T>(nbt, Q, Rr, N, n, R, s, par, pq_part, nbg, rr_part, Ur, pc ? k : 0, isf, isg, t_part,
                               hist, max_iter, q));
     RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
     if (pc && k > 0) {

@@ -214,11 +214,12 @@ __global__ void k_gram_partial(const double* __restrict__ L, int N, int n, int k
   }
 }
 
-// U[:, i] = G V[:, i] / sigma_i  (components with sigma_i = 0 are dropped).
+// U[:, i] = G V[:, i] / sigma_i  (components with sigma_i = 0 are dropped), stored
+// column-major (U) and row-major (Ur).
 // (Vs holds V with column i divided by sigma_i.)  One thread per row, outputs in
 // groups of 16 so that each L entry is read k/16 times.
 __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, double isf, double isg,
-                         const double* __restrict__ sV, double* __restrict__ U) {
+                         const double* __restrict__ sV, double* __restrict__ U, double* __restrict__ Ur) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   double sc = e < n ? isf : isg;
@@ -235,7 +236,10 @@ __global__ void k_make_u(const double* __restrict__ L, int N, int n, int k, doub
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      if (i0 + i < k) U[(size_t)(i0 + i) * N + e] = acc[i] * sc;
+      if (i0 + i < k) {
+        U[(size_t)(i0 + i) * N + e] = acc[i] * sc;
+        Ur[(size_t)e * k + i0 + i] = acc[i] * sc;  // row-major copy for the projections
+      }
   }
 }
 
@@ -288,7 +292,7 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
     return launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, pc->U, 0, nullptr, Z, ldz, rz_partial, st);
   PcWork w;
   DSKI_TRY(pc_work(pc, R, w));
-  DSKI_TRY(launch_proj<T>(Rm, ld, N, p->n, R, isf, isg, pc->U, k, w.partial, st));
+  DSKI_TRY(launch_proj<T>(Rm, ld, N, p->n, R, isf, isg, pc->Ur, k, w.partial, st));
   RedJob j{w.partial, w.nblk, k * R, R, w.t, pc->w, nullptr, 1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j, nullptr, st));
   return launch_final<T>(Rm, ld, N, p->n, R, isf, isg, isf, isg, pc->U, k, w.coef, Z, ldz, rz_partial, st);
@@ -315,7 +319,7 @@ dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int l
     return launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, pc->U, 0, nullptr, Z, ldz, nullptr, st);
   PcWork w;
   DSKI_TRY(pc_work(pc, R, w));
-  DSKI_TRY(launch_proj<T>(W, ld, N, p->n, R, 1.0, 1.0, pc->U, k, w.partial, st));
+  DSKI_TRY(launch_proj<T>(W, ld, N, p->n, R, 1.0, 1.0, pc->Ur, k, w.partial, st));
   RedJob j{w.partial, w.nblk, k * R, R, w.t, pc->rootc, nullptr, -1.0, w.coef, nullptr};
   DSKI_TRY(launch_reduce(j, nullptr, st));
   return launch_final<T>(W, ld, N, p->n, R, 1.0, 1.0, p->sf, p->sg, pc->U, k, w.coef, Z, ldz, nullptr, st);
@@ -330,6 +334,7 @@ static void destroy_pc(dski_precond pc) {
   (void)hipFree(pc->piv_tile);
   (void)hipFree(pc->L);
   (void)hipFree(pc->U);
+  (void)hipFree(pc->Ur);
   (void)hipFree(pc->w);
   (void)hipFree(pc->rootc);
   pc->work.release();
@@ -414,6 +419,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     double isf = 1.0 / p->sf, isg = 1.0 / p->sg;
     double logdetD = (double)n * 2.0 * std::log(p->sf) + (double)(N - n) * 2.0 * std::log(p->sg);
     DSKI_HIP(hipMalloc(&pc->U, sizeof(double) * (size_t)N * std::max(r, 1)));
+    DSKI_HIP(hipMalloc(&pc->Ur, sizeof(double) * (size_t)N * std::max(r, 1)));
     DSKI_HIP(hipMalloc(&pc->w, sizeof(double) * std::max(r, 1)));
     DSKI_HIP(hipMalloc(&pc->rootc, sizeof(double) * std::max(r, 1)));
     if (r == 0) {
@@ -468,8 +474,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
       rc = DSKI_EHIP;
       break;
     }
-    k_make_u<<<(N + kBlock - 1) / kBlock, kBlock, 0, st>>>(pc->L, N, n, r, isf, isg,
-                                                                                dV, pc->U);
+    k_make_u<<<(N + kBlock - 1) / kBlock, kBlock, 0, st>>>(pc->L, N, n, r, isf, isg, dV, pc->U, pc->Ur);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(st);
     (void)hipFree(dV);

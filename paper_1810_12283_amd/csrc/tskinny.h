@@ -4,8 +4,9 @@
 //
 //   projection  t = U^T (pre .* X)   one wavefront per 64 rows on the FP64
 //                                matrix cores (v_mfma_f64_16x16x4f64): U is the
-//                                A operand, read straight from memory (16
-//                                columns x 4 consecutive rows per load), the
+//                                A operand, read straight from its row-major
+//                                copy (4 rows x 16 consecutive columns per
+//                                load), the
 //                                64 x R block of X, staged unscaled in LDS, the
 //                                B operand with the row scale applied in
 //                                registers; one partial per wavefront,
@@ -60,7 +61,7 @@ struct ProjLds {
 // the row scale is pre_v below row n and pre_g from n on.  Writes
 // partial[(i R + c) nw + w] for i < k, c < R.  CB = column blocks of 16.
 template <int CB, typename S>
-__device__ __forceinline__ void wave_project(const double* __restrict__ U, int N, int n, int k, int R, int e0,
+__device__ __forceinline__ void wave_project(const double* __restrict__ Ur, int N, int n, int k, int R, int e0,
                                              const S* __restrict__ sx, double pre_v, double pre_g,
                                              double* __restrict__ partial, int nw, int w) {
   constexpr int XP = ProjLds<CB>::XP;
@@ -80,14 +81,6 @@ __device__ __forceinline__ void wave_project(const double* __restrict__ U, int N
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[b][cb] = dski_pdbl4{0.0, 0.0, 0.0, 0.0};
-    const double* ub[4];
-    bool ok[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = i0 + 16 * b + r16;
-      ok[b] = i < k;
-      ub[b] = U + (size_t)(ok[b] ? i : 0) * N;
-    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {  // two halves of 8 steps: 32 loads in flight
       double aop[8][4];
@@ -95,7 +88,10 @@ __device__ __forceinline__ void wave_project(const double* __restrict__ U, int N
       for (int s = 0; s < 8; ++s) {
         const int e = e0 + 4 * (8 * h + s) + kq;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) aop[s][b] = ld_or0(ub[b], (size_t)e, 0, ok[b] && e < N);
+        for (int b = 0; b < 4; ++b) {  // row-major U: 16 consecutive columns of 4 rows per load
+          const int i = i0 + 16 * b + r16;
+          aop[s][b] = ld_or0(Ur, (size_t)e * k + i, 0, i < k && e < N);
+        }
       }
 #pragma unroll
       for (int s = 0; s < 8; ++s)
@@ -137,7 +133,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 // Standalone projection: partials of t = U^T (pre .* X), one per wavefront.
 template <typename T, int CB>
 static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X, int ld, int N, int n, int R,
-                                                        double pre_v, double pre_g, const double* __restrict__ U,
+                                                        double pre_v, double pre_g, const double* __restrict__ Ur,
                                                         int k, double* __restrict__ partial) {
   extern __shared__ __align__(16) char smem[];
   constexpr int XP = ProjLds<CB>::XP;
@@ -149,23 +145,23 @@ static __global__ __launch_bounds__(256) void k_ts_proj(const T* __restrict__ X,
 #pragma unroll
   for (int c = 0; c < 16 * CB; ++c) sx[lane * XP + c] = ld_or0(X, (size_t)c * ld + e, 0, c < R && e < N);
   wave_lds_fence();
-  wave_project<CB>(U, N, n, k, R, e0, sx, pre_v, pre_g, partial, nw, w);
+  wave_project<CB>(Ur, N, n, k, R, e0, sx, pre_v, pre_g, partial, nw, w);
 }
 
 template <typename T>
 static inline dski_status launch_proj(const T* X, int ld, int N, int n, int R, double pre_v, double pre_g,
-                                      const double* U, int k, double* partial, hipStream_t st) {
+                                      const double* Ur, int k, double* partial, hipStream_t st) {
   const int nb = (proj_waves(N) + 3) / 4;
   if (R <= 16) {
     constexpr size_t sh = ProjLds<1>::bytes<T>();
     static bool done = false;
     DSKI_TRY(lds_limit(&k_ts_proj<T, 1>, sh, done));
-    k_ts_proj<T, 1><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, partial);
+    k_ts_proj<T, 1><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, Ur, k, partial);
   } else {
     constexpr size_t sh = ProjLds<2>::bytes<T>();
     static bool done = false;
     DSKI_TRY(lds_limit(&k_ts_proj<T, 2>, sh, done));
-    k_ts_proj<T, 2><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, U, k, partial);
+    k_ts_proj<T, 2><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, Ur, k, partial);
   }
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
