@@ -162,16 +162,16 @@ dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int
 /* Times the interchangeable kernel variants for R right-hand sides on this
  * plan's shape (scatter: LDS node tiles with the base number of columns per
  * work-group / direct one column per thread / direct two columns per thread /
- * LDS node tiles with 1.5 and with 2 times the base columns; gather: 2 / 1 / 4
+ * LDS node tiles with 1.5, 2 and 5 times the base columns; gather: 2 / 1 / 4
  * columns per thread; K_UU factor of each axis: circulant FFT / dense Toeplitz
  * product on the FP64 matrix cores) and keeps the fastest of each.  Scatter
  * variants give bitwise-identical results, and so do gather variants; the
- * K_UU variants agree up to rounding.  times_host (14 entries, may be NULL)
- * receives the measured microseconds: scatter (5), gather (3), then FFT and
+ * K_UU variants agree up to rounding.  times_host (15 entries, may be NULL)
+ * receives the measured microseconds: scatter (6), gather (3), then FFT and
  * dense for axes 0, 1, 2 (all 0 for a D-SKIP plan).  1 <= R <= 32. */
 dski_status dski_autotune(dski_plan plan, int R, double* times_host, dski_stream stream);
 
-/* Select the scatter (0..4) and gather (0..2) variants directly. */
+/* Select the scatter (0..5) and gather (0..2) variants directly. */
 dski_status dski_set_variants(dski_plan plan, int scatter_variant, int gather_variant);
 
 /* K_UU factor of one axis: 0 circulant FFT, 1 dense Toeplitz product on the

@@ -1,5 +1,5 @@
-// Per-shape autotuning of kernel variants.  The scatter (W^T) has three
-// LDS-tiled forms (base, 1.5 and 2 times the base number of columns per
+// Per-shape autotuning of kernel variants.  The scatter (W^T) has four
+// LDS-tiled forms (base, 1.5, 2 and 5 times the base number of columns per
 // work-group) and two cache-direct forms, all with identical results; the
 // gather (W) takes 2, 1 or 4 columns per thread (identical results); each K_UU factor has a
 // circulant-FFT and a dense matrix-core form (equal up to rounding).  Which is
@@ -12,7 +12,7 @@
 
 namespace dski {
 
-constexpr int kScatterVariants = 5;
+constexpr int kScatterVariants = 6;
 constexpr int kGatherVariants = 3;
 constexpr int kTuneTimes = kScatterVariants + kGatherVariants + 2 * DSKI_MAXD;
 

@@ -382,12 +382,12 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
 }
 
 // Columns per work-group of the LDS-tiled scatter: a base chunk (4 FP32 or 2
-// FP64 columns in 1-D and 2-D, half that in 3-D) times 1, 1.5 or 2; wider
+// FP64 columns in 1-D and 2-D, half that in 3-D) times 1, 1.5, 2 or 5; wider
 // chunks mean fewer work-groups, each staging its region once for more columns.
 template <int D, typename T, int WIDTH>
 constexpr int scatter_cr() {
   constexpr int base = (sizeof(T) == 4 && D <= 2) ? 4 : (D <= 2 ? 2 : (sizeof(T) == 4 ? 2 : 1));
-  constexpr int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : 2 * base);
+  constexpr int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : (WIDTH == 2 ? 2 * base : 5 * base));
   return D == 3 && cr > 3 ? 3 : cr;  // 3-D: the region tables leave room for 3 columns
 }
 
@@ -497,6 +497,7 @@ static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, double* G,
     case 2: launch_scatter_direct<D, 2, T>(p, R, V, ldv, G, st); break;
     case 3: launch_scatter<D, T, 1>(p, R, V, ldv, G, st); break;
     case 4: launch_scatter<D, T, 2>(p, R, V, ldv, G, st); break;
+    case 5: launch_scatter<D, T, 3>(p, R, V, ldv, G, st); break;
     default: launch_scatter<D, T, 0>(p, R, V, ldv, G, st); break;
   }
 }

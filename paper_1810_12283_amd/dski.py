@@ -248,10 +248,10 @@ class Plan:
 
     def autotune(self, R: int, stream=None) -> dict:
         """Time the kernel variants for this shape and keep the fastest."""
-        t = (C.c_double * 14)()
+        t = (C.c_double * 15)()
         _check(lib().dski_autotune(self._h, int(R), t, _stream(stream)), "dski_autotune")
-        return {"scatter_us": [t[0], t[1], t[2], t[3], t[4]], "gather_us": [t[5], t[6], t[7]],
-                "kuu_us": [[t[8 + 2 * a], t[9 + 2 * a]] for a in range(min(self.d, 3))]}
+        return {"scatter_us": [t[i] for i in range(6)], "gather_us": [t[6], t[7], t[8]],
+                "kuu_us": [[t[9 + 2 * a], t[10 + 2 * a]] for a in range(min(self.d, 3))]}
 
     def set_variants(self, scatter: int, gather: int = 0):
         _check(lib().dski_set_variants(self._h, int(scatter), int(gather)), "dski_set_variants")

@@ -134,7 +134,7 @@ def test_kernel_variants_agree(name):
     plan, op = make(W)
     V = to_gpu(np.random.default_rng(4).standard_normal((op.N, 17)))
     outs = []
-    for v in range(5):
+    for v in range(6):
         plan.set_variants(v, 0)
         outs.append(plan.mvm(V))
     for gv in range(3):

@@ -71,7 +71,7 @@ def test_pivchol_exact_low_rank_and_truncation():
 
 
 @pytest.mark.parametrize("name,bits,variant", [("small2d", 32, 1), ("terrain_small", 32, 4), ("small2d", 64, 3),
-                                              ("terrain_small", 32, 0),
+                                              ("terrain_small", 32, 0), ("small2d", 32, 5),
                                               ("terrain_small", 32, 2), ("small2d", 64, 4)])
 def test_pcg_true_residual(name, bits, variant):
     W = {"small2d": workloads.small2d(), "terrain_small": workloads.terrain(n=3000, grid=60)}[name]
