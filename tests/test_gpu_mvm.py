@@ -199,3 +199,37 @@ def test_mvm_long_axes_match_oracle(m):
     assert rel_cols(Yd, op.matvec_dtheta(0, V)).max() < 1e-12
     Vf = V.astype(np.float32).astype(np.float64)
     assert rel_cols(from_gpu(plan.mvm(to_gpu(Vf))), op.matvec(Vf)).max() < TOL_MVM
+
+
+def test_mvm_clustered_points_mix_both_scatter_paths():
+    """A quarter of the points packed into a small disc: tiles there hold more
+    than 256 region points (read through the cache), the others are staged in
+    LDS; FP64 MVM to 1e-12 against the oracle and the same bits from every
+    scatter and gather variant."""
+    dski = need_gpu()
+    from oracle import dski as odski
+    say("clustered points")
+    r = np.random.default_rng(31)
+    Xu = r.random((3000, 2))
+    ang, rad = r.uniform(0, 2 * np.pi, 1000), 0.04 * np.sqrt(r.random(1000))
+    Xc = np.stack([0.5 + rad * np.cos(ang), 0.5 + rad * np.sin(ang)], axis=1)
+    X = np.concatenate([Xu, Xc])
+    m = [80, 80]
+    ell = np.log([0.05, 0.05])
+    plan = dski.Plan(torch.tensor(X, device="cuda"), m, [0, 0], [1, 1])
+    plan.set_hypers(ell, 0.1, np.log(0.05), np.log(0.1))
+    op = odski.DSKI(X, m, [0, 0], [1, 1], ell, 0.1, np.log(0.05), np.log(0.1))
+    V = np.random.default_rng(32).standard_normal((op.N, 6))
+    Vd = torch.tensor(V.T.copy(), device="cuda")
+    outs = []
+    for sv in range(6):
+        plan.set_variants(sv, 0)
+        outs.append(plan.mvm(Vd))
+    for gv in range(3):
+        plan.set_variants(0, gv)
+        outs.append(plan.mvm(Vd))
+    err = rel_cols(outs[0].cpu().numpy().T, op.matvec(V)).max()
+    say("  fp64 max rel err", err)
+    assert err < 1e-12
+    for o in outs[1:]:
+        assert torch.equal(outs[0], o)
