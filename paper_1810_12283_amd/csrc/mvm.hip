@@ -222,7 +222,10 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
                                                      double* __restrict__ G, long long M) {
   static_assert(PMAX == 256, "one thread stages one region point");
   using TS = TileShape<D>;
-  __shared__ double s_w[D * 8][PMAX];
+  // weights point-major, 8 D + 1 doubles per point: lanes reading one point at
+  // different stencil offsets hit adjacent banks, different points rarely share one
+  constexpr int WS = 8 * D + 1;
+  __shared__ double s_w[PMAX * WS];
   __shared__ T s_v[PMAX * CR * (D + 1)];
   __shared__ int s_lcs[TS::max_cells + 1];
   __shared__ int s_cl[PMAX];  // last-axis cell (1-based) of every region point
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
           x[r * (D + 1) + b] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
                                       (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
 #pragma unroll
-      for (int a8 = 0; a8 < D * 8; ++a8) s_w[a8][q] = w[a8];
+      for (int a8 = 0; a8 < D * 8; ++a8) s_w[q * WS + a8] = w[a8];
 #pragma unroll
       for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
       s_cl[q] = cq;
@@ -330,8 +333,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         const int o = j[a] - (a == last ? cl : c[a]) + 1;
-        wv[a] = s_w[a * 8 + o][q];
-        wd[a] = s_w[a * 8 + 4 + o][q];
+        wv[a] = s_w[q * WS + a * 8 + o];
+        wd[a] = s_w[q * WS + a * 8 + 4 + o];
       }
       scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)q * CR * (D + 1));
       ++q;
