@@ -46,9 +46,10 @@ def source_digest(path=MVM_SOURCE):
 
 
 def measured_traffic():
-    """HBM bytes per launch of each MVM stage from the committed PMC summary
-    (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size), or None
-    when the summary is missing or was taken on a different mvm.hip."""
+    """HBM bytes per launch of each MVM kernel variant (scatter_v0.., gather_v0..,
+    kuu_fft, kuu_dense: one launch, one axis for K_UU) from the committed PMC
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size), or
+    None when the summary is missing or was taken on a different mvm.hip."""
     try:
         with open(PMC_SUMMARY) as f:
             for line in f:
@@ -155,16 +156,24 @@ def main(argv=None):
     if a.pmc_mvm:
         plan = dski.Plan(X, W.grid_m, W.lo, W.hi)
         plan.set_hypers(*W.hypers())
-        plan.autotune(R)
+        tuned_first = plan.autotune(R)
         Vt = plan.permute(Vblk, +1)
         Yt = torch.empty_like(Vt)
         for _ in range(5):
             plan.mvm_stage(0, Vt)
             plan.mvm_stage(1, Vt)
             plan.mvm_stage(2, Vt, Yt)
-        tuned = plan.autotune(R)
-        chosen = [0 if kk[0] <= kk[1] else 1 for kk in tuned["kuu_us"]]
-        for v in (1 - chosen[0], chosen[0]):  # the other K_UU variant too, then the tuned one
+        # every scatter, gather and K_UU variant a few times (the tuner's pick is not
+        # stable while counters are collected; the summary keys traffic by variant)
+        for sv in range(len(tuned_first["scatter_us"])):
+            plan.set_variants(sv, 0)
+            for _ in range(3):
+                plan.mvm_stage(0, Vt)
+        for gv in range(len(tuned_first["gather_us"])):
+            plan.set_variants(0, gv)
+            for _ in range(3):
+                plan.mvm_stage(2, Vt, Yt)
+        for v in (1, 0):
             for ax in range(d):
                 plan.set_kuu_variant(ax, v)
             for _ in range(3):
@@ -243,6 +252,14 @@ def main(argv=None):
     stage_ms = {k: float(np.mean([r["ms_stage"][k] for r in recs])) for k in sb}
     dom = max(stage_ms, key=stage_ms.get)
     ach = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    # measured HBM bytes of the dominant stage for the variant the tuner picked
+    tune = recs[-1]["tune"]
+    pick = {"scatter": f"scatter_v{int(np.argmin(tune['scatter_us']))}",
+            "gather": f"gather_v{int(np.argmin(tune['gather_us']))}",
+            "kuu": "kuu_" + ("fft" if all(t[0] <= t[1] for t in tune["kuu_us"]) else "dense")}[dom]
+    traffic = (measured_traffic() or {}).get(pick)
+    if traffic is not None and dom == "kuu":
+        traffic *= d  # one launch per axis
     line = {
         "metric": "D-SKI grad-kernel MVM GB/s; block-PCG s to 1e-4 resid (n=20k,d=2,17 RHS)",
         "value": round(gbs, 2),
@@ -275,7 +292,7 @@ def main(argv=None):
         "logdet": recs[-1]["logdet"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": (measured_traffic() or {}).get(dom)},
+                     "traffic": traffic},
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, R)
