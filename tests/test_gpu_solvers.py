@@ -273,3 +273,41 @@ def test_pcg_graph_replay_equals_eager(name):
     assert out[True][1] == out[False][1] and out[True][3] == out[False][3]
     np.testing.assert_array_equal(out[True][2], out[False][2])
     np.testing.assert_array_equal(out[True][0], out[False][0])
+
+
+@pytest.mark.parametrize("k", [1, 17, 65, 100])
+def test_precond_apply_column_widths_and_ranks(k):
+    """The tall-skinny products at ranks around the 16- and 64-column blocks of
+    the matrix-core kernels and at every padded width (R = 1 .. 40, the last in
+    groups of 32): FP32 storage to 1e-4, FP64 storage to 1e-8 against the oracle's
+    M^{-1} on the same factor."""
+    W = workloads.terrain(n=3000, grid=60)
+    say("precond widths, rank", k)
+    plan, op, pc, L, gaps = _pivchol_pair(W, k)
+    P = precond.Precond(L, op.Dn)
+    rng = np.random.default_rng(41 + k)
+    for R in (1, 5, 16, 17, 20, 21, 30, 40):
+        B = rng.standard_normal((op.N, R)).astype(np.float32).astype(np.float64)
+        ref = P.solve(B)
+        e32 = rel_cols(from_gpu(pc.apply(to_gpu(B))), ref).max()
+        Z64 = pc.apply(torch.tensor(B.T.copy(), device="cuda")).cpu().numpy().T
+        e64 = rel_cols(Z64, ref).max()
+        say("  R", R, "fp32", e32, "fp64", e64)
+        assert e32 < 1e-4 and e64 < 1e-8
+
+
+@pytest.mark.parametrize("R,k", [(6, 70), (13, 33), (24, 70)])
+def test_pcg_true_residual_column_widths(R, k):
+    """The fused PCG iteration at padded widths 8, 16 and 24 (one or two
+    matrix-core column blocks) and ranks off the 16-column blocks."""
+    W = workloads.terrain(n=3000, grid=60)
+    say("pcg widths", R, k)
+    plan, op = make(W)
+    pc = plan.pivchol(k)
+    B = np.concatenate([W.y[:, None], orng.rademacher(SEED, 0, R - 1, op.N)], axis=1)
+    B = B.astype(np.float32).astype(np.float64)
+    X, iters, relres, st, _ = plan.pcg(to_gpu(B), pc, tol=1e-4, max_iter=20000)
+    assert st == 0
+    tr = krylov.true_relres(op.matvec, B, from_gpu(X))
+    say("  iters", max(iters), "true relres", tr.max())
+    assert tr.max() <= 1e-4
