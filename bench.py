@@ -8,17 +8,21 @@ hyper-parameters; 17 right-hand sides = the data vector + 16 preconditioned
 Rademacher probes; pivoted-Cholesky rank 50; PCG tolerance 1e-4).
 
 One step = one pass of the whole hot path on resident inputs:
-  plan set-up (cells, tile order) and spectra for the hyper-parameters,
-  10 block MVMs with the 17 columns,
+  plan set-up (cells, tile order, region tables) and spectra, the tuner,
+  23 block MVMs with the 17 columns (3 untimed, 20 timed one by one) and the
+  per-stage timings,
   pivoted Cholesky (rank 50) and the preconditioner,
   block PCG of the 17 columns to 1e-4,
   mll and its gradient (its own block PCG, SLQ log det, adjoint products).
 
 Printed: one JSON line.  `value` is the D-SKI MVM throughput in GB/s of
 algorithmic bytes B = 4 (3 N R + 4 m R + 2 n (d + 1)) per product over the
-measured product time; `pcg_s` the block-PCG seconds to 1e-4.  `roofline`
-is that of the dominant MVM stage, timed live with events on the stream the
-kernels run on; `cpu_baseline` the FP64 CPU oracle on a bounded sample.
+median product time (`mvm_ms_p10_p90` the spread); `copy_gbs_same_size` the
+rate of a device copy of B bytes; `pcg_s` the block-PCG seconds to 1e-4.
+`roofline` is that of the dominant MVM stage, timed live with events on the
+stream the kernels run on, with the measured traffic of the tuned variant;
+`dskip` a D-SKIP block MVM (8-D ridge workload); `cpu_baseline` the FP64 CPU
+oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -75,6 +79,49 @@ def _events_ms(fn, reps, stream):
     return start.elapsed_time(end) / reps
 
 
+def _events_stats(fn, reps, stream, warm=3):
+    """Median, 10th and 90th percentile (ms) of `reps` launches of fn, each
+    bracketed by its own pair of events on `stream`, after `warm` untimed ones."""
+    import numpy as np
+    import torch
+    for _ in range(warm):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    ev[-1][1].synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return float(np.median(t)), float(np.percentile(t, 10)), float(np.percentile(t, 90))
+
+
+def dskip_block(R, stream, reps=20):
+    """D-SKIP block MVM on the 8-D ridge workload (n = 4,000, 1-D grids of 100,
+    Lanczos rank 32): build seconds, MVM time and the root products' flop rate
+    (4 N r^2 R flops per block MVM with r padded to 32)."""
+    import torch
+    import workloads
+    from paper_1810_12283_amd import dski
+    W = workloads.ridge8d()
+    X = torch.tensor(W.X, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = dski.DskipPlan(X, W.skip_m, W.skip_rank, 7, W.log_ell, W.lo, W.hi)
+    plan.set_hypers(W.log_ell, W.log_s, W.log_sigma_f, W.log_sigma_g)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    V = dski.rademacher(99, 0, R, W.N, device="cuda")
+    Y = torch.empty_like(V)
+    med, p10, p90 = _events_stats(lambda: plan.mvm_tiled(V, out=Y), reps, stream)
+    flops = 4.0 * W.N * 32 * 32 * R
+    plan.close()
+    return {"workload": f"ridge n={W.n} d={W.d} m_1d={W.skip_m} rank={W.skip_rank} R={R}",
+            "build_s": round(build_s, 4), "mvm_ms": round(med, 4), "mvm_ms_p10_p90": [round(p10, 4), round(p90, 4)],
+            "gflops": round(flops / (med * 1e-3) / 1e9, 1),
+            "frac_fp64_vector_peak": round(flops / (med * 1e-3) / 78.6e12, 4)}
+
+
 def mvm_bytes(N, M, n, d, R):
     """Algorithmic bytes of one block MVM (FP32 vectors and grid):
     V read by the scatter and again for the noise term, Y written (3 N R);
@@ -120,7 +167,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mvm-reps", type=int, default=10)
+    ap.add_argument("--mvm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--grid", type=int, default=200)
@@ -199,7 +246,7 @@ def main(argv=None):
         tune = plan.autotune(R)
         Vt = plan.permute(Vblk, +1)
         Yt = torch.empty_like(Vt)
-        ms_mvm = _events_ms(lambda: plan.mvm_tiled(Vt, out=Yt), a.mvm_reps, stream)
+        ms_mvm, ms_p10, ms_p90 = _events_stats(lambda: plan.mvm_tiled(Vt, out=Yt), a.mvm_reps, stream)
         # per stage (each stage's kernels alone between events)
         ms_stage = {"scatter": _events_ms(lambda: plan.mvm_stage(0, Vt), a.mvm_reps, stream)}
         ms_stage["kuu"] = _events_ms(lambda: plan.mvm_stage(1, Vt), a.mvm_reps, stream)
@@ -227,7 +274,8 @@ def main(argv=None):
             Bd = B.double()
             Rt = Bd - plan.mvm(Xs)
             true_rel = (Rt.norm(dim=1) / Bd.norm(dim=1)).max().item()
-            out = dict(tune=tune, ms_mvm=ms_mvm, ms_stage=ms_stage, setup_s=t1 - t0, pivchol_s=t2 - t1,
+            out = dict(tune=tune, ms_mvm=ms_mvm, ms_p10=ms_p10, ms_p90=ms_p90, ms_stage=ms_stage,
+                       setup_s=t1 - t0, pivchol_s=t2 - t1,
                        pcg_s=t3 - t2, mll_s=t4 - t3, iters=iters, relres=max(relres), status=st,
                        true_rel=true_rel, mll=res["mll"], logdet=res["logdet"],
                        mll_iters=max(res["iters"]), grad=res["grad"].tolist())
@@ -247,6 +295,13 @@ def main(argv=None):
 
     ms_mvm = float(np.mean([r["ms_mvm"] for r in recs]))
     Bm = mvm_bytes(N, M, n, d, R)
+    # a device copy of the same number of bytes as one MVM moves (half read, half
+    # written): the rate that memory traffic of this size reaches on this GPU
+    src = torch.ones(Bm // 8, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms_copy = _events_stats(lambda: dst.copy_(src), a.mvm_reps, stream)[0]
+    copy_gbs = round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)
+    del src, dst
     gbs = Bm / (ms_mvm * 1e-3) / 1e9
     sb = stage_bytes(N, M, n, d, R)
     stage_ms = {k: float(np.mean([r["ms_stage"][k] for r in recs])) for k in sb}
@@ -279,6 +334,9 @@ def main(argv=None):
                    "n": n, "d": d, "N": N, "grid": list(W.grid_m), "rhs": R, "rank": W.rank,
                    "tol": W.tol},
         "mvm_ms": round(ms_mvm, 4),
+        "mvm_ms_p10_p90": [round(float(np.mean([r["ms_p10"] for r in recs])), 4),
+                           round(float(np.mean([r["ms_p90"] for r in recs])), 4)],
+        "copy_gbs_same_size": copy_gbs,
         "mvm_algorithmic_bytes": Bm,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pcg_s": round(float(np.mean([r["pcg_s"] for r in recs])), 4),
@@ -294,6 +352,7 @@ def main(argv=None):
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
     }
+    line["dskip"] = dskip_block(R, stream)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, R)
     print(json.dumps(line), flush=True)
