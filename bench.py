@@ -171,6 +171,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--grid", type=int, default=200)
+    ap.add_argument("--sweep", action="store_true",
+                    help="MVM throughput at n = 20k, 200k, 500k (grids 200^2, 632^2, 1000^2; working set above "
+                         "the Infinity Cache at the largest) instead of the full step; one JSON line per size")
     ap.add_argument("--pmc-mvm", action="store_true",
                     help="run only the MVM stages (and a 256 MiB device copy for calibration) for rocprofv3 --pmc")
     a = ap.parse_args(argv)
@@ -199,6 +202,48 @@ def main(argv=None):
     M = int(np.prod(W.grid_m))
     Vblk = dski.rademacher(12345, 0, R, N, device=dev)
     Vblk[0] = y[0]
+
+    if a.sweep:
+        for n_s, g_s in ((20000, 200), (200000, 632), (500000, 1000)):
+            Ws = workloads.terrain(n=n_s, grid=g_s)
+            Xs = torch.tensor(Ws.X, dtype=torch.float64, device=dev)
+            t0 = time.perf_counter()
+            plan = dski.Plan(Xs, Ws.grid_m, Ws.lo, Ws.hi)
+            plan.set_hypers(*Ws.hypers())
+            tune = plan.autotune(R)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            V = dski.rademacher(12345, 0, R, Ws.N, device=dev)
+            Vt = plan.permute(V, +1)
+            Yt = torch.empty_like(Vt)
+            med, p10, p90 = _events_stats(lambda: plan.mvm_tiled(Vt, out=Yt), a.mvm_reps, stream)
+            Ms = int(np.prod(Ws.grid_m))
+            Bs = mvm_bytes(Ws.N, Ms, Ws.n, Ws.d, R)
+            src = torch.ones(Bs // 8, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            ms_copy = _events_stats(lambda: dst.copy_(src), a.mvm_reps, stream)[0]
+            del src, dst
+            stage = {"scatter": _events_stats(lambda: plan.mvm_stage(0, Vt), a.mvm_reps, stream)[0],
+                     "kuu": _events_stats(lambda: plan.mvm_stage(1, Vt), a.mvm_reps, stream)[0]}
+            plan.mvm_stage(0, Vt)
+            stage["gather"] = _events_stats(lambda: plan.mvm_stage(2, Vt, Yt), a.mvm_reps, stream)[0]
+            gbs = Bs / (med * 1e-3) / 1e9
+            print(json.dumps({"sweep": f"terrain n={n_s} grid={g_s}x{g_s} R={R}", "N": Ws.N, "grid_nodes": Ms,
+                              "algorithmic_bytes": Bs, "mvm_ms": round(med, 4),
+                              "mvm_ms_p10_p90": [round(p10, 4), round(p90, 4)], "gbs": round(gbs, 1),
+                              "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4),
+                              "copy_gbs_same_size": round(2 * (Bs // 8) * 4 / (ms_copy * 1e-3) / 1e9, 1),
+                              "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+                              "setup_and_tune_s": round(t_setup, 3),
+                              "tuned": {"scatter": int(np.argmin(tune["scatter_us"])),
+                                        "gather": int(np.argmin(tune["gather_us"])),
+                                        "kuu": ["fft" if t[1] < 0 or t[0] <= t[1] else "dense"
+                                                for t in tune["kuu_us"]]}}),
+                  flush=True)
+            plan.close()
+            del Xs, V, Vt, Yt
+            torch.cuda.empty_cache()
+        return 0
 
     if a.pmc_mvm:
         plan = dski.Plan(X, W.grid_m, W.lo, W.hi)
@@ -311,7 +356,7 @@ def main(argv=None):
     tune = recs[-1]["tune"]
     pick = {"scatter": f"scatter_v{int(np.argmin(tune['scatter_us']))}",
             "gather": f"gather_v{int(np.argmin(tune['gather_us']))}",
-            "kuu": "kuu_" + ("fft" if all(t[0] <= t[1] for t in tune["kuu_us"]) else "dense")}[dom]
+            "kuu": "kuu_" + ("fft" if all(t[1] < 0 or t[0] <= t[1] for t in tune["kuu_us"]) else "dense")}[dom]
     traffic = (measured_traffic() or {}).get(pick)
     if traffic is not None and dom == "kuu":
         traffic *= d  # one launch per axis

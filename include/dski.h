@@ -168,7 +168,8 @@ dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int
  * variants give bitwise-identical results, and so do gather variants; the
  * K_UU variants agree up to rounding.  times_host (15 entries, may be NULL)
  * receives the measured microseconds: scatter (6), gather (3), then FFT and
- * dense for axes 0, 1, 2 (all 0 for a D-SKIP plan).  1 <= R <= 32. */
+ * dense for axes 0, 1, 2 (all 0 for a D-SKIP plan; dense is -1 on an axis
+ * longer than 448 nodes, which has no dense form).  1 <= R <= 32. */
 dski_status dski_autotune(dski_plan plan, int R, double* times_host, dski_stream stream);
 
 /* Select the scatter (0..5) and gather (0..2) variants directly. */

@@ -82,6 +82,7 @@ __host__ __device__ constexpr int fft_tw_offset(int lg, int s, int dir) {
 }
 __host__ __device__ constexpr int fft_tw_size(int lg) { return fft_tw_offset(lg, fft_npass(lg), -1); }
 constexpr int kFftMaxLog2 = 11;  // L <= 2048, m <= 1024 per axis
+constexpr int kDenseMaxM = 448;  // largest axis for the dense matrix-core Toeplitz product
 
 // Per-axis geometry of the grid and its circulant embedding.
 struct Axis {

@@ -879,7 +879,6 @@ static dski_status launch_toeplitz(double* G, long long nlines, int m, long long
 // Exact up to rounding; O(m^2) per line against O(L log L) for the FFT, which
 // the per-axis tuner weighs.  m <= kDenseMaxM.
 typedef double dski_dbl4 __attribute__((ext_vector_type(4)));
-constexpr int kDenseMaxM = 448;
 
 template <int NT>  // row tiles per wavefront: 4 NT >= ceil(m / 16)
 __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, long long nlines, int m,
