@@ -643,26 +643,38 @@ __device__ __forceinline__ long long xcd_block(unsigned bid, unsigned nb) {
   return (long long)(bid & 7u) * (full >> 3) + (bid >> 3);
 }
 
-// Shape of the line-pair FFT for L = 2^LG: TPL lanes hold one pair of real grid
-// lines as one complex sequence (E values per lane), PW pairs per wavefront,
-// four wavefronts per work-group.
+// Shape of the line-pair FFT for L = 2^LG: TPL = L / 8 lanes hold one pair of
+// real grid lines as one complex sequence, eight values per lane (one radix-8
+// butterfly per pass); 256 / TPL pairs per work-group.  Up to L = 512 a pair
+// lives in one wavefront (exchanges need only wavefront ordering); beyond it a
+// pair spans 2 or 4 wavefronts and exchanges synchronise the work-group, which
+// keeps four work-groups (16 wavefronts) per CU at L = 2048 instead of one.
 template <int LG>
 struct FftShape {
   static constexpr int L = 1 << LG;
-  static constexpr int TPL = L / 8 < 64 ? L / 8 : 64;
-  static constexpr int PW = 64 / TPL;
-  static constexpr int E = L / TPL;
+  static constexpr int TPL = L / 8;
+  static constexpr bool WIDE = TPL > 64;                   // a pair spans several wavefronts
+  static constexpr int E = 8;
   static constexpr int NP = fft_npass(LG);
-  static constexpr int PAIRS = 4 * PW;
+  static constexpr int PAIRS = 256 / TPL;
   static constexpr int NL = 2 * PAIRS;                      // lines per work-group
-  static constexpr int LGNL = LG <= 9 ? 12 - LG : 3;        // log2(NL)
+  static constexpr int LGNL = 12 - LG;                      // log2(NL)
   static constexpr int LP = L + L / 8 + 1;                  // odd: pair buffers start on different banks
-  static constexpr bool STAGE = L <= 1024;                  // twiddles and spectrum in LDS
+  static constexpr bool STAGE = L <= 512;                   // twiddles and spectrum in LDS
   static constexpr int TW = fft_tw_size(LG);
   static constexpr size_t lds_bytes() {
     return sizeof(double2) * (size_t)PAIRS * LP + (STAGE ? sizeof(double2) * TW + sizeof(double) * L : 0);
   }
 };
+
+// Orders the LDS accesses of the lanes that share a line pair.
+template <int LG>
+__device__ __forceinline__ void pair_sync() {
+  if constexpr (FftShape<LG>::WIDE)
+    __syncthreads();
+  else
+    wave_lds_sync();
+}
 
 // Radix-RAD butterflies of one pass (stride NS, direction DIR) on the values a
 // lane holds: v[b RAD + r] is input r of butterfly jj = lane + b TPL, i.e. the
@@ -706,12 +718,12 @@ __device__ __forceinline__ void fft_exchange(double2* v, double2* __restrict__ b
 #pragma unroll
     for (int r = 0; r < RA; ++r) buf[padi(o + r * NSA)] = v[b * RA + r];
   }
-  wave_lds_sync();
+  pair_sync<LG>();
 #pragma unroll
   for (int b = 0; b < NBB; ++b)
 #pragma unroll
     for (int r = 0; r < RB; ++r) v[b * RB + r] = buf[padi(lp + b * S::TPL + r * (S::L / RB))];
-  wave_lds_sync();
+  pair_sync<LG>();
 }
 
 // Passes S0.. of one direction; v enters holding the inputs of pass S0.
@@ -731,8 +743,7 @@ __device__ __forceinline__ void fft_run(double2* v, double2* __restrict__ buf, c
 // (m values at stride `inner`) is zero-padded to L, transformed, multiplied by
 // the circulant eigenvalues `spec` (scaled by 1/L) and transformed back; two
 // lines share one complex FFT (real and imaginary parts), which is exact because
-// the spectrum is real and even.  One pair per TPL lanes, all exchanges inside
-// the wavefront.  The last forward pass leaves element jj + r L / RAD in the
+// the spectrum is real and even.  One pair per TPL lanes (see FftShape).  The last forward pass leaves element jj + r L / RAD in the
 // lane that the first inverse pass (same radix, NS = 1) needs it in, so the
 // spectrum is applied in registers between the two; the first forward pass and
 // the last inverse pass touch the elements lane + r L / 8, which contiguous
@@ -748,9 +759,8 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   constexpr int RL = fft_radix_dir(LG, S::NP - 1, +1);         // radix of the last forward pass
   extern __shared__ double2 smem[];
   __shared__ long long s_base[S::NL];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lp = lane % TPL;
-  const int pair = wave * S::PW + lane / TPL;
+  const int lp = threadIdx.x % TPL;
+  const int pair = threadIdx.x / TPL;
   const long long line0 = xcd_block(blockIdx.x, gridDim.x) * S::NL;
   double2* buf = smem + (size_t)pair * S::LP;
   const double2* stw = tw;
@@ -810,7 +820,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
       const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
       v[e] = pos < m ? buf[padi(pos)] : make_double2(0.0, 0.0);
     }
-    wave_lds_sync();
+    pair_sync<LG>();
   }
   fft_run<LG, +1, 0>(v, buf, stw, lp);
 #pragma unroll
