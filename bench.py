@@ -49,6 +49,14 @@ def source_digest(path=MVM_SOURCE):
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
+def tuned_variants(tune):
+    """The variants the tuner keeps: the first fastest scatter and gather form, and
+    per axis the FFT unless the dense form (timed, not -1) is strictly faster."""
+    import numpy as np
+    return {"scatter": int(np.argmin(tune["scatter_us"])), "gather": int(np.argmin(tune["gather_us"])),
+            "kuu": [0 if (t[1] < 0 or t[0] <= t[1]) else 1 for t in tune["kuu_us"]]}
+
+
 def measured_traffic():
     """HBM bytes per launch of each MVM kernel variant (scatter_v0.., gather_v0..,
     kuu_fft, kuu_dense: one launch, one axis for K_UU) from the committed PMC
@@ -174,6 +182,9 @@ def main(argv=None):
     ap.add_argument("--sweep", action="store_true",
                     help="MVM throughput at n = 20k, 200k, 500k (grids 200^2, 632^2, 1000^2; working set above "
                          "the Infinity Cache at the largest) instead of the full step; one JSON line per size")
+    ap.add_argument("--variants", default=None,
+                    help="S,G,K0,K1: pin the scatter, gather and per-axis K_UU variants after the tuner has run "
+                         "(for profiled runs, whose per-dispatch overhead distorts the tuner's timings)")
     ap.add_argument("--pmc-mvm", action="store_true",
                     help="run only the MVM stages (and a 256 MiB device copy for calibration) for rocprofv3 --pmc")
     a = ap.parse_args(argv)
@@ -194,6 +205,13 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     W = workloads.terrain(n=a.n, grid=a.grid)
+    pinned = None
+    if a.variants:
+        pinned = [int(v) for v in a.variants.split(",")]
+        if len(pinned) != 2 + len(W.grid_m):
+            print(f"--variants needs {2 + len(W.grid_m)} integers (scatter, gather, one K_UU form per axis)",
+                  file=sys.stderr)
+            return 2
     t_probes = W.num_probes
     R = 1 + t_probes
     X = torch.tensor(W.X, dtype=torch.float64, device=dev)
@@ -289,6 +307,12 @@ def main(argv=None):
         plan = dski.Plan(X, W.grid_m, W.lo, W.hi)
         plan.set_hypers(*W.hypers())
         tune = plan.autotune(R)
+        variants = tuned_variants(tune)
+        if pinned is not None:
+            variants = {"scatter": pinned[0], "gather": pinned[1], "kuu": pinned[2:2 + d]}
+            plan.set_variants(variants["scatter"], variants["gather"])
+            for ax, v in enumerate(variants["kuu"]):
+                plan.set_kuu_variant(ax, v)
         Vt = plan.permute(Vblk, +1)
         Yt = torch.empty_like(Vt)
         ms_mvm, ms_p10, ms_p90 = _events_stats(lambda: plan.mvm_tiled(Vt, out=Yt), a.mvm_reps, stream)
@@ -319,7 +343,7 @@ def main(argv=None):
             Bd = B.double()
             Rt = Bd - plan.mvm(Xs)
             true_rel = (Rt.norm(dim=1) / Bd.norm(dim=1)).max().item()
-            out = dict(tune=tune, ms_mvm=ms_mvm, ms_p10=ms_p10, ms_p90=ms_p90, ms_stage=ms_stage,
+            out = dict(tune=tune, variants=variants, ms_mvm=ms_mvm, ms_p10=ms_p10, ms_p90=ms_p90, ms_stage=ms_stage,
                        setup_s=t1 - t0, pivchol_s=t2 - t1,
                        pcg_s=t3 - t2, mll_s=t4 - t3, iters=iters, relres=max(relres), status=st,
                        true_rel=true_rel, mll=res["mll"], logdet=res["logdet"],
@@ -353,10 +377,9 @@ def main(argv=None):
     dom = max(stage_ms, key=stage_ms.get)
     ach = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
     # measured HBM bytes of the dominant stage for the variant the tuner picked
-    tune = recs[-1]["tune"]
-    pick = {"scatter": f"scatter_v{int(np.argmin(tune['scatter_us']))}",
-            "gather": f"gather_v{int(np.argmin(tune['gather_us']))}",
-            "kuu": "kuu_" + ("fft" if all(t[1] < 0 or t[0] <= t[1] for t in tune["kuu_us"]) else "dense")}[dom]
+    var = recs[-1]["variants"]
+    pick = {"scatter": f"scatter_v{var['scatter']}", "gather": f"gather_v{var['gather']}",
+            "kuu": "kuu_" + ("fft" if all(v == 0 for v in var["kuu"]) else "dense")}[dom]
     traffic = (measured_traffic() or {}).get(pick)
     if traffic is not None and dom == "kuu":
         traffic *= d  # one launch per axis
@@ -391,6 +414,8 @@ def main(argv=None):
         "mll_and_grad_s": round(float(np.mean([r["mll_s"] for r in recs])), 4),
         "mll_pcg_iters": int(max(r["mll_iters"] for r in recs)),
         "autotune_us": recs[-1]["tune"],
+        "variants": recs[-1]["variants"],
+        "variants_pinned": pinned is not None,
         "mll": recs[-1]["mll"],
         "logdet": recs[-1]["logdet"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
