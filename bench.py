@@ -107,7 +107,9 @@ def _events_stats(fn, reps, stream, warm=3):
 def dskip_block(R, stream, reps=20):
     """D-SKIP block MVM on the 8-D ridge workload (n = 4,000, 1-D grids of 100,
     Lanczos rank 32): build seconds, MVM time and the root products' flop rate
-    (4 N r^2 R flops per block MVM with r padded to 32)."""
+    (4 N r^2 R flops per block MVM with r padded to 32, against the FP32
+    matrix-core peak the two root products run on), then the configuration's block PCG (data vector and 16
+    probes, rank-100 pivoted-Cholesky preconditioner, tolerance 1e-4)."""
     import torch
     import workloads
     from paper_1810_12283_amd import dski
@@ -123,11 +125,26 @@ def dskip_block(R, stream, reps=20):
     Y = torch.empty_like(V)
     med, p10, p90 = _events_stats(lambda: plan.mvm_tiled(V, out=Y), reps, stream)
     flops = 4.0 * W.N * 32 * 32 * R
+    # the block PCG of the configuration: data vector + 16 probes, rank-100 preconditioner
+    import numpy as np
+    B = V.clone()
+    B[0] = torch.tensor(W.y.astype(np.float32), device="cuda")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pc = plan.pivchol(W.rank)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _, iters, _, st, _ = plan.pcg(B, pc, tol=W.tol, max_iter=20000)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    pc.close()
     plan.close()
     return {"workload": f"ridge n={W.n} d={W.d} m_1d={W.skip_m} rank={W.skip_rank} R={R}",
             "build_s": round(build_s, 4), "mvm_ms": round(med, 4), "mvm_ms_p10_p90": [round(p10, 4), round(p90, 4)],
             "gflops": round(flops / (med * 1e-3) / 1e9, 1),
-            "frac_fp64_vector_peak": round(flops / (med * 1e-3) / 78.6e12, 4)}
+            "frac_fp32_mfma_peak": round(flops / (med * 1e-3) / 157.3e12, 4),
+            "pivchol_s": round(t2 - t1, 4), "pcg_s": round(t3 - t2, 4), "pcg_iters": int(max(iters)),
+            "pcg_status": int(st), "rank": W.rank, "tol": W.tol}
 
 
 def mvm_bytes(N, M, n, d, R):

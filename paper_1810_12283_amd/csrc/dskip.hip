@@ -23,9 +23,12 @@
 //   C = Qa^T diag(v) Qb                                   (r x r, a reduction over N rows)
 //   y_i = sum_k (Qa Ta)_{ik} sum_l (Qb Tb)_{il} C_{kl}     (independent rows)
 // 2 N r^2 FMAs per phase and column.  Factors are stored column-major N x RP,
-// RP in {32, 64} (zero-padded), in FP64 and FP32; products accumulate in FP64.
+// RP in {32, 64} (zero-padded), in FP64, with FP32 copies for the solvers' FP32
+// MVM.  The FP64 MVM accumulates in FP64 on the vector ALU; the FP32 MVM runs
+// both phases on the FP32 matrix cores, FP64 across wavefronts and chunks.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -142,7 +145,15 @@ __global__ void k_to_f32(const double* __restrict__ x, size_t len, float* __rest
     y[i] = (float)x[i];
 }
 
-// ---------------------------------------------------------------- Hadamard MVM
+// FP32 row-major copy of a column-major N x RP factor: y[i RP + c] = x[c N + i].
+__global__ void k_to_f32_rows(const double* __restrict__ x, int N, int RP, float* __restrict__ y) {
+  const size_t len = (size_t)N * RP;
+  for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < len; o += (size_t)gridDim.x * blockDim.x)
+    y[o] = (float)x[(o % RP) * N + o / RP];
+}
+
+// ---------------------------------------------------------------- Hadamard MVM, FP64 vector ALU
+// (the FP64 MVM and the Lanczos products of the build)
 // Phase 1: per-chunk partials of C_c = Qa^T diag(v_c) Qb for a group of CG
 // columns.  Thread t owns the output row k = t / (RP/4) and the column quad
 // l0 = 4 (t mod RP/4) (RP = 64: four such (k, quad) pairs).  Rows are staged in
@@ -220,16 +231,51 @@ __global__ __launch_bounds__(256) void k_had_gram(const TF* __restrict__ Qa, con
 
 // C[f] = sum over chunks b of part[b * nout + f], in the order b = s, s + 4, ...
 // for the four slices s, then slices 0 + 1 + 2 + 3.  64 outputs per block.
+// Sum over chunks b = s, s + 4, ... of the slice s (four loads in flight, added
+// in order), then slices 0 + 1 + 2 + 3.
+__device__ __forceinline__ double had_slice_sum(const double* __restrict__ part, int nchunk, size_t nout, size_t f,
+                                                int s) {
+  double a = 0.0;
+  int b = s;
+  for (; b + 12 < nchunk; b += 16) {
+    const double x0 = part[(size_t)b * nout + f], x1 = part[(size_t)(b + 4) * nout + f];
+    const double x2 = part[(size_t)(b + 8) * nout + f], x3 = part[(size_t)(b + 12) * nout + f];
+    a += x0;
+    a += x1;
+    a += x2;
+    a += x3;
+  }
+  for (; b < nchunk; b += 4) a += part[(size_t)b * nout + f];
+  return a;
+}
+
 __global__ void k_had_reduce(const double* __restrict__ part, int nchunk, int nout, double* __restrict__ C) {
   __shared__ double red[4][64];
   const int fl = threadIdx.x & 63, s = threadIdx.x >> 6;
   const int f = blockIdx.x * 64 + fl;
-  double a = 0.0;
-  if (f < nout)
-    for (int b = s; b < nchunk; b += 4) a += part[(size_t)b * nout + f];
-  red[s][fl] = a;
+  red[s][fl] = f < nout ? had_slice_sum(part, nchunk, nout, f, s) : 0.0;
   __syncthreads();
   if (s == 0 && f < nout) C[f] = ((red[0][fl] + red[1][fl]) + red[2][fl]) + red[3][fl];
+}
+
+// The same sums, written in FP32 as the matrix-core fragments of phase 2:
+// C_c[16g + m][4s + kk] goes to Cf[(((c H + g) 4 + kk) 16 + m) S + s]
+// (H = RP/16, S = RP/4), so that lane l = 16 kk + m of a wavefront finds its S
+// operands of (c, g) contiguous and the lanes follow one another.
+template <int RP>
+__global__ void k_had_reduce_frag(const double* __restrict__ part, int nchunk, int R, float* __restrict__ Cf) {
+  constexpr int H = RP / 16, S = RP / 4;
+  __shared__ double red[4][64];
+  const int nout = R * RP * RP;
+  const int fl = threadIdx.x & 63, s = threadIdx.x >> 6;
+  const int f = blockIdx.x * 64 + fl;
+  red[s][fl] = f < nout ? had_slice_sum(part, nchunk, nout, f, s) : 0.0;
+  __syncthreads();
+  if (s == 0 && f < nout) {
+    const int c = f / (RP * RP), k = (f / RP) % RP, l = f % RP;
+    const int g = k / 16, m = k % 16, kk = l % 4, st = l / 4;
+    Cf[(((c * H + g) * 4 + kk) * 16 + m) * S + st] = (float)(((red[0][fl] + red[1][fl]) + red[2][fl]) + red[3][fl]);
+  }
 }
 
 // Phase 2: Y_c = ks * rowsum(Aa o (Ab C_c^T)) + D V_c, one thread per row,
@@ -289,6 +335,266 @@ __global__ __launch_bounds__(256) void k_had_apply(const TF* __restrict__ Aa, co
   }
 }
 
+// ---------------------------------------------------------------- Hadamard MVM, matrix cores
+// The FP32 root MVM of the solvers runs both phases on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32, D += A B with A 16 x 4 and B 4 x 16: lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; register r of lane l holds D[4(l/16) + r][l%16]).
+// The FP32 matrix cores of this GPU deliver about three times the FP64 ones.
+// A wavefront accumulates at most a few hundred rows in FP32; wavefronts,
+// work-groups and the row sums of phase 2 are added in FP64 (relative error a
+// few 1e-7, against 1e-5 required for FP32 MVMs).
+// Qa and Qb have FP32 row-major copies (N x RP) for the Gram phase, Qa Ta and
+// Qb Tb stay column-major: in both phases a wavefront's operand loads are runs
+// of 16 consecutive floats.  Each wavefront loads the operands of its next step
+// while the matrix cores work on the current one.
+typedef float had_flt4 __attribute__((ext_vector_type(4)));
+
+// Phase 1: per-chunk partials of C_c = Qa^T diag(v_c) Qb, contracting over the
+// rows four at a time: A[m][kk] = Qa[i0 + kk][16h + m] v_c[i0 + kk] and
+// B[kk][j] = Qb[i0 + kk][16g + j], so lane l loads entry 16h + l%16 of row
+// i0 + l/16 of each row-major copy.  The 8 wavefronts of a work-group take
+// interleaved 4-row steps of the chunk; their tiles are added in FP64 through
+// LDS one 16-row band of one column at a time (wave order fixed), and written
+// block-major, part[b * (R RP RP) + (c RP + k) RP + l].
+template <int RP, int CG>
+struct GramStep {
+  float qa[RP / 16], qb[RP / 16], v[CG];
+  bool ok;  // the row belongs to this chunk: applied to v at use, so that the
+            // prefetch never waits for its loads
+};
+
+template <int RP, int CG>
+__device__ __forceinline__ void gram_load(GramStep<RP, CG>& o, const float* __restrict__ Qar,
+                                          const float* __restrict__ Qbr, const float* __restrict__ V, int ldv,
+                                          int R, int c0, int i, bool ok, int lc) {
+  const size_t row = ok ? (size_t)i : 0;  // row 0 stands in for rows outside the chunk
+#pragma unroll
+  for (int h = 0; h < RP / 16; ++h) {
+    o.qa[h] = Qar[row * RP + 16 * h + lc];
+    o.qb[h] = Qbr[row * RP + 16 * h + lc];
+  }
+#pragma unroll
+  for (int c = 0; c < CG; ++c) o.v[c] = V[(size_t)min(c0 + c, R - 1) * ldv + row];
+  o.ok = ok;
+}
+
+template <int RP, int CG>
+__global__ __launch_bounds__(512) void k_had_gram_mfma(const float* __restrict__ Qar, const float* __restrict__ Qbr,
+                                                       int N, const float* __restrict__ V, int ldv, int R, int rows,
+                                                       double* __restrict__ part) {
+  constexpr int H = RP / 16;
+  constexpr int NW = 8;
+  __shared__ double red[NW - 1][16 * RP];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int c0 = blockIdx.y * CG;
+  const int e0 = blockIdx.x * rows;
+  const int e1 = min(N, e0 + rows);
+  had_flt4 acc[CG][H][H];
+#pragma unroll
+  for (int c = 0; c < CG; ++c)
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int g = 0; g < H; ++g) acc[c][h][g] = had_flt4{0.f, 0.f, 0.f, 0.f};
+  // macro-steps of MS 4-row steps; the operands of the next macro-step are
+  // loaded while the current one runs
+  constexpr int MS = RP == 32 ? 4 : 2;
+  GramStep<RP, CG> cur[MS];
+  int i0 = e0 + 4 * wv;
+#pragma unroll
+  for (int q = 0; q < MS; ++q) {
+    const int i = i0 + 4 * NW * q + lr;
+    gram_load<RP, CG>(cur[q], Qar, Qbr, V, ldv, R, c0, i, i < e1, lc);
+  }
+  for (; i0 < e1; i0 += 4 * NW * MS) {
+    GramStep<RP, CG> nxt[MS];
+#pragma unroll
+    for (int q = 0; q < MS; ++q) {
+      const int i = i0 + 4 * NW * (MS + q) + lr;
+      gram_load<RP, CG>(nxt[q], Qar, Qbr, V, ldv, R, c0, i, i < e1, lc);
+    }
+    // keep the prefetch ahead of the products (the scheduler would otherwise
+    // sink the loads next to their first use at the end of the macro-step)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < MS; ++q) {
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        // rows outside the chunk and columns beyond R contribute zero
+        const float vv = cur[q].ok && c0 + c < R ? cur[q].v[c] : 0.f;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const float a = cur[q].qa[h] * vv;
+#pragma unroll
+          for (int g = 0; g < H; ++g)
+            acc[c][h][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cur[q].qb[g], acc[c][h][g], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MS; ++q) cur[q] = nxt[q];
+  }
+  const size_t nout = (size_t)R * RP * RP;
+  double* pb = part + (size_t)blockIdx.x * nout;
+#pragma unroll
+  for (int c = 0; c < CG; ++c) {
+    if (c0 + c >= R) break;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      if (wv > 0) {
+#pragma unroll
+        for (int g = 0; g < H; ++g)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wv - 1][(4 * lr + r) * RP + 16 * g + lc] = (double)acc[c][h][g][r];
+      }
+      __syncthreads();
+      if (wv == 0) {
+#pragma unroll
+        for (int g = 0; g < H; ++g)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int o = (4 * lr + r) * RP + 16 * g + lc;
+            double t = (double)acc[c][h][g][r];
+#pragma unroll
+            for (int w = 0; w < NW - 1; ++w) t += red[w][o];
+            pb[((size_t)(c0 + c) * RP + 16 * h + 4 * lr + r) * RP + 16 * g + lc] = t;
+          }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Phase 2: Y_c = ks * rowsum(Aa o (Ab C_c^T)) + D V_c, per 16-row tile as the
+// transposed product P^T = C_c Ab^T contracting over l four at a time:
+// A[m][kk] = C_c[16g + m][4s + kk] (rounded to FP32, in registers for the
+// wavefront's CG2 columns) and B[kk][j] = Ab[i0 + j][4s + kk].  Register r of
+// lane l then holds P[i0 + l%16][16g + 4(l/16) + r]: each lane multiplies its
+// entries by the matching ones of Aa and adds them in FP64, and the four lanes
+// of a row (l, l + 16, l + 32, l + 48) add theirs; lanes 0..15 write rows
+// i0..i0+15.  A wavefront covers 64 rows (4 tiles), a work-group 256 rows;
+// per-block partials of V_c . Y_c are output-major, pq[c * gridDim.x + b].
+template <int RP>
+struct ApplyTile {
+  float ab[RP / 4], aa[RP / 16][4];
+};
+
+template <int RP>
+__device__ __forceinline__ void apply_load(ApplyTile<RP>& o, const float* __restrict__ Aa,
+                                           const float* __restrict__ Ab, int N, int i0, int lr, int lc) {
+  const bool ok = i0 + lc < N;
+  const size_t i = ok ? (size_t)(i0 + lc) : 0;
+#pragma unroll
+  for (int s = 0; s < RP / 4; ++s) o.ab[s] = ld_or0(Ab, (size_t)(4 * s + lr) * N + i, (size_t)(4 * s + lr) * N, ok);
+#pragma unroll
+  for (int g = 0; g < RP / 16; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      o.aa[g][r] = ld_or0(Aa, (size_t)(16 * g + 4 * lr + r) * N + i, (size_t)(16 * g + 4 * lr + r) * N, ok);
+}
+
+template <int RP, int CG2>
+__global__ __launch_bounds__(256) void k_had_apply_mfma(const float* __restrict__ Aa, const float* __restrict__ Ab,
+                                                        int N, int n, const float* __restrict__ Cf, int R,
+                                                        const float* __restrict__ V, int ldv, float* __restrict__ Y,
+                                                        int ldy, double ks, double nv, double ng,
+                                                        double* __restrict__ pq) {
+  constexpr int H = RP / 16;
+  constexpr int S = RP / 4;
+  constexpr int FR = H * 64 * S;  // fragment floats per column
+  __shared__ double red[CG2][4];
+  __shared__ float4 sC[CG2 * FR / 4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int c0 = blockIdx.y * CG2;
+  const int base = blockIdx.x * 256 + wv * 64;
+  // every operand of the wavefront's 4 tiles is requested before the first product
+  ApplyTile<RP> tile[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) apply_load<RP>(tile[t], Aa, Ab, N, base + 16 * t, lr, lc);
+  float xv[4][CG2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int c = 0; c < CG2; ++c) {
+      const int row = base + 16 * t + lc;
+      const size_t vo = (size_t)min(c0 + c, R - 1) * ldv;
+      xv[t][c] = ld_or0(V, vo + row, vo, lr == 0 && row < N && c0 + c < R);
+    }
+  // the fragments of this work-group's columns (zero beyond R) through LDS
+  {
+    const int nc = min(CG2, R - c0);
+    const float4* src = reinterpret_cast<const float4*>(Cf + (size_t)c0 * FR);
+    for (int e = threadIdx.x; e < CG2 * FR / 4; e += 256)
+      sC[e] = e < nc * FR / 4 ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+  float cf[CG2][H][S];
+#pragma unroll
+  for (int c = 0; c < CG2; ++c)
+#pragma unroll
+    for (int g = 0; g < H; ++g)
+#pragma unroll
+      for (int q = 0; q < S / 4; ++q) {
+        const float4 w = sC[(((c * H + g) * 64 + lane) * S) / 4 + q];
+        cf[c][g][4 * q] = w.x;
+        cf[c][g][4 * q + 1] = w.y;
+        cf[c][g][4 * q + 2] = w.z;
+        cf[c][g][4 * q + 3] = w.w;
+      }
+  double dot[CG2];
+#pragma unroll
+  for (int c = 0; c < CG2; ++c) dot[c] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i0 = base + 16 * t;
+    if (i0 >= N) break;  // uniform over the wavefront
+    had_flt4 acc[CG2][H];
+#pragma unroll
+    for (int c = 0; c < CG2; ++c)
+#pragma unroll
+      for (int g = 0; g < H; ++g) acc[c][g] = had_flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int c = 0; c < CG2; ++c)
+#pragma unroll
+        for (int g = 0; g < H; ++g)
+          acc[c][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(cf[c][g][s], tile[t].ab[s], acc[c][g], 0, 0, 0);
+    const int row = i0 + lc;
+#pragma unroll
+    for (int c = 0; c < CG2; ++c) {
+      if (c0 + c >= R) break;
+      double v = 0.0;
+#pragma unroll
+      for (int g = 0; g < H; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v += (double)tile[t].aa[g][r] * (double)acc[c][g][r];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      const bool wr = lr == 0 && row < N;
+      const double x = (double)xv[t][c];
+      const float out = (float)(ks * v + (row < n ? nv : ng) * x);
+      if (wr) Y[(size_t)(c0 + c) * ldy + row] = out;
+      dot[c] += wr ? x * (double)out : 0.0;
+    }
+  }
+  if (pq) {
+#pragma unroll
+    for (int c = 0; c < CG2; ++c) {
+      if (c0 + c >= R) break;
+      const double w = wave_sum64(dot[c]);
+      if (lane == 0) red[c][wv] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < CG2 && c0 + (int)threadIdx.x < R) {
+      const int c = threadIdx.x;
+      pq[(size_t)(c0 + c) * gridDim.x + blockIdx.x] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+    }
+  }
+}
+
 // Row chunks of the Gram phase: enough work-groups to fill the CUs, at least 64
 // rows each; for wide blocks the partial volume (chunks x R RP^2) caps the count.
 static int had_chunks(int N, int R) {
@@ -301,31 +607,53 @@ template <int RP, typename TF, typename T>
 static dski_status had_apply_rp(DskipData* D, const TF* Qa, const TF* Aa, const TF* Qb, const TF* Ab, int N,
                                 int n, int R, const T* V, int ldv, T* Y, int ldy, double ks, double nv,
                                 double ng, double* pq, hipStream_t st) {
-  constexpr int CG = RP == 32 ? 4 : 2;
-  constexpr int CG2 = RP == 32 ? 4 : 1;
-  const bool one = R == 1;
-  const int ngroups = one ? 1 : (R + CG - 1) / CG;
-  const int nchunk = had_chunks(N, R);
-  const int rows = (N + nchunk - 1) / nchunk;
-  const size_t nout = (size_t)R * RP * RP;
-  DSKI_TRY(D->gram.reserve(sizeof(double) * (nout * (size_t)nchunk + nout) + 256));
-  double* part = D->gram.as<double>();
-  double* C = part + nout * (size_t)nchunk;
-  if (one)
-    k_had_gram<RP, 1, TF, T><<<dim3(nchunk, 1), 256, 0, st>>>(Qa, Qb, N, V, ldv, R, rows, part);
-  else
-    k_had_gram<RP, CG, TF, T><<<dim3(nchunk, ngroups), 256, 0, st>>>(Qa, Qb, N, V, ldv, R, rows, part);
-  DSKI_HIP(hipGetLastError());
-  k_had_reduce<<<(unsigned)((nout + 63) / 64), 256, 0, st>>>(part, nchunk, (int)nout, C);
-  DSKI_HIP(hipGetLastError());
-  const int nb = (N + 255) / 256;
-  if (one)
-    k_had_apply<RP, 1, TF, T><<<dim3(nb, 1), 256, 0, st>>>(Aa, Ab, N, n, C, R, V, ldv, Y, ldy, ks, nv, ng, pq);
-  else
-    k_had_apply<RP, CG2, TF, T><<<dim3(nb, (R + CG2 - 1) / CG2), 256, 0, st>>>(Aa, Ab, N, n, C, R, V, ldv, Y,
-                                                                              ldy, ks, nv, ng, pq);
-  DSKI_HIP(hipGetLastError());
-  return DSKI_OK;
+  if constexpr (std::is_same<TF, float>::value && std::is_same<T, float>::value) {
+    // matrix-core form (FP32 factors in the layouts the kernels expect)
+    // 6 columns per wavefront at rank 32 (a 17-column block is 3 near-equal
+    // groups), 2 at rank 64; about one Gram work-group per CU
+    constexpr int MG = RP == 32 ? 6 : 2;
+    const int ng1 = (R + MG - 1) / MG;
+    const int nchunk = std::max(1, std::min((N + 255) / 256, 255 / ng1));
+    const int rows = (N + nchunk - 1) / nchunk;
+    const size_t nout = (size_t)R * RP * RP;
+    DSKI_TRY(D->gram.reserve(sizeof(double) * (nout * (size_t)nchunk + nout) + 256));
+    double* part = D->gram.as<double>();
+    float* Cf = reinterpret_cast<float*>(part + nout * (size_t)nchunk);
+    k_had_gram_mfma<RP, MG><<<dim3(nchunk, ng1), 512, 0, st>>>(Qa, Qb, N, V, ldv, R, rows, part);
+    DSKI_HIP(hipGetLastError());
+    k_had_reduce_frag<RP><<<(unsigned)((nout + 63) / 64), 256, 0, st>>>(part, nchunk, R, Cf);
+    DSKI_HIP(hipGetLastError());
+    k_had_apply_mfma<RP, MG><<<dim3((N + 255) / 256, ng1), 256, 0, st>>>(Aa, Ab, N, n, Cf, R, V, ldv, Y, ldy, ks,
+                                                                          nv, ng, pq);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  } else {
+    constexpr int CG = RP == 32 ? 4 : 2;
+    constexpr int CG2 = RP == 32 ? 4 : 1;
+    const bool one = R == 1;
+    const int ngroups = one ? 1 : (R + CG - 1) / CG;
+    const int nchunk = had_chunks(N, R);
+    const int rows = (N + nchunk - 1) / nchunk;
+    const size_t nout = (size_t)R * RP * RP;
+    DSKI_TRY(D->gram.reserve(sizeof(double) * (nout * (size_t)nchunk + nout) + 256));
+    double* part = D->gram.as<double>();
+    double* C = part + nout * (size_t)nchunk;
+    if (one)
+      k_had_gram<RP, 1, TF, T><<<dim3(nchunk, 1), 256, 0, st>>>(Qa, Qb, N, V, ldv, R, rows, part);
+    else
+      k_had_gram<RP, CG, TF, T><<<dim3(nchunk, ngroups), 256, 0, st>>>(Qa, Qb, N, V, ldv, R, rows, part);
+    DSKI_HIP(hipGetLastError());
+    k_had_reduce<<<(unsigned)((nout + 63) / 64), 256, 0, st>>>(part, nchunk, (int)nout, C);
+    DSKI_HIP(hipGetLastError());
+    const int nb = (N + 255) / 256;
+    if (one)
+      k_had_apply<RP, 1, TF, T><<<dim3(nb, 1), 256, 0, st>>>(Aa, Ab, N, n, C, R, V, ldv, Y, ldy, ks, nv, ng, pq);
+    else
+      k_had_apply<RP, CG2, TF, T><<<dim3(nb, (R + CG2 - 1) / CG2), 256, 0, st>>>(Aa, Ab, N, n, C, R, V, ldv, Y,
+                                                                                ldy, ks, nv, ng, pq);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  }
 }
 
 template <typename TF, typename T>
@@ -468,9 +796,9 @@ static dski_status dskip_build(dski_plan p, hipStream_t st) {
   D->fb = level[1];
   size_t len = (size_t)N * D->RP;
   const int cb = (int)std::min<size_t>((len + kBlock - 1) / kBlock, 4096);
-  k_to_f32<<<cb, kBlock, 0, st>>>(D->fa.Q, len, D->Qa32);
+  k_to_f32_rows<<<cb, kBlock, 0, st>>>(D->fa.Q, N, D->RP, D->Qa32);
   k_to_f32<<<cb, kBlock, 0, st>>>(D->fa.A, len, D->Aa32);
-  k_to_f32<<<cb, kBlock, 0, st>>>(D->fb.Q, len, D->Qb32);
+  k_to_f32_rows<<<cb, kBlock, 0, st>>>(D->fb.Q, N, D->RP, D->Qb32);
   k_to_f32<<<cb, kBlock, 0, st>>>(D->fb.A, len, D->Ab32);
   DSKI_HIP(hipGetLastError());
   D->built = true;
