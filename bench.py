@@ -202,6 +202,8 @@ def main(argv=None):
     ap.add_argument("--variants", default=None,
                     help="S,G,K0,K1: pin the scatter, gather and per-axis K_UU variants after the tuner has run "
                          "(for profiled runs, whose per-dispatch overhead distorts the tuner's timings)")
+    ap.add_argument("--dskip-only", action="store_true",
+                    help="only the D-SKIP block of the 8-D ridge workload (build, block MVMs, block PCG)")
     ap.add_argument("--pmc-mvm", action="store_true",
                     help="run only the MVM stages (and a 256 MiB device copy for calibration) for rocprofv3 --pmc")
     a = ap.parse_args(argv)
@@ -237,6 +239,10 @@ def main(argv=None):
     M = int(np.prod(W.grid_m))
     Vblk = dski.rademacher(12345, 0, R, N, device=dev)
     Vblk[0] = y[0]
+
+    if a.dskip_only:
+        print(json.dumps({"dskip": dskip_block(R, stream)}), flush=True)
+        return 0
 
     if a.sweep:
         for n_s, g_s in ((20000, 200), (200000, 632), (500000, 1000)):

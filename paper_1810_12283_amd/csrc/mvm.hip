@@ -538,11 +538,16 @@ static dski_status build_tiles(dski_plan p, hipStream_t st) {
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_tot);
   DSKI_HIP(e);
-  long long slots = 0;
+  long long slots = 0, over = 0;
   for (long long t = 0; t < tiles; ++t) {
     off[(size_t)t] = (int)slots;
     slots += tot[(size_t)t];
+    if (tot[(size_t)t] > 256) over += tot[(size_t)t];
   }
+  // Most region points in tiles too full for LDS staging (256 points; dense
+  // 1-D grids with many points per cell): the cache-direct form is the default;
+  // the tuner may still pick another form (all give identical results).
+  if (2 * over > slots) p->scatter_variant = 1;
   if (slots > (1ll << 31) - 1) {
     set_error("scatter region tables too large");
     return DSKI_ENOTSUP;
