@@ -147,6 +147,51 @@ def dskip_block(R, stream, reps=20):
             "pcg_status": int(st), "rank": W.rank, "tol": W.tol}
 
 
+def surrogate_block(W, y, rank, stream, reps=20):
+    """The learned log-det surrogate on the terrain data: one SLQ log det +
+    gradient evaluation (16 probes) against one data-fit evaluation (a single
+    PCG column) at the true hyper-parameters, and the network's kernels at the
+    sizes of the configuration (8 -> 128 -> 128 -> 1, 2,000 training points):
+    one full-batch value + gradient training step (backward and Adam) and one
+    inference (value and 5 input tangents, batch 1)."""
+    import numpy as np
+    import torch
+    from paper_1810_12283_amd import dski, surrogate
+    plan = dski.Plan(torch.tensor(W.X, dtype=torch.float64, device="cuda"), W.grid_m, W.lo, W.hi)
+    theta = np.concatenate([W.log_ell, [W.log_s, W.log_sigma_f, W.log_sigma_g]])
+    plan.set_hypers(W.log_ell, W.log_s, W.log_sigma_f, W.log_sigma_g)
+    plan.autotune(1 + W.num_probes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    surrogate.logdet_and_grad(plan, theta, rank, W.num_probes, 7, W.tol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    surrogate.data_fit_and_grad(plan, theta, y, rank, W.tol)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    plan.close()
+    F, H, J, B = 8, 128, 5, 2000
+    r = np.random.default_rng(0)
+    net = dski.Mlp(dski.Mlp.pack(r.standard_normal((H, F)) * 0.5, np.zeros(H), r.standard_normal((H, H)) * 0.1,
+                                 np.zeros(H), r.standard_normal(H) * 0.1, np.zeros(1)), F=F, H=H, J=J)
+    X = torch.tensor(r.standard_normal((B, F)), dtype=torch.float32, device="cuda")
+    t = torch.tensor(r.standard_normal(B), dtype=torch.float32, device="cuda")
+    g = torch.tensor(r.standard_normal((B, J)), dtype=torch.float32, device="cuda")
+    x1 = X[:1].contiguous()
+
+    def train_step():
+        net.backward(X, t, g, 1.0)
+        net.step(lr=1e-4)
+    train_ms = _events_stats(train_step, reps, stream)[0]
+    infer_ms = _events_stats(lambda: net.jvp(x1), reps, stream)[0]
+    net.close()
+    return {"workload": f"terrain n={W.n} d={W.d} grid={W.grid_m[0]}x{W.grid_m[1]}, network {F}-{H}-{H}-1, "
+                        f"{B} training points",
+            "slq_logdet_grad_s": round(t1 - t0, 4), "data_fit_grad_s": round(t2 - t1, 4),
+            "mlp_train_step_ms": round(train_ms, 4), "mlp_infer_ms": round(infer_ms, 4),
+            "eval_speedup": round((t1 - t0) / (t2 - t1 + infer_ms * 1e-3), 3)}
+
+
 def mvm_bytes(N, M, n, d, R):
     """Algorithmic bytes of one block MVM (FP32 vectors and grid):
     V read by the scatter and again for the noise term, Y written (3 N R);
@@ -446,6 +491,7 @@ def main(argv=None):
                      "traffic": traffic},
     }
     line["dskip"] = dskip_block(R, stream)
+    line["surrogate"] = surrogate_block(W, y, W.rank, stream)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, R)
     print(json.dumps(line), flush=True)

@@ -461,23 +461,38 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
     // stencil position on the last axis changes at each cell boundary
     for (int cl = lo[last]; cl <= hi[last]; ++cl) {
       const int kb = cstart[base + cl - 1], ke = cstart[base + cl];
-      for (int k = kb; k < ke; ++k) {
-        double wv[D], wd[D];
+      // four points per step: all their loads are issued before the first
+      // product; the points are then added in order, exactly as one at a time
+      for (int k0 = kb; k0 < ke; k0 += 4) {
+        double wv[4][D], wd[4][D];
+        T x[4][CRD * (D + 1)];
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          int ca = (a == last) ? cl : c[a];
-          int o = j[a] - ca + 1;
-          wv[a] = wts[(size_t)(a * 8 + o) * n + k];
-          wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u < ke ? k0 + u : kb;  // a valid point stands in past the run
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            int ca = (a == last) ? cl : c[a];
+            int o = j[a] - ca + 1;
+            wv[u][a] = wts[(size_t)(a * 8 + o) * n + k];
+            wd[u][a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
+          }
+#pragma unroll
+          for (int r = 0; r < CRD; ++r)
+#pragma unroll
+            for (int b2 = 0; b2 <= D; ++b2)
+              x[u][r * (D + 1) + b2] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b2 * n + k,
+                                              (size_t)r0 * ldv + (size_t)b2 * n + k, r < rc);
         }
-        T x[CRD * (D + 1)];
 #pragma unroll
-        for (int r = 0; r < CRD; ++r)
+        for (int u = 0; u < 4; ++u) {
+          double t[CRD];
 #pragma unroll
-          for (int b2 = 0; b2 <= D; ++b2)
-            x[r * (D + 1) + b2] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b2 * n + k,
-                                         (size_t)r0 * ldv + (size_t)b2 * n + k, r < rc);
-        scatter_accum<D, CRD>(acc, wv, wd, x);
+          for (int r = 0; r < CRD; ++r) t[r] = acc[r];
+          scatter_accum<D, CRD>(t, wv[u], wd[u], x[u]);
+          const bool ok = k0 + u < ke;
+#pragma unroll
+          for (int r = 0; r < CRD; ++r) acc[r] = ok ? t[r] : acc[r];
+        }
       }
     }
   }
