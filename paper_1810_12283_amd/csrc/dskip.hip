@@ -28,6 +28,7 @@
 // both phases on the FP32 matrix cores, FP64 across wavefronts and chunks.
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <type_traits>
 #include <vector>
 
@@ -604,7 +605,7 @@ static int had_chunks(int N, int R) {
 
 // Y = ks (A o B) V + D V with A = Qa Ta Qa^T, B = Qb Tb Qb^T given as (Q, Q T).
 template <int RP, typename TF, typename T>
-static dski_status had_apply_rp(DskipData* D, const TF* Qa, const TF* Aa, const TF* Qb, const TF* Ab, int N,
+static dski_status had_apply_rp(DevBuf& gram, const TF* Qa, const TF* Aa, const TF* Qb, const TF* Ab, int N,
                                 int n, int R, const T* V, int ldv, T* Y, int ldy, double ks, double nv,
                                 double ng, double* pq, hipStream_t st) {
   if constexpr (std::is_same<TF, float>::value && std::is_same<T, float>::value) {
@@ -616,8 +617,8 @@ static dski_status had_apply_rp(DskipData* D, const TF* Qa, const TF* Aa, const 
     const int nchunk = std::max(1, std::min((N + 255) / 256, 255 / ng1));
     const int rows = (N + nchunk - 1) / nchunk;
     const size_t nout = (size_t)R * RP * RP;
-    DSKI_TRY(D->gram.reserve(sizeof(double) * (nout * (size_t)nchunk + nout) + 256));
-    double* part = D->gram.as<double>();
+    DSKI_TRY(gram.reserve(sizeof(double) * (nout * (size_t)nchunk + nout) + 256));
+    double* part = gram.as<double>();
     float* Cf = reinterpret_cast<float*>(part + nout * (size_t)nchunk);
     k_had_gram_mfma<RP, MG><<<dim3(nchunk, ng1), 512, 0, st>>>(Qa, Qb, N, V, ldv, R, rows, part);
     DSKI_HIP(hipGetLastError());
@@ -635,8 +636,8 @@ static dski_status had_apply_rp(DskipData* D, const TF* Qa, const TF* Aa, const 
     const int nchunk = had_chunks(N, R);
     const int rows = (N + nchunk - 1) / nchunk;
     const size_t nout = (size_t)R * RP * RP;
-    DSKI_TRY(D->gram.reserve(sizeof(double) * (nout * (size_t)nchunk + nout) + 256));
-    double* part = D->gram.as<double>();
+    DSKI_TRY(gram.reserve(sizeof(double) * (nout * (size_t)nchunk + nout) + 256));
+    double* part = gram.as<double>();
     double* C = part + nout * (size_t)nchunk;
     if (one)
       k_had_gram<RP, 1, TF, T><<<dim3(nchunk, 1), 256, 0, st>>>(Qa, Qb, N, V, ldv, R, rows, part);
@@ -657,84 +658,157 @@ static dski_status had_apply_rp(DskipData* D, const TF* Qa, const TF* Aa, const 
 }
 
 template <typename TF, typename T>
-static dski_status had_apply(DskipData* D, const TF* Qa, const TF* Aa, const TF* Qb, const TF* Ab, int N, int n,
+static dski_status had_apply(DskipData* D, DevBuf& gram, const TF* Qa, const TF* Aa, const TF* Qb, const TF* Ab, int N, int n,
                              int R, const T* V, int ldv, T* Y, int ldy, double ks, double nv, double ng, double* pq,
                              hipStream_t st) {
   if (R <= 0) return DSKI_OK;
   if (D->RP == 32)
-    return had_apply_rp<32, TF, T>(D, Qa, Aa, Qb, Ab, N, n, R, V, ldv, Y, ldy, ks, nv, ng, pq, st);
-  return had_apply_rp<64, TF, T>(D, Qa, Aa, Qb, Ab, N, n, R, V, ldv, Y, ldy, ks, nv, ng, pq, st);
+    return had_apply_rp<32, TF, T>(gram, Qa, Aa, Qb, Ab, N, n, R, V, ldv, Y, ldy, ks, nv, ng, pq, st);
+  return had_apply_rp<64, TF, T>(gram, Qa, Aa, Qb, Ab, N, n, R, V, ldv, Y, ldy, ks, nv, ng, pq, st);
 }
 
 // ---------------------------------------------------------------- Lanczos
-// r steps on a symmetric operator F (FP64, N-vectors) with full
-// re-orthogonalisation; F(x, y) writes y = F x.  The factor receives Q (N x RP,
-// zero beyond the steps kept) and A = Q T.
-template <class F>
-static dski_status lanczos(DskipData* D, int N, int node, F&& apply, DskipFactor& out, hipStream_t st) {
-  const int RP = D->RP, r = D->r;
-  const int nb = std::min(256, std::max(1, (N + 1023) / 1024));
-  const int vb = (N + kBlock - 1) / kBlock;
-  DSKI_TRY(D->work.reserve(sizeof(double) * ((size_t)N + 2 * (size_t)RP * nb + 4 * (size_t)RP + RP * RP + 64)));
-  double* w = D->work.as<double>();
-  double* part = w + N;
-  double* h = part + 2 * (size_t)RP * nb;
-  double* h2 = h + RP;
-  double* nn = h2 + RP;
-  double* Tdev = nn + 2 * RP;
-  if (!out.Q) DSKI_HIP(hipMalloc(&out.Q, sizeof(double) * (size_t)N * RP));
-  if (!out.A) DSKI_HIP(hipMalloc(&out.A, sizeof(double) * (size_t)N * RP));
-  DSKI_HIP(hipMemsetAsync(out.Q, 0, sizeof(double) * (size_t)N * RP, st));
-  DSKI_HIP(hipMemsetAsync(out.A, 0, sizeof(double) * (size_t)N * RP, st));
-  double* Q = out.Q;
-  // q_0 = z / ||z|| with z the Rademacher column `node` (||z|| = sqrt(N))
-  DSKI_TRY(rademacher<double>(D->seed, node, 1, N, Q, N, st));
-  k_scale_copy<<<vb, kBlock, 0, st>>>(Q, N, 1.0 / std::sqrt((double)N), Q);
+// r steps on a symmetric operator (FP64, N-vectors) with full
+// re-orthogonalisation; apply(x, y, stream) writes y = F x.  The factor
+// receives Q (N x RP, zero beyond the steps kept) and A = Q T.  The runs of one
+// tree level are independent: each has its own stream and buffers, their
+// steps are issued in turn and the host waits once per step for all of them
+// (a run's step count depends on its own breakdown test only, so every factor
+// is the one a run by itself would give).
+struct LanczosJob {
+  int node = 0;
+  std::function<dski_status(const double*, double*, hipStream_t)> apply;
+  DskipFactor* out = nullptr;
+  hipStream_t st = nullptr;
+  DevBuf work;                  // w, partials, h, h2, |w|^2, T
+  DevBuf tmp;                   // operator scratch (1-D D-SKI vectors or Hadamard partials)
   std::vector<double> alpha, beta;
-  for (int j = 0; j < r; ++j) {
-    double* qj = Q + (size_t)j * N;
-    DSKI_TRY(apply(qj, w));
-    // pass 1: h = Q^T w (alpha = h_j = q_j . w), w -= Q h; pass 2 the same
-    for (int pass = 0; pass < 2; ++pass) {
-      double* hh = pass == 0 ? h : h2;
-      k_cols_dot<<<dim3(nb, j + 1), kBlock, 0, st>>>(Q, N, w, part);
-      RedJob jr{part, nb, j + 1, 1, hh, nullptr, nullptr, 1.0, nullptr, nullptr};
-      DSKI_TRY(launch_reduce(jr, nullptr, st));
-      k_cols_sub<<<vb, kBlock, 0, st>>>(Q, N, j + 1, hh, w);
-    }
-    k_cols_dot<<<dim3(nb, 1), kBlock, 0, st>>>(w, N, w, part);
-    RedJob jn{part, nb, 1, 1, nn, nullptr, nullptr, 1.0, nullptr, nullptr};
-    DSKI_TRY(launch_reduce(jn, nullptr, st));
-    DSKI_HIP(hipGetLastError());
-    double ha = 0.0, hn = 0.0;
-    DSKI_HIP(hipMemcpyAsync(&ha, h + j, sizeof(double), hipMemcpyDeviceToHost, st));
-    DSKI_HIP(hipMemcpyAsync(&hn, nn, sizeof(double), hipMemcpyDeviceToHost, st));
-    DSKI_HIP(hipStreamSynchronize(st));
-    double b = std::sqrt(std::max(hn, 0.0));
-    alpha.push_back(ha);
-    if (j == r - 1 || b <= 1e-12 * std::max(std::fabs(ha), 1.0)) break;
-    beta.push_back(b);
-    k_scale_copy<<<vb, kBlock, 0, st>>>(w, N, 1.0 / b, Q + (size_t)(j + 1) * N);
-  }
-  const int k = (int)alpha.size();
-  std::vector<double> T((size_t)k * k, 0.0);
-  for (int j = 0; j < k; ++j) {
-    T[(size_t)j * k + j] = alpha[j];
-    if (j + 1 < k) T[(size_t)j * k + j + 1] = T[(size_t)(j + 1) * k + j] = beta[j];
-  }
-  DSKI_HIP(hipMemcpyAsync(Tdev, T.data(), sizeof(double) * T.size(), hipMemcpyHostToDevice, st));
-  k_q_times_t<<<dim3(vb, k), kBlock, 0, st>>>(Q, N, k, Tdev, out.A);
-  DSKI_HIP(hipGetLastError());
-  DSKI_HIP(hipStreamSynchronize(st));  // T lives on the host stack
-  out.k = k;
-  return DSKI_OK;
-}
+  bool done = false;
+};
 
 static void free_factor(DskipFactor& f) {
   (void)hipFree(f.Q);
   (void)hipFree(f.A);
   f = DskipFactor{};
 }
+
+static dski_status lanczos_batch(DskipData* D, int N, std::vector<LanczosJob>& jobs, double* hpin) {
+  const int RP = D->RP, r = D->r;
+  const int nb = std::min(256, std::max(1, (N + 1023) / 1024));
+  const int vb = (N + kBlock - 1) / kBlock;
+  const size_t wlen = (size_t)N + 2 * (size_t)RP * nb + 4 * (size_t)RP + (size_t)RP * RP + 64;
+  auto bufs = [&](LanczosJob& J, double** w, double** part, double** h, double** h2, double** nn, double** Tdev) {
+    *w = J.work.as<double>();
+    *part = *w + N;
+    *h = *part + 2 * (size_t)RP * nb;
+    *h2 = *h + RP;
+    *nn = *h2 + RP;
+    *Tdev = *nn + 2 * RP;
+  };
+  for (auto& J : jobs) {
+    DSKI_TRY(J.work.reserve(sizeof(double) * wlen));
+    DskipFactor& out = *J.out;
+    if (!out.Q) DSKI_HIP(hipMalloc(&out.Q, sizeof(double) * (size_t)N * RP));
+    if (!out.A) DSKI_HIP(hipMalloc(&out.A, sizeof(double) * (size_t)N * RP));
+    DSKI_HIP(hipMemsetAsync(out.Q, 0, sizeof(double) * (size_t)N * RP, J.st));
+    DSKI_HIP(hipMemsetAsync(out.A, 0, sizeof(double) * (size_t)N * RP, J.st));
+    // q_0 = z / ||z|| with z the Rademacher column `node` (||z|| = sqrt(N))
+    DSKI_TRY(rademacher<double>(D->seed, J.node, 1, N, out.Q, N, J.st));
+    k_scale_copy<<<vb, kBlock, 0, J.st>>>(out.Q, N, 1.0 / std::sqrt((double)N), out.Q);
+    J.alpha.clear();
+    J.beta.clear();
+    J.done = false;
+  }
+  for (int j = 0; j < r; ++j) {
+    bool any = false;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      LanczosJob& J = jobs[i];
+      if (J.done) continue;
+      any = true;
+      double *w, *part, *h, *h2, *nn, *Tdev;
+      bufs(J, &w, &part, &h, &h2, &nn, &Tdev);
+      const double* Q = J.out->Q;
+      DSKI_TRY(J.apply(Q + (size_t)j * N, w, J.st));
+      // pass 1: h = Q^T w (alpha = h_j = q_j . w), w -= Q h; pass 2 the same
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hh = pass == 0 ? h : h2;
+        k_cols_dot<<<dim3(nb, j + 1), kBlock, 0, J.st>>>(Q, N, w, part);
+        RedJob jr{part, nb, j + 1, 1, hh, nullptr, nullptr, 1.0, nullptr, nullptr};
+        DSKI_TRY(launch_reduce(jr, nullptr, J.st));
+        k_cols_sub<<<vb, kBlock, 0, J.st>>>(Q, N, j + 1, hh, w);
+      }
+      k_cols_dot<<<dim3(nb, 1), kBlock, 0, J.st>>>(w, N, w, part);
+      RedJob jn{part, nb, 1, 1, nn, nullptr, nullptr, 1.0, nullptr, nullptr};
+      DSKI_TRY(launch_reduce(jn, nullptr, J.st));
+      DSKI_HIP(hipGetLastError());
+      DSKI_HIP(hipMemcpyAsync(hpin + 2 * i, h + j, sizeof(double), hipMemcpyDeviceToHost, J.st));
+      DSKI_HIP(hipMemcpyAsync(hpin + 2 * i + 1, nn, sizeof(double), hipMemcpyDeviceToHost, J.st));
+    }
+    if (!any) break;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      LanczosJob& J = jobs[i];
+      if (J.done) continue;
+      DSKI_HIP(hipStreamSynchronize(J.st));
+      const double ha = hpin[2 * i], hn = hpin[2 * i + 1];
+      const double b = std::sqrt(std::max(hn, 0.0));
+      J.alpha.push_back(ha);
+      if (j == r - 1 || b <= 1e-12 * std::max(std::fabs(ha), 1.0)) {
+        J.done = true;
+        continue;
+      }
+      J.beta.push_back(b);
+      double *w, *part, *h, *h2, *nn, *Tdev;
+      bufs(J, &w, &part, &h, &h2, &nn, &Tdev);
+      k_scale_copy<<<vb, kBlock, 0, J.st>>>(w, N, 1.0 / b, J.out->Q + (size_t)(j + 1) * N);
+    }
+  }
+  for (auto& J : jobs) {
+    const int k = (int)J.alpha.size();
+    std::vector<double> T((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) {
+      T[(size_t)j * k + j] = J.alpha[j];
+      if (j + 1 < k) T[(size_t)j * k + j + 1] = T[(size_t)(j + 1) * k + j] = J.beta[j];
+    }
+    double *w, *part, *h, *h2, *nn, *Tdev;
+    bufs(J, &w, &part, &h, &h2, &nn, &Tdev);
+    DSKI_HIP(hipMemcpyAsync(Tdev, T.data(), sizeof(double) * T.size(), hipMemcpyHostToDevice, J.st));
+    k_q_times_t<<<dim3(vb, k), kBlock, 0, J.st>>>(J.out->Q, N, k, Tdev, J.out->A);
+    DSKI_HIP(hipGetLastError());
+    DSKI_HIP(hipStreamSynchronize(J.st));  // T lives on the host stack
+    J.out->k = k;
+  }
+  return DSKI_OK;
+}
+
+// Streams for the independent Lanczos runs of the build (default priority),
+// ordered after the caller's stream at creation and before it on release.
+struct BuildStreams {
+  std::vector<hipStream_t> st;
+  hipEvent_t ev = nullptr;
+  double* hpin = nullptr;
+  ~BuildStreams() {
+    for (auto s : st) (void)hipStreamDestroy(s);
+    if (ev) (void)hipEventDestroy(ev);
+    if (hpin) (void)hipHostFree(hpin);
+  }
+  dski_status init(int n, hipStream_t caller) {
+    DSKI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    DSKI_HIP(hipEventRecord(ev, caller));
+    for (int i = 0; i < n; ++i) {
+      hipStream_t s = nullptr;
+      DSKI_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      st.push_back(s);
+      DSKI_HIP(hipStreamWaitEvent(s, ev, 0));
+    }
+    DSKI_HIP(hipHostMalloc(&hpin, sizeof(double) * 2 * (size_t)std::max(n, 1), hipHostMallocDefault));
+    return DSKI_OK;
+  }
+  dski_status join(hipStream_t caller) {
+    for (auto s : st) DSKI_HIP(hipStreamSynchronize(s));
+    (void)caller;
+    return DSKI_OK;
+  }
+};
 
 static dski_status dskip_build(dski_plan p, hipStream_t st) {
   DskipData* D = p->ds;
@@ -746,48 +820,68 @@ static dski_status dskip_build(dski_plan p, hipStream_t st) {
     D->sub[a]->sf = 0.0;  // G_p is the noise-free 1-D D-SKI matrix
     D->sub[a]->sg = 0.0;
   }
-  TmpBuf tmp;
-  DSKI_TRY(tmp.reserve(sizeof(double) * 4 * (size_t)std::max(n, 1)));
-  double* u = tmp.as<double>();
-  double* y = u + 2 * (size_t)n;
   free_factor(D->fa);
   free_factor(D->fb);
+  BuildStreams bs;
+  DSKI_TRY(bs.init(d, st));
   std::vector<DskipFactor> level(d);
   dski_status rc = DSKI_OK;
-  for (int a = 0; a < d && rc >= 0; ++a) {
-    dski_plan sp = D->sub[a];
-    int* iperm = D->iperm[a];
-    auto leaf = [&](const double* q, double* w) -> dski_status {
-      k_compress<<<pb, kBlock, 0, st>>>(q, n, d, a, sp->perm, u);
-      DSKI_TRY(mvm_tiled<double>(sp, 1, u, 2 * n, y, 2 * n, nullptr, st));
-      k_expand<<<pb, kBlock, 0, st>>>(y, n, d, a, iperm, w);
-      DSKI_HIP(hipGetLastError());
-      return DSKI_OK;
-    };
-    rc = lanczos(D, N, a, leaf, level[a], st);
+  {
+    // leaves: the 1-D factor of every axis
+    std::vector<LanczosJob> jobs(d);
+    for (int a = 0; a < d && rc >= 0; ++a) {
+      LanczosJob& J = jobs[a];
+      J.node = a;
+      J.out = &level[a];
+      J.st = bs.st[a];
+      rc = J.tmp.reserve(sizeof(double) * 4 * (size_t)std::max(n, 1));
+      dski_plan sp = D->sub[a];
+      int* iperm = D->iperm[a];
+      double* u = J.tmp.as<double>();
+      double* y = u + 2 * (size_t)n;
+      J.apply = [=](const double* q, double* w, hipStream_t s) -> dski_status {
+        k_compress<<<pb, kBlock, 0, s>>>(q, n, d, a, sp->perm, u);
+        DSKI_TRY(mvm_tiled<double>(sp, 1, u, 2 * n, y, 2 * n, nullptr, s));
+        k_expand<<<pb, kBlock, 0, s>>>(y, n, d, a, iperm, w);
+        DSKI_HIP(hipGetLastError());
+        return DSKI_OK;
+      };
+    }
+    if (rc >= 0) rc = lanczos_batch(D, N, jobs, bs.hpin);
+    if (rc < 0) (void)bs.join(st);  // nothing in flight before buffers are freed
   }
+  // binary tree: pairs (0,1), (2,3), ... recompressed level by level; an odd
+  // factor moves up unchanged; internal nodes numbered on from d
   int node = d;
   while (rc >= 0 && level.size() > 2) {
-    std::vector<DskipFactor> nxt;
-    for (size_t i = 0; i + 1 < level.size() && rc >= 0; i += 2) {
-      DskipFactor& fa = level[i];
-      DskipFactor& fb = level[i + 1];
-      auto had = [&](const double* q, double* w) -> dski_status {
-        return had_apply<double, double>(D, fa.Q, fa.A, fb.Q, fb.A, N, n, 1, q, N, w, N, 1.0, 0.0, 0.0, nullptr,
-                                         st);
+    const size_t np = level.size() / 2;
+    std::vector<DskipFactor> nxt(np);
+    std::vector<LanczosJob> jobs(np);
+    for (size_t i = 0; i < np; ++i) {
+      LanczosJob& J = jobs[i];
+      J.node = node++;
+      J.out = &nxt[i];
+      J.st = bs.st[i];
+      DskipFactor* fa = &level[2 * i];
+      DskipFactor* fb = &level[2 * i + 1];
+      DevBuf* gram = &J.tmp;
+      J.apply = [=](const double* q, double* w, hipStream_t s) -> dski_status {
+        return had_apply<double, double>(D, *gram, fa->Q, fa->A, fb->Q, fb->A, N, n, 1, q, N, w, N, 1.0, 0.0, 0.0,
+                                         nullptr, s);
       };
-      DskipFactor f;
-      rc = lanczos(D, N, node++, had, f, st);
-      nxt.push_back(f);
     }
+    rc = lanczos_batch(D, N, jobs, bs.hpin);
+    if (rc < 0) (void)bs.join(st);
     if (level.size() % 2) nxt.push_back(level.back());
-    for (size_t i = 0; i + 1 < level.size(); i += 2) {
-      free_factor(level[i]);
-      free_factor(level[i + 1]);
+    for (size_t i = 0; i < np; ++i) {
+      free_factor(level[2 * i]);
+      free_factor(level[2 * i + 1]);
     }
+    if (rc < 0)
+      for (auto& f : nxt) free_factor(f);
     level.swap(nxt);
   }
-  tmp.release();
+  DSKI_TRY(bs.join(st));
   if (rc < 0) {
     for (auto& f : level) free_factor(f);
     return rc;
@@ -837,7 +931,7 @@ dski_status dskip_apply(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, 
   }
   const T *Qa, *Aa, *Qb, *Ab;
   FactorsOf<T>::get(D, &Qa, &Aa, &Qb, &Ab);
-  return had_apply<T, T>(D, Qa, Aa, Qb, Ab, p->N, p->n, R, V, ldv, Y, ldy, ks, nv, ng, pq_partial, st);
+  return had_apply<T, T>(D, D->gram, Qa, Aa, Qb, Ab, p->N, p->n, R, V, ldv, Y, ldy, ks, nv, ng, pq_partial, st);
 }
 
 template <typename T>
