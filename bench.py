@@ -13,7 +13,8 @@ One step = one pass of the whole hot path on resident inputs:
   per-stage timings,
   pivoted Cholesky (rank 50) and the preconditioner,
   block PCG of the 17 columns to 1e-4,
-  mll and its gradient (its own block PCG, SLQ log det, adjoint products).
+  mll and its gradient (its own block PCG, SLQ log det, adjoint products),
+  the same block PCG and mll with FP64 vectors (`f64_vectors`).
 
 Printed: one JSON line.  `value` is the D-SKI MVM throughput in GB/s of
 algorithmic bytes B = 4 (3 N R + 4 m R + 2 n (d + 1)) per product over the
@@ -21,8 +22,9 @@ median product time (`mvm_ms_p10_p90` the spread); `copy_gbs_same_size` the
 rate of a device copy of B bytes; `pcg_s` the block-PCG seconds to 1e-4.
 `roofline` is that of the dominant MVM stage, timed live with events on the
 stream the kernels run on, with the measured traffic of the tuned variant;
-`dskip` a D-SKIP block MVM (8-D ridge workload); `cpu_baseline` the FP64 CPU
-oracle on a bounded sample.
+`dskip` a D-SKIP block MVM and block PCG (8-D ridge workload); `surrogate`
+the learned log det surrogate's evaluation and training costs at this size;
+`cpu_baseline` the FP64 CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -405,17 +407,30 @@ def main(argv=None):
         res = plan.mll_and_grad(y, pc, num_probes=t_probes, seed=SEED, tol=W.tol, max_iter=20000)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
+        # the same solve and mll with FP64 vectors (the solver's storage precision
+        # above the configuration's FP32: fewer iterations to the same tolerance)
+        B64 = B.double()
+        Xs64, iters64, _, _, _ = plan.pcg(B64, pc, tol=W.tol, max_iter=20000)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        res64 = plan.mll_and_grad(y.double(), pc, num_probes=t_probes, seed=SEED, tol=W.tol, max_iter=20000)
+        torch.cuda.synchronize()
+        t6 = time.perf_counter()
         out = None
         if record:
             # true relative residual of the FP64 solutions with the FP64-storage operator
             Bd = B.double()
             Rt = Bd - plan.mvm(Xs)
             true_rel = (Rt.norm(dim=1) / Bd.norm(dim=1)).max().item()
+            Rt64 = Bd - plan.mvm(Xs64)
+            true_rel64 = (Rt64.norm(dim=1) / Bd.norm(dim=1)).max().item()
             out = dict(tune=tune, variants=variants, ms_mvm=ms_mvm, ms_p10=ms_p10, ms_p90=ms_p90, ms_stage=ms_stage,
                        setup_s=t1 - t0, pivchol_s=t2 - t1,
                        pcg_s=t3 - t2, mll_s=t4 - t3, iters=iters, relres=max(relres), status=st,
                        true_rel=true_rel, mll=res["mll"], logdet=res["logdet"],
-                       mll_iters=max(res["iters"]), grad=res["grad"].tolist())
+                       mll_iters=max(res["iters"]), grad=res["grad"].tolist(),
+                       pcg64_s=t5 - t4, iters64=iters64, true_rel64=true_rel64, mll64_s=t6 - t5,
+                       mll64_iters=max(res64["iters"]), mll64=res64["mll"], logdet64=res64["logdet"])
         pc.close()
         plan.close()
         return out
@@ -481,6 +496,12 @@ def main(argv=None):
         "pivchol_s": round(float(np.mean([r["pivchol_s"] for r in recs])), 4),
         "mll_and_grad_s": round(float(np.mean([r["mll_s"] for r in recs])), 4),
         "mll_pcg_iters": int(max(r["mll_iters"] for r in recs)),
+        "f64_vectors": {"pcg_s": round(float(np.mean([r["pcg64_s"] for r in recs])), 4),
+                        "pcg_iters": int(max(max(r["iters64"]) for r in recs)),
+                        "pcg_true_relres": float(max(r["true_rel64"] for r in recs)),
+                        "mll_and_grad_s": round(float(np.mean([r["mll64_s"] for r in recs])), 4),
+                        "mll_pcg_iters": int(max(r["mll64_iters"] for r in recs)),
+                        "mll": recs[-1]["mll64"], "logdet": recs[-1]["logdet64"]},
         "autotune_us": recs[-1]["tune"],
         "variants": recs[-1]["variants"],
         "variants_pinned": pinned is not None,

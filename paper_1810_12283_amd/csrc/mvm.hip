@@ -16,8 +16,6 @@
 #include <cmath>
 #include <vector>
 
-#include <type_traits>
-
 #include "internal.h"
 
 namespace dski {
@@ -71,12 +69,6 @@ __device__ __forceinline__ void scatter_accum(double (&acc)[CR], const double (&
     acc[r] = s;
   }
 }
-
-// Interpolation weights as the scatter uses them: FP32 for FP32 column values
-// (relative change 6e-8, halves the weights' LDS footprint and traffic), FP64
-// otherwise.  Every scatter form rounds the same way, so all give the same bits.
-template <typename T>
-using ScatterW = typename std::conditional<std::is_same<T, float>::value, float, double>::type;
 
 // LDS-staged version: a work-group owns a tile of grid nodes and one chunk of
 // CR columns.  It copies into LDS the weights and the CR column values of every
@@ -233,8 +225,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   // weights point-major, 8 D + 1 doubles per point: lanes reading one point at
   // different stencil offsets hit adjacent banks, different points rarely share one
   constexpr int WS = 8 * D + 1;
-  using WT = ScatterW<T>;
-  __shared__ WT s_w[PMAX * WS];
+  __shared__ double s_w[PMAX * WS];
   __shared__ T s_v[PMAX * CR * (D + 1)];
   __shared__ int s_lcs[TS::max_cells + 1];
   __shared__ int s_cl[PMAX];  // last-axis cell (1-based) of every region point
@@ -282,7 +273,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
           x[r * (D + 1) + b] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
                                       (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
 #pragma unroll
-      for (int a8 = 0; a8 < D * 8; ++a8) s_w[q * WS + a8] = (WT)w[a8];
+      for (int a8 = 0; a8 < D * 8; ++a8) s_w[q * WS + a8] = w[a8];
 #pragma unroll
       for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
       s_cl[q] = cq;
@@ -342,8 +333,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         const int o = j[a] - (a == last ? cl : c[a]) + 1;
-        wv[a] = (double)s_w[q * WS + a * 8 + o];
-        wd[a] = (double)s_w[q * WS + a * 8 + 4 + o];
+        wv[a] = s_w[q * WS + a * 8 + o];
+        wd[a] = s_w[q * WS + a * 8 + 4 + o];
       }
       scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)q * CR * (D + 1));
       ++q;
@@ -371,8 +362,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           const int o = j[a] - ((a == last) ? clast : c[a]) + 1;
-          wv[a] = (double)(WT)wts[(size_t)(a * 8 + o) * n + k];
-          wd[a] = (double)(WT)wts[(size_t)(a * 8 + 4 + o) * n + k];
+          wv[a] = wts[(size_t)(a * 8 + o) * n + k];
+          wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
         }
         T x[CR * (D + 1)];
 #pragma unroll
@@ -388,11 +379,11 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   long long node = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
-#pragma unroll
   // Streaming stores (here, in the FFT and in the gather): the next kernel reads
   // the grid after the kernel boundary has written back and invalidated the
   // XCD L2s anyway, so keeping it in L2 gains nothing (scatter and gather about
   // 0.8 us faster each).
+#pragma unroll
   for (int r = 0; r < CR; ++r)
     if (r < rc) __builtin_nontemporal_store(acc[r], &G[(size_t)(r0 + r) * M + node]);
 }
@@ -486,8 +477,8 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
           for (int a = 0; a < D; ++a) {
             int ca = (a == last) ? cl : c[a];
             int o = j[a] - ca + 1;
-            wv[u][a] = (double)(ScatterW<T>)wts[(size_t)(a * 8 + o) * n + k];
-            wd[u][a] = (double)(ScatterW<T>)wts[(size_t)(a * 8 + 4 + o) * n + k];
+            wv[u][a] = wts[(size_t)(a * 8 + o) * n + k];
+            wd[u][a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
           }
 #pragma unroll
           for (int r = 0; r < CRD; ++r)
