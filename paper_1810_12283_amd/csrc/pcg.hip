@@ -37,6 +37,7 @@ struct PcgScal {
 
 constexpr int kVecChunk = 1024;  // rows per work-group in the streaming vector kernels
 constexpr int kGraphIters = 8;   // PCG iterations per captured HIP graph
+constexpr int kReplaceEvery = 256;  // iterations between residual replacements (FP32 vectors)
 
 // Captured iterations of one solve (side stream, ordering events, graph).
 struct PcgGraph {
@@ -441,6 +442,21 @@ __global__ void k_pcg_restart_scal(const double* __restrict__ rr_part, int nb_r,
   }
 }
 
+// Residual replacement of the columns in `mask` (the active ones): r.r and r.z
+// of the replaced residual for the next iteration (parity par); p, the
+// iteration counts and the active flags stay.
+__global__ void k_pcg_replace_scal(const double* __restrict__ rr_part, int nb_r, const double* __restrict__ rz_part,
+                                   int nb_z, int R, const int* __restrict__ mask, PcgScal s, int par) {
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wv; c < R; c += nw) {
+    double rr = wave_out_sum(rr_part, nb_r, c);
+    double rz = rz_part ? wave_out_sum(rz_part, nb_z, c) : rr;
+    if ((threadIdx.x & 63) != 0 || !mask[c]) continue;
+    s.rr[c] = rr;
+    s.rz[par * R + c] = rz;
+  }
+}
+
 template <typename T>
 __global__ void k_copy_cols_masked(const T* __restrict__ a, T* __restrict__ b, int N, int R,
                                    const int* __restrict__ mask) {
@@ -591,6 +607,28 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
     DSKI_HIP(hipStreamWaitEvent(st, gr.ev1, 0));
     return DSKI_OK;
   };
+  // Residual replacement (FP32 vectors only): every kReplaceEvery iterations the
+  // recurrence residual of the active columns is replaced by b - K~ x (FP64
+  // iterate, FP64-storage operator), z and r.z are recomputed and p is kept, so
+  // that the recurrence cannot drift away from the true residual (which would
+  // otherwise end in a restart that discards the Krylov space).
+  DevBuf repbuf;
+  int last_rep = 0;
+  auto replace = [&]() -> dski_status {
+    DSKI_TRY(repbuf.reserve(sizeof(double) * nr + 64));
+    double* Y = repbuf.as<double>();
+    DSKI_TRY(mvm_tiled<double>(p, R, Xd, N, Y, N, nullptr, st));
+    const int par = it & 1;
+    const int* mask = s.active + par * R;
+    k_true_resid<T><<<nbv, kBlock, 0, st>>>(B, ldb, Y, Rr, N, R, mask, rr_part);
+    DSKI_HIP(hipGetLastError());
+    if (pc) DSKI_TRY(precond_apply_tiled<T>(pc, R, Rr, N, Z, N, rz_part, nullptr, st));
+    k_pcg_replace_scal<<<1, 256, 0, st>>>(rr_part, nbv, pc ? rz_part : nullptr, nbz, R, mask, s, par);
+    DSKI_HIP(hipGetLastError());
+    last_rep = it;
+    return DSKI_OK;
+  };
+  const bool replacing = sizeof(T) == 4 && fixed_iters <= 0;
   auto run = [&]() -> dski_status {
     int check = 1;
     while (it < limit) {
@@ -612,6 +650,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
       }
       if (hflags[0] <= 0) break;
       check = std::min(check * 2, 32);
+      if (replacing && it - last_rep >= kReplaceEvery) DSKI_TRY(replace());
     }
     return DSKI_OK;
   };
