@@ -26,6 +26,16 @@ __global__ void k_fill_pm1(float* __restrict__ out, size_t len, uint64_t seed) {
   }
 }
 
+__global__ void k_fill_pm1_d(double* __restrict__ out, size_t len, uint64_t seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[i] = (z >> 63) ? -0.5 : 0.5;
+  }
+}
+
 template <class F>
 static dski_status time_us(F&& fn, int reps, hipStream_t st, double* us) {
   hipEvent_t a, b;
@@ -77,6 +87,25 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
     if (t[v] < t[best_s]) best_s = v;
   }
   p->scatter_variant = best_s;
+  // the same forms with FP64 column values (their column chunks differ, and so
+  // may the fastest form); not reported, kept for the FP64 MVMs
+  if (p->kind == 0) {
+    DevBuf buf64;
+    DSKI_TRY(buf64.reserve(sizeof(double) * nv + 64));
+    double* V64 = buf64.as<double>();
+    k_fill_pm1_d<<<1024, 256, 0, st>>>(V64, nv, 12345);
+    DSKI_HIP(hipGetLastError());
+    int best64 = 0;
+    double t64[kScatterVariants] = {0};
+    for (int v = 0; v < kScatterVariants; ++v) {
+      p->scatter_variant64 = v;
+      DSKI_TRY(time_us([&]() { return scatter<double>(p, R, V64, N, G, st); }, reps, st, &t64[v]));
+      if (t64[v] < t64[best64]) best64 = v;
+    }
+    p->scatter_variant64 = best64;
+    DSKI_HIP(hipStreamSynchronize(st));
+    buf64.release();
+  }
   // gather: columns per thread (on the scattered grid; writes into the second half of V)
   int best_g = 0;
   if (p->kind == 0) {
@@ -122,6 +151,7 @@ extern "C" dski_status dski_set_variants(dski_plan p, int scatter_variant, int g
     return DSKI_EINVAL;
   }
   p->scatter_variant = scatter_variant;
+  p->scatter_variant64 = scatter_variant;
   p->gather_variant = gather_variant;
   return DSKI_OK;
 }

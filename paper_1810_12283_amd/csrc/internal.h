@@ -141,6 +141,7 @@ struct dski_plan_s {
   // kernel variants chosen by dski_autotune (defaults: the LDS-tiled kernels)
   int scatter_variant = 0;     // 0 LDS node tiles, 1 direct 1 column/thread, 2 direct 2 columns/thread,
                                // 3 / 4 / 5 LDS node tiles with 1.5 / 2 / 5 times the columns per work-group
+  int scatter_variant64 = 0;   // the same choice for FP64 column values (tuned separately)
   int gather_variant = 0;      // columns per gather thread: 0 -> 2, 1 -> 1, 2 -> 4 (3-D: always 1)
   int use_graph = 1;           // PCG bursts replayed from a captured HIP graph
   int kuu_variant[DSKI_MAXD] = {0, 0, 0};  // per axis: 0 FFT, 1 dense matrix-core product

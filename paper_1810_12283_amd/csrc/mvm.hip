@@ -388,12 +388,13 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
     if (r < rc) __builtin_nontemporal_store(acc[r], &G[(size_t)(r0 + r) * M + node]);
 }
 
-// Columns per work-group of the LDS-tiled scatter: a base chunk (4 FP32 or 2
-// FP64 columns in 1-D and 2-D, half that in 3-D) times 1, 1.5, 2 or 5; wider
-// chunks mean fewer work-groups, each staging its region once for more columns.
+// Columns per work-group of the LDS-tiled scatter: a base chunk (4 columns in
+// 1-D and 2-D; 2 FP32 or 1 FP64 in 3-D) times 1, 1.5, 2 or 5; wider chunks mean
+// fewer work-groups, each staging its region once for more columns.  FP32 and
+// FP64 column values are tuned separately.
 template <int D, typename T, int WIDTH>
 constexpr int scatter_cr() {
-  constexpr int base = (sizeof(T) == 4 && D <= 2) ? 4 : (D <= 2 ? 2 : (sizeof(T) == 4 ? 2 : 1));
+  constexpr int base = D <= 2 ? 4 : (sizeof(T) == 4 ? 2 : 1);
   constexpr int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : (WIDTH == 2 ? 2 * base : 5 * base));
   return D == 3 && cr > 3 ? 3 : cr;  // 3-D: the region tables leave room for 3 columns
 }
@@ -514,7 +515,7 @@ static void launch_scatter_direct(dski_plan p, int R, const T* V, int ldv, doubl
 
 template <int D, typename T>
 static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
-  switch (p->scatter_variant) {
+  switch (sizeof(T) == 8 ? p->scatter_variant64 : p->scatter_variant) {
     case 1: launch_scatter_direct<D, 1, T>(p, R, V, ldv, G, st); break;
     case 2: launch_scatter_direct<D, 2, T>(p, R, V, ldv, G, st); break;
     case 3: launch_scatter<D, T, 1>(p, R, V, ldv, G, st); break;
@@ -566,7 +567,7 @@ static dski_status build_tiles(dski_plan p, hipStream_t st) {
   // Most region points in tiles too full for LDS staging (256 points; dense
   // 1-D grids with many points per cell): the cache-direct form is the default;
   // the tuner may still pick another form (all give identical results).
-  if (2 * over > slots) p->scatter_variant = 1;
+  if (2 * over > slots) p->scatter_variant = p->scatter_variant64 = 1;
   if (slots > (1ll << 31) - 1) {
     set_error("scatter region tables too large");
     return DSKI_ENOTSUP;
