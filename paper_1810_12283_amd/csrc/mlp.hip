@@ -233,13 +233,26 @@ __global__ void k_mlp_sum_chunks(const double* __restrict__ part, int nchunk, in
   out[f] = (float)s;
 }
 
-// column sums over row ranges: out[j][l] = sum_{b < B} M[(j * B + b) * H + l], j < nj (FP64)
-__global__ void k_mlp_colsum(const float* __restrict__ Mx, int B, int H, double* __restrict__ out) {
-  const int j = blockIdx.x, l = threadIdx.x;
-  if (l >= H) return;
-  double s = 0.0;
-  for (int b = 0; b < B; ++b) s += (double)Mx[((size_t)j * B + b) * H + l];
-  out[(size_t)j * H + l] = s;
+// column sums over row ranges: out[j][l] = sum_{b < B} M[(j * B + b) * H + l], j < nj (FP64).
+// One work-group per j of S * H threads: slice s adds rows s, s + S, ... in
+// order (eight loads in flight), then the S slices are added in order.
+__global__ __launch_bounds__(1024) void k_mlp_colsum(const float* __restrict__ Mx, int B, int H,
+                                                     double* __restrict__ out) {
+  __shared__ double red[1024];
+  const int j = blockIdx.x;
+  const int S = blockDim.x / H;
+  const int l = threadIdx.x % H, sl = threadIdx.x / H;
+  double acc = 0.0;
+  const float* col = Mx + (size_t)j * B * H + l;
+#pragma unroll 8
+  for (int b = sl; b < B; b += S) acc += (double)col[(size_t)b * H];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < H) {
+    double t = 0.0;
+    for (int q = 0; q < S; ++q) t += red[q * H + threadIdx.x];
+    out[(size_t)j * H + threadIdx.x] = t;
+  }
 }
 
 __global__ void k_mlp_loss(const double* __restrict__ lp, int B, double* __restrict__ out) {
@@ -429,8 +442,9 @@ dski_status mlp_backward(dski_mlp net, int B, const float* X, const float* t, co
   // dW1 = D1[0:B]^T X  (value rows only); tangent rows add their column sums below
   const size_t chB = ((size_t)B + nchunk - 1) / nchunk;
   k_mlp_gemm_tn<<<dim3(H, nchunk), 128, 0, st>>>(w.D1, H, X, F, (size_t)B, H, F, chB, pW1);
-  k_mlp_colsum<<<J + 1, 128, 0, st>>>(w.D1, B, H, cs);
-  k_mlp_colsum<<<1, 128, 0, st>>>(w.D2, B, H, cs2);
+  const int cst = (1024 / H) * H;
+  k_mlp_colsum<<<J + 1, cst, 0, st>>>(w.D1, B, H, cs);
+  k_mlp_colsum<<<1, cst, 0, st>>>(w.D2, B, H, cs2);
   k_mlp_loss<<<1, 256, 0, st>>>(lp, B, lsum);
   DSKI_HIP(hipGetLastError());
   // assemble the packed gradient (FP32)
