@@ -169,10 +169,13 @@ dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int
  * K_UU variants agree up to rounding.  times_host (15 entries, may be NULL)
  * receives the measured microseconds: scatter (6), gather (3), then FFT and
  * dense for axes 0, 1, 2 (all 0 for a D-SKIP plan; dense is -1 on an axis
- * longer than 448 nodes, which has no dense form).  1 <= R <= 32. */
+ * longer than 448 nodes, which has no dense form).  The scatter forms are
+ * timed once more with FP64 column values (their column chunks differ); that
+ * choice, not reported, serves the FP64 MVMs and solvers.  1 <= R <= 32. */
 dski_status dski_autotune(dski_plan plan, int R, double* times_host, dski_stream stream);
 
-/* Select the scatter (0..5) and gather (0..2) variants directly. */
+/* Select the scatter (0..5, for FP32 and FP64 column values alike) and gather
+ * (0..2) variants directly. */
 dski_status dski_set_variants(dski_plan plan, int scatter_variant, int gather_variant);
 
 /* K_UU factor of one axis: 0 circulant FFT, 1 dense Toeplitz product on the
