@@ -379,10 +379,11 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   long long node = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
-  // Streaming stores (here, in the FFT and in the gather): the next kernel reads
-  // the grid after the kernel boundary has written back and invalidated the
-  // XCD L2s anyway, so keeping it in L2 gains nothing (scatter and gather about
-  // 0.8 us faster each).
+  // Streaming stores (here and in the gather): the next kernel reads the grid
+  // after the kernel boundary has written back and invalidated the XCD L2s
+  // anyway, so keeping it in L2 gains nothing (scatter and gather about 0.8 us
+  // faster each).  The FFT keeps ordinary stores: streaming ones made K_UU
+  // slower on the 632^2 and 1000^2 grids and no faster on 200^2.
 #pragma unroll
   for (int r = 0; r < CR; ++r)
     if (r < rc) __builtin_nontemporal_store(acc[r], &G[(size_t)(r0 + r) * M + node]);
@@ -858,8 +859,8 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
     for (int e = 0; e < E; ++e) {
       const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
       if (pos < m) {
-        if (va) __builtin_nontemporal_store(v[e].x, &A[pos]);
-        if (vb) __builtin_nontemporal_store(v[e].y, &A[m + pos]);
+        if (va) A[pos] = v[e].x;
+        if (vb) A[m + pos] = v[e].y;
       }
     }
   } else {
@@ -874,9 +875,8 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
       const int l = f & (S::NL - 1);
       const long long b = s_base[l];
       if (b >= 0)
-        __builtin_nontemporal_store(
-            reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * S::LP + padi(f >> S::LGNL)])[l & 1],
-            &G[b + (long long)(f >> S::LGNL) * inner]);
+        G[b + (long long)(f >> S::LGNL) * inner] =
+            reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * S::LP + padi(f >> S::LGNL)])[l & 1];
     }
   }
 }
