@@ -781,7 +781,8 @@ static dski_status lanczos_batch(DskipData* D, int N, std::vector<LanczosJob>& j
 }
 
 // Streams for the independent Lanczos runs of the build (default priority),
-// ordered after the caller's stream at creation and before it on release.
+// ordered after the caller's stream at creation and drained before the build
+// continues on the caller's stream.
 struct BuildStreams {
   std::vector<hipStream_t> st;
   hipEvent_t ev = nullptr;
@@ -803,9 +804,9 @@ struct BuildStreams {
     DSKI_HIP(hipHostMalloc(&hpin, sizeof(double) * 2 * (size_t)std::max(n, 1), hipHostMallocDefault));
     return DSKI_OK;
   }
-  dski_status join(hipStream_t caller) {
+  // every stream drained (the caller's stream then follows on the host side)
+  dski_status join() {
     for (auto s : st) DSKI_HIP(hipStreamSynchronize(s));
-    (void)caller;
     return DSKI_OK;
   }
 };
@@ -848,7 +849,7 @@ static dski_status dskip_build(dski_plan p, hipStream_t st) {
       };
     }
     if (rc >= 0) rc = lanczos_batch(D, N, jobs, bs.hpin);
-    if (rc < 0) (void)bs.join(st);  // nothing in flight before buffers are freed
+    if (rc < 0) (void)bs.join();  // nothing in flight before buffers are freed
   }
   // binary tree: pairs (0,1), (2,3), ... recompressed level by level; an odd
   // factor moves up unchanged; internal nodes numbered on from d
@@ -871,7 +872,7 @@ static dski_status dskip_build(dski_plan p, hipStream_t st) {
       };
     }
     rc = lanczos_batch(D, N, jobs, bs.hpin);
-    if (rc < 0) (void)bs.join(st);
+    if (rc < 0) (void)bs.join();
     if (level.size() % 2) nxt.push_back(level.back());
     for (size_t i = 0; i < np; ++i) {
       free_factor(level[2 * i]);
@@ -881,7 +882,7 @@ static dski_status dskip_build(dski_plan p, hipStream_t st) {
       for (auto& f : nxt) free_factor(f);
     level.swap(nxt);
   }
-  DSKI_TRY(bs.join(st));
+  DSKI_TRY(bs.join());
   if (rc < 0) {
     for (auto& f : level) free_factor(f);
     return rc;
