@@ -624,8 +624,9 @@ static dski_status had_apply_rp(DevBuf& gram, const TF* Qa, const TF* Aa, const 
     DSKI_HIP(hipGetLastError());
     k_had_reduce_frag<RP><<<(unsigned)((nout + 63) / 64), 256, 0, st>>>(part, nchunk, R, Cf);
     DSKI_HIP(hipGetLastError());
-    k_had_apply_mfma<RP, MG><<<dim3((N + 255) / 256, ng1), 256, 0, st>>>(Aa, Ab, N, n, Cf, R, V, ldv, Y, ldy, ks,
-                                                                          nv, ng, pq);
+    constexpr int AG = RP == 32 ? 3 : 1;  // columns per apply wavefront: two wavefronts per SIMD
+    k_had_apply_mfma<RP, AG><<<dim3((N + 255) / 256, (R + AG - 1) / AG), 256, 0, st>>>(Aa, Ab, N, n, Cf, R, V, ldv,
+                                                                                      Y, ldy, ks, nv, ng, pq);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   } else {
