@@ -1,0 +1,62 @@
+"""Pins of the oracle's posterior mean at test points (Sec. 1, O(1) prediction;
+mean = K_{*X} alpha with alpha = K~^{-1} y).  Not the formula retyped: the
+identity at the training points, the exact derivative-SE posterior mean as the
+grid is refined, and finite differences of the predicted value."""
+import numpy as np
+
+from oracle import dski as odski, predict
+from oracle.kernels import noise_diag
+
+
+def small_problem(n=40, d=2, m=20, seed=5):
+    r = np.random.default_rng(seed)
+    X = r.uniform(0.0, 1.0, (n, d))
+    y = r.standard_normal(n * (d + 1))
+    le, ls, lf, lg = np.log([0.3] * d), 0.2, np.log(0.05), np.log(0.1)
+    op = odski.DSKI(X, [m] * d, np.zeros(d), np.ones(d), le, ls, lf, lg)
+    return X, y, op, (np.exp(le), np.exp(ls), np.exp(lf), np.exp(lg))
+
+
+def test_mean_at_training_points_is_y_minus_noise_times_alpha():
+    """At the training points S_* = S, so S K_UU S^T alpha = (K~ - D) alpha = y - D alpha."""
+    X, y, op, _ = small_problem()
+    alpha = np.linalg.solve(op.dense(), y)
+    mu = predict.predict_mean(op, predict.grid_vector(op, alpha), X)
+    want = (y - op.Dn * alpha).reshape(X.shape[1] + 1, -1).T
+    assert np.abs(mu - want).max() <= 1e-10 * np.abs(want).max()
+
+
+def test_dski_mean_tends_to_the_exact_derivative_se_mean():
+    """With the grid refined, the D-SKI posterior mean (value and gradient) at
+    test points approaches the exact derivative-SE one (cubic interpolation
+    error O(h^3) in the kernel)."""
+    r = np.random.default_rng(11)
+    n, d = 30, 2
+    X = r.uniform(0.0, 1.0, (n, d))
+    y = r.standard_normal(n * (d + 1))
+    Xs = r.uniform(0.05, 0.95, (25, d))
+    ell, s, sf, sg = 0.3, np.exp(0.2), 0.05, 0.1
+    exact = predict.exact_predict_mean(X, y, Xs, [ell] * d, s, sf, sg)
+    errs = []
+    for m in (30, 60, 120):
+        op = odski.DSKI(X, [m] * d, np.zeros(d), np.ones(d), np.log([ell] * d), 0.2, np.log(sf), np.log(sg))
+        alpha = np.linalg.solve(op.dense(), y)
+        mu = predict.predict_mean(op, predict.grid_vector(op, alpha), Xs)
+        errs.append(np.abs(mu - exact).max() / np.abs(exact).max())
+    assert errs[2] < 5e-3  # measured 9.4e-2, 8.0e-3, 2.1e-3
+    assert errs[2] < errs[1] < errs[0]
+
+
+def test_gradient_rows_are_derivatives_of_the_value_row():
+    X, y, op, _ = small_problem()
+    alpha = np.linalg.solve(op.dense(), y)
+    g = predict.grid_vector(op, alpha)
+    r = np.random.default_rng(2)
+    Xs = r.uniform(0.1, 0.9, (10, 2))
+    mu = predict.predict_mean(op, g, Xs)
+    h = 1e-6
+    for p in range(2):
+        e = np.zeros(2)
+        e[p] = h
+        fd = (predict.predict_mean(op, g, Xs + e)[:, 0] - predict.predict_mean(op, g, Xs - e)[:, 0]) / (2 * h)
+        assert np.abs(fd - mu[:, 1 + p]).max() <= 1e-6 * np.abs(mu[:, 1 + p]).max()
