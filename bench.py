@@ -24,6 +24,7 @@ rate of a device copy of B bytes; `pcg_s` the block-PCG seconds to 1e-4.
 stream the kernels run on, with the measured traffic of the tuned variant;
 `dskip` a D-SKIP block MVM and block PCG (8-D ridge workload); `surrogate`
 the learned log det surrogate's evaluation and training costs at this size;
+`predict` the posterior mean at 1,000,000 test points;
 `cpu_baseline` the FP64 CPU oracle on a bounded sample.
 """
 from __future__ import annotations
@@ -192,6 +193,27 @@ def surrogate_block(W, y, rank, stream, reps=20):
             "slq_logdet_grad_s": round(t1 - t0, 4), "data_fit_grad_s": round(t2 - t1, 4),
             "mlp_train_step_ms": round(train_ms, 4), "mlp_infer_ms": round(infer_ms, 4),
             "eval_speedup": round((t1 - t0) / (t2 - t1 + infer_ms * 1e-3), 3)}
+
+
+def predict_block(W, stream, npts=1_000_000, reps=20):
+    """Posterior mean at test points on the terrain workload: the grid vector
+    g = K_UU S^T alpha (one scatter and the K_UU factors) and the stencil means
+    [f, grad f] of 1,000,000 uniform test points (16 grid reads each)."""
+    import numpy as np
+    import torch
+    from paper_1810_12283_amd import dski
+    plan = dski.Plan(torch.tensor(W.X, dtype=torch.float64, device="cuda"), W.grid_m, W.lo, W.hi)
+    plan.set_hypers(*W.hypers())
+    alpha = torch.tensor(np.random.default_rng(5).standard_normal(W.N), device="cuda")
+    r = np.random.default_rng(6)
+    Xs = torch.tensor(r.uniform(0.0, 1.0, (npts, W.d)), device="cuda")
+    g_ms = _events_stats(lambda: plan.predict_grid(alpha), reps, stream)[0]
+    g = plan.predict_grid(alpha)
+    p_ms = _events_stats(lambda: plan.predict(g, Xs), reps, stream)[0]
+    plan.close()
+    return {"workload": f"terrain n={W.n} grid={W.grid_m[0]}x{W.grid_m[1]}, {npts} test points",
+            "grid_vector_ms": round(g_ms, 4), "predict_ms": round(p_ms, 4),
+            "test_points_per_s": round(npts / (p_ms * 1e-3), 1)}
 
 
 def mvm_bytes(N, M, n, d, R):
@@ -513,6 +535,7 @@ def main(argv=None):
     }
     line["dskip"] = dskip_block(R, stream)
     line["surrogate"] = surrogate_block(W, y, W.rank, stream)
+    line["predict"] = predict_block(W, stream)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, R)
     print(json.dumps(line), flush=True)

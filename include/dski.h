@@ -136,6 +136,23 @@ dski_status dski_mvm_dtheta(dski_plan plan, int which, int R, const float* V, in
 dski_status dski_mvm_dtheta_f64(dski_plan plan, int which, int R, const double* V, int ldv,
                                 double* Y, int ldy, dski_stream stream);
 
+/* Posterior mean at test points (Sec. 1: O(1) prediction per test point).  With
+ * alpha = K~^{-1} y (from pcg_solve_f64 or pcg_solve), the posterior mean of
+ * the test observations [f(x*); grad f(x*)] is K_{*X} alpha, which under D-SKI
+ * (Sec. 3.1) is S_* K_UU S^T alpha.
+ * dski_predict_grid forms the grid vector g = K_UU S^T alpha once: alpha is an
+ *   N-vector in user order (device, FP64, block-major as every N-vector), g
+ *   receives M = prod m_p doubles (device, grid in C order).
+ * dski_predict interpolates g at n_test points X_test (device, n_test x d
+ *   row-major, FP64; each inside the interpolation box of the plan) on their
+ *   cubic stencils: out (device, n_test x (d + 1) row-major) receives per
+ *   point [mean f, mean df/dx_1, ..., mean df/dx_d].  It synchronizes `stream`;
+ *   DSKI_EINVAL if a test point lies outside the box (out then holds the
+ *   clamped points' values).  D-SKI plans only (DSKI_ENOTSUP for D-SKIP). */
+dski_status dski_predict_grid(dski_plan plan, const double* alpha, double* g, dski_stream stream);
+dski_status dski_predict(dski_plan plan, const double* g, int n_test, const double* X_test, double* out,
+                         dski_stream stream);
+
 /* Tile order: the internal point order (sorted by interpolation cell) that the
  * solvers use.  dir = +1: user -> tile, dir = -1: tile -> user.  perm_host (n
  * ints, may be NULL) receives, for tile position k, the user index. */

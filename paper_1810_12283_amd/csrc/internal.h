@@ -84,6 +84,20 @@ __host__ __device__ constexpr int fft_tw_size(int lg) { return fft_tw_offset(lg,
 constexpr int kFftMaxLog2 = 11;  // L <= 2048, m <= 1024 per axis
 constexpr int kDenseMaxM = 448;  // largest axis for the dense matrix-core Toeplitz product
 
+// Keys cubic-convolution weights (a = -1/2) of the four stencil nodes i - 1 ..
+// i + 2 at offset t in [0, 1] of cell i, and their derivatives times 1 / h.
+__device__ __forceinline__ void keys_weights(double t, double ih, double* w, double* dw) {
+  const double t2 = t * t, t3 = t2 * t;
+  w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+  w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+  w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+  w[3] = 0.5 * (t3 - t2);
+  dw[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0) * ih;
+  dw[1] = 0.5 * (9.0 * t2 - 10.0 * t) * ih;
+  dw[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0) * ih;
+  dw[3] = 0.5 * (3.0 * t2 - 2.0 * t) * ih;
+}
+
 // Per-axis geometry of the grid and its circulant embedding.
 struct Axis {
   int m = 0;          // grid nodes

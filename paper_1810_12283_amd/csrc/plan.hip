@@ -144,17 +144,13 @@ __global__ void k_weights(const double* __restrict__ toff, int n, int d, const d
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   for (int a = 0; a < d; ++a) {
-    double t = toff[(size_t)a * n + k];
-    double t2 = t * t, t3 = t2 * t, ih = invh[a];
-    double* w = wts + (size_t)a * 8 * n + k;
-    w[0 * (size_t)n] = 0.5 * (-t3 + 2.0 * t2 - t);
-    w[1 * (size_t)n] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-    w[2 * (size_t)n] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-    w[3 * (size_t)n] = 0.5 * (t3 - t2);
-    w[4 * (size_t)n] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0) * ih;
-    w[5 * (size_t)n] = 0.5 * (9.0 * t2 - 10.0 * t) * ih;
-    w[6 * (size_t)n] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0) * ih;
-    w[7 * (size_t)n] = 0.5 * (3.0 * t2 - 2.0 * t) * ih;
+    double w[4], dw[4];
+    keys_weights(toff[(size_t)a * n + k], invh[a], w, dw);
+    double* o = wts + (size_t)a * 8 * n + k;
+    for (int q = 0; q < 4; ++q) {
+      o[q * (size_t)n] = w[q];
+      o[(4 + q) * (size_t)n] = dw[q];
+    }
   }
 }
 

@@ -49,6 +49,8 @@ _SIGS = {
     "dski_set_hypers": (C.c_int, [vp, dp, C.c_double, C.c_double, C.c_double, vp]),
     "dski_mvm": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_mvm_dtheta": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_predict_grid": (C.c_int, [vp, vp, vp, vp]),
+    "dski_predict": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
     "dski_permute": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_tile_order": (C.c_int, [vp, ip]),
     "dski_mvm_tiled": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -231,6 +233,27 @@ class Plan:
         _check(lib().dski_mvm_stage(self._h, int(stage), V.shape[0], _dptr(V), self.N, yp, self.N,
                                     _stream(stream)), "dski_mvm_stage")
         return Y
+
+    def predict_grid(self, alpha: torch.Tensor, stream=None) -> torch.Tensor:
+        """Grid vector g = K_UU S^T alpha (M doubles) for the posterior mean;
+        alpha = K~^{-1} y, an FP64 CUDA N-vector in user order."""
+        if not alpha.is_cuda or alpha.dtype != torch.float64 or alpha.numel() != self.N:
+            raise TypeError("alpha must be a CUDA float64 tensor with N entries")
+        alpha = alpha.contiguous()
+        g = torch.empty(int(np.prod(self.grid_m)), dtype=torch.float64, device=alpha.device)
+        _check(lib().dski_predict_grid(self._h, _dptr(alpha), _dptr(g), _stream(stream)), "dski_predict_grid")
+        return g
+
+    def predict(self, g: torch.Tensor, Xs: torch.Tensor, stream=None) -> torch.Tensor:
+        """Posterior means at the test points Xs (n* x d, FP64, CUDA): n* x (d + 1),
+        column 0 the value, column 1 + p the derivative along axis p."""
+        if not Xs.is_cuda or Xs.dtype != torch.float64 or Xs.dim() != 2 or Xs.shape[1] != self.d:
+            raise TypeError("Xs must be a CUDA float64 tensor of shape (n*, d)")
+        Xs = Xs.contiguous()
+        out = torch.empty((Xs.shape[0], self.d + 1), dtype=torch.float64, device=Xs.device)
+        _check(lib().dski_predict(self._h, _dptr(g.contiguous()), Xs.shape[0], _dptr(Xs), _dptr(out),
+                                  _stream(stream)), "dski_predict")
+        return out
 
     def mvm_dtheta(self, which: int, V: torch.Tensor, stream=None) -> torch.Tensor:
         V = _block(V, self.N, "V")

@@ -1,0 +1,75 @@
+"""GPU parity of the posterior mean at test points (Sec. 1, O(1) prediction)
+against the FP64 oracle: grid vector g = K_UU S^T alpha and the stencil means
+[f, grad f] at test points, on the small 2-D and 3-D workloads (ragged grids
+included), at the full terrain size on sampled test points, at the training
+points (the identity mean = K alpha), and the out-of-box error."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import predict as opred
+from tests.gpu_common import SEED, make, need_gpu, say, small_workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _alpha(N, seed):
+    return np.random.default_rng(seed).standard_normal(N)
+
+
+def _test_points(W, k, seed):
+    r = np.random.default_rng(seed)
+    lo, hi = np.asarray(W.lo, dtype=np.float64), np.asarray(W.hi, dtype=np.float64)
+    return lo + (hi - lo) * r.uniform(0.0, 1.0, (k, len(lo)))
+
+
+@pytest.mark.parametrize("name", [nm for nm, _ in small_workloads()])
+def test_predict_matches_oracle(name):
+    W = dict(small_workloads())[name]
+    say("predict", name, W.n, W.grid_m)
+    plan, op = make(W)
+    alpha = _alpha(op.N, SEED)
+    g = plan.predict_grid(torch.tensor(alpha, device="cuda"))
+    g_ref = opred.grid_vector(op, alpha)
+    eg = np.abs(g.cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
+    Xs = _test_points(W, 777, SEED + 1)
+    mu = plan.predict(g, torch.tensor(Xs, device="cuda")).cpu().numpy()
+    ref = opred.predict_mean(op, g_ref, Xs)
+    em = np.abs(mu - ref).max() / np.abs(ref).max()
+    # at the training points the mean is the noise-free K alpha
+    mt = plan.predict(g, torch.tensor(W.X, device="cuda")).cpu().numpy()
+    kt = op.matvec_K(alpha).reshape(W.d + 1, -1).T
+    et = np.abs(mt - kt).max() / np.abs(kt).max()
+    say("  grid vector", eg, "test means", em, "training means", et)
+    assert eg < 1e-11 and em < 1e-11 and et < 1e-11
+
+
+def test_predict_full_terrain_sampled():
+    """Terrain size (n = 20,000, 200 x 200 grid): 200,000 test points on the
+    GPU, checked against the oracle on a sample of 2,000 of them."""
+    W = workloads.terrain()
+    say("predict terrain", W.n, W.grid_m)
+    plan, op = make(W)
+    alpha = _alpha(op.N, SEED + 2)
+    g = plan.predict_grid(torch.tensor(alpha, device="cuda"))
+    Xs = _test_points(W, 200000, SEED + 3)
+    mu = plan.predict(g, torch.tensor(Xs, device="cuda")).cpu().numpy()
+    idx = np.random.default_rng(4).choice(len(Xs), 2000, replace=False)
+    ref = opred.predict_mean(op, opred.grid_vector(op, alpha), Xs[idx])
+    e = np.abs(mu[idx] - ref).max() / np.abs(ref).max()
+    say("  sampled rel err", e)
+    assert e < 1e-11
+
+
+def test_predict_rejects_points_outside_the_box():
+    dski = need_gpu()
+    W = workloads.small2d()
+    plan, op = make(W)
+    g = plan.predict_grid(torch.tensor(_alpha(op.N, 1), device="cuda"))
+    Xs = _test_points(W, 10, 2)
+    Xs[3, 0] = np.asarray(W.hi)[0] + 0.5
+    with pytest.raises(dski.DSKIError) as e:
+        plan.predict(g, torch.tensor(Xs, device="cuda"))
+    assert e.value.status == -1  # DSKI_EINVAL
+    assert plan.predict(g, torch.zeros((0, W.d), dtype=torch.float64, device="cuda")).shape == (0, W.d + 1)
