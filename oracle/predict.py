@@ -11,15 +11,28 @@ derivative interpolation rows of the test points, so the grid vector
 g = K_UU S^T alpha is formed once and each test point interpolates it on its
 cubic stencil: mean = S_* g (4^d nodes per test point, whatever n).
 
-Readings (the paper states the complexity, not the steps):
+Predictive variance (Sec. 4.3, first approach): with the pivoted-Cholesky
+preconditioner M = D + L L^T in place of K~,
+    v^(x) = k(x, x) - K_{xX} M^{-1} K_{Xx}
+for the value f(x) at a test point (the paper writes the single-noise QR form
+sigma^{-2}(||K_{Xx}||^2 - ||Q_1^T K_{Xx}||^2) of the same quantity).
+
+Readings (the paper states the complexity and the formula, not the steps):
 * the mean of every test observation, value and all d partial derivatives,
   is returned, as the training observations are value and gradient;
-* test points must lie in the interpolation box of the training grid.
+* test points must lie in the interpolation box of the training grid;
+* k(x, x) and K_{Xx} are those of the D-SKI kernel (w_x^T K_UU w_x and
+  S K_UU w_x, w_x the test point's value stencil), so that v^ is the variance
+  of the approximate model;
+* the paper calls v^ a small overestimate of v; since pivoted Cholesky gives
+  L L^T <= K, M <= K~ and v^ <= v: v^ underestimates v, and equals it when L
+  has full rank (both checked by the pins).
 """
 import numpy as np
 
 from . import interp
 from .kernels import dse_dense, noise_diag
+from .precond import Precond
 
 
 def grid_vector(op, alpha):
@@ -46,3 +59,27 @@ def exact_predict_mean(X, y, Xs, ell, s, sigma_f, sigma_g):
     alpha = np.linalg.solve(K, y)
     Ks = dse_dense(np.asarray(Xs, dtype=np.float64), ell, s, X2=X)
     return (Ks @ alpha).reshape(d + 1, -1).T
+
+
+def prior_cov(op, Xs):
+    """(k(x, x) per test point, K_{Xx} as N x n*) of the D-SKI kernel: with w_x
+    the value stencil, w_x^T K_UU w_x and S K_UU w_x."""
+    Xs = np.asarray(Xs, dtype=np.float64)
+    ns = Xs.shape[0]
+    Wv = interp.interp_matrices(Xs, op.grid)[:ns]            # value stencils, n* x m
+    H = np.asarray(op.kuu_apply(Wv.T.toarray()))              # K_UU w_x, m x n*
+    kxx = np.asarray((Wv.multiply(H.T)).sum(axis=1)).ravel()
+    return kxx, op.S @ H
+
+
+def predictive_variance(op, L, Xs):
+    """v^(x) = k(x, x) - K_{xX} M^{-1} K_{Xx} of f(x) at each test point, with
+    M = D + L L^T (L: N x k pivoted-Cholesky factor of the noise-free K)."""
+    kxx, Kx = prior_cov(op, Xs)
+    return kxx - np.sum(Kx * Precond(L, op.Dn).solve(Kx), axis=0)
+
+
+def exact_variance(op, Xs):
+    """v(x) = k(x, x) - K_{xX} K~^{-1} K_{Xx} with the dense D-SKI matrix."""
+    kxx, Kx = prior_cov(op, Xs)
+    return kxx - np.sum(Kx * np.linalg.solve(op.dense(), Kx), axis=0)

@@ -5,7 +5,7 @@ grid is refined, and finite differences of the predicted value."""
 import numpy as np
 
 from oracle import dski as odski, predict
-from oracle.kernels import noise_diag
+from oracle.kernels import dse_dense, noise_diag
 
 
 def small_problem(n=40, d=2, m=20, seed=5):
@@ -60,3 +60,45 @@ def test_gradient_rows_are_derivatives_of_the_value_row():
         e[p] = h
         fd = (predict.predict_mean(op, g, Xs + e)[:, 0] - predict.predict_mean(op, g, Xs - e)[:, 0]) / (2 * h)
         assert np.abs(fd - mu[:, 1 + p]).max() <= 1e-6 * np.abs(mu[:, 1 + p]).max()
+
+
+def test_variance_equals_exact_with_full_rank_and_underestimates_otherwise():
+    """v^ uses M = D + L L^T for K~: with a full-rank pivoted Cholesky M = K~ and
+    v^ is the exact D-SKI posterior variance; with rank k < N, L L^T <= K so
+    v^ <= v (the paper's 'overestimate' is read as this inequality's other
+    side); the exact variance itself lies in [0, k(x, x)]."""
+    from oracle import pivchol
+    X, y, op, _ = small_problem(n=30, m=16)
+    r = np.random.default_rng(9)
+    Xs = r.uniform(0.05, 0.95, (12, 2))
+    K = op.dense_K()
+    v = predict.exact_variance(op, Xs)
+    Lf, piv, _ = pivchol.pivoted_cholesky(np.diag(K), lambda i: K[i], op.N, rel_tol=0.0)
+    # full rank up to the numerical rank of K: M = D + L L^T reproduces K~
+    vf = predict.predictive_variance(op, Lf, Xs)
+    assert np.abs(vf - v).max() <= 1e-8 * np.abs(v).max() + 1e-12
+    L5, _, _ = pivchol.pivoted_cholesky(np.diag(K), lambda i: K[i], 5)
+    v5 = predict.predictive_variance(op, L5, Xs)
+    assert (v5 <= v + 1e-12).all()
+    assert (v >= -1e-12).all()
+    kxx, _ = predict.prior_cov(op, Xs)
+    assert (v <= kxx + 1e-12).all()
+
+
+def test_prior_covariances_tend_to_the_exact_derivative_se_ones():
+    """k(x, x) and K_{Xx} of the D-SKI kernel approach the exact derivative-SE
+    covariances of f(x) with the training values and gradients as the grid is
+    refined (App. B entries, cubic interpolation error O(h^3))."""
+    r = np.random.default_rng(12)
+    n, d = 25, 2
+    X = r.uniform(0.0, 1.0, (n, d))
+    Xs = r.uniform(0.05, 0.95, (10, d))
+    ell, ls = 0.3, 0.2
+    ref = dse_dense(Xs, [ell] * d, np.exp(ls), X2=X)[:len(Xs)].T     # N x n*: Cov(obs, f(x*))
+    kref = np.diag(dse_dense(Xs, [ell] * d, np.exp(ls))[:len(Xs), :len(Xs)])
+    errs = []
+    for m in (20, 40, 80):
+        op = odski.DSKI(X, [m] * d, np.zeros(d), np.ones(d), np.log([ell] * d), ls, np.log(0.05), np.log(0.1))
+        kxx, Kx = predict.prior_cov(op, Xs)
+        errs.append(max(np.abs(kxx - kref).max() / kref.max(), np.abs(Kx - ref).max() / np.abs(ref).max()))
+    assert errs[-1] < 2e-3 and errs[2] < errs[1] < errs[0], errs
