@@ -198,7 +198,9 @@ def surrogate_block(W, y, rank, stream, reps=20):
 def predict_block(W, stream, npts=1_000_000, reps=20):
     """Posterior mean at test points on the terrain workload: the grid vector
     g = K_UU S^T alpha (one scatter and the K_UU factors) and the stencil means
-    [f, grad f] of 1,000,000 uniform test points (16 grid reads each)."""
+    [f, grad f] of 1,000,000 uniform test points (16 grid reads each); the
+    pivoted-Cholesky predictive variance (rank 100) of 4,096 of them, 32 per
+    batch (one grid column each: stencil, K_UU, gather, preconditioner solve)."""
     import numpy as np
     import torch
     from paper_1810_12283_amd import dski
@@ -210,10 +212,17 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
     g_ms = _events_stats(lambda: plan.predict_grid(alpha), reps, stream)[0]
     g = plan.predict_grid(alpha)
     p_ms = _events_stats(lambda: plan.predict(g, Xs), reps, stream)[0]
+    nvar = 4096
+    pc = plan.pivchol(100)
+    Xv = Xs[:nvar].contiguous()
+    v_ms = _events_stats(lambda: plan.predict_var(pc, Xv), 5, stream)[0]
+    pc.close()
     plan.close()
     return {"workload": f"terrain n={W.n} grid={W.grid_m[0]}x{W.grid_m[1]}, {npts} test points",
             "grid_vector_ms": round(g_ms, 4), "predict_ms": round(p_ms, 4),
-            "test_points_per_s": round(npts / (p_ms * 1e-3), 1)}
+            "test_points_per_s": round(npts / (p_ms * 1e-3), 1),
+            "variance_rank": 100, "variance_points": nvar, "variance_ms": round(v_ms, 3),
+            "variance_points_per_s": round(nvar / (v_ms * 1e-3), 1)}
 
 
 def mvm_bytes(N, M, n, d, R):

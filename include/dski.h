@@ -153,6 +153,19 @@ dski_status dski_predict_grid(dski_plan plan, const double* alpha, double* g, ds
 dski_status dski_predict(dski_plan plan, const double* g, int n_test, const double* X_test, double* out,
                          dski_stream stream);
 
+/* Predictive variance of f at test points (Sec. 4.3, first approach): the
+ * pivoted-Cholesky preconditioner M = D + L L^T stands in for K~,
+ *   v^(x) = k(x, x) - K_{xX} M^{-1} K_{Xx},
+ * with k(x, x) = w_x^T K_UU w_x and K_{Xx} = S K_UU w_x those of the D-SKI
+ * kernel (w_x the value stencil of x).  Since L L^T <= K, v^ <= v (equality
+ * at full rank).  pc must be built on `plan` (dski_precond_build).  X_test:
+ * device, n_test x d row-major FP64, inside the interpolation box; out:
+ * device, n_test FP64.  Points go through in batches of up to 32 (one grid
+ * column each); the call uses the plan's scratch buffers and synchronizes
+ * `stream`.  DSKI_EINVAL for a point outside the box, DSKI_ENOTSUP for D-SKIP. */
+dski_status dski_predict_var(dski_plan plan, dski_precond pc, int n_test, const double* X_test,
+                             double* out, dski_stream stream);
+
 /* Tile order: the internal point order (sorted by interpolation cell) that the
  * solvers use.  dir = +1: user -> tile, dir = -1: tile -> user.  perm_host (n
  * ints, may be NULL) receives, for tile position k, the user index. */

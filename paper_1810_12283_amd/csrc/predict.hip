@@ -5,7 +5,10 @@
 // scatter and the K_UU factors, as in the MVM) and every test point then
 // interpolates g on its cubic stencil, value and d derivative weights, with
 // 4^d grid reads whatever the number of training points.
+#include <algorithm>
+
 #include "internal.h"
+#include "tskinny.h"
 
 namespace dski {
 
@@ -14,17 +17,13 @@ struct PredGeo {
   double lo[DSKI_MAXD], h[DSKI_MAXD], ih[DSKI_MAXD];
 };
 
-// One thread per test point: cell and offset as for the training points (a
-// point outside the interpolation box sets err), then the stencil sums in
-// FP64; out row u = [mean f, mean d f / d x_1 .. d x_D].
+// Cubic stencil of test point u: value and derivative weights per axis and
+// the first stencil node; a point outside the interpolation box (or not
+// finite) sets err and is clamped into it.
 template <int D>
-__global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, PredGeo geo, int ns,
-                                                 const double* __restrict__ Xs, double* __restrict__ out,
-                                                 int* __restrict__ err) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= ns) return;
-  double w[D][4], dw[D][4];
-  long long c0[D];
+__device__ inline void pred_stencil(const double* __restrict__ Xs, int u, const PredGeo& geo,
+                                    double (&w)[D][4], double (&dw)[D][4], long long (&c0)[D],
+                                    int* __restrict__ err) {
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     double s = (Xs[(size_t)u * D + a] - geo.lo[a]) / geo.h[a];
@@ -38,25 +37,49 @@ __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, P
     keys_weights(t, geo.ih[a], w[a], dw[a]);
     c0[a] = i - 1;
   }
+}
+
+// Grid node and value weight of stencil entry e (axis offsets in base 4, the
+// last axis fastest).
+template <int D>
+__device__ inline long long stencil_node(int e, const PredGeo& geo, const double (&w)[D][4],
+                                         const long long (&c0)[D], int (&o)[D], double& wp) {
+  int rem = e;
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    o[a] = rem & 3;
+    rem >>= 2;
+  }
+  long long node = 0;
+  wp = 1.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    node = node * geo.m[a] + c0[a] + o[a];
+    wp *= w[a][o[a]];
+  }
+  return node;
+}
+
+// One thread per test point: the stencil sums in FP64; out row u =
+// [mean f, mean d f / d x_1 .. d x_D].
+template <int D>
+__global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, PredGeo geo, int ns,
+                                                 const double* __restrict__ Xs, double* __restrict__ out,
+                                                 int* __restrict__ err) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= ns) return;
+  double w[D][4], dw[D][4];
+  long long c0[D];
+  pred_stencil<D>(Xs, u, geo, w, dw, c0, err);
   double acc[D + 1];
 #pragma unroll
   for (int q = 0; q <= D; ++q) acc[q] = 0.0;
   constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
   for (int e = 0; e < NS; ++e) {
     int o[D];
-    int rem = e;
-#pragma unroll
-    for (int a = D - 1; a >= 0; --a) {
-      o[a] = rem & 3;
-      rem >>= 2;
-    }
-    long long node = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) node = node * geo.m[a] + c0[a] + o[a];
+    double wp;
+    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
     const double gv = g[node];
-    double wp = 1.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) wp *= w[a][o[a]];
     acc[0] += wp * gv;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
@@ -69,6 +92,65 @@ __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, P
   }
 #pragma unroll
   for (int q = 0; q <= D; ++q) out[(size_t)u * (D + 1) + q] = acc[q];
+}
+
+// Predictive variance (Sec. 4.3, first approach) of f at a batch of test
+// points, one grid column per point.  k_var_fill writes the value stencil w_x
+// of point r0 + j into column j of G (zeroed before); k_var_kxx reads the same
+// stencil against K_UU w_x to give k(x, x) = w_x^T K_UU w_x; k_var_final
+// subtracts K_{xX} M^{-1} K_{Xx} from its per-block partials (block-major per
+// column, nb blocks).
+template <int D>
+__global__ __launch_bounds__(256) void k_var_fill(PredGeo geo, int r0, int nb_pts, const double* __restrict__ Xs,
+                                                  double* __restrict__ G, long long M, int* __restrict__ err) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nb_pts) return;
+  double w[D][4], dw[D][4];
+  long long c0[D];
+  pred_stencil<D>(Xs, r0 + j, geo, w, dw, c0, err);
+  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  for (int e = 0; e < NS; ++e) {
+    int o[D];
+    double wp;
+    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+    G[(size_t)j * M + node] = wp;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_var_kxx(PredGeo geo, int r0, int nb_pts, const double* __restrict__ Xs,
+                                                 const double* __restrict__ G, long long M,
+                                                 double* __restrict__ kxx, int* __restrict__ err) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nb_pts) return;
+  double w[D][4], dw[D][4];
+  long long c0[D];
+  pred_stencil<D>(Xs, r0 + j, geo, w, dw, c0, err);
+  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  double acc = 0.0;
+  for (int e = 0; e < NS; ++e) {
+    int o[D];
+    double wp;
+    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+    acc += wp * G[(size_t)j * M + node];
+  }
+  kxx[j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_var_final(const double* __restrict__ kxx,
+                                                   const double* __restrict__ part, int nb,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)j * nb + b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = kxx[j] - red[0];
 }
 
 }  // namespace dski
@@ -95,6 +177,17 @@ extern "C" dski_status dski_predict_grid(dski_plan p, const double* alpha, doubl
   return DSKI_OK;
 }
 
+static PredGeo pred_geo(dski_plan p) {
+  PredGeo geo{};
+  for (int a = 0; a < p->d; ++a) {
+    geo.m[a] = p->ax[a].m;
+    geo.lo[a] = p->ax[a].lo;
+    geo.h[a] = p->ax[a].h;
+    geo.ih[a] = 1.0 / p->ax[a].h;
+  }
+  return geo;
+}
+
 extern "C" dski_status dski_predict(dski_plan p, const double* g, int n_test, const double* X_test, double* out,
                                     dski_stream stream) {
   if (!p || n_test < 0 || (n_test > 0 && (!g || !X_test || !out))) {
@@ -107,13 +200,7 @@ extern "C" dski_status dski_predict(dski_plan p, const double* g, int n_test, co
   }
   if (n_test == 0) return DSKI_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  PredGeo geo{};
-  for (int a = 0; a < p->d; ++a) {
-    geo.m[a] = p->ax[a].m;
-    geo.lo[a] = p->ax[a].lo;
-    geo.h[a] = p->ax[a].h;
-    geo.ih[a] = 1.0 / p->ax[a].h;
-  }
+  const PredGeo geo = pred_geo(p);
   DSKI_TRY(p->vout.reserve(sizeof(int) + 64));  // the plan's scratch: the out-of-box flag
   int* err = p->vout.as<int>();
   DSKI_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
@@ -130,6 +217,78 @@ extern "C" dski_status dski_predict(dski_plan p, const double* g, int n_test, co
   DSKI_HIP(hipStreamSynchronize(st));
   if (herr) {
     set_error("dski_predict: a test point lies outside the interpolation box (or is not finite)");
+    return DSKI_EINVAL;
+  }
+  return DSKI_OK;
+}
+
+extern "C" dski_status dski_predict_var(dski_plan p, dski_precond pc, int n_test, const double* X_test,
+                                        double* out, dski_stream stream) {
+  if (!p || !pc || pc->plan != p || n_test < 0 || (n_test > 0 && (!X_test || !out))) {
+    set_error("dski_predict_var: bad arguments");
+    return DSKI_EINVAL;
+  }
+  if (p->kind != 0) {
+    set_error("dski_predict_var: D-SKI plans only");
+    return DSKI_ENOTSUP;
+  }
+  if (n_test == 0) return DSKI_OK;
+  if (p->d < 1 || p->d > 3) {
+    set_error("d=%d not supported", p->d);
+    return DSKI_ENOTSUP;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const PredGeo geo = pred_geo(p);
+  const long long M = p->M;
+  const int N = p->N;
+  // test points per batch: at most one tall-skinny launch of columns (the
+  // preconditioner returns its dot partials only then), and grid plus the two
+  // N-vectors per point within 2 GiB
+  const size_t per_pt = sizeof(double) * ((size_t)M + 2 * (size_t)N);
+  const int B = (int)std::max<size_t>(
+      1, std::min<size_t>({(size_t)kFinalMaxR, (size_t)n_test, ((size_t)2 << 30) / per_pt}));
+  const int nb = vec_blocks(N);
+  DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)M * B));
+  DSKI_TRY(p->vin.reserve(sizeof(double) * 2 * (size_t)N * B + 64));
+  DSKI_TRY(p->vout.reserve(sizeof(double) * (size_t)B + 64));
+  DSKI_TRY(p->partial.reserve(sizeof(double) * (size_t)nb * B + 64));
+  DSKI_TRY(p->scal.reserve(sizeof(int) + 64));
+  double* G = p->grid.as<double>();
+  double* Y = p->vin.as<double>();          // K_{Xx}, N x B (tile order)
+  double* Z = Y + (size_t)N * B;            // M^{-1} K_{Xx}; zero while it is the gather's noise input
+  double* kxx = p->vout.as<double>();
+  double* part = p->partial.as<double>();
+  int* err = p->scal.as<int>();
+  DSKI_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
+  for (int r0 = 0; r0 < n_test; r0 += B) {
+    const int b = std::min(B, n_test - r0);
+    const unsigned gb = (unsigned)((b + 255) / 256);
+    DSKI_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)M * b, st));
+    DSKI_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)N * b, st));
+    switch (p->d) {
+      case 1: k_var_fill<1><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
+      case 2: k_var_fill<2><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
+      default: k_var_fill<3><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
+    }
+    DSKI_HIP(hipGetLastError());
+    DSKI_TRY(apply_kuu(p, b, G, st));  // G = K_UU w_x
+    switch (p->d) {
+      case 1: k_var_kxx<1><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, kxx, err); break;
+      case 2: k_var_kxx<2><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, kxx, err); break;
+      default: k_var_kxx<3><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, kxx, err); break;
+    }
+    DSKI_HIP(hipGetLastError());
+    DSKI_TRY(gather<double>(p, b, G, Z, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = S K_UU w_x
+    int nbk = 0;
+    DSKI_TRY(precond_apply_tiled<double>(pc, b, Y, N, Z, N, part, &nbk, st));
+    k_var_final<<<(unsigned)b, 256, 0, st>>>(kxx, part, nbk, out + r0);
+    DSKI_HIP(hipGetLastError());
+  }
+  int herr = 0;
+  DSKI_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  DSKI_HIP(hipStreamSynchronize(st));
+  if (herr) {
+    set_error("dski_predict_var: a test point lies outside the interpolation box (or is not finite)");
     return DSKI_EINVAL;
   }
   return DSKI_OK;

@@ -51,6 +51,7 @@ _SIGS = {
     "dski_mvm_dtheta": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_predict_grid": (C.c_int, [vp, vp, vp, vp]),
     "dski_predict": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
+    "dski_predict_var": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
     "dski_permute": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_tile_order": (C.c_int, [vp, ip]),
     "dski_mvm_tiled": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -253,6 +254,17 @@ class Plan:
         out = torch.empty((Xs.shape[0], self.d + 1), dtype=torch.float64, device=Xs.device)
         _check(lib().dski_predict(self._h, _dptr(g.contiguous()), Xs.shape[0], _dptr(Xs), _dptr(out),
                                   _stream(stream)), "dski_predict")
+        return out
+
+    def predict_var(self, pc: "Precond", Xs: torch.Tensor, stream=None) -> torch.Tensor:
+        """Predictive variance of f at the test points Xs (n* x d, FP64, CUDA) with
+        the preconditioner pc (built on this plan) standing in for K~: n* values."""
+        if not Xs.is_cuda or Xs.dtype != torch.float64 or Xs.dim() != 2 or Xs.shape[1] != self.d:
+            raise TypeError("Xs must be a CUDA float64 tensor of shape (n*, d)")
+        Xs = Xs.contiguous()
+        out = torch.empty(Xs.shape[0], dtype=torch.float64, device=Xs.device)
+        _check(lib().dski_predict_var(self._h, pc.handle, Xs.shape[0], _dptr(Xs), _dptr(out), _stream(stream)),
+               "dski_predict_var")
         return out
 
     def mvm_dtheta(self, which: int, V: torch.Tensor, stream=None) -> torch.Tensor:

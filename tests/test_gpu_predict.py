@@ -73,3 +73,53 @@ def test_predict_rejects_points_outside_the_box():
         plan.predict(g, torch.tensor(Xs, device="cuda"))
     assert e.value.status == -1  # DSKI_EINVAL
     assert plan.predict(g, torch.zeros((0, W.d), dtype=torch.float64, device="cuda")).shape == (0, W.d + 1)
+
+
+def _var_case(W, k, n_test, seed, sample=None):
+    """GPU predictive variance with a rank-k pivoted Cholesky against the oracle
+    with the same pivots (near-ties may order them either way); relative to
+    the larger of the two terms k(x, x) and K_{xX} M^{-1} K_{Xx} that v^ subtracts."""
+    from oracle import pivchol
+    plan, op = make(W)
+    pc = plan.pivchol(k)
+    L, _, gaps = pivchol.pivoted_cholesky(op.diag_K(), op.row_K, pc.rank, forced=pc.pivots)
+    assert gaps.size == 0 or gaps.max() <= 1e-4
+    Xs = _test_points(W, n_test, seed)
+    v = plan.predict_var(pc, torch.tensor(Xs, device="cuda")).cpu().numpy()
+    idx = np.arange(n_test) if sample is None else np.random.default_rng(seed).choice(n_test, sample, replace=False)
+    ref = opred.predictive_variance(op, L, Xs[idx])
+    kxx = opred.prior_cov(op, Xs[idx])[0]
+    scale = np.maximum(kxx, np.abs(kxx - ref)).max()
+    e = np.abs(v[idx] - ref).max() / scale
+    say("  variance rel err", e, "rank", pc.rank, "min/max v", v.min(), v.max())
+    return e
+
+
+@pytest.mark.parametrize("name,k", [("small2d", 20), ("small2d_ragged", 0), ("terrain_small", 50),
+                                    ("torus_small", 30)])
+def test_predict_var_matches_oracle(name, k):
+    """300 test points: nine full batches of 32 grid columns and a ragged one."""
+    W = dict(small_workloads())[name]
+    say("predict_var", name, W.n, W.grid_m, k)
+    assert _var_case(W, k, 300, SEED + 5) < 1e-7
+
+
+def test_predict_var_full_terrain_sampled():
+    """Terrain size (n = 20,000, 200 x 200 grid), rank 100: 2,000 test points on
+    the GPU, 100 of them checked against the oracle."""
+    W = workloads.terrain()
+    say("predict_var terrain", W.n, W.grid_m)
+    assert _var_case(W, 100, 2000, SEED + 6, sample=100) < 1e-7
+
+
+def test_predict_var_rejects_points_outside_the_box():
+    dski = need_gpu()
+    W = workloads.small2d()
+    plan, op = make(W)
+    pc = plan.pivchol(10)
+    Xs = _test_points(W, 40, 3)
+    Xs[35, 1] = np.asarray(W.lo)[1] - 1.0
+    with pytest.raises(dski.DSKIError) as e:
+        plan.predict_var(pc, torch.tensor(Xs, device="cuda"))
+    assert e.value.status == -1  # DSKI_EINVAL
+    assert plan.predict_var(pc, torch.zeros((0, W.d), dtype=torch.float64, device="cuda")).shape == (0,)
