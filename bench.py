@@ -199,7 +199,7 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
     """Posterior mean at test points on the terrain workload: the grid vector
     g = K_UU S^T alpha (one scatter and the K_UU factors) and the stencil means
     [f, grad f] of 1,000,000 uniform test points (16 grid reads each); the
-    pivoted-Cholesky predictive variance (rank 100) of 4,096 of them, 32 per
+    pivoted-Cholesky predictive variance (rank 100) of 4,096 of them, 128 per
     batch (one grid column each: stencil, K_UU, gather, preconditioner solve)."""
     import numpy as np
     import torch
@@ -282,6 +282,9 @@ def main(argv=None):
                          "(for profiled runs, whose per-dispatch overhead distorts the tuner's timings)")
     ap.add_argument("--dskip-only", action="store_true",
                     help="only the D-SKIP block of the 8-D ridge workload (build, block MVMs, block PCG)")
+    ap.add_argument("--predict-only", action="store_true",
+                    help="only the prediction block of the terrain workload (grid vector, means of 1,000,000 "
+                         "test points, pivoted-Cholesky variance of 4,096)")
     ap.add_argument("--pmc-mvm", action="store_true",
                     help="run only the MVM stages (and a 256 MiB device copy for calibration) for rocprofv3 --pmc")
     a = ap.parse_args(argv)
@@ -320,6 +323,9 @@ def main(argv=None):
 
     if a.dskip_only:
         print(json.dumps({"dskip": dskip_block(R, stream)}), flush=True)
+        return 0
+    if a.predict_only:
+        print(json.dumps({"predict": predict_block(W, stream)}), flush=True)
         return 0
 
     if a.sweep:

@@ -160,7 +160,7 @@ dski_status dski_predict(dski_plan plan, const double* g, int n_test, const doub
  * kernel (w_x the value stencil of x).  Since L L^T <= K, v^ <= v (equality
  * at full rank).  pc must be built on `plan` (dski_precond_build).  X_test:
  * device, n_test x d row-major FP64, inside the interpolation box; out:
- * device, n_test FP64.  Points go through in batches of up to 32 (one grid
+ * device, n_test FP64.  Points go through in batches of up to 128 (one grid
  * column each); the call uses the plan's scratch buffers and synchronizes
  * `stream`.  DSKI_EINVAL for a point outside the box, DSKI_ENOTSUP for D-SKIP. */
 dski_status dski_predict_var(dski_plan plan, dski_precond pc, int n_test, const double* X_test,

@@ -241,12 +241,10 @@ extern "C" dski_status dski_predict_var(dski_plan p, dski_precond pc, int n_test
   const PredGeo geo = pred_geo(p);
   const long long M = p->M;
   const int N = p->N;
-  // test points per batch: at most one tall-skinny launch of columns (the
-  // preconditioner returns its dot partials only then), and grid plus the two
-  // N-vectors per point within 2 GiB
+  // test points per batch: up to 128, with the grid columns and the two
+  // N-vectors of a batch within 2 GiB
   const size_t per_pt = sizeof(double) * ((size_t)M + 2 * (size_t)N);
-  const int B = (int)std::max<size_t>(
-      1, std::min<size_t>({(size_t)kFinalMaxR, (size_t)n_test, ((size_t)2 << 30) / per_pt}));
+  const int B = (int)std::max<size_t>(1, std::min<size_t>({(size_t)128, (size_t)n_test, ((size_t)2 << 30) / per_pt}));
   const int nb = vec_blocks(N);
   DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)M * B));
   DSKI_TRY(p->vin.reserve(sizeof(double) * 2 * (size_t)N * B + 64));
@@ -279,9 +277,14 @@ extern "C" dski_status dski_predict_var(dski_plan p, dski_precond pc, int n_test
     }
     DSKI_HIP(hipGetLastError());
     DSKI_TRY(gather<double>(p, b, G, Z, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = S K_UU w_x
-    int nbk = 0;
-    DSKI_TRY(precond_apply_tiled<double>(pc, b, Y, N, Z, N, part, &nbk, st));
-    k_var_final<<<(unsigned)b, 256, 0, st>>>(kxx, part, nbk, out + r0);
+    // M^{-1} K_{Xx} and its column dots, one tall-skinny launch of columns at a
+    // time (the preconditioner returns dot partials per launch)
+    for (int c0 = 0; c0 < b; c0 += kFinalMaxR) {
+      const int rc = std::min(kFinalMaxR, b - c0);
+      DSKI_TRY(precond_apply_tiled<double>(pc, rc, Y + (size_t)c0 * N, N, Z + (size_t)c0 * N, N,
+                                           part + (size_t)c0 * nb, nullptr, st));
+    }
+    k_var_final<<<(unsigned)b, 256, 0, st>>>(kxx, part, nb, out + r0);
     DSKI_HIP(hipGetLastError());
   }
   int herr = 0;

@@ -98,7 +98,7 @@ def _var_case(W, k, n_test, seed, sample=None):
 @pytest.mark.parametrize("name,k", [("small2d", 20), ("small2d_ragged", 0), ("terrain_small", 50),
                                     ("torus_small", 30)])
 def test_predict_var_matches_oracle(name, k):
-    """300 test points: nine full batches of 32 grid columns and a ragged one."""
+    """300 test points: two full batches of 128 grid columns and a ragged one."""
     W = dict(small_workloads())[name]
     say("predict_var", name, W.n, W.grid_m, k)
     assert _var_case(W, k, 300, SEED + 5) < 1e-7
