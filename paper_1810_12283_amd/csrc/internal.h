@@ -209,6 +209,11 @@ dski_status precond_apply_tiled(dski_precond pc, int R, const T* Rm, int ld, T* 
 template <typename T>
 dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int ld, T* Z, int ldz,
                                        hipStream_t st);
+// Low-rank part of r^T M^{-1} r for R <= kFinalMaxR FP64 columns (tile order):
+// with M^{-1} = D^{-1/2}(I - U diag(w) U^T)D^{-1/2} and t = U^T D^{-1/2} r,
+// kq[c] = sum_i w_i t_i^2, so that r^T M^{-1} r = ||D^{-1/2} r||^2 - kq[c]
+// (the projection and reduction of one application, without its final pass).
+dski_status precond_lowrank_quad(dski_precond pc, int R, const double* Rm, int ld, double* kq, hipStream_t st);
 int vec_blocks(int N);
 
 // --- PCG core (tile order) -----------------------------------------------------------

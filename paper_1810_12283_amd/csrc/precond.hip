@@ -302,6 +302,44 @@ template dski_status precond_apply_tiled<float>(dski_precond, int, const float*,
 template dski_status precond_apply_tiled<double>(dski_precond, int, const double*, int, double*, int,
                                                  double*, int*, hipStream_t);
 
+// kq[c] = sum_i w_i t_ic^2 with t = t(r_c) the projection of one application.
+static __global__ void k_pc_lowrank_quad(const double* __restrict__ t, const double* __restrict__ coef, int k,
+                                         int R, double* __restrict__ kq) {
+  __shared__ double red[64];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) s += t[(size_t)i * R + c] * coef[(size_t)i * R + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) kq[c] = red[0];
+}
+
+dski_status precond_lowrank_quad(dski_precond pc, int R, const double* Rm, int ld, double* kq, hipStream_t st) {
+  if (R <= 0) return DSKI_OK;
+  if (R > kFinalMaxR) {
+    set_error("precond_lowrank_quad: at most %d columns", kFinalMaxR);
+    return DSKI_EINVAL;
+  }
+  dski_plan p = pc->plan;
+  const int k = pc->k;
+  if (k == 0) {
+    DSKI_HIP(hipMemsetAsync(kq, 0, sizeof(double) * (size_t)R, st));
+    return DSKI_OK;
+  }
+  PcWork w;
+  DSKI_TRY(pc_work(pc, R, w));
+  DSKI_TRY(launch_proj<double>(Rm, ld, p->N, p->n, R, 1.0 / p->sf, 1.0 / p->sg, pc->Ur, k, w.partial, st));
+  RedJob j{w.partial, w.nblk, k * R, R, w.t, pc->w, nullptr, 1.0, w.coef, nullptr};
+  DSKI_TRY(launch_reduce(j, nullptr, st));
+  k_pc_lowrank_quad<<<(unsigned)R, 64, 0, st>>>(w.t, w.coef, k, R, kq);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
 template <typename T>
 dski_status precond_factor_apply_tiled(dski_precond pc, int R, const T* W, int ld, T* Z, int ldz,
                                        hipStream_t st) {

@@ -97,9 +97,10 @@ __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, P
 // Predictive variance (Sec. 4.3, first approach) of f at a batch of test
 // points, one grid column per point.  k_var_fill writes the value stencil w_x
 // of point r0 + j into column j of G (zeroed before); k_var_kxx reads the same
-// stencil against K_UU w_x to give k(x, x) = w_x^T K_UU w_x; k_var_final
-// subtracts K_{xX} M^{-1} K_{Xx} from its per-block partials (block-major per
-// column, nb blocks).
+// stencil against K_UU w_x to give k(x, x) = w_x^T K_UU w_x; k_var_sqnorm
+// forms per-block partials of ||D^{-1/2} K_{Xx}||^2 (kVarSplit blocks per
+// column); k_var_final subtracts K_{xX} M^{-1} K_{Xx} = that norm - kq, kq the
+// preconditioner's low-rank term.
 template <int D>
 __global__ __launch_bounds__(256) void k_var_fill(PredGeo geo, int r0, int nb_pts, const double* __restrict__ Xs,
                                                   double* __restrict__ G, long long M, int* __restrict__ err) {
@@ -137,20 +138,40 @@ __global__ __launch_bounds__(256) void k_var_kxx(PredGeo geo, int r0, int nb_pts
   kxx[j] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_var_final(const double* __restrict__ kxx,
-                                                   const double* __restrict__ part, int nb,
-                                                   double* __restrict__ out) {
+constexpr int kVarSplit = 8;
+
+// grid (kVarSplit, columns): block (b, j) sums (D^{-1/2} Y)_e^2 over rows
+// e = b*256 + t + s*kVarSplit*256 of column j (value rows e < n scaled by
+// 1/sigma_f^2, gradient rows by 1/sigma_g^2).
+__global__ __launch_bounds__(256) void k_var_sqnorm(const double* __restrict__ Y, int N, int n, double iv,
+                                                    double ig, double* __restrict__ part) {
   __shared__ double red[256];
-  const int j = blockIdx.x;
+  const int j = blockIdx.y;
+  const double* y = Y + (size_t)j * N;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)j * nb + b];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < N; e += kVarSplit * 256) {
+    const double v = y[e];
+    s += (e < n ? iv : ig) * v * v;
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[j] = kxx[j] - red[0];
+  if (threadIdx.x == 0) part[(size_t)j * kVarSplit + blockIdx.x] = red[0];
+}
+
+// out[j] = k(x, x) - (||D^{-1/2} K_{Xx}||^2 - kq[j]); one thread per point.
+__global__ __launch_bounds__(256) void k_var_final(const double* __restrict__ kxx, const double* __restrict__ part,
+                                                   const double* __restrict__ kq, int b,
+                                                   double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= b) return;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kVarSplit; ++q) s += part[(size_t)j * kVarSplit + q];
+  out[j] = kxx[j] - (s - kq[j]);
 }
 
 }  // namespace dski
@@ -245,24 +266,24 @@ extern "C" dski_status dski_predict_var(dski_plan p, dski_precond pc, int n_test
   // N-vectors of a batch within 2 GiB
   const size_t per_pt = sizeof(double) * ((size_t)M + 2 * (size_t)N);
   const int B = (int)std::max<size_t>(1, std::min<size_t>({(size_t)128, (size_t)n_test, ((size_t)2 << 30) / per_pt}));
-  const int nb = vec_blocks(N);
   DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)M * B));
   DSKI_TRY(p->vin.reserve(sizeof(double) * 2 * (size_t)N * B + 64));
-  DSKI_TRY(p->vout.reserve(sizeof(double) * (size_t)B + 64));
-  DSKI_TRY(p->partial.reserve(sizeof(double) * (size_t)nb * B + 64));
+  DSKI_TRY(p->vout.reserve(sizeof(double) * 2 * (size_t)B + 64));
+  DSKI_TRY(p->partial.reserve(sizeof(double) * (size_t)kVarSplit * B + 64));
   DSKI_TRY(p->scal.reserve(sizeof(int) + 64));
   double* G = p->grid.as<double>();
   double* Y = p->vin.as<double>();          // K_{Xx}, N x B (tile order)
-  double* Z = Y + (size_t)N * B;            // M^{-1} K_{Xx}; zero while it is the gather's noise input
+  double* Z = Y + (size_t)N * B;            // zeros: the gather's noise input (noise weights 0)
   double* kxx = p->vout.as<double>();
+  double* kq = kxx + B;
   double* part = p->partial.as<double>();
   int* err = p->scal.as<int>();
   DSKI_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
+  DSKI_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)N * B, st));
   for (int r0 = 0; r0 < n_test; r0 += B) {
     const int b = std::min(B, n_test - r0);
     const unsigned gb = (unsigned)((b + 255) / 256);
     DSKI_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)M * b, st));
-    DSKI_HIP(hipMemsetAsync(Z, 0, sizeof(double) * (size_t)N * b, st));
     switch (p->d) {
       case 1: k_var_fill<1><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
       case 2: k_var_fill<2><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
@@ -277,14 +298,14 @@ extern "C" dski_status dski_predict_var(dski_plan p, dski_precond pc, int n_test
     }
     DSKI_HIP(hipGetLastError());
     DSKI_TRY(gather<double>(p, b, G, Z, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = S K_UU w_x
-    // M^{-1} K_{Xx} and its column dots, one tall-skinny launch of columns at a
-    // time (the preconditioner returns dot partials per launch)
-    for (int c0 = 0; c0 < b; c0 += kFinalMaxR) {
-      const int rc = std::min(kFinalMaxR, b - c0);
-      DSKI_TRY(precond_apply_tiled<double>(pc, rc, Y + (size_t)c0 * N, N, Z + (size_t)c0 * N, N,
-                                           part + (size_t)c0 * nb, nullptr, st));
-    }
-    k_var_final<<<(unsigned)b, 256, 0, st>>>(kxx, part, nb, out + r0);
+    // K_{xX} M^{-1} K_{Xx} = ||D^{-1/2} K_{Xx}||^2 - kq: the norm here, kq from
+    // the preconditioner's projection, one tall-skinny launch of columns at a time
+    k_var_sqnorm<<<dim3(kVarSplit, (unsigned)b), 256, 0, st>>>(Y, N, p->n, 1.0 / (p->sf * p->sf),
+                                                                1.0 / (p->sg * p->sg), part);
+    DSKI_HIP(hipGetLastError());
+    for (int c0 = 0; c0 < b; c0 += kFinalMaxR)
+      DSKI_TRY(precond_lowrank_quad(pc, std::min(kFinalMaxR, b - c0), Y + (size_t)c0 * N, N, kq + c0, st));
+    k_var_final<<<gb, 256, 0, st>>>(kxx, part, kq, b, out + r0);
     DSKI_HIP(hipGetLastError());
   }
   int herr = 0;
