@@ -17,6 +17,12 @@ preconditioner M = D + L L^T in place of K~,
 for the value f(x) at a test point (the paper writes the single-noise QR form
 sigma^{-2}(||K_{Xx}||^2 - ||Q_1^T K_{Xx}||^2) of the same quantity).
 
+Randomized variance (Sec. 4.3, second approach): the pivoted-Cholesky
+estimate as a control variate for a diagonal estimator with probes z over the
+test points,
+    v = v^ - E_z[ z .* (K_{X'X} (K~^{-1} - M^{-1}) K_{XX'} z) ],
+unbiased when E[z z^T] = I; the mean over the caller's probes replaces E_z.
+
 Readings (the paper states the complexity and the formula, not the steps):
 * the mean of every test observation, value and all d partial derivatives,
   is returned, as the training observations are value and gradient;
@@ -24,6 +30,10 @@ Readings (the paper states the complexity and the formula, not the steps):
 * k(x, x) and K_{Xx} are those of the D-SKI kernel (w_x^T K_UU w_x and
   S K_UU w_x, w_x the test point's value stencil), so that v^ is the variance
   of the approximate model;
+* the printed randomized formula subtracts v^ and starts from diag(K_{X'X'});
+  read as the control-variate form above (v^ plus the estimate of
+  diag(K_{X'X} (M^{-1} - K~^{-1}) K_{XX'}) with the opposite sign), the only
+  form whose expectation is v;
 * the paper calls v^ a small overestimate of v; since pivoted Cholesky gives
   L L^T <= K, M <= K~ and v^ <= v: v^ underestimates v, and equals it when L
   has full rank (both checked by the pins).
@@ -83,3 +93,17 @@ def exact_variance(op, Xs):
     """v(x) = k(x, x) - K_{xX} K~^{-1} K_{Xx} with the dense D-SKI matrix."""
     kxx, Kx = prior_cov(op, Xs)
     return kxx - np.sum(Kx * np.linalg.solve(op.dense(), Kx), axis=0)
+
+
+def predictive_variance_probes(op, L, Xs, Zp):
+    """Randomized predictive variance of f at the test points Xs with the
+    pivoted-Cholesky estimate as control variate; Zp (R x n*) holds the probes
+    (row r = probe r over the test points)."""
+    Zp = np.asarray(Zp, dtype=np.float64)
+    R = Zp.shape[0]
+    vhat = predictive_variance(op, L, Xs)
+    _, Kx = prior_cov(op, Xs)                       # K_{XX'}, N x n*
+    b = Kx @ Zp.T                                   # K_{XX'} z, N x R
+    u = np.linalg.solve(op.dense(), b) - Precond(L, op.Dn).solve(b)
+    e = Kx.T @ u                                    # K_{X'X} (K~^{-1} - M^{-1}) K_{XX'} z, n* x R
+    return vhat - np.sum(Zp.T * e, axis=1) / R

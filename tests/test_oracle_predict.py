@@ -102,3 +102,23 @@ def test_prior_covariances_tend_to_the_exact_derivative_se_ones():
         kxx, Kx = predict.prior_cov(op, Xs)
         errs.append(max(np.abs(kxx - kref).max() / kref.max(), np.abs(Kx - ref).max() / np.abs(ref).max()))
     assert errs[-1] < 2e-3 and errs[2] < errs[1] < errs[0], errs
+
+
+def test_randomized_variance_is_exact_with_scaled_unit_probes_and_unbiased():
+    """With the n* probes sqrt(n*) e_j (E[z z^T] = I exactly over the set) the
+    diagonal estimate is exact and the result is the exact D-SKI variance; with
+    many Rademacher probes it approaches it, from a control variate far from it."""
+    from oracle import pivchol
+    X, y, op, _ = small_problem(n=30, m=16)
+    r = np.random.default_rng(21)
+    Xs = r.uniform(0.05, 0.95, (8, 2))
+    K = op.dense_K()
+    L, _, _ = pivchol.pivoted_cholesky(np.diag(K), lambda i: K[i], 10)
+    v = predict.exact_variance(op, Xs)
+    vhat = predict.predictive_variance(op, L, Xs)
+    ns = len(Xs)
+    ve = predict.predictive_variance_probes(op, L, Xs, np.sqrt(ns) * np.eye(ns))
+    assert np.abs(ve - v).max() <= 1e-9 * np.abs(vhat - v).max()
+    Zr = r.choice([-1.0, 1.0], (4000, ns))
+    vr = predict.predictive_variance_probes(op, L, Xs, Zr)
+    assert np.abs(vr - v).max() <= 0.1 * np.abs(vhat - v).max()
