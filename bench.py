@@ -200,7 +200,8 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
     g = K_UU S^T alpha (one scatter and the K_UU factors) and the stencil means
     [f, grad f] of 1,000,000 uniform test points (16 grid reads each); the
     pivoted-Cholesky predictive variance (rank 100) of 4,096 of them, 128 per
-    batch (one grid column each: stencil, K_UU, gather, preconditioner solve)."""
+    batch (one grid column each: stencil, K_UU, gather, preconditioner
+    projection); the randomized variance of 1,024 of them with 16 probes."""
     import numpy as np
     import torch
     from paper_1810_12283_amd import dski
@@ -216,13 +217,25 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
     pc = plan.pivchol(100)
     Xv = Xs[:nvar].contiguous()
     v_ms = _events_stats(lambda: plan.predict_var(pc, Xv), 5, stream)[0]
+    # randomized variance with that estimate as control variate: 16 Rademacher
+    # probes over 1,024 test points, block PCG to the workload's tolerance
+    nprb, npv = 16, 1024
+    Zp = torch.tensor(r.choice([-1.0, 1.0], (nprb, npv)), device="cuda")
+    Xp = Xs[:npv].contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, pst = plan.predict_var_probes(pc, Xp, Zp, tol=W.tol, max_iter=20000)
+    torch.cuda.synchronize()
+    pr_s = time.perf_counter() - t0
     pc.close()
     plan.close()
     return {"workload": f"terrain n={W.n} grid={W.grid_m[0]}x{W.grid_m[1]}, {npts} test points",
             "grid_vector_ms": round(g_ms, 4), "predict_ms": round(p_ms, 4),
             "test_points_per_s": round(npts / (p_ms * 1e-3), 1),
             "variance_rank": 100, "variance_points": nvar, "variance_ms": round(v_ms, 3),
-            "variance_points_per_s": round(nvar / (v_ms * 1e-3), 1)}
+            "variance_points_per_s": round(nvar / (v_ms * 1e-3), 1),
+            "randomized_variance": {"points": npv, "probes": nprb, "tol": W.tol, "s": round(pr_s, 3),
+                                    "status": int(pst)}}
 
 
 def mvm_bytes(N, M, n, d, R):

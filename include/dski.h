@@ -166,6 +166,24 @@ dski_status dski_predict(dski_plan plan, const double* g, int n_test, const doub
 dski_status dski_predict_var(dski_plan plan, dski_precond pc, int n_test, const double* X_test,
                              double* out, dski_stream stream);
 
+/* Randomized predictive variance of f at test points (Sec. 4.3, second
+ * approach): the pivoted-Cholesky estimate v^ of dski_predict_var as control
+ * variate for a diagonal estimator over the test points,
+ *   v = v^ - (1/R) sum_r z_r .* (K_{X'X} (K~^{-1} - M^{-1}) K_{XX'} z_r),
+ * unbiased for v when E[z z^T] = I (Rademacher or Gaussian probes; the n_test
+ * probes sqrt(n_test) e_j give the exact variance).  Per chunk of up to 32
+ * probes: test stencils weighted by z scattered onto the grid, K_UU, gather
+ * (K_{XX'} z), block PCG with pc to relative residual tol (FP64 vectors) and
+ * M^{-1}, scatter of the difference, K_UU, stencil reads at the test points.
+ * Zp: device, R x n_test row-major FP64 (row r = probe r).  X_test, out as for
+ * dski_predict_var.  Allocates a work buffer of 3 N min(R, 32) + n_test doubles per call and
+ * synchronizes `stream`.  DSKI_NOT_CONVERGED if a solve reached max_iter (out
+ * then uses its last iterate), DSKI_EINVAL for a point outside the box,
+ * DSKI_ENOTSUP for D-SKIP. */
+dski_status dski_predict_var_probes(dski_plan plan, dski_precond pc, int n_test, const double* X_test,
+                                    int R, const double* Zp, double tol, int max_iter, double* out,
+                                    dski_stream stream);
+
 /* Tile order: the internal point order (sorted by interpolation cell) that the
  * solvers use.  dir = +1: user -> tile, dir = -1: tile -> user.  perm_host (n
  * ints, may be NULL) receives, for tile position k, the user index. */

@@ -174,6 +174,66 @@ __global__ __launch_bounds__(256) void k_var_final(const double* __restrict__ kx
   out[j] = kxx[j] - (s - kq[j]);
 }
 
+// Randomized variance (Sec. 4.3, second approach), per chunk of probes.
+// k_probe_scatter: grid column r receives sum_j z_{r0+r, j} w_{x_j} (test-point
+// value stencils weighted by the probe; FP64 atomic adds, as stencils overlap).
+template <int D>
+__global__ __launch_bounds__(256) void k_probe_scatter(PredGeo geo, int ns, const double* __restrict__ Xs,
+                                                       const double* __restrict__ Zp, int r0,
+                                                       double* __restrict__ G, long long M, int* __restrict__ err) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (j >= ns) return;
+  double w[D][4], dw[D][4];
+  long long c0[D];
+  pred_stencil<D>(Xs, j, geo, w, dw, c0, err);
+  const double z = Zp[(size_t)(r0 + r) * ns + j];
+  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  for (int e = 0; e < NS; ++e) {
+    int o[D];
+    double wp;
+    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+    atomicAdd(&G[(size_t)r * M + node], z * wp);
+  }
+}
+
+// acc[j] += sum_r z_{r0+r, j} w_{x_j}^T G_r over the rc columns of the chunk.
+template <int D>
+__global__ __launch_bounds__(256) void k_probe_read(PredGeo geo, int ns, const double* __restrict__ Xs,
+                                                    const double* __restrict__ Zp, int r0, int rc,
+                                                    const double* __restrict__ G, long long M,
+                                                    double* __restrict__ acc, int* __restrict__ err) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  double w[D][4], dw[D][4];
+  long long c0[D];
+  pred_stencil<D>(Xs, j, geo, w, dw, c0, err);
+  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  double a = acc[j];
+  for (int r = 0; r < rc; ++r) {
+    double e_r = 0.0;
+    for (int e = 0; e < NS; ++e) {
+      int o[D];
+      double wp;
+      const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+      e_r += wp * G[(size_t)r * M + node];
+    }
+    a += Zp[(size_t)(r0 + r) * ns + j] * e_r;
+  }
+  acc[j] = a;
+}
+
+__global__ __launch_bounds__(256) void k_sub_inplace(double* __restrict__ a, const double* __restrict__ b,
+                                                     size_t count) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+    a[e] -= b[e];
+}
+
+__global__ __launch_bounds__(256) void k_probe_final(const double* __restrict__ acc, int ns, double inv_r,
+                                                     double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < ns) out[j] -= inv_r * acc[j];
+}
+
 }  // namespace dski
 
 using namespace dski;
@@ -316,4 +376,82 @@ extern "C" dski_status dski_predict_var(dski_plan p, dski_precond pc, int n_test
     return DSKI_EINVAL;
   }
   return DSKI_OK;
+}
+
+namespace {
+struct ScopedBuf {
+  dski::DevBuf b;
+  ~ScopedBuf() { b.release(); }
+};
+}  // namespace
+
+extern "C" dski_status dski_predict_var_probes(dski_plan p, dski_precond pc, int n_test, const double* X_test,
+                                               int R, const double* Zp, double tol, int max_iter, double* out,
+                                               dski_stream stream) {
+  if (!p || !pc || pc->plan != p || n_test < 0 || R < 1 || !(tol > 0.0) || max_iter < 1 ||
+      (n_test > 0 && (!X_test || !Zp || !out))) {
+    set_error("dski_predict_var_probes: bad arguments");
+    return DSKI_EINVAL;
+  }
+  if (p->kind != 0) {
+    set_error("dski_predict_var_probes: D-SKI plans only");
+    return DSKI_ENOTSUP;
+  }
+  if (n_test == 0) return DSKI_OK;
+  // the control variate v^ (also rejects points outside the box)
+  DSKI_TRY(dski_predict_var(p, pc, n_test, X_test, out, stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const PredGeo geo = pred_geo(p);
+  const long long M = p->M;
+  const int N = p->N;
+  const int C = std::min(R, kFinalMaxR);  // probes per chunk
+  ScopedBuf wb;
+  DSKI_TRY(wb.b.reserve(sizeof(double) * (3 * (size_t)N * C + (size_t)n_test) + 256));
+  double* Y = wb.b.as<double>();         // K_{XX'} z, N x C (tile order)
+  double* U1 = Y + (size_t)N * C;        // K~^{-1} K_{XX'} z, then minus M^{-1} K_{XX'} z
+  double* U2 = U1 + (size_t)N * C;       // zeros (the gather's noise input), then M^{-1} K_{XX'} z
+  double* acc = U2 + (size_t)N * C;
+  int* err = reinterpret_cast<int*>(acc + n_test);
+  DSKI_HIP(hipMemsetAsync(acc, 0, sizeof(double) * (size_t)n_test + sizeof(int), st));
+  dski_status status = DSKI_OK;
+  const unsigned gb = (unsigned)((n_test + 255) / 256);
+  for (int r0 = 0; r0 < R; r0 += C) {
+    const int rc = std::min(C, R - r0);
+    DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)M * rc));
+    double* G = p->grid.as<double>();
+    DSKI_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)M * rc, st));
+    DSKI_HIP(hipMemsetAsync(U2, 0, sizeof(double) * (size_t)N * rc, st));
+    switch (p->d) {
+      case 1: k_probe_scatter<1><<<dim3(gb, rc), 256, 0, st>>>(geo, n_test, X_test, Zp, r0, G, M, err); break;
+      case 2: k_probe_scatter<2><<<dim3(gb, rc), 256, 0, st>>>(geo, n_test, X_test, Zp, r0, G, M, err); break;
+      default: k_probe_scatter<3><<<dim3(gb, rc), 256, 0, st>>>(geo, n_test, X_test, Zp, r0, G, M, err); break;
+    }
+    DSKI_HIP(hipGetLastError());
+    DSKI_TRY(apply_kuu(p, rc, G, st));
+    DSKI_TRY(gather<double>(p, rc, G, U2, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = K_{XX'} z
+    PcgResult res;
+    std::vector<double> tols(rc, tol);
+    std::vector<int> verify(rc, 1);
+    const dski_status pr = pcg_tiled<double>(p, pc, rc, Y, N, U1, N, tols.data(), max_iter, 0, nullptr, res, st,
+                                             nullptr, verify.data());
+    if (pr < 0) return pr;
+    if (pr == DSKI_NOT_CONVERGED) status = DSKI_NOT_CONVERGED;
+    DSKI_TRY(precond_apply_tiled<double>(pc, rc, Y, N, U2, N, nullptr, nullptr, st));
+    k_sub_inplace<<<1024, 256, 0, st>>>(U1, U2, (size_t)N * rc);
+    DSKI_HIP(hipGetLastError());
+    DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)M * rc));  // the solver's products may have resized it
+    G = p->grid.as<double>();
+    DSKI_TRY(scatter<double>(p, rc, U1, N, G, st));
+    DSKI_TRY(apply_kuu(p, rc, G, st));
+    switch (p->d) {
+      case 1: k_probe_read<1><<<gb, 256, 0, st>>>(geo, n_test, X_test, Zp, r0, rc, G, M, acc, err); break;
+      case 2: k_probe_read<2><<<gb, 256, 0, st>>>(geo, n_test, X_test, Zp, r0, rc, G, M, acc, err); break;
+      default: k_probe_read<3><<<gb, 256, 0, st>>>(geo, n_test, X_test, Zp, r0, rc, G, M, acc, err); break;
+    }
+    DSKI_HIP(hipGetLastError());
+  }
+  k_probe_final<<<gb, 256, 0, st>>>(acc, n_test, 1.0 / R, out);
+  DSKI_HIP(hipGetLastError());
+  DSKI_HIP(hipStreamSynchronize(st));
+  return status;
 }

@@ -52,6 +52,7 @@ _SIGS = {
     "dski_predict_grid": (C.c_int, [vp, vp, vp, vp]),
     "dski_predict": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
     "dski_predict_var": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
+    "dski_predict_var_probes": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, vp, C.c_double, C.c_int, vp, vp]),
     "dski_permute": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_tile_order": (C.c_int, [vp, ip]),
     "dski_mvm_tiled": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -266,6 +267,22 @@ class Plan:
         _check(lib().dski_predict_var(self._h, pc.handle, Xs.shape[0], _dptr(Xs), _dptr(out), _stream(stream)),
                "dski_predict_var")
         return out
+
+    def predict_var_probes(self, pc: "Precond", Xs: torch.Tensor, Zp: torch.Tensor, tol: float = 1e-8,
+                           max_iter: int = 10000, stream=None):
+        """Randomized predictive variance of f at Xs with the pivoted-Cholesky
+        estimate as control variate; Zp (R x n*, FP64, CUDA) holds the probes.
+        Returns (n* values, status): status 1 if a solve reached max_iter."""
+        if not Xs.is_cuda or Xs.dtype != torch.float64 or Xs.dim() != 2 or Xs.shape[1] != self.d:
+            raise TypeError("Xs must be a CUDA float64 tensor of shape (n*, d)")
+        if not Zp.is_cuda or Zp.dtype != torch.float64 or Zp.dim() != 2 or Zp.shape[1] != Xs.shape[0]:
+            raise TypeError("Zp must be a CUDA float64 tensor of shape (R, n*)")
+        Xs, Zp = Xs.contiguous(), Zp.contiguous()
+        out = torch.empty(Xs.shape[0], dtype=torch.float64, device=Xs.device)
+        st = _check(lib().dski_predict_var_probes(self._h, pc.handle, Xs.shape[0], _dptr(Xs), Zp.shape[0],
+                                                  _dptr(Zp), float(tol), int(max_iter), _dptr(out),
+                                                  _stream(stream)), "dski_predict_var_probes")
+        return out, st
 
     def mvm_dtheta(self, which: int, V: torch.Tensor, stream=None) -> torch.Tensor:
         V = _block(V, self.N, "V")

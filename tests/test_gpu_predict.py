@@ -123,3 +123,48 @@ def test_predict_var_rejects_points_outside_the_box():
         plan.predict_var(pc, torch.tensor(Xs, device="cuda"))
     assert e.value.status == -1  # DSKI_EINVAL
     assert plan.predict_var(pc, torch.zeros((0, W.d), dtype=torch.float64, device="cuda")).shape == (0,)
+
+
+@pytest.mark.parametrize("name,k,ns,R", [("small2d", 20, 40, 16), ("torus_small", 30, 24, 40),
+                                         ("small2d_ragged", 10, 300, 8)])
+def test_predict_var_probes_matches_oracle(name, k, ns, R):
+    """Randomized variance with Rademacher probes (the same on both sides; R = 40
+    runs a chunk of 32 probes and a ragged one) against the oracle's dense
+    solves, relative to the size of the correction |v - v^|; PCG to 1e-10."""
+    from oracle import pivchol
+    W = dict(small_workloads())[name]
+    say("predict_var_probes", name, k, ns, R)
+    plan, op = make(W)
+    pc = plan.pivchol(k)
+    L, _, _ = pivchol.pivoted_cholesky(op.diag_K(), op.row_K, pc.rank, forced=pc.pivots)
+    Xs = _test_points(W, ns, SEED + 7)
+    Zp = np.random.default_rng(SEED + 8).choice([-1.0, 1.0], (R, ns))
+    v, st = plan.predict_var_probes(pc, torch.tensor(Xs, device="cuda"), torch.tensor(Zp, device="cuda"),
+                                    tol=1e-10, max_iter=20000)
+    v = v.cpu().numpy()
+    ref = opred.predictive_variance_probes(op, L, Xs, Zp)
+    corr = np.abs(ref - opred.predictive_variance(op, L, Xs)).max()
+    e = np.abs(v - ref).max() / corr
+    say("  status", st, "rel err", e, "correction", corr)
+    assert st == 0 and e < 1e-6
+
+
+def test_predict_var_probes_with_unit_probes_is_the_exact_variance():
+    """Probes sqrt(n*) e_j make the estimate exact: the GPU result equals the
+    exact D-SKI posterior variance from the oracle's dense solve."""
+    from oracle import pivchol
+    W = workloads.small2d()
+    plan, op = make(W)
+    pc = plan.pivchol(20)
+    ns = 12
+    Xs = _test_points(W, ns, SEED + 9)
+    Zp = np.sqrt(ns) * np.eye(ns)
+    v, st = plan.predict_var_probes(pc, torch.tensor(Xs, device="cuda"), torch.tensor(Zp, device="cuda"),
+                                    tol=1e-10, max_iter=20000)
+    v = v.cpu().numpy()
+    exact = opred.exact_variance(op, Xs)
+    L, _, _ = pivchol.pivoted_cholesky(op.diag_K(), op.row_K, pc.rank, forced=pc.pivots)
+    corr = np.abs(exact - opred.predictive_variance(op, L, Xs)).max()
+    e = np.abs(v - exact).max() / corr
+    say("  unit probes: status", st, "rel err", e, "min v", v.min())
+    assert st == 0 and e < 1e-6
