@@ -153,7 +153,7 @@ dski_status dski_predict_grid(dski_plan plan, const double* alpha, double* g, ds
 dski_status dski_predict(dski_plan plan, const double* g, int n_test, const double* X_test, double* out,
                          dski_stream stream);
 
-/* Predictive variance of f at test points (Sec. 4.3, first approach): the
+/* Predictive variance of f at test points (Sec. 4.4, first approach): the
  * pivoted-Cholesky preconditioner M = D + L L^T stands in for K~,
  *   v^(x) = k(x, x) - K_{xX} M^{-1} K_{Xx},
  * with k(x, x) = w_x^T K_UU w_x and K_{Xx} = S K_UU w_x those of the D-SKI
@@ -166,7 +166,7 @@ dski_status dski_predict(dski_plan plan, const double* g, int n_test, const doub
 dski_status dski_predict_var(dski_plan plan, dski_precond pc, int n_test, const double* X_test,
                              double* out, dski_stream stream);
 
-/* Randomized predictive variance of f at test points (Sec. 4.3, second
+/* Randomized predictive variance of f at test points (Sec. 4.4, second
  * approach): the pivoted-Cholesky estimate v^ of dski_predict_var as control
  * variate for a diagonal estimator over the test points,
  *   v = v^ - (1/R) sum_r z_r .* (K_{X'X} (K~^{-1} - M^{-1}) K_{XX'} z_r),

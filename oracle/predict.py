@@ -11,13 +11,13 @@ derivative interpolation rows of the test points, so the grid vector
 g = K_UU S^T alpha is formed once and each test point interpolates it on its
 cubic stencil: mean = S_* g (4^d nodes per test point, whatever n).
 
-Predictive variance (Sec. 4.3, first approach): with the pivoted-Cholesky
+Predictive variance (Sec. 4.4, first approach): with the pivoted-Cholesky
 preconditioner M = D + L L^T in place of K~,
     v^(x) = k(x, x) - K_{xX} M^{-1} K_{Xx}
 for the value f(x) at a test point (the paper writes the single-noise QR form
 sigma^{-2}(||K_{Xx}||^2 - ||Q_1^T K_{Xx}||^2) of the same quantity).
 
-Randomized variance (Sec. 4.3, second approach): the pivoted-Cholesky
+Randomized variance (Sec. 4.4, second approach): the pivoted-Cholesky
 estimate as a control variate for a diagonal estimator with probes z over the
 test points,
     v = v^ - E_z[ z .* (K_{X'X} (K~^{-1} - M^{-1}) K_{XX'} z) ],

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, P
   for (int q = 0; q <= D; ++q) out[(size_t)u * (D + 1) + q] = acc[q];
 }
 
-// Predictive variance (Sec. 4.3, first approach) of f at a batch of test
+// Predictive variance (Sec. 4.4, first approach) of f at a batch of test
 // points, one grid column per point.  k_var_fill writes the value stencil w_x
 // of point r0 + j into column j of G (zeroed before); k_var_kxx reads the same
 // stencil against K_UU w_x to give k(x, x) = w_x^T K_UU w_x; k_var_sqnorm
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_var_final(const double* __restrict__ kx
   out[j] = kxx[j] - (s - kq[j]);
 }
 
-// Randomized variance (Sec. 4.3, second approach), per chunk of probes.
+// Randomized variance (Sec. 4.4, second approach), per chunk of probes.
 // k_probe_scatter: grid column r receives sum_j z_{r0+r, j} w_{x_j} (test-point
 // value stencils weighted by the probe; FP64 atomic adds, as stencils overlap).
 template <int D>

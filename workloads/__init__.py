@@ -15,10 +15,10 @@ Workloads (sizes follow the paper's experiment families, Sec. 4):
 * ``small2d``   – n=500 on [0,1]^2, sum of 8 random sinusoids; 50x50 grid.
 * ``terrain``   – n=20,000 on [0,1]^2, 64 random Fourier modes with a
                   |k|^-1.5 spectrum (stands in for the LiDAR terrain of
-                  Sec. 4.3); 200x200 grid.
+                  Sec. 4.2); 200x200 grid.
 * ``torus``     – n=30,000 points on a perturbed torus with unit outward
                   normals as gradients and value 0 (stands in for the
-                  implicit-surface experiment of Sec. 4.4); 48^3 grid.
+                  implicit-surface experiment of Sec. 4.3); 48^3 grid.
 * ``ridge8d``   – n=4,000 on [-1,1]^8, sum of 16 tanh ridge functions
                   (high-dimensional D-SKIP case of Sec. 3.2).
 """
