@@ -238,6 +238,36 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
                                     "status": int(pst)}}
 
 
+def active_block(D=20, n=20000, reps=10):
+    """Active subspace of a ridge function in D = 20 dimensions from n = 20,000
+    gradient samples (C on the GPU, Jacobi on the host) and the projection of
+    the points and gradients onto its 2 dominant directions."""
+    import numpy as np
+    import torch
+    from paper_1810_12283_amd import dski
+    r = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(r.standard_normal((D, 2)))
+    X = r.uniform(-1.0, 1.0, (n, D))
+    G = 2.0 * np.cos(2.0 * X @ Q[:, 0])[:, None] * Q[:, 0] + (X @ Q[:, 1])[:, None] * Q[:, 1]
+    Gd = torch.tensor(np.ascontiguousarray(G.T), device="cuda")
+    Xd = torch.tensor(X, device="cuda")
+    dski.active_subspace(Gd, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P, lam = dski.active_subspace(Gd, 2)
+    s_ms = (time.perf_counter() - t0) / reps * 1e3
+    dski.active_project(Xd, Gd, P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dski.active_project(Xd, Gd, P)
+    torch.cuda.synchronize()
+    p_ms = (time.perf_counter() - t0) / reps * 1e3
+    return {"workload": f"ridge function D={D}, n={n}, d=2", "subspace_ms": round(s_ms, 3),
+            "project_ms": round(p_ms, 3), "eigenvalue_ratio_3_1": float(lam[2] / lam[0])}
+
+
 def mvm_bytes(N, M, n, d, R):
     """Algorithmic bytes of one block MVM (FP32 vectors and grid):
     V read by the scatter and again for the noise term, Y written (3 N R);
@@ -297,7 +327,7 @@ def main(argv=None):
                     help="only the D-SKIP block of the 8-D ridge workload (build, block MVMs, block PCG)")
     ap.add_argument("--predict-only", action="store_true",
                     help="only the prediction block of the terrain workload (grid vector, means of 1,000,000 "
-                         "test points, pivoted-Cholesky variance of 4,096)")
+                         "test points, pivoted-Cholesky and randomized variance) and the active-subspace block")
     ap.add_argument("--pmc-mvm", action="store_true",
                     help="run only the MVM stages (and a 256 MiB device copy for calibration) for rocprofv3 --pmc")
     a = ap.parse_args(argv)
@@ -338,7 +368,7 @@ def main(argv=None):
         print(json.dumps({"dskip": dskip_block(R, stream)}), flush=True)
         return 0
     if a.predict_only:
-        print(json.dumps({"predict": predict_block(W, stream)}), flush=True)
+        print(json.dumps({"predict": predict_block(W, stream), "active_subspace": active_block()}), flush=True)
         return 0
 
     if a.sweep:
@@ -564,6 +594,7 @@ def main(argv=None):
     line["dskip"] = dskip_block(R, stream)
     line["surrogate"] = surrogate_block(W, y, W.rank, stream)
     line["predict"] = predict_block(W, stream)
+    line["active_subspace"] = active_block()
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, R)
     print(json.dumps(line), flush=True)

@@ -184,6 +184,28 @@ dski_status dski_predict_var_probes(dski_plan plan, dski_precond pc, int n_test,
                                     int R, const double* Zp, double tol, int max_iter, double* out,
                                     dski_stream stream);
 
+/* Active-subspace dimension reduction (Sec. 3.4).  C = (1/n) sum_i g_i g_i^T
+ * over n gradient samples g_i in R^D; P holds its d dominant eigenvectors, and
+ * a GP on the reduced points u_i = P^T x_i with gradients P^T g_i uses the
+ * kernel k(P^T x, P^T x').
+ * dski_active_subspace: G device FP64, component p of sample i at
+ *   G[p*ldg + i] (the derivative blocks of an N-vector, ldg >= n); 1 <= d <=
+ *   D <= 64.  P_host (D x d row-major) receives the eigenvectors as columns,
+ *   each signed so that its entry of largest magnitude is positive; eig_host
+ *   (D) all eigenvalues of C in decreasing order.  C is formed on the GPU
+ *   (per-block partials summed on the host in block order), then a cyclic
+ *   Jacobi eigen-decomposition runs on the host.  Synchronizes `stream`;
+ *   DSKI_ENOTSUP for D > 64.
+ * dski_active_project: X device n x D row-major, P device D x d row-major;
+ *   U (device, n x d row-major) receives P^T x_i; if G is given (layout as
+ *   above), Gu (device, d blocks of n) receives P^T g_i, so that the values
+ *   followed by Gu form the reduced N-vector.  G and Gu are both NULL or both
+ *   set.  Asynchronous on `stream`. */
+dski_status dski_active_subspace(int n, int D, const double* G, int ldg, int d, double* P_host,
+                                 double* eig_host, dski_stream stream);
+dski_status dski_active_project(int n, int D, int d, const double* X, const double* G, int ldg,
+                                const double* P, double* U, double* Gu, dski_stream stream);
+
 /* Tile order: the internal point order (sorted by interpolation cell) that the
  * solvers use.  dir = +1: user -> tile, dir = -1: tile -> user.  perm_host (n
  * ints, may be NULL) receives, for tile position k, the user index. */

@@ -52,6 +52,8 @@ _SIGS = {
     "dski_predict_grid": (C.c_int, [vp, vp, vp, vp]),
     "dski_predict": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
     "dski_predict_var": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
+    "dski_active_subspace": (C.c_int, [C.c_int, C.c_int, vp, C.c_int, C.c_int, vp, vp, vp]),
+    "dski_active_project": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, vp, vp]),
     "dski_predict_var_probes": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, vp, C.c_double, C.c_int, vp, vp]),
     "dski_permute": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_tile_order": (C.c_int, [vp, ip]),
@@ -529,6 +531,41 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+def active_subspace(G: torch.Tensor, d: int, stream=None):
+    """Active subspace from gradient samples G (CUDA FP64, D x n: row p holds
+    component p of every sample): (P as a D x d numpy array, the D eigenvalues
+    of C = (1/n) sum g g^T in decreasing order)."""
+    if not G.is_cuda or G.dtype != torch.float64 or G.dim() != 2:
+        raise TypeError("G must be a CUDA float64 tensor of shape (D, n)")
+    G = G.contiguous()
+    D, n = G.shape
+    P = np.zeros((D, d), dtype=np.float64)
+    lam = np.zeros(D, dtype=np.float64)
+    _check(lib().dski_active_subspace(n, D, _dptr(G), n, int(d), P.ctypes.data_as(vp), lam.ctypes.data_as(vp),
+                                      _stream(stream)), "dski_active_subspace")
+    return P, lam
+
+
+def active_project(X: torch.Tensor, G: Optional[torch.Tensor], P, stream=None):
+    """Reduced data: U = X P (n x d) and, if G (D x n) is given, the reduced
+    gradients as a d x n tensor (row j = P[:, j]^T g_i); CUDA FP64."""
+    if not X.is_cuda or X.dtype != torch.float64 or X.dim() != 2:
+        raise TypeError("X must be a CUDA float64 tensor of shape (n, D)")
+    X = X.contiguous()
+    n, D = X.shape
+    Pt = torch.as_tensor(np.ascontiguousarray(P, dtype=np.float64), device=X.device)
+    d = Pt.shape[1]
+    U = torch.empty((n, d), dtype=torch.float64, device=X.device)
+    Gu = None
+    if G is not None:
+        G = G.contiguous()
+        Gu = torch.empty((d, n), dtype=torch.float64, device=X.device)
+    _check(lib().dski_active_project(n, D, d, _dptr(X), _dptr(G) if G is not None else None, n, _dptr(Pt),
+                                     _dptr(U), _dptr(Gu) if Gu is not None else None, _stream(stream)),
+           "dski_active_project")
+    return U, Gu
 
 
 def rademacher(seed: int, col0: int, ncols: int, N: int, device="cuda", stream=None) -> torch.Tensor:
