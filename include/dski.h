@@ -206,6 +206,19 @@ dski_status dski_active_subspace(int n, int D, const double* G, int ldg, int d, 
 dski_status dski_active_project(int n, int D, int d, const double* X, const double* G, int ldg,
                                 const double* P, double* U, double* Gu, dski_stream stream);
 
+/* Expected-improvement acquisition over n_cand candidates (Sec. 4.4, Alg. 1),
+ * for minimisation: EI = E[max(f_best - xi - Y, 0)] with Y ~ N(mu, sigma^2),
+ * sigma = sqrt(max(var, 0)) (a negative variance estimate counts as zero).
+ * mu: device, mean of candidate j at mu[j*mu_stride] (mu_stride = d + 1 reads
+ * the value column of dski_predict's output); var: device, n_cand; xi >= 0 an
+ * exploration margin; ei: device, n_cand (may be NULL) receives every EI.
+ * best_idx_host / best_ei_host receive the largest EI and its candidate (the
+ * first on a tie; candidates whose EI is not finite are never chosen).
+ * Synchronizes `stream`; DSKI_EINVAL if no EI is finite. */
+dski_status dski_expected_improvement(int n_cand, const double* mu, int mu_stride, const double* var,
+                                      double f_best, double xi, double* ei, int* best_idx_host,
+                                      double* best_ei_host, dski_stream stream);
+
 /* Tile order: the internal point order (sorted by interpolation cell) that the
  * solvers use.  dir = +1: user -> tile, dir = -1: tile -> user.  perm_host (n
  * ints, may be NULL) receives, for tile position k, the user index. */

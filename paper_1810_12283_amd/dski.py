@@ -52,6 +52,7 @@ _SIGS = {
     "dski_predict_grid": (C.c_int, [vp, vp, vp, vp]),
     "dski_predict": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
     "dski_predict_var": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
+    "dski_expected_improvement": (C.c_int, [C.c_int, vp, C.c_int, vp, C.c_double, C.c_double, vp, ip, vp, vp]),
     "dski_active_subspace": (C.c_int, [C.c_int, C.c_int, vp, C.c_int, C.c_int, vp, vp, vp]),
     "dski_active_project": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, vp, C.c_int, vp, vp, vp, vp]),
     "dski_predict_var_probes": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, vp, C.c_double, C.c_int, vp, vp]),
@@ -531,6 +532,25 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+def expected_improvement(mu: torch.Tensor, var: torch.Tensor, f_best: float, xi: float = 0.0, stream=None):
+    """EI of every candidate (minimisation) and the best one: (ei tensor, index,
+    value).  mu: CUDA FP64, n_cand values or dski_predict's n_cand x (d + 1)
+    output (its value column is used); var: CUDA FP64, n_cand."""
+    if not mu.is_cuda or mu.dtype != torch.float64 or not var.is_cuda or var.dtype != torch.float64:
+        raise TypeError("mu and var must be CUDA float64 tensors")
+    mu, var = mu.contiguous(), var.contiguous()
+    stride = 1 if mu.dim() == 1 else mu.shape[1]
+    n = var.numel()
+    if mu.shape[0] != n:
+        raise ValueError("mu and var hold different numbers of candidates")
+    ei = torch.empty(n, dtype=torch.float64, device=var.device)
+    idx = C.c_int()
+    best = C.c_double()
+    _check(lib().dski_expected_improvement(n, _dptr(mu), stride, _dptr(var), float(f_best), float(xi), _dptr(ei),
+                                           C.byref(idx), C.byref(best), _stream(stream)), "dski_expected_improvement")
+    return ei, idx.value, best.value
 
 
 def active_subspace(G: torch.Tensor, d: int, stream=None):
