@@ -245,7 +245,9 @@ class Plan:
         if not alpha.is_cuda or alpha.dtype != torch.float64 or alpha.numel() != self.N:
             raise TypeError("alpha must be a CUDA float64 tensor with N entries")
         alpha = alpha.contiguous()
-        g = torch.empty(int(np.prod(self.grid_m)), dtype=torch.float64, device=alpha.device)
+        # D-SKIP plans have no single grid; the library refuses them (DSKI_ENOTSUP)
+        m = getattr(self, "grid_m", None)
+        g = torch.empty(int(np.prod(m)) if m is not None else 1, dtype=torch.float64, device=alpha.device)
         _check(lib().dski_predict_grid(self._h, _dptr(alpha), _dptr(g), _stream(stream)), "dski_predict_grid")
         return g
 

@@ -168,3 +168,31 @@ def test_predict_var_probes_with_unit_probes_is_the_exact_variance():
     e = np.abs(v - exact).max() / corr
     say("  unit probes: status", st, "rel err", e, "min v", v.min())
     assert st == 0 and e < 1e-6
+
+
+def test_prediction_error_paths():
+    """Forced from the host: a solve capped at one iteration reports
+    DSKI_NOT_CONVERGED (1) with finite outputs; D-SKIP plans are refused by
+    every prediction call (DSKI_ENOTSUP); a probe matrix of the wrong shape is
+    refused by the binding."""
+    dski = need_gpu()
+    W = workloads.small2d()
+    plan, op = make(W)
+    pc = plan.pivchol(10)
+    Xs = torch.tensor(_test_points(W, 20, 4), device="cuda")
+    Zp = torch.tensor(np.random.default_rng(5).choice([-1.0, 1.0], (4, 20)), device="cuda")
+    v, st = plan.predict_var_probes(pc, Xs, Zp, tol=1e-12, max_iter=1)
+    assert st == 1 and torch.isfinite(v).all()
+    with pytest.raises(TypeError):
+        plan.predict_var_probes(pc, Xs, Zp[:, :10])
+    Wk = workloads.ridge8d(n=300, skip_m=16, skip_rank=8)
+    sp = dski.DskipPlan(torch.tensor(Wk.X, device="cuda"), Wk.skip_m, Wk.skip_rank, SEED, Wk.log_ell, Wk.lo, Wk.hi)
+    sp.set_hypers(*Wk.hypers())
+    spc = sp.pivchol(5)
+    Xk = torch.tensor(_test_points(Wk, 5, 6), device="cuda")
+    for call in (lambda: sp.predict_grid(torch.zeros(sp.N, dtype=torch.float64, device="cuda")),
+                 lambda: sp.predict_var(spc, Xk),
+                 lambda: sp.predict_var_probes(spc, Xk, torch.ones((2, 5), dtype=torch.float64, device="cuda"))):
+        with pytest.raises(dski.DSKIError) as e:
+            call()
+        assert e.value.status == -5  # DSKI_ENOTSUP
