@@ -201,7 +201,8 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
     [f, grad f] of 1,000,000 uniform test points (16 grid reads each); the
     pivoted-Cholesky predictive variance (rank 100) of 4,096 of them, 128 per
     batch (one grid column each: stencil, K_UU, gather, preconditioner
-    projection); the randomized variance of 1,024 of them with 16 probes."""
+    projection); the randomized variance of 1,024 of them with 16 probes; the
+    EI acquisition over all 1,000,000 and its best candidate."""
     import numpy as np
     import torch
     from paper_1810_12283_amd import dski
@@ -213,6 +214,11 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
     g_ms = _events_stats(lambda: plan.predict_grid(alpha), reps, stream)[0]
     g = plan.predict_grid(alpha)
     p_ms = _events_stats(lambda: plan.predict(g, Xs), reps, stream)[0]
+    # EI acquisition over the same 1,000,000 candidates (value column of the
+    # means, synthetic variances)
+    mu_all = plan.predict(g, Xs)
+    var_all = torch.tensor(r.uniform(0.0, 1.0, npts), device="cuda")
+    ei_ms = _events_stats(lambda: dski.expected_improvement(mu_all, var_all, 0.0), reps, stream)[0]
     nvar = 4096
     pc = plan.pivchol(100)
     Xv = Xs[:nvar].contiguous()
@@ -232,6 +238,7 @@ def predict_block(W, stream, npts=1_000_000, reps=20):
     return {"workload": f"terrain n={W.n} grid={W.grid_m[0]}x{W.grid_m[1]}, {npts} test points",
             "grid_vector_ms": round(g_ms, 4), "predict_ms": round(p_ms, 4),
             "test_points_per_s": round(npts / (p_ms * 1e-3), 1),
+            "ei_ms": round(ei_ms, 4), "ei_candidates_per_s": round(npts / (ei_ms * 1e-3), 1),
             "variance_rank": 100, "variance_points": nvar, "variance_ms": round(v_ms, 3),
             "variance_points_per_s": round(nvar / (v_ms * 1e-3), 1),
             "randomized_variance": {"points": npv, "probes": nprb, "tol": W.tol, "s": round(pr_s, 3),
