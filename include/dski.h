@@ -179,7 +179,8 @@ dski_status dski_predict_var(dski_plan plan, dski_precond pc, int n_test, const 
  * dski_predict_var.  Allocates a work buffer of 3 N min(R, 32) + n_test doubles per call and
  * synchronizes `stream`.  DSKI_NOT_CONVERGED if a solve reached max_iter (out
  * then uses its last iterate), DSKI_EINVAL for a point outside the box,
- * DSKI_ENOTSUP for D-SKIP. */
+ * DSKI_ENOTSUP for D-SKIP.  The probe scatter adds overlapping stencils with
+ * atomics, so repeated calls can differ in the last bits. */
 dski_status dski_predict_var_probes(dski_plan plan, dski_precond pc, int n_test, const double* X_test,
                                     int R, const double* Zp, double tol, int max_iter, double* out,
                                     dski_stream stream);
