@@ -34,6 +34,9 @@ __global__ __launch_bounds__(256) void k_ei(int nc, const double* __restrict__ m
   if (j < nc) {
     e = ei_value(mu[(size_t)j * mu_stride], var[j], f_best, xi);
     if (ei) ei[j] = e;
+    // a NaN would absorb every partner it meets in the tree below and an
+    // infinite EI would win it: neither may be chosen
+    if (!isfinite(e)) e = -1.0;
   }
   sv[threadIdx.x] = e;
   si[threadIdx.x] = j;

@@ -256,6 +256,10 @@ class Plan:
         column 0 the value, column 1 + p the derivative along axis p."""
         if not Xs.is_cuda or Xs.dtype != torch.float64 or Xs.dim() != 2 or Xs.shape[1] != self.d:
             raise TypeError("Xs must be a CUDA float64 tensor of shape (n*, d)")
+        if not isinstance(g, torch.Tensor) or not g.is_cuda or g.dtype != torch.float64:
+            raise TypeError("g must be the CUDA float64 grid vector of predict_grid")
+        if self.grid_nodes and g.numel() != self.grid_nodes:
+            raise ValueError(f"g has {g.numel()} entries; this plan's grid has {self.grid_nodes} nodes")
         Xs = Xs.contiguous()
         out = torch.empty((Xs.shape[0], self.d + 1), dtype=torch.float64, device=Xs.device)
         _check(lib().dski_predict(self._h, _dptr(g.contiguous()), Xs.shape[0], _dptr(Xs), _dptr(out),
@@ -578,10 +582,15 @@ def active_project(X: torch.Tensor, G: Optional[torch.Tensor], P, stream=None):
     X = X.contiguous()
     n, D = X.shape
     Pt = torch.as_tensor(np.ascontiguousarray(P, dtype=np.float64), device=X.device)
+    if Pt.dim() != 2 or Pt.shape[0] != D or not 1 <= Pt.shape[1] <= D:
+        raise ValueError(f"P must be a (D, d) matrix with D = {D} and 1 <= d <= D, got {tuple(Pt.shape)}")
     d = Pt.shape[1]
     U = torch.empty((n, d), dtype=torch.float64, device=X.device)
     Gu = None
     if G is not None:
+        if not G.is_cuda or G.dtype != torch.float64 or G.dim() != 2 or tuple(G.shape) != (D, n):
+            raise ValueError(f"G must be a CUDA float64 tensor of shape (D, n) = ({D}, {n}), "
+                             f"got {tuple(G.shape)}")
         G = G.contiguous()
         Gu = torch.empty((d, n), dtype=torch.float64, device=X.device)
     _check(lib().dski_active_project(n, D, d, _dptr(X), _dptr(G) if G is not None else None, n, _dptr(Pt),

@@ -10,7 +10,7 @@ gradient (``mll_and_grad`` with a zero data vector, so only the log det terms
 remain).  During a fit the data-fit part (one PCG column, ``mll_and_grad``
 with zero probes) is exact and the log det comes from the network; every
 ``recheck`` evaluations SLQ re-computes the log det, and when the relative
-error exceeds ``fallback_tol`` the fit continues with plain SLQ.
+error exceeds ``fallback_tol`` L-BFGS restarts from that point on plain SLQ.
 
 This module only orchestrates device calls (and the 5-parameter L-BFGS on the
 host); every numerical step of the method runs in the library's kernels.
@@ -152,31 +152,52 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
 
     state = {"evals": 0, "fallback": surrogate is None, "rechecks": []}
     t0 = time.perf_counter()
+    d = plan.d
 
-    def objective(theta):
+    class _FallBack(Exception):
+        """Raised by a failed re-check: L-BFGS-B's curvature pairs and line
+        search were built on the surrogate, so the search restarts from this
+        point on plain SLQ instead of switching functions in mid-run."""
+
+        def __init__(self, theta):
+            super().__init__()
+            self.theta = theta
+
+    def slq_objective(theta):
         state["evals"] += 1
-        if state["fallback"]:
-            d = plan.d
-            plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
-            res = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=20000)
-            return -res["mll"], -np.asarray(res["grad"])
+        plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
+        res = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=20000)
+        return -res["mll"], -np.asarray(res["grad"])
+
+    def surrogate_objective(theta):
+        state["evals"] += 1
         dfit, dgrad = data_fit_and_grad(plan, theta, y, k, tol)
         ld, ldg = surrogate(theta)
         if state["evals"] % recheck == 0:
-            ld_slq, _ = logdet_and_grad(plan, theta, k, num_probes, seed, tol)
+            ld_slq, ldg_slq = logdet_and_grad(plan, theta, k, num_probes, seed, tol)
             err = abs(ld - ld_slq) / abs(ld_slq)
             state["rechecks"].append((state["evals"], ld, ld_slq, err))
             if err > fallback_tol:
                 state["fallback"] = True
-                ld, ldg = logdet_and_grad(plan, theta, k, num_probes, seed, tol)
+                raise _FallBack(np.array(theta, dtype=np.float64))
+            # the re-check's own value and gradient are the better ones here
+            ld, ldg = ld_slq, ldg_slq
         mll = dfit - 0.5 * ld
         grad = dgrad - 0.5 * ldg
         return -mll, -grad
 
-    res = minimize(objective, np.asarray(theta0, dtype=np.float64), jac=True, method="L-BFGS-B", bounds=bounds,
-                   options={"maxfun": max_evals, "gtol": gtol})
+    theta = np.asarray(theta0, dtype=np.float64)
+    res = None
+    if not state["fallback"]:
+        try:
+            res = minimize(surrogate_objective, theta, jac=True, method="L-BFGS-B", bounds=bounds,
+                           options={"maxfun": max_evals, "gtol": gtol})
+        except _FallBack as fb:
+            theta = fb.theta
+    if res is None:
+        res = minimize(slq_objective, theta, jac=True, method="L-BFGS-B", bounds=bounds,
+                       options={"maxfun": max(1, max_evals - state["evals"]), "gtol": gtol})
     # final value with the full method at the optimum
-    d = plan.d
     th = res.x
     plan.set_hypers(th[:d], th[d], th[d + 1], th[d + 2])
     final = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=20000)

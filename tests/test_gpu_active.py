@@ -59,3 +59,21 @@ def test_active_subspace_limits():
     P = np.eye(4)[:, :2]
     U, Gu = dski.active_project(torch.zeros((0, 4), dtype=torch.float64, device="cuda"), None, P)
     assert U.shape == (0, 2) and Gu is None
+
+
+def test_active_project_rejects_wrong_shapes():
+    """P must be (D, d) and G (D, n): the oracle's n x D gradient layout and a
+    transposed P are refused before any launch."""
+    dski = need_gpu()
+    r = np.random.default_rng(2)
+    X = torch.tensor(r.uniform(-1, 1, (50, 6)), device="cuda")
+    P = np.linalg.qr(r.standard_normal((6, 2)))[0]
+    G = torch.tensor(r.standard_normal((6, 50)), device="cuda")
+    with pytest.raises(ValueError):
+        dski.active_project(X, G, P.T)
+    with pytest.raises(ValueError):
+        dski.active_project(X, G.T.contiguous(), P)
+    with pytest.raises(ValueError):
+        dski.active_project(X, G.float(), P)
+    U, Gu = dski.active_project(X, G, P)
+    assert U.shape == (50, 2) and Gu.shape == (2, 50)

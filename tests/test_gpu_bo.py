@@ -62,6 +62,33 @@ def test_ei_rejects_all_non_finite():
     assert e.value.status == -1
 
 
+@pytest.mark.parametrize("lane", [0, 1])
+def test_ei_skips_nan_and_infinite_candidates(lane):
+    """A NaN EI (NaN mean, positive variance) at lane 0 or 1 of a block that
+    also holds the true maximum, and an infinite EI (infinite variance) in
+    another block: the best candidate is the finite maximum; the NaN and the
+    infinity still appear in the EI output."""
+    dski = need_gpu()
+    mu, var = _cands(1000, 13)
+    var = np.abs(var) + 0.1
+    j = 256 + 77                      # the true maximum, in block 1
+    mu[j] = -5.0
+    mu[256 + lane] = np.nan
+    var[600] = np.inf
+    f_best = 0.0
+    ok = np.isfinite(mu) & np.isfinite(var)
+    ref = np.full(mu.size, np.nan)
+    ref[ok] = bo.expected_improvement(mu[ok], var[ok], f_best)
+    say("ei nan lane", lane)
+    ei, idx, best = dski.expected_improvement(torch.tensor(mu, device="cuda"), torch.tensor(var, device="cuda"),
+                                              f_best)
+    e = ei.cpu().numpy()
+    assert np.isnan(e[256 + lane]) and not np.isfinite(e[600])
+    assert np.abs(e[ok] - ref[ok]).max() <= 1e-13 * ref[ok].max()
+    assert idx == j == int(np.nanargmax(np.where(ok, ref, -1.0)))
+    assert abs(best - ref[j]) <= 1e-13 * ref[j]
+
+
 def test_one_step_of_alg1_matches_oracle():
     """One step of Alg. 1 run through the GPU entry points and, independently,
     through the oracle: active subspace of a ridge function in D = 10 from

@@ -45,6 +45,22 @@ def test_predict_matches_oracle(name):
     assert eg < 1e-11 and em < 1e-11 and et < 1e-11
 
 
+def test_predict_rejects_a_wrong_grid_vector():
+    """The grid vector must be this plan's FP64 CUDA vector of prod(m) nodes:
+    an FP32 copy, a host copy and the vector of a smaller grid are refused
+    before any launch (the kernel reads 4^d nodes around each test point)."""
+    W = workloads.small2d()
+    plan, op = make(W)
+    g = plan.predict_grid(torch.tensor(_alpha(op.N, SEED), device="cuda"))
+    Xs = torch.tensor(_test_points(W, 10, SEED), device="cuda")
+    small, _ = make(W, grid=[20, 20])
+    g_small = small.predict_grid(torch.tensor(_alpha(op.N, SEED), device="cuda"))
+    for bad, exc in ((g.float(), TypeError), (g.cpu(), TypeError), (g_small, ValueError), (g[:-1], ValueError)):
+        with pytest.raises(exc):
+            plan.predict(bad, Xs)
+    assert plan.predict(g, Xs).shape == (10, W.d + 1)
+
+
 def test_predict_full_terrain_sampled():
     """Terrain size (n = 20,000, 200 x 200 grid): 200,000 test points on the
     GPU, checked against the oracle on a sample of 2,000 of them."""
