@@ -52,12 +52,6 @@ int sym_eig_jacobi(int k, double* A, double* V, double* w) {
   return sweep;
 }
 
-// e_1^T log(T) e_1 for the Lanczos tridiagonal of J CG steps,
-//   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_{j,j+1} = sqrt(beta_j)/alpha_j,
-// by the implicit symmetric QL iteration with Wilkinson-type shifts that
-// accumulates only the first row of the eigenvector matrix (Golub-Welsch):
-// the Ritz values theta_k and weights z_k^2 give sum_k z_k^2 log theta_k.
-// *ok = 0 if a Ritz value is not positive or the iteration fails.
 // sqrt(a^2 + b^2) without the cost of std::hypot where no overflow can occur
 static inline double fast_hypot(double a, double b) {
   const double m = std::fmax(std::fabs(a), std::fabs(b));
@@ -65,73 +59,92 @@ static inline double fast_hypot(double a, double b) {
   return std::sqrt(a * a + b * b);
 }
 
+// One implicit symmetric QR step with the Wilkinson shift on the unreduced
+// block lo..hi of the tridiagonal (a = diagonal, b[i] couples i and i + 1),
+// by bulge chasing (Golub & Van Loan, Matrix Computations, Sec. 8.3.5).  Each
+// plane rotation G (c, s) on coordinates (k, k + 1) replaces T by G^T T G; the
+// row vector q (first row of the accumulated eigenvector matrix) becomes q G.
+static void qr_step(double* a, double* b, double* q, int lo, int hi) {
+  // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer to a[hi]
+  const double half = 0.5 * (a[hi - 1] - a[hi]);
+  const double bt = b[hi - 1];
+  const double root = fast_hypot(half, bt);
+  const double mu = a[hi] - bt * bt / (half + (half >= 0.0 ? root : -root));
+  double x = a[lo] - mu, z = b[lo];
+  double bulge = 0.0;
+  for (int k = lo; k < hi; ++k) {
+    if (k > lo) {
+      x = b[k - 1];
+      z = bulge;
+    }
+    // c x - s z = r, s x + c z = 0
+    const double r = fast_hypot(x, z);
+    double c = 1.0, s = 0.0;
+    if (r != 0.0) {
+      c = x / r;
+      s = -z / r;
+    }
+    if (k > lo) b[k - 1] = r;
+    const double al = a[k], ga = a[k + 1], be = b[k];
+    const double cc = c * c, ss = s * s, cs = c * s;
+    a[k] = cc * al - 2.0 * cs * be + ss * ga;
+    a[k + 1] = ss * al + 2.0 * cs * be + cc * ga;
+    b[k] = cs * (al - ga) + (cc - ss) * be;
+    if (k + 1 < hi) {
+      bulge = -s * b[k + 1];
+      b[k + 1] *= c;
+    }
+    const double qk = q[k], qk1 = q[k + 1];
+    q[k] = c * qk - s * qk1;
+    q[k + 1] = s * qk + c * qk1;
+  }
+}
+
+// e_1^T log(T) e_1 for the Lanczos tridiagonal of J CG steps,
+//   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_{j,j+1} = sqrt(beta_j)/alpha_j,
+// as Gauss quadrature (Golub & Welsch, Math. Comp. 23, 1969): with
+// T = Q diag(theta) Q^T the value is sum_k Q_1k^2 log theta_k.  The
+// eigen-decomposition runs the symmetric tridiagonal QR algorithm (Wilkinson
+// shifts, deflation of negligible couplings from the bottom up), carrying only
+// the first row of Q.  *ok = 0 if a Ritz value is not positive or the
+// iteration does not converge.
 double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok) {
   *ok = 1;
   if (J <= 0) {
     *ok = 0;
     return 0.0;
   }
-  std::vector<double> d(J), e(J, 0.0), z(J, 0.0);
+  std::vector<double> a(J), b(J, 0.0), q(J, 0.0);
   for (int j = 0; j < J; ++j) {
-    d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
-    if (j + 1 < J) e[j] = std::sqrt(std::fmax(beta[j], 0.0)) / alpha[j];
+    a[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < J) b[j] = std::sqrt(std::fmax(beta[j], 0.0)) / alpha[j];
   }
-  z[0] = 1.0;
+  q[0] = 1.0;
   const double eps = 2.220446049250313e-16;
-  for (int l = 0; l < J; ++l) {
-    int iter = 0;
-    int m;
-    while (true) {
-      for (m = l; m < J - 1; ++m) {
-        double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= eps * dd) break;
-      }
-      if (m == l) break;
-      if (++iter > 200) {
-        *ok = 0;
-        return 0.0;
-      }
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = fast_hypot(g, 1.0);
-      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
-      double s = 1.0, c = 1.0, p = 0.0;
-      int i;
-      bool early = false;
-      for (i = m - 1; i >= l; --i) {
-        double f = s * e[i];
-        double b = c * e[i];
-        r = fast_hypot(f, g);
-        e[i + 1] = r;
-        if (r == 0.0) {
-          d[i + 1] -= p;
-          e[m] = 0.0;
-          early = true;
-          break;
-        }
-        s = f / r;
-        c = g / r;
-        g = d[i + 1] - p;
-        r = (d[i] - g) * s + 2.0 * c * b;
-        p = s * r;
-        d[i + 1] = g + p;
-        g = c * r - b;
-        double zf = z[i + 1];
-        z[i + 1] = s * z[i] + c * zf;
-        z[i] = c * z[i] - s * zf;
-      }
-      if (early) continue;
-      d[l] -= p;
-      e[l] = g;
-      e[m] = 0.0;
+  auto negligible = [&](int i) { return std::fabs(b[i]) <= eps * (std::fabs(a[i]) + std::fabs(a[i + 1])); };
+  int hi = J - 1, steps = 0;
+  while (hi > 0) {
+    if (negligible(hi - 1)) {
+      b[hi - 1] = 0.0;
+      --hi;
+      continue;
     }
-  }
-  double acc = 0.0;
-  for (int j = 0; j < J; ++j) {
-    if (!(d[j] > 0.0)) {
+    int lo = hi - 1;
+    while (lo > 0 && !negligible(lo - 1)) --lo;
+    if (lo > 0) b[lo - 1] = 0.0;
+    if (++steps > 60 * J) {
       *ok = 0;
       return 0.0;
     }
-    acc += z[j] * z[j] * std::log(d[j]);
+    qr_step(a.data(), b.data(), q.data(), lo, hi);
+  }
+  double acc = 0.0;
+  for (int j = 0; j < J; ++j) {
+    if (!(a[j] > 0.0)) {
+      *ok = 0;
+      return 0.0;
+    }
+    acc += q[j] * q[j] * std::log(a[j]);
   }
   return acc;
 }

@@ -9,8 +9,9 @@
 //                           it, in a fixed order (no atomics, bitwise
 //                           reproducible), FP64 accumulation;
 //   K_UU     G <- K_UU G    per axis, per grid line: circulant-embedded Toeplitz
-//                           product by an LDS radix-4/2 Stockham FFT (FP64), two
-//                           real lines packed into one complex transform;
+//                           product by a radix-8 Stockham FFT in registers with
+//                           LDS exchanges (FP64), two real lines packed into one
+//                           complex transform;
 //   gather   Y = S G + D V  one thread per point, FP64 accumulation, FP32 store,
 //                           optional fused per-block partials of V.Y.
 #include <cmath>

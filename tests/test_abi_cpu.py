@@ -57,3 +57,22 @@ def test_lanczos_quadrature_matches_oracle():
     assert got == pytest.approx(want, rel=1e-10, abs=1e-12)
     # a 1x1 tridiagonal is log(1/alpha)
     assert dski.lanczos_quad_log([0.25], []) == pytest.approx(np.log(4.0), rel=1e-15)
+
+
+@pytest.mark.parametrize("J,seed", [(2, 1), (7, 2), (300, 3), (3000, 4)])
+def test_lanczos_quadrature_random_cg_coefficients(J, seed):
+    """The host quadrature against LAPACK (the oracle's tridiagonal
+    eigen-solver) on CG coefficients of a random SPD spectrum: Lanczos
+    tridiagonals up to the lengths of a terrain solve, a spread of four
+    decades and a tight cluster of ten eigenvalues."""
+    dski = _lib()
+    from oracle import krylov, slq
+    r = np.random.default_rng(seed)
+    lam = np.concatenate([np.geomspace(1e-2, 1e2, 3990), 2.0 + 1e-9 * np.arange(10)])
+    lam = lam[r.permutation(lam.size)]
+    z = r.choice([-1.0, 1.0], lam.size)
+    res = krylov.pcg(lambda V: lam[:, None] * V, z, fixed_iters=J)
+    a, b = res["alpha"][0], res["beta"][0]
+    want = slq.quad_from_tridiag(*krylov.cg_tridiag(a, b))
+    got = dski.lanczos_quad_log(a, b[:-1])
+    assert got == pytest.approx(want, rel=1e-10, abs=1e-12)
