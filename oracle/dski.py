@@ -147,10 +147,14 @@ class DSKI:
         e[i, 0] = 1.0
         return self.matvec_K(e)[:, 0]
 
-    def dense_K(self):
-        """Dense S K_UU S^T (tiny problems only)."""
-        KS = self.kuu_apply(self.ST.toarray())
-        return (self.S @ KS)
+    def dense_K(self, chunk=512):
+        """Dense S K_UU S^T (small problems only), assembled `chunk` columns
+        at a time so that the grid-sized intermediate K_UU S^T stays small."""
+        out = np.empty((self.N, self.N))
+        for c0 in range(0, self.N, chunk):
+            c1 = min(self.N, c0 + chunk)
+            out[:, c0:c1] = self.S @ self.kuu_apply(self.ST[:, c0:c1].toarray())
+        return out
 
     def dense(self):
         return self.dense_K() + np.diag(self.Dn)

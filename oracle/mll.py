@@ -43,10 +43,17 @@ def exact_from_dense(op, A, cf, y):
     mll = -0.5 * (y @ alpha + logdet + N * math.log(2 * math.pi))
     Ainv = sla.cho_solve(cf, np.eye(N))
     grad = np.empty(op.d + 3)
-    eye = np.eye(N)
+    chunk = 512
     for j in range(op.d + 3):
-        dK = op.matvec_dtheta(j, eye)
-        grad[j] = 0.5 * alpha @ (dK @ alpha) - 0.5 * np.sum(Ainv * dK.T)
+        # tr(K~^{-1} dK) = sum_i (K~^{-1} dK)_ii, over column chunks of dK = dK I
+        tr = 0.0
+        for c0 in range(0, N, chunk):
+            c1 = min(N, c0 + chunk)
+            E = np.zeros((N, c1 - c0))
+            E[np.arange(c0, c1), np.arange(c1 - c0)] = 1.0
+            dKc = op.matvec_dtheta(j, E)
+            tr += np.sum(Ainv[c0:c1, :] * dKc.T)
+        grad[j] = 0.5 * alpha @ op.matvec_dtheta(j, alpha) - 0.5 * tr
     return dict(mll=mll, grad=grad, logdet=logdet, alpha=alpha)
 
 
