@@ -285,6 +285,18 @@ dski_status dski_plan_set_precision(dski_plan plan, int bits);
  * into the N-vector, may be NULL) receives the pivots. */
 dski_status pivchol_build(dski_plan plan, int k, dski_precond* out, int* rank_host,
                           int* piv_host, dski_stream stream);
+
+/* The same factorisation with the pivot of step j dictated by
+ * forced_piv_host[j] (k user-order N-indices, host memory) instead of the
+ * largest residual diagonal: it lets a caller reproduce another
+ * implementation's pivot sequence, which the near-constant D-SKI diagonal
+ * leaves to rounding at near-ties (Sec. 3.3).  The stop test still looks at
+ * the largest residual diagonal; a forced pivot whose residual diagonal is not
+ * positive (e.g. one chosen before) ends the factorisation there
+ * (DSKI_RANK_TRUNCATED).  DSKI_EINVAL if an index is outside 0..N-1. */
+dski_status pivchol_build_forced(dski_plan plan, int k, const int* forced_piv_host,
+                                 dski_precond* out, int* rank_host, int* piv_host,
+                                 dski_stream stream);
 dski_status dski_precond_destroy(dski_precond pc);
 
 /* Z = M^{-1} R for R vectors (user order); the Woodbury identity of Sec. 3.3

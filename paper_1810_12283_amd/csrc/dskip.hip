@@ -989,8 +989,9 @@ dski_status dskip_diag(dski_plan p, double* diag, hipStream_t st) {
 __global__ void k_dskip_pivot(const double* __restrict__ pv, const int* __restrict__ pi, int nblk, int j,
                               double rel_tol, PivState* __restrict__ ps, int* __restrict__ piv_list,
                               const double* __restrict__ Qa, const double* __restrict__ Qb, int N, int RP,
-                              double* __restrict__ prow, const double* __restrict__ L, double* __restrict__ lrow) {
-  const int e = pivot_select_block(pv, pi, nblk, j, rel_tol, ps, piv_list);
+                              double* __restrict__ prow, const double* __restrict__ L, double* __restrict__ lrow,
+                              const int* __restrict__ forced, const double* __restrict__ dres) {
+  const int e = pivot_select_block(pv, pi, nblk, j, rel_tol, ps, piv_list, forced, dres);
   if (e < 0) return;
   for (int k = threadIdx.x; k < RP; k += blockDim.x) {
     prow[k] = Qa[(size_t)k * N + e];
@@ -1022,12 +1023,13 @@ __global__ void k_dskip_column(int j, const PivState* __restrict__ ps, const dou
 }
 
 dski_status dskip_pc_step(dski_plan p, int j, const double* pv, const int* pi, int nblk, double rel_tol,
-                          PivState* ps, int* piv_list, double* L, double* lrow, double* dres, hipStream_t st) {
+                          PivState* ps, int* piv_list, double* L, double* lrow, double* dres, const int* forced,
+                          hipStream_t st) {
   DskipData* D = p->ds;
   DSKI_TRY(D->rows.reserve(sizeof(double) * 2 * D->RP));
   double* prow = D->rows.as<double>();
   k_dskip_pivot<<<1, kBlock, 0, st>>>(pv, pi, nblk, j, rel_tol, ps, piv_list, D->fa.Q, D->fb.Q, p->N, D->RP, prow,
-                                      L, lrow);
+                                      L, lrow, forced, dres);
   k_dskip_column<<<(p->N + kBlock - 1) / kBlock, kBlock, 0, st>>>(j, ps, D->fa.A, D->fb.A, p->N, D->RP,
                                                                   p->s * p->s, prow, lrow, L, dres);
   DSKI_HIP(hipGetLastError());

@@ -245,7 +245,8 @@ dski_status dskip_set_hypers(dski_plan p, const double* log_ell, hipStream_t st)
 dski_status dskip_diag(dski_plan p, double* diag, hipStream_t st);
 // one pivoted-Cholesky step j (after the arg-max partials pv/pi of nblk blocks)
 dski_status dskip_pc_step(dski_plan p, int j, const double* pv, const int* pi, int nblk, double rel_tol,
-                          PivState* ps, int* piv_list, double* L, double* lrow, double* dres, hipStream_t st);
+                          PivState* ps, int* piv_list, double* L, double* lrow, double* dres, const int* forced,
+                          hipStream_t st);
 void dskip_destroy(dski_plan p);
 
 // --- host numerics ---------------------------------------------------------------------

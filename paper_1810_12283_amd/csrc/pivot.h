@@ -10,10 +10,14 @@ namespace dski {
 // index among exact ties), the stop test (residual <= rel_tol * largest initial
 // diagonal, or not positive) and the bookkeeping of step j.  Called by every
 // thread of one work-group of kBlock threads; returns the pivot (tile-order
-// N-index) to all of them, or -1 once the factorisation has stopped.
+// N-index) to all of them, or -1 once the factorisation has stopped.  With a
+// forced list the pivot of step j is forced[j] instead of the arg-max (the
+// stop test still looks at the largest residual, and a forced pivot whose
+// residual diagonal dres is not positive stops the factorisation).
 __device__ inline int pivot_select_block(const double* __restrict__ pv, const int* __restrict__ pi,
                                          int nblk, int j, double rel_tol, PivState* __restrict__ ps,
-                                         int* __restrict__ piv_list) {
+                                         int* __restrict__ piv_list, const int* __restrict__ forced,
+                                         const double* __restrict__ dres) {
   __shared__ double sv[kBlock];
   __shared__ int si[kBlock];
   __shared__ int s_piv;
@@ -49,12 +53,19 @@ __device__ inline int pivot_select_block(const double* __restrict__ pv, const in
     }
     int stop = ps->stop;
     if (!stop && !(sv[0] > rel_tol * ps->dmax0 && sv[0] > 0.0)) stop = 1;
+    int pick = si[0];
+    double dpick = sv[0];
+    if (forced && !stop) {
+      pick = forced[j];
+      dpick = dres[pick];
+      if (!(dpick > 0.0)) stop = 1;
+    }
     ps->stop = stop;
-    s_piv = stop ? -1 : si[0];
+    s_piv = stop ? -1 : pick;
     if (!stop) {
-      ps->piv = si[0];
-      ps->dpiv = sv[0];
-      piv_list[j] = si[0];
+      ps->piv = pick;
+      ps->dpiv = dpick;
+      piv_list[j] = pick;
       ps->rank = j + 1;
     }
   }

@@ -129,8 +129,9 @@ __global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int*
                                int nblk, int j, double rel_tol, PivState* __restrict__ ps,
                                int* __restrict__ piv_list, const int* __restrict__ cell,
                                const double* __restrict__ toff, double* __restrict__ arow,
-                               const double* __restrict__ L, double* __restrict__ lrow) {
-  const int e = pivot_select_block(pv, pi, nblk, j, rel_tol, ps, piv_list);
+                               const double* __restrict__ L, double* __restrict__ lrow,
+                               const int* __restrict__ forced, const double* __restrict__ dres) {
+  const int e = pivot_select_block(pv, pi, nblk, j, rel_tol, ps, piv_list, forced, dres);
   if (e < 0) return;
   int blk = e / g.n, k = e % g.n;
   int c[DSKI_MAXD];
@@ -380,7 +381,7 @@ static void destroy_pc(dski_precond pc) {
 }
 
 static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_host, int* piv_host,
-                              hipStream_t st) {
+                              const int* forced, hipStream_t st) {
   int N = p->N, n = p->n;
   GeoP g = p->kind == 0 ? geop_of(p) : GeoP{};
   DSKI_HIP(hipMalloc(&pc->piv_tile, sizeof(int) * std::max(k, 1)));
@@ -413,12 +414,12 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     for (int j = 0; j < k; ++j) {
       k_argmax_partial<<<nblk, kBlock, 0, st>>>(dres, N, pv, pi);
       if (p->kind == 1) {
-        rc = dskip_pc_step(p, j, pv, pi, nblk, rel_tol, ps, pc->piv_tile, pc->L, lrow, dres, st);
+        rc = dskip_pc_step(p, j, pv, pi, nblk, rel_tol, ps, pc->piv_tile, pc->L, lrow, dres, forced, st);
         if (rc < 0) break;
         continue;
       }
       k_pivot_select<<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, pc->piv_tile, p->cell, p->toff,
-                                           arow, pc->L, lrow);
+                                           arow, pc->L, lrow, forced, dres);
       k_pc_column<<<vb, kBlock, 0, st>>>(g, j, ps, p->cell, p->toff, arow, lrow, pc->L, dres);
     }
     if (rc < 0) break;
@@ -531,28 +532,80 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
 
 using namespace dski;
 
-extern "C" {
-
-dski_status pivchol_build(dski_plan p, int k, dski_precond* out, int* rank_host, int* piv_host,
-                          dski_stream stream) {
+static dski_status build_entry(const char* who, dski_plan p, int k, dski_precond* out, int* rank_host,
+                               int* piv_host, const int* forced_user, hipStream_t st) {
   if (!p || !out || k < 0 || k > p->N || k > 1024) {
-    set_error("pivchol_build: bad arguments (k=%d)", k);
+    set_error("%s: bad arguments (k=%d)", who, k);
     return DSKI_EINVAL;
   }
   if (k > 256) {
-    set_error("pivchol_build: rank %d too large for this build (max 256)", k);
+    set_error("%s: rank %d too large for this build (max 256)", who, k);
     return DSKI_ENOTSUP;
   }
   *out = nullptr;
+  // forced pivots: user-order N-indices -> tile order, checked on the host
+  DevBuf fbuf;
+  const int* forced = nullptr;
+  if (forced_user && k > 0) {
+    const int n = p->n;
+    std::vector<int> perm(n), inv(n), ft(k);
+    if (p->kind == 0) {
+      if (hipMemcpy(perm.data(), p->perm, sizeof(int) * n, hipMemcpyDeviceToHost) != hipSuccess) {
+        set_error("%s: permutation copy failed", who);
+        return DSKI_EHIP;
+      }
+      for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+    } else {
+      for (int i = 0; i < n; ++i) inv[i] = i;
+    }
+    for (int j = 0; j < k; ++j) {
+      const int e = forced_user[j];
+      if (e < 0 || e >= p->N) {
+        set_error("%s: forced pivot %d of step %d is outside 0..N-1", who, e, j);
+        return DSKI_EINVAL;
+      }
+      ft[j] = (e / n) * n + inv[e % n];
+    }
+    DSKI_TRY(fbuf.reserve(sizeof(int) * k));
+    if (hipMemcpyAsync(fbuf.as<int>(), ft.data(), sizeof(int) * k, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      fbuf.release();
+      set_error("%s: forced pivot copy failed", who);
+      return DSKI_EHIP;
+    }
+    forced = fbuf.as<int>();
+  }
   dski_precond pc = new dski_precond_s();
   pc->plan = p;
-  dski_status rc = build_impl(p, k, pc, rank_host, piv_host, static_cast<hipStream_t>(stream));
+  dski_status rc = build_impl(p, k, pc, rank_host, piv_host, forced, st);
+  if (forced) {
+    // the build has synchronised its stream before returning
+    hipStreamSynchronize(st);
+    fbuf.release();
+  }
   if (rc < 0) {
     destroy_pc(pc);
     return rc;
   }
   *out = pc;
   return rc;
+}
+
+extern "C" {
+
+dski_status pivchol_build(dski_plan p, int k, dski_precond* out, int* rank_host, int* piv_host,
+                          dski_stream stream) {
+  return build_entry("pivchol_build", p, k, out, rank_host, piv_host, nullptr, static_cast<hipStream_t>(stream));
+}
+
+dski_status pivchol_build_forced(dski_plan p, int k, const int* forced_piv_host, dski_precond* out,
+                                 int* rank_host, int* piv_host, dski_stream stream) {
+  if (!forced_piv_host) {
+    set_error("pivchol_build_forced: NULL pivot list");
+    return DSKI_EINVAL;
+  }
+  return build_entry("pivchol_build_forced", p, k, out, rank_host, piv_host, forced_piv_host,
+                     static_cast<hipStream_t>(stream));
 }
 
 dski_status dski_precond_destroy(dski_precond pc) {

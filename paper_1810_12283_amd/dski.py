@@ -60,6 +60,7 @@ _SIGS = {
     "dski_tile_order": (C.c_int, [vp, ip]),
     "dski_mvm_tiled": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "pivchol_build": (C.c_int, [vp, C.c_int, C.POINTER(vp), ip, ip, vp]),
+    "pivchol_build_forced": (C.c_int, [vp, C.c_int, ip, C.POINTER(vp), ip, ip, vp]),
     "dski_precond_destroy": (C.c_int, [vp]),
     "dski_precond_apply": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_precond_logdet": (C.c_int, [vp, dp]),
@@ -334,8 +335,8 @@ class Plan:
         _check(lib().dski_tile_order(self._h, perm), "dski_tile_order")
         return np.frombuffer(perm, dtype=np.int32).copy()
 
-    def pivchol(self, k: int, stream=None) -> "Precond":
-        return Precond(self, k, stream)
+    def pivchol(self, k: int, stream=None, forced=None) -> "Precond":
+        return Precond(self, k, stream, forced=forced)
 
     def pcg(self, B: torch.Tensor, precond: Optional["Precond"] = None, tol=1e-4, max_iter=10000,
             history=False, stream=None):
@@ -430,13 +431,23 @@ class MarginalLikelihood(torch.autograd.Function):
 class Precond:
     """Pivoted-Cholesky preconditioner (owns a dski_precond)."""
 
-    def __init__(self, plan: Plan, k: int, stream=None):
+    def __init__(self, plan: Plan, k: int, stream=None, forced=None):
+        """forced: optional pivot sequence (k user-order N-indices) that replaces
+        the greedy choice (pivchol_build_forced)."""
         self.plan = plan
         h = vp()
         rank = C.c_int()
         piv = (C.c_int * max(k, 1))()
-        self.status = _check(lib().pivchol_build(plan.handle, int(k), C.byref(h), C.byref(rank), piv,
-                                                 _stream(stream)), "pivchol_build")
+        if forced is None:
+            self.status = _check(lib().pivchol_build(plan.handle, int(k), C.byref(h), C.byref(rank), piv,
+                                                     _stream(stream)), "pivchol_build")
+        else:
+            f = [int(v) for v in forced]
+            if len(f) != k:
+                raise ValueError(f"forced holds {len(f)} pivots, k = {k}")
+            self.status = _check(lib().pivchol_build_forced(plan.handle, int(k), _arr(f, C.c_int), C.byref(h),
+                                                            C.byref(rank), piv, _stream(stream)),
+                                 "pivchol_build_forced")
         self._h = h
         self.rank = rank.value
         self.pivots = np.array([piv[i] for i in range(self.rank)], dtype=np.int64)
