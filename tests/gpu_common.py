@@ -54,6 +54,17 @@ def rel_cols(a, b):
     return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
 
 
+def rel_cols_max(a, b):
+    """Element-wise bar: per column, the largest |a - b| over the largest |b|
+    (catches an error at a few entries that a 2-norm over N entries hides)."""
+    return np.abs(a - b).max(axis=0) / np.abs(b).max(axis=0)
+
+
+def mvm_errors(Y, ref):
+    """(2-norm error, element-wise error), each the worst over the columns."""
+    return float(rel_cols(Y, ref).max()), float(rel_cols_max(Y, ref).max())
+
+
 def small_workloads():
     return [
         ("small2d", workloads.small2d()),
