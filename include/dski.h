@@ -235,6 +235,19 @@ dski_status dski_mvm_tiled(dski_plan plan, int R, const float* V, int ldv, float
 dski_status dski_mvm_tiled_f64(dski_plan plan, int R, const double* V, int ldv, double* Y,
                                int ldy, dski_stream stream);
 
+/* dski_mvm_tiled for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the grid workspace (M x R doubles, M = grid
+ * nodes) in a fixed 16 MiB device array of the library instead of the plan's
+ * growable buffer.  No call allocates or frees device memory.  Limits:
+ * M * R <= 2,097,152 (e.g. R <= 52 on a 200 x 200 grid, R <= 18 on 48^3);
+ * beyond that DSKI_EINVAL; D-SKIP plans DSKI_ENOTSUP.  Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents: calls that
+ * overlap on one GPU (two streams, two host threads) race and must be ordered
+ * by the caller.  The array is held on each GPU until the process ends. */
+dski_status dski_mvm_tiled_noalloc(dski_plan plan, int R, const float* V, int ldv, float* Y,
+                                   int ldy, dski_stream stream);
+
 /* One stage of dski_mvm_tiled, for profiling and custom pipelines: stage 0 =
  * scatter G = S^T V into the plan's FP64 grid workspace (M x R), stage 1 =
  * G <- K_UU G in place (FFT, one launch per axis), stage 2 = gather

@@ -15,6 +15,7 @@
 //   gather   Y = S G + D V  one thread per point, FP64 accumulation, FP32 store,
 //                           optional fused per-block partials of V.Y.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -1261,16 +1262,55 @@ template dski_status gather<float>(dski_plan, int, const double*, const float*, 
 template dski_status gather<double>(dski_plan, int, const double*, const double*, int, double*, int,
                                     double, double, double*, hipStream_t);
 
+// The three stages on a caller-chosen grid workspace G (M x R doubles).
+template <typename T>
+static dski_status mvm_tiled_on(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double* pq_partial,
+                                double* G, hipStream_t st) {
+  DSKI_TRY(scatter<T>(p, R, V, ldv, G, st));
+  DSKI_TRY(apply_kuu(p, R, G, st));
+  return gather<T>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, pq_partial, st);
+}
+
 template <typename T>
 dski_status mvm_tiled(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double* pq_partial,
                       hipStream_t st) {
   if (R <= 0) return DSKI_OK;
   if (p->kind == 1) return dskip_mvm<T>(p, R, V, ldv, Y, ldy, pq_partial, st);
   DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
-  double* G = p->grid.as<double>();
-  DSKI_TRY(scatter<T>(p, R, V, ldv, G, st));
-  DSKI_TRY(apply_kuu(p, R, G, st));
-  return gather<T>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, pq_partial, st);
+  return mvm_tiled_on<T>(p, R, V, ldv, Y, ldy, pq_partial, p->grid.as<double>(), st);
+}
+
+// ------------------------------------------------------------------ fixed workspace
+// The grid workspace of dski_mvm_tiled_noalloc: a file-scope device array of
+// kNoAllocBytes, one copy on every GPU the library is loaded on, held until
+// the process ends.  Host code must not pass the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): its device address is looked
+// up once per device with hipGetSymbolAddress and kept in noalloc_ptr.
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+static std::mutex noalloc_mu;
+static double* noalloc_ptr[kMaxDevices];
+
+static dski_status noalloc_workspace(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error("dski_mvm_tiled_noalloc: no current device (or device id %d beyond %d)", dev, kMaxDevices);
+    return DSKI_EHIP;
+  }
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error("dski_mvm_tiled_noalloc: hipGetSymbolAddress of the workspace failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return DSKI_EHIP;
+    }
+    noalloc_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = noalloc_ptr[dev];
+  return DSKI_OK;
 }
 template dski_status mvm_tiled<float>(dski_plan, int, const float*, int, float*, int, double*,
                                       hipStream_t);
@@ -1377,6 +1417,26 @@ dski_status dski_mvm_tiled_f64(dski_plan p, int R, const double* V, int ldv, dou
                                dski_stream stream) {
   DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
   return mvm_tiled<double>(p, R, V, ldv, Y, ldy, nullptr, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_mvm_tiled_noalloc(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
+                                   dski_stream stream) {
+  DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
+  if (p->kind != 0) {
+    set_error("dski_mvm_tiled_noalloc: D-SKIP plans are not supported (their product has no grid stage)");
+    return DSKI_ENOTSUP;
+  }
+  if (R == 0 || p->n == 0) return DSKI_OK;
+  const size_t need = sizeof(double) * (size_t)p->M * (size_t)R;
+  if (need > kNoAllocBytes) {
+    set_error("dski_mvm_tiled_noalloc: %d columns on %lld grid nodes need %zu bytes of grid workspace; the "
+              "fixed workspace holds %zu (grid nodes x columns <= %zu)",
+              R, (long long)p->M, need, kNoAllocBytes, kNoAllocBytes / sizeof(double));
+    return DSKI_EINVAL;
+  }
+  double* G = nullptr;
+  DSKI_TRY(noalloc_workspace(&G));
+  return mvm_tiled_on<float>(p, R, V, ldv, Y, ldy, nullptr, G, static_cast<hipStream_t>(stream));
 }
 
 dski_status dski_mvm_stage(dski_plan p, int stage, int R, const float* V, int ldv, float* Y, int ldy,

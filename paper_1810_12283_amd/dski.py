@@ -59,6 +59,7 @@ _SIGS = {
     "dski_permute": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_tile_order": (C.c_int, [vp, ip]),
     "dski_mvm_tiled": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
+    "dski_mvm_tiled_noalloc": (C.c_int, [vp, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "pivchol_build": (C.c_int, [vp, C.c_int, C.POINTER(vp), ip, ip, vp]),
     "pivchol_build_forced": (C.c_int, [vp, C.c_int, ip, C.POINTER(vp), ip, ip, vp]),
     "dski_precond_destroy": (C.c_int, [vp]),
@@ -231,6 +232,16 @@ class Plan:
         _check(_fn("dski_mvm_tiled", V)(self._h, V.shape[0], _dptr(V), self.N, _dptr(Y), self.N,
                                     _stream(stream)), "dski_mvm_tiled")
         return Y
+
+    def mvm_tiled_noalloc(self, V: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """dski_mvm_tiled with the library's fixed grid workspace (no device
+        allocation inside the call): FP32 tile-ordered V (R x N) into out."""
+        V = _block(V, self.N, "V")
+        if V.dtype != torch.float32 or out.dtype != torch.float32 or out.shape != V.shape or not out.is_cuda:
+            raise TypeError("V and out must be CUDA float32 tensors of the same shape (R, N)")
+        _check(lib().dski_mvm_tiled_noalloc(self._h, V.shape[0], _dptr(V), self.N, _dptr(out), self.N,
+                                            _stream(stream)), "dski_mvm_tiled_noalloc")
+        return out
 
     def mvm_stage(self, stage: int, V: torch.Tensor, Y: Optional[torch.Tensor] = None, stream=None):
         """One stage of the tile-ordered MVM (0 scatter, 1 K_UU, 2 gather into Y)."""
