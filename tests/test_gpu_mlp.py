@@ -75,14 +75,21 @@ def test_mlp_backward_and_adam(B):
         err = np.abs(Gg[k] - Gr[k]).max() / max(np.abs(Gr[k]).max(), 1e-30)
         say("  grad", k, err)
         assert err < 1e-5, k
-    # one Adam step from zero moments
-    net.step(lr=1e-3)
+    # five Adam steps from zero moments, each on the gradient at the current
+    # parameters (beyond the first step the bias corrections and both decay
+    # rates matter)
     state = {}
     Pn = {k: v.copy() for k, v in P.items()}
-    omlp.adam_step(Pn, Gr, state, lr=1e-3)
-    Pg = _unpack(net.params())
-    for k in Pn:
-        assert np.abs(Pg[k] - Pn[k]).max() < 2e-6, k
+    for step in range(5):
+        if step > 0:
+            net.backward(Xd, td, gd, lam)
+            Gr = omlp.backward(Pn, X64, t64, g64, lam)
+        net.step(lr=1e-3, beta1=0.8, beta2=0.95)
+        omlp.adam_step(Pn, Gr, state, lr=1e-3, beta1=0.8, beta2=0.95)
+        Pg = _unpack(net.params())
+        dev = max(np.abs(Pg[k] - Pn[k]).max() for k in Pn)
+        say("  Adam step", step + 1, "max parameter deviation", dev)
+        assert dev < 2e-6 * (step + 1)
 
 
 def test_mlp_training_reduces_the_loss_on_a_smooth_target():

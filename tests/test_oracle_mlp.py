@@ -67,3 +67,21 @@ def test_adam_first_step_moves_by_lr():
     mlp.adam_step(P, G, {}, lr=0.01)
     # with bias correction the first step is lr * sign(g) (up to eps)
     np.testing.assert_allclose(P["w"], [1.0 - 0.01, -2.0 + 0.01], rtol=1e-7)
+
+
+def test_adam_two_steps_hand_computed():
+    """Two Adam steps worked out by hand with beta1 = 0.5, beta2 = 0.75,
+    eps = 0 (Kingma & Ba 2015, Alg. 1), where a wrong decay or bias-correction
+    exponent changes the second step (the first is lr * sign(g) whatever the
+    betas):
+      t = 1: m = 0.25, v = 0.0625, m^ = 0.5, v^ = 0.25, step 0.1  -> 0.9
+      t = 2: m = -0.375, v = 0.296875, m^ = -0.5, v^ = 19/28,
+             step -0.1 * 0.5 / sqrt(19/28) = -0.0606976979 -> 0.9606976979"""
+    P = {"w": np.array([1.0])}
+    state = {}
+    mlp.adam_step(P, {"w": np.array([0.5])}, state, lr=0.1, beta1=0.5, beta2=0.75, eps=0.0)
+    np.testing.assert_allclose(P["w"], [0.9], rtol=1e-15)
+    mlp.adam_step(P, {"w": np.array([-1.0])}, state, lr=0.1, beta1=0.5, beta2=0.75, eps=0.0)
+    np.testing.assert_allclose(P["w"], [0.9606976978666885], rtol=1e-14)
+    np.testing.assert_allclose(state["m_w"], [-0.375], rtol=1e-15)
+    np.testing.assert_allclose(state["v_w"], [0.296875], rtol=1e-15)
