@@ -49,11 +49,11 @@ class DSKI:
 
     theta: log_ell (d,), log_s, log_sigma_f, log_sigma_g (natural logs)."""
 
-    def __init__(self, X, grid_m, lo_box, hi_box, log_ell, log_s, log_sigma_f, log_sigma_g):
+    def __init__(self, X, grid_m, lo_box, hi_box, log_ell, log_s, log_sigma_f, log_sigma_g, interp_kind="cubic"):
         self.X = np.asarray(X, dtype=np.float64)
         self.n, self.d = self.X.shape
         self.N = self.n * (self.d + 1)
-        self.grid = interp.Grid(lo_box, hi_box, grid_m)
+        self.grid = interp.Grid(lo_box, hi_box, grid_m, interp_kind)
         self.S = interp.interp_matrices(self.X, self.grid)
         self.ST = self.S.T.tocsr()
         self.set_hypers(log_ell, log_s, log_sigma_f, log_sigma_g)
