@@ -70,20 +70,27 @@ const char* dski_last_error(void);
 /* Build version string (library build identifier). */
 const char* dski_version(void);
 
+/* Interpolation kernels of the D-SKI weights (Sec. 3.1). */
+#define DSKI_INTERP_CUBIC 0    /* Keys' cubic convolution (a = -1/2), 4 nodes per axis      */
+#define DSKI_INTERP_QUINTIC 1  /* the quintic convolution kernel of Meijering et al. (1999):
+                                * 6 nodes per axis, C^2, reproduces quartics               */
+
 /* Create a D-SKI plan for n points in d = 1..3 dimensions (Sec. 3.1).
  *   X        : n x d row-major FP64 point coordinates (device).
- *   grid_m   : d grid sizes m_p >= 4 (host).
+ *   grid_m   : d grid sizes m_p >= S (host), S = 4 (cubic) or 6 (quintic)
+ *              stencil nodes per axis.
  *   lo, hi   : data box per axis (host, FP64).  The grid is h_p =
- *              (hi_p - lo_p)/(m_p - 3), first node lo_p - h_p, so every point
- *              of the box has its 4-node stencil inside the grid.  NULL for
- *              both = the bounding box of X.
+ *              (hi_p - lo_p)/(m_p - S + 1), first node lo_p - (S/2 - 1) h_p,
+ *              so every point of the box has its S-node stencil inside the
+ *              grid.  NULL for both = the bounding box of X.
+ *   interp   : DSKI_INTERP_CUBIC or DSKI_INTERP_QUINTIC.
  * Setup (per data set, independent of the hyper-parameters): cell index and
  * offsets of every point, points sorted by cell ("tile order"), per-axis FFT
  * sizes.  Points outside the box give DSKI_EINVAL.  Hyper-parameters start at
  * log ell = log s = 0, log sigma = log 0.1; call dski_set_hypers. */
 dski_status dski_plan_create(dski_plan* out, int n, int d, const double* X,
                              const int* grid_m_host, const double* lo_host,
-                             const double* hi_host, dski_stream stream);
+                             const double* hi_host, int interp, dski_stream stream);
 dski_status dski_plan_destroy(dski_plan plan);
 
 /* D-SKIP operator (Sec. 3.2) for higher d: the kernel matrix of the product SE

@@ -83,7 +83,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
   double* G = p->grid.as<double>();
   for (int v = 0; v < (p->kind == 0 ? kScatterVariants : 0); ++v) {
     p->scatter_variant = v;
-    DSKI_TRY(time_us([&]() { return scatter<float>(p, R, V, N, G, st); }, reps, st, &t[v]));
+    DSKI_TRY(time_us([&]() { return scatter<float, double>(p, R, V, N, G, st); }, reps, st, &t[v]));
     if (t[v] < t[best_s]) best_s = v;
   }
   p->scatter_variant = best_s;
@@ -99,12 +99,13 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
     double t64[kScatterVariants] = {0};
     for (int v = 0; v < kScatterVariants; ++v) {
       p->scatter_variant64 = v;
-      DSKI_TRY(time_us([&]() { return scatter<double>(p, R, V64, N, G, st); }, reps, st, &t64[v]));
+      DSKI_TRY(time_us([&]() { return scatter<double, double>(p, R, V64, N, G, st); }, reps, st, &t64[v]));
       if (t64[v] < t64[best64]) best64 = v;
     }
     p->scatter_variant64 = best64;
     DSKI_HIP(hipStreamSynchronize(st));
     buf64.release();
+    DSKI_TRY((scatter<float, double>(p, R, V, N, G, st)));  // the FP32 columns' grid for the stages below
   }
   // gather: columns per thread (on the scattered grid; writes into the second half of V)
   int best_g = 0;
@@ -115,7 +116,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
     for (int v = 0; v < kGatherVariants; ++v) {
       p->gather_variant = v;
       double* tg = t + kScatterVariants;
-      DSKI_TRY(time_us([&]() { return gather<float>(p, R, G, V, N, Y, N, 1.0, 1.0, nullptr, st); }, reps, st,
+      DSKI_TRY(time_us([&]() { return gather<float, double>(p, R, G, V, N, Y, N, 1.0, 1.0, nullptr, st); }, reps, st,
                        &tg[v]));
       if (tg[v] < tg[best_g]) best_g = v;
     }
@@ -132,7 +133,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
         ta[v] = -1.0;
         continue;
       }
-      DSKI_TRY(time_us([&]() { return kuu_axis(p, R, G, st, -1, a, v); }, reps, st, &ta[v]));
+      DSKI_TRY(time_us([&]() { return kuu_axis<double>(p, R, G, st, -1, a, v); }, reps, st, &ta[v]));
       if (ta[v] < ta[best]) best = v;
     }
     p->kuu_variant[a] = best;

@@ -1073,7 +1073,8 @@ static dski_status dskip_create_impl(dski_plan p, const double* X, const double*
     DSKI_HIP(hipGetLastError());
     dski_plan sp = nullptr;
     int m = D->m1;
-    DSKI_TRY(dski_plan_create(&sp, n, 1, col.as<double>(), &m, lo ? lo + a : nullptr, hi ? hi + a : nullptr, st));
+    DSKI_TRY(dski_plan_create(&sp, n, 1, col.as<double>(), &m, lo ? lo + a : nullptr, hi ? hi + a : nullptr,
+                              DSKI_INTERP_CUBIC, st));
     D->sub.push_back(sp);
     int* ip = nullptr;
     DSKI_HIP(hipMalloc(&ip, sizeof(int) * (size_t)n));

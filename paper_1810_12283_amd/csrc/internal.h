@@ -84,24 +84,10 @@ __host__ __device__ constexpr int fft_tw_size(int lg) { return fft_tw_offset(lg,
 constexpr int kFftMaxLog2 = 11;  // L <= 2048, m <= 1024 per axis
 constexpr int kDenseMaxM = 448;  // largest axis for the dense matrix-core Toeplitz product
 
-// Keys cubic-convolution weights (a = -1/2) of the four stencil nodes i - 1 ..
-// i + 2 at offset t in [0, 1] of cell i, and their derivatives times 1 / h.
-__device__ __forceinline__ void keys_weights(double t, double ih, double* w, double* dw) {
-  const double t2 = t * t, t3 = t2 * t;
-  w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
-  w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-  w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-  w[3] = 0.5 * (t3 - t2);
-  dw[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0) * ih;
-  dw[1] = 0.5 * (9.0 * t2 - 10.0 * t) * ih;
-  dw[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0) * ih;
-  dw[3] = 0.5 * (3.0 * t2 - 2.0 * t) * ih;
-}
-
 // Per-axis geometry of the grid and its circulant embedding.
 struct Axis {
   int m = 0;          // grid nodes
-  int ncell = 0;      // interpolation cells = m - 3
+  int ncell = 0;      // interpolation cells = m - S + 1 (S stencil nodes per axis)
   int L = 0;          // circulant length (power of two >= 2m - 1)
   double lo = 0, h = 0;
   double* twiddle = nullptr;  // fft_tw_size(log2 L) complex pass twiddles (device, interleaved re, im)
@@ -127,6 +113,7 @@ struct dski_plan_s {
   int kind = 0;                // 0 D-SKI (grid), 1 D-SKIP (Hadamard of 1-D factors)
   dski::DskipData* ds = nullptr;
   int n = 0, d = 0, N = 0;
+  int S = 4;                   // stencil nodes per axis: 4 cubic (Keys), 6 quintic
   long long M = 0;             // grid nodes
   int ncells = 0;              // total interpolation cells
   dski::Axis ax[DSKI_MAXD];
@@ -135,19 +122,17 @@ struct dski_plan_s {
   double s = 1, sf = 0.1, sg = 0.1;
   // point data in tile order (device)
   int* perm = nullptr;         // tile position -> user index
-  int* cell = nullptr;         // linear cell id per tile position
-  double* toff = nullptr;      // d x n offsets in [0, 1] (SoA, FP64)
-  double* wts = nullptr;       // d x 8 x n: Keys weights w_0..w_3 and dw_0..dw_3 / h per axis (FP64)
+  int* cell = nullptr;         // linear cell id per tile position (per axis: first stencil node)
+  double* toff = nullptr;      // d x n offsets in [0, 1] (SoA, FP64); the weights follow from them
   int* cell_start = nullptr;   // ncells + 1
   // scatter region tables (per node tile: its region's points, see mvm.hip)
   int* tile_off = nullptr;     // tiles + 1 slot offsets
   int* tile_lcs = nullptr;     // tiles x (region cells + 1) local point ranges
   int* tile_pts = nullptr;     // slots: point (tile order)
-  int* tile_cl = nullptr;      // slots: last-axis cell of the point
-  double* tile_w = nullptr;    // 8 d x slots: the point's weights
+  int* tile_cl = nullptr;      // slots: last-axis anchor node of the point
   long long tile_slots = 0;
   // workspaces
-  dski::DevBuf grid;           // FP64 grid buffer, M * Rmax
+  dski::DevBuf grid;           // grid buffer, M * Rmax values (FP32 or FP64)
   dski::DevBuf vin, vout;      // tile-ordered FP32 vectors
   dski::DevBuf partial;        // FP64 block partials
   dski::DevBuf scal;           // FP64 small scalars
@@ -179,14 +164,18 @@ namespace dski {
 constexpr int kBlock = 256;
 
 // --- plan / grid ------------------------------------------------------------------
-// T is the storage type of N-vectors (float or double); grids are FP64.
-dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich = -1);
-dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, int a, int variant);
-template <typename T>
-dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st);
+// T is the storage type of N-vectors (float or double), GT that of the grid
+// (instantiated for FP64 grids: <float, double>, <double, double>); sums and
+// transforms run in FP64.
+template <typename GT>
+dski_status apply_kuu(dski_plan p, int R, GT* G, hipStream_t st, int dwhich = -1);
+template <typename GT>
+dski_status kuu_axis(dski_plan p, int R, GT* G, hipStream_t st, int dwhich, int a, int variant);
+template <typename T, typename GT>
+dski_status scatter(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st);
 dski_status scatter_tables(dski_plan p, hipStream_t st);  // build the region tables (plan set-up)
-template <typename T>
-dski_status gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
+template <typename T, typename GT>
+dski_status gather(dski_plan p, int R, const GT* G, const T* V, int ldv, T* Y, int ldy,
                    double nv, double ng, double* pq_partial, hipStream_t st);
 template <typename T>
 dski_status mvm_dtheta(dski_plan p, int which, int R, const T* V, int ldv, T* Y, int ldy,

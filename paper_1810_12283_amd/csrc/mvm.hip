@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "interp.h"
 
 namespace dski {
 
@@ -41,8 +42,12 @@ static GeoK geo_of(dski_plan p) {
 // ------------------------------------------------------------------ scatter
 // Grid node j receives sum over points k with j in stencil(k) of
 //   w(x_k)_j V_0[k] + sum_q d_q w(x_k)_j V_q[k].
-// Cell c (1-based per axis) covers nodes c-1..c+2, so node j is touched by
-// cells j-2..j+1 (clipped to 1..m-3); its stencil position in cell c is j-c+1.
+// A point's cell on axis a is its stencil's anchor node c_a (stored 0-based as
+// c_a - H, H = S/2 - 1); its S stencil nodes are c_a - H + o, o < S, so node j
+// is touched by the cells j - (S - 1 - H) .. j + H (clipped to H .. nc + H - 1)
+// at stencil position o = j - c + H.  The weights are computed from the point
+// offsets by interp_weights<S>, the function the gather uses too, so the
+// scatter applies exactly the transpose of the gather's interpolation.
 // The contribution of one point to one node for CR columns: the stencil
 // weights of the node on every axis (value wv, derivative wd) form
 // w = prod wv and d_q w = wd_q prod_{a != q} wv_a, and each column adds
@@ -72,36 +77,54 @@ __device__ __forceinline__ void scatter_accum(double (&acc)[CR], const double (&
   }
 }
 
+// Value and derivative weight of stencil position o (o < S) at offset t:
+// all S weights are formed as in interp_weights<S> and the one at o selected
+// (a select chain, no indexed private array).
+template <int S>
+__device__ __forceinline__ void interp_weight_at(double t, double ih, int o, double& wv, double& wd) {
+  double w[S], dw[S];
+  interp_weights<S>(t, ih, w, dw);
+  wv = w[0];
+  wd = dw[0];
+#pragma unroll
+  for (int u = 1; u < S; ++u) {
+    wv = o == u ? w[u] : wv;
+    wd = o == u ? dw[u] : wd;
+  }
+}
+
 // LDS-staged version: a work-group owns a tile of grid nodes and one chunk of
 // CR columns.  It copies into LDS the weights and the CR column values of every
 // point in the cells whose stencils reach the tile (the tile's cells plus a
-// halo of 2 below / 1 above), with a table of each cell's range, then every
-// thread sums its node's contributions from LDS in the same fixed order as
-// above.  Up to PMAX = 256 region points one thread stages one point; regions
-// with more points fall back to reading through the cache (same order, same
-// result).  VS is the type the column values are held in LDS (the input type,
-// or FP64 to convert once at staging).
-template <int D>
+// halo of S - 1 - H below and H above), with a table of each cell's range, then
+// every thread sums its node's contributions from LDS in the same fixed order
+// as above.  Up to PMAX = 256 region points one thread stages one point;
+// regions with more points fall back to reading through the cache (same order,
+// same result).
+template <int D, int S>
 struct TileShape {
   static constexpr int e0 = D == 1 ? 256 : (D == 2 ? 16 : 4);
   static constexpr int e1 = D == 2 ? 16 : 8;
   static constexpr int e2 = 8;
+  static constexpr int HALO = S - 1;  // region cells beyond a tile's node extent
   static __host__ __device__ constexpr int ext(int a) { return a == 0 ? e0 : (a == 1 ? e1 : e2); }
-  static constexpr int max_cells = D == 1 ? (e0 + 3) : (D == 2 ? (e0 + 3) * (e1 + 3) : (e0 + 3) * (e1 + 3) * (e2 + 3));
-  static constexpr int max_rows = D == 1 ? 1 : (D == 2 ? (e0 + 3) : (e0 + 3) * (e1 + 3));
-  static constexpr int last_span = ext(D - 1) + 3;
+  static constexpr int max_cells = D == 1 ? (e0 + HALO)
+                                          : (D == 2 ? (e0 + HALO) * (e1 + HALO)
+                                                    : (e0 + HALO) * (e1 + HALO) * (e2 + HALO));
+  static constexpr int max_rows = D == 1 ? 1 : (D == 2 ? (e0 + HALO) : (e0 + HALO) * (e1 + HALO));
+  static constexpr int last_span = ext(D - 1) + HALO;
 };
 
-// Region of a tile: the cells whose stencils reach its nodes (the tile's cells
-// plus a halo of 2 below / 1 above, clipped), as per-axis first cell rlo and
-// span; rows = all region axes but the last (their cells are contiguous in the
-// sorted order).
-template <int D>
+// Region of a tile: the cells whose stencils reach its nodes, as per-axis
+// first cell rlo (anchor-node numbering) and span; rows = all region axes but
+// the last (their cells are contiguous in the sorted order).
+template <int D, int S>
 struct TileRegion {
   int origin[D], span[D], rlo[D];
   int nrows, ncells;
   __device__ TileRegion(int tile, const GeoK& g) {
-    using TS = TileShape<D>;
+    using TS = TileShape<D, S>;
+    constexpr int H = S / 2 - 1;
     int rem = tile;
     for (int a = D - 1; a >= 0; --a) {
       const int nt = (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
@@ -113,8 +136,8 @@ struct TileRegion {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const int tlast = min(origin[a] + TS::ext(a) - 1, g.m[a] - 1);
-      rlo[a] = max(1, origin[a] - 2);
-      const int rhi = min(g.nc[a], tlast + 1);
+      rlo[a] = max(H, origin[a] - (S - 1 - H));
+      const int rhi = min(g.nc[a] + H - 1, tlast + H);
       span[a] = rhi - rlo[a] + 1;
       ncells *= span[a];
       if (a < D - 1) nrows *= span[a];
@@ -124,9 +147,10 @@ struct TileRegion {
 
 // Per-row point ranges of a tile's region in LDS (global first point s_rg0, first
 // region cell s_rcb, local offset s_roff, total in s_roff[nrows]); all threads.
-template <int D>
-__device__ void tile_rows(const TileRegion<D>& T, const GeoK& g, const int* __restrict__ cstart, int* s_rg0,
+template <int D, int S>
+__device__ void tile_rows(const TileRegion<D, S>& T, const GeoK& g, const int* __restrict__ cstart, int* s_rg0,
                           int* s_rcb, int* s_rcnt, int* s_roff) {
+  constexpr int H = S / 2 - 1;
   const int last = D - 1;
   for (int row = threadIdx.x; row < T.nrows; row += blockDim.x) {
     int rem = row, base = 0;
@@ -135,8 +159,8 @@ __device__ void tile_rows(const TileRegion<D>& T, const GeoK& g, const int* __re
       c[a] = T.rlo[a] + rem % T.span[a];
       rem /= T.span[a];
     }
-    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
-    base = base * g.nc[last] + T.rlo[last] - 1;
+    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - H);
+    base = base * g.nc[last] + T.rlo[last] - H;
     const int g0 = cstart[base];
     const int g1 = cstart[base + T.span[last]];
     s_rcb[row] = base;
@@ -165,31 +189,30 @@ __device__ void tile_rows(const TileRegion<D>& T, const GeoK& g, const int* __re
 }
 
 // Plan set-up, pass 1: the number of points in every tile's region.
-template <int D>
+template <int D, int S>
 __global__ __launch_bounds__(256) void k_tile_count(const int* __restrict__ cstart, GeoK g,
                                                     int* __restrict__ total) {
-  using TS = TileShape<D>;
+  using TS = TileShape<D, S>;
   __shared__ int s_rg0[TS::max_rows], s_rcb[TS::max_rows], s_rcnt[TS::max_rows], s_roff[TS::max_rows + 1];
-  const TileRegion<D> T(blockIdx.x, g);
-  tile_rows<D>(T, g, cstart, s_rg0, s_rcb, s_rcnt, s_roff);
+  const TileRegion<D, S> T(blockIdx.x, g);
+  tile_rows<D, S>(T, g, cstart, s_rg0, s_rcb, s_rcnt, s_roff);
   if (threadIdx.x == 0) total[blockIdx.x] = s_roff[T.nrows];
 }
 
 // Plan set-up, pass 2: every tile's region tables (fixed by the points alone):
 // the local point range of each region cell (row-major, last axis fastest), and
-// for each local slot q (tile_off[t] + q) the point, its last-axis cell and its
-// 8 D interpolation weights (SoA with stride `slots`).
-template <int D>
-__global__ __launch_bounds__(256) void k_tile_fill(const int* __restrict__ cell, const double* __restrict__ wts,
-                                                   const int* __restrict__ cstart, int n, GeoK g,
-                                                   const int* __restrict__ tile_off, int* __restrict__ tile_lcs,
-                                                   int* __restrict__ tile_pts, int* __restrict__ tile_cl,
-                                                   double* __restrict__ tile_w, long long slots) {
-  using TS = TileShape<D>;
+// for each local slot q (tile_off[t] + q) the point and its last-axis anchor.
+template <int D, int S>
+__global__ __launch_bounds__(256) void k_tile_fill(const int* __restrict__ cell, const int* __restrict__ cstart,
+                                                   GeoK g, const int* __restrict__ tile_off,
+                                                   int* __restrict__ tile_lcs, int* __restrict__ tile_pts,
+                                                   int* __restrict__ tile_cl) {
+  using TS = TileShape<D, S>;
+  constexpr int H = S / 2 - 1;
   __shared__ int s_rg0[TS::max_rows], s_rcb[TS::max_rows], s_rcnt[TS::max_rows], s_roff[TS::max_rows + 1];
   const int last = D - 1;
-  const TileRegion<D> T(blockIdx.x, g);
-  tile_rows<D>(T, g, cstart, s_rg0, s_rcb, s_rcnt, s_roff);
+  const TileRegion<D, S> T(blockIdx.x, g);
+  tile_rows<D, S>(T, g, cstart, s_rg0, s_rcb, s_rcnt, s_roff);
   const int total = s_roff[T.nrows];
   int* lcs = tile_lcs + (size_t)blockIdx.x * (TS::max_cells + 1);
   for (int f = threadIdx.x; f < T.nrows * TS::last_span; f += blockDim.x) {
@@ -206,33 +229,32 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int* __restrict__ cell,
     }
     const int kq = s_rg0[lo_r] + q - s_roff[lo_r];
     tile_pts[off + q] = kq;
-    tile_cl[off + q] = cell[kq] % g.nc[last] + 1;
-    for (int a8 = 0; a8 < D * 8; ++a8) tile_w[a8 * slots + off + q] = wts[(size_t)a8 * n + kq];
+    tile_cl[off + q] = cell[kq] % g.nc[last] + H;
   }
 }
 
-template <int D, int CR, typename T, int PMAX>
+template <int D, int S, int CR, typename T, typename GT>
 __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cell,
-                                                     const double* __restrict__ wts,
+                                                     const double* __restrict__ toff,
                                                      const int* __restrict__ cstart, int n, GeoK g,
                                                      const int* __restrict__ tile_off,
                                                      const int* __restrict__ tile_lcs,
                                                      const int* __restrict__ tile_pts,
                                                      const int* __restrict__ tile_cl,
-                                                     const double* __restrict__ tile_w, long long slots,
                                                      const T* __restrict__ V, int ldv, int R, int cr,
-                                                     double* __restrict__ G, long long M) {
-  static_assert(PMAX == 256, "one thread stages one region point");
-  using TS = TileShape<D>;
-  // weights point-major, 8 D + 1 doubles per point: lanes reading one point at
+                                                     GT* __restrict__ G, long long M) {
+  constexpr int PMAX = 256;  // one thread stages one region point
+  constexpr int H = S / 2 - 1;
+  using TS = TileShape<D, S>;
+  // weights point-major, 2 S D + 1 doubles per point: lanes reading one point at
   // different stencil offsets hit adjacent banks, different points rarely share one
-  constexpr int WS = 8 * D + 1;
+  constexpr int WS = 2 * S * D + 1;
   __shared__ double s_w[PMAX * WS];
   __shared__ T s_v[PMAX * CR * (D + 1)];
   __shared__ int s_lcs[TS::max_cells + 1];
-  __shared__ int s_cl[PMAX];  // last-axis cell (1-based) of every region point
+  __shared__ int s_cl[PMAX];  // last-axis anchor node of every region point
   const int last = D - 1;
-  const TileRegion<D> TR(blockIdx.x, g);
+  const TileRegion<D, S> TR(blockIdx.x, g);
   int origin[D], span[D], rlo[D], jl[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -257,16 +279,17 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   const bool lds_ok = total <= PMAX;
   if (lds_ok) {
     // the region tables of the plan: cell ranges, and for this thread's slot the
-    // point, its last-axis cell and weights; then the point's column values
+    // point and its last-axis anchor; then the point's offsets (its weights) and
+    // column values
     const int* lcs = tile_lcs + (size_t)blockIdx.x * (TS::max_cells + 1);
     for (int f = threadIdx.x; f <= TR.ncells; f += blockDim.x) s_lcs[f] = lcs[f];
     const int q = threadIdx.x;
     if (q < total) {
       const int kq = tile_pts[off + q];
       const int cq = tile_cl[off + q];
-      double w[D * 8];
+      double tq[D];
 #pragma unroll
-      for (int a8 = 0; a8 < D * 8; ++a8) w[a8] = tile_w[a8 * slots + off + q];
+      for (int a = 0; a < D; ++a) tq[a] = toff[(size_t)a * n + kq];
       T x[CR * (D + 1)];
 #pragma unroll
       for (int r = 0; r < CR; ++r)
@@ -275,7 +298,15 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
           x[r * (D + 1) + b] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
                                       (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
 #pragma unroll
-      for (int a8 = 0; a8 < D * 8; ++a8) s_w[q * WS + a8] = w[a8];
+      for (int a = 0; a < D; ++a) {
+        double w[S], dw[S];
+        interp_weights<S>(tq[a], g.invh[a], w, dw);
+#pragma unroll
+        for (int o = 0; o < S; ++o) {
+          s_w[q * WS + a * 2 * S + o] = w[o];
+          s_w[q * WS + a * 2 * S + S + o] = dw[o];
+        }
+      }
 #pragma unroll
       for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
       s_cl[q] = cq;
@@ -296,8 +327,8 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   int lo[D], hi[D], c[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    lo[a] = max(1, j[a] - 2);
-    hi[a] = min(g.nc[a], j[a] + 1);
+    lo[a] = max(H, j[a] - (S - 1 - H));
+    hi[a] = min(g.nc[a] + H - 1, j[a] + H);
     c[a] = lo[a];
   }
   if (lds_ok) {
@@ -334,9 +365,9 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
       const int cl = s_cl[q];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const int o = j[a] - (a == last ? cl : c[a]) + 1;
-        wv[a] = s_w[q * WS + a * 8 + o];
-        wd[a] = s_w[q * WS + a * 8 + 4 + o];
+        const int o = j[a] - (a == last ? cl : c[a]) + H;
+        wv[a] = s_w[q * WS + a * 2 * S + o];
+        wd[a] = s_w[q * WS + a * 2 * S + S + o];
       }
       scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)q * CR * (D + 1));
       ++q;
@@ -354,18 +385,17 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
         rem /= sp;
       }
 #pragma unroll
-      for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+      for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - H);
       base *= g.nc[last];
-      const int kb = cstart[base + lo[last] - 1];
-      const int ke = cstart[base + hi[last]];
+      const int kb = cstart[base + lo[last] - H];
+      const int ke = cstart[base + hi[last] - H + 1];
       for (int k = kb; k < ke; ++k) {
-        const int clast = cell[k] % g.nc[last] + 1;
+        const int clast = cell[k] % g.nc[last] + H;
         double wv[D], wd[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const int o = j[a] - ((a == last) ? clast : c[a]) + 1;
-          wv[a] = wts[(size_t)(a * 8 + o) * n + k];
-          wd[a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
+          const int o = j[a] - ((a == last) ? clast : c[a]) + H;
+          interp_weight_at<S>(toff[(size_t)a * n + k], g.invh[a], o, wv[a], wd[a]);
         }
         T x[CR * (D + 1)];
 #pragma unroll
@@ -388,45 +418,53 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   // slower on the 632^2 and 1000^2 grids and no faster on 200^2.
 #pragma unroll
   for (int r = 0; r < CR; ++r)
-    if (r < rc) __builtin_nontemporal_store(acc[r], &G[(size_t)(r0 + r) * M + node]);
+    if (r < rc) __builtin_nontemporal_store((GT)acc[r], &G[(size_t)(r0 + r) * M + node]);
 }
 
 // Columns per work-group of the LDS-tiled scatter: a base chunk (4 columns in
 // 1-D and 2-D; 2 FP32 or 1 FP64 in 3-D) times 1, 1.5, 2 or 5; wider chunks mean
 // fewer work-groups, each staging its region once for more columns.  FP32 and
 // FP64 column values are tuned separately.
-template <int D, typename T, int WIDTH>
+template <int D, int S, typename T, int WIDTH>
 constexpr int scatter_cr() {
   constexpr int base = D <= 2 ? 4 : (sizeof(T) == 4 ? 2 : 1);
-  constexpr int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : (WIDTH == 2 ? 2 * base : 5 * base));
-  return D == 3 && cr > 3 ? 3 : cr;  // 3-D: the region tables leave room for 3 columns
+  int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : (WIDTH == 2 ? 2 * base : 5 * base));
+  if (D == 3 && cr > 3) cr = 3;  // 3-D: the region tables leave room for 3 columns
+  // the staged column values share the 160 KB of LDS with the weights and tables
+  using TS = TileShape<D, S>;
+  while (cr > 1 && 256 * (2 * S * D + 1) * 8 + 256 * cr * (D + 1) * (int)sizeof(T) + (TS::max_cells + 1) * 4 +
+                       256 * 4 > 160 * 1024)
+    --cr;
+  return cr;
 }
 
-template <int D, typename T, int WIDTH>
-static void launch_scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
+template <int D, int S, typename T, typename GT, int WIDTH>
+static void launch_scatter(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st) {
   GeoK g = geo_of(p);
-  using TS = TileShape<D>;
+  using TS = TileShape<D, S>;
   long long tiles = 1;
   for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
   // columns per work-group: at most CR, chunks of equal width but the last
-  constexpr int CR = scatter_cr<D, T, WIDTH>();
+  constexpr int CR = scatter_cr<D, S, T, WIDTH>();
   const int nch = (R + CR - 1) / CR;
   const int cr = (R + nch - 1) / nch;
   dim3 grid((unsigned)tiles, nch);
-  k_scatter_lds<D, CR, T, 256><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, p->tile_off,
-                                                      p->tile_lcs, p->tile_pts, p->tile_cl, p->tile_w,
-                                                      p->tile_slots, V, ldv, R, cr, G, p->M);
+  k_scatter_lds<D, S, CR, T, GT><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, p->tile_off,
+                                                        p->tile_lcs, p->tile_pts, p->tile_cl, V, ldv, R, cr, G,
+                                                        p->M);
 }
 
 // Direct variant: one thread per (grid node, CRD columns), no LDS; cell ranges,
-// weights and column values are read through the caches (neighbouring nodes share
-// points).  Same summation order as the tiled kernel, hence the same result.
-template <int D, int CRD, typename T>
+// offsets and column values are read through the caches (neighbouring nodes
+// share points).  Same summation order and weights as the tiled kernel, hence
+// the same result.
+template <int D, int S, int CRD, typename T, typename GT>
 __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ cell,
-                                                        const double* __restrict__ wts,
+                                                        const double* __restrict__ toff,
                                                         const int* __restrict__ cstart, int n, GeoK g,
                                                         const T* __restrict__ V, int ldv, int R,
-                                                        double* __restrict__ G, long long M) {
+                                                        GT* __restrict__ G, long long M) {
+  constexpr int H = S / 2 - 1;
   const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= M) return;
   const int r0 = blockIdx.y * CRD;
@@ -444,8 +482,8 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
   int lo[D], hi[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    lo[a] = max(1, j[a] - 2);
-    hi[a] = min(g.nc[a], j[a] + 1);
+    lo[a] = max(H, j[a] - (S - 1 - H));
+    hi[a] = min(g.nc[a] + H - 1, j[a] + H);
   }
   int outer_cnt = 1;
 #pragma unroll
@@ -463,27 +501,22 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
       rem /= sp;
     }
 #pragma unroll
-    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - 1);
+    for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - H);
     base *= g.nc[last];
     // the cells lo..hi of the last axis are one contiguous run of points; the
     // stencil position on the last axis changes at each cell boundary
     for (int cl = lo[last]; cl <= hi[last]; ++cl) {
-      const int kb = cstart[base + cl - 1], ke = cstart[base + cl];
+      const int kb = cstart[base + cl - H], ke = cstart[base + cl - H + 1];
       // four points per step: all their loads are issued before the first
       // product; the points are then added in order, exactly as one at a time
       for (int k0 = kb; k0 < ke; k0 += 4) {
-        double wv[4][D], wd[4][D];
+        double tq[4][D];
         T x[4][CRD * (D + 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = k0 + u < ke ? k0 + u : kb;  // a valid point stands in past the run
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            int ca = (a == last) ? cl : c[a];
-            int o = j[a] - ca + 1;
-            wv[u][a] = wts[(size_t)(a * 8 + o) * n + k];
-            wd[u][a] = wts[(size_t)(a * 8 + 4 + o) * n + k];
-          }
+          for (int a = 0; a < D; ++a) tq[u][a] = toff[(size_t)a * n + k];
 #pragma unroll
           for (int r = 0; r < CRD; ++r)
 #pragma unroll
@@ -493,10 +526,16 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
+          double wv[D], wd[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const int ca = (a == last) ? cl : c[a];
+            interp_weight_at<S>(tq[u][a], g.invh[a], j[a] - ca + H, wv[a], wd[a]);
+          }
           double t[CRD];
 #pragma unroll
           for (int r = 0; r < CRD; ++r) t[r] = acc[r];
-          scatter_accum<D, CRD>(t, wv[u], wd[u], x[u]);
+          scatter_accum<D, CRD>(t, wv, wd, x[u]);
           const bool ok = k0 + u < ke;
 #pragma unroll
           for (int r = 0; r < CRD; ++r) acc[r] = ok ? t[r] : acc[r];
@@ -506,56 +545,64 @@ __global__ __launch_bounds__(256) void k_scatter_direct(const int* __restrict__ 
   }
 #pragma unroll
   for (int r = 0; r < CRD; ++r)
-    if (r < rc) __builtin_nontemporal_store(acc[r], &G[(size_t)(r0 + r) * M + node]);
+    if (r < rc) __builtin_nontemporal_store((GT)acc[r], &G[(size_t)(r0 + r) * M + node]);
 }
 
-template <int D, int CRD, typename T>
-static void launch_scatter_direct(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
+template <int D, int S, int CRD, typename T, typename GT>
+static void launch_scatter_direct(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st) {
   GeoK g = geo_of(p);
   dim3 grid((unsigned)((p->M + 255) / 256), (R + CRD - 1) / CRD);
-  k_scatter_direct<D, CRD, T><<<grid, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, V, ldv, R, G, p->M);
+  k_scatter_direct<D, S, CRD, T, GT><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, V, ldv, R, G,
+                                                           p->M);
 }
 
-template <int D, typename T>
-static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
+template <int D, int S, typename T, typename GT>
+static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st) {
   switch (sizeof(T) == 8 ? p->scatter_variant64 : p->scatter_variant) {
-    case 1: launch_scatter_direct<D, 1, T>(p, R, V, ldv, G, st); break;
-    case 2: launch_scatter_direct<D, 2, T>(p, R, V, ldv, G, st); break;
-    case 3: launch_scatter<D, T, 1>(p, R, V, ldv, G, st); break;
-    case 4: launch_scatter<D, T, 2>(p, R, V, ldv, G, st); break;
-    case 5: launch_scatter<D, T, 3>(p, R, V, ldv, G, st); break;
-    default: launch_scatter<D, T, 0>(p, R, V, ldv, G, st); break;
+    case 1: launch_scatter_direct<D, S, 1, T, GT>(p, R, V, ldv, G, st); break;
+    case 2: launch_scatter_direct<D, S, 2, T, GT>(p, R, V, ldv, G, st); break;
+    case 3: launch_scatter<D, S, T, GT, 1>(p, R, V, ldv, G, st); break;
+    case 4: launch_scatter<D, S, T, GT, 2>(p, R, V, ldv, G, st); break;
+    case 5: launch_scatter<D, S, T, GT, 3>(p, R, V, ldv, G, st); break;
+    default: launch_scatter<D, S, T, GT, 0>(p, R, V, ldv, G, st); break;
   }
 }
 
-template <typename T>
-dski_status scatter(dski_plan p, int R, const T* V, int ldv, double* G, hipStream_t st) {
-  if (R <= 0) return DSKI_OK;
+template <int S, typename T, typename GT>
+static dski_status scatter_s(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st) {
   switch (p->d) {
-    case 1: scatter_dispatch<1, T>(p, R, V, ldv, G, st); break;
-    case 2: scatter_dispatch<2, T>(p, R, V, ldv, G, st); break;
-    case 3: scatter_dispatch<3, T>(p, R, V, ldv, G, st); break;
+    case 1: scatter_dispatch<1, S, T, GT>(p, R, V, ldv, G, st); break;
+    case 2: scatter_dispatch<2, S, T, GT>(p, R, V, ldv, G, st); break;
+    case 3: scatter_dispatch<3, S, T, GT>(p, R, V, ldv, G, st); break;
     default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
   }
+  return DSKI_OK;
+}
+
+template <typename T, typename GT>
+dski_status scatter(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st) {
+  if (R <= 0) return DSKI_OK;
+  DSKI_TRY((p->S == kInterpQuintic ? scatter_s<kInterpQuintic, T, GT>(p, R, V, ldv, G, st)
+                                   : scatter_s<kInterpCubic, T, GT>(p, R, V, ldv, G, st)));
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
-template dski_status scatter<float>(dski_plan, int, const float*, int, double*, hipStream_t);
-template dski_status scatter<double>(dski_plan, int, const double*, int, double*, hipStream_t);
+template dski_status scatter<float, double>(dski_plan, int, const float*, int, double*, hipStream_t);
+template dski_status scatter<double, double>(dski_plan, int, const double*, int, double*, hipStream_t);
 
 // Region tables of the LDS-tiled scatter, built once per plan: pass 1 counts
 // every tile's region points, the host forms the offsets, pass 2 fills the
 // tables (see k_tile_fill).
-template <int D>
+template <int D, int S>
 static dski_status build_tiles(dski_plan p, hipStream_t st) {
-  using TS = TileShape<D>;
+  using TS = TileShape<D, S>;
   GeoK g = geo_of(p);
   long long tiles = 1;
   for (int a = 0; a < D; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
   std::vector<int> tot((size_t)tiles), off((size_t)tiles + 1);
   int* d_tot = nullptr;
   DSKI_HIP(hipMalloc(&d_tot, sizeof(int) * (size_t)tiles));
-  k_tile_count<D><<<(unsigned)tiles, 256, 0, st>>>(p->cell_start, g, d_tot);
+  k_tile_count<D, S><<<(unsigned)tiles, 256, 0, st>>>(p->cell_start, g, d_tot);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(tot.data(), d_tot, sizeof(int) * (size_t)tiles, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -581,22 +628,26 @@ static dski_status build_tiles(dski_plan p, hipStream_t st) {
   DSKI_HIP(hipMalloc(&p->tile_lcs, sizeof(int) * (size_t)tiles * (TS::max_cells + 1)));
   DSKI_HIP(hipMalloc(&p->tile_pts, sizeof(int) * (size_t)std::max(slots, 1ll)));
   DSKI_HIP(hipMalloc(&p->tile_cl, sizeof(int) * (size_t)std::max(slots, 1ll)));
-  DSKI_HIP(hipMalloc(&p->tile_w, sizeof(double) * 8 * D * (size_t)std::max(slots, 1ll)));
   DSKI_HIP(hipMemcpyAsync(p->tile_off, off.data(), sizeof(int) * (size_t)(tiles + 1), hipMemcpyHostToDevice, st));
-  k_tile_fill<D><<<(unsigned)tiles, 256, 0, st>>>(p->cell, p->wts, p->cell_start, p->n, g, p->tile_off,
-                                                  p->tile_lcs, p->tile_pts, p->tile_cl, p->tile_w, slots);
+  k_tile_fill<D, S><<<(unsigned)tiles, 256, 0, st>>>(p->cell, p->cell_start, g, p->tile_off, p->tile_lcs,
+                                                     p->tile_pts, p->tile_cl);
   DSKI_HIP(hipGetLastError());
   DSKI_HIP(hipStreamSynchronize(st));
   return DSKI_OK;
 }
 
-dski_status scatter_tables(dski_plan p, hipStream_t st) {
+template <int S>
+static dski_status scatter_tables_s(dski_plan p, hipStream_t st) {
   switch (p->d) {
-    case 1: return build_tiles<1>(p, st);
-    case 2: return build_tiles<2>(p, st);
-    case 3: return build_tiles<3>(p, st);
+    case 1: return build_tiles<1, S>(p, st);
+    case 2: return build_tiles<2, S>(p, st);
+    case 3: return build_tiles<3, S>(p, st);
     default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
   }
+}
+
+dski_status scatter_tables(dski_plan p, hipStream_t st) {
+  return p->S == kInterpQuintic ? scatter_tables_s<kInterpQuintic>(p, st) : scatter_tables_s<kInterpCubic>(p, st);
 }
 
 // ------------------------------------------------------------------ K_UU by FFT
@@ -777,8 +828,8 @@ __device__ __forceinline__ void fft_run(double2* v, double2* __restrict__ buf, c
 // the last inverse pass touch the elements lane + r L / 8, which contiguous
 // lines (inner = 1) load and store straight from and to the grid.  Strided
 // lines go through LDS with work-group-wide coalesced loads and stores.
-template <int LG>
-__global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long long nlines, int m,
+template <int LG, typename GT>
+__global__ __launch_bounds__(256) void k_toeplitz(GT* __restrict__ G, long long nlines, int m,
                                                   long long inner, const double2* __restrict__ tw,
                                                   const double* __restrict__ spec) {
   using S = FftShape<LG>;
@@ -804,13 +855,13 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   double2 v[E];
   const long long la = line0 + 2 * pair;
   if (inner == 1) {
-    const double* A = G + la * m;
+    const GT* A = G + la * m;
     const bool va = la < nlines, vb = la + 1 < nlines;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
       const bool in = pos < m;
-      v[e] = make_double2(in && va ? A[pos] : 0.0, in && vb ? A[m + pos] : 0.0);
+      v[e] = make_double2(in && va ? (double)A[pos] : 0.0, in && vb ? (double)A[m + pos] : 0.0);
     }
     if constexpr (S::STAGE) __syncthreads();
   } else {
@@ -831,7 +882,7 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
       for (int u = 0; u < 8; ++u) {
         const int f = f0 + 256 * u;
         const long long b = f < tot ? s_base[f & (S::NL - 1)] : -1;
-        x[u] = ld_or0(G, (size_t)(b + (long long)(f >> S::LGNL) * inner), 0, b >= 0);
+        x[u] = (double)ld_or0(G, (size_t)(b + (long long)(f >> S::LGNL) * inner), 0, b >= 0);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -855,14 +906,14 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
   for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sspec[lp + (e / RL) * TPL + (e % RL) * (L / RL)]);
   fft_run<LG, -1, 0>(v, buf, stw, lp);
   if (inner == 1) {
-    double* A = G + la * m;
+    GT* A = G + la * m;
     const bool va = la < nlines, vb = la + 1 < nlines;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int pos = lp + (e / R0) * TPL + (e % R0) * (L / R0);
       if (pos < m) {
-        if (va) A[pos] = v[e].x;
-        if (vb) A[m + pos] = v[e].y;
+        if (va) A[pos] = (GT)v[e].x;
+        if (vb) A[m + pos] = (GT)v[e].y;
       }
     }
   } else {
@@ -878,13 +929,13 @@ __global__ __launch_bounds__(256) void k_toeplitz(double* __restrict__ G, long l
       const long long b = s_base[l];
       if (b >= 0)
         G[b + (long long)(f >> S::LGNL) * inner] =
-            reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * S::LP + padi(f >> S::LGNL)])[l & 1];
+            (GT)reinterpret_cast<const double*>(&smem[(size_t)(l >> 1) * S::LP + padi(f >> S::LGNL)])[l & 1];
     }
   }
 }
 
-template <int LG>
-static dski_status launch_toeplitz(double* G, long long nlines, int m, long long inner, const double2* tw,
+template <int LG, typename GT>
+static dski_status launch_toeplitz(GT* G, long long nlines, int m, long long inner, const double2* tw,
                                    const double* spec, hipStream_t st) {
   using S = FftShape<LG>;
   static_assert(S::lds_bytes() <= 160 * 1024, "LDS");
@@ -893,13 +944,13 @@ static dski_status launch_toeplitz(double* G, long long nlines, int m, long long
   if (sh > 64 * 1024) {
     static bool done = false;
     if (!done) {
-      DSKI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_toeplitz<LG>),
+      DSKI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_toeplitz<LG, GT>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
       done = true;
     }
   }
   const long long blocks = (nlines + S::NL - 1) / S::NL;
-  k_toeplitz<LG><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, m, inner, tw, spec);
+  k_toeplitz<LG, GT><<<(unsigned)blocks, 256, sh, st>>>(G, nlines, m, inner, tw, spec);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
@@ -918,8 +969,8 @@ static dski_status launch_toeplitz(double* G, long long nlines, int m, long long
 // the per-axis tuner weighs.  m <= kDenseMaxM.
 typedef double dski_dbl4 __attribute__((ext_vector_type(4)));
 
-template <int NT>  // row tiles per wavefront: 4 NT >= ceil(m / 16)
-__global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, long long nlines, int m,
+template <int NT, typename GT>  // row tiles per wavefront: 4 NT >= ceil(m / 16)
+__global__ __launch_bounds__(256) void k_toeplitz_mfma(GT* __restrict__ G, long long nlines, int m,
                                                        long long inner, const double* __restrict__ col,
                                                        double scale, int deriv, double h_over_ell) {
   extern __shared__ double smem_d[];
@@ -956,7 +1007,7 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
         l = f / mp;
       }
       const long long base = f < tot ? s_base[l] : -1;
-      v[u] = (base >= 0 && bb < m) ? G[base + (long long)bb * inner] : 0.0;
+      v[u] = (base >= 0 && bb < m) ? (double)G[base + (long long)bb * inner] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -1014,13 +1065,14 @@ __global__ __launch_bounds__(256) void k_toeplitz_mfma(double* __restrict__ G, l
     const int l = inner > 1 ? f % 16 : f / m;
     const int bb = inner > 1 ? f / 16 : f % m;
     const long long base = s_base[l];
-    if (base >= 0) G[base + (long long)bb * inner] = sX[bb * 17 + l];
+    if (base >= 0) G[base + (long long)bb * inner] = (GT)sX[bb * 17 + l];
   }
 }
 
 // K_UU factor of one axis (stride `inner`) for R columns, FFT (variant 0) or
 // dense matrix-core product (variant 1, m <= kDenseMaxM).
-dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, int a, int variant) {
+template <typename GT>
+dski_status kuu_axis(dski_plan p, int R, GT* G, hipStream_t st, int dwhich, int a, int variant) {
   const Axis& A = p->ax[a];
   long long inner = 1;
   for (int b = a + 1; b < p->d; ++b) inner *= p->ax[b].m;
@@ -1034,13 +1086,13 @@ dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, 
     const int dv = a == dwhich ? 1 : 0;
     const double hl = A.h / p->ell[a];
     switch (nt) {
-      case 1: k_toeplitz_mfma<1><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
-      case 2: k_toeplitz_mfma<2><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
-      case 3: k_toeplitz_mfma<3><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
-      case 4: k_toeplitz_mfma<4><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
-      case 5: k_toeplitz_mfma<5><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
-      case 6: k_toeplitz_mfma<6><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
-      default: k_toeplitz_mfma<7><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 1: k_toeplitz_mfma<1, GT><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 2: k_toeplitz_mfma<2, GT><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 3: k_toeplitz_mfma<3, GT><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 4: k_toeplitz_mfma<4, GT><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 5: k_toeplitz_mfma<5, GT><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      case 6: k_toeplitz_mfma<6, GT><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
+      default: k_toeplitz_mfma<7, GT><<<nb, 256, sh, st>>>(G, nlines, A.m, inner, A.col, scale, dv, hl); break;
     }
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
@@ -1048,45 +1100,53 @@ dski_status kuu_axis(dski_plan p, int R, double* G, hipStream_t st, int dwhich, 
   const double* spec = (a == dwhich) ? A.dspec : A.spec;
   const double2* tw = reinterpret_cast<const double2*>(A.twiddle);
   switch (A.L) {
-    case 8: return launch_toeplitz<3>(G, nlines, A.m, inner, tw, spec, st);
-    case 16: return launch_toeplitz<4>(G, nlines, A.m, inner, tw, spec, st);
-    case 32: return launch_toeplitz<5>(G, nlines, A.m, inner, tw, spec, st);
-    case 64: return launch_toeplitz<6>(G, nlines, A.m, inner, tw, spec, st);
-    case 128: return launch_toeplitz<7>(G, nlines, A.m, inner, tw, spec, st);
-    case 256: return launch_toeplitz<8>(G, nlines, A.m, inner, tw, spec, st);
-    case 512: return launch_toeplitz<9>(G, nlines, A.m, inner, tw, spec, st);
-    case 1024: return launch_toeplitz<10>(G, nlines, A.m, inner, tw, spec, st);
-    case 2048: return launch_toeplitz<11>(G, nlines, A.m, inner, tw, spec, st);
+    case 8: return launch_toeplitz<3, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 16: return launch_toeplitz<4, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 32: return launch_toeplitz<5, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 64: return launch_toeplitz<6, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 128: return launch_toeplitz<7, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 256: return launch_toeplitz<8, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 512: return launch_toeplitz<9, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 1024: return launch_toeplitz<10, GT>(G, nlines, A.m, inner, tw, spec, st);
+    case 2048: return launch_toeplitz<11, GT>(G, nlines, A.m, inner, tw, spec, st);
     default:
       set_error("FFT length %d not supported (grid size per axis 4..1024)", A.L);
       return DSKI_ENOTSUP;
   }
 }
 
+template dski_status kuu_axis<double>(dski_plan, int, double*, hipStream_t, int, int, int);
+
 // G <- K_UU G for R columns; dwhich = p (0..d-1) uses d T_p / dlog ell_p on axis p.
-dski_status apply_kuu(dski_plan p, int R, double* G, hipStream_t st, int dwhich) {
+// Every transform computes in FP64 whatever the grid's storage type GT.
+template <typename GT>
+dski_status apply_kuu(dski_plan p, int R, GT* G, hipStream_t st, int dwhich) {
   if (R <= 0) return DSKI_OK;
-  for (int a = 0; a < p->d; ++a) DSKI_TRY(kuu_axis(p, R, G, st, dwhich, a, p->kuu_variant[a]));
+  for (int a = 0; a < p->d; ++a) DSKI_TRY(kuu_axis<GT>(p, R, G, st, dwhich, a, p->kuu_variant[a]));
   return DSKI_OK;
 }
+template dski_status apply_kuu<double>(dski_plan, int, double*, hipStream_t, int);
 
 // ------------------------------------------------------------------ gather + noise
-// One thread per (point, group of CG columns): the point's weights are read
-// once for the group, the 4^d grid values of each column give the value and
-// all d derivative rows.  Y = S G + D V with FP64 accumulation; optional
-// per-block partials of V.Y per column (p^T q of CG), stored output-major:
-// pq_partial[column * blocks + block].  The 1-D grid is laid out so that all
-// column groups of one block of points run on the same XCD (the hardware deals
-// work-groups to the 8 XCDs in turn): the points' weights are fetched into one
-// L2.  The number of point blocks is padded to a multiple of 8; padded blocks
-// write zero partials.
-template <int D, int CG, typename T>
+// One thread per (point, group of CG columns): the point's weights are formed
+// once for the group (interp_weights<S> from its offsets, as in the scatter),
+// the S^d grid values of each column give the value and all d derivative rows.
+// Y = S G + D V with FP64 accumulation; optional per-block partials of V.Y per
+// column (p^T q of CG), stored output-major: pq_partial[column * blocks +
+// block].  The 1-D grid is laid out so that all column groups of one block of
+// points run on the same XCD (the hardware deals work-groups to the 8 XCDs in
+// turn): the points' offsets are fetched into one L2.  The number of point
+// blocks is padded to a multiple of 8; padded blocks write zero partials.
+// The S x S grid values of one stencil plane are loaded together before they
+// are combined (S^d values for d <= 2, one plane at a time in 3-D).
+template <int D, int S, int CG, typename T, typename GT>
 __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
-                                                const double* __restrict__ wts, int n, GeoK g,
-                                                const double* __restrict__ G, long long M,
+                                                const double* __restrict__ toff, int n, GeoK g,
+                                                const GT* __restrict__ G, long long M,
                                                 const T* __restrict__ V, int ldv,
                                                 T* __restrict__ Y, int ldy, int R, int ngy, double nv,
                                                 double ng, double* __restrict__ pq_partial) {
+  constexpr int H = S / 2 - 1;
   const unsigned bid = blockIdx.x, xcd = bid & 7u, sq = bid >> 3;
   const int bx = (int)(xcd + 8u * (sq / (unsigned)ngy));   // point block
   const int r0 = (int)(sq % (unsigned)ngy) * CG;          // first column of the group
@@ -1096,44 +1156,23 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
 #pragma unroll
   for (int j = 0; j < CG; ++j) dot[j] = 0.0;
   if (k < n) {
-    double w[D][4], dw[D][4];
+    double w[D][S], dw[D][S];
     int c[D];
     int rem = cell[k];
 #pragma unroll
     for (int a = D - 1; a >= 0; --a) {
-      c[a] = rem % g.nc[a] + 1;
+      c[a] = rem % g.nc[a];      // first stencil node (anchor - H)
       rem /= g.nc[a];
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int o = 0; o < 4; ++o) {
-        w[a][o] = wts[(size_t)(a * 8 + o) * n + k];
-        dw[a][o] = wts[(size_t)(a * 8 + 4 + o) * n + k];
-      }
+    for (int a = 0; a < D; ++a) interp_weights<S>(toff[(size_t)a * n + k], g.invh[a], w[a], dw[a]);
     long long base = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) base = base * g.m[a] + (c[a] - 1);
+    for (int a = 0; a < D; ++a) base = base * g.m[a] + c[a];
     long long stride[D];
     stride[D - 1] = 1;
 #pragma unroll
     for (int a = D - 2; a >= 0; --a) stride[a] = stride[a + 1] * g.m[a + 1];
-    // the grid values of every column of the group, loaded together
-    constexpr int NG = D == 1 ? 4 : (D == 2 ? 16 : 64);
-    double gv[CG][NG];
-#pragma unroll
-    for (int j = 0; j < CG; ++j) {
-      const bool ok = r0 + j < R;
-      const double* Gr = G + (size_t)(ok ? r0 + j : r0) * M + base;
-#pragma unroll
-      for (int f = 0; f < NG; ++f) {
-        long long off;
-        if (D == 1) off = f;
-        else if (D == 2) off = (f >> 2) * stride[0] + (f & 3);
-        else off = (f >> 4) * stride[0] + ((f >> 2) & 3) * stride[1] + (f & 3);
-        gv[j][f] = ok ? Gr[off] : 0.0;
-      }
-    }
     T vin_t[CG][D + 1];
 #pragma unroll
     for (int j = 0; j < CG; ++j)
@@ -1141,60 +1180,88 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
       for (int q = 0; q <= D; ++q)
         vin_t[j][q] = ld_or0(V, (size_t)(r0 + j) * ldv + (size_t)q * n + k, (size_t)r0 * ldv + (size_t)q * n + k,
                              r0 + j < R);
+    double acc[CG][D + 1];
 #pragma unroll
-    for (int j = 0; j < CG; ++j) {
-      double acc[D + 1];
+    for (int j = 0; j < CG; ++j)
 #pragma unroll
-      for (int q = 0; q <= D; ++q) acc[q] = 0.0;
-      if (D == 1) {
+      for (int q = 0; q <= D; ++q) acc[j][q] = 0.0;
+    if constexpr (D <= 2) {
+      constexpr int NG = D == 1 ? S : S * S;
+      double gv[CG][NG];
 #pragma unroll
-        for (int o0 = 0; o0 < 4; ++o0) {
-          acc[0] += w[0][o0] * gv[j][o0];
-          acc[1] += dw[0][o0] * gv[j][o0];
+      for (int j = 0; j < CG; ++j) {
+        const bool ok = r0 + j < R;
+        const GT* Gr = G + (size_t)(ok ? r0 + j : r0) * M + base;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) {
+          const long long off = D == 1 ? f : (f / S) * stride[0] + (f % S);
+          gv[j][f] = ok ? (double)Gr[off] : 0.0;
         }
-      } else if (D == 2) {
+      }
 #pragma unroll
-        for (int o0 = 0; o0 < 4; ++o0) {
-          double s0 = 0.0, s1 = 0.0;
+      for (int j = 0; j < CG; ++j) {
+        if constexpr (D == 1) {
 #pragma unroll
-          for (int o1 = 0; o1 < 4; ++o1) {
-            const double x = gv[j][o0 * 4 + o1];
-            s0 += w[D - 1][o1] * x;
-            s1 += dw[D - 1][o1] * x;
+          for (int o0 = 0; o0 < S; ++o0) {
+            acc[j][0] += w[0][o0] * gv[j][o0];
+            acc[j][1] += dw[0][o0] * gv[j][o0];
           }
-          acc[0] += w[0][o0] * s0;
-          acc[1] += dw[0][o0] * s0;
-          acc[2] += w[0][o0] * s1;
-        }
-      } else {
+        } else {
 #pragma unroll
-        for (int o0 = 0; o0 < 4; ++o0) {
+          for (int o0 = 0; o0 < S; ++o0) {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int o1 = 0; o1 < S; ++o1) {
+              const double x = gv[j][o0 * S + o1];
+              s0 += w[1][o1] * x;
+              s1 += dw[1][o1] * x;
+            }
+            acc[j][0] += w[0][o0] * s0;
+            acc[j][1] += dw[0][o0] * s0;
+            acc[j][2] += w[0][o0] * s1;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < CG; ++j) {
+        const bool ok = r0 + j < R;
+        const GT* Gr = G + (size_t)(ok ? r0 + j : r0) * M + base;
+#pragma unroll
+        for (int o0 = 0; o0 < S; ++o0) {
+          double gv[S * S];
+#pragma unroll
+          for (int f = 0; f < S * S; ++f)
+            gv[f] = ok ? (double)Gr[o0 * stride[0] + (f / S) * stride[1] + (f % S)] : 0.0;
           double t0 = 0.0, t1 = 0.0, t2 = 0.0;
 #pragma unroll
-          for (int o1 = 0; o1 < 4; ++o1) {
+          for (int o1 = 0; o1 < S; ++o1) {
             double s0 = 0.0, s2 = 0.0;
 #pragma unroll
-            for (int o2 = 0; o2 < 4; ++o2) {
-              const double x = gv[j][o0 * 16 + o1 * 4 + o2];
-              s0 += w[D - 1][o2] * x;
-              s2 += dw[D - 1][o2] * x;
+            for (int o2 = 0; o2 < S; ++o2) {
+              const double x = gv[o1 * S + o2];
+              s0 += w[2][o2] * x;
+              s2 += dw[2][o2] * x;
             }
             t0 += w[1][o1] * s0;
             t1 += dw[1][o1] * s0;
             t2 += w[1][o1] * s2;
           }
-          acc[0] += w[0][o0] * t0;
-          acc[1] += dw[0][o0] * t0;
-          acc[2] += w[0][o0] * t1;
-          acc[3] += w[0][o0] * t2;
+          acc[j][0] += w[0][o0] * t0;
+          acc[j][1] += dw[0][o0] * t0;
+          acc[j][2] += w[0][o0] * t1;
+          acc[j][3] += w[0][o0] * t2;
         }
       }
+    }
+#pragma unroll
+    for (int j = 0; j < CG; ++j) {
       if (r0 + j < R) {
         T* yy = Y + (size_t)(r0 + j) * ldy + k;
 #pragma unroll
         for (int q = 0; q <= D; ++q) {
           const double vin = (double)vin_t[j][q];
-          const T out = (T)(acc[q] + (q == 0 ? nv : ng) * vin);
+          const T out = (T)(acc[j][q] + (q == 0 ? nv : ng) * vin);
           __builtin_nontemporal_store(out, &yy[(size_t)q * n]);
           dot[j] += vin * (double)out;
         }
@@ -1220,55 +1287,69 @@ __global__ __launch_bounds__(256) void k_gather(const int* __restrict__ cell,
 static int gather_point_blocks(dski_plan p) { return (((p->n + 255) / 256) + 7) & ~7; }
 int gather_blocks(dski_plan p) { return p->kind == 1 ? (p->N + 255) / 256 : gather_point_blocks(p); }
 
-template <int D, int CG, typename T>
-static void launch_gather_cg(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy, double nv,
+template <int D, int S, int CG, typename T, typename GT>
+static void launch_gather_cg(dski_plan p, int R, const GT* G, const T* V, int ldv, T* Y, int ldy, double nv,
                              double ng, double* pq_partial, hipStream_t st) {
   GeoK g = geo_of(p);
   const int ngy = (R + CG - 1) / CG;
   const unsigned nb = (unsigned)(gather_point_blocks(p) * ngy);
-  k_gather<D, CG, T><<<nb, 256, 0, st>>>(p->cell, p->wts, p->n, g, G, p->M, V, ldv, Y, ldy, R, ngy, nv, ng,
-                                         pq_partial);
+  k_gather<D, S, CG, T, GT><<<nb, 256, 0, st>>>(p->cell, p->toff, p->n, g, G, p->M, V, ldv, Y, ldy, R, ngy, nv,
+                                                ng, pq_partial);
 }
 
-template <int D, typename T>
-static void launch_gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy,
+template <int D, int S, typename T, typename GT>
+static void launch_gather(dski_plan p, int R, const GT* G, const T* V, int ldv, T* Y, int ldy,
                           double nv, double ng, double* pq_partial, hipStream_t st) {
-  if constexpr (D == 3) {  // 64 grid values per column: one column per thread
-    launch_gather_cg<D, 1, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st);
+  if constexpr (D == 3) {  // S^3 grid values per column: one column per thread
+    launch_gather_cg<D, S, 1, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st);
   } else {
     switch (p->gather_variant) {
-      case 1: launch_gather_cg<D, 1, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
-      case 2: launch_gather_cg<D, 4, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
-      default: launch_gather_cg<D, 2, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+      case 1: launch_gather_cg<D, S, 1, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+      case 2: launch_gather_cg<D, S, 4, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+      default: launch_gather_cg<D, S, 2, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
     }
   }
 }
 
-template <typename T>
-dski_status gather(dski_plan p, int R, const double* G, const T* V, int ldv, T* Y, int ldy, double nv,
-                   double ng, double* pq_partial, hipStream_t st) {
-  if (R <= 0 || p->n == 0) return DSKI_OK;
+template <int S, typename T, typename GT>
+static dski_status gather_s(dski_plan p, int R, const GT* G, const T* V, int ldv, T* Y, int ldy, double nv,
+                            double ng, double* pq_partial, hipStream_t st) {
   switch (p->d) {
-    case 1: launch_gather<1, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
-    case 2: launch_gather<2, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
-    case 3: launch_gather<3, T>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 1: launch_gather<1, S, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 2: launch_gather<2, S, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
+    case 3: launch_gather<3, S, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st); break;
     default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
   }
+  return DSKI_OK;
+}
+
+template <typename T, typename GT>
+dski_status gather(dski_plan p, int R, const GT* G, const T* V, int ldv, T* Y, int ldy, double nv,
+                   double ng, double* pq_partial, hipStream_t st) {
+  if (R <= 0 || p->n == 0) return DSKI_OK;
+  DSKI_TRY((p->S == kInterpQuintic
+                ? gather_s<kInterpQuintic, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st)
+                : gather_s<kInterpCubic, T, GT>(p, R, G, V, ldv, Y, ldy, nv, ng, pq_partial, st)));
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
-template dski_status gather<float>(dski_plan, int, const double*, const float*, int, float*, int,
-                                   double, double, double*, hipStream_t);
-template dski_status gather<double>(dski_plan, int, const double*, const double*, int, double*, int,
-                                    double, double, double*, hipStream_t);
+template dski_status gather<float, double>(dski_plan, int, const double*, const float*, int, float*, int,
+                                           double, double, double*, hipStream_t);
+template dski_status gather<double, double>(dski_plan, int, const double*, const double*, int, double*, int,
+                                            double, double, double*, hipStream_t);
 
-// The three stages on a caller-chosen grid workspace G (M x R doubles).
+// The three stages on a caller-chosen grid workspace G (M x R doubles).  The
+// grid stays FP64 beside FP32 vectors: an FP32 grid between the stages was
+// measured to move the terrain MVM 1.6e-5 away from the FP64 product (3e-8
+// with the FP64 grid) and to cost the FP32 block PCG 21 % more iterations,
+// because the gather's derivative weights (of order 1/h) difference nearby
+// grid values.
 template <typename T>
 static dski_status mvm_tiled_on(dski_plan p, int R, const T* V, int ldv, T* Y, int ldy, double* pq_partial,
                                 double* G, hipStream_t st) {
-  DSKI_TRY(scatter<T>(p, R, V, ldv, G, st));
-  DSKI_TRY(apply_kuu(p, R, G, st));
-  return gather<T>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, pq_partial, st);
+  DSKI_TRY((scatter<T, double>(p, R, V, ldv, G, st)));
+  DSKI_TRY(apply_kuu<double>(p, R, G, st));
+  return gather<T, double>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, pq_partial, st);
 }
 
 template <typename T>
@@ -1349,9 +1430,9 @@ dski_status mvm_dtheta(dski_plan p, int which, int R, const T* V, int ldv, T* Y,
   if (which <= d) {
     DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
     double* G = p->grid.as<double>();
-    DSKI_TRY(scatter<T>(p, R, V, ldv, G, st));
-    DSKI_TRY(apply_kuu(p, R, G, st, which < d ? which : -1));
-    DSKI_TRY(gather<T>(p, R, G, V, ldv, Y, ldy, 0.0, 0.0, nullptr, st));
+    DSKI_TRY((scatter<T, double>(p, R, V, ldv, G, st)));
+    DSKI_TRY(apply_kuu<double>(p, R, G, st, which < d ? which : -1));
+    DSKI_TRY((gather<T, double>(p, R, G, V, ldv, Y, ldy, 0.0, 0.0, nullptr, st)));
     if (which == d) {
       k_noise_deriv<T><<<blocks, 256, 0, st>>>(Y, ldy, Y, ldy, p->N, p->N, R, 2.0, 2.0);
       DSKI_HIP(hipGetLastError());
@@ -1458,9 +1539,9 @@ dski_status dski_mvm_stage(dski_plan p, int stage, int R, const float* V, int ld
     return DSKI_EINVAL;
   }
   double* G = p->grid.as<double>();
-  if (stage == 0) return scatter<float>(p, R, V, ldv, G, st);
-  if (stage == 1) return apply_kuu(p, R, G, st);
-  return gather<float>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, nullptr, st);
+  if (stage == 0) return scatter<float, double>(p, R, V, ldv, G, st);
+  if (stage == 1) return apply_kuu<double>(p, R, G, st);
+  return gather<float, double>(p, R, G, V, ldv, Y, ldy, p->sf * p->sf, p->sg * p->sg, nullptr, st);
 }
 
 dski_status dski_mvm(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,

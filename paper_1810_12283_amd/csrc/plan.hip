@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "interp.h"
 
 namespace dski {
 
@@ -43,6 +44,7 @@ void DevBuf::release() {
 
 struct Geo {
   int d;
+  int S;  // stencil nodes per axis
   int m[DSKI_MAXD];
   int nc[DSKI_MAXD];
   double lo[DSKI_MAXD];
@@ -50,26 +52,31 @@ struct Geo {
 };
 
 // Cell index and offset of every point (user order), histogram of cells.
-// Cell i_p = clamp(floor(s_p), 1, m_p - 3) with s_p = (x_p - lo_p) / h_p, so
-// the stencil nodes i_p - 1 .. i_p + 2 lie in the grid; t_p = s_p - i_p.
+// With S stencil nodes per axis and H = S/2 - 1, the anchor node is
+// i_p = clamp(floor(s_p), H, m_p - S + H), s_p = (x_p - lo_p) / h_p, so the
+// stencil nodes i_p - H .. i_p - H + S - 1 lie in the grid; t_p = s_p - i_p;
+// the cell id on the axis is i_p - H (its first stencil node).
 __global__ void k_cells(const double* __restrict__ X, int n, Geo g, int* __restrict__ cell_u,
                         double* __restrict__ t_u, int* __restrict__ counts, int* __restrict__ err) {
   int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
+  const int H = g.S / 2 - 1;
   int lin = 0;
   for (int p = 0; p < g.d; ++p) {
     double x = X[(size_t)u * g.d + p];
     double s = (x - g.lo[p]) / g.h[p];
-    if (!(s >= 1.0 - 1e-9 && s <= (double)(g.m[p] - 2) + 1e-9)) {
+    const double smin = (double)H, smax = (double)(g.m[p] - g.S + H + 1);
+    if (!(s >= smin - 1e-9 && s <= smax + 1e-9)) {
       atomicOr(err, 1);
-      s = fmin(fmax(s, 1.0), (double)(g.m[p] - 2));
+      s = fmin(fmax(s, smin), smax);
     }
     int i = (int)floor(s);
-    i = i < 1 ? 1 : (i > g.m[p] - 3 ? g.m[p] - 3 : i);
+    const int imax = g.m[p] - g.S + H;
+    i = i < H ? H : (i > imax ? imax : i);
     double t = s - (double)i;
     t = fmin(fmax(t, 0.0), 1.0);
     t_u[(size_t)p * n + u] = t;
-    lin = lin * g.nc[p] + (i - 1);
+    lin = lin * g.nc[p] + (i - H);
   }
   cell_u[u] = lin;
   atomicAdd(&counts[lin], 1);
@@ -133,25 +140,6 @@ __global__ void k_gather_points(const int* __restrict__ perm, int n, int d,
   int u = perm[k];
   cell[k] = cell_u[u];
   for (int p = 0; p < d; ++p) toff[(size_t)p * n + k] = t_u[(size_t)p * n + u];
-}
-
-// Interpolation weights of every point, computed once per plan (they depend only
-// on the point offsets): for axis a, Keys cubic convolution (a = -1/2) weights
-// w_0..w_3 of the stencil nodes i-1..i+2 at offset t, and their derivatives
-// dw_0..dw_3 with respect to x (d/dt divided by h).  Layout wts[(a * 8 + j) * n + k].
-__global__ void k_weights(const double* __restrict__ toff, int n, int d, const double* __restrict__ invh,
-                          double* __restrict__ wts) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  for (int a = 0; a < d; ++a) {
-    double w[4], dw[4];
-    keys_weights(toff[(size_t)a * n + k], invh[a], w, dw);
-    double* o = wts + (size_t)a * 8 * n + k;
-    for (int q = 0; q < 4; ++q) {
-      o[q * (size_t)n] = w[q];
-      o[(4 + q) * (size_t)n] = dw[q];
-    }
-  }
 }
 
 // Pass twiddles of the length-2^lg FFT in the layout of the radix plan
@@ -322,13 +310,11 @@ dski_status dski_plan_destroy(dski_plan p) {
   (void)hipFree(p->perm);
   (void)hipFree(p->cell);
   (void)hipFree(p->toff);
-  (void)hipFree(p->wts);
   (void)hipFree(p->cell_start);
   (void)hipFree(p->tile_off);
   (void)hipFree(p->tile_lcs);
   (void)hipFree(p->tile_pts);
   (void)hipFree(p->tile_cl);
-  (void)hipFree(p->tile_w);
   for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     (void)hipFree(p->ax[a].twiddle);
     (void)hipFree(p->ax[a].spec);
@@ -347,8 +333,10 @@ dski_status dski_plan_destroy(dski_plan p) {
 static dski_status plan_create_impl(dski_plan p, const double* X, const int* grid_m,
                                     const double* lo, const double* hi, hipStream_t st) {
   int n = p->n, d = p->d;
+  const int S = p->S, H = S / 2 - 1;
   Geo g{};
   g.d = d;
+  g.S = S;
   std::vector<double> blo(d), bhi(d);
   if (lo && hi) {
     for (int a = 0; a < d; ++a) {
@@ -374,8 +362,8 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
   long long nc = 1;
   for (int a = 0; a < d; ++a) {
     Axis& A = p->ax[a];
-    if (grid_m[a] < 4) {
-      set_error("grid size %d on axis %d: need >= 4", grid_m[a], a);
+    if (grid_m[a] < S) {
+      set_error("grid size %d on axis %d: need >= %d (the interpolation stencil)", grid_m[a], a, S);
       return DSKI_EINVAL;
     }
     if (!(bhi[a] > blo[a]) || !std::isfinite(blo[a]) || !std::isfinite(bhi[a])) {
@@ -383,9 +371,9 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
       return DSKI_EINVAL;
     }
     A.m = grid_m[a];
-    A.ncell = A.m - 3;
-    A.h = (bhi[a] - blo[a]) / (double)(A.m - 3);
-    A.lo = blo[a] - A.h;
+    A.ncell = A.m - S + 1;
+    A.h = (bhi[a] - blo[a]) / (double)A.ncell;
+    A.lo = blo[a] - H * A.h;
     A.L = fft_len(A.m);
     if (A.L > (1 << kFftMaxLog2)) {
       set_error("grid size %d on axis %d exceeds the FFT limit (m <= 1024)", A.m, a);
@@ -407,7 +395,6 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
   DSKI_HIP(hipMalloc(&p->perm, sizeof(int) * (size_t)std::max(n, 1)));
   DSKI_HIP(hipMalloc(&p->cell, sizeof(int) * (size_t)std::max(n, 1)));
   DSKI_HIP(hipMalloc(&p->toff, sizeof(double) * (size_t)std::max(n, 1) * d));
-  DSKI_HIP(hipMalloc(&p->wts, sizeof(double) * (size_t)std::max(n, 1) * d * 8));
   DSKI_HIP(hipMalloc(&p->cell_start, sizeof(int) * (size_t)(nc + 1)));
   for (int a = 0; a < d; ++a) {
     Axis& A = p->ax[a];
@@ -450,18 +437,6 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
       k_gather_points<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(p->perm, n, d, cell_u, t_u, p->cell,
                                                                    p->toff);
     }
-    if (n > 0) {
-      double invh[DSKI_MAXD];
-      for (int a = 0; a < d; ++a) invh[a] = 1.0 / p->ax[a].h;
-      double* dinvh = reinterpret_cast<double*>(err + 2);  // scratch after the error flag (aligned)
-      dinvh = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(dinvh) + 7) & ~uintptr_t(7));
-      if (hipMemcpyAsync(dinvh, invh, sizeof(double) * d, hipMemcpyHostToDevice, st) != hipSuccess) {
-        set_error("set-up copy failed");
-        rc = DSKI_EHIP;
-        break;
-      }
-      k_weights<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(p->toff, n, d, dinvh, p->wts);
-    }
     if (hipGetLastError() != hipSuccess) {
       set_error("set-up kernel launch failed");
       rc = DSKI_EHIP;
@@ -485,7 +460,7 @@ static dski_status plan_create_impl(dski_plan p, const double* X, const int* gri
 }
 
 dski_status dski_plan_create(dski_plan* out, int n, int d, const double* X, const int* grid_m_host,
-                             const double* lo_host, const double* hi_host, dski_stream stream) {
+                             const double* lo_host, const double* hi_host, int interp, dski_stream stream) {
   if (!out) {
     set_error("out is NULL");
     return DSKI_EINVAL;
@@ -501,11 +476,16 @@ dski_status dski_plan_create(dski_plan* out, int n, int d, const double* X, cons
     set_error("n too large");
     return DSKI_EINVAL;
   }
+  if (interp != DSKI_INTERP_CUBIC && interp != DSKI_INTERP_QUINTIC) {
+    set_error("dski_plan_create: interp must be DSKI_INTERP_CUBIC (0) or DSKI_INTERP_QUINTIC (1), got %d", interp);
+    return DSKI_EINVAL;
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   dski_plan p = new dski_plan_s();
   p->n = n;
   p->d = d;
   p->N = n * (d + 1);
+  p->S = interp == DSKI_INTERP_QUINTIC ? kInterpQuintic : kInterpCubic;
   dski_status rc = plan_create_impl(p, X, grid_m_host, lo_host, hi_host, st);
   if (rc < 0) {
     dski_plan_destroy(p);

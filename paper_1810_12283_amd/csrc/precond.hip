@@ -4,9 +4,9 @@
 // Diagonal and rows use the separable form of the D-SKI entries (the D-SKI
 // matrix of a product kernel is a Hadamard product of 1-D SKI factors,
 // Sec. 3.2):  K[(a,i),(b,j)] = s^2 prod_p  w_p^{(a)}(x_ip)^T T_p w_p^{(b)}(x_jp),
-// where w_p^{(a)} are the 4 value weights, or derivative weights when block a
-// is the derivative along axis p.  A row costs O(N d 4 + sum_p m_p), the
-// diagonal O(N d 16).
+// where w_p^{(a)} are the S value weights (S = 4 cubic, 6 quintic), or
+// derivative weights when block a is the derivative along axis p.  A row costs
+// O(N d S + sum_p m_p), the diagonal O(N d S^2).
 //
 // Greedy pivoting on the largest residual diagonal entry, lowest index among
 // exact ties; every step runs on the device (no host round trip per pivot).
@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "interp.h"
 #include "pivot.h"
 #include "tskinny.h"
 
@@ -49,29 +50,16 @@ static GeoP geop_of(dski_plan p) {
   return g;
 }
 
-__device__ __forceinline__ void kw(double t, bool deriv, double invh, double w[4]) {
-  double t2 = t * t, t3 = t2 * t;
-  if (!deriv) {
-    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
-    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
-    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
-    w[3] = 0.5 * (t3 - t2);
-  } else {
-    w[0] = 0.5 * (-3.0 * t2 + 4.0 * t - 1.0) * invh;
-    w[1] = 0.5 * (9.0 * t2 - 10.0 * t) * invh;
-    w[2] = 0.5 * (-9.0 * t2 + 8.0 * t + 1.0) * invh;
-    w[3] = 0.5 * (3.0 * t2 - 2.0 * t) * invh;
-  }
-}
-
+// First stencil node of every axis of cell id cl.
 __device__ __forceinline__ void cell_coords(int cl, const GeoP& g, int c[DSKI_MAXD]) {
   for (int a = g.d - 1; a >= 0; --a) {
-    c[a] = cl % g.nc[a] + 1;
+    c[a] = cl % g.nc[a];
     cl /= g.nc[a];
   }
 }
 
 // diag[e] for e = blk * n + k (tile order)
+template <int S>
 __global__ void k_pc_diag(GeoP g, const int* __restrict__ cell, const double* __restrict__ toff,
                           double* __restrict__ diag) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -79,11 +67,11 @@ __global__ void k_pc_diag(GeoP g, const int* __restrict__ cell, const double* __
   int blk = e / g.n, k = e % g.n;
   double v = g.s2;
   for (int a = 0; a < g.d; ++a) {
-    double w[4];
-    kw((double)toff[(size_t)a * g.n + k], blk == a + 1, g.invh[a], w);
+    double w[S];
+    interp_weights_one<S>((double)toff[(size_t)a * g.n + k], g.invh[a], blk == a + 1, w);
     double q = 0.0;
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) q += w[i] * g.col[a][i > j ? i - j : j - i] * w[j];
+    for (int i = 0; i < S; ++i)
+      for (int j = 0; j < S; ++j) q += w[i] * g.col[a][i > j ? i - j : j - i] * w[j];
     v *= q;
   }
   diag[e] = v;
@@ -125,6 +113,7 @@ __global__ void k_argmax_partial(const double* __restrict__ dres, int N, double*
 
 // Final arg-max, stop test, pivot bookkeeping, pivot-row factors a_p and the
 // pivot's row of L.  One work-group.
+template <int S>
 __global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int* __restrict__ pi,
                                int nblk, int j, double rel_tol, PivState* __restrict__ ps,
                                int* __restrict__ piv_list, const int* __restrict__ cell,
@@ -136,15 +125,15 @@ __global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int*
   int blk = e / g.n, k = e % g.n;
   int c[DSKI_MAXD];
   cell_coords(cell[k], g, c);
-  // a_p[u] = sum_o T_p[u, c_p - 1 + o] w_p^{(blk)}(x_kp)[o], u < m_p
+  // a_p[u] = sum_o T_p[u, c_p + o] w_p^{(blk)}(x_kp)[o], u < m_p (c_p the first stencil node)
   int off = 0;
   for (int a = 0; a < g.d; ++a) {
-    double w[4];
-    kw((double)toff[(size_t)a * g.n + k], blk == a + 1, g.invh[a], w);
+    double w[S];
+    interp_weights_one<S>((double)toff[(size_t)a * g.n + k], g.invh[a], blk == a + 1, w);
     for (int u = threadIdx.x; u < g.m[a]; u += blockDim.x) {
       double acc = 0.0;
-      for (int o = 0; o < 4; ++o) {
-        int v = c[a] - 1 + o;
+      for (int o = 0; o < S; ++o) {
+        int v = c[a] + o;
         acc += g.col[a][u > v ? u - v : v - u] * w[o];
       }
       arow[off + u] = acc;
@@ -155,6 +144,7 @@ __global__ void k_pivot_select(GeoP g, const double* __restrict__ pv, const int*
 }
 
 // Column j of L and the residual-diagonal update.
+template <int S>
 __global__ void k_pc_column(GeoP g, int j, const PivState* __restrict__ ps,
                             const int* __restrict__ cell, const double* __restrict__ toff,
                             const double* __restrict__ arow, const double* __restrict__ lrow,
@@ -168,10 +158,10 @@ __global__ void k_pc_column(GeoP g, int j, const PivState* __restrict__ ps,
   double row = g.s2;
   int off = 0;
   for (int a = 0; a < g.d; ++a) {
-    double w[4];
-    kw((double)toff[(size_t)a * g.n + k], blk == a + 1, g.invh[a], w);
+    double w[S];
+    interp_weights_one<S>((double)toff[(size_t)a * g.n + k], g.invh[a], blk == a + 1, w);
     double q = 0.0;
-    for (int o = 0; o < 4; ++o) q += w[o] * arow[off + c[a] - 1 + o];
+    for (int o = 0; o < S; ++o) q += w[o] * arow[off + c[a] + o];
     row *= q;
     off += g.m[a];
   }
@@ -408,7 +398,10 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
       rc = dskip_diag(p, dres, st);
       if (rc < 0) break;
     } else {
-      k_pc_diag<<<vb, kBlock, 0, st>>>(g, p->cell, p->toff, dres);
+      if (p->S == kInterpQuintic)
+        k_pc_diag<kInterpQuintic><<<vb, kBlock, 0, st>>>(g, p->cell, p->toff, dres);
+      else
+        k_pc_diag<kInterpCubic><<<vb, kBlock, 0, st>>>(g, p->cell, p->toff, dres);
     }
     const double rel_tol = 1e-12;
     for (int j = 0; j < k; ++j) {
@@ -418,9 +411,15 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
         if (rc < 0) break;
         continue;
       }
-      k_pivot_select<<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, pc->piv_tile, p->cell, p->toff,
-                                           arow, pc->L, lrow, forced, dres);
-      k_pc_column<<<vb, kBlock, 0, st>>>(g, j, ps, p->cell, p->toff, arow, lrow, pc->L, dres);
+      if (p->S == kInterpQuintic) {
+        k_pivot_select<kInterpQuintic><<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, pc->piv_tile, p->cell,
+                                                             p->toff, arow, pc->L, lrow, forced, dres);
+        k_pc_column<kInterpQuintic><<<vb, kBlock, 0, st>>>(g, j, ps, p->cell, p->toff, arow, lrow, pc->L, dres);
+      } else {
+        k_pivot_select<kInterpCubic><<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, pc->piv_tile, p->cell,
+                                                           p->toff, arow, pc->L, lrow, forced, dres);
+        k_pc_column<kInterpCubic><<<vb, kBlock, 0, st>>>(g, j, ps, p->cell, p->toff, arow, lrow, pc->L, dres);
+      }
     }
     if (rc < 0) break;
     if (hipGetLastError() != hipSuccess) {
@@ -580,7 +579,7 @@ static dski_status build_entry(const char* who, dski_plan p, int k, dski_precond
   dski_status rc = build_impl(p, k, pc, rank_host, piv_host, forced, st);
   if (forced) {
     // the build has synchronised its stream before returning
-    hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(st);
     fbuf.release();
   }
   if (rc < 0) {

@@ -6,49 +6,68 @@
 // interpolates g on its cubic stencil, value and d derivative weights, with
 // 4^d grid reads whatever the number of training points.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
+#include "interp.h"
 #include "tskinny.h"
 
 namespace dski {
+
+// Calls f(D, S) with the plan's dimension and stencil width as integral
+// constants (d = 1..3 is checked by the callers' plans).
+template <int V>
+using IC = std::integral_constant<int, V>;
+template <typename F>
+static void with_ds(dski_plan p, F&& f) {
+  const bool q = p->S == kInterpQuintic;
+  switch (p->d) {
+    case 1: q ? f(IC<1>{}, IC<kInterpQuintic>{}) : f(IC<1>{}, IC<kInterpCubic>{}); break;
+    case 2: q ? f(IC<2>{}, IC<kInterpQuintic>{}) : f(IC<2>{}, IC<kInterpCubic>{}); break;
+    default: q ? f(IC<3>{}, IC<kInterpQuintic>{}) : f(IC<3>{}, IC<kInterpCubic>{}); break;
+  }
+}
 
 struct PredGeo {
   int m[DSKI_MAXD];
   double lo[DSKI_MAXD], h[DSKI_MAXD], ih[DSKI_MAXD];
 };
 
-// Cubic stencil of test point u: value and derivative weights per axis and
-// the first stencil node; a point outside the interpolation box (or not
-// finite) sets err and is clamped into it.
-template <int D>
+// Stencil of test point u (S nodes per axis, H = S/2 - 1 below the anchor):
+// value and derivative weights per axis and the first stencil node; a point
+// outside the interpolation box (or not finite) sets err and is clamped into it.
+template <int D, int S>
 __device__ inline void pred_stencil(const double* __restrict__ Xs, int u, const PredGeo& geo,
-                                    double (&w)[D][4], double (&dw)[D][4], long long (&c0)[D],
+                                    double (&w)[D][S], double (&dw)[D][S], long long (&c0)[D],
                                     int* __restrict__ err) {
 #pragma unroll
   for (int a = 0; a < D; ++a) {
+    constexpr int H = S / 2 - 1;
+    const double smin = (double)H, smax = (double)(geo.m[a] - S + H + 1);
     double s = (Xs[(size_t)u * D + a] - geo.lo[a]) / geo.h[a];
-    if (!(s >= 1.0 - 1e-9 && s <= (double)(geo.m[a] - 2) + 1e-9)) {
+    if (!(s >= smin - 1e-9 && s <= smax + 1e-9)) {
       atomicOr(err, 1);
-      s = fmin(fmax(s, 1.0), (double)(geo.m[a] - 2));
+      s = fmin(fmax(s, smin), smax);
     }
     int i = (int)floor(s);
-    i = i < 1 ? 1 : (i > geo.m[a] - 3 ? geo.m[a] - 3 : i);
+    const int imax = geo.m[a] - S + H;
+    i = i < H ? H : (i > imax ? imax : i);
     const double t = fmin(fmax(s - (double)i, 0.0), 1.0);
-    keys_weights(t, geo.ih[a], w[a], dw[a]);
-    c0[a] = i - 1;
+    interp_weights<S>(t, geo.ih[a], w[a], dw[a]);
+    c0[a] = i - H;
   }
 }
 
-// Grid node and value weight of stencil entry e (axis offsets in base 4, the
+// Grid node and value weight of stencil entry e (axis offsets in base S, the
 // last axis fastest).
-template <int D>
-__device__ inline long long stencil_node(int e, const PredGeo& geo, const double (&w)[D][4],
+template <int D, int S>
+__device__ inline long long stencil_node(int e, const PredGeo& geo, const double (&w)[D][S],
                                          const long long (&c0)[D], int (&o)[D], double& wp) {
   int rem = e;
 #pragma unroll
   for (int a = D - 1; a >= 0; --a) {
-    o[a] = rem & 3;
-    rem >>= 2;
+    o[a] = rem % S;
+    rem /= S;
   }
   long long node = 0;
   wp = 1.0;
@@ -62,23 +81,23 @@ __device__ inline long long stencil_node(int e, const PredGeo& geo, const double
 
 // One thread per test point: the stencil sums in FP64; out row u =
 // [mean f, mean d f / d x_1 .. d x_D].
-template <int D>
+template <int D, int S>
 __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, PredGeo geo, int ns,
                                                  const double* __restrict__ Xs, double* __restrict__ out,
                                                  int* __restrict__ err) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= ns) return;
-  double w[D][4], dw[D][4];
+  double w[D][S], dw[D][S];
   long long c0[D];
-  pred_stencil<D>(Xs, u, geo, w, dw, c0, err);
+  pred_stencil<D, S>(Xs, u, geo, w, dw, c0, err);
   double acc[D + 1];
 #pragma unroll
   for (int q = 0; q <= D; ++q) acc[q] = 0.0;
-  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  constexpr int NS = D == 1 ? S : (D == 2 ? S * S : S * S * S);
   for (int e = 0; e < NS; ++e) {
     int o[D];
     double wp;
-    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+    const long long node = stencil_node<D, S>(e, geo, w, c0, o, wp);
     const double gv = g[node];
     acc[0] += wp * gv;
 #pragma unroll
@@ -101,38 +120,38 @@ __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ g, P
 // forms per-block partials of ||D^{-1/2} K_{Xx}||^2 (kVarSplit blocks per
 // column); k_var_final subtracts K_{xX} M^{-1} K_{Xx} = that norm - kq, kq the
 // preconditioner's low-rank term.
-template <int D>
+template <int D, int S>
 __global__ __launch_bounds__(256) void k_var_fill(PredGeo geo, int r0, int nb_pts, const double* __restrict__ Xs,
                                                   double* __restrict__ G, long long M, int* __restrict__ err) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nb_pts) return;
-  double w[D][4], dw[D][4];
+  double w[D][S], dw[D][S];
   long long c0[D];
-  pred_stencil<D>(Xs, r0 + j, geo, w, dw, c0, err);
-  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  pred_stencil<D, S>(Xs, r0 + j, geo, w, dw, c0, err);
+  constexpr int NS = D == 1 ? S : (D == 2 ? S * S : S * S * S);
   for (int e = 0; e < NS; ++e) {
     int o[D];
     double wp;
-    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+    const long long node = stencil_node<D, S>(e, geo, w, c0, o, wp);
     G[(size_t)j * M + node] = wp;
   }
 }
 
-template <int D>
+template <int D, int S>
 __global__ __launch_bounds__(256) void k_var_kxx(PredGeo geo, int r0, int nb_pts, const double* __restrict__ Xs,
                                                  const double* __restrict__ G, long long M,
                                                  double* __restrict__ kxx, int* __restrict__ err) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nb_pts) return;
-  double w[D][4], dw[D][4];
+  double w[D][S], dw[D][S];
   long long c0[D];
-  pred_stencil<D>(Xs, r0 + j, geo, w, dw, c0, err);
-  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  pred_stencil<D, S>(Xs, r0 + j, geo, w, dw, c0, err);
+  constexpr int NS = D == 1 ? S : (D == 2 ? S * S : S * S * S);
   double acc = 0.0;
   for (int e = 0; e < NS; ++e) {
     int o[D];
     double wp;
-    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+    const long long node = stencil_node<D, S>(e, geo, w, c0, o, wp);
     acc += wp * G[(size_t)j * M + node];
   }
   kxx[j] = acc;
@@ -177,44 +196,44 @@ __global__ __launch_bounds__(256) void k_var_final(const double* __restrict__ kx
 // Randomized variance (Sec. 4.4, second approach), per chunk of probes.
 // k_probe_scatter: grid column r receives sum_j z_{r0+r, j} w_{x_j} (test-point
 // value stencils weighted by the probe; FP64 atomic adds, as stencils overlap).
-template <int D>
+template <int D, int S>
 __global__ __launch_bounds__(256) void k_probe_scatter(PredGeo geo, int ns, const double* __restrict__ Xs,
                                                        const double* __restrict__ Zp, int r0,
                                                        double* __restrict__ G, long long M, int* __restrict__ err) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
   if (j >= ns) return;
-  double w[D][4], dw[D][4];
+  double w[D][S], dw[D][S];
   long long c0[D];
-  pred_stencil<D>(Xs, j, geo, w, dw, c0, err);
+  pred_stencil<D, S>(Xs, j, geo, w, dw, c0, err);
   const double z = Zp[(size_t)(r0 + r) * ns + j];
-  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  constexpr int NS = D == 1 ? S : (D == 2 ? S * S : S * S * S);
   for (int e = 0; e < NS; ++e) {
     int o[D];
     double wp;
-    const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+    const long long node = stencil_node<D, S>(e, geo, w, c0, o, wp);
     atomicAdd(&G[(size_t)r * M + node], z * wp);
   }
 }
 
 // acc[j] += sum_r z_{r0+r, j} w_{x_j}^T G_r over the rc columns of the chunk.
-template <int D>
+template <int D, int S>
 __global__ __launch_bounds__(256) void k_probe_read(PredGeo geo, int ns, const double* __restrict__ Xs,
                                                     const double* __restrict__ Zp, int r0, int rc,
                                                     const double* __restrict__ G, long long M,
                                                     double* __restrict__ acc, int* __restrict__ err) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= ns) return;
-  double w[D][4], dw[D][4];
+  double w[D][S], dw[D][S];
   long long c0[D];
-  pred_stencil<D>(Xs, j, geo, w, dw, c0, err);
-  constexpr int NS = D == 1 ? 4 : (D == 2 ? 16 : 64);
+  pred_stencil<D, S>(Xs, j, geo, w, dw, c0, err);
+  constexpr int NS = D == 1 ? S : (D == 2 ? S * S : S * S * S);
   double a = acc[j];
   for (int r = 0; r < rc; ++r) {
     double e_r = 0.0;
     for (int e = 0; e < NS; ++e) {
       int o[D];
       double wp;
-      const long long node = stencil_node<D>(e, geo, w, c0, o, wp);
+      const long long node = stencil_node<D, S>(e, geo, w, c0, o, wp);
       e_r += wp * G[(size_t)r * M + node];
     }
     a += Zp[(size_t)(r0 + r) * ns + j] * e_r;
@@ -253,8 +272,8 @@ extern "C" dski_status dski_predict_grid(dski_plan p, const double* alpha, doubl
   DSKI_TRY(p->vout.reserve(sizeof(double) * (size_t)std::max(N, 1) + 64));
   double* at = p->vout.as<double>();
   DSKI_TRY(permute(p, +1, 1, alpha, N, at, N, st));
-  DSKI_TRY(scatter<double>(p, 1, at, N, g, st));
-  DSKI_TRY(apply_kuu(p, 1, g, st));
+  DSKI_TRY((scatter<double, double>)(p, 1, at, N, g, st));
+  DSKI_TRY(apply_kuu<double>(p, 1, g, st));
   return DSKI_OK;
 }
 
@@ -286,12 +305,10 @@ extern "C" dski_status dski_predict(dski_plan p, const double* g, int n_test, co
   int* err = p->vout.as<int>();
   DSKI_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
   const unsigned nb = (unsigned)((n_test + 255) / 256);
-  switch (p->d) {
-    case 1: k_predict<1><<<nb, 256, 0, st>>>(g, geo, n_test, X_test, out, err); break;
-    case 2: k_predict<2><<<nb, 256, 0, st>>>(g, geo, n_test, X_test, out, err); break;
-    case 3: k_predict<3><<<nb, 256, 0, st>>>(g, geo, n_test, X_test, out, err); break;
-    default: set_error("d=%d not supported", p->d); return DSKI_ENOTSUP;
-  }
+  with_ds(p, [&](auto Dc, auto Sc) {
+    constexpr int D_ = decltype(Dc)::value, S_ = decltype(Sc)::value;
+    k_predict<D_, S_><<<nb, 256, 0, st>>>(g, geo, n_test, X_test, out, err);
+  });
   DSKI_HIP(hipGetLastError());
   int herr = 0;
   DSKI_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -344,20 +361,18 @@ extern "C" dski_status dski_predict_var(dski_plan p, dski_precond pc, int n_test
     const int b = std::min(B, n_test - r0);
     const unsigned gb = (unsigned)((b + 255) / 256);
     DSKI_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)M * b, st));
-    switch (p->d) {
-      case 1: k_var_fill<1><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
-      case 2: k_var_fill<2><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
-      default: k_var_fill<3><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err); break;
-    }
+    with_ds(p, [&](auto Dc, auto Sc) {
+      constexpr int D_ = decltype(Dc)::value, S_ = decltype(Sc)::value;
+      k_var_fill<D_, S_><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, err);
+    });
     DSKI_HIP(hipGetLastError());
-    DSKI_TRY(apply_kuu(p, b, G, st));  // G = K_UU w_x
-    switch (p->d) {
-      case 1: k_var_kxx<1><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, kxx, err); break;
-      case 2: k_var_kxx<2><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, kxx, err); break;
-      default: k_var_kxx<3><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, kxx, err); break;
-    }
+    DSKI_TRY(apply_kuu<double>(p, b, G, st));  // G = K_UU w_x
+    with_ds(p, [&](auto Dc, auto Sc) {
+      constexpr int D_ = decltype(Dc)::value, S_ = decltype(Sc)::value;
+      k_var_kxx<D_, S_><<<gb, 256, 0, st>>>(geo, r0, b, X_test, G, M, kxx, err);
+    });
     DSKI_HIP(hipGetLastError());
-    DSKI_TRY(gather<double>(p, b, G, Z, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = S K_UU w_x
+    DSKI_TRY((gather<double, double>)(p, b, G, Z, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = S K_UU w_x
     // K_{xX} M^{-1} K_{Xx} = ||D^{-1/2} K_{Xx}||^2 - kq: the norm here, kq from
     // the preconditioner's projection, one tall-skinny launch of columns at a time
     k_var_sqnorm<<<dim3(kVarSplit, (unsigned)b), 256, 0, st>>>(Y, N, p->n, 1.0 / (p->sf * p->sf),
@@ -421,14 +436,13 @@ extern "C" dski_status dski_predict_var_probes(dski_plan p, dski_precond pc, int
     double* G = p->grid.as<double>();
     DSKI_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)M * rc, st));
     DSKI_HIP(hipMemsetAsync(U2, 0, sizeof(double) * (size_t)N * rc, st));
-    switch (p->d) {
-      case 1: k_probe_scatter<1><<<dim3(gb, rc), 256, 0, st>>>(geo, n_test, X_test, Zp, r0, G, M, err); break;
-      case 2: k_probe_scatter<2><<<dim3(gb, rc), 256, 0, st>>>(geo, n_test, X_test, Zp, r0, G, M, err); break;
-      default: k_probe_scatter<3><<<dim3(gb, rc), 256, 0, st>>>(geo, n_test, X_test, Zp, r0, G, M, err); break;
-    }
+    with_ds(p, [&](auto Dc, auto Sc) {
+      constexpr int D_ = decltype(Dc)::value, S_ = decltype(Sc)::value;
+      k_probe_scatter<D_, S_><<<dim3(gb, rc), 256, 0, st>>>(geo, n_test, X_test, Zp, r0, G, M, err);
+    });
     DSKI_HIP(hipGetLastError());
-    DSKI_TRY(apply_kuu(p, rc, G, st));
-    DSKI_TRY(gather<double>(p, rc, G, U2, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = K_{XX'} z
+    DSKI_TRY(apply_kuu<double>(p, rc, G, st));
+    DSKI_TRY((gather<double, double>)(p, rc, G, U2, N, Y, N, 0.0, 0.0, nullptr, st));  // Y = K_{XX'} z
     PcgResult res;
     std::vector<double> tols(rc, tol);
     std::vector<int> verify(rc, 1);
@@ -441,13 +455,12 @@ extern "C" dski_status dski_predict_var_probes(dski_plan p, dski_precond pc, int
     DSKI_HIP(hipGetLastError());
     DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)M * rc));  // the solver's products may have resized it
     G = p->grid.as<double>();
-    DSKI_TRY(scatter<double>(p, rc, U1, N, G, st));
-    DSKI_TRY(apply_kuu(p, rc, G, st));
-    switch (p->d) {
-      case 1: k_probe_read<1><<<gb, 256, 0, st>>>(geo, n_test, X_test, Zp, r0, rc, G, M, acc, err); break;
-      case 2: k_probe_read<2><<<gb, 256, 0, st>>>(geo, n_test, X_test, Zp, r0, rc, G, M, acc, err); break;
-      default: k_probe_read<3><<<gb, 256, 0, st>>>(geo, n_test, X_test, Zp, r0, rc, G, M, acc, err); break;
-    }
+    DSKI_TRY((scatter<double, double>)(p, rc, U1, N, G, st));
+    DSKI_TRY(apply_kuu<double>(p, rc, G, st));
+    with_ds(p, [&](auto Dc, auto Sc) {
+      constexpr int D_ = decltype(Dc)::value, S_ = decltype(Sc)::value;
+      k_probe_read<D_, S_><<<gb, 256, 0, st>>>(geo, n_test, X_test, Zp, r0, rc, G, M, acc, err);
+    });
     DSKI_HIP(hipGetLastError());
   }
   k_probe_final<<<gb, 256, 0, st>>>(acc, n_test, 1.0 / R, out);

@@ -257,9 +257,9 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
     if (rc < 0) break;
     double* G = p->grid.as<double>();
     double* H = G + (size_t)M * Rg;
-    rc = scatter<T>(p, R, X, N, G, st);
+    rc = scatter<T, double>(p, R, X, N, G, st);
     if (rc < 0) break;
-    rc = scatter<T>(p, t, Vv, N, G + (size_t)M * R, st);
+    rc = scatter<T, double>(p, t, Vv, N, G + (size_t)M * R, st);
     if (rc < 0) break;
     std::vector<int> cols;
     cols.push_back(0);
@@ -284,7 +284,7 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
     for (int which = 0; which <= d && rc >= 0; ++which) {
       int nb = (int)std::min<long long>(1024, (M + kBlock - 1) / kBlock);
       k_copy_cols_d<<<dim3(nb, 1 + t), kBlock, 0, st>>>(G, H, M, dcols, 1 + t);
-      rc = apply_kuu(p, 1 + t, H, st, which < d ? which : -1);
+      rc = apply_kuu<double>(p, 1 + t, H, st, which < d ? which : -1);
       if (rc < 0) break;
       std::vector<double> dots;
       rc = pair_dots<double>(H, M, G, M, gp, 0, M, dots, dotbuf, st);

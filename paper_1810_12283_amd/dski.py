@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdski.so")
 
 OK, NOT_CONVERGED, RANK_TRUNCATED = 0, 1, 2
+INTERP = {"cubic": 0, "quintic": 1}   # DSKI_INTERP_CUBIC, DSKI_INTERP_QUINTIC
 _STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "RANK_TRUNCATED", -1: "EINVAL", -2: "ENOMEM",
            -3: "EHIP", -4: "EBREAKDOWN", -5: "ENOTSUP"}
 
@@ -40,7 +41,7 @@ dp = C.POINTER(C.c_double)
 _SIGS = {
     "dski_last_error": (C.c_char_p, []),
     "dski_version": (C.c_char_p, []),
-    "dski_plan_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, vp, ip, dp, dp, vp]),
+    "dski_plan_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, vp, ip, dp, dp, C.c_int, vp]),
     "dski_plan_destroy": (C.c_int, [vp]),
     "dskip_plan_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, vp, C.c_int, C.c_int, C.c_uint64,
                                     dp, dp, dp, vp]),
@@ -157,8 +158,13 @@ def _block(V: torch.Tensor, N: int, name: str) -> torch.Tensor:
 class Plan:
     """A D-SKI operator on fixed points and grid (owns a dski_plan)."""
 
-    def __init__(self, X: torch.Tensor, grid_m: Sequence[int], lo=None, hi=None, stream=None):
+    def __init__(self, X: torch.Tensor, grid_m: Sequence[int], lo=None, hi=None, stream=None,
+                 interp: str = "cubic"):
+        """interp: "cubic" (Keys, 4 nodes per axis) or "quintic" (Meijering,
+        6 nodes per axis)."""
         L = lib()
+        if interp not in INTERP:
+            raise ValueError(f"interp must be one of {sorted(INTERP)}")
         if not X.is_cuda or X.dtype != torch.float64 or X.dim() != 2:
             raise TypeError("X must be a CUDA float64 tensor of shape (n, d)")
         X = X.contiguous()
@@ -168,8 +174,9 @@ class Plan:
         m = _arr([int(v) for v in grid_m], C.c_int)
         lo_a = _arr([float(v) for v in lo], C.c_double) if lo is not None else None
         hi_a = _arr([float(v) for v in hi], C.c_double) if hi is not None else None
-        _check(L.dski_plan_create(C.byref(h), n, d, _dptr(X), m, lo_a, hi_a, _stream(stream)),
+        _check(L.dski_plan_create(C.byref(h), n, d, _dptr(X), m, lo_a, hi_a, INTERP[interp], _stream(stream)),
                "dski_plan_create")
+        self.interp = interp
         self._h = h
         self._info()
 

@@ -26,14 +26,14 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make(W, grid=None):
+def make(W, grid=None, interp="cubic"):
     """(GPU plan, oracle operator) for a workload at its hyper-parameters."""
     dski = need_gpu()
     Xg = torch.tensor(W.X, dtype=torch.float64, device="cuda")
     m = grid or W.grid_m
-    plan = dski.Plan(Xg, m, W.lo, W.hi)
+    plan = dski.Plan(Xg, m, W.lo, W.hi, interp=interp)
     plan.set_hypers(*W.hypers())
-    op = odski.DSKI(W.X, m, W.lo, W.hi, *W.hypers())
+    op = odski.DSKI(W.X, m, W.lo, W.hi, *W.hypers(), interp_kind=interp)
     return plan, op
 
 
