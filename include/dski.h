@@ -357,7 +357,13 @@ dski_status pcg_solve_f64(dski_plan plan, dski_precond pc, int R, const double* 
 /* Stochastic Lanczos quadrature estimate of log det K~ (Sec. 2).  Probe i is
  * z_i = C w_i with w_i the Rademacher column i of the SplitMix64 stream
  * `seed` (see dski_rademacher) and C C^T = M (plain w_i when pc is NULL).
- * lanczos_steps > 0: that many PCG/Lanczos steps per probe; 0: to tol.
+ * lanczos_steps = 0: T_i from the CG coefficients of the block PCG on the
+ *   probes, run to tol (storage precision: dski_plan_set_precision).
+ * lanczos_steps > 0: that many steps of the explicit Lanczos process of the
+ *   preconditioned operator (M-inner product) per probe, with full
+ *   re-orthogonalisation, FP64 vectors; a probe whose Krylov space is exhausted
+ *   earlier stops there.  (The same tridiagonal as CG's in exact arithmetic;
+ *   a short run without re-orthogonalisation is ill-conditioned.)
  * logdet = log det M + (1/t) sum_i (z_i^T M^{-1} z_i) e_1^T log(T_i) e_1. */
 dski_status slq_logdet(dski_plan plan, dski_precond pc, int num_probes, int lanczos_steps,
                        double tol, int max_iter, uint64_t seed, double* logdet_host,

@@ -114,11 +114,24 @@ double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok) {
     *ok = 0;
     return 0.0;
   }
-  std::vector<double> a(J), b(J, 0.0), q(J, 0.0);
+  std::vector<double> a(J), b(J, 0.0);
   for (int j = 0; j < J; ++j) {
     a[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
     if (j + 1 < J) b[j] = std::sqrt(std::fmax(beta[j], 0.0)) / alpha[j];
   }
+  return gauss_quad_log_tri(a.data(), b.data(), J, ok);
+}
+
+// The same quadrature for a tridiagonal given directly: diagonal a[0..J),
+// couplings b[0..J-1).
+double gauss_quad_log_tri(const double* diag, const double* off, int J, int* ok) {
+  *ok = 1;
+  if (J <= 0) {
+    *ok = 0;
+    return 0.0;
+  }
+  std::vector<double> a(diag, diag + J), b(J, 0.0), q(J, 0.0);
+  for (int j = 0; j + 1 < J; ++j) b[j] = off[j];
   q[0] = 1.0;
   const double eps = 2.220446049250313e-16;
   auto negligible = [&](int i) { return std::fabs(b[i]) <= eps * (std::fabs(a[i]) + std::fabs(a[i + 1])); };

@@ -10,6 +10,7 @@
 // for ell_p and s it is S K_UU' S^T with K_UU' the Kronecker-Toeplitz matrix with
 // the derivative spectrum on axis p (or 2 K_UU), so the products reduce to dot
 // products of scattered grids; for the noise levels it is diagonal.
+#include <algorithm>
 #include <cmath>
 #include <thread>
 
@@ -123,6 +124,201 @@ static void slq_combine(const std::vector<double>& ab, int max_iter, int R, int 
 }  // namespace dski
 
 using namespace dski;
+
+// ---------------------------------------------------------------- fixed-step Lanczos
+// part[b, i t + c] = sum over a row chunk of A[i t + c] . Bv[c] (column stride N),
+// for the first J vector slots i of each of the t columns.
+__global__ void k_lz_dots(const double* __restrict__ A, const double* __restrict__ Bv, int N, int t, int J,
+                          double* __restrict__ part) {
+  const int q = blockIdx.y, c = q % t;
+  const double* a = A + (size_t)q * N;
+  const double* b = Bv + (size_t)c * N;
+  double acc = 0.0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x)
+    acc += a[e] * b[e];
+  __shared__ double red[4];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)blockIdx.x * ((size_t)J * t) + q] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// W[c] -= sum_{i < J} h[i t + c] Q[i t + c]   (Q column stride N)
+__global__ void k_lz_sub(const double* __restrict__ Q, const double* __restrict__ h, int N, int t, int J,
+                         double* __restrict__ W) {
+  const int c = blockIdx.y;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x) {
+    double v = W[(size_t)c * N + e];
+    for (int i = 0; i < J; ++i) v -= h[(size_t)i * t + c] * Q[((size_t)i * t + c) * N + e];
+    W[(size_t)c * N + e] = v;
+  }
+}
+
+// Out[c] = In[c] * f[c]
+__global__ void k_lz_scale(const double* __restrict__ In, const double* __restrict__ f, int N,
+                           double* __restrict__ Out) {
+  const int c = blockIdx.y;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x)
+    Out[(size_t)c * N + e] = In[(size_t)c * N + e] * f[c];
+}
+
+// Fixed-step SLQ (lanczos_steps > 0): for every probe z = C w the explicit
+// Lanczos process of the preconditioned operator in the M-inner product (the
+// process CG runs implicitly, Sec. 2), with full re-orthogonalisation:
+// residual-space vectors q_j and z_j = M^{-1} q_j,
+//   w = K~ z_j,  a_j = z_j . w,  w -= a_j q_j + b_{j-1} q_{j-1},
+//   then twice  w -= sum_{i <= j} (z_i . w) q_i   (classical Gram-Schmidt),
+//   b_j = sqrt(w . M^{-1} w),  q_{j+1} = w / b_j.
+// The quadrature weight is ||z||^2_{M^{-1}}.  A short run without
+// re-orthogonalisation is ill-conditioned (rounding-level changes of K~ or
+// M^{-1} move its value by ~1e-3); this one is not.  All vectors FP64.
+static dski_status slq_fixed_lanczos(dski_plan p, dski_precond pc, int t, int steps, uint64_t seed,
+                                     double* logdet_host, double* stderr_host, hipStream_t st) {
+  const int N = p->N;
+  const size_t nr = (size_t)N * t;
+  const int nb = std::max(1, std::min(256, (N + kBlock - 1) / kBlock));
+  const int vb = std::max(1, std::min(1024, (N + kBlock - 1) / kBlock));
+  DevBuf tmp;
+  // Qs, Zs (steps + 1 slots of t columns each), W, ZW, X; partials and small scalars
+  const size_t vec_doubles = 2 * (size_t)(steps + 1) * nr + 3 * nr;
+  const size_t small = (size_t)nb * (steps + 1) * t + 2 * (size_t)(steps + 1) * t + 64;
+  DSKI_TRY(tmp.reserve(sizeof(double) * (vec_doubles + small)));
+  double* Qs = tmp.as<double>();
+  double* Zs = Qs + (size_t)(steps + 1) * nr;
+  double* W = Zs + (size_t)(steps + 1) * nr;
+  double* ZW = W + nr;
+  double* X = ZW + nr;
+  double* part = X + nr;
+  double* hdev = part + (size_t)nb * (steps + 1) * t;
+  double* rdev = hdev + (size_t)(steps + 1) * t;
+  auto dots = [&](const double* A, const double* Bv, int J, std::vector<double>& out) -> dski_status {
+    k_lz_dots<<<dim3(nb, J * t), kBlock, 0, st>>>(A, Bv, N, t, J, part);
+    DSKI_HIP(hipGetLastError());
+    DSKI_TRY(reduce_partials(part, nb, J * t, rdev, st));
+    out.assign((size_t)J * t, 0.0);
+    DSKI_HIP(hipMemcpyAsync(out.data(), rdev, sizeof(double) * out.size(), hipMemcpyDeviceToHost, st));
+    DSKI_HIP(hipStreamSynchronize(st));
+    return DSKI_OK;
+  };
+  auto sub = [&](const std::vector<double>& h, int J) -> dski_status {
+    DSKI_HIP(hipMemcpyAsync(hdev, h.data(), sizeof(double) * (size_t)J * t, hipMemcpyHostToDevice, st));
+    k_lz_sub<<<dim3(vb, t), kBlock, 0, st>>>(Qs, hdev, N, t, J, W);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  };
+  auto scale = [&](const double* In, const std::vector<double>& f, double* Out) -> dski_status {
+    DSKI_HIP(hipMemcpyAsync(hdev, f.data(), sizeof(double) * t, hipMemcpyHostToDevice, st));
+    k_lz_scale<<<dim3(vb, t), kBlock, 0, st>>>(In, hdev, N, Out);
+    DSKI_HIP(hipGetLastError());
+    return DSKI_OK;
+  };
+  auto msolve = [&](const double* In, double* Out) -> dski_status {
+    if (pc) return precond_apply_tiled<double>(pc, t, In, N, Out, N, nullptr, nullptr, st);
+    DSKI_HIP(hipMemcpyAsync(Out, In, sizeof(double) * nr, hipMemcpyDeviceToDevice, st));
+    return DSKI_OK;
+  };
+  dski_status rc = DSKI_OK;
+  do {
+    // probes in user order -> tile order -> r_0 = z = C w
+    rc = rademacher<double>(seed, 0, t, N, X, N, st);
+    if (rc < 0) break;
+    rc = permute(p, +1, t, X, N, ZW, N, st);
+    if (rc < 0) break;
+    if (pc) {
+      rc = precond_factor_apply_tiled<double>(pc, t, ZW, N, W, N, st);
+    } else {
+      rc = hipMemcpyAsync(W, ZW, sizeof(double) * nr, hipMemcpyDeviceToDevice, st) == hipSuccess ? DSKI_OK
+                                                                                                 : DSKI_EHIP;
+    }
+    if (rc < 0) break;
+    rc = msolve(W, ZW);
+    if (rc < 0) break;
+    std::vector<double> nrm2;
+    rc = dots(ZW, W, 1, nrm2);  // z . M^{-1} z  (slot 0 of ZW pairs with column c of W)
+    if (rc < 0) break;
+    std::vector<double> f(t);
+    for (int c = 0; c < t; ++c) f[c] = nrm2[c] > 0.0 ? 1.0 / std::sqrt(nrm2[c]) : 0.0;
+    rc = scale(W, f, Qs);
+    if (rc < 0) break;
+    rc = scale(ZW, f, Zs);
+    if (rc < 0) break;
+    std::vector<std::vector<double>> diag(t), off(t);
+    std::vector<int> done(t, 0);
+    std::vector<double> bprev(t, 0.0);
+    for (int j = 0; j < steps && rc >= 0; ++j) {
+      const double* Qj = Qs + (size_t)j * nr;
+      const double* Zj = Zs + (size_t)j * nr;
+      rc = mvm_tiled<double>(p, t, Zj, N, W, N, nullptr, st);
+      if (rc < 0) break;
+      std::vector<double> a;
+      rc = dots(Zj, W, 1, a);
+      if (rc < 0) break;
+      // three-term step: coefficients a_j on slot j and b_{j-1} on slot j-1
+      std::vector<double> h((size_t)(j + 1) * t, 0.0);
+      for (int c = 0; c < t; ++c) {
+        if (!done[c]) diag[c].push_back(a[c]);
+        h[(size_t)j * t + c] = a[c];
+        if (j > 0) h[(size_t)(j - 1) * t + c] = bprev[c];
+      }
+      rc = sub(h, j + 1);
+      if (rc < 0) break;
+      for (int pass = 0; pass < 2 && rc >= 0; ++pass) {  // full re-orthogonalisation
+        std::vector<double> hh;
+        rc = dots(Zs, W, j + 1, hh);
+        if (rc < 0) break;
+        rc = sub(hh, j + 1);
+      }
+      if (rc < 0) break;
+      rc = msolve(W, ZW);
+      if (rc < 0) break;
+      std::vector<double> bb;
+      rc = dots(ZW, W, 1, bb);
+      if (rc < 0) break;
+      if (j == steps - 1) break;
+      for (int c = 0; c < t; ++c) {
+        const double b = std::sqrt(std::fmax(bb[c], 0.0));
+        // a vanishing b ends the column's process (Krylov space exhausted); its
+        // later slots only carry zeros
+        if (done[c] || !(b > 1e-14 * std::fabs(diag[c].back()))) {
+          done[c] = 1;
+          f[c] = 0.0;
+          bprev[c] = 0.0;
+        } else {
+          off[c].push_back(b);
+          f[c] = 1.0 / b;
+          bprev[c] = b;
+        }
+      }
+      rc = scale(W, f, Qs + (size_t)(j + 1) * nr);
+      if (rc < 0) break;
+      rc = scale(ZW, f, Zs + (size_t)(j + 1) * nr);
+    }
+    if (rc < 0) break;
+    std::vector<double> vals(t);
+    bool ok_all = true;
+    for (int c = 0; c < t; ++c) {
+      int ok = 0;
+      const double q = gauss_quad_log_tri(diag[c].data(), off[c].data(), (int)diag[c].size(), &ok);
+      if (!ok) ok_all = false;
+      vals[c] = nrm2[c] * q;
+    }
+    if (!ok_all) {
+      set_error("SLQ: non-positive Ritz value or quadrature failure");
+      rc = DSKI_EBREAKDOWN;
+      break;
+    }
+    double mean = 0.0;
+    for (double v : vals) mean += v;
+    mean /= t;
+    double var = 0.0;
+    for (double v : vals) var += (v - mean) * (v - mean);
+    *logdet_host = (pc ? pc->logdet : 0.0) + mean;
+    if (stderr_host) *stderr_host = t > 1 ? std::sqrt(var / (t - 1) / t) : NAN;
+  } while (0);
+  (void)hipStreamSynchronize(st);
+  tmp.release();
+  return rc;
+}
 
 template <typename T>
 static dski_status slq_impl(dski_plan p, dski_precond pc, int t, int lanczos_steps, double tol, int max_iter,
@@ -357,6 +553,7 @@ dski_status slq_logdet(dski_plan p, dski_precond pc, int t, int lanczos_steps, d
     return DSKI_EINVAL;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (lanczos_steps > 0) return slq_fixed_lanczos(p, pc, t, lanczos_steps, seed, logdet_host, stderr_host, st);
   if (p->precision == 64)
     return slq_impl<double>(p, pc, t, lanczos_steps, tol, max_iter, seed, logdet_host, stderr_host, st);
   return slq_impl<float>(p, pc, t, lanczos_steps, tol, max_iter, seed, logdet_host, stderr_host, st);

@@ -115,43 +115,39 @@ def _oracle_slq_pcg(op, P, Z, steps=None, tol=None):
     return slq.estimate(q, w, P.logdet())
 
 
-def test_slq_fixed_steps_fp64_matches_oracle():
-    """small2d (an FP64 configuration): 10 probes x 30 Lanczos steps with FP64
-    storage, same probes and preconditioner as the oracle.  Thirty CG steps
-    without re-orthogonalisation leave this estimate ill-conditioned: the GPU's
-    operator and preconditioner applications differ from the oracle's at the
-    FP64 rounding level, and symmetric perturbations of K~ and M^{-1} of that
-    size (1e-13 of their largest entry) move the oracle's own value by about
-    1e-3 relative.  The bar is 1e-3 relative or four times the RMS deviation of
-    eight such perturbed oracle runs, whichever is larger (a wrong estimator is
-    off by percents); the converged estimate (next test) is held to 1e-3."""
+def test_slq_fixed_steps_matches_oracle():
+    """small2d (the FP64 configuration): 10 probes x 30 Lanczos steps, the
+    explicit preconditioned Lanczos process with full re-orthogonalisation on
+    both sides, same probes and pivots as the oracle: log det within 1e-3
+    relative (the spec bar; without re-orthogonalisation a 30-step run
+    is ill-conditioned and this bar could not be held).  Also checked with
+    FP32 plan storage (the fixed-step path keeps FP64 vectors) and against the
+    exact log det within the truncation bias of 30 steps (7 % here)."""
     W = workloads.small2d()
-    say("slq small2d fp64, 30 steps")
+    say("slq small2d, 30 re-orthogonalised Lanczos steps")
     plan, op, pc, L, gaps = _pivchol_pair(W, W.rank)
-    plan.set_precision(64)
-    ld_gpu, se_gpu = plan.slq_logdet(pc, W.num_probes, W.lanczos_steps, seed=SEED)
     P = precond.Precond(L, op.Dn)
-    Z = P.factor_apply(orng.rademacher(SEED, 0, W.num_probes, op.N))
-    ld_or, se_or = _oracle_slq_pcg(op, P, Z, steps=W.lanczos_steps)
-    Minv = P.solve(np.eye(op.N))
-    K = op.dense()
-    devs = []
-    for s in range(11, 19):
-        r = np.random.default_rng(s)
-        E = r.standard_normal((op.N, op.N))
-        E = (E + E.T) * (1e-13 * np.abs(Minv).max())
-        F = r.standard_normal((op.N, op.N))
-        F = (F + F.T) * (1e-13 * np.abs(K).max())
-        Pp = type("Pp", (), {"solve": staticmethod(lambda B, E=E: P.solve(B) + E @ B),
-                             "logdet": staticmethod(P.logdet)})
-        opp = type("Op", (), {"matvec": staticmethod(lambda B, F=F: op.matvec(B) + F @ B)})
-        devs.append(_oracle_slq_pcg(opp, Pp, Z, steps=W.lanczos_steps)[0] - ld_or)
-    rms = float(np.sqrt(np.mean(np.square(devs))))
-    exact = np.linalg.slogdet(K)[1]
-    say("  gpu", ld_gpu, se_gpu, "oracle", ld_or, se_or, "perturbed oracle deviations", np.round(devs, 3),
-        "rms", rms, "exact", exact)
-    assert abs(ld_gpu - ld_or) <= max(1e-3 * abs(ld_or), 4.0 * rms)
-    assert abs(ld_gpu - exact) < 0.15 * abs(exact)
+    Wr = orng.rademacher(SEED, 0, W.num_probes, op.N)
+    ld_or, se_or = slq.fixed_step_logdet(op.matvec, P, Wr, W.lanczos_steps)
+    exact = np.linalg.slogdet(op.dense())[1]
+    for bits in (64, 32):
+        plan.set_precision(bits)
+        ld_gpu, se_gpu = plan.slq_logdet(pc, W.num_probes, W.lanczos_steps, seed=SEED)
+        rel = abs(ld_gpu - ld_or) / abs(ld_or)
+        say("  bits", bits, "gpu", ld_gpu, se_gpu, "oracle", ld_or, se_or, "rel", rel, "exact", exact)
+        assert rel <= 1e-3
+        assert abs(se_gpu - se_or) <= 1e-3 * se_or
+    assert abs(ld_gpu - exact) < 0.1 * abs(exact)
+    # a probe block whose Krylov space is exhausted early (6 x 6 grid, rank 36:
+    # the preconditioner is exact) ends after one step: log det M
+    dski = need_gpu()
+    r = np.random.default_rng(3)
+    X = r.random((20, 2))
+    plan2 = dski.Plan(torch.tensor(X, device="cuda"), [6, 6], [0, 0], [1, 1])
+    plan2.set_hypers(np.log([0.3, 0.3]), 0.0, np.log(0.05), np.log(0.1))
+    pc2 = plan2.pivchol(60)
+    ld2, _ = plan2.slq_logdet(pc2, 3, 10, seed=SEED)
+    assert ld2 == pytest.approx(pc2.logdet(), rel=1e-10)
 
 
 @pytest.mark.parametrize("bits", [32, 64])
