@@ -275,6 +275,60 @@ def active_block(D=20, n=20000, reps=10):
             "project_ms": round(p_ms, 3), "eigenvalue_ratio_3_1": float(lam[2] / lam[0])}
 
 
+def grid_block(W, R, stream, interp="cubic", reps=20, solve=True, max_iter=20000):
+    """One D-SKI workload on its own (tuner, block MVM of R columns with its
+    per-stage times and the roofline of the dominant stage), then, with solve,
+    the rank-k pivoted Cholesky and mll_and_grad with 16 probes to the
+    workload's tolerance: used for the implicit-surface workload (torus,
+    n = 30,000 on 48^3) and for the terrain workload with quintic weights."""
+    import numpy as np
+    import torch
+    from paper_1810_12283_amd import dski
+    t0 = time.perf_counter()
+    plan = dski.Plan(torch.tensor(W.X, dtype=torch.float64, device="cuda"), W.grid_m, W.lo, W.hi, interp=interp)
+    plan.set_hypers(*W.hypers())
+    tune = plan.autotune(R)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    N, n, d, M = W.N, W.n, W.d, plan.grid_nodes
+    V = torch.sign(torch.randn((R, N), device="cuda", dtype=torch.float32))
+    Vt = plan.permute(V, +1)
+    Yt = torch.empty_like(Vt)
+    med, p10, p90 = _events_stats(lambda: plan.mvm_tiled(Vt, out=Yt), reps, stream)
+    stage = {"scatter": _events_ms(lambda: plan.mvm_stage(0, Vt), reps, stream),
+             "kuu": _events_ms(lambda: plan.mvm_stage(1, Vt), reps, stream)}
+    plan.mvm_stage(0, Vt)
+    stage["gather"] = _events_ms(lambda: plan.mvm_stage(2, Vt, Yt), reps, stream)
+    Bm = mvm_bytes(N, M, n, d, R)
+    sb = stage_bytes(N, M, n, d, R)
+    dom = max(stage, key=stage.get)
+    ach = sb[dom] / (stage[dom] * 1e-3) / 1e9
+    out = {"workload": f"{W.name} n={n} d={d} grid={'x'.join(map(str, W.grid_m))} R={R} interp={interp}",
+           "setup_and_tune_s": round(t_setup, 3), "mvm_ms": round(med, 4), "mvm_ms_p10_p90": [round(p10, 4),
+                                                                                            round(p90, 4)],
+           "mvm_algorithmic_bytes": Bm, "mvm_gbs": round(Bm / (med * 1e-3) / 1e9, 1),
+           "stage_ms": {k: round(v, 4) for k, v in stage.items()}, "variants": tuned_variants(tune),
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}}
+    if solve:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pc = plan.pivchol(W.rank)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        y = torch.tensor(W.y, dtype=torch.float32, device="cuda")[None, :]
+        res = plan.mll_and_grad(y, pc, num_probes=W.num_probes, seed=SEED, tol=W.tol, max_iter=max_iter)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out.update({"rank": W.rank, "tol": W.tol, "pivchol_s": round(t2 - t1, 4),
+                    "mll_and_grad_s": round(t3 - t2, 4), "mll_pcg_iters": int(max(res["iters"])),
+                    "mll_status": int(res["status"]), "mll": res["mll"], "logdet": res["logdet"],
+                    "grad": [float(v) for v in res["grad"]]})
+        pc.close()
+    plan.close()
+    return out
+
+
 def mvm_bytes(N, M, n, d, R):
     """Algorithmic bytes of one block MVM (FP32 vectors and grid):
     V read by the scatter and again for the noise term, Y written (3 N R);
@@ -291,12 +345,19 @@ def stage_bytes(N, M, n, d, R):
     }
 
 
-def cpu_baseline(W, R, budget_s=20.0):
-    """The FP64 oracle's MVM on the same workload, timed on the host cores."""
+def cpu_baseline(W, R, X_gpu=None, B=None, budget_s=12.0, pcg_iters=20):
+    """The FP64 oracle on the same workload, timed on the host cores: its MVM
+    of the R-column block (repeated for about budget_s), and its block PCG with
+    the oracle's rank-k pivoted-Cholesky preconditioner, of which `pcg_iters`
+    iterations are timed and the seconds to 1e-4 extrapolated from that
+    per-iteration time and the oracle's iteration count (stored by
+    tests/golden/make_oracle_golden.py from a full oracle run).  With the GPU's
+    block-PCG solution X_gpu of B (host arrays, N x R), also the oracle's FP64
+    true relative residual ||b - K~ x|| / ||b|| of every column (worst one)."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
-    from oracle import dski as odski
+    from oracle import dski as odski, krylov, pivchol, precond
     op = odski.DSKI(W.X, W.grid_m, W.lo, W.hi, *W.hypers())
     V = np.random.default_rng(0).standard_normal((op.N, R))
     op.matvec(V)  # warm
@@ -309,10 +370,30 @@ def cpu_baseline(W, R, budget_s=20.0):
             break
     dt = (time.perf_counter() - t0) / reps
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    B = mvm_bytes(op.N, op.grid.size, op.n, op.d, R)
-    return {"value": round(B / dt / 1e9, 4), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{reps} FP64 oracle MVMs (scipy CSR + dense Kronecker K_UU) of the {R}-column "
-                      f"terrain block, {dt * 1e3:.1f} ms each"}
+    Bm = mvm_bytes(op.N, op.grid.size, op.n, op.d, R)
+    out = {"value": round(Bm / dt / 1e9, 4), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{reps} FP64 oracle MVMs (scipy CSR + dense Kronecker K_UU) of the {R}-column "
+                     f"terrain block, {dt * 1e3:.1f} ms each; {pcg_iters} oracle block-PCG iterations"}
+    # block PCG: per-iteration time of the oracle's own loop on the same columns
+    L, _, _ = pivchol.pivoted_cholesky(op.diag_K(), op.row_K, W.rank)
+    P = precond.Precond(L, op.Dn)
+    Bo = B if B is not None else V
+    t1 = time.perf_counter()
+    krylov.pcg(op.matvec, Bo, precond=P.solve, fixed_iters=pcg_iters)
+    per_iter = (time.perf_counter() - t1) / pcg_iters
+    gold = os.path.join(ROOT, "tests", "golden", "terrain_full_oracle.json")
+    iters = None
+    if os.path.exists(gold):
+        with open(gold) as f:
+            iters = int(max(json.load(f)["iters"]))
+    out["pcg_s_per_iter"] = round(per_iter, 5)
+    out["pcg_oracle_iters"] = iters
+    out["pcg_s"] = round(per_iter * iters, 2) if iters else None
+    out["pcg_s_kind"] = ("extrapolated: measured per-iteration time x the iteration count of a full oracle run "
+                         "to 1e-4 (stored)")
+    if X_gpu is not None and B is not None:
+        out["gpu_pcg_true_relres_oracle"] = float(krylov.true_relres(op.matvec, B, X_gpu).max())
+    return out
 
 
 def main(argv=None):
@@ -511,7 +592,8 @@ def main(argv=None):
             true_rel = (Rt.norm(dim=1) / Bd.norm(dim=1)).max().item()
             Rt64 = Bd - plan.mvm(Xs64)
             true_rel64 = (Rt64.norm(dim=1) / Bd.norm(dim=1)).max().item()
-            out = dict(tune=tune, variants=variants, ms_mvm=ms_mvm, ms_p10=ms_p10, ms_p90=ms_p90, ms_stage=ms_stage,
+            out = dict(X_host=Xs.cpu().numpy().T.copy(), B_host=B.double().cpu().numpy().T.copy(),
+                       tune=tune, variants=variants, ms_mvm=ms_mvm, ms_p10=ms_p10, ms_p90=ms_p90, ms_stage=ms_stage,
                        setup_s=t1 - t0, pivchol_s=t2 - t1,
                        pcg_s=t3 - t2, mll_s=t4 - t3, iters=iters, relres=max(relres), status=st,
                        true_rel=true_rel, mll=res["mll"], logdet=res["logdet"],
@@ -598,12 +680,16 @@ def main(argv=None):
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
     }
+    line["torus"] = grid_block(workloads.torus(), R, stream)
+    line["terrain_quintic"] = grid_block(W, R, stream, interp="quintic")
     line["dskip"] = dskip_block(R, stream)
     line["surrogate"] = surrogate_block(W, y, W.rank, stream)
     line["predict"] = predict_block(W, stream)
     line["active_subspace"] = active_block()
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(W, R)
+        line["cpu_baseline"] = cpu_baseline(W, R, recs[-1]["X_host"], recs[-1]["B_host"])
+        # the headline solve's residual as the oracle's FP64 operator sees it
+        line["pcg_true_relres_oracle"] = line["cpu_baseline"].get("gpu_pcg_true_relres_oracle")
     print(json.dumps(line), flush=True)
     return 0
 

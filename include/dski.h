@@ -278,6 +278,17 @@ dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int
  * choice, not reported, serves the FP64 MVMs and solvers.  1 <= R <= 32. */
 dski_status dski_autotune(dski_plan plan, int R, double* times_host, dski_stream stream);
 
+/* dski_autotune with a per-shape cache: cache_path (host string) names a text
+ * file of tuned shapes, one line each, keyed by the device architecture, plan
+ * kind, d, stencil width, n, grid sizes and R.  A matching line sets the
+ * variants without timing anything (*hit_host = 1, times_host filled with -1);
+ * otherwise the tuner runs and appends its choice (*hit_host = 0).  hit_host and
+ * times_host may be NULL.  Calls in one process are serialised; the file is
+ * not locked against other processes.  DSKI_EINVAL when the path is empty or
+ * cannot be appended to. */
+dski_status dski_autotune_cached(dski_plan plan, int R, const char* cache_path, int* hit_host,
+                                 double* times_host, dski_stream stream);
+
 /* Select the scatter (0..5, for FP32 and FP64 column values alike) and gather
  * (0..2) variants directly. */
 dski_status dski_set_variants(dski_plan plan, int scatter_variant, int gather_variant);

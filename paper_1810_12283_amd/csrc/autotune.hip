@@ -7,6 +7,10 @@
 // number of right-hand sides.  The tuner times each candidate with HIP events
 // on the caller's stream and keeps the fastest in the plan.
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
 
 #include "internal.h"
 
@@ -172,5 +176,75 @@ extern "C" dski_status dski_set_kuu_variant(dski_plan p, int axis, int variant) 
     return DSKI_EINVAL;
   }
   p->kuu_variant[axis] = variant;
+  return DSKI_OK;
+}
+
+// ---------------------------------------------------------------- per-shape cache
+// One text line per tuned shape:
+//   dski-tune-v1 <arch> kind=<0|1> d=<d> S=<S> n=<n> m=<m0>x<m1>x<m2> R=<R> : <scatter> <scatter64> <gather> <kuu0> <kuu1> <kuu2>
+// The key holds everything the timings depend on (device architecture, plan
+// kind, dimension, stencil, points, grid and right-hand sides).
+static std::mutex tune_cache_mu;
+
+static std::string tune_key(dski_plan p, int R) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  char buf[256];
+  int m[3] = {0, 0, 0};
+  for (int a = 0; a < p->d && a < 3; ++a) m[a] = p->ax[a].m;
+  snprintf(buf, sizeof(buf), "dski-tune-v1 %s kind=%d d=%d S=%d n=%d m=%dx%dx%d R=%d", arch.c_str(), p->kind, p->d,
+           p->S, p->n, m[0], m[1], m[2], R);
+  return buf;
+}
+
+extern "C" dski_status dski_autotune_cached(dski_plan p, int R, const char* cache_path, int* hit_host,
+                                            double* times_host, dski_stream stream) {
+  if (!p || R <= 0 || R > 32 || !cache_path || !cache_path[0]) {
+    set_error("dski_autotune_cached: bad arguments (1 <= R <= 32, cache path required)");
+    return DSKI_EINVAL;
+  }
+  const std::string key = tune_key(p, R);
+  std::lock_guard<std::mutex> lock(tune_cache_mu);
+  if (FILE* f = fopen(cache_path, "r")) {
+    char line[512];
+    bool found = false;
+    int v[6] = {0, 0, 0, 0, 0, 0};
+    while (fgets(line, sizeof(line), f)) {
+      const char* colon = strstr(line, " : ");
+      if (!colon || (size_t)(colon - line) != key.size() || strncmp(line, key.c_str(), key.size()) != 0) continue;
+      int w[6];
+      if (sscanf(colon + 3, "%d %d %d %d %d %d", &w[0], &w[1], &w[2], &w[3], &w[4], &w[5]) == 6 && w[0] >= 0 &&
+          w[0] < kScatterVariants && w[1] >= 0 && w[1] < kScatterVariants && w[2] >= 0 && w[2] < kGatherVariants &&
+          w[3] >= 0 && w[3] <= 1 && w[4] >= 0 && w[4] <= 1 && w[5] >= 0 && w[5] <= 1) {
+        for (int i = 0; i < 6; ++i) v[i] = w[i];
+        found = true;  // the last matching line wins
+      }
+    }
+    fclose(f);
+    if (found) {
+      p->scatter_variant = v[0];
+      p->scatter_variant64 = v[1];
+      p->gather_variant = v[2];
+      for (int a = 0; a < DSKI_MAXD; ++a) p->kuu_variant[a] = (a < p->d && p->ax[a].m <= kDenseMaxM) ? v[3 + a] : 0;
+      if (hit_host) *hit_host = 1;
+      if (times_host)
+        for (int i = 0; i < kTuneTimes; ++i) times_host[i] = -1.0;  // not measured
+      return DSKI_OK;
+    }
+  }
+  DSKI_TRY(dski_autotune(p, R, times_host, stream));
+  if (hit_host) *hit_host = 0;
+  FILE* f = fopen(cache_path, "a");
+  if (!f) {
+    set_error("dski_autotune_cached: cannot append to %s", cache_path);
+    return DSKI_EINVAL;
+  }
+  fprintf(f, "%s : %d %d %d %d %d %d\n", key.c_str(), p->scatter_variant, p->scatter_variant64, p->gather_variant,
+          p->kuu_variant[0], p->kuu_variant[1], p->kuu_variant[2]);
+  fclose(f);
   return DSKI_OK;
 }

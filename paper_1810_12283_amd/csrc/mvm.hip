@@ -98,9 +98,10 @@ __device__ __forceinline__ void interp_weight_at(double t, double ih, int o, dou
 // point in the cells whose stencils reach the tile (the tile's cells plus a
 // halo of S - 1 - H below and H above), with a table of each cell's range, then
 // every thread sums its node's contributions from LDS in the same fixed order
-// as above.  Up to PMAX = 256 region points one thread stages one point;
-// regions with more points fall back to reading through the cache (same order,
-// same result).
+// as above.  One thread stages one region point; regions of more than 256
+// points (dense tiles: surfaces in 3-D, wide quintic stencils) are staged 256
+// points at a time, each node adding the points of every chunk that fall in
+// its cells (same order, same result).
 template <int D, int S>
 struct TileShape {
   static constexpr int e0 = D == 1 ? 256 : (D == 2 ? 16 : 4);
@@ -276,17 +277,41 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   const int rc = min(cr, R - r0);
   const long long off = tile_off[blockIdx.x];
   const int total = (int)(tile_off[blockIdx.x + 1] - off);
-  const bool lds_ok = total <= PMAX;
-  if (lds_ok) {
-    // the region tables of the plan: cell ranges, and for this thread's slot the
-    // point and its last-axis anchor; then the point's offsets (its weights) and
-    // column values
+  {
     const int* lcs = tile_lcs + (size_t)blockIdx.x * (TS::max_cells + 1);
     for (int f = threadIdx.x; f <= TR.ncells; f += blockDim.x) s_lcs[f] = lcs[f];
+  }
+  int j[D];
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    j[a] = origin[a] + jl[a];
+    inside = inside && j[a] < g.m[a];
+  }
+  double acc[CR];
+#pragma unroll
+  for (int r = 0; r < CR; ++r) acc[r] = 0.0;
+  int lo[D], hi[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = max(H, j[a] - (S - 1 - H));
+    hi[a] = min(g.nc[a] + H - 1, j[a] + H);
+  }
+  int nrow = 1;  // the node's outer cell rows (all axes but the last)
+#pragma unroll
+  for (int a = 0; a < last; ++a) nrow *= hi[a] - lo[a] + 1;
+  // The region's points are staged PMAX at a time, in slot order (one thread
+  // per point: its last-axis anchor, weights and column values).  After each
+  // chunk every node adds the points of that chunk that lie in its cells: its
+  // outer cell rows in odometer order, and in each the contiguous run of cells
+  // lo..hi on the last axis.  The node therefore adds its points in the same
+  // order whatever the chunking (rows ascending, slots ascending in a row).
+  for (int q0 = 0; q0 < total; q0 += PMAX) {
+    if (q0 > 0) __syncthreads();  // every node is done with the previous chunk
     const int q = threadIdx.x;
-    if (q < total) {
-      const int kq = tile_pts[off + q];
-      const int cq = tile_cl[off + q];
+    if (q0 + q < total) {
+      const int kq = tile_pts[off + q0 + q];
+      const int cq = tile_cl[off + q0 + q];
       double tq[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) tq[a] = toff[(size_t)a * n + kq];
@@ -311,103 +336,37 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
       for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
       s_cl[q] = cq;
     }
-  }
-  __syncthreads();
-  int j[D];
-  bool inside = true;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    j[a] = origin[a] + jl[a];
-    inside = inside && j[a] < g.m[a];
-  }
-  if (!inside) return;
-  double acc[CR];
-#pragma unroll
-  for (int r = 0; r < CR; ++r) acc[r] = 0.0;
-  int lo[D], hi[D], c[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    lo[a] = max(H, j[a] - (S - 1 - H));
-    hi[a] = min(g.nc[a] + H - 1, j[a] + H);
-    c[a] = lo[a];
-  }
-  if (lds_ok) {
-    // The node's points in the fixed order: outer cells c[0..last-1] in
-    // odometer order, and for each the contiguous run of points of cells
-    // lo..hi on the last axis.  All runs are walked as one sequence, so a
-    // wavefront iterates as often as its busiest node has points.
-    auto run = [&](int& q, int& qe) {
-      int lrow = 0;
-#pragma unroll
-      for (int a = 0; a < last; ++a) lrow = lrow * span[a] + (c[a] - rlo[a]);
-      q = s_lcs[lrow * span[last] + lo[last] - rlo[last]];
-      qe = s_lcs[lrow * span[last] + hi[last] - rlo[last] + 1];
-    };
-    int q, qe;
-    run(q, qe);
-    while (true) {
-      bool done = false;
-      while (q >= qe) {
-        int a = last - 1;
-        while (a >= 0 && c[a] == hi[a]) {
-          c[a] = lo[a];
-          --a;
-        }
-        if (a < 0) {
-          done = true;
-          break;
-        }
-        ++c[a];
-        run(q, qe);
-      }
-      if (done) break;
-      double wv[D], wd[D];
-      const int cl = s_cl[q];
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const int o = j[a] - (a == last ? cl : c[a]) + H;
-        wv[a] = s_w[q * WS + a * 2 * S + o];
-        wd[a] = s_w[q * WS + a * 2 * S + S + o];
-      }
-      scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)q * CR * (D + 1));
-      ++q;
-    }
-  } else {
-    int outer_cnt = 1;
-#pragma unroll
-    for (int a = 0; a < last; ++a) outer_cnt *= hi[a] - lo[a] + 1;
-    for (int oc = 0; oc < outer_cnt; ++oc) {
-      int rem = oc, base = 0;
+    __syncthreads();
+    if (!inside) continue;
+    const int q1 = min(total, q0 + PMAX);
+    for (int row = 0; row < nrow; ++row) {
+      int c[D];
+      int rem = row, lrow = 0;
 #pragma unroll
       for (int a = last - 1; a >= 0; --a) {
-        int sp = hi[a] - lo[a] + 1;
+        const int sp = hi[a] - lo[a] + 1;
         c[a] = lo[a] + rem % sp;
         rem /= sp;
       }
 #pragma unroll
-      for (int a = 0; a < last; ++a) base = base * g.nc[a] + (c[a] - H);
-      base *= g.nc[last];
-      const int kb = cstart[base + lo[last] - H];
-      const int ke = cstart[base + hi[last] - H + 1];
-      for (int k = kb; k < ke; ++k) {
-        const int clast = cell[k] % g.nc[last] + H;
+      for (int a = 0; a < last; ++a) lrow = lrow * span[a] + (c[a] - rlo[a]);
+      const int qs = max(q0, s_lcs[lrow * span[last] + lo[last] - rlo[last]]);
+      const int qe = min(q1, s_lcs[lrow * span[last] + hi[last] - rlo[last] + 1]);
+      for (int qq = qs; qq < qe; ++qq) {
+        const int ql = qq - q0;
         double wv[D], wd[D];
+        const int cl = s_cl[ql];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const int o = j[a] - ((a == last) ? clast : c[a]) + H;
-          interp_weight_at<S>(toff[(size_t)a * n + k], g.invh[a], o, wv[a], wd[a]);
+          const int o = j[a] - (a == last ? cl : c[a]) + H;
+          wv[a] = s_w[ql * WS + a * 2 * S + o];
+          wd[a] = s_w[ql * WS + a * 2 * S + S + o];
         }
-        T x[CR * (D + 1)];
-#pragma unroll
-        for (int r = 0; r < CR; ++r)
-#pragma unroll
-          for (int b2 = 0; b2 <= D; ++b2)
-            x[r * (D + 1) + b2] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b2 * n + k,
-                                         (size_t)r0 * ldv + (size_t)b2 * n + k, r < rc);
-        scatter_accum<D, CR>(acc, wv, wd, x);
+        scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)ql * CR * (D + 1));
       }
     }
   }
+  if (!inside) return;
   long long node = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) node = node * g.m[a] + j[a];
@@ -608,16 +567,11 @@ static dski_status build_tiles(dski_plan p, hipStream_t st) {
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_tot);
   DSKI_HIP(e);
-  long long slots = 0, over = 0;
+  long long slots = 0;
   for (long long t = 0; t < tiles; ++t) {
     off[(size_t)t] = (int)slots;
     slots += tot[(size_t)t];
-    if (tot[(size_t)t] > 256) over += tot[(size_t)t];
   }
-  // Most region points in tiles too full for LDS staging (256 points; dense
-  // 1-D grids with many points per cell): the cache-direct form is the default;
-  // the tuner may still pick another form (all give identical results).
-  if (2 * over > slots) p->scatter_variant = p->scatter_variant64 = 1;
   if (slots > (1ll << 31) - 1) {
     set_error("scatter region tables too large");
     return DSKI_ENOTSUP;

@@ -76,6 +76,7 @@ _SIGS = {
     "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
     "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_autotune": (C.c_int, [vp, C.c_int, dp, vp]),
+    "dski_autotune_cached": (C.c_int, [vp, C.c_int, C.c_char_p, ip, dp, vp]),
     "dski_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
     "dski_set_graph": (C.c_int, [vp, C.c_int]),
     "dski_set_kuu_variant": (C.c_int, [vp, C.c_int, C.c_int]),
@@ -326,12 +327,21 @@ class Plan:
                                   _stream(stream)), "dski_permute")
         return Y
 
-    def autotune(self, R: int, stream=None) -> dict:
-        """Time the kernel variants for this shape and keep the fastest."""
+    def autotune(self, R: int, stream=None, cache: Optional[str] = None) -> dict:
+        """Time the kernel variants for this shape and keep the fastest; with
+        cache (a file path) reuse the choice stored for this shape if there is
+        one (the result then has cached=True and no timings)."""
         t = (C.c_double * 15)()
-        _check(lib().dski_autotune(self._h, int(R), t, _stream(stream)), "dski_autotune")
+        if cache is None:
+            _check(lib().dski_autotune(self._h, int(R), t, _stream(stream)), "dski_autotune")
+            hit = False
+        else:
+            h = C.c_int()
+            _check(lib().dski_autotune_cached(self._h, int(R), str(cache).encode(), C.byref(h), t, _stream(stream)),
+                   "dski_autotune_cached")
+            hit = bool(h.value)
         return {"scatter_us": [t[i] for i in range(6)], "gather_us": [t[6], t[7], t[8]],
-                "kuu_us": [[t[9 + 2 * a], t[10 + 2 * a]] for a in range(min(self.d, 3))]}
+                "kuu_us": [[t[9 + 2 * a], t[10 + 2 * a]] for a in range(min(self.d, 3))], "cached": hit}
 
     def set_variants(self, scatter: int, gather: int = 0):
         _check(lib().dski_set_variants(self._h, int(scatter), int(gather)), "dski_set_variants")

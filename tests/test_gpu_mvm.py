@@ -256,3 +256,26 @@ def test_mvm_clustered_points_mix_both_scatter_paths():
     assert err < 1e-12
     for o in outs[1:]:
         assert torch.equal(outs[0], o)
+
+
+def test_autotune_cache_reuses_the_choice_per_shape(tmp_path):
+    """The per-shape tuner cache: the first plan of a shape is timed and its
+    choice appended; a second plan of the same shape reuses it without timing
+    (and multiplies identically); another R or stencil width is a new shape."""
+    W = workloads.terrain(n=3000, grid=60)
+    say("autotune cache")
+    cache = str(tmp_path / "tune.txt")
+    plan, op = make(W)
+    t1 = plan.autotune(17, cache=cache)
+    assert not t1["cached"] and min(t1["scatter_us"]) > 0
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and " R=17 : " in lines[0] and " S=4 " in lines[0]
+    plan2, _ = make(W)
+    t2 = plan2.autotune(17, cache=cache)
+    assert t2["cached"] and all(v == -1 for v in t2["scatter_us"])
+    V = to_gpu(np.random.default_rng(9).standard_normal((op.N, 17)))
+    assert torch.equal(plan.mvm(V), plan2.mvm(V))
+    assert not plan2.autotune(5, cache=cache)["cached"]
+    plan3, _ = make(W, interp="quintic")
+    assert not plan3.autotune(17, cache=cache)["cached"]
+    assert len(open(cache).read().splitlines()) == 3
