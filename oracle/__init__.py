@@ -16,7 +16,7 @@ instead of Cholesky-QR, explicit Lanczos as well as CG-derived tridiagonals.
 Modules:
   rng       counter-based SplitMix64 Rademacher probes (Steele et al. 2014)
   kernels   SE kernel and the exact derivative kernel k^grad (Sec. 2, App. A, App. B)
-  interp    uniform grid and Keys cubic convolution weights (Sec. 3.1)
+  interp    uniform grid, Keys cubic and quintic convolution weights (Sec. 3.1)
   dski      D-SKI operator [W; dW] K_UU [W; dW]^T + D, its diagonal and rows (Sec. 3.1, 3.3)
   pivchol   truncated pivoted Cholesky (Sec. 3.3)
   precond   M = D + L L^T, stable QR solve and square-root form (Sec. 3.3)
@@ -24,6 +24,7 @@ Modules:
   slq       stochastic Lanczos quadrature for log det (Sec. 2)
   mll       log marginal likelihood eq. (1) and its hyper-parameter gradient
   dskip     D-SKIP Hadamard operator with Lanczos compression (Sec. 3.2)
+  spline    thin-plate spline kernel under D-SKI, dense K_UU (App. A, Sec. 4.3)
   mlp       the small GELU MLP log-det surrogate (FP64 reference)
 
 Readings of points the paper leaves open are stated in each function's
