@@ -302,6 +302,25 @@ dski_status dski_set_kuu_variant(dski_plan plan, int axis, int variant);
  * by events); 0 launches every kernel directly.  Results are bitwise equal. */
 dski_status dski_set_graph(dski_plan plan, int on);
 
+/* Kernels of K_UU (App. A). */
+#define DSKI_KERNEL_SE 0      /* squared exponential, ARD length scales (default)          */
+#define DSKI_KERNEL_SPLINE 1  /* thin-plate spline s^2 (r^3 + a r^2 + b) (d odd) or
+                               * s^2 (r^2 log r + a r^2 + b) (d even)                      */
+
+/* Select the kernel of a D-SKI plan.  The spline kernel (App. A; the implicit
+ * surface of Sec. 4.3) is not a product kernel: K_UU is a symmetric multi-level
+ * Toeplitz matrix, applied by its d-dimensional circulant embedding (FFT along
+ * every axis, lengths L_p >= 2 m_p - 1).  Its a and b (not given in the paper)
+ * are those of the Williams-Fitzgibbon thin-plate covariances with domain size R
+ * = twice the grid diameter: d odd a = -3R/2, b = R^3/2; d even
+ * a = -(1 + 2 log R)/2, b = R^2/2, which makes K_UU positive definite on the
+ * grid.  Hyper-parameters: s and the noise levels; the length scales passed to
+ * dski_set_hypers are ignored and their gradient entries are zero.  Every
+ * solver call works on such a plan; dski_mvm_tiled_noalloc and the dense K_UU
+ * variant do not apply.  Computes the spectrum once (on `stream`).
+ * DSKI_ENOTSUP for D-SKIP plans. */
+dski_status dski_set_kernel(dski_plan plan, int kernel, dski_stream stream);
+
 /* Storage precision (32 or 64 bits) of the N-vectors that slq_logdet creates
  * internally (probes, Krylov vectors).  Default 32. */
 dski_status dski_plan_set_precision(dski_plan plan, int bits);

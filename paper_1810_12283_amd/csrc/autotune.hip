@@ -133,7 +133,8 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
     int best = 0;
     for (int v = 0; v < 2; ++v) {
       double* ta = t + kScatterVariants + kGatherVariants + 2 * a;
-      if (v == 1 && p->ax[a].m > kDenseMaxM) {  // no dense form on this axis: reported as -1
+      if (p->kernel == kKernelSpline || (v == 1 && p->ax[a].m > kDenseMaxM)) {
+        // no dense form on this axis (or no separable factor at all): -1
         ta[v] = -1.0;
         continue;
       }

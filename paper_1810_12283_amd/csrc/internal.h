@@ -82,6 +82,8 @@ __host__ __device__ constexpr int fft_tw_offset(int lg, int s, int dir) {
 }
 __host__ __device__ constexpr int fft_tw_size(int lg) { return fft_tw_offset(lg, fft_npass(lg), -1); }
 constexpr int kFftMaxLog2 = 11;  // L <= 2048, m <= 1024 per axis
+constexpr int kKernelSE = 0;
+constexpr int kKernelSpline = 1;
 constexpr int kDenseMaxM = 448;  // largest axis for the dense matrix-core Toeplitz product
 
 // Per-axis geometry of the grid and its circulant embedding.
@@ -114,6 +116,10 @@ struct dski_plan_s {
   dski::DskipData* ds = nullptr;
   int n = 0, d = 0, N = 0;
   int S = 4;                   // stencil nodes per axis: 4 cubic (Keys), 6 quintic
+  int kernel = 0;              // kKernelSE (separable Toeplitz factors) or kKernelSpline
+  double spline_R = 0;         // spline kernel: domain size R (twice the grid diameter)
+  double* bttb_spec = nullptr; // spline kernel: spectrum of the embedded K_UU / prod L (device)
+  dski::DevBuf bttb_work;      // spline kernel: complex embedded columns
   long long M = 0;             // grid nodes
   int ncells = 0;              // total interpolation cells
   dski::Axis ax[DSKI_MAXD];
@@ -174,6 +180,7 @@ dski_status kuu_axis(dski_plan p, int R, GT* G, hipStream_t st, int dwhich, int 
 template <typename T, typename GT>
 dski_status scatter(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st);
 dski_status scatter_tables(dski_plan p, hipStream_t st);  // build the region tables (plan set-up)
+dski_status bttb_build_spectrum(dski_plan p, hipStream_t st);  // spline kernel: spectrum of K_UU
 template <typename T, typename GT>
 dski_status gather(dski_plan p, int R, const GT* G, const T* V, int ldv, T* Y, int ldy,
                    double nv, double ng, double* pq_partial, hipStream_t st);

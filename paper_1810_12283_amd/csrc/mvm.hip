@@ -14,8 +14,10 @@
 //                           complex transform;
 //   gather   Y = S G + D V  one thread per point, FP64 accumulation, FP32 store,
 //                           optional fused per-block partials of V.Y.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -1071,11 +1073,382 @@ dski_status kuu_axis(dski_plan p, int R, GT* G, hipStream_t st, int dwhich, int 
 
 template dski_status kuu_axis<double>(dski_plan, int, double*, hipStream_t, int, int, int);
 
+// ------------------------------------------------------------------ K_UU of the spline kernel
+// The spline kernel (App. A) is not a product kernel: K_UU is a symmetric
+// multi-level Toeplitz matrix (block Toeplitz with Toeplitz blocks in 2-D),
+// applied through its d-dimensional circulant embedding of size L_0 x .. x
+// L_{d-1} (the per-axis FFT lengths, L_p >= 2 m_p - 1):
+//   K_UU G = crop( F^{-1} diag(lambda) F pad(G) ),  lambda = F c,
+// with c the embedded generating array (kernel values at the node offsets,
+// wrapped, zero outside the band).  lambda is real (c is even on every axis),
+// so two real grid columns travel as the real and imaginary parts of one
+// complex array.  The transform runs axis by axis with the line FFT of the
+// separable case (radix-8 Stockham passes in registers, LDS exchanges):
+// forward on axes 0 .. d-2, forward * lambda * inverse on the last
+// (contiguous) axis in one kernel, inverse on axes d-2 .. 0.
+
+// Natural position of value e of lane lp (input of a forward transform, output
+// of an inverse one), and the frequency it holds after the last forward pass
+// (input of the first inverse pass).
+template <int LG>
+__device__ __forceinline__ int fft_pos_nat(int lp, int e) {
+  using S = FftShape<LG>;
+  constexpr int R0 = fft_radix_dir(LG, 0, +1);
+  return lp + (e / R0) * S::TPL + (e % R0) * (S::L / R0);
+}
+template <int LG>
+__device__ __forceinline__ int fft_pos_freq(int lp, int e) {
+  using S = FftShape<LG>;
+  constexpr int RL = fft_radix_dir(LG, S::NP - 1, +1);
+  return lp + (e / RL) * S::TPL + (e % RL) * (S::L / RL);
+}
+
+// One complex FFT (DIR = +1 forward, -1 inverse, unnormalised) of every line of
+// length L = 2^LG along an axis: line l starts at (l / inner) L inner + l % inner
+// and steps by inner.  A forward transform reads natural order and writes
+// frequency order; an inverse one the reverse.  In place (a work-group holds
+// its lines in registers between the read and the write).
+template <int LG, int DIR>
+__global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long long nlines, long long inner,
+                                                  const double2* __restrict__ tw) {
+  using S = FftShape<LG>;
+  constexpr int E = S::E, TPL = S::TPL, L = S::L;
+  extern __shared__ double2 smem[];
+  const int lp = threadIdx.x % TPL;
+  const int slot = threadIdx.x / TPL;
+  double2* buf = smem + (size_t)slot * S::LP;
+  const double2* stw = tw;
+  if constexpr (S::STAGE) {
+    double2* t = smem + (size_t)S::PAIRS * S::LP;
+    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
+    stw = t;
+    __syncthreads();
+  }
+  const long long line = (long long)blockIdx.x * S::PAIRS + slot;
+  const bool ok = line < nlines;
+  const long long base = ok ? (line / inner) * L * inner + line % inner : 0;
+  double2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int pos = DIR > 0 ? fft_pos_nat<LG>(lp, e) : fft_pos_freq<LG>(lp, e);
+    v[e] = ok ? Z[base + (long long)pos * inner] : make_double2(0.0, 0.0);
+  }
+  fft_run<LG, DIR, 0>(v, buf, stw, lp);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int pos = DIR > 0 ? fft_pos_freq<LG>(lp, e) : fft_pos_nat<LG>(lp, e);
+      Z[base + (long long)pos * inner] = v[e];
+    }
+  }
+}
+
+// Last (contiguous) axis: forward, times lambda (row o = l mod nouter of the
+// spectrum, L values), inverse.
+template <int LG>
+__global__ __launch_bounds__(256) void k_fft_last_spec(double2* __restrict__ Z, long long nlines, long long nouter,
+                                                       const double2* __restrict__ tw,
+                                                       const double* __restrict__ spec) {
+  using S = FftShape<LG>;
+  constexpr int E = S::E, TPL = S::TPL, L = S::L;
+  extern __shared__ double2 smem[];
+  const int lp = threadIdx.x % TPL;
+  const int slot = threadIdx.x / TPL;
+  double2* buf = smem + (size_t)slot * S::LP;
+  const double2* stw = tw;
+  if constexpr (S::STAGE) {
+    double2* t = smem + (size_t)S::PAIRS * S::LP;
+    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
+    stw = t;
+    __syncthreads();
+  }
+  const long long line = (long long)blockIdx.x * S::PAIRS + slot;
+  const bool ok = line < nlines;
+  double2* A = Z + (ok ? line : 0) * L;
+  const double* sp = spec + (ok ? line % nouter : 0) * L;
+  double2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = ok ? A[fft_pos_nat<LG>(lp, e)] : make_double2(0.0, 0.0);
+  fft_run<LG, +1, 0>(v, buf, stw, lp);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sp[fft_pos_freq<LG>(lp, e)]);
+  fft_run<LG, -1, 0>(v, buf, stw, lp);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) A[fft_pos_nat<LG>(lp, e)] = v[e];
+  }
+}
+
+struct BoxL {
+  int d;
+  int m[DSKI_MAXD], L[DSKI_MAXD];
+  double h[DSKI_MAXD];
+};
+
+static BoxL box_of(dski_plan p) {
+  BoxL b{};
+  b.d = p->d;
+  for (int a = 0; a < p->d; ++a) {
+    b.m[a] = p->ax[a].m;
+    b.L[a] = p->ax[a].L;
+    b.h[a] = p->ax[a].h;
+  }
+  return b;
+}
+
+// Multi-index of embedded position j (last axis fastest); returns the node
+// index (last axis fastest) or -1 outside the m box.
+__device__ __forceinline__ long long bttb_node(long long j, const BoxL& b, int (&jj)[DSKI_MAXD]) {
+  long long rem = j, node = 0, stride = 1;
+  bool in = true;
+  for (int a = b.d - 1; a >= 0; --a) {
+    jj[a] = (int)(rem % b.L[a]);
+    rem /= b.L[a];
+    in = in && jj[a] < b.m[a];
+  }
+  if (!in) return -1;
+  for (int a = b.d - 1; a >= 0; --a) {
+    node += (long long)jj[a] * stride;
+    stride *= b.m[a];
+  }
+  return node;
+}
+
+// Spline kernel profile k(r) / s^2 (App. A; a, b as in the header: domain size R).
+__device__ __forceinline__ double spline_profile(double r, int d, double R) {
+  if (d & 1) return r * r * r - 1.5 * R * r * r + 0.5 * R * R * R;
+  const double rl = r > 0.0 ? r * r * log(r) : 0.0;
+  return rl - 0.5 * (1.0 + 2.0 * log(R)) * r * r + 0.5 * R * R;
+}
+
+// Generating array of the circulant embedding: offset j_p (wrapped) on every
+// axis, zero outside the band |offset| < m_p.
+__global__ void k_bttb_gen(BoxL b, double R, long long tot, double2* __restrict__ Z) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < tot;
+       j += (long long)gridDim.x * blockDim.x) {
+    long long rem = j;
+    double r2 = 0.0;
+    bool band = true;
+    for (int a = b.d - 1; a >= 0; --a) {
+      const int ja = (int)(rem % b.L[a]);
+      rem /= b.L[a];
+      const int off = ja < b.m[a] ? ja : (ja > b.L[a] - b.m[a] ? b.L[a] - ja : -1);
+      band = band && off >= 0;
+      const double x = (double)off * b.h[a];
+      r2 += x * x;
+    }
+    Z[j] = make_double2(band ? spline_profile(sqrt(r2), b.d, R) : 0.0, 0.0);
+  }
+}
+
+__global__ void k_bttb_spec(const double2* __restrict__ Z, long long tot, double scale, double* __restrict__ spec) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < tot;
+       j += (long long)gridDim.x * blockDim.x)
+    spec[j] = Z[j].x * scale;
+}
+
+// Z[c2] = G[2 c2] + i G[2 c2 + 1] on the m box, zero elsewhere.
+__global__ void k_bttb_pack(const double* __restrict__ G, long long M, int R, BoxL b, long long tot,
+                            double2* __restrict__ Z) {
+  const int c2 = blockIdx.y;
+  const int ca = 2 * c2, cb = 2 * c2 + 1;
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < tot;
+       j += (long long)gridDim.x * blockDim.x) {
+    int jj[DSKI_MAXD];
+    const long long node = bttb_node(j, b, jj);
+    double2 v = make_double2(0.0, 0.0);
+    if (node >= 0) {
+      v.x = G[(size_t)ca * M + node];
+      if (cb < R) v.y = G[(size_t)cb * M + node];
+    }
+    Z[(size_t)c2 * tot + j] = v;
+  }
+}
+
+// G[2 c2] = scale Re Z[c2], G[2 c2 + 1] = scale Im Z[c2] on the m box.
+__global__ void k_bttb_unpack(const double2* __restrict__ Z, long long M, int R, BoxL b, long long tot,
+                              double scale, double* __restrict__ G) {
+  const int c2 = blockIdx.y;
+  const int ca = 2 * c2, cb = 2 * c2 + 1;
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < tot;
+       j += (long long)gridDim.x * blockDim.x) {
+    int jj[DSKI_MAXD];
+    const long long node = bttb_node(j, b, jj);
+    if (node < 0) continue;
+    const double2 v = Z[(size_t)c2 * tot + j];
+    G[(size_t)ca * M + node] = scale * v.x;
+    if (cb < R) G[(size_t)cb * M + node] = scale * v.y;
+  }
+}
+
+template <int LG, int DIR>
+static dski_status launch_fft_axis(double2* Z, long long nlines, long long inner, const double2* tw, hipStream_t st) {
+  using S = FftShape<LG>;
+  const size_t sh = sizeof(double2) * ((size_t)S::PAIRS * S::LP + (S::STAGE ? S::TW : 0));
+  if (sh > 64 * 1024) {
+    static bool done = false;
+    if (!done) {
+      DSKI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_axis<LG, DIR>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+      done = true;
+    }
+  }
+  const long long blocks = (nlines + S::PAIRS - 1) / S::PAIRS;
+  k_fft_axis<LG, DIR><<<(unsigned)blocks, 256, sh, st>>>(Z, nlines, inner, tw);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+template <int LG>
+static dski_status launch_fft_last(double2* Z, long long nlines, long long nouter, const double2* tw,
+                                   const double* spec, hipStream_t st) {
+  using S = FftShape<LG>;
+  const size_t sh = sizeof(double2) * ((size_t)S::PAIRS * S::LP + (S::STAGE ? S::TW : 0));
+  if (sh > 64 * 1024) {
+    static bool done = false;
+    if (!done) {
+      DSKI_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_last_spec<LG>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+      done = true;
+    }
+  }
+  const long long blocks = (nlines + S::PAIRS - 1) / S::PAIRS;
+  k_fft_last_spec<LG><<<(unsigned)blocks, 256, sh, st>>>(Z, nlines, nouter, tw, spec);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+static int log2_exact(int L) {
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  return lg;
+}
+
+static dski_status fft_axis(double2* Z, int L, int dir, long long nlines, long long inner, const double2* tw,
+                            hipStream_t st) {
+#define DSKI_FA(LGV)                                                                          \
+  case LGV:                                                                                   \
+    return dir > 0 ? launch_fft_axis<LGV, +1>(Z, nlines, inner, tw, st)                       \
+                   : launch_fft_axis<LGV, -1>(Z, nlines, inner, tw, st);
+  switch (log2_exact(L)) {
+    DSKI_FA(3)
+    DSKI_FA(4)
+    DSKI_FA(5)
+    DSKI_FA(6)
+    DSKI_FA(7)
+    DSKI_FA(8)
+    DSKI_FA(9)
+    DSKI_FA(10)
+    DSKI_FA(11)
+    default:
+      set_error("FFT length %d not supported", L);
+      return DSKI_ENOTSUP;
+  }
+#undef DSKI_FA
+}
+
+static dski_status fft_last(double2* Z, int L, long long nlines, long long nouter, const double2* tw,
+                            const double* spec, hipStream_t st) {
+  switch (log2_exact(L)) {
+    case 3: return launch_fft_last<3>(Z, nlines, nouter, tw, spec, st);
+    case 4: return launch_fft_last<4>(Z, nlines, nouter, tw, spec, st);
+    case 5: return launch_fft_last<5>(Z, nlines, nouter, tw, spec, st);
+    case 6: return launch_fft_last<6>(Z, nlines, nouter, tw, spec, st);
+    case 7: return launch_fft_last<7>(Z, nlines, nouter, tw, spec, st);
+    case 8: return launch_fft_last<8>(Z, nlines, nouter, tw, spec, st);
+    case 9: return launch_fft_last<9>(Z, nlines, nouter, tw, spec, st);
+    case 10: return launch_fft_last<10>(Z, nlines, nouter, tw, spec, st);
+    case 11: return launch_fft_last<11>(Z, nlines, nouter, tw, spec, st);
+    default:
+      set_error("FFT length %d not supported", L);
+      return DSKI_ENOTSUP;
+  }
+}
+
+static long long bttb_total(dski_plan p) {
+  long long tot = 1;
+  for (int a = 0; a < p->d; ++a) tot *= p->ax[a].L;
+  return tot;
+}
+
+// Spectrum of the spline kernel's K_UU (without s^2): lambda / prod L_p, in
+// the natural frequency order of the embedded array.  Independent of the
+// hyper-parameters (s enters as a factor at application).
+dski_status bttb_build_spectrum(dski_plan p, hipStream_t st) {
+  const long long tot = bttb_total(p);
+  double R2 = 0.0;
+  for (int a = 0; a < p->d; ++a) {
+    const double ext = (p->ax[a].m - 1) * p->ax[a].h;
+    R2 += ext * ext;
+  }
+  p->spline_R = 2.0 * std::sqrt(R2);
+  if (!p->bttb_spec) DSKI_HIP(hipMalloc(&p->bttb_spec, sizeof(double) * (size_t)tot));
+  DevBuf work;
+  DSKI_TRY(work.reserve(sizeof(double2) * (size_t)tot));
+  double2* Z = work.as<double2>();
+  BoxL b = box_of(p);
+  const unsigned nb = (unsigned)std::min<long long>(4096, (tot + 255) / 256);
+  k_bttb_gen<<<nb, 256, 0, st>>>(b, p->spline_R, tot, Z);
+  DSKI_HIP(hipGetLastError());
+  long long inner = 1;
+  for (int a = p->d - 1; a >= 0; --a) {
+    const int L = p->ax[a].L;
+    DSKI_TRY(fft_axis(Z, L, +1, tot / L, inner, reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
+    inner *= L;
+  }
+  // the last-axis kernel expects each spectrum row in natural frequency order
+  // too, so this is lambda in the layout both passes index
+  k_bttb_spec<<<nb, 256, 0, st>>>(Z, tot, 1.0 / (double)tot, p->bttb_spec);
+  DSKI_HIP(hipGetLastError());
+  DSKI_HIP(hipStreamSynchronize(st));
+  work.release();
+  return DSKI_OK;
+}
+
+// G <- s^2 K_spl G for R FP64 grid columns.
+static dski_status bttb_apply(dski_plan p, int R, double* G, hipStream_t st, double scale) {
+  const long long tot = bttb_total(p);
+  const int R2 = (R + 1) / 2;
+  DSKI_TRY(p->bttb_work.reserve(sizeof(double2) * (size_t)tot * R2));
+  double2* Z = p->bttb_work.as<double2>();
+  BoxL b = box_of(p);
+  const unsigned nb = (unsigned)std::min<long long>(2048, (tot + 255) / 256);
+  k_bttb_pack<<<dim3(nb, R2), 256, 0, st>>>(G, p->M, R, b, tot, Z);
+  DSKI_HIP(hipGetLastError());
+  const int d = p->d;
+  // strides of the embedded array (last axis fastest), all R2 arrays stacked
+  long long inner[DSKI_MAXD];
+  inner[d - 1] = 1;
+  for (int a = d - 2; a >= 0; --a) inner[a] = inner[a + 1] * p->ax[a + 1].L;
+  const long long lines_of = tot * R2;
+  for (int a = 0; a < d - 1; ++a)
+    DSKI_TRY(fft_axis(Z, p->ax[a].L, +1, lines_of / p->ax[a].L, inner[a],
+                      reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
+  const int Ll = p->ax[d - 1].L;
+  DSKI_TRY(fft_last(Z, Ll, lines_of / Ll, tot / Ll, reinterpret_cast<const double2*>(p->ax[d - 1].twiddle),
+                    p->bttb_spec, st));
+  for (int a = d - 2; a >= 0; --a)
+    DSKI_TRY(fft_axis(Z, p->ax[a].L, -1, lines_of / p->ax[a].L, inner[a],
+                      reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
+  k_bttb_unpack<<<dim3(nb, R2), 256, 0, st>>>(Z, p->M, R, b, tot, scale, G);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
 // G <- K_UU G for R columns; dwhich = p (0..d-1) uses d T_p / dlog ell_p on axis p.
 // Every transform computes in FP64 whatever the grid's storage type GT.
 template <typename GT>
 dski_status apply_kuu(dski_plan p, int R, GT* G, hipStream_t st, int dwhich) {
   if (R <= 0) return DSKI_OK;
+  if (p->kernel == kKernelSpline) {
+    if constexpr (std::is_same<GT, double>::value) {
+      // no length scale: a derivative along one is zero
+      return bttb_apply(p, R, G, st, dwhich >= 0 && dwhich < p->d ? 0.0 : p->s * p->s);
+    } else {
+      set_error("spline kernel: FP64 grids only");
+      return DSKI_ENOTSUP;
+    }
+  }
   for (int a = 0; a < p->d; ++a) DSKI_TRY(kuu_axis<GT>(p, R, G, st, dwhich, a, p->kuu_variant[a]));
   return DSKI_OK;
 }
@@ -1457,8 +1830,9 @@ dski_status dski_mvm_tiled_f64(dski_plan p, int R, const double* V, int ldv, dou
 dski_status dski_mvm_tiled_noalloc(dski_plan p, int R, const float* V, int ldv, float* Y, int ldy,
                                    dski_stream stream) {
   DSKI_TRY(check_mvm_args(p, R, V, ldv, Y, ldy));
-  if (p->kind != 0) {
-    set_error("dski_mvm_tiled_noalloc: D-SKIP plans are not supported (their product has no grid stage)");
+  if (p->kind != 0 || p->kernel != kKernelSE) {
+    set_error("dski_mvm_tiled_noalloc: D-SKIP plans and the spline kernel are not supported (they need more "
+              "workspace than the grid)");
     return DSKI_ENOTSUP;
   }
   if (R == 0 || p->n == 0) return DSKI_OK;

@@ -315,6 +315,8 @@ dski_status dski_plan_destroy(dski_plan p) {
   (void)hipFree(p->tile_lcs);
   (void)hipFree(p->tile_pts);
   (void)hipFree(p->tile_cl);
+  (void)hipFree(p->bttb_spec);
+  p->bttb_work.release();
   for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {
     (void)hipFree(p->ax[a].twiddle);
     (void)hipFree(p->ax[a].spec);
@@ -570,6 +572,20 @@ dski_status dski_permute_f64(dski_plan p, int dir, int R, const double* in, int 
     return DSKI_EINVAL;
   }
   return permute(p, dir, R, in, ldi, out, ldo, static_cast<hipStream_t>(stream));
+}
+
+dski_status dski_set_kernel(dski_plan p, int kernel, dski_stream stream) {
+  if (!p || (kernel != DSKI_KERNEL_SE && kernel != DSKI_KERNEL_SPLINE)) {
+    set_error("dski_set_kernel: kernel must be DSKI_KERNEL_SE (0) or DSKI_KERNEL_SPLINE (1)");
+    return DSKI_EINVAL;
+  }
+  if (p->kind != 0) {
+    set_error("dski_set_kernel: D-SKIP plans carry the SE product kernel only");
+    return DSKI_ENOTSUP;
+  }
+  if (kernel == DSKI_KERNEL_SPLINE) DSKI_TRY(bttb_build_spectrum(p, static_cast<hipStream_t>(stream)));
+  p->kernel = kernel == DSKI_KERNEL_SPLINE ? kKernelSpline : kKernelSE;
+  return DSKI_OK;
 }
 
 dski_status dski_plan_set_precision(dski_plan p, int bits) {

@@ -174,6 +174,160 @@ __global__ void k_pc_column(GeoP g, int j, const PivState* __restrict__ ps,
   dres[e] = dn;
 }
 
+// ---------------------------------------------------------------- spline kernel
+// The spline kernel is not separable, so its diagonal and rows come from the
+// kernel itself.  Diagonal entry of row (block, point): with the tensor weights
+// w_a = prod_p w_p[o_{a,p}] of the point's stencil, sum_{a,b} w_a w_b k(|u_a - u_b|)
+// depends only on the node offsets Delta = o_a - o_b, so it is
+//   s^2 sum_Delta prod_p ac_p[Delta_p] k(|Delta h|),  ac_p[D] = sum_o w_p[o] w_p[o - D]
+// ((2S-1)^d terms).  A row is K e_piv = S K_UU S^T e_piv: the pivot's stencil
+// written into a grid column, one K_UU product and one gather.
+__device__ __forceinline__ double spline_prof(double r, int d, double R) {
+  if (d & 1) return r * r * r - 1.5 * R * r * r + 0.5 * R * R * R;
+  const double rl = r > 0.0 ? r * r * log(r) : 0.0;
+  return rl - 0.5 * (1.0 + 2.0 * log(R)) * r * r + 0.5 * R * R;
+}
+
+struct GeoS {
+  int d, n, N;
+  int m[DSKI_MAXD], nc[DSKI_MAXD];
+  double invh[DSKI_MAXD], h[DSKI_MAXD];
+  double s2, R;
+};
+
+static GeoS geos_of(dski_plan p) {
+  GeoS g{};
+  g.d = p->d;
+  g.n = p->n;
+  g.N = p->N;
+  for (int a = 0; a < p->d; ++a) {
+    g.m[a] = p->ax[a].m;
+    g.nc[a] = p->ax[a].ncell;
+    g.invh[a] = 1.0 / p->ax[a].h;
+    g.h[a] = p->ax[a].h;
+  }
+  g.s2 = p->s * p->s;
+  g.R = p->spline_R;
+  return g;
+}
+
+template <int S>
+__global__ void k_pc_diag_spline(GeoS g, const double* __restrict__ toff, double* __restrict__ diag) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.N) return;
+  const int blk = e / g.n, k = e % g.n;
+  constexpr int NA = 2 * S - 1;
+  double ac[DSKI_MAXD][NA];
+  for (int a = 0; a < g.d; ++a) {
+    double w[S];
+    interp_weights_one<S>(toff[(size_t)a * g.n + k], g.invh[a], blk == a + 1, w);
+    for (int dd = 0; dd < NA; ++dd) {
+      const int D = dd - (S - 1);
+      double acc = 0.0;
+      for (int o = 0; o < S; ++o)
+        if (o - D >= 0 && o - D < S) acc += w[o] * w[o - D];
+      ac[a][dd] = acc;
+    }
+  }
+  int tot = 1;
+  for (int a = 0; a < g.d; ++a) tot *= NA;
+  double v = 0.0;
+  for (int f = 0; f < tot; ++f) {
+    int rem = f;
+    double prod = 1.0, r2 = 0.0;
+    for (int a = g.d - 1; a >= 0; --a) {
+      const int dd = rem % NA;
+      rem /= NA;
+      prod *= ac[a][dd];
+      const double x = (double)(dd - (S - 1)) * g.h[a];
+      r2 += x * x;
+    }
+    v += prod * spline_prof(sqrt(r2), g.d, g.R);
+  }
+  diag[e] = g.s2 * v;
+}
+
+__global__ void k_fill_zero_d(double* __restrict__ x, long long len) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
+// Pivot selection, the pivot's row of L, and its stencil written into the
+// (zeroed) grid column G: value weights, or derivative weights on the axis of
+// its block.
+template <int S>
+__global__ void k_pivot_select_spline(GeoS g, const double* __restrict__ pv, const int* __restrict__ pi, int nblk,
+                                      int j, double rel_tol, PivState* __restrict__ ps, int* __restrict__ piv_list,
+                                      const int* __restrict__ cell, const double* __restrict__ toff,
+                                      const double* __restrict__ L, double* __restrict__ lrow,
+                                      const int* __restrict__ forced, const double* __restrict__ dres,
+                                      double* __restrict__ G) {
+  const int e = pivot_select_block(pv, pi, nblk, j, rel_tol, ps, piv_list, forced, dres);
+  if (e < 0) return;
+  const int blk = e / g.n, k = e % g.n;
+  for (int l = threadIdx.x; l < j; l += blockDim.x) lrow[l] = L[(size_t)l * g.N + e];
+  int c[DSKI_MAXD];
+  int cl = cell[k];
+  for (int a = g.d - 1; a >= 0; --a) {
+    c[a] = cl % g.nc[a];
+    cl /= g.nc[a];
+  }
+  double w[DSKI_MAXD][S];
+  for (int a = 0; a < g.d; ++a)
+    interp_weights_one<S>(toff[(size_t)a * g.n + k], g.invh[a], blk == a + 1, w[a]);
+  int tot = 1;
+  for (int a = 0; a < g.d; ++a) tot *= S;
+  for (int f = threadIdx.x; f < tot; f += blockDim.x) {
+    int rem = f;
+    long long node = 0, stride = 1;
+    double wp = 1.0;
+    for (int a = g.d - 1; a >= 0; --a) {
+      const int o = rem % S;
+      rem /= S;
+      node += (long long)(c[a] + o) * stride;
+      stride *= g.m[a];
+      wp *= w[a][o];
+    }
+    G[node] = wp;
+  }
+}
+
+// Column j of L from the pivot's row (tile order) and the residual-diagonal update.
+__global__ void k_pc_column_row(int N, int j, const PivState* __restrict__ ps, const double* __restrict__ row,
+                                const double* __restrict__ lrow, double* __restrict__ L, double* __restrict__ dres) {
+  if (ps->stop) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  double acc = row[e];
+  for (int l = 0; l < j; ++l) acc -= L[(size_t)l * N + e] * lrow[l];
+  const double lj = acc / sqrt(ps->dpiv);
+  L[(size_t)j * N + e] = lj;
+  double dn = dres[e] - lj * lj;
+  if (e == ps->piv) dn = -INFINITY;
+  dres[e] = dn;
+}
+
+// One pivoted-Cholesky step of a spline-kernel plan (after the arg-max partials).
+static dski_status spline_pc_step(dski_plan p, int j, const double* pv, const int* pi, int nblk, double rel_tol,
+                                  PivState* ps, int* piv_list, double* L, double* lrow, double* dres,
+                                  const int* forced, double* G, double* row, const double* zeros, hipStream_t st) {
+  GeoS g = geos_of(p);
+  const int vb = (p->N + kBlock - 1) / kBlock;
+  k_fill_zero_d<<<(unsigned)std::min<long long>(1024, (p->M + kBlock - 1) / kBlock), kBlock, 0, st>>>(G, p->M);
+  if (p->S == kInterpQuintic)
+    k_pivot_select_spline<kInterpQuintic><<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, piv_list, p->cell,
+                                                                p->toff, L, lrow, forced, dres, G);
+  else
+    k_pivot_select_spline<kInterpCubic><<<1, kBlock, 0, st>>>(g, pv, pi, nblk, j, rel_tol, ps, piv_list, p->cell,
+                                                              p->toff, L, lrow, forced, dres, G);
+  DSKI_HIP(hipGetLastError());
+  DSKI_TRY(apply_kuu<double>(p, 1, G, st));
+  DSKI_TRY((gather<double, double>(p, 1, G, zeros, p->N, row, p->N, 0.0, 0.0, nullptr, st)));
+  k_pc_column_row<<<vb, kBlock, 0, st>>>(p->N, j, ps, row, lrow, L, dres);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
 // Gram partials of G = D^{-1/2} L: pairs (i <= j) over a chunk of rows.
 __global__ void k_gram_partial(const double* __restrict__ L, int N, int n, int k, int rows,
                                double isf, double isg, double* __restrict__ partial) {
@@ -384,6 +538,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
   size_t bytes = sizeof(double) * ((size_t)N + nblk + msum + k + 8) + sizeof(int) * (nblk + 8) +
                  sizeof(PivState) + 256;
   char* scratch = nullptr;
+  double* spl_buf = nullptr;  // spline kernel: grid column, zeros and the pivot's row
   DSKI_HIP(hipMalloc(&scratch, bytes));
   double* dres = reinterpret_cast<double*>(scratch);
   double* pv = dres + N;
@@ -397,6 +552,20 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     if (p->kind == 1) {
       rc = dskip_diag(p, dres, st);
       if (rc < 0) break;
+    } else if (p->kernel == kKernelSpline) {
+      GeoS gs = geos_of(p);
+      if (p->S == kInterpQuintic)
+        k_pc_diag_spline<kInterpQuintic><<<vb, kBlock, 0, st>>>(gs, p->toff, dres);
+      else
+        k_pc_diag_spline<kInterpCubic><<<vb, kBlock, 0, st>>>(gs, p->toff, dres);
+      if (hipMalloc(&spl_buf, sizeof(double) * ((size_t)p->M + 2 * (size_t)N)) != hipSuccess) {
+        spl_buf = nullptr;
+        set_error("pivoted Cholesky: allocation failed");
+        rc = DSKI_ENOMEM;
+        break;
+      }
+      k_fill_zero_d<<<(unsigned)std::min<long long>(1024, (2 * (long long)N + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+          spl_buf + p->M, 2 * (long long)N);
     } else {
       if (p->S == kInterpQuintic)
         k_pc_diag<kInterpQuintic><<<vb, kBlock, 0, st>>>(g, p->cell, p->toff, dres);
@@ -408,6 +577,13 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
       k_argmax_partial<<<nblk, kBlock, 0, st>>>(dres, N, pv, pi);
       if (p->kind == 1) {
         rc = dskip_pc_step(p, j, pv, pi, nblk, rel_tol, ps, pc->piv_tile, pc->L, lrow, dres, forced, st);
+        if (rc < 0) break;
+        continue;
+      }
+      if (p->kernel == kKernelSpline) {
+        // grid column, the pivot's row, and zeros for the gather's noise input
+        rc = spline_pc_step(p, j, pv, pi, nblk, rel_tol, ps, pc->piv_tile, pc->L, lrow, dres, forced, spl_buf,
+                            spl_buf + p->M + N, spl_buf + p->M, st);
         if (rc < 0) break;
         continue;
       }
@@ -524,6 +700,7 @@ static dski_status build_impl(dski_plan p, int k, dski_precond pc, int* rank_hos
     if (r < k) rc = DSKI_RANK_TRUNCATED;
   } while (0);
   (void)hipFree(scratch);
+  if (spl_buf) (void)hipFree(spl_buf);
   return rc;
 }
 

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libdski.so")
 
 OK, NOT_CONVERGED, RANK_TRUNCATED = 0, 1, 2
 INTERP = {"cubic": 0, "quintic": 1}   # DSKI_INTERP_CUBIC, DSKI_INTERP_QUINTIC
+KERNEL = {"se": 0, "spline": 1}       # DSKI_KERNEL_SE, DSKI_KERNEL_SPLINE
 _STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "RANK_TRUNCATED", -1: "EINVAL", -2: "ENOMEM",
            -3: "EHIP", -4: "EBREAKDOWN", -5: "ENOTSUP"}
 
@@ -74,6 +75,7 @@ _SIGS = {
     "dski_rademacher": (C.c_int, [C.c_uint64, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]),
     "dski_lanczos_quad_log": (C.c_double, [dp, dp, C.c_int, ip]),
     "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
+    "dski_set_kernel": (C.c_int, [vp, C.c_int, vp]),
     "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
     "dski_autotune": (C.c_int, [vp, C.c_int, dp, vp]),
     "dski_autotune_cached": (C.c_int, [vp, C.c_int, C.c_char_p, ip, dp, vp]),
@@ -160,12 +162,15 @@ class Plan:
     """A D-SKI operator on fixed points and grid (owns a dski_plan)."""
 
     def __init__(self, X: torch.Tensor, grid_m: Sequence[int], lo=None, hi=None, stream=None,
-                 interp: str = "cubic"):
+                 interp: str = "cubic", kernel: str = "se"):
         """interp: "cubic" (Keys, 4 nodes per axis) or "quintic" (Meijering,
-        6 nodes per axis)."""
+        6 nodes per axis); kernel: "se" (squared exponential) or "spline"
+        (thin-plate spline, multi-level Toeplitz K_UU)."""
         L = lib()
         if interp not in INTERP:
             raise ValueError(f"interp must be one of {sorted(INTERP)}")
+        if kernel not in KERNEL:
+            raise ValueError(f"kernel must be one of {sorted(KERNEL)}")
         if not X.is_cuda or X.dtype != torch.float64 or X.dim() != 2:
             raise TypeError("X must be a CUDA float64 tensor of shape (n, d)")
         X = X.contiguous()
@@ -178,6 +183,10 @@ class Plan:
         _check(L.dski_plan_create(C.byref(h), n, d, _dptr(X), m, lo_a, hi_a, INTERP[interp], _stream(stream)),
                "dski_plan_create")
         self.interp = interp
+        self._h = h
+        if kernel != "se":
+            _check(L.dski_set_kernel(h, KERNEL[kernel], _stream(stream)), "dski_set_kernel")
+        self.kernel = kernel
         self._h = h
         self._info()
 
