@@ -275,7 +275,7 @@ def active_block(D=20, n=20000, reps=10):
             "project_ms": round(p_ms, 3), "eigenvalue_ratio_3_1": float(lam[2] / lam[0])}
 
 
-def grid_block(W, R, stream, interp="cubic", reps=20, solve=True, max_iter=20000):
+def grid_block(W, R, stream, interp="cubic", reps=20, solve=True, max_iter=20000, kernel="se"):
     """One D-SKI workload on its own (tuner, block MVM of R columns with its
     per-stage times and the roofline of the dominant stage), then, with solve,
     the rank-k pivoted Cholesky and mll_and_grad with 16 probes to the
@@ -285,7 +285,8 @@ def grid_block(W, R, stream, interp="cubic", reps=20, solve=True, max_iter=20000
     import torch
     from paper_1810_12283_amd import dski
     t0 = time.perf_counter()
-    plan = dski.Plan(torch.tensor(W.X, dtype=torch.float64, device="cuda"), W.grid_m, W.lo, W.hi, interp=interp)
+    plan = dski.Plan(torch.tensor(W.X, dtype=torch.float64, device="cuda"), W.grid_m, W.lo, W.hi, interp=interp,
+                     kernel=kernel)
     plan.set_hypers(*W.hypers())
     tune = plan.autotune(R)
     torch.cuda.synchronize()
@@ -303,7 +304,8 @@ def grid_block(W, R, stream, interp="cubic", reps=20, solve=True, max_iter=20000
     sb = stage_bytes(N, M, n, d, R)
     dom = max(stage, key=stage.get)
     ach = sb[dom] / (stage[dom] * 1e-3) / 1e9
-    out = {"workload": f"{W.name} n={n} d={d} grid={'x'.join(map(str, W.grid_m))} R={R} interp={interp}",
+    out = {"workload": f"{W.name} n={n} d={d} grid={'x'.join(map(str, W.grid_m))} R={R} interp={interp} "
+                       f"kernel={kernel}",
            "setup_and_tune_s": round(t_setup, 3), "mvm_ms": round(med, 4), "mvm_ms_p10_p90": [round(p10, 4),
                                                                                             round(p90, 4)],
            "mvm_algorithmic_bytes": Bm, "mvm_gbs": round(Bm / (med * 1e-3) / 1e9, 1),
@@ -327,6 +329,24 @@ def grid_block(W, R, stream, interp="cubic", reps=20, solve=True, max_iter=20000
         pc.close()
     plan.close()
     return out
+
+
+def bo_block(iters=10, n0=60, seed=11):
+    """Alg. 1 (Sec. 4.4) on the paper's setting: 5-D Ackley embedded in
+    [-10, 15]^50, d = 2 random directions inside the 5-D estimated active
+    subspace, D-SKI on a 30 x 30 reduced grid, EI; n0 initial samples (the
+    reduced system stays within the full-rank pivoted Cholesky, N <= 256)."""
+    import numpy as np
+    import workloads
+    from paper_1810_12283_amd import bo
+    obj, lo, hi, _ = workloads.embedded_objective("ackley", 50, 5, seed)
+    X0 = lo + (hi - lo) * np.random.default_rng(seed + 1).random((n0, 50))
+    f0 = min(obj(x)[0] for x in X0)
+    r = bo.run_alg1(obj, X0, lo, hi, iters=iters, d=2, k_active=5, grid=30, seed=seed + 2)
+    return {"workload": f"ackley 5-D in 50-D, n0={n0}, {iters} iterations, d=2 of a 5-D active subspace",
+            "s_per_iter": round(float(np.mean([s.seconds for s in r.steps])), 4),
+            "initial_best": round(float(f0), 4), "best": round(r.best_f, 4),
+            "trace": [round(s.f, 4) for s in r.steps]}
 
 
 def mvm_bytes(N, M, n, d, R):
@@ -682,10 +702,12 @@ def main(argv=None):
     }
     line["torus"] = grid_block(workloads.torus(), R, stream)
     line["terrain_quintic"] = grid_block(W, R, stream, interp="quintic")
+    line["torus_spline"] = grid_block(workloads.torus(), R, stream, kernel="spline")
     line["dskip"] = dskip_block(R, stream)
     line["surrogate"] = surrogate_block(W, y, W.rank, stream)
     line["predict"] = predict_block(W, stream)
     line["active_subspace"] = active_block()
+    line["bo_alg1"] = bo_block()
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, R, recs[-1]["X_host"], recs[-1]["B_host"])
         # the headline solve's residual as the oracle's FP64 operator sees it

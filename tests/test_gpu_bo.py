@@ -141,3 +141,47 @@ def test_one_step_of_alg1_matches_oracle():
         "best", idx, int(np.argmax(ei_ref)))
     assert st == 0 and em < 1e-7 and ev < 1e-7 and ee < 1e-6
     assert ei_ref[idx] >= ei_ref.max() * (1 - 1e-6)
+
+
+def test_alg1_loop_converges_and_is_deterministic():
+    """Alg. 1 end to end: a quadratic of two variables embedded in 10
+    dimensions, 20 initial samples, six iterations (active subspace of the
+    gradients, reduced D-SKI fit with refitted hyper-parameters, EI maximised
+    over the reduced search space, sample, update).  The gradients span the
+    embedding exactly, so P spans it from the first iteration; every new
+    sample lies in the domain box; the best value falls well below the initial
+    design's; a second run with the same seeds takes the same steps."""
+    need_gpu()
+    import workloads
+    from paper_1810_12283_amd import bo
+    obj, lo, hi, Q = workloads.embedded_objective("quadratic", 10, 2, 3)
+    X0 = lo + (hi - lo) * np.random.default_rng(4).random((20, 10))
+    f0 = min(obj(x)[0] for x in X0)
+    say("alg1 loop, initial best", f0)
+    r1 = bo.run_alg1(obj, X0, lo, hi, iters=6, d=2, grid=30, seed=5, n_cand=2048, n_local=256)
+    P = r1.steps[0].P
+    say("  steps", [round(s.f, 5) for s in r1.steps], "best", r1.best_f,
+        "subspace err", np.abs(P @ P.T - Q @ Q.T).max(), "s/iter", [round(s.seconds, 3) for s in r1.steps])
+    assert np.abs(P @ P.T - Q @ Q.T).max() < 1e-8
+    for s in r1.steps:
+        assert np.all(s.x >= lo - 1e-12) and np.all(s.x <= hi + 1e-12)
+    assert r1.best_f < 0.2 * f0 and r1.best_f < 0.05
+    r2 = bo.run_alg1(obj, X0, lo, hi, iters=6, d=2, grid=30, seed=5, n_cand=2048, n_local=256)
+    assert np.array_equal(r1.X, r2.X)
+
+
+def test_alg1_random_directions_of_a_wider_active_subspace():
+    """The paper's setting: d = 2 directions drawn at random inside a larger
+    estimated active subspace (here 4 of the 4 effective variables of an
+    embedded Rastrigin in 12 dimensions); P has orthonormal columns inside it."""
+    need_gpu()
+    import workloads
+    from paper_1810_12283_amd import bo
+    obj, lo, hi, Q = workloads.embedded_objective("rastrigin", 12, 4, 6)
+    X0 = lo + (hi - lo) * np.random.default_rng(7).random((40, 12))
+    r = bo.run_alg1(obj, X0, lo, hi, iters=2, d=2, k_active=4, grid=30, seed=8, n_cand=1024, n_local=128)
+    for s in r.steps:
+        P = s.P
+        assert np.allclose(P.T @ P, np.eye(2), atol=1e-10)
+        assert np.abs(P - Q @ (Q.T @ P)).max() < 1e-8   # inside span(Q)
+    say("  rastrigin steps", [round(s.f, 3) for s in r.steps], "initial best", min(obj(x)[0] for x in X0))

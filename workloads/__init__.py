@@ -38,6 +38,7 @@ __all__ = [
     "ridge8d",
     "by_name",
     "block_vector",
+    "embedded_objective",
 ]
 
 
@@ -227,3 +228,50 @@ def by_name(name: str, **kw) -> Workload:
     return {"small2d": small2d, "terrain": terrain, "torus": torus,
             "ridge8d": ridge8d}[name](**kw)
 
+
+
+def embedded_objective(kind: str, D: int, d_eff: int, seed: int):
+    """A test function of d_eff variables embedded in D dimensions, as the
+    Bayesian-optimisation experiment of Sec. 4.4 does (5-D Ackley and
+    Rastrigin in [-10, 15]^50 and [-4, 5]^50): f(x) = g(Q^T x) with Q a seeded
+    D x d_eff matrix with orthonormal columns.  Returns (objective, lo, hi,
+    Q) where objective(x) -> (f, grad f) and [lo, hi] is the domain box.
+    kind: "quadratic" (|z - c|^2, c seeded in [-0.3, 0.3]^d_eff, box [-1, 1]^D),
+    "ackley" (box [-10, 15]^D) or "rastrigin" (box [-4, 5]^D)."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((D, d_eff)))
+    if kind == "quadratic":
+        c = rng.uniform(-0.3, 0.3, d_eff)
+        lo, hi = -np.ones(D), np.ones(D)
+
+        def g(z):
+            r = z - c
+            return float(r @ r), 2.0 * r
+    elif kind == "ackley":
+        lo, hi = np.full(D, -10.0), np.full(D, 15.0)
+
+        def g(z):
+            k = z.size
+            a = math.sqrt(float(z @ z) / k)
+            b = float(np.cos(2 * math.pi * z).sum()) / k
+            e1, e2 = math.exp(-0.2 * a), math.exp(b)
+            val = -20.0 * e1 - e2 + 20.0 + math.e
+            ga = (z / (k * a)) if a > 0 else np.zeros_like(z)
+            grad = 20.0 * 0.2 * e1 * ga + e2 * (2 * math.pi / k) * np.sin(2 * math.pi * z)
+            return val, grad
+    elif kind == "rastrigin":
+        lo, hi = np.full(D, -4.0), np.full(D, 5.0)
+
+        def g(z):
+            val = 10.0 * z.size + float((z * z - 10.0 * np.cos(2 * math.pi * z)).sum())
+            grad = 2.0 * z + 20.0 * math.pi * np.sin(2 * math.pi * z)
+            return val, grad
+    else:
+        raise ValueError(kind)
+
+    def objective(x):
+        z = Q.T @ np.asarray(x, dtype=np.float64)
+        v, gz = g(z)
+        return v, Q @ gz
+
+    return objective, lo, hi, Q
