@@ -415,6 +415,18 @@ dski_status mll_and_grad_f64(dski_plan plan, dski_precond pc, int k, const doubl
                              double* mll_host, double* grad_host, double* logdet_host,
                              int* iters_host, dski_stream stream);
 
+/* mll_and_grad with a warm start for the data solve (hyper-parameter searches
+ * move theta a little between evaluations, so the last alpha is a good start):
+ * x0 (N doubles, device, user order, or NULL for x_0 = 0) starts alpha; the
+ * solve of K~ dx = y - K~ x0 stops when ||y - K~ alpha|| <= tol ||y||, alpha =
+ * x0 + dx.  The probe columns still start at zero (their Lanczos runs define
+ * the quadrature).  alpha_out (N doubles, device, user order, or NULL)
+ * receives alpha in FP64.  Otherwise as mll_and_grad (FP32 vectors). */
+dski_status mll_and_grad_warm(dski_plan plan, dski_precond pc, int k, const float* y, int num_probes,
+                              uint64_t seed, double tol, int max_iter, const double* x0, double* alpha_out,
+                              double* mll_host, double* grad_host, double* logdet_host, int* iters_host,
+                              dski_stream stream);
+
 /* out[c*ld + i] = +-1 (FP32): Rademacher column col0+c of the counter-based
  * SplitMix64 stream `seed` (Steele et al. 2014): entry i of column c is -1
  * iff bit 63 of mix64(seed + (c*N + i + 1) * 0x9E3779B97F4A7C15) is set. */
@@ -427,6 +439,14 @@ dski_status dski_rademacher(uint64_t seed, int col0, int ncols, int N, float* ou
  * (Gauss quadrature of Sec. 2's Lanczos connection).  *ok = 0 if a Ritz value
  * is not positive or the eigen-iteration fails. */
 double dski_lanczos_quad_log(const double* alpha_host, const double* beta_host, int J, int* ok);
+
+/* Host utility: the same value from the leading j x j blocks of T (the Gauss
+ * rules of j Lanczos steps): j = min(J, 256), then doubled until two successive
+ * values agree to rtol * max(1, |value|) or j = J; *used (may be NULL) receives
+ * the final j.  slq_logdet and mll_and_grad evaluate their quadratures this way
+ * with rtol = 1e-10, at O(j^2) instead of O(J^2) host work per probe. */
+double dski_lanczos_quad_log_adaptive(const double* alpha_host, const double* beta_host, int J, double rtol,
+                                      int* ok, int* used);
 
 /* ---------------------------------------------------------------------------------
  * Learned log-determinant surrogate (a network of this project, not of the paper):

@@ -1,6 +1,7 @@
 // Small dense FP64 numerics that run on the host: the k x k symmetric
 // eigen-decomposition of the preconditioner's Gram matrix and the Gauss
 // quadrature e_1^T log(T) e_1 of a Lanczos tridiagonal T (Sec. 2).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -122,6 +123,30 @@ double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok) {
   return gauss_quad_log_tri(a.data(), b.data(), J, ok);
 }
 
+// The same value from the leading j x j blocks of T (the Gauss rules of j
+// Lanczos steps, which converge to the J-step rule as j grows): j starts at
+// min(J, 256) and doubles until two successive values agree to
+// rtol * max(1, |value|), or j = J.  The cost is O(j^2) in the j reached
+// instead of O(J^2).  *used receives the j of the returned value.
+double gauss_quad_log_adaptive(const double* alpha, const double* beta, int J, double rtol, int* ok, int* used) {
+  int j = std::min(J, 256);
+  double g = gauss_quad_log(alpha, beta, j, ok);
+  if (used) *used = j;
+  while (*ok && j < J) {
+    const int j2 = j >= J / 2 ? J : 2 * j;
+    int ok2 = 0;
+    const double g2 = gauss_quad_log(alpha, beta, j2, &ok2);
+    *ok = ok2;
+    if (used) *used = j2;
+    if (!ok2) return 0.0;
+    const bool done = std::fabs(g2 - g) <= rtol * std::fmax(1.0, std::fabs(g2));
+    g = g2;
+    j = j2;
+    if (done) break;
+  }
+  return g;
+}
+
 // The same quadrature for a tridiagonal given directly: diagonal a[0..J),
 // couplings b[0..J-1).
 double gauss_quad_log_tri(const double* diag, const double* off, int J, int* ok) {
@@ -169,5 +194,14 @@ extern "C" double dski_lanczos_quad_log(const double* alpha_host, const double* 
   int tmp = 0;
   double v = dski::gauss_quad_log(alpha_host, beta_host, J, &tmp);
   if (ok) *ok = tmp;
+  return v;
+}
+
+extern "C" double dski_lanczos_quad_log_adaptive(const double* alpha_host, const double* beta_host, int J,
+                                                 double rtol, int* ok, int* used) {
+  int tmp = 0, u = 0;
+  double v = dski::gauss_quad_log_adaptive(alpha_host, beta_host, J, rtol, &tmp, &u);
+  if (ok) *ok = tmp;
+  if (used) *used = u;
   return v;
 }

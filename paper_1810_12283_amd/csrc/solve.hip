@@ -74,6 +74,30 @@ __global__ void k_copy_cols_d(const double* __restrict__ src, double* __restrict
     d[e] = s[e];
 }
 
+static const std::vector<int>& p00_pair() {
+  static const std::vector<int> v = {0, 0};
+  return v;
+}
+
+template <typename T>
+__global__ void k_swap_cols(T* __restrict__ a, T* __restrict__ b, int N) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x) {
+    const T v = a[e];
+    a[e] = b[e];
+    b[e] = v;
+  }
+}
+
+template <typename T>
+static dski_status swap_first_column(T* a, T* b, int N, hipStream_t st) {
+  k_swap_cols<T><<<std::max(1, std::min(1024, (N + kBlock - 1) / kBlock)), kBlock, 0, st>>>(a, b, N);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+// convergence threshold of the quadrature over growing Lanczos blocks
+constexpr double kQuadRtol = 1e-10;
+
 struct ProbeRun {
   std::vector<double> quad, weight;
   double logdet = 0, stderr_ = 0;
@@ -86,13 +110,16 @@ static void slq_combine(const std::vector<double>& ab, int max_iter, int R, int 
   out.weight.assign(t, 0.0);
   std::vector<double> vals(t);
   std::vector<int> okv(t, 1);
-  // one Gauss quadrature per probe (O(J^2) each): probes spread over host threads
+  // one Gauss quadrature per probe, on leading blocks of the CG tridiagonal until
+  // the rule has converged (O(j^2) in the block size j reached): probes spread
+  // over host threads
   auto work = [&](int i) {
     const int c = col0 + i;
     const int J = std::min(res.iters[c], max_iter);
-    int ok = 0;
-    const double q = gauss_quad_log(ab.data() + (size_t)c * max_iter,
-                                    ab.data() + (size_t)R * max_iter + (size_t)c * max_iter, J, &ok);
+    int ok = 0, used = 0;
+    const double q = gauss_quad_log_adaptive(ab.data() + (size_t)c * max_iter,
+                                             ab.data() + (size_t)R * max_iter + (size_t)c * max_iter, J,
+                                             kQuadRtol, &ok, &used);
     okv[i] = ok;
     out.quad[i] = q;
     out.weight[i] = res.rz0[c];
@@ -370,10 +397,29 @@ static dski_status slq_impl(dski_plan p, dski_precond pc, int t, int lanczos_ste
   return rc;
 }
 
+// Warm start of the data column: r0 = y - K~ x0 (FP64 in, storage T out).
+template <typename T>
+__global__ void k_warm_residual(const T* __restrict__ y, const double* __restrict__ kx0, int N, T* __restrict__ r0) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x)
+    r0[e] = (T)((double)y[e] - kx0[e]);
+}
+
+// alpha = x0 + dx (FP64) into the storage-type data column and an FP64 copy.
+template <typename T>
+__global__ void k_warm_alpha(const double* __restrict__ x0, const double* __restrict__ dx, int N, T* __restrict__ a,
+                             double* __restrict__ a64) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N; e += gridDim.x * blockDim.x) {
+    const double v = x0[e] + dx[e];
+    a[e] = (T)v;
+    a64[e] = v;
+  }
+}
+
 template <typename T>
 static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uint64_t seed, double tol,
                             int max_iter, double* mll_host, double* grad_host, double* logdet_host,
-                            int* iters_host, hipStream_t st) {
+                            int* iters_host, hipStream_t st, const double* x0 = nullptr,
+                            double* alpha_out = nullptr) {
   int N = p->N, n = p->n, d = p->d;
   long long M = p->M;
   dski_status rc = DSKI_OK;
@@ -403,9 +449,66 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
     PcgResult res;
     std::vector<int> verify(R, 0);
     verify[0] = 1;  // the data solve alpha; probe columns keep a single Krylov run for SLQ
-    rc = pcg_tiled<T>(p, pc, R, B, N, X, N, tols.data(), max_iter, 0, ab, res, st, nullptr, verify.data());
+    // warm start of the data column (x0 in user order): solve K~ dx = y - K~ x0 to
+    // the tolerance of ||y - K~ alpha|| <= tol ||y||, then alpha = x0 + dx
+    DevBuf warm;
+    double* x0t = nullptr;
+    double* X64 = nullptr;
+    T* ysave = nullptr;
+    const int wb = std::max(1, std::min(1024, (N + kBlock - 1) / kBlock));
+    if (x0 || alpha_out) {
+      rc = warm.reserve(sizeof(double) * ((size_t)N * 2 + nr) + sizeof(T) * (size_t)N + 256);
+      if (rc < 0) break;
+      x0t = warm.as<double>();
+      double* kx0 = x0t + N;
+      X64 = kx0 + N;
+      ysave = reinterpret_cast<T*>(X64 + nr);
+      if (x0) {
+        rc = permute(p, +1, 1, x0, N, x0t, N, st);
+        if (rc < 0) break;
+        rc = mvm_tiled<double>(p, 1, x0t, N, kx0, N, nullptr, st);
+        if (rc < 0) break;
+        std::vector<double> yy, rr;
+        rc = pair_dots<T>(B, N, B, N, p00_pair(), 0, N, yy, dotbuf, st);
+        if (rc < 0) break;
+        k_warm_residual<T><<<wb, kBlock, 0, st>>>(B, kx0, N, ysave);
+        if (hipGetLastError() != hipSuccess) {
+          set_error("mll_and_grad: warm-start launch failed");
+          rc = DSKI_EHIP;
+          break;
+        }
+        // B[:, 0] <- r0; y waits in ysave until the solve is done
+        rc = swap_first_column<T>(B, ysave, N, st);
+        if (rc < 0) break;
+        rc = pair_dots<T>(B, N, B, N, p00_pair(), 0, N, rr, dotbuf, st);
+        if (rc < 0) break;
+        if (rr[0] > 0.0) tols[0] = tol * std::sqrt(yy[0] / rr[0]);
+      } else if (hipMemsetAsync(x0t, 0, sizeof(double) * N, st) != hipSuccess) {
+        set_error("mll_and_grad: clearing the start failed");
+        rc = DSKI_EHIP;
+        break;
+      }
+    }
+    rc = pcg_tiled<T>(p, pc, R, B, N, X, N, tols.data(), max_iter, 0, ab, res, st, X64, verify.data());
     if (rc < 0) break;
     dski_status pcg_rc = rc;
+    if (x0 || alpha_out) {
+      // alpha = x0 + dx in the data column (storage type) and in FP64; y back in B[:, 0]
+      k_warm_alpha<T><<<wb, kBlock, 0, st>>>(x0t, X64, N, X, X64);
+      if (hipGetLastError() != hipSuccess) {
+        set_error("mll_and_grad: warm-start launch failed");
+        rc = DSKI_EHIP;
+        break;
+      }
+      if (x0) {
+        rc = swap_first_column<T>(B, ysave, N, st);
+        if (rc < 0) break;
+      }
+      if (alpha_out) {
+        rc = permute(p, -1, 1, X64, N, alpha_out, N, st);
+        if (rc < 0) break;
+      }
+    }
     // v_i = M^{-1} z_i
     rc = precond_apply_tiled<T>(pc, t, B + N, N, Vv, N, nullptr, nullptr, st);
     if (rc < 0) break;
@@ -520,7 +623,8 @@ static dski_status mll_impl(dski_plan p, dski_precond pc, const T* y, int t, uin
 template <typename T>
 static dski_status mll_user(dski_plan p, dski_precond pc_in, int k, const T* y, int t, uint64_t seed,
                             double tol, int max_iter, double* mll_host, double* grad_host,
-                            double* logdet_host, int* iters_host, hipStream_t st) {
+                            double* logdet_host, int* iters_host, hipStream_t st, const double* x0 = nullptr,
+                            double* alpha_out = nullptr) {
   if (!p || !y || t < 0 || tol <= 0 || max_iter <= 0 || (!pc_in && k < 0) ||
       (pc_in && pc_in->plan != p) || p->N == 0) {
     set_error("mll_and_grad: bad arguments");
@@ -538,7 +642,7 @@ static dski_status mll_user(dski_plan p, dski_precond pc_in, int k, const T* y, 
     if (rc < 0) return rc;
   }
   dski_status rc = mll_impl<T>(p, pc, y, t, seed, tol, max_iter, mll_host, grad_host, logdet_host,
-                               iters_host, st);
+                               iters_host, st, x0, alpha_out);
   if (!pc_in) dski_precond_destroy(pc);
   return rc;
 }
@@ -564,6 +668,13 @@ dski_status mll_and_grad(dski_plan p, dski_precond pc, int k, const float* y, in
                          double* logdet_host, int* iters_host, dski_stream stream) {
   return mll_user<float>(p, pc, k, y, t, seed, tol, max_iter, mll_host, grad_host, logdet_host,
                          iters_host, static_cast<hipStream_t>(stream));
+}
+
+dski_status mll_and_grad_warm(dski_plan p, dski_precond pc, int k, const float* y, int t, uint64_t seed,
+                              double tol, int max_iter, const double* x0, double* alpha_out, double* mll_host,
+                              double* grad_host, double* logdet_host, int* iters_host, dski_stream stream) {
+  return mll_user<float>(p, pc, k, y, t, seed, tol, max_iter, mll_host, grad_host, logdet_host, iters_host,
+                         static_cast<hipStream_t>(stream), x0, alpha_out);
 }
 
 dski_status mll_and_grad_f64(dski_plan p, dski_precond pc, int k, const double* y, int t, uint64_t seed,

@@ -74,6 +74,7 @@ _SIGS = {
                                dp, dp, dp, ip, vp]),
     "dski_rademacher": (C.c_int, [C.c_uint64, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]),
     "dski_lanczos_quad_log": (C.c_double, [dp, dp, C.c_int, ip]),
+    "dski_lanczos_quad_log_adaptive": (C.c_double, [dp, dp, C.c_int, C.c_double, ip, ip]),
     "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
     "dski_set_kernel": (C.c_int, [vp, C.c_int, vp]),
     "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -98,6 +99,8 @@ _SIGS = {
     "pcg_solve_f64": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, vp, C.c_int, dp, C.c_int, ip, dp, vp, vp]),
     "mll_and_grad_f64": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, C.c_uint64, C.c_double, C.c_int,
                                    dp, dp, dp, ip, vp]),
+    "mll_and_grad_warm": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, C.c_uint64, C.c_double, C.c_int, vp, vp,
+                                    dp, dp, dp, ip, vp]),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -400,17 +403,36 @@ class Plan:
 
     def mll_and_grad(self, y: torch.Tensor, precond: Optional["Precond"] = None, k: int = 50,
                      num_probes: int = 16, seed: int = 0x181012283, tol: float = 1e-4,
-                     max_iter: int = 10000, stream=None):
+                     max_iter: int = 10000, stream=None, x0: Optional[torch.Tensor] = None,
+                     want_alpha: bool = False):
+        """x0 (CUDA FP64, N values, user order) warm-starts the data solve and
+        want_alpha returns alpha (as "alpha") for the next warm start; both
+        need FP32 y (mll_and_grad_warm)."""
         y = _block(y, self.N, "y")
         mll, ld = C.c_double(), C.c_double()
         grad = (C.c_double * (self.d + 3))()
         iters = (C.c_int * (1 + num_probes))()
-        st = _check(_fn("mll_and_grad", y)(self._h, precond.handle if precond else None, int(k), _dptr(y),
-                                       int(num_probes), C.c_uint64(seed), float(tol), int(max_iter),
-                                       C.byref(mll), grad, C.byref(ld), iters, _stream(stream)),
-                    "mll_and_grad")
-        return dict(mll=mll.value, grad=np.array(list(grad)), logdet=ld.value, iters=list(iters),
-                    status=st)
+        alpha = None
+        if x0 is not None or want_alpha:
+            if y.dtype != torch.float32:
+                raise TypeError("warm starts take an FP32 y")
+            if x0 is not None and (not x0.is_cuda or x0.dtype != torch.float64 or x0.numel() != self.N):
+                raise TypeError("x0 must be a CUDA float64 tensor with N entries")
+            alpha = torch.empty(self.N, dtype=torch.float64, device=y.device) if want_alpha else None
+            st = _check(lib().mll_and_grad_warm(self._h, precond.handle if precond else None, int(k), _dptr(y),
+                                                int(num_probes), C.c_uint64(seed), float(tol), int(max_iter),
+                                                _dptr(x0.contiguous()) if x0 is not None else None,
+                                                _dptr(alpha) if alpha is not None else None, C.byref(mll), grad,
+                                                C.byref(ld), iters, _stream(stream)), "mll_and_grad_warm")
+        else:
+            st = _check(_fn("mll_and_grad", y)(self._h, precond.handle if precond else None, int(k), _dptr(y),
+                                           int(num_probes), C.c_uint64(seed), float(tol), int(max_iter),
+                                           C.byref(mll), grad, C.byref(ld), iters, _stream(stream)),
+                        "mll_and_grad")
+        out = dict(mll=mll.value, grad=np.array(list(grad)), logdet=ld.value, iters=list(iters), status=st)
+        if alpha is not None:
+            out["alpha"] = alpha
+        return out
 
 
 class DskipPlan(Plan):
@@ -663,6 +685,18 @@ def lanczos_quad_log(alpha: Sequence[float], beta: Sequence[float]) -> float:
     if not ok.value:
         raise DSKIError(-4, "quadrature failed (non-positive Ritz value)")
     return v
+
+
+def lanczos_quad_log_adaptive(alpha: Sequence[float], beta: Sequence[float], rtol: float = 1e-10):
+    """(value, j used): the quadrature from growing leading blocks of T."""
+    J = len(alpha)
+    a = _arr([float(v) for v in alpha], C.c_double)
+    b = _arr([float(v) for v in beta] + [0.0], C.c_double)
+    ok, used = C.c_int(), C.c_int()
+    v = lib().dski_lanczos_quad_log_adaptive(a, b, J, float(rtol), C.byref(ok), C.byref(used))
+    if not ok.value:
+        raise DSKIError(-4, "quadrature failed (non-positive Ritz value)")
+    return v, used.value
 
 
 def version() -> str:

@@ -31,22 +31,40 @@ LOG2PI = math.log(2.0 * math.pi)
 
 
 def logdet_and_grad(plan: dski.Plan, theta: np.ndarray, k: int, num_probes: int, seed: int, tol: float,
-                    max_iter: int = 20000):
-    """SLQ log det K~ and its gradient (d + 3 log hyper-parameters) at theta."""
+                    max_iter: int = 20000, info: Optional[dict] = None):
+    """SLQ log det K~ and its gradient (d + 3 log hyper-parameters) at theta;
+    `info` (a dict) receives the PCG iterations per column and the status."""
     d = plan.d
     plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
     zero = torch.zeros((1, plan.N), dtype=torch.float32, device="cuda")
     res = plan.mll_and_grad(zero, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=max_iter)
+    if info is not None:
+        info["iters"] = res["iters"]
+        info["status"] = res["status"]
     # with y = 0: mll = -(log det + N log 2 pi) / 2, grad = -(d log det) / 2
     return res["logdet"], -2.0 * np.asarray(res["grad"])
 
 
+def _mll(plan: dski.Plan, y: torch.Tensor, k: int, num_probes: int, seed: int, tol: float, max_iter: int,
+         warm: Optional[dict]):
+    """mll_and_grad; with `warm` (a dict) the data solve starts from warm["alpha"]
+    when present, and warm["alpha"] receives the new alpha (FP32 y only)."""
+    if warm is None or y.dtype != torch.float32:
+        return plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=max_iter)
+    res = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=max_iter,
+                            x0=warm.get("alpha"), want_alpha=True)
+    warm["alpha"] = res["alpha"]
+    warm["iters"] = warm.get("iters", 0) + res["iters"][0]
+    return res
+
+
 def data_fit_and_grad(plan: dski.Plan, theta: np.ndarray, y: torch.Tensor, k: int, tol: float,
-                      max_iter: int = 20000):
-    """-y^T K~^{-1} y / 2 - N log(2 pi) / 2 and its gradient (one PCG column)."""
+                      max_iter: int = 20000, warm: Optional[dict] = None):
+    """-y^T K~^{-1} y / 2 - N log(2 pi) / 2 and its gradient (one PCG column),
+    warm-started as in _mll when `warm` is given."""
     d = plan.d
     plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
-    res = plan.mll_and_grad(y, None, k=k, num_probes=0, tol=tol, max_iter=max_iter)
+    res = _mll(plan, y, k, 0, 0, tol, max_iter, warm)
     return res["mll"], np.asarray(res["grad"])
 
 
@@ -97,8 +115,10 @@ def training_data(plan: dski.Plan, thetas: np.ndarray, k: int, num_probes: int, 
 
 
 def train(thetas: np.ndarray, logdets: np.ndarray, grads: np.ndarray, n: int, h: np.ndarray, steps: int = 2000,
-          lr: float = 2e-3, lam: float = 1.0, hidden: int = 128, seed: int = 0) -> Surrogate:
-    """Fit the network to log det / n and its gradient with full-batch Adam on the device."""
+          lr: float = 2e-3, lam: float = 1.0, hidden: int = 128, seed: int = 0,
+          lr_final: Optional[float] = None) -> Surrogate:
+    """Fit the network to log det / n and its gradient with full-batch Adam on
+    the device; the step size decays geometrically from lr to lr_final (if given)."""
     J = thetas.shape[1]
     const = np.concatenate([[math.log(n)], np.log(h)])
     Xf = np.concatenate([thetas, np.repeat(const[None, :], len(thetas), axis=0)], axis=1)
@@ -120,9 +140,10 @@ def train(thetas: np.ndarray, logdets: np.ndarray, grads: np.ndarray, n: int, h:
     td = torch.tensor(ts, dtype=torch.float32, device="cuda")
     gd = torch.tensor(gs, dtype=torch.float32, device="cuda")
     hist = []
+    decay = (lr_final / lr) ** (1.0 / max(1, steps - 1)) if lr_final else 1.0
     for s in range(steps):
         loss = net.backward(Xd, td, gd, lam)
-        net.step(lr=lr)
+        net.step(lr=lr * decay ** s)
         if s % 100 == 0 or s == steps - 1:
             hist.append((s, loss))
     return Surrogate(net, mu_x, sd_x, mu_t, sd_t, n, const, hist)
@@ -136,21 +157,24 @@ class FitResult:
     seconds: float
     fell_back: bool
     rechecks: list
+    data_iters: int = 0               # PCG iterations of the data column over all evaluations
 
 
 def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes: int, seed: int, tol: float,
         surrogate: Optional[Surrogate] = None, recheck: int = 10, fallback_tol: float = 1e-3,
-        max_evals: int = 60, gtol: float = 1e-5, bounds=None) -> FitResult:
+        max_evals: int = 60, gtol: float = 1e-5, bounds=None, warm: bool = True) -> FitResult:
     """Maximise the marginal likelihood over the log hyper-parameters with L-BFGS.
 
     With a surrogate: mll = data-fit part (exact) - log det (network) / 2, with
     SLQ re-checks every `recheck` evaluations and a fall-back to plain SLQ when
     the relative log det error exceeds `fallback_tol`.  `bounds` (a list of
     (lo, hi) per log hyper-parameter) keeps the search inside the region the
-    surrogate was trained on."""
+    surrogate was trained on.  `warm` starts each evaluation's data solve from
+    the previous evaluation's alpha (FP32 y)."""
     from scipy.optimize import minimize
 
     state = {"evals": 0, "fallback": surrogate is None, "rechecks": []}
+    wst = {} if warm else None
     t0 = time.perf_counter()
     d = plan.d
 
@@ -166,12 +190,12 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
     def slq_objective(theta):
         state["evals"] += 1
         plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
-        res = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=20000)
+        res = _mll(plan, y, k, num_probes, seed, tol, 20000, wst)
         return -res["mll"], -np.asarray(res["grad"])
 
     def surrogate_objective(theta):
         state["evals"] += 1
-        dfit, dgrad = data_fit_and_grad(plan, theta, y, k, tol)
+        dfit, dgrad = data_fit_and_grad(plan, theta, y, k, tol, warm=wst)
         ld, ldg = surrogate(theta)
         if state["evals"] % recheck == 0:
             ld_slq, ldg_slq = logdet_and_grad(plan, theta, k, num_probes, seed, tol)
@@ -203,4 +227,4 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
     final = plan.mll_and_grad(y, None, k=k, num_probes=num_probes, seed=seed, tol=tol, max_iter=20000)
     torch.cuda.synchronize()
     return FitResult(th, final["mll"], state["evals"], time.perf_counter() - t0, state["fallback"],
-                     state["rechecks"])
+                     state["rechecks"], (wst or {}).get("iters", 0))

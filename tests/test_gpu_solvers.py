@@ -189,6 +189,45 @@ def test_mll_and_grad_matches_oracle_small(bits):
     assert abs(res["logdet"] - ex["logdet"]) < 5e-2 * abs(ex["logdet"])
 
 
+def test_mll_warm_start_matches_cold():
+    """mll_and_grad_warm: a zero start reproduces the cold call; a start from
+    the alpha of nearby hyper-parameters meets the same oracle true residual
+    with fewer data-column iterations, and the probe columns (which always
+    start at zero) give the same log det."""
+    W = workloads.terrain(n=3000, grid=60)
+    say("mll warm start terrain", W.n, W.grid_m)
+    plan, op = make(W)
+    y = to_gpu(W.y.astype(np.float32)).contiguous()
+    k, t, tol = 30, 4, 1e-5
+    cold0 = plan.mll_and_grad(y, None, k=k, num_probes=t, seed=SEED, tol=tol)
+    z = plan.mll_and_grad(y, None, k=k, num_probes=t, seed=SEED, tol=tol, want_alpha=True)
+    assert z["mll"] == pytest.approx(cold0["mll"], rel=1e-12)
+    assert z["iters"] == cold0["iters"]
+    le, ls, lf, lg = W.hypers()
+    step = np.array([0.02, -0.02])
+    h1 = (le + step, ls + 0.02, lf - 0.02, lg + 0.02)
+    plan.set_hypers(*h1)
+    op.set_hypers(*h1)
+    cold = plan.mll_and_grad(y, None, k=k, num_probes=t, seed=SEED, tol=tol)
+    warm = plan.mll_and_grad(y, None, k=k, num_probes=t, seed=SEED, tol=tol, x0=z["alpha"], want_alpha=True)
+    say("  data-column iterations: cold", cold["iters"][0], "warm", warm["iters"][0])
+    say("  mll cold", cold["mll"], "warm", warm["mll"], " log det", cold["logdet"], warm["logdet"])
+    y64 = W.y.astype(np.float32).astype(np.float64)
+    a = warm["alpha"].cpu().numpy()
+    rel = np.linalg.norm(y64 - op.matvec(a[:, None])[:, 0]) / np.linalg.norm(y64)
+    say("  oracle true residual of the warm alpha", rel)
+    assert rel <= 1.05 * tol
+    assert warm["iters"][0] < cold["iters"][0]
+    assert warm["iters"][1:] == cold["iters"][1:]
+    assert warm["logdet"] == pytest.approx(cold["logdet"], rel=1e-9)
+    assert warm["mll"] == pytest.approx(cold["mll"], rel=1e-4, abs=1e-6 * abs(cold["logdet"]))
+    g, gc = warm["grad"], cold["grad"]
+    assert np.linalg.norm(g - gc) / np.linalg.norm(gc) < 1e-3
+    with pytest.raises(TypeError):
+        plan.mll_and_grad(y.double(), None, k=k, num_probes=0, tol=tol, want_alpha=True)
+    plan.close()
+
+
 def test_autograd_mll_on_the_implicit_surface():
     """torch.autograd through MarginalLikelihood returns the adjoint gradient of
     mll_and_grad (bitwise); on a small torus (d = 3) that gradient matches the
