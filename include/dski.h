@@ -436,17 +436,12 @@ dski_status dski_rademacher(uint64_t seed, int col0, int ncols, int N, float* ou
 /* Host utility: e_1^T log(T) e_1 for the Lanczos tridiagonal of J CG steps with
  * coefficients alpha, beta (host arrays, as returned by pcg_solve):
  * T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} = sqrt(beta_j)/alpha_j
- * (Gauss quadrature of Sec. 2's Lanczos connection).  *ok = 0 if a Ritz value
- * is not positive or the eigen-iteration fails. */
+ * (Gauss quadrature of Sec. 2's Lanczos connection).  Up to J = 64 by the
+ * symmetric tridiagonal QR algorithm on the first row of the eigenvectors;
+ * longer tridiagonals by the trapezoidal rule on the integral representation of
+ * log(T) in log t, O(J * nodes) with about 250 nodes instead of O(J^2).  *ok = 0
+ * if T is not positive definite or the iteration fails. */
 double dski_lanczos_quad_log(const double* alpha_host, const double* beta_host, int J, int* ok);
-
-/* Host utility: the same value from the leading j x j blocks of T (the Gauss
- * rules of j Lanczos steps): j = min(J, 256), then doubled until two successive
- * values agree to rtol * max(1, |value|) or j = J; *used (may be NULL) receives
- * the final j.  slq_logdet and mll_and_grad evaluate their quadratures this way
- * with rtol = 1e-10, at O(j^2) instead of O(J^2) host work per probe. */
-double dski_lanczos_quad_log_adaptive(const double* alpha_host, const double* beta_host, int J, double rtol,
-                                      int* ok, int* used);
 
 /* ---------------------------------------------------------------------------------
  * Learned log-determinant surrogate (a network of this project, not of the paper):

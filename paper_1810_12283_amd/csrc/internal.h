@@ -247,7 +247,6 @@ void dskip_destroy(dski_plan p);
 
 // --- host numerics ---------------------------------------------------------------------
 double gauss_quad_log(const double* alpha, const double* beta, int J, int* ok);
-double gauss_quad_log_adaptive(const double* alpha, const double* beta, int J, double rtol, int* ok, int* used);
 double gauss_quad_log_tri(const double* diag, const double* off, int J, int* ok);
 int sym_eig_jacobi(int k, double* A, double* V, double* w);
 

@@ -95,9 +95,6 @@ static dski_status swap_first_column(T* a, T* b, int N, hipStream_t st) {
   return DSKI_OK;
 }
 
-// convergence threshold of the quadrature over growing Lanczos blocks
-constexpr double kQuadRtol = 1e-10;
-
 struct ProbeRun {
   std::vector<double> quad, weight;
   double logdet = 0, stderr_ = 0;
@@ -110,16 +107,13 @@ static void slq_combine(const std::vector<double>& ab, int max_iter, int R, int 
   out.weight.assign(t, 0.0);
   std::vector<double> vals(t);
   std::vector<int> okv(t, 1);
-  // one Gauss quadrature per probe, on leading blocks of the CG tridiagonal until
-  // the rule has converged (O(j^2) in the block size j reached): probes spread
-  // over host threads
+  // one Gauss quadrature per probe: probes spread over host threads
   auto work = [&](int i) {
     const int c = col0 + i;
     const int J = std::min(res.iters[c], max_iter);
-    int ok = 0, used = 0;
-    const double q = gauss_quad_log_adaptive(ab.data() + (size_t)c * max_iter,
-                                             ab.data() + (size_t)R * max_iter + (size_t)c * max_iter, J,
-                                             kQuadRtol, &ok, &used);
+    int ok = 0;
+    const double q = gauss_quad_log(ab.data() + (size_t)c * max_iter,
+                                    ab.data() + (size_t)R * max_iter + (size_t)c * max_iter, J, &ok);
     okv[i] = ok;
     out.quad[i] = q;
     out.weight[i] = res.rz0[c];

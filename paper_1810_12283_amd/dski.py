@@ -74,7 +74,6 @@ _SIGS = {
                                dp, dp, dp, ip, vp]),
     "dski_rademacher": (C.c_int, [C.c_uint64, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]),
     "dski_lanczos_quad_log": (C.c_double, [dp, dp, C.c_int, ip]),
-    "dski_lanczos_quad_log_adaptive": (C.c_double, [dp, dp, C.c_int, C.c_double, ip, ip]),
     "dski_plan_set_precision": (C.c_int, [vp, C.c_int]),
     "dski_set_kernel": (C.c_int, [vp, C.c_int, vp]),
     "dski_mvm_stage": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]),
@@ -685,18 +684,6 @@ def lanczos_quad_log(alpha: Sequence[float], beta: Sequence[float]) -> float:
     if not ok.value:
         raise DSKIError(-4, "quadrature failed (non-positive Ritz value)")
     return v
-
-
-def lanczos_quad_log_adaptive(alpha: Sequence[float], beta: Sequence[float], rtol: float = 1e-10):
-    """(value, j used): the quadrature from growing leading blocks of T."""
-    J = len(alpha)
-    a = _arr([float(v) for v in alpha], C.c_double)
-    b = _arr([float(v) for v in beta] + [0.0], C.c_double)
-    ok, used = C.c_int(), C.c_int()
-    v = lib().dski_lanczos_quad_log_adaptive(a, b, J, float(rtol), C.byref(ok), C.byref(used))
-    if not ok.value:
-        raise DSKIError(-4, "quadrature failed (non-positive Ritz value)")
-    return v, used.value
 
 
 def version() -> str:

@@ -78,31 +78,36 @@ def test_lanczos_quadrature_random_cg_coefficients(J, seed):
     assert got == pytest.approx(want, rel=1e-10, abs=1e-12)
 
 
-@pytest.mark.parametrize("outlier", [False, True])
-def test_lanczos_quadrature_adaptive_blocks(outlier):
-    """The quadrature over growing leading blocks against the full-length rule
-    and against e_1^T log(A) e_1 of the spectrum itself (sum of z_i^2 log lam_i
-    over ||z||^2), on 3,000 CG steps of a four-decade spectrum, with and without
-    one isolated small eigenvalue that CG resolves late."""
+
+def test_lanczos_quadrature_against_high_precision():
+    """The integral-form quadrature (tridiagonals longer than 64) against a
+    30-digit eigen-decomposition (mpmath) of an 80-step CG tridiagonal of a
+    spectrum over ten decades, and both forms against each other at the
+    switch-over length."""
+    mp = pytest.importorskip("mpmath")
     dski = _lib()
     from oracle import krylov
-    r = np.random.default_rng(5)
-    lam = np.geomspace(1e-1, 1e3, 4000)
-    if outlier:
-        lam[0] = 1e-6
-    lam = lam[r.permutation(lam.size)]
+    r = np.random.default_rng(0)
+    lam = np.geomspace(1e-6, 1e4, 3000)
     z = r.choice([-1.0, 1.0], lam.size)
-    res = krylov.pcg(lambda V: lam[:, None] * V, z, fixed_iters=3000)
+    res = krylov.pcg(lambda V: lam[:, None] * V, z, fixed_iters=80)
     a, b = res["alpha"][0], res["beta"][0]
-    full = dski.lanczos_quad_log(a, b[:-1])
-    got, used = dski.lanczos_quad_log_adaptive(a, b[:-1], 1e-10)
-    exact = float(np.sum(z * z * np.log(lam)) / np.sum(z * z))
-    if not outlier:
-        assert used < 3000
-    # a stagnating rule can stop with an error a few times rtol: far below
-    # the stochastic error of the estimator
-    assert got == pytest.approx(full, rel=1e-8)
-    assert got == pytest.approx(exact, rel=1e-8)
-    # a tolerance of zero takes the whole tridiagonal
-    v0, u0 = dski.lanczos_quad_log_adaptive(a, b[:-1], 0.0)
-    assert u0 == 3000 and v0 == full
+    J = len(a)
+    diag = [1.0 / a[j] + (b[j - 1] / a[j - 1] if j > 0 else 0.0) for j in range(J)]
+    off = [np.sqrt(b[j]) / a[j] for j in range(J - 1)]
+    mp.mp.dps = 30
+    T = mp.matrix(J, J)
+    for i in range(J):
+        T[i, i] = mp.mpf(diag[i])
+        if i + 1 < J:
+            T[i, i + 1] = T[i + 1, i] = mp.mpf(off[i])
+    E, Q = mp.eighe(T)
+    want = float(sum(Q[0, k] ** 2 * mp.log(E[k]) for k in range(J)))
+    got = dski.lanczos_quad_log(a, b[:-1])
+    assert got == pytest.approx(want, rel=1e-13)
+    # the QR form at J = 64 and the integral form at J = 65 describe the same rule
+    # family: each against LAPACK on its own leading block
+    from oracle import slq
+    for Jc in (64, 65):
+        w = slq.quad_from_tridiag(*krylov.cg_tridiag(a[:Jc], b[:Jc]))
+        assert dski.lanczos_quad_log(a[:Jc], b[:Jc - 1]) == pytest.approx(w, rel=1e-10)
