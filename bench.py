@@ -41,6 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PMC_MARKER_SEED = 0x504D43
 SEED = 0x181012283
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "terrain_mvm_pmc.md")
 MVM_SOURCE = os.path.join(ROOT, "paper_1810_12283_amd", "csrc", "mvm.hip")
@@ -76,6 +77,169 @@ def measured_traffic():
     except OSError:
         return None
     return None
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stats_table(csv_path, top=40):
+    """Markdown rows (kernel, calls, total ms, avg us, %) of a rocprofv3
+    --kernel-trace --stats kernel_stats.csv, largest total first."""
+    import csv
+    rows = []
+    with open(csv_path, newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]),
+                         float(r["Percentage"])))
+    rows.sort(key=lambda r: -r[2])
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for name, calls, tot, avg, pct in rows[:top]:
+        out.append(f"| `{_short_kernel(name)}` | {calls} | {tot / 1e6:.1f} | {avg / 1e3:.2f} | {pct:.1f} |")
+    out.append("")
+    out.append(f"Total kernel time {sum(r[2] for r in rows) / 1e6:.1f} ms over {len(rows)} kernels "
+               f"({min(top, len(rows))} largest shown).")
+    return "\n".join(out)
+
+
+def _pmc_dispatches(folder):
+    """{dispatch id: (kernel name, grid size, {counter: value})} from the
+    counter-collection CSV files rocprofv3 wrote under `folder`."""
+    import csv
+    import glob
+    out = {}
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *counter_collection.csv under {folder}")
+    for fn in files:
+        with open(fn, newline="") as f:
+            for row in csv.DictReader(f):
+                did = int(row["Dispatch_Id"])
+                name = row.get("Kernel_Name", "")
+                grid = int(float(row.get("Grid_Size", 0) or 0))
+                ent = out.setdefault(did, (name, grid, {}))
+                c = row["Counter_Name"]
+                ent[2][c] = ent[2].get(c, 0.0) + float(row["Counter_Value"])
+    return out
+
+
+def _pmc_groups(disp, labels):
+    """Dispatches split at the marker dispatches (the 64-entry Rademacher column)
+    into {label: [(name, counters), ...]} in dispatch order."""
+    groups, cur = {}, None
+    marks = 0
+    for did in sorted(disp):
+        name, grid, ctr = disp[did]
+        if "k_rademacher" in name and 0 < grid <= 1024:
+            if marks >= len(labels):
+                raise ValueError("more marker dispatches than labels")
+            cur = labels[marks]
+            marks += 1
+            groups[cur] = []
+            continue
+        if cur is not None:
+            groups[cur].append((name, ctr))
+    if marks != len(labels):
+        raise ValueError(f"{marks} marker dispatches for {len(labels)} labels")
+    return groups
+
+
+def _short_kernel(name):
+    name = name.split("(")[0].strip()
+    return name[5:] if name.startswith("void ") else name
+
+
+def pmc_summary(fetch_dir, write_dir, log_path, sq_dir=None, out_path=PMC_SUMMARY, commands=None):
+    """Write the PMC summary of `bench.py --pmc-mvm` (one rocprofv3 run per counter
+    group) with per-variant HBM bytes per launch keyed to the mvm.hip digest."""
+    import numpy as np
+    info = None
+    with open(log_path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{") and '"pmc_mvm"' in line:
+                info = json.loads(line)
+    if info is None:
+        raise ValueError(f"no pmc_mvm line in {log_path}")
+    labels = info["labels"]
+    gf = _pmc_groups(_pmc_dispatches(fetch_dir), labels)
+    gw = _pmc_groups(_pmc_dispatches(write_dir), labels)
+    gs = _pmc_groups(_pmc_dispatches(sq_dir), labels) if sq_dir else None
+
+    def main_kernel(group):
+        names = {}
+        for name, _ in group:
+            names[name] = names.get(name, 0) + 1
+        return max(names, key=names.get)
+
+    def med(group, name, counter):
+        v = [c.get(counter) for n, c in group if n == name and counter in c]
+        return float(np.median(v)) if v else float("nan")
+
+    # calibration on the copy group: the runtime copy and the multiply each move
+    # copy_bytes in and copy_bytes out
+    cb = info["copy_bytes"]
+    copy_f = [c["FETCH_SIZE"] for _, c in gf["copy"] if c.get("FETCH_SIZE", 0) * 1024 > 0.25 * cb]
+    copy_w = [c["WRITE_SIZE"] for _, c in gw["copy"] if c.get("WRITE_SIZE", 0) * 1024 > 0.25 * cb]
+    kf = cb / (float(np.median(copy_f)) * 1024)
+    kw = cb / (float(np.median(copy_w)) * 1024)
+    rows, traffic = [], {}
+    for lab in labels:
+        if lab == "copy":
+            continue
+        names = [main_kernel(gf[lab])] if lab != "pcg" else sorted({n for n, _ in gf[lab]})
+        for name in names:
+            fk = med(gf[lab], name, "FETCH_SIZE")
+            wk = med(gw[lab], name, "WRITE_SIZE")
+            byts = fk * 1024 * kf + wk * 1024 * kw
+            extra = ""
+            if gs is not None:
+                waves = med(gs[lab], name, "SQ_WAVES")
+                vals = [med(gs[lab], name, c) for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT",
+                                                        "SQ_WAIT_INST_ANY")]
+                extra = f" | {waves:.0f} | " + " | ".join(f"{v / waves:.0f}" if waves else "-" for v in vals)
+            rows.append(f"| {lab} | `{_short_kernel(name)}` | {fk:.0f} | {wk:.0f} | {byts / 1e6:.2f} MB{extra} |")
+            if lab != "pcg":
+                traffic[lab] = byts
+    cmd = "\n".join(commands or [])
+    head = ("| label | kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes / launch"
+            + (" | waves | VALU instr / wave | LDS instr / wave | LDS bank-conflict cycles / wave | "
+               "wait-any instr cycles / wave |" if gs is not None else " |"))
+    sep = "|---|---|---:|---:|---:" + ("|---:|---:|---:|---:|---:|" if gs is not None else "|")
+    text = [
+        "# PMC counters of the terrain MVM stages and PCG kernels "
+        "(n = 20,000, d = 2, 200 x 200 grid, 17 columns, rank 50)",
+        "",
+        "Commands (from the repository root on one MI355X; one counter group per run), then "
+        "`python bench.py --pmc-summary` on their output folders:",
+        "",
+        "```",
+        cmd,
+        "```",
+        "",
+        "`bench.py --pmc-mvm` builds the plan and runs the tuner, then launches every scatter, gather and "
+        "K_UU variant three times, a 20-iteration block PCG with direct launches and the rank-50 "
+        "preconditioner, and three 256 MiB copies through the runtime's copy kernel and an elementwise "
+        "multiply; a 64-entry Rademacher column before each group marks where it starts. Figures are "
+        "medians over the launches of a group's kernel.",
+        "",
+        f"Calibration on the copies ({cb / 2**20:.0f} MiB read and written per launch): FETCH_SIZE reads "
+        f"{np.median(copy_f):.0f} KiB, WRITE_SIZE {np.median(copy_w):.0f} KiB, so fetched bytes = FETCH_SIZE x "
+        f"1024 x {kf:.3f} and written bytes = WRITE_SIZE x 1024 x {kw:.3f}. FETCH_SIZE counts what the L2s of "
+        "all 8 XCDs fetch from the fabric, part of which the Infinity Cache serves, so the fetch figures "
+        "bound HBM reads from above.",
+        "",
+        head,
+        sep,
+        *rows,
+        "",
+        "traffic-bytes-per-launch: " + " ".join(f"{k}={v:.0f}" for k, v in traffic.items())
+        + f" source={info['source']}",
+        "",
+    ]
+    with open(out_path, "w") as f:
+        f.write("\n".join(text))
+    return traffic
 
 
 def _events_ms(fn, reps, stream):
@@ -436,9 +600,27 @@ def main(argv=None):
     ap.add_argument("--predict-only", action="store_true",
                     help="only the prediction block of the terrain workload (grid vector, means of 1,000,000 "
                          "test points, pivoted-Cholesky and randomized variance) and the active-subspace block")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="PATH", default=None,
+                    help="FETCH_DIR WRITE_DIR LOG [SQ_DIR]: write the PMC summary from rocprofv3 --pmc runs of "
+                         "--pmc-mvm (counter folders and the run's stdout), no GPU needed")
+    ap.add_argument("--stats-table", default=None, metavar="CSV",
+                    help="print the markdown table of a rocprofv3 --stats kernel_stats.csv (no GPU needed)")
+    ap.add_argument("--pmc-command", action="append", default=[],
+                    help="a command line to record in the PMC summary (repeatable)")
     ap.add_argument("--pmc-mvm", action="store_true",
                     help="run only the MVM stages (and a 256 MiB device copy for calibration) for rocprofv3 --pmc")
     a = ap.parse_args(argv)
+    if a.stats_table:
+        print(stats_table(a.stats_table))
+        return 0
+    if a.pmc_summary:
+        p = a.pmc_summary
+        if len(p) not in (3, 4):
+            print("--pmc-summary takes FETCH_DIR WRITE_DIR LOG [SQ_DIR]", file=sys.stderr)
+            return 2
+        t = pmc_summary(p[0], p[1], p[2], p[3] if len(p) == 4 else None, commands=a.pmc_command)
+        print(json.dumps({"pmc_summary": PMC_SUMMARY, "traffic": t}))
+        return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the block PCG would shard "
               f"its right-hand sides across GPUs, which this build does not do.", file=sys.stderr)
@@ -527,37 +709,49 @@ def main(argv=None):
         tuned_first = plan.autotune(R)
         Vt = plan.permute(Vblk, +1)
         Yt = torch.empty_like(Vt)
-        for _ in range(5):
-            plan.mvm_stage(0, Vt)
-            plan.mvm_stage(1, Vt)
-            plan.mvm_stage(2, Vt, Yt)
+        labels = []
+
+        def mark(label):
+            # a 64-entry Rademacher column: a dispatch the summary recognises by name and
+            # size, so every dispatch after it (up to the next marker) belongs to `label`
+            dski.rademacher(PMC_MARKER_SEED, 0, 1, 64, device=dev)
+            labels.append(label)
+
         # every scatter, gather and K_UU variant a few times (the tuner's pick is not
         # stable while counters are collected; the summary keys traffic by variant)
         for sv in range(len(tuned_first["scatter_us"])):
             plan.set_variants(sv, 0)
+            mark(f"scatter_v{sv}")
             for _ in range(3):
                 plan.mvm_stage(0, Vt)
         for gv in range(len(tuned_first["gather_us"])):
             plan.set_variants(0, gv)
+            plan.mvm_stage(0, Vt)
+            mark(f"gather_v{gv}")
             for _ in range(3):
                 plan.mvm_stage(2, Vt, Yt)
-        for v in (1, 0):
+        for v, name in ((1, "kuu_dense"), (0, "kuu_fft")):
             for ax in range(d):
                 plan.set_kuu_variant(ax, v)
+            mark(name)
             for _ in range(3):
                 plan.mvm_stage(1, Vt)
         # a short direct-launch block PCG with the rank-k preconditioner (per-dispatch counters)
         plan.set_graph(False)
         pc = plan.pivchol(W.rank)
+        mark("pcg")
         plan.pcg(Vblk, pc, tol=1e-30, max_iter=20)
         plan.set_graph(True)
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        mark("copy")
         for _ in range(3):
             dst.copy_(src)                   # runtime copy kernel: 256 MiB read, 256 MiB written
             torch.mul(src, 1.0, out=dst)     # elementwise kernel: the same bytes
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_mvm": "done", "copy_bytes": src.numel() * 4, "source": source_digest()}), flush=True)
+        print(json.dumps({"pmc_mvm": "done", "copy_bytes": src.numel() * 4, "source": source_digest(),
+                          "labels": labels}), flush=True)
         return 0
 
     def step(record):
@@ -624,8 +818,9 @@ def main(argv=None):
         plan.close()
         return out
 
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
         step(False)
+        _progress(f"warm-up step {i + 1}/{a.warmup}")
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
@@ -633,6 +828,7 @@ def main(argv=None):
         recs.append(step(True))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    _progress(f"{a.steps} timed steps in {wall:.1f} s")
 
     ms_mvm = float(np.mean([r["ms_mvm"] for r in recs]))
     Bm = mvm_bytes(N, M, n, d, R)
@@ -700,14 +896,18 @@ def main(argv=None):
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
     }
-    line["torus"] = grid_block(workloads.torus(), R, stream)
-    line["terrain_quintic"] = grid_block(W, R, stream, interp="quintic")
-    line["torus_spline"] = grid_block(workloads.torus(), R, stream, kernel="spline")
-    line["dskip"] = dskip_block(R, stream)
-    line["surrogate"] = surrogate_block(W, y, W.rank, stream)
-    line["predict"] = predict_block(W, stream)
-    line["active_subspace"] = active_block()
-    line["bo_alg1"] = bo_block()
+    blocks = (("torus", lambda: grid_block(workloads.torus(), R, stream)),
+              ("terrain_quintic", lambda: grid_block(W, R, stream, interp="quintic")),
+              ("torus_spline", lambda: grid_block(workloads.torus(), R, stream, kernel="spline")),
+              ("dskip", lambda: dskip_block(R, stream)),
+              ("surrogate", lambda: surrogate_block(W, y, W.rank, stream)),
+              ("predict", lambda: predict_block(W, stream)),
+              ("active_subspace", active_block),
+              ("bo_alg1", bo_block))
+    for name, fn in blocks:
+        tb = time.perf_counter()
+        line[name] = fn()
+        _progress(f"{name} block {time.perf_counter() - tb:.1f} s")
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, R, recs[-1]["X_host"], recs[-1]["B_host"])
         # the headline solve's residual as the oracle's FP64 operator sees it

@@ -178,7 +178,8 @@ def run_alg1(objective: Callable[[np.ndarray], tuple], X0: np.ndarray, lo, hi, i
                 if e.status != -4:  # only a CG breakdown (numerically singular K~) is a rejected step
                     raise
                 return 1e300, np.zeros_like(th)
-            return -r["mll"], -np.asarray(r["grad"])
+            # scaled by 1/N: in nats the first L-BFGS-B step would land on the bounds
+            return -r["mll"] / N, -np.asarray(r["grad"]) / N
 
         if fit_evals > 0:
             opt = minimize(neg_mll, theta, jac=True, method="L-BFGS-B", bounds=list(zip(hlo, hhi)),

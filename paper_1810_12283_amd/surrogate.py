@@ -177,6 +177,9 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
     wst = {} if warm else None
     t0 = time.perf_counter()
     d = plan.d
+    # L-BFGS-B sees -mll / N: in nats the gradient is O(N) and the first
+    # projected step would land on the bounds
+    inv_n = 1.0 / plan.N
 
     class _FallBack(Exception):
         """Raised by a failed re-check: L-BFGS-B's curvature pairs and line
@@ -191,7 +194,7 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
         state["evals"] += 1
         plan.set_hypers(theta[:d], theta[d], theta[d + 1], theta[d + 2])
         res = _mll(plan, y, k, num_probes, seed, tol, 20000, wst)
-        return -res["mll"], -np.asarray(res["grad"])
+        return -res["mll"] * inv_n, -np.asarray(res["grad"]) * inv_n
 
     def surrogate_objective(theta):
         state["evals"] += 1
@@ -208,7 +211,7 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
             ld, ldg = ld_slq, ldg_slq
         mll = dfit - 0.5 * ld
         grad = dgrad - 0.5 * ldg
-        return -mll, -grad
+        return -mll * inv_n, -grad * inv_n
 
     theta = np.asarray(theta0, dtype=np.float64)
     res = None
