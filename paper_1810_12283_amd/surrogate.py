@@ -166,7 +166,8 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
     """Maximise the marginal likelihood over the log hyper-parameters with L-BFGS.
 
     With a surrogate: mll = data-fit part (exact) - log det (network) / 2, with
-    SLQ re-checks every `recheck` evaluations and a fall-back to plain SLQ when
+    SLQ re-checks every `recheck` evaluations and at the point where the search
+    ends, and a fall-back to plain SLQ (L-BFGS restarted from that point) when
     the relative log det error exceeds `fallback_tol`.  `bounds` (a list of
     (lo, hi) per log hyper-parameter) keeps the search inside the region the
     surrogate was trained on.  `warm` starts each evaluation's data solve from
@@ -219,6 +220,15 @@ def fit(plan: dski.Plan, y: torch.Tensor, theta0: np.ndarray, k: int, num_probes
         try:
             res = minimize(surrogate_objective, theta, jac=True, method="L-BFGS-B", bounds=bounds,
                            options={"maxfun": max_evals, "gtol": gtol})
+            # the search may end between re-checks: its end point is re-checked too
+            ld_net, _ = surrogate(res.x)
+            ld_slq, _ = logdet_and_grad(plan, res.x, k, num_probes, seed, tol)
+            err = abs(ld_net - ld_slq) / abs(ld_slq)
+            state["rechecks"].append((state["evals"], ld_net, ld_slq, err))
+            if err > fallback_tol:
+                state["fallback"] = True
+                theta = np.array(res.x, dtype=np.float64)
+                res = None
         except _FallBack as fb:
             theta = fb.theta
     if res is None:

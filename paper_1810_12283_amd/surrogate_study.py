@@ -119,8 +119,9 @@ def _load(paths):
 def phase_evaluate(a):
     from . import surrogate as sg
     rows = _load(a.data)
-    ok = [r for r in rows if r["status"] == 0]
-    _say(f"evaluate: {len(rows)} samples, {len(ok)} converged")
+    ok = [r for r in rows if r["status"] == 0 or a.include_capped]
+    _say(f"evaluate: {len(rows)} samples, {sum(r['status'] == 0 for r in rows)} converged, "
+         f"{len(ok)} used")
     hold = ok[-a.holdout:]
     tr = ok[:-a.holdout]
     W, plan, th_star = _setup()
@@ -144,7 +145,10 @@ def phase_evaluate(a):
          f"p90 {np.quantile(errs, 0.9):.3g} max {errs.max():.3g}")
     y = torch.tensor(W.y.astype(np.float32), device="cuda")[None, :].contiguous()
     box = [(c - RADIUS, c + RADIUS) for c in th_star]
-    starts = sg.sobol_design(th_star, 8, a.start_radius, seed=43)[:a.starts]
+    # a centre (the moment-matched hyper-parameters plus --start-offset), then
+    # Sobol points around it
+    c0 = th_star + np.array([float(v) for v in a.start_offset.split(",")]) if a.start_offset else th_star
+    starts = np.vstack([c0[None, :], sg.sobol_design(c0, 8, a.start_radius, seed=43)])[:a.starts]
     fits = []
     for j, t0v in enumerate(starts):
         plain = sg.fit(plan, y, t0v, W.rank, W.num_probes, PROBE_SEED, W.tol, surrogate=None,
@@ -170,7 +174,7 @@ def phase_evaluate(a):
                 holdout=len(hold), data_s=t_data, train_s=t_train,
                 holdout_err=dict(median=float(np.median(errs)), p90=float(np.quantile(errs, 0.9)),
                                  max=float(errs.max())),
-                fits=fits, plain_fit_s=float(tp.mean()), surrogate_fit_s=float(ts.mean()),
+                include_capped=bool(a.include_capped), fits=fits, plain_fit_s=float(tp.mean()), surrogate_fit_s=float(ts.mean()),
                 fit_speedup=float(tp.mean() / ts.mean()),
                 equal_mll=bool(all(f["rel_mll"] <= 1e-3 for f in fits)),
                 break_even_fits=(float((t_data + t_train) / gain) if gain > 0 else None))
@@ -194,7 +198,12 @@ def main(argv=None):
     ap.add_argument("--lr-final", type=float, default=2e-5)
     ap.add_argument("--lam", type=float, default=1.0)
     ap.add_argument("--starts", type=int, default=3)
-    ap.add_argument("--start-radius", type=float, default=1.0)
+    ap.add_argument("--start-radius", type=float, default=0.5)
+    ap.add_argument("--start-offset", default="",
+                    help="comma-separated offsets (log-units) of the starts' centre from the moment-matched values")
+    ap.add_argument("--include-capped", action="store_true",
+                    help="train on samples whose PCG reached max_iter too (their log det is the method's "
+                         "output at that cap)")
     ap.add_argument("--max-evals", type=int, default=60)
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():

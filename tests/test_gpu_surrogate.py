@@ -2,9 +2,17 @@
 (n = 2,000, 60 x 60 grid; 64 training points within 0.5 log-units of a
 plain-SLQ fit, length scales >= 3h): training targets from the device SLQ, training with
 the device Adam kernels, accuracy on fresh Sobol points, and an L-BFGS fit
-with the surrogate (SLQ re-check every 10 evaluations, fall-back above 1e-3),
-bounded to the trained region, against the same fit with plain SLQ: equal final marginal likelihood within
-1e-3 relative, and what the surrogate saves per evaluation."""
+with the surrogate (SLQ re-check every 5 evaluations and at the end point,
+fall-back above 1e-3), bounded to the trained region, against the same fit
+with plain SLQ: equal final marginal likelihood within 1e-3 relative, and what
+the surrogate saves per evaluation.
+
+The test asserts the mechanism, not a speed-up: the surrogate falls back. At
+the full terrain configuration (n = 20,000, 2,000 SLQ samples within +-2
+log-units, 1,391 converged ones for training) the held-out log det error is
+0.19 % median, and the fits fail their first re-check with errors of 0.56 -
+0.92 %, above the 1e-3 band, and then cost what plain fits cost
+(paper_1810_12283_amd.surrogate_study reproduces those runs)."""
 import time
 
 import numpy as np
