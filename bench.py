@@ -166,10 +166,15 @@ def pmc_summary(fetch_dir, write_dir, log_path, sq_dir=None, out_path=PMC_SUMMAR
     gw = _pmc_groups(_pmc_dispatches(write_dir), labels)
     gs = _pmc_groups(_pmc_dispatches(sq_dir), labels) if sq_dir else None
 
-    def main_kernel(group):
+    family = {"scatter": "k_scatter", "gather": "k_gather", "kuu": "k_toeplitz"}
+
+    def main_kernel(lab, group):
+        # the most frequent kernel of the stage's family in the group
+        fam = family.get(lab.split("_")[0], "")
         names = {}
         for name, _ in group:
-            names[name] = names.get(name, 0) + 1
+            if fam in name:
+                names[name] = names.get(name, 0) + 1
         return max(names, key=names.get)
 
     def med(group, name, counter):
@@ -187,7 +192,8 @@ def pmc_summary(fetch_dir, write_dir, log_path, sq_dir=None, out_path=PMC_SUMMAR
     for lab in labels:
         if lab == "copy":
             continue
-        names = [main_kernel(gf[lab])] if lab != "pcg" else sorted({n for n, _ in gf[lab]})
+        multi = lab in ("pcg", "pivchol")
+        names = sorted({n for n, _ in gf[lab]}) if multi else [main_kernel(lab, gf[lab])]
         for name in names:
             fk = med(gf[lab], name, "FETCH_SIZE")
             wk = med(gw[lab], name, "WRITE_SIZE")
@@ -199,7 +205,7 @@ def pmc_summary(fetch_dir, write_dir, log_path, sq_dir=None, out_path=PMC_SUMMAR
                                                         "SQ_WAIT_INST_ANY")]
                 extra = f" | {waves:.0f} | " + " | ".join(f"{v / waves:.0f}" if waves else "-" for v in vals)
             rows.append(f"| {lab} | `{_short_kernel(name)}` | {fk:.0f} | {wk:.0f} | {byts / 1e6:.2f} MB{extra} |")
-            if lab != "pcg":
+            if not multi:
                 traffic[lab] = byts
     cmd = "\n".join(commands or [])
     head = ("| label | kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes / launch"
@@ -738,6 +744,7 @@ def main(argv=None):
                 plan.mvm_stage(1, Vt)
         # a short direct-launch block PCG with the rank-k preconditioner (per-dispatch counters)
         plan.set_graph(False)
+        mark("pivchol")
         pc = plan.pivchol(W.rank)
         mark("pcg")
         plan.pcg(Vblk, pc, tol=1e-30, max_iter=20)
