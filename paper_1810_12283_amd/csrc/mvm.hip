@@ -100,10 +100,11 @@ __device__ __forceinline__ void interp_weight_at(double t, double ih, int o, dou
 // point in the cells whose stencils reach the tile (the tile's cells plus a
 // halo of S - 1 - H below and H above), with a table of each cell's range, then
 // every thread sums its node's contributions from LDS in the same fixed order
-// as above.  One thread stages one region point; regions of more than 256
-// points (dense tiles: surfaces in 3-D, wide quintic stencils) are staged 256
-// points at a time, each node adding the points of every chunk that fall in
-// its cells (same order, same result).
+// as above.  One thread stages one region point; regions of more than PMAX
+// points (256 in 1-D and 2-D, 128 in 3-D, where the LDS then holds all the
+// columns of a 17-column block) are staged PMAX points at a time, each node
+// adding the points of every chunk that fall in its cells (same order, same
+// result).
 template <int D, int S>
 struct TileShape {
   static constexpr int e0 = D == 1 ? 256 : (D == 2 ? 16 : 4);
@@ -236,6 +237,11 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int* __restrict__ cell,
   }
 }
 
+template <int D>
+constexpr int scatter_pmax() {
+  return D == 3 ? 128 : 256;
+}
+
 template <int D, int S, int CR, typename T, typename GT>
 __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cell,
                                                      const double* __restrict__ toff,
@@ -246,7 +252,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
                                                      const int* __restrict__ tile_cl,
                                                      const T* __restrict__ V, int ldv, int R, int cr,
                                                      GT* __restrict__ G, long long M) {
-  constexpr int PMAX = 256;  // one thread stages one region point
+  constexpr int PMAX = scatter_pmax<D>();  // one thread stages one region point
   constexpr int H = S / 2 - 1;
   using TS = TileShape<D, S>;
   // weights point-major, 2 S D + 1 doubles per point: lanes reading one point at
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   for (int q0 = 0; q0 < total; q0 += PMAX) {
     if (q0 > 0) __syncthreads();  // every node is done with the previous chunk
     const int q = threadIdx.x;
-    if (q0 + q < total) {
+    if (q < PMAX && q0 + q < total) {
       const int kq = tile_pts[off + q0 + q];
       const int cq = tile_cl[off + q0 + q];
       double tq[D];
@@ -354,15 +360,38 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
       for (int a = 0; a < last; ++a) lrow = lrow * span[a] + (c[a] - rlo[a]);
       const int qs = max(q0, s_lcs[lrow * span[last] + lo[last] - rlo[last]]);
       const int qe = min(q1, s_lcs[lrow * span[last] + hi[last] - rlo[last] + 1]);
-      for (int qq = qs; qq < qe; ++qq) {
-        const int ql = qq - q0;
-        double wv[D], wd[D];
-        const int cl = s_cl[ql];
+      int wo[D];  // LDS offsets of the outer axes' weights in this row
+#pragma unroll
+      for (int a = 0; a < last; ++a) wo[a] = a * 2 * S + j[a] - c[a] + H;
+      // two points per step: both points' LDS loads are issued before the first
+      // product (the loop is bound by dependent LDS latency), then the points
+      // are added in order, exactly as one at a time
+      int qq = qs;
+      for (; qq + 1 < qe; qq += 2) {
+        const int qa = qq - q0, qb = qa + 1;
+        const int cla = s_cl[qa], clb = s_cl[qb];
+        double wva[D], wda[D], wvb[D], wdb[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const int o = j[a] - (a == last ? cl : c[a]) + H;
-          wv[a] = s_w[ql * WS + a * 2 * S + o];
-          wd[a] = s_w[ql * WS + a * 2 * S + S + o];
+          const int oa = a == last ? last * 2 * S + j[a] - cla + H : wo[a];
+          const int ob = a == last ? last * 2 * S + j[a] - clb + H : wo[a];
+          wva[a] = s_w[qa * WS + oa];
+          wda[a] = s_w[qa * WS + S + oa];
+          wvb[a] = s_w[qb * WS + ob];
+          wdb[a] = s_w[qb * WS + S + ob];
+        }
+        scatter_accum<D, CR>(acc, wva, wda, s_v + (size_t)qa * CR * (D + 1));
+        scatter_accum<D, CR>(acc, wvb, wdb, s_v + (size_t)qb * CR * (D + 1));
+      }
+      if (qq < qe) {
+        const int ql = qq - q0;
+        const int cl = s_cl[ql];
+        double wv[D], wd[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const int o = a == last ? last * 2 * S + j[a] - cl + H : wo[a];
+          wv[a] = s_w[ql * WS + o];
+          wd[a] = s_w[ql * WS + S + o];
         }
         scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)ql * CR * (D + 1));
       }
@@ -383,18 +412,23 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
 }
 
 // Columns per work-group of the LDS-tiled scatter: a base chunk (4 columns in
-// 1-D and 2-D; 2 FP32 or 1 FP64 in 3-D) times 1, 1.5, 2 or 5; wider chunks mean
-// fewer work-groups, each staging its region once for more columns.  FP32 and
-// FP64 column values are tuned separately.
+// 1-D and 2-D; 2 FP32 or 1 FP64 in 3-D) times 1, 1.5, 2 or 5 (9 in 3-D, so that
+// a 17-column block is one chunk of FP32 columns); wider chunks mean fewer
+// work-groups, each staging its region once for more columns.  FP32 and FP64
+// column values are tuned separately.  On 3-D surface data the narrow chunks
+// win: a node's loop length follows its point count, which varies widely
+// within a wavefront (about 15 % of the lanes busy per step on the torus), and
+// wide chunks lower the occupancy that hides the LDS latency.
 template <int D, int S, typename T, int WIDTH>
 constexpr int scatter_cr() {
   constexpr int base = D <= 2 ? 4 : (sizeof(T) == 4 ? 2 : 1);
-  int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : (WIDTH == 2 ? 2 * base : 5 * base));
-  if (D == 3 && cr > 3) cr = 3;  // 3-D: the region tables leave room for 3 columns
+  constexpr int wide = D == 3 ? 9 : 5;
+  int cr = WIDTH == 0 ? base : (WIDTH == 1 ? base + (base + 1) / 2 : (WIDTH == 2 ? 2 * base : wide * base));
   // the staged column values share the 160 KB of LDS with the weights and tables
   using TS = TileShape<D, S>;
-  while (cr > 1 && 256 * (2 * S * D + 1) * 8 + 256 * cr * (D + 1) * (int)sizeof(T) + (TS::max_cells + 1) * 4 +
-                       256 * 4 > 160 * 1024)
+  constexpr int P = scatter_pmax<D>();
+  while (cr > 1 && P * (2 * S * D + 1) * 8 + P * cr * (D + 1) * (int)sizeof(T) + (TS::max_cells + 1) * 4 +
+                       P * 4 > 160 * 1024)
     --cr;
   return cr;
 }
