@@ -7,11 +7,14 @@
  *
  *     K~ = [W; dW_1; ...; dW_d] K_UU [W; dW_1; ...; dW_d]^T + D,
  *
- * where W holds cubic-convolution interpolation weights (Keys 1981, a = -1/2)
- * onto a uniform grid U, dW_p their derivatives along axis p, K_UU the SE
- * kernel (App. A) on the grid (Kronecker product of symmetric Toeplitz
- * factors, applied by FFT over circulant embeddings, Sec. 2), and
- * D = diag(sigma_f^2 1_n, sigma_g^2 1_{nd}) the value / gradient noise.
+ * where W holds convolution interpolation weights onto a uniform grid U
+ * (Keys' cubic kernel, a = -1/2, or the quintic kernel of Meijering et al.,
+ * Sec. 3.1), dW_p their derivatives along axis p, K_UU the kernel on the grid
+ * (SE, App. A: a Kronecker product of symmetric Toeplitz factors applied by
+ * FFT over circulant embeddings, Sec. 2; or the thin-plate spline kernel of
+ * App. A: a multi-level Toeplitz matrix applied by a d-dimensional circulant
+ * embedding), and D = diag(sigma_f^2 1_n, sigma_g^2 1_{nd}) the value /
+ * gradient noise.
  * On top of it: truncated pivoted Cholesky preconditioning (Sec. 3.3),
  * preconditioned CG, stochastic Lanczos quadrature for log det (Sec. 2), and
  * the log marginal likelihood eq. (1) with its hyper-parameter gradient.

@@ -1,17 +1,21 @@
 // The D-SKI matrix-vector product (Sec. 3.1):
 //     Y = [W; dW_1..dW_d] K_UU [W; dW_1..dW_d]^T V + D V
-// in three stages over tile-ordered vectors:
-// The Keys cubic-convolution weights of every point are precomputed at plan
-// set-up (FP64); both stages read the same table, so the operator is exactly
-// symmetric.
+// in three stages over tile-ordered vectors.  The interpolation weights (Keys
+// cubic, 4 nodes per axis, or the quintic kernel, 6 nodes per axis) are not
+// stored: every stage evaluates them from the points' cell offsets with the
+// same FMA Horner routine (interp.h), so the scatter is exactly the transpose
+// of the gather.
 //   scatter  G = S^T V      owner-computes: one thread per grid node pulls the
-//                           contributions of the points whose 4^d stencil covers
-//                           it, in a fixed order (no atomics, bitwise
+//                           contributions of the points whose S^d stencil
+//                           covers it, in a fixed order (no atomics, bitwise
 //                           reproducible), FP64 accumulation;
-//   K_UU     G <- K_UU G    per axis, per grid line: circulant-embedded Toeplitz
-//                           product by a radix-8 Stockham FFT in registers with
-//                           LDS exchanges (FP64), two real lines packed into one
-//                           complex transform;
+//   K_UU     G <- K_UU G    SE kernel: per axis, per grid line, the circulant-
+//                           embedded Toeplitz product by a radix-8 Stockham FFT
+//                           in registers with LDS exchanges (FP64), two real
+//                           lines packed into one complex transform, or a dense
+//                           Toeplitz product on the FP64 matrix cores; spline
+//                           kernel: the d-dimensional circulant embedding of
+//                           the multi-level Toeplitz K_UU (App. A);
 //   gather   Y = S G + D V  one thread per point, FP64 accumulation, FP32 store,
 //                           optional fused per-block partials of V.Y.
 #include <algorithm>
