@@ -1141,13 +1141,26 @@ __device__ __forceinline__ int fft_pos_freq(int lp, int e) {
   return lp + (e / RL) * S::TPL + (e % RL) * (S::L / RL);
 }
 
-// One complex FFT (DIR = +1 forward, -1 inverse, unnormalised) of every line of
-// length L = 2^LG along an axis: line l starts at (l / inner) L inner + l % inner
-// and steps by inner.  A forward transform reads natural order and writes
-// frequency order; an inverse one the reverse.  In place (a work-group holds
-// its lines in registers between the read and the write).
+// The lines an axis pass transforms: line l = (outer index o, inner index i)
+// with o = l / ninner over every position of the axes before the axis (and the
+// stacked arrays), i = l % ninner over a box of the axes after it, given per
+// axis (slowest first) by its count and its stride in the array.  The line
+// starts at o * outer_step + sum of digit * stride and steps by `step`; its
+// positions from `valid` on are read as zeros (the padding of the embedding,
+// which is then never stored).
+struct LineMap {
+  long long ninner, outer_step, step;
+  int nd, valid;
+  int cnt[DSKI_MAXD];
+  long long stride[DSKI_MAXD];
+};
+
+// One complex FFT (DIR = +1 forward, -1 inverse, unnormalised) of each line of
+// length L = 2^LG that `map` selects.  A forward transform reads natural order
+// and writes frequency order; an inverse one the reverse.  In place (a
+// work-group holds its lines in registers between the read and the write).
 template <int LG, int DIR>
-__global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long long nlines, long long inner,
+__global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long long nlines, LineMap map,
                                                   const double2* __restrict__ tw) {
   using S = FftShape<LG>;
   constexpr int E = S::E, TPL = S::TPL, L = S::L;
@@ -1164,28 +1177,37 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long 
   }
   const long long line = (long long)blockIdx.x * S::PAIRS + slot;
   const bool ok = line < nlines;
-  const long long base = ok ? (line / inner) * L * inner + line % inner : 0;
+  long long base = 0;
+  if (ok) {
+    long long rem = line % map.ninner;
+    base = (line / map.ninner) * map.outer_step;
+    for (int t = map.nd - 1; t >= 0; --t) {
+      base += (rem % map.cnt[t]) * map.stride[t];
+      rem /= map.cnt[t];
+    }
+  }
+  const long long step = map.step;
   double2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int pos = DIR > 0 ? fft_pos_nat<LG>(lp, e) : fft_pos_freq<LG>(lp, e);
-    v[e] = ok ? Z[base + (long long)pos * inner] : make_double2(0.0, 0.0);
+    v[e] = ok && pos < map.valid ? Z[base + (long long)pos * step] : make_double2(0.0, 0.0);
   }
   fft_run<LG, DIR, 0>(v, buf, stw, lp);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int pos = DIR > 0 ? fft_pos_freq<LG>(lp, e) : fft_pos_nat<LG>(lp, e);
-      Z[base + (long long)pos * inner] = v[e];
+      Z[base + (long long)pos * step] = v[e];
     }
   }
 }
 
 // Last (contiguous) axis: forward, times lambda (row o = l mod nouter of the
-// spectrum, L values), inverse.
+// spectrum, L values), inverse.  Positions from `valid` on are read as zeros.
 template <int LG>
 __global__ __launch_bounds__(256) void k_fft_last_spec(double2* __restrict__ Z, long long nlines, long long nouter,
-                                                       const double2* __restrict__ tw,
+                                                       int valid, const double2* __restrict__ tw,
                                                        const double* __restrict__ spec) {
   using S = FftShape<LG>;
   constexpr int E = S::E, TPL = S::TPL, L = S::L;
@@ -1206,7 +1228,10 @@ __global__ __launch_bounds__(256) void k_fft_last_spec(double2* __restrict__ Z, 
   const double* sp = spec + (ok ? line % nouter : 0) * L;
   double2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = ok ? A[fft_pos_nat<LG>(lp, e)] : make_double2(0.0, 0.0);
+  for (int e = 0; e < E; ++e) {
+    const int pos = fft_pos_nat<LG>(lp, e);
+    v[e] = ok && pos < valid ? A[pos] : make_double2(0.0, 0.0);
+  }
   fft_run<LG, +1, 0>(v, buf, stw, lp);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sp[fft_pos_freq<LG>(lp, e)]);
@@ -1232,24 +1257,6 @@ static BoxL box_of(dski_plan p) {
     b.h[a] = p->ax[a].h;
   }
   return b;
-}
-
-// Multi-index of embedded position j (last axis fastest); returns the node
-// index (last axis fastest) or -1 outside the m box.
-__device__ __forceinline__ long long bttb_node(long long j, const BoxL& b, int (&jj)[DSKI_MAXD]) {
-  long long rem = j, node = 0, stride = 1;
-  bool in = true;
-  for (int a = b.d - 1; a >= 0; --a) {
-    jj[a] = (int)(rem % b.L[a]);
-    rem /= b.L[a];
-    in = in && jj[a] < b.m[a];
-  }
-  if (!in) return -1;
-  for (int a = b.d - 1; a >= 0; --a) {
-    node += (long long)jj[a] * stride;
-    stride *= b.m[a];
-  }
-  return node;
 }
 
 // Spline kernel profile k(r) / s^2 (App. A; a, b as in the header: domain size R).
@@ -1285,21 +1292,29 @@ __global__ void k_bttb_spec(const double2* __restrict__ Z, long long tot, double
     spec[j] = Z[j].x * scale;
 }
 
-// Z[c2] = G[2 c2] + i G[2 c2 + 1] on the m box, zero elsewhere.
+// Embedded position (last axis fastest, L box) of grid node `node` (m box).
+__device__ __forceinline__ long long bttb_pos(long long node, const BoxL& b) {
+  long long rem = node, j = 0, stride = 1;
+  for (int a = b.d - 1; a >= 0; --a) {
+    j += (rem % b.m[a]) * stride;
+    rem /= b.m[a];
+    stride *= b.L[a];
+  }
+  return j;
+}
+
+// Z[c2] = G[2 c2] + i G[2 c2 + 1] on the m box.  The rest of the embedded
+// array is not written: the transforms read it as zeros.
 __global__ void k_bttb_pack(const double* __restrict__ G, long long M, int R, BoxL b, long long tot,
                             double2* __restrict__ Z) {
   const int c2 = blockIdx.y;
   const int ca = 2 * c2, cb = 2 * c2 + 1;
-  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < tot;
-       j += (long long)gridDim.x * blockDim.x) {
-    int jj[DSKI_MAXD];
-    const long long node = bttb_node(j, b, jj);
-    double2 v = make_double2(0.0, 0.0);
-    if (node >= 0) {
-      v.x = G[(size_t)ca * M + node];
-      if (cb < R) v.y = G[(size_t)cb * M + node];
-    }
-    Z[(size_t)c2 * tot + j] = v;
+  for (long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x; node < M;
+       node += (long long)gridDim.x * blockDim.x) {
+    double2 v;
+    v.x = G[(size_t)ca * M + node];
+    v.y = cb < R ? G[(size_t)cb * M + node] : 0.0;
+    Z[(size_t)c2 * tot + bttb_pos(node, b)] = v;
   }
 }
 
@@ -1308,19 +1323,17 @@ __global__ void k_bttb_unpack(const double2* __restrict__ Z, long long M, int R,
                               double scale, double* __restrict__ G) {
   const int c2 = blockIdx.y;
   const int ca = 2 * c2, cb = 2 * c2 + 1;
-  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < tot;
-       j += (long long)gridDim.x * blockDim.x) {
-    int jj[DSKI_MAXD];
-    const long long node = bttb_node(j, b, jj);
-    if (node < 0) continue;
-    const double2 v = Z[(size_t)c2 * tot + j];
+  for (long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x; node < M;
+       node += (long long)gridDim.x * blockDim.x) {
+    const double2 v = Z[(size_t)c2 * tot + bttb_pos(node, b)];
     G[(size_t)ca * M + node] = scale * v.x;
     if (cb < R) G[(size_t)cb * M + node] = scale * v.y;
   }
 }
 
 template <int LG, int DIR>
-static dski_status launch_fft_axis(double2* Z, long long nlines, long long inner, const double2* tw, hipStream_t st) {
+static dski_status launch_fft_axis(double2* Z, long long nlines, const LineMap& map, const double2* tw,
+                                   hipStream_t st) {
   using S = FftShape<LG>;
   const size_t sh = sizeof(double2) * ((size_t)S::PAIRS * S::LP + (S::STAGE ? S::TW : 0));
   if (sh > 64 * 1024) {
@@ -1332,13 +1345,13 @@ static dski_status launch_fft_axis(double2* Z, long long nlines, long long inner
     }
   }
   const long long blocks = (nlines + S::PAIRS - 1) / S::PAIRS;
-  k_fft_axis<LG, DIR><<<(unsigned)blocks, 256, sh, st>>>(Z, nlines, inner, tw);
+  k_fft_axis<LG, DIR><<<(unsigned)blocks, 256, sh, st>>>(Z, nlines, map, tw);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
 
 template <int LG>
-static dski_status launch_fft_last(double2* Z, long long nlines, long long nouter, const double2* tw,
+static dski_status launch_fft_last(double2* Z, long long nlines, long long nouter, int valid, const double2* tw,
                                    const double* spec, hipStream_t st) {
   using S = FftShape<LG>;
   const size_t sh = sizeof(double2) * ((size_t)S::PAIRS * S::LP + (S::STAGE ? S::TW : 0));
@@ -1351,7 +1364,7 @@ static dski_status launch_fft_last(double2* Z, long long nlines, long long noute
     }
   }
   const long long blocks = (nlines + S::PAIRS - 1) / S::PAIRS;
-  k_fft_last_spec<LG><<<(unsigned)blocks, 256, sh, st>>>(Z, nlines, nouter, tw, spec);
+  k_fft_last_spec<LG><<<(unsigned)blocks, 256, sh, st>>>(Z, nlines, nouter, valid, tw, spec);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
@@ -1362,12 +1375,12 @@ static int log2_exact(int L) {
   return lg;
 }
 
-static dski_status fft_axis(double2* Z, int L, int dir, long long nlines, long long inner, const double2* tw,
+static dski_status fft_axis(double2* Z, int L, int dir, long long nlines, const LineMap& map, const double2* tw,
                             hipStream_t st) {
 #define DSKI_FA(LGV)                                                                          \
   case LGV:                                                                                   \
-    return dir > 0 ? launch_fft_axis<LGV, +1>(Z, nlines, inner, tw, st)                       \
-                   : launch_fft_axis<LGV, -1>(Z, nlines, inner, tw, st);
+    return dir > 0 ? launch_fft_axis<LGV, +1>(Z, nlines, map, tw, st)                         \
+                   : launch_fft_axis<LGV, -1>(Z, nlines, map, tw, st);
   switch (log2_exact(L)) {
     DSKI_FA(3)
     DSKI_FA(4)
@@ -1385,18 +1398,18 @@ static dski_status fft_axis(double2* Z, int L, int dir, long long nlines, long l
 #undef DSKI_FA
 }
 
-static dski_status fft_last(double2* Z, int L, long long nlines, long long nouter, const double2* tw,
+static dski_status fft_last(double2* Z, int L, long long nlines, long long nouter, int valid, const double2* tw,
                             const double* spec, hipStream_t st) {
   switch (log2_exact(L)) {
-    case 3: return launch_fft_last<3>(Z, nlines, nouter, tw, spec, st);
-    case 4: return launch_fft_last<4>(Z, nlines, nouter, tw, spec, st);
-    case 5: return launch_fft_last<5>(Z, nlines, nouter, tw, spec, st);
-    case 6: return launch_fft_last<6>(Z, nlines, nouter, tw, spec, st);
-    case 7: return launch_fft_last<7>(Z, nlines, nouter, tw, spec, st);
-    case 8: return launch_fft_last<8>(Z, nlines, nouter, tw, spec, st);
-    case 9: return launch_fft_last<9>(Z, nlines, nouter, tw, spec, st);
-    case 10: return launch_fft_last<10>(Z, nlines, nouter, tw, spec, st);
-    case 11: return launch_fft_last<11>(Z, nlines, nouter, tw, spec, st);
+    case 3: return launch_fft_last<3>(Z, nlines, nouter, valid, tw, spec, st);
+    case 4: return launch_fft_last<4>(Z, nlines, nouter, valid, tw, spec, st);
+    case 5: return launch_fft_last<5>(Z, nlines, nouter, valid, tw, spec, st);
+    case 6: return launch_fft_last<6>(Z, nlines, nouter, valid, tw, spec, st);
+    case 7: return launch_fft_last<7>(Z, nlines, nouter, valid, tw, spec, st);
+    case 8: return launch_fft_last<8>(Z, nlines, nouter, valid, tw, spec, st);
+    case 9: return launch_fft_last<9>(Z, nlines, nouter, valid, tw, spec, st);
+    case 10: return launch_fft_last<10>(Z, nlines, nouter, valid, tw, spec, st);
+    case 11: return launch_fft_last<11>(Z, nlines, nouter, valid, tw, spec, st);
     default:
       set_error("FFT length %d not supported", L);
       return DSKI_ENOTSUP;
@@ -1407,6 +1420,36 @@ static long long bttb_total(dski_plan p) {
   long long tot = 1;
   for (int a = 0; a < p->d; ++a) tot *= p->ax[a].L;
   return tot;
+}
+
+// Lines along axis a of `stack` embedded arrays (last axis fastest): every
+// position of the axes before a, and on the axes after it either every position
+// (full) or only the first m_b (the grid box).  Restricting a forward pass so
+// skips lines that are still all zero (the box was padded with zeros and no
+// pass has touched the later axes yet: their transforms would be exact zeros);
+// restricting an inverse pass skips lines whose outputs the crop to the box
+// discards.  Either way the values the crop keeps are the same bits.
+static LineMap line_map(dski_plan p, int a, long long stack, bool box, long long* nlines) {
+  LineMap m{};
+  long long inner_full = 1;
+  for (int b = p->d - 1; b > a; --b) inner_full *= p->ax[b].L;
+  m.step = inner_full;
+  m.outer_step = inner_full * p->ax[a].L;
+  m.valid = p->ax[a].L;
+  long long outer = stack;
+  for (int b = 0; b < a; ++b) outer *= p->ax[b].L;
+  m.nd = 0;
+  m.ninner = 1;
+  long long stride = inner_full;
+  for (int b = a + 1; b < p->d; ++b) {
+    stride /= p->ax[b].L;
+    m.cnt[m.nd] = box ? p->ax[b].m : p->ax[b].L;
+    m.stride[m.nd] = stride;
+    m.ninner *= m.cnt[m.nd];
+    ++m.nd;
+  }
+  *nlines = outer * m.ninner;
+  return m;
 }
 
 // Spectrum of the spline kernel's K_UU (without s^2): lambda / prod L_p, in
@@ -1428,11 +1471,10 @@ dski_status bttb_build_spectrum(dski_plan p, hipStream_t st) {
   const unsigned nb = (unsigned)std::min<long long>(4096, (tot + 255) / 256);
   k_bttb_gen<<<nb, 256, 0, st>>>(b, p->spline_R, tot, Z);
   DSKI_HIP(hipGetLastError());
-  long long inner = 1;
   for (int a = p->d - 1; a >= 0; --a) {
-    const int L = p->ax[a].L;
-    DSKI_TRY(fft_axis(Z, L, +1, tot / L, inner, reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
-    inner *= L;
+    long long nl = 0;
+    const LineMap map = line_map(p, a, 1, false, &nl);
+    DSKI_TRY(fft_axis(Z, p->ax[a].L, +1, nl, map, reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
   }
   // the last-axis kernel expects each spectrum row in natural frequency order
   // too, so this is lambda in the layout both passes index
@@ -1450,24 +1492,28 @@ static dski_status bttb_apply(dski_plan p, int R, double* G, hipStream_t st, dou
   DSKI_TRY(p->bttb_work.reserve(sizeof(double2) * (size_t)tot * R2));
   double2* Z = p->bttb_work.as<double2>();
   BoxL b = box_of(p);
-  const unsigned nb = (unsigned)std::min<long long>(2048, (tot + 255) / 256);
+  const unsigned nb = (unsigned)std::min<long long>(2048, (p->M + 255) / 256);
   k_bttb_pack<<<dim3(nb, R2), 256, 0, st>>>(G, p->M, R, b, tot, Z);
   DSKI_HIP(hipGetLastError());
   const int d = p->d;
-  // strides of the embedded array (last axis fastest), all R2 arrays stacked
-  long long inner[DSKI_MAXD];
-  inner[d - 1] = 1;
-  for (int a = d - 2; a >= 0; --a) inner[a] = inner[a + 1] * p->ax[a + 1].L;
+  // all R2 arrays stacked; forward passes on axes 0 .. d-2 over the lines whose
+  // later axes lie in the grid box (each reading past m_a as zeros: the pack
+  // wrote only the box), inverse passes over the lines the crop keeps
   const long long lines_of = tot * R2;
-  for (int a = 0; a < d - 1; ++a)
-    DSKI_TRY(fft_axis(Z, p->ax[a].L, +1, lines_of / p->ax[a].L, inner[a],
-                      reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
+  for (int a = 0; a < d - 1; ++a) {
+    long long nl = 0;
+    LineMap map = line_map(p, a, R2, true, &nl);
+    map.valid = p->ax[a].m;
+    DSKI_TRY(fft_axis(Z, p->ax[a].L, +1, nl, map, reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
+  }
   const int Ll = p->ax[d - 1].L;
-  DSKI_TRY(fft_last(Z, Ll, lines_of / Ll, tot / Ll, reinterpret_cast<const double2*>(p->ax[d - 1].twiddle),
-                    p->bttb_spec, st));
-  for (int a = d - 2; a >= 0; --a)
-    DSKI_TRY(fft_axis(Z, p->ax[a].L, -1, lines_of / p->ax[a].L, inner[a],
-                      reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
+  DSKI_TRY(fft_last(Z, Ll, lines_of / Ll, tot / Ll, p->ax[d - 1].m,
+                    reinterpret_cast<const double2*>(p->ax[d - 1].twiddle), p->bttb_spec, st));
+  for (int a = d - 2; a >= 0; --a) {
+    long long nl = 0;
+    const LineMap map = line_map(p, a, R2, true, &nl);
+    DSKI_TRY(fft_axis(Z, p->ax[a].L, -1, nl, map, reinterpret_cast<const double2*>(p->ax[a].twiddle), st));
+  }
   k_bttb_unpack<<<dim3(nb, R2), 256, 0, st>>>(Z, p->M, R, b, tot, scale, G);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
