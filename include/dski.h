@@ -60,7 +60,7 @@ typedef enum {
   DSKI_ENOMEM = -2,            /* device allocation failed                         */
   DSKI_EHIP = -3,              /* a HIP runtime call failed                        */
   DSKI_EBREAKDOWN = -4,        /* p^T K~ p <= 0 or r^T M^{-1} r < 0 in PCG         */
-  DSKI_ENOTSUP = -5            /* configuration not supported by this build        */
+  DSKI_ENOTSUP = -5            /* configuration the library does not support       */
 } dski_status;
 
 typedef struct dski_plan_s* dski_plan;       /* points, grid, tile order, spectra  */

@@ -715,7 +715,7 @@ static dski_status build_entry(const char* who, dski_plan p, int k, dski_precond
     return DSKI_EINVAL;
   }
   if (k > 256) {
-    set_error("%s: rank %d too large for this build (max 256)", who, k);
+    set_error("%s: rank %d too large (at most 256)", who, k);
     return DSKI_ENOTSUP;
   }
   *out = nullptr;
