@@ -117,3 +117,39 @@ def test_spline_predict_matches_oracle():
     e = np.abs(mu - ref).max() / np.abs(ref).max()
     say("  mean rel err", e)
     assert e < 1e-10
+
+
+def test_spline_full_torus_sampled_rows():
+    """The full torus (n = 30,000 on 48^3, the 128^3 embedding with the pruned
+    axis passes): sampled rows of the FP64 MVM, each computed one by one from
+    the oracle's interpolation matrix and the kernel function (the row's
+    stencil nodes against every grid node), value and derivative rows."""
+    from oracle import interp
+    dski = need_gpu()
+    W = workloads.torus()
+    say("spline full torus", W.n, W.grid_m)
+    plan = dski.Plan(torch.tensor(W.X, device="cuda"), W.grid_m, W.lo, W.hi, kernel="spline")
+    plan.set_hypers(*W.hypers())
+    r = np.random.default_rng(11)
+    N = W.n * 4
+    V = r.standard_normal((N, 2))
+    Y = plan.mvm(torch.tensor(V.T.copy(), device="cuda")).cpu().numpy().T
+    grid = interp.Grid(W.lo, W.hi, W.grid_m, "cubic")
+    S = interp.interp_matrices(W.X, grid)
+    G = S.T @ V
+    nodes = np.stack(np.meshgrid(*[grid.nodes(p) for p in range(3)], indexing="ij"), -1).reshape(-1, 3)
+    R = spline.grid_domain_size(grid)
+    s2 = np.exp(2 * W.log_s)
+    rows = np.concatenate([r.choice(W.n, 5, replace=False), W.n + r.choice(3 * W.n, 7, replace=False)])
+    worst = 0.0
+    for i in rows:
+        idx = S.indices[S.indptr[i]:S.indptr[i + 1]]
+        w = S.data[S.indptr[i]:S.indptr[i + 1]]
+        dist = np.linalg.norm(nodes[idx][:, None, :] - nodes[None, :, :], axis=-1)
+        ref = s2 * (w @ (spline.spline_k(dist, 3, R) @ G))
+        ref += (np.exp(2 * W.log_sigma_f) if i < W.n else np.exp(2 * W.log_sigma_g)) * V[i]
+        err = np.abs(Y[i] - ref).max() / np.abs(Y).max(axis=0).max()
+        worst = max(worst, err)
+    say("  sampled rows, worst error relative to max |Y|", worst)
+    assert worst < 1e-10  # the element-wise FP64 bar of the small cases
+    plan.close()
