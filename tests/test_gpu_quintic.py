@@ -3,9 +3,9 @@ the FP64 oracle: the D-SKI MVM in 1-D, 2-D and 3-D (FP32 storage to 1e-5 as a
 2-norm and element-wise, FP64 storage to 1e-12 as a 2-norm and element-wise,
 1e-11 element-wise in 3-D), its hyper-parameter
 derivatives, every scatter and gather variant giving the same bits, the
-pivoted Cholesky and block PCG to an oracle true residual of 1e-4, and the
-posterior mean at test points; also the plan's refusal of a grid narrower than
-the stencil."""
+pivoted Cholesky and block PCG to an oracle true residual of 1e-4 (also at the
+full terrain size), and the posterior mean at test points; also the plan's
+refusal of a grid narrower than the stencil."""
 import numpy as np
 import pytest
 import torch
@@ -115,3 +115,25 @@ def test_quintic_plan_needs_six_nodes_per_axis():
     with pytest.raises(ValueError):
         dski.Plan(X, [8, 8], [0, 0], [1, 1], interp="septic")
     dski.Plan(X, [6, 6], [0, 0], [1, 1], interp="quintic")
+
+
+def test_quintic_full_terrain_mvm_and_pcg():
+    """The terrain configuration with quintic weights (n = 20,000, 200^2, 17
+    columns, rank 50, FP32 vectors): the MVM against the oracle (1e-5 as a
+    2-norm and element-wise), and the block PCG to 1e-4 with every column's
+    true residual by the oracle's FP64 operator."""
+    W = workloads.terrain()
+    say("quintic full terrain", W.n, W.grid_m)
+    plan, op = make(W, interp="quintic")
+    B = np.concatenate([W.y[:, None], orng.rademacher(SEED, 0, 16, op.N)], axis=1)
+    B = B.astype(np.float32).astype(np.float64)
+    e2, emax = mvm_errors(from_gpu(plan.mvm(to_gpu(B))), op.matvec(B))
+    say("  MVM", e2, emax)
+    assert e2 < 1e-5 and emax < 1e-5
+    pc = plan.pivchol(W.rank)
+    X, iters, relres, st, _ = plan.pcg(to_gpu(B), pc, tol=W.tol, max_iter=20000)
+    tr = krylov.true_relres(op.matvec, B, from_gpu(X))
+    say("  iters", max(iters), "oracle true relres", tr.max())
+    assert st == 0 and tr.max() <= 1e-4
+    pc.close()
+    plan.close()
