@@ -7,12 +7,16 @@
 //   da2_j = W2 dh1_j, dh2_j = gelu'(a2) da2_j, dy_j = w3 . dh2_j
 //   loss = (1/B) sum_b [(y_b - t_b)^2 + lam sum_j (dy_bj - g_bj)^2]
 //
-// Per-sample kernel: one work-group of H threads per sample (thread = hidden
-// unit), activations and tangents in LDS, W2 read column-major for W2 v and
-// row-major for W2^T v (both copies kept) so that every load is coalesced.
-// Weight gradients are products over the batch (K = (1 + J) B rows), split over
-// K chunks with FP64 partials summed in a fixed order: deterministic.
-// Adam (Kingma & Ba) updates the packed parameters in place.
+// The batch is laid out as K = (1 + J) B rows of H values: the value rows of
+// the B samples, then their tangent rows along input 0, 1, .., J - 1.  Layer 1
+// and the GELU factors are elementwise kernels; the three products with the
+// H x H matrix W2 run on the FP32 matrix cores (v_mfma_f32_16x16x4f32): the
+// layer-2 pre-activations of all K rows (rows x W2^T), the layer-1 deltas of
+// all K rows (rows x W2), and the weight gradient D2^T S1 contracted over the
+// K rows in chunks.  Per-sample reductions over the hidden units (y, dy_j) use
+// one work-group per sample.  The chunks of every batch contraction are added
+// in FP64 in a fixed order: deterministic.  Adam (Kingma & Ba) updates the
+// packed parameters in place.
 #include <cmath>
 #include <vector>
 
@@ -22,7 +26,6 @@ struct dski_mlp_s {
   int F = 8, H = 128, J = 5, maxB = 0;
   int np = 0;                 // packed parameters
   float* params = nullptr;    // W1 (H x F), b1 (H), W2 (H x H), b2 (H), w3 (H), b3 (1), row-major
-  float* W2c = nullptr;       // W2 column-major copy
   float* grad = nullptr;      // packed gradient of the last mlp_backward
   float* m = nullptr;         // Adam moments
   float* v = nullptr;
@@ -71,61 +74,102 @@ __device__ __forceinline__ float block_sum128(float v, float* red) {
   return s;
 }
 
-// Per-sample layout of the saved rows (each row H floats), (1 + J) B rows per group:
-//   S1 = [h1; dh1_1..J], D2 = [da2; dda2_1..J], S2 = [h2; dh2_1..J], D1 = [da1; dda1_1..J]
-// row index of (j, b) = j * B + b.  E = [ey; eg_1..J] ((1 + J) B scalars).
+// Saved rows (each H floats), row index of (j, b) = j * B + b, (1 + J) B rows:
+//   S1 = [h1; dh1_1..J], C = layer-2 pre-activations (then the layer-1 deltas),
+//   D2 = [da2; dda2_1..J], S2 = [h2; dh2_1..J], D1 = [da1; dda1_1..J];
+// A1 = a1 of the B samples; E = [ey; eg_1..J] ((1 + J) B scalars).
 struct MlpWork {
-  float *S1, *D2, *S2, *D1, *E;
+  float *S1, *C, *D2, *S2, *D1, *A1, *E;
   double* part;
   size_t rows;  // (1 + J) B
 };
 
-// mode 0: y (and dy if dy != NULL); mode 1: also the deltas of the loss.
-__global__ __launch_bounds__(128) void k_mlp_sample(const float* __restrict__ P, const float* __restrict__ W2c,
-                                                    int F, int H, int J, MlpOff o, int B,
-                                                    const float* __restrict__ X, const float* __restrict__ tv,
-                                                    const float* __restrict__ tg, float lam, int mode,
-                                                    float* __restrict__ y_out, float* __restrict__ dy_out,
-                                                    MlpWork w, double* __restrict__ loss_part) {
-  __shared__ float sx[kMlpMaxF];
-  __shared__ float sh1[kMlpMaxJ + 1][kMlpMaxH];
-  __shared__ float sd2[kMlpMaxJ + 1][kMlpMaxH];
+typedef float mlp_flt4 __attribute__((ext_vector_type(4)));
+
+// Layer 1, one thread per (sample b, unit i): a1 = W1 x + b1, h1 = gelu(a1),
+// tangent rows dh1_j = gelu'(a1) W1[i][j] (j < J).
+__global__ void k_mlp_l1(const float* __restrict__ P, int F, int H, int J, MlpOff o, int B,
+                         const float* __restrict__ X, MlpWork w) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (long long)B * H) return;
+  const int b = (int)(f / H), i = (int)(f % H);
+  float a1 = P[o.b1 + i];
+  for (int j = 0; j < F; ++j) a1 += P[o.W1 + i * F + j] * X[(size_t)b * F + j];
+  w.A1[f] = a1;
+  w.S1[f] = gelu_f(a1);
+  const float g1 = gelu_d1f(a1);
+  for (int j = 0; j < J; ++j) w.S1[((size_t)(j + 1) * B + b) * H + i] = g1 * P[o.W1 + i * F + j];
+}
+
+// C (M x H) = A (M x H) times Bv (H x H), Bv[k][c] = W[c][k] (TB) or W[k][c], on the
+// FP32 matrix cores (D += A B, A 16 x 4 and B 4 x 16: lane l holds A[l%16][l/16]
+// and B[l/16][l%16], register q of lane l holds D[4(l/16) + q][l%16]).  A
+// work-group stages Bv (zero-padded to 128 x 128) in LDS; each wavefront takes
+// 16 rows, loads its 16 x 128 operand block into registers at once and runs
+// 32 k-steps over the 8 column blocks.  Accumulation in FP32 over the H terms
+// of each dot product, as in a vector-ALU loop.
+template <bool TB>
+__global__ __launch_bounds__(256) void k_mlp_mm(const float* __restrict__ A, long long M, const float* __restrict__ W,
+                                                int H, float* __restrict__ C) {
+  __shared__ float sB[128 * 128];
+  for (int f = threadIdx.x; f < 128 * 128; f += 256) {
+    const int k = f >> 7, c = f & 127;
+    sB[f] = k < H && c < H ? (TB ? W[c * H + k] : W[k * H + c]) : 0.f;
+  }
+  const int lane = threadIdx.x & 63;
+  const long long r0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const long long row = r0 + (lane & 15);
+  const int kq = lane >> 4;
+  float aop[32];
+#pragma unroll
+  for (int s4 = 0; s4 < 32; ++s4) {
+    const int k = 4 * s4 + kq;
+    aop[s4] = row < M && k < H ? A[row * H + k] : 0.f;
+  }
+  __syncthreads();
+  mlp_flt4 acc[8];
+#pragma unroll
+  for (int cb = 0; cb < 8; ++cb) acc[cb] = mlp_flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s4 = 0; s4 < 32; ++s4) {
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb)
+      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s4], sB[(4 * s4 + kq) * 128 + 16 * cb + (lane & 15)],
+                                                     acc[cb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 8; ++cb) {
+    const int c = 16 * cb + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long r = r0 + 4 * kq + q;
+      if (r < M && c < H) C[r * H + c] = acc[cb][q];
+    }
+  }
+}
+
+// Per sample (one work-group of 128 threads, thread = layer-2 unit): a2 = C + b2,
+// h2 = gelu(a2), tangents dh2_j = gelu'(a2) C_j, y = w3 . h2 + b3, dy_j = w3 .
+// dh2_j; mode 1 also the loss deltas and the layer-2 deltas
+// da2 = ey w3 gelu'(a2) + sum_j eg_j w3 gelu''(a2) da2_j, dda2_j = eg_j w3 gelu'(a2).
+__global__ __launch_bounds__(128) void k_mlp_l2(const float* __restrict__ P, int H, int J, MlpOff o, int B,
+                                                const float* __restrict__ tv, const float* __restrict__ tg,
+                                                float lam, int mode, float* __restrict__ y_out,
+                                                float* __restrict__ dy_out, MlpWork w,
+                                                double* __restrict__ loss_part) {
   __shared__ float red[2];
   const int b = blockIdx.x;
   const int i = threadIdx.x;
-  if (i < F) sx[i] = X[(size_t)b * F + i];
-  __syncthreads();
   const bool u = i < H;
-  // layer 1 (thread i = unit i)
-  float a1 = 0.f, g1 = 0.f, g1d = 0.f;
-  float ta1[kMlpMaxJ];
-  if (u) {
-    a1 = P[o.b1 + i];
-    for (int j = 0; j < F; ++j) a1 += P[o.W1 + i * F + j] * sx[j];
-    g1 = gelu_d1f(a1);
-    g1d = gelu_d2f(a1);
-    sh1[0][i] = gelu_f(a1);
-#pragma unroll
-    for (int j = 0; j < kMlpMaxJ; ++j) {
-      ta1[j] = j < J ? P[o.W1 + i * F + j] : 0.f;
-      if (j < J) sh1[j + 1][i] = g1 * ta1[j];
-    }
-  }
-  __syncthreads();
-  // layer 2: a2_i = sum_l W2[i, l] h1_l (column-major copy: coalesced over i)
   float a2 = 0.f, g2 = 0.f, g2d = 0.f, h2 = 0.f;
   float ta2[kMlpMaxJ], th2[kMlpMaxJ];
 #pragma unroll
   for (int j = 0; j < kMlpMaxJ; ++j) ta2[j] = 0.f;
   if (u) {
-    a2 = P[o.b2 + i];
-    for (int l = 0; l < H; ++l) {
-      const float wv = W2c[l * H + i];
-      a2 += wv * sh1[0][l];
+    a2 = w.C[(size_t)b * H + i] + P[o.b2 + i];
 #pragma unroll
-      for (int j = 0; j < kMlpMaxJ; ++j)
-        if (j < J) ta2[j] += wv * sh1[j + 1][l];
-    }
+    for (int j = 0; j < kMlpMaxJ; ++j)
+      if (j < J) ta2[j] = w.C[((size_t)(j + 1) * B + b) * H + i];
     g2 = gelu_d1f(a2);
     g2d = gelu_d2f(a2);
     h2 = gelu_f(a2);
@@ -143,7 +187,6 @@ __global__ __launch_bounds__(128) void k_mlp_sample(const float* __restrict__ P,
       for (int j = 0; j < J; ++j) dy_out[(size_t)b * J + j] = dy[j];
   }
   if (mode == 0) return;
-  // loss deltas
   const float ey = 2.0f * (y - tv[b]) / (float)B;
   float eg[kMlpMaxJ];
   double lpart = (double)(y - tv[b]) * (double)(y - tv[b]);
@@ -156,51 +199,82 @@ __global__ __launch_bounds__(128) void k_mlp_sample(const float* __restrict__ P,
       lpart += (double)lam * (double)dd * (double)dd;
     }
   }
-  const size_t rows = w.rows;
   if (i == 0) {
     loss_part[b] = lpart;
     w.E[b] = ey;
     for (int j = 0; j < J; ++j) w.E[(size_t)(j + 1) * B + b] = eg[j];
   }
   if (u) {
-    w.S1[(size_t)b * H + i] = sh1[0][i];
     w.S2[(size_t)b * H + i] = h2;
     float da2 = ey * w3i * g2;
     for (int j = 0; j < J; ++j) {
       const float ddh2 = eg[j] * w3i;
       da2 += ddh2 * g2d * ta2[j];
-      const float dda2 = ddh2 * g2;
-      sd2[j + 1][i] = dda2;
-      w.S1[((size_t)(j + 1) * B + b) * H + i] = sh1[j + 1][i];
       w.S2[((size_t)(j + 1) * B + b) * H + i] = th2[j];
-      w.D2[((size_t)(j + 1) * B + b) * H + i] = dda2;
+      w.D2[((size_t)(j + 1) * B + b) * H + i] = ddh2 * g2;
     }
-    sd2[0][i] = da2;
     w.D2[(size_t)b * H + i] = da2;
   }
-  __syncthreads();
-  // layer 1 deltas: dh1_l = sum_i W2[i, l] da2_i (row-major: coalesced over l)
-  if (u) {
-    const int l = i;
-    float dh1 = 0.f;
-    float ddh1[kMlpMaxJ];
-#pragma unroll
-    for (int j = 0; j < kMlpMaxJ; ++j) ddh1[j] = 0.f;
-    for (int r = 0; r < H; ++r) {
-      const float wv = P[o.W2 + r * H + l];
-      dh1 += wv * sd2[0][r];
-#pragma unroll
-      for (int j = 0; j < kMlpMaxJ; ++j)
-        if (j < J) ddh1[j] += wv * sd2[j + 1][r];
-    }
-    float da1 = dh1 * g1;
-    for (int j = 0; j < J; ++j) {
-      da1 += ddh1[j] * g1d * ta1[j];
-      w.D1[((size_t)(j + 1) * B + b) * H + l] = ddh1[j] * g1;
-    }
-    w.D1[(size_t)b * H + l] = da1;
+}
+
+// Layer-1 deltas from the products C = D2 W2 (one thread per (sample, unit)):
+// da1 = dh1 gelu'(a1) + sum_j ddh1_j gelu''(a1) W1[l][j], dda1_j = ddh1_j gelu'(a1).
+__global__ void k_mlp_d1(const float* __restrict__ P, int F, int H, int J, MlpOff o, int B, MlpWork w) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (long long)B * H) return;
+  const int b = (int)(f / H), l = (int)(f % H);
+  const float a1 = w.A1[f];
+  const float g1 = gelu_d1f(a1), g1d = gelu_d2f(a1);
+  float da1 = w.C[f] * g1;
+  for (int j = 0; j < J; ++j) {
+    const size_t r = ((size_t)(j + 1) * B + b) * H + l;
+    const float ddh1 = w.C[r];
+    da1 += ddh1 * g1d * P[o.W1 + l * F + j];
+    w.D1[r] = ddh1 * g1;
   }
-  (void)rows;
+  w.D1[f] = da1;
+}
+
+// Chunk partials of dW2 = D2^T S1 (H x H, contracting over the K rows) on the
+// FP32 matrix cores: work-group c takes rows [c chunk, (c + 1) chunk) four at a
+// time; its four wavefronts take the four 64 x 64 quadrants of the product
+// (A[m][kk] = D2[r + kk][16 h + m], B[kk][n] = S1[r + kk][16 g + n]).  Each
+// chunk's tile is written in FP64: part[(c H + i) H + l].
+__global__ __launch_bounds__(256) void k_mlp_gram(const float* __restrict__ D2, const float* __restrict__ S1,
+                                                  long long K, int H, long long chunk, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int h0 = (wv >> 1) * 4, g0 = (wv & 1) * 4;
+  const long long k0 = (long long)blockIdx.x * chunk, k1 = k0 + chunk < K ? k0 + chunk : K;
+  const int kq = lane >> 4, m = lane & 15;
+  mlp_flt4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = mlp_flt4{0.f, 0.f, 0.f, 0.f};
+  for (long long r = k0; r < k1; r += 4) {
+    const long long rr = r + kq;
+    const bool ok = rr < k1;
+    float av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int ci = 16 * (h0 + a) + m, cl = 16 * (g0 + a) + m;
+      av[a] = ok && ci < H ? D2[rr * H + ci] : 0.f;
+      bv[a] = ok && cl < H ? S1[rr * H + cl] : 0.f;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[c], acc[a][c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * (h0 + a) + 4 * kq + q, l = 16 * (g0 + c) + m;
+        if (i < H && l < H) part[((size_t)blockIdx.x * H + i) * H + l] = (double)acc[a][c][q];
+      }
 }
 
 // partial[c][i][l] = sum over k in chunk c of A[k][i] * Bm[k][l]  (FP64), rows k of
@@ -255,6 +329,36 @@ __global__ __launch_bounds__(1024) void k_mlp_colsum(const float* __restrict__ M
   }
 }
 
+// The small gradients in one work-group: W1 = its chunk partials plus the
+// tangent column sums (dW1[i][j] += sum_b dda1_j[b][i], j < J), b1 and b2 from the
+// column sums of the value rows of D1 and D2, b3 = sum_b ey_b (FP64, fixed order).
+__global__ __launch_bounds__(256) void k_mlp_small_grads(const double* __restrict__ pW1, int nchunk, int H, int F,
+                                                         int J, const double* __restrict__ cs,
+                                                         const double* __restrict__ cs2, const float* __restrict__ E,
+                                                         int B, MlpOff o, float* __restrict__ grad) {
+  __shared__ double red[256];
+  for (int f = threadIdx.x; f < H * F; f += 256) {
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += pW1[(size_t)c * H * F + f];
+    const int i = f / F, j = f % F;
+    if (j < J) v += cs[(size_t)(j + 1) * H + i];
+    grad[o.W1 + f] = (float)v;
+  }
+  for (int i = threadIdx.x; i < H; i += 256) {
+    grad[o.b1 + i] = (float)cs[i];
+    grad[o.b2 + i] = (float)cs2[i];
+  }
+  double e = 0.0;
+  for (int b = threadIdx.x; b < B; b += 256) e += (double)E[b];
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[o.b3] = (float)red[0];
+}
+
 __global__ void k_mlp_loss(const double* __restrict__ lp, int B, double* __restrict__ out) {
   __shared__ double red[256];
   double s = 0.0;
@@ -266,13 +370,6 @@ __global__ void k_mlp_loss(const double* __restrict__ lp, int B, double* __restr
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0] / (double)B;
-}
-
-__global__ void k_mlp_transpose(const float* __restrict__ W, int H, float* __restrict__ Wc) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= H * H) return;
-  const int r = f / H, c = f % H;
-  Wc[c * H + r] = W[f];
 }
 
 __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ m,
@@ -287,20 +384,24 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
   P[f] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
+constexpr int kMlpChunks = 16;      // chunks of the small batch contractions (dW1, dw3)
+constexpr int kMlpGramChunks = 64;  // chunks of dW2 = D2^T S1
+
 static dski_status mlp_reserve(dski_mlp net, int B, MlpWork& w) {
   const int H = net->H, J = net->J;
   const size_t rows = (size_t)(1 + J) * B;
-  const size_t fl = 4 * rows * H + rows + 64;
-  const int nchunk = 16;
-  const size_t parts = (size_t)nchunk * ((size_t)H * H + (size_t)H * net->F + H) + (size_t)(J + 2) * H +
-                       (size_t)H * net->F + B + 64;
+  const size_t fl = 5 * rows * H + (size_t)B * H + rows + 64;
+  const size_t parts = (size_t)kMlpGramChunks * H * H + (size_t)kMlpChunks * ((size_t)H * net->F + H) +
+                       (size_t)(J + 2) * H + B + 64;
   DSKI_TRY(net->work.reserve(sizeof(float) * fl + sizeof(double) * parts + 256));
   float* base = net->work.as<float>();
   w.S1 = base;
-  w.D2 = w.S1 + rows * H;
+  w.C = w.S1 + rows * H;
+  w.D2 = w.C + rows * H;
   w.S2 = w.D2 + rows * H;
   w.D1 = w.S2 + rows * H;
-  w.E = w.D1 + rows * H;
+  w.A1 = w.D1 + rows * H;
+  w.E = w.A1 + (size_t)B * H;
   size_t off = ((sizeof(float) * fl) + 63) / 64 * 64;
   w.part = reinterpret_cast<double*>(net->work.as<char>() + off);
   w.rows = rows;
@@ -330,7 +431,6 @@ dski_status mlp_create(dski_mlp* out, int F, int H, int J, const float* params_h
   auto fail = [&](const char* what) {
     set_error("mlp_create: %s", what);
     (void)hipFree(net->params);
-    (void)hipFree(net->W2c);
     (void)hipFree(net->grad);
     (void)hipFree(net->m);
     (void)hipFree(net->v);
@@ -338,7 +438,6 @@ dski_status mlp_create(dski_mlp* out, int F, int H, int J, const float* params_h
     return DSKI_EHIP;
   };
   if (hipMalloc(&net->params, sizeof(float) * o.n) != hipSuccess ||
-      hipMalloc(&net->W2c, sizeof(float) * H * H) != hipSuccess ||
       hipMalloc(&net->grad, sizeof(float) * o.n) != hipSuccess ||
       hipMalloc(&net->m, sizeof(float) * o.n) != hipSuccess || hipMalloc(&net->v, sizeof(float) * o.n) != hipSuccess)
     return fail("allocation failed");
@@ -347,8 +446,7 @@ dski_status mlp_create(dski_mlp* out, int F, int H, int J, const float* params_h
       hipMemsetAsync(net->v, 0, sizeof(float) * o.n, st) != hipSuccess ||
       hipMemsetAsync(net->grad, 0, sizeof(float) * o.n, st) != hipSuccess)
     return fail("upload failed");
-  k_mlp_transpose<<<(H * H + 255) / 256, 256, 0, st>>>(net->params + o.W2, H, net->W2c);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return fail("transpose failed");
+  if (hipStreamSynchronize(st) != hipSuccess) return fail("upload failed");
   *out = net;
   return DSKI_OK;
 }
@@ -356,7 +454,6 @@ dski_status mlp_create(dski_mlp* out, int F, int H, int J, const float* params_h
 dski_status mlp_destroy(dski_mlp net) {
   if (!net) return DSKI_OK;
   (void)hipFree(net->params);
-  (void)hipFree(net->W2c);
   (void)hipFree(net->grad);
   (void)hipFree(net->m);
   (void)hipFree(net->v);
@@ -391,10 +488,16 @@ static dski_status mlp_eval(dski_mlp net, int B, const float* X, float* y, float
     return DSKI_EINVAL;
   }
   if (B == 0) return DSKI_OK;
-  MlpOff o = mlp_off(net->F, net->H);
-  MlpWork w{};
-  k_mlp_sample<<<B, 128, 0, st>>>(net->params, net->W2c, net->F, net->H, dy ? net->J : 0, o, B, X, nullptr,
-                                  nullptr, 0.f, 0, y, dy, w, nullptr);
+  const int F = net->F, H = net->H, J = dy ? net->J : 0;
+  MlpOff o = mlp_off(F, H);
+  MlpWork w;
+  DSKI_TRY(mlp_reserve(net, B, w));
+  w.rows = (size_t)(1 + J) * B;
+  const long long BH = (long long)B * H;
+  k_mlp_l1<<<(unsigned)((BH + 255) / 256), 256, 0, st>>>(net->params, F, H, J, o, B, X, w);
+  k_mlp_mm<true><<<(unsigned)((w.rows + 63) / 64), 256, 0, st>>>(w.S1, (long long)w.rows, net->params + o.W2, H,
+                                                                 w.C);
+  k_mlp_l2<<<B, 128, 0, st>>>(net->params, H, J, o, B, nullptr, nullptr, 0.f, 0, y, dy, w, nullptr);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
@@ -422,21 +525,30 @@ dski_status mlp_backward(dski_mlp net, int B, const float* X, const float* t, co
   MlpOff o = mlp_off(F, H);
   MlpWork w;
   DSKI_TRY(mlp_reserve(net, B, w));
-  const int nchunk = 16;
-  double* pW2 = w.part;                                // nchunk x H x H
-  double* pW1 = pW2 + (size_t)nchunk * H * H;          // nchunk x H x F
+  const int nchunk = kMlpChunks;
+  double* pW2 = w.part;                                // kMlpGramChunks x H x H
+  double* pW1 = pW2 + (size_t)kMlpGramChunks * H * H;  // nchunk x H x F
   double* pw3 = pW1 + (size_t)nchunk * H * F;          // nchunk x 1 x H
   double* cs = pw3 + (size_t)nchunk * H;               // column sums of D1 row groups: (J+1) x H
   double* cs2 = cs + (size_t)(J + 1) * H;              // column sums of D2 rows 0..B-1: H
-  double* dadd = cs2 + H;                              // tangent columns of dW1: H x F
-  double* lp = dadd + (size_t)H * F;                   // B loss partials
+  double* lp = cs2 + H;                                // B loss partials
   double* lsum = lp + B;
-  k_mlp_sample<<<B, 128, 0, st>>>(net->params, net->W2c, F, H, J, o, B, X, t, g, lam, 1, nullptr, nullptr, w, lp);
-  DSKI_HIP(hipGetLastError());
   const size_t K = (size_t)(1 + J) * B;
+  const long long BH = (long long)B * H;
+  const unsigned mmb = (unsigned)((K + 63) / 64);
+  // forward: layer 1, layer-2 pre-activations of all K rows (matrix cores), layer 2,
+  // loss and layer-2 deltas
+  k_mlp_l1<<<(unsigned)((BH + 255) / 256), 256, 0, st>>>(net->params, F, H, J, o, B, X, w);
+  k_mlp_mm<true><<<mmb, 256, 0, st>>>(w.S1, (long long)K, net->params + o.W2, H, w.C);
+  k_mlp_l2<<<B, 128, 0, st>>>(net->params, H, J, o, B, t, g, lam, 1, nullptr, nullptr, w, lp);
+  // layer-1 deltas: C = D2 W2 (matrix cores), then the GELU factors
+  k_mlp_mm<false><<<mmb, 256, 0, st>>>(w.D2, (long long)K, net->params + o.W2, H, w.C);
+  k_mlp_d1<<<(unsigned)((BH + 255) / 256), 256, 0, st>>>(net->params, F, H, J, o, B, w);
+  DSKI_HIP(hipGetLastError());
   const size_t ch = (K + nchunk - 1) / nchunk;
-  // dW2 = D2^T S1
-  k_mlp_gemm_tn<<<dim3(H, nchunk), 128, 0, st>>>(w.D2, H, w.S1, H, K, H, H, ch, pW2);
+  // dW2 = D2^T S1 (matrix cores, FP64 chunk partials)
+  const long long gch = (((long long)K + kMlpGramChunks - 1) / kMlpGramChunks + 3) / 4 * 4;
+  k_mlp_gram<<<kMlpGramChunks, 256, 0, st>>>(w.D2, w.S1, (long long)K, H, gch, pW2);
   // dw3 = E^T S2
   k_mlp_gemm_tn<<<dim3(1, nchunk), 128, 0, st>>>(w.E, 1, w.S2, H, K, 1, H, ch, pw3);
   // dW1 = D1[0:B]^T X  (value rows only); tangent rows add their column sums below
@@ -446,38 +558,12 @@ dski_status mlp_backward(dski_mlp net, int B, const float* X, const float* t, co
   k_mlp_colsum<<<J + 1, cst, 0, st>>>(w.D1, B, H, cs);
   k_mlp_colsum<<<1, cst, 0, st>>>(w.D2, B, H, cs2);
   k_mlp_loss<<<1, 256, 0, st>>>(lp, B, lsum);
+  k_mlp_sum_chunks<<<(H * H + 255) / 256, 256, 0, st>>>(pW2, kMlpGramChunks, H * H, net->grad + o.W2, nullptr);
+  k_mlp_sum_chunks<<<(H + 255) / 256, 256, 0, st>>>(pw3, nchunk, H, net->grad + o.w3, nullptr);
+  k_mlp_small_grads<<<1, 256, 0, st>>>(pW1, nchunk, H, F, J, cs, cs2, w.E, B, o, net->grad);
   DSKI_HIP(hipGetLastError());
-  // assemble the packed gradient (FP32)
-  std::vector<double> hcs((size_t)(J + 1) * H), hcs2(H);
-  DSKI_HIP(hipMemcpyAsync(hcs.data(), cs, sizeof(double) * hcs.size(), hipMemcpyDeviceToHost, st));
-  DSKI_HIP(hipMemcpyAsync(hcs2.data(), cs2, sizeof(double) * H, hipMemcpyDeviceToHost, st));
   double hloss = 0.0;
   DSKI_HIP(hipMemcpyAsync(&hloss, lsum, sizeof(double), hipMemcpyDeviceToHost, st));
-  DSKI_HIP(hipStreamSynchronize(st));
-  // W1 tangent columns: dW1[i][j] += sum_b dda1_j[b][i]  (j < J); b1 = column sums of da1
-  std::vector<double> addW1((size_t)H * F, 0.0);
-  for (int i = 0; i < H; ++i)
-    for (int j = 0; j < J; ++j) addW1[(size_t)i * F + j] = hcs[(size_t)(j + 1) * H + i];
-  DSKI_HIP(hipMemcpyAsync(dadd, addW1.data(), sizeof(double) * H * F, hipMemcpyHostToDevice, st));
-  k_mlp_sum_chunks<<<(H * F + 255) / 256, 256, 0, st>>>(pW1, nchunk, H * F, net->grad + o.W1, dadd);
-  k_mlp_sum_chunks<<<(H * H + 255) / 256, 256, 0, st>>>(pW2, nchunk, H * H, net->grad + o.W2, nullptr);
-  k_mlp_sum_chunks<<<(H + 255) / 256, 256, 0, st>>>(pw3, nchunk, H, net->grad + o.w3, nullptr);
-  std::vector<float> hb((size_t)2 * H + 1);
-  for (int i = 0; i < H; ++i) {
-    hb[i] = (float)hcs[i];        // b1
-    hb[H + i] = (float)hcs2[i];   // b2
-  }
-  // db3 = sum_b ey_b = (2 / B) sum_b (y_b - t_b): from E row 0
-  std::vector<float> hey(B);
-  DSKI_HIP(hipMemcpyAsync(hey.data(), w.E, sizeof(float) * B, hipMemcpyDeviceToHost, st));
-  DSKI_HIP(hipStreamSynchronize(st));
-  double db3 = 0.0;
-  for (int b = 0; b < B; ++b) db3 += hey[b];
-  DSKI_HIP(hipMemcpyAsync(net->grad + o.b1, hb.data(), sizeof(float) * H, hipMemcpyHostToDevice, st));
-  DSKI_HIP(hipMemcpyAsync(net->grad + o.b2, hb.data() + H, sizeof(float) * H, hipMemcpyHostToDevice, st));
-  float fb3 = (float)db3;
-  DSKI_HIP(hipMemcpyAsync(net->grad + o.b3, &fb3, sizeof(float), hipMemcpyHostToDevice, st));
-  DSKI_HIP(hipGetLastError());
   DSKI_HIP(hipStreamSynchronize(st));
   if (loss_host) *loss_host = hloss;
   return DSKI_OK;
@@ -493,8 +579,6 @@ dski_status mlp_step(dski_mlp net, float lr, float beta1, float beta2, float eps
   const float c1 = 1.0f - powf(beta1, (float)net->t), c2 = 1.0f - powf(beta2, (float)net->t);
   k_adam<<<(net->np + 255) / 256, 256, 0, st>>>(net->params, net->grad, net->m, net->v, net->np, lr, beta1, beta2, eps,
                                                c1, c2);
-  MlpOff o = mlp_off(net->F, net->H);
-  k_mlp_transpose<<<(net->H * net->H + 255) / 256, 256, 0, st>>>(net->params + o.W2, net->H, net->W2c);
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
