@@ -603,6 +603,9 @@ def main(argv=None):
                          "(for profiled runs, whose per-dispatch overhead distorts the tuner's timings)")
     ap.add_argument("--dskip-only", action="store_true",
                     help="only the D-SKIP block of the 8-D ridge workload (build, block MVMs, block PCG)")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the surrogate block of the terrain workload (SLQ and data-fit evaluations, "
+                         "training step and inference of the network)")
     ap.add_argument("--predict-only", action="store_true",
                     help="only the prediction block of the terrain workload (grid vector, means of 1,000,000 "
                          "test points, pivoted-Cholesky and randomized variance) and the active-subspace block")
@@ -662,6 +665,9 @@ def main(argv=None):
 
     if a.dskip_only:
         print(json.dumps({"dskip": dskip_block(R, stream)}), flush=True)
+        return 0
+    if a.surrogate_only:
+        print(json.dumps({"surrogate": surrogate_block(W, y, W.rank, stream)}), flush=True)
         return 0
     if a.predict_only:
         print(json.dumps({"predict": predict_block(W, stream), "active_subspace": active_block()}), flush=True)

@@ -17,6 +17,7 @@
 // one work-group per sample.  The chunks of every batch contraction are added
 // in FP64 in a fixed order: deterministic.  Adam (Kingma & Ba) updates the
 // packed parameters in place.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -76,10 +77,11 @@ __device__ __forceinline__ float block_sum128(float v, float* red) {
 
 // Saved rows (each H floats), row index of (j, b) = j * B + b, (1 + J) B rows:
 //   S1 = [h1; dh1_1..J], C = layer-2 pre-activations (then the layer-1 deltas),
-//   D2 = [da2; dda2_1..J], S2 = [h2; dh2_1..J], D1 = [da1; dda1_1..J];
-// A1 = a1 of the B samples; E = [ey; eg_1..J] ((1 + J) B scalars).
+//   D2 = [da2; dda2_1..J], D1 = [da1; dda1_1..J];
+// per sample (B rows): A1 = a1, P3 = the w3-gradient terms; E = [ey; eg_1..J]
+// ((1 + J) B scalars).
 struct MlpWork {
-  float *S1, *C, *D2, *S2, *D1, *A1, *E;
+  float *S1, *C, *D2, *P3, *D1, *A1, *E;
   double* part;
   size_t rows;  // (1 + J) B
 };
@@ -150,8 +152,9 @@ __global__ __launch_bounds__(256) void k_mlp_mm(const float* __restrict__ A, lon
 
 // Per sample (one work-group of 128 threads, thread = layer-2 unit): a2 = C + b2,
 // h2 = gelu(a2), tangents dh2_j = gelu'(a2) C_j, y = w3 . h2 + b3, dy_j = w3 .
-// dh2_j; mode 1 also the loss deltas and the layer-2 deltas
-// da2 = ey w3 gelu'(a2) + sum_j eg_j w3 gelu''(a2) da2_j, dda2_j = eg_j w3 gelu'(a2).
+// dh2_j; mode 1 also the loss deltas, the layer-2 deltas
+// da2 = ey w3 gelu'(a2) + sum_j eg_j w3 gelu''(a2) da2_j, dda2_j = eg_j w3 gelu'(a2),
+// and the sample's share of the w3 gradient, ey h2 + sum_j eg_j dh2_j (row b of P3).
 __global__ __launch_bounds__(128) void k_mlp_l2(const float* __restrict__ P, int H, int J, MlpOff o, int B,
                                                 const float* __restrict__ tv, const float* __restrict__ tg,
                                                 float lam, int mode, float* __restrict__ y_out,
@@ -205,15 +208,16 @@ __global__ __launch_bounds__(128) void k_mlp_l2(const float* __restrict__ P, int
     for (int j = 0; j < J; ++j) w.E[(size_t)(j + 1) * B + b] = eg[j];
   }
   if (u) {
-    w.S2[(size_t)b * H + i] = h2;
+    float p3 = ey * h2;
     float da2 = ey * w3i * g2;
     for (int j = 0; j < J; ++j) {
       const float ddh2 = eg[j] * w3i;
       da2 += ddh2 * g2d * ta2[j];
-      w.S2[((size_t)(j + 1) * B + b) * H + i] = th2[j];
+      p3 += eg[j] * th2[j];
       w.D2[((size_t)(j + 1) * B + b) * H + i] = ddh2 * g2;
     }
     w.D2[(size_t)b * H + i] = da2;
+    w.P3[(size_t)b * H + i] = p3;
   }
 }
 
@@ -277,23 +281,34 @@ __global__ __launch_bounds__(256) void k_mlp_gram(const float* __restrict__ D2, 
       }
 }
 
-// partial[c][i][l] = sum over k in chunk c of A[k][i] * Bm[k][l]  (FP64), rows k of
-// A have lda floats, rows of Bm ldb floats; grid (M, nchunk), block ncols threads.
-__global__ void k_mlp_gemm_tn(const float* __restrict__ A, int lda, const float* __restrict__ Bm, int ldb,
-                              size_t K, int M, int ncols, size_t chunk, double* __restrict__ part) {
-  const int i = blockIdx.x, c = blockIdx.y, l = threadIdx.x;
-  if (l >= ncols) return;
-  const size_t k0 = (size_t)c * chunk, k1 = k0 + chunk < K ? k0 + chunk : K;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  size_t k = k0;
-  for (; k + 4 <= k1; k += 4) {
-    acc0 += (double)A[k * lda + i] * (double)Bm[k * ldb + l];
-    acc1 += (double)A[(k + 1) * lda + i] * (double)Bm[(k + 1) * ldb + l];
-    acc2 += (double)A[(k + 2) * lda + i] * (double)Bm[(k + 2) * ldb + l];
-    acc3 += (double)A[(k + 3) * lda + i] * (double)Bm[(k + 3) * ldb + l];
+// Chunk partials of dW1's value part, part[c][i][l] = sum over the rows b of chunk
+// c of D1[b][i] X[b][l] (FP64): threads over the (i, l) entries, one work-group
+// per chunk of rows.
+__global__ void k_mlp_tn_chunks(const float* __restrict__ A, int na, const float* __restrict__ Bm, int nb,
+                                long long K, long long chunk, double* __restrict__ part) {
+  const long long k0 = (long long)blockIdx.x * chunk, k1 = k0 + chunk < K ? k0 + chunk : K;
+  for (int f = threadIdx.x; f < na * nb; f += blockDim.x) {
+    const int i = f / nb, l = f % nb;
+    double acc = 0.0;
+    for (long long r = k0; r < k1; ++r) acc += (double)A[r * na + i] * (double)Bm[r * nb + l];
+    part[(size_t)blockIdx.x * na * nb + f] = acc;
   }
-  for (; k < k1; ++k) acc0 += (double)A[k * lda + i] * (double)Bm[k * ldb + l];
-  part[((size_t)c * M + i) * ncols + l] = (acc0 + acc1) + (acc2 + acc3);
+}
+
+// Chunk partials of column sums over B rows of H values, for G sources at once:
+// source g (blockIdx.y) starts at src + offs[g] rows; out[(g nchunk + c) H + i] (FP64).
+struct MlpColSrc {
+  const float* p[kMlpMaxJ + 3];
+};
+__global__ void k_mlp_colsums(MlpColSrc src, int B, int H, long long chunk, double* __restrict__ out) {
+  const int g = blockIdx.y, c = blockIdx.x, nchunk = gridDim.x;
+  const long long k0 = (long long)c * chunk, k1 = k0 + chunk < B ? k0 + chunk : B;
+  const float* A = src.p[g];
+  for (int i = threadIdx.x; i < H; i += blockDim.x) {
+    double acc = 0.0;
+    for (long long r = k0; r < k1; ++r) acc += (double)A[r * H + i];
+    out[((size_t)g * nchunk + c) * H + i] = acc;
+  }
 }
 
 // out[f] (FP32) = sum over chunks of part[c][f], plus (optionally) add[f]
@@ -307,47 +322,46 @@ __global__ void k_mlp_sum_chunks(const double* __restrict__ part, int nchunk, in
   out[f] = (float)s;
 }
 
-// column sums over row ranges: out[j][l] = sum_{b < B} M[(j * B + b) * H + l], j < nj (FP64).
-// One work-group per j of S * H threads: slice s adds rows s, s + S, ... in
-// order (eight loads in flight), then the S slices are added in order.
-__global__ __launch_bounds__(1024) void k_mlp_colsum(const float* __restrict__ Mx, int B, int H,
-                                                     double* __restrict__ out) {
-  __shared__ double red[1024];
-  const int j = blockIdx.x;
-  const int S = blockDim.x / H;
-  const int l = threadIdx.x % H, sl = threadIdx.x / H;
-  double acc = 0.0;
-  const float* col = Mx + (size_t)j * B * H + l;
-#pragma unroll 8
-  for (int b = sl; b < B; b += S) acc += (double)col[(size_t)b * H];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < H) {
-    double t = 0.0;
-    for (int q = 0; q < S; ++q) t += red[q * H + threadIdx.x];
-    out[(size_t)j * H + threadIdx.x] = t;
-  }
-}
-
-// The small gradients in one work-group: W1 = its chunk partials plus the
-// tangent column sums (dW1[i][j] += sum_b dda1_j[b][i], j < J), b1 and b2 from the
-// column sums of the value rows of D1 and D2, b3 = sum_b ey_b (FP64, fixed order).
-__global__ __launch_bounds__(256) void k_mlp_small_grads(const double* __restrict__ pW1, int nchunk, int H, int F,
-                                                         int J, const double* __restrict__ cs,
-                                                         const double* __restrict__ cs2, const float* __restrict__ E,
-                                                         int B, MlpOff o, float* __restrict__ grad) {
-  __shared__ double red[256];
-  for (int f = threadIdx.x; f < H * F; f += 256) {
+// The small gradients from chunk partials added in a fixed order (FP64), one
+// thread per entry: W1 = the value rows' D1^T X plus the tangent column sums
+// (dW1[i][j] += sum_b dda1_j[b][i], j < J), then w3 (column sums of P3), b1 and b2
+// (column sums of the value rows of D1 and D2).  cs holds nchunk x H partials of
+// each column-sum source: D1 row groups 0..J, then D2's value rows (cs2), then P3
+// (pw3).
+__global__ void k_mlp_small_grads(const double* __restrict__ pW1, const double* __restrict__ pw3,
+                                  const double* __restrict__ cs, const double* __restrict__ cs2, int nchunk, int H,
+                                  int F, int J, MlpOff o, float* __restrict__ grad) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  auto csum = [&](int g, int i) {  // column sum of D1 row group g, unit i
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += cs[((size_t)g * nchunk + c) * H + i];
+    return v;
+  };
+  if (f < H * F) {
     double v = 0.0;
     for (int c = 0; c < nchunk; ++c) v += pW1[(size_t)c * H * F + f];
     const int i = f / F, j = f % F;
-    if (j < J) v += cs[(size_t)(j + 1) * H + i];
+    if (j < J) v += csum(j + 1, i);
     grad[o.W1 + f] = (float)v;
+  } else if (f < H * F + H) {
+    const int i = f - H * F;
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += pw3[(size_t)c * H + i];
+    grad[o.w3 + i] = (float)v;
+  } else if (f < H * F + 2 * H) {
+    const int i = f - H * F - H;
+    grad[o.b1 + i] = (float)csum(0, i);
+  } else if (f < H * F + 3 * H) {
+    const int i = f - H * F - 2 * H;
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += cs2[(size_t)c * H + i];
+    grad[o.b2 + i] = (float)v;
   }
-  for (int i = threadIdx.x; i < H; i += 256) {
-    grad[o.b1 + i] = (float)cs[i];
-    grad[o.b2 + i] = (float)cs2[i];
-  }
+}
+
+// b3 = sum_b ey_b (FP64, one work-group).
+__global__ __launch_bounds__(256) void k_mlp_b3(const float* __restrict__ E, int B, float* __restrict__ out) {
+  __shared__ double red[256];
   double e = 0.0;
   for (int b = threadIdx.x; b < B; b += 256) e += (double)E[b];
   red[threadIdx.x] = e;
@@ -356,7 +370,7 @@ __global__ __launch_bounds__(256) void k_mlp_small_grads(const double* __restric
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) grad[o.b3] = (float)red[0];
+  if (threadIdx.x == 0) out[0] = (float)red[0];
 }
 
 __global__ void k_mlp_loss(const double* __restrict__ lp, int B, double* __restrict__ out) {
@@ -384,23 +398,23 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
   P[f] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
-constexpr int kMlpChunks = 16;      // chunks of the small batch contractions (dW1, dw3)
+constexpr int kMlpChunks = 64;      // chunks of the small batch contractions (dW1, dw3, column sums)
 constexpr int kMlpGramChunks = 64;  // chunks of dW2 = D2^T S1
 
 static dski_status mlp_reserve(dski_mlp net, int B, MlpWork& w) {
   const int H = net->H, J = net->J;
   const size_t rows = (size_t)(1 + J) * B;
-  const size_t fl = 5 * rows * H + (size_t)B * H + rows + 64;
-  const size_t parts = (size_t)kMlpGramChunks * H * H + (size_t)kMlpChunks * ((size_t)H * net->F + H) +
-                       (size_t)(J + 2) * H + B + 64;
+  const size_t fl = 4 * rows * H + 2 * (size_t)B * H + rows + 64;
+  const size_t parts = (size_t)kMlpGramChunks * H * H +
+                       (size_t)kMlpChunks * ((size_t)H * net->F + (size_t)(J + 3) * H) + B + 64;
   DSKI_TRY(net->work.reserve(sizeof(float) * fl + sizeof(double) * parts + 256));
   float* base = net->work.as<float>();
   w.S1 = base;
   w.C = w.S1 + rows * H;
   w.D2 = w.C + rows * H;
-  w.S2 = w.D2 + rows * H;
-  w.D1 = w.S2 + rows * H;
-  w.A1 = w.D1 + rows * H;
+  w.D1 = w.D2 + rows * H;
+  w.P3 = w.D1 + rows * H;
+  w.A1 = w.P3 + (size_t)B * H;
   w.E = w.A1 + (size_t)B * H;
   size_t off = ((sizeof(float) * fl) + 63) / 64 * 64;
   w.part = reinterpret_cast<double*>(net->work.as<char>() + off);
@@ -528,10 +542,10 @@ dski_status mlp_backward(dski_mlp net, int B, const float* X, const float* t, co
   const int nchunk = kMlpChunks;
   double* pW2 = w.part;                                // kMlpGramChunks x H x H
   double* pW1 = pW2 + (size_t)kMlpGramChunks * H * H;  // nchunk x H x F
-  double* pw3 = pW1 + (size_t)nchunk * H * F;          // nchunk x 1 x H
-  double* cs = pw3 + (size_t)nchunk * H;               // column sums of D1 row groups: (J+1) x H
-  double* cs2 = cs + (size_t)(J + 1) * H;              // column sums of D2 rows 0..B-1: H
-  double* lp = cs2 + H;                                // B loss partials
+  double* cs = pW1 + (size_t)nchunk * H * F;           // column sums of D1 row groups: (J+1) x nchunk x H
+  double* cs2 = cs + (size_t)(J + 1) * nchunk * H;     // column sums of D2 rows 0..B-1: nchunk x H
+  double* pw3 = cs2 + (size_t)nchunk * H;              // column sums of P3: nchunk x H
+  double* lp = pw3 + (size_t)nchunk * H;               // B loss partials
   double* lsum = lp + B;
   const size_t K = (size_t)(1 + J) * B;
   const long long BH = (long long)B * H;
@@ -545,22 +559,23 @@ dski_status mlp_backward(dski_mlp net, int B, const float* X, const float* t, co
   k_mlp_mm<false><<<mmb, 256, 0, st>>>(w.D2, (long long)K, net->params + o.W2, H, w.C);
   k_mlp_d1<<<(unsigned)((BH + 255) / 256), 256, 0, st>>>(net->params, F, H, J, o, B, w);
   DSKI_HIP(hipGetLastError());
-  const size_t ch = (K + nchunk - 1) / nchunk;
   // dW2 = D2^T S1 (matrix cores, FP64 chunk partials)
   const long long gch = (((long long)K + kMlpGramChunks - 1) / kMlpGramChunks + 3) / 4 * 4;
   k_mlp_gram<<<kMlpGramChunks, 256, 0, st>>>(w.D2, w.S1, (long long)K, H, gch, pW2);
-  // dw3 = E^T S2
-  k_mlp_gemm_tn<<<dim3(1, nchunk), 128, 0, st>>>(w.E, 1, w.S2, H, K, 1, H, ch, pw3);
-  // dW1 = D1[0:B]^T X  (value rows only); tangent rows add their column sums below
-  const size_t chB = ((size_t)B + nchunk - 1) / nchunk;
-  k_mlp_gemm_tn<<<dim3(H, nchunk), 128, 0, st>>>(w.D1, H, X, F, (size_t)B, H, F, chB, pW1);
-  const int cst = (1024 / H) * H;
-  k_mlp_colsum<<<J + 1, cst, 0, st>>>(w.D1, B, H, cs);
-  k_mlp_colsum<<<1, cst, 0, st>>>(w.D2, B, H, cs2);
+  // the small contractions in row chunks: dW1 = D1^T X (value rows), and in one
+  // launch the column sums of each D1 row group, of the D2 value rows and of P3
+  const long long chB = ((long long)B + nchunk - 1) / nchunk;
+  k_mlp_tn_chunks<<<nchunk, std::min(1024, H * F), 0, st>>>(w.D1, H, X, F, (long long)B, chB, pW1);
+  MlpColSrc src{};
+  for (int gi = 0; gi <= J; ++gi) src.p[gi] = w.D1 + (size_t)gi * B * H;
+  src.p[J + 1] = w.D2;
+  src.p[J + 2] = w.P3;
+  k_mlp_colsums<<<dim3(nchunk, J + 3), H, 0, st>>>(src, B, H, chB, cs);
   k_mlp_loss<<<1, 256, 0, st>>>(lp, B, lsum);
   k_mlp_sum_chunks<<<(H * H + 255) / 256, 256, 0, st>>>(pW2, kMlpGramChunks, H * H, net->grad + o.W2, nullptr);
-  k_mlp_sum_chunks<<<(H + 255) / 256, 256, 0, st>>>(pw3, nchunk, H, net->grad + o.w3, nullptr);
-  k_mlp_small_grads<<<1, 256, 0, st>>>(pW1, nchunk, H, F, J, cs, cs2, w.E, B, o, net->grad);
+  const int nsmall = H * F + 3 * H;
+  k_mlp_small_grads<<<(nsmall + 255) / 256, 256, 0, st>>>(pW1, pw3, cs, cs2, nchunk, H, F, J, o, net->grad);
+  k_mlp_b3<<<1, 256, 0, st>>>(w.E, B, net->grad + o.b3);
   DSKI_HIP(hipGetLastError());
   double hloss = 0.0;
   DSKI_HIP(hipMemcpyAsync(&hloss, lsum, sizeof(double), hipMemcpyDeviceToHost, st));
