@@ -609,6 +609,9 @@ def main(argv=None):
     ap.add_argument("--predict-only", action="store_true",
                     help="only the prediction block of the terrain workload (grid vector, means of 1,000,000 "
                          "test points, pivoted-Cholesky and randomized variance) and the active-subspace block")
+    ap.add_argument("--pcg-only", action="store_true",
+                    help="only the terrain block PCG (tuner, pivoted Cholesky, one solve with FP32 and one with "
+                         "FP64 vectors): per-kernel profiles of the solver's iteration")
     ap.add_argument("--pmc-summary", nargs="+", metavar="PATH", default=None,
                     help="FETCH_DIR WRITE_DIR LOG [SQ_DIR]: write the PMC summary from rocprofv3 --pmc runs of "
                          "--pmc-mvm (counter folders and the run's stdout), no GPU needed")
@@ -671,6 +674,36 @@ def main(argv=None):
         return 0
     if a.predict_only:
         print(json.dumps({"predict": predict_block(W, stream), "active_subspace": active_block()}), flush=True)
+        return 0
+
+    if a.pcg_only:
+        plan = dski.Plan(X, W.grid_m, W.lo, W.hi)
+        plan.set_hypers(*W.hypers())
+        tune = plan.autotune(R)
+        variants = tuned_variants(tune)
+        if pinned is not None:
+            variants = {"scatter": pinned[0], "gather": pinned[1], "kuu": pinned[2:2 + d]}
+            plan.set_variants(variants["scatter"], variants["gather"])
+            for ax, v in enumerate(variants["kuu"]):
+                plan.set_kuu_variant(ax, v)
+        pc = plan.pivchol(W.rank)
+        B = torch.empty((R, N), dtype=torch.float32, device=dev)
+        B[0] = y[0]
+        B[1:] = dski.rademacher(SEED, 0, t_probes, N, device=dev)
+        out = {"workload": f"terrain n={n} d={d} grid={W.grid_m[0]}x{W.grid_m[1]} R={R} rank={W.rank}",
+               "variants": variants}
+        for name, Bv in (("f32", B), ("f64", B.double())):
+            _progress(f"pcg {name}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, iters, _, st, _ = plan.pcg(Bv, pc, tol=W.tol, max_iter=20000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            it = int(max(iters))
+            out[name] = {"pcg_s": round(dt, 4), "iters": it, "us_per_iter": round(dt / it * 1e6, 2),
+                         "status": int(st)}
+        print(json.dumps({"pcg_only": out}), flush=True)
+        plan.close()
         return 0
 
     if a.sweep:

@@ -110,139 +110,166 @@ __global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, co
 }
 
 // alpha, the r update, partials of r.r and of U^T D^{-1/2} r.  A wavefront
-// takes 64 rows: it updates them (one row per lane, all columns), keeps the
-// new r in LDS and projects it on the FP64 matrix cores (the first 16 columns,
-// and the next 16 when RB > 20) with up to 4 remaining columns on the vector
-// ALU.  The four wavefronts' partials are added in LDS in a fixed order and
-// written once per work-group, block-major (t_part[b k R + i R + c],
-// rr_part[b R + c]).  RB = R padded to a multiple of 4.
+// takes 32 rows (each lane one row and half of the columns), keeps the new r in
+// LDS and projects it on the FP64 matrix cores (the first 16 columns, and the
+// next 16 when RB > 20) with up to 4 remaining columns on the vector ALU.  Four
+// wavefronts form a work-group of 128 rows, and two work-groups share a CU, so
+// that one's loads overlap the other's products.  The four wavefronts' partials
+// are added in LDS in a fixed order and written once per work-group,
+// block-major (t_part[b k R + i R + c], rr_part[b R + c]).  RB = R padded to a
+// multiple of 4.
+constexpr int kPqRegs = 16;  // p.q partials per lane held in registers (8 lanes: 128 blocks)
+constexpr int kUpdRows = 32;   // rows per wavefront
+constexpr int kUpdWaves = 4;   // wavefronts per work-group
+static int upd_blocks(int N) { return (N + kUpdRows * kUpdWaves - 1) / (kUpdRows * kUpdWaves); }
+
 template <int RB>
 struct UpdShape {
   static constexpr int MB = RB <= 20 ? 1 : 2;           // matrix-core column blocks
   static constexpr int VR = RB > 16 && RB <= 20 ? RB - 16 : 0;  // vector-ALU columns
   static constexpr int CW = RB > 16 * MB ? RB : 16 * MB;  // columns held per row (zeros beyond R)
+  static constexpr int HC = CW / 2;                     // columns per lane (two lanes per row)
   static constexpr int XP = CW + 1;                     // LDS row stride of the new r
   static constexpr int TB = 64 * CW;                    // one group of 64 outputs i per column
   template <typename T>
   static constexpr size_t bytes() {
-    return 4 * sizeof(T) * (size_t)kProjRows * XP + sizeof(double) * 4 * (size_t)TB;
+    return kUpdWaves * sizeof(T) * (size_t)kUpdRows * XP + sizeof(double) * kUpdWaves * (size_t)TB;
   }
 };
 
-template <typename T, int RB>
-__global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* __restrict__ Rr, int N, int n,
-                                                    int R, PcgScal s, int par, const double* __restrict__ pq_part,
-                                                    int nb_pq, double* __restrict__ rr_part,
-                                                    const double* __restrict__ Ur, int k, double isf, double isg,
-                                                    double* __restrict__ t_part, double* __restrict__ hist,
-                                                    int max_iter) {
+template <typename T, int RB, bool PC>
+__global__ __launch_bounds__(256, 2) void k_pcg_update(const T* __restrict__ Q, T* __restrict__ Rr, int N, int n,
+                                                       int R, PcgScal s, int par,
+                                                       const double* __restrict__ pq_part, int nb_pq,
+                                                       double* __restrict__ rr_part,
+                                                       const double* __restrict__ Ur, int k, double isf, double isg,
+                                                       double* __restrict__ t_part, double* __restrict__ hist,
+                                                       int max_iter) {
   using S = UpdShape<RB>;
-  constexpr int XP = S::XP, MB = S::MB, VR = S::VR, CW = S::CW;
+  constexpr int XP = S::XP, MB = S::MB, VR = S::VR, CW = S::CW, HC = S::HC, UR = kUpdRows, NS = UR / 4;
+  static_assert(kUpdWaves * 64 == kBlock, "one work-group of kBlock threads");
   extern __shared__ __align__(16) char smem[];
-  T* sx = reinterpret_cast<T*>(smem) + (size_t)(threadIdx.x >> 6) * kProjRows * XP;
-  double* st = reinterpret_cast<double*>(smem + 4 * sizeof(T) * (size_t)kProjRows * XP);  // 4 x TB
+  T* sx = reinterpret_cast<T*>(smem) + (size_t)(threadIdx.x >> 6) * UR * XP;
+  double* st = reinterpret_cast<double*>(smem + kUpdWaves * sizeof(T) * (size_t)UR * XP);  // kUpdWaves x TB
   __shared__ double s_alpha[kPcgMaxR];
   __shared__ int s_act[kPcgMaxR];
-  __shared__ double s_rr[4][RB];
+  __shared__ double s_rr[kUpdWaves][RB];
   const int* act = s.active + par * R;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
-  const int w = blockIdx.x * 4 + wv;
-  const int e0 = w * kProjRows, e = e0 + lane;
-  // A operands of the projection (U rows 4 s + kq of the 64, columns i0 + 16 b + l % 16),
-  // for the first group of 64 columns issued before anything else: their latency
-  // overlaps alpha and the r update
-  double aop[16][4];
+  const int e0 = (blockIdx.x * kUpdWaves + wv) * UR;
+  const int rl = lane & (UR - 1), hh = lane / UR;  // this lane's row and half of the columns
+  const int e = e0 + rl;
+  // Every load of the kernel is issued before the first wait, in the order
+  // their values are needed (loads complete in order): the column state and
+  // the p.q partials for alpha, this lane's row of r and q, then the
+  // projection's operands.
+  // alpha: 8 lanes per column; lane j adds blocks j, j + 8, ... in order
+  const int c_al = threadIdx.x >> 3, j_al = threadIdx.x & 7;
+  const bool col = c_al < R;
+  const int on_al = col ? act[c_al] : 0;
+  const double rz_al = col ? s.rz[par * R + c_al] : 0.0;
+  const double* pqc = pq_part + (size_t)(col ? c_al : 0) * nb_pq;
+  double pqv[kPqRegs];
+#pragma unroll
+  for (int u = 0; u < kPqRegs; ++u) pqv[u] = ld_or0(pqc, (size_t)(j_al + 8 * u), 0, col && j_al + 8 * u < nb_pq);
+  const bool in = e < N;  // rows past N (and wavefronts past the last row) act as zeros
+  // r and q of this lane's row, its half of the columns (q of a finished
+  // column is read and not used)
+  T rv[HC], qv[HC];
+#pragma unroll
+  for (int j = 0; j < HC; ++j) {
+    const int c = hh * HC + j;
+    const size_t idx = (size_t)(c < R ? c : 0) * N + (in ? e : 0);
+    rv[j] = Rr[idx];
+    qv[j] = Q[idx];
+  }
+  // A operands of the projection (U rows e0 + 4 s + kq, columns i0 + 16 b +
+  // l % 16).  The indices are clamped into U instead of masked: a row past N
+  // meets a zero B row, and an output i >= k is never written, so whatever
+  // finite entry of U stands in adds nothing that is kept.
+  double aop[NS][4];
+  const size_t nk_last = (size_t)N * (size_t)(k > 0 ? k : 1) - 1;
   auto load_u = [&](int i0) {  // row-major U: 4 rows x 16 consecutive columns per load
 #pragma unroll
-    for (int s16 = 0; s16 < 16; ++s16) {
-      const int er = e0 + 4 * s16 + kq;
+    for (int s4 = 0; s4 < NS; ++s4) {
+      const int er = e0 + 4 * s4 + kq;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int i = i0 + 16 * b + r16;
-        aop[s16][b] = ld_or0(Ur, (size_t)er * k + i, 0, i < k && er < N);
+        const size_t i = (size_t)er * k + (size_t)(i0 + 16 * b + r16);
+        aop[s4][b] = Ur[i < nk_last ? i : nk_last];
       }
     }
   };
-  if (k > 0) load_u(0);
-  {  // alpha of every column at once: 8 lanes per column, all loads in flight together
-    const int c = threadIdx.x >> 3, j = threadIdx.x & 7;
-    const bool col = c < R;
-    const int on = col ? act[c] : 0;
-    const double rz = col ? s.rz[par * R + c] : 0.0;
+  // (PC: k > 0, a compile-time branch, so that the loads stay in one basic
+  // block and the wait for the partials below does not cover them)
+  if (PC) load_u(0);
+  {
     double pq = 0.0;
-    for (int b = j; b < nb_pq; b += 8) pq += ld_or0(pq_part, (size_t)(col ? c : 0) * nb_pq + b, 0, col);
+#pragma unroll
+    for (int u = 0; u < kPqRegs; ++u) pq += pqv[u];
+    for (int b = j_al + 8 * kPqRegs; b < nb_pq; b += 8) pq += ld_or0(pqc, (size_t)b, 0, col);
     pq += __shfl_xor(pq, 1, 64);
     pq += __shfl_xor(pq, 2, 64);
     pq += __shfl_xor(pq, 4, 64);
-    if (col && j == 0) {
+    if (col && j_al == 0) {
+      const int c = c_al;
       double a = 0.0;
-      if (on) {
+      if (on_al) {
         if (!(pq > 0.0) || !isfinite(pq)) {
           if (blockIdx.x == 0) s.flags[1] = 1;
         } else {
-          a = rz / pq;
+          a = rz_al / pq;
         }
         if (blockIdx.x == 0 && hist && s.iters[c] < max_iter) hist[(size_t)c * max_iter + s.iters[c]] = a;
       }
       if (blockIdx.x == 0) s.alpha[c] = a;
       s_alpha[c] = a;
-      s_act[c] = on;
+      s_act[c] = on_al;
     }
   }
   __syncthreads();
-  const bool in = e < N;  // rows past N (and wavefronts past the last row) act as zeros
-  // r -= alpha q on this lane's row, every column's loads in flight (x += alpha p
-  // is done by the beta kernel, which reads p anyway)
-  {
-    T rv[RB], qv[RB];
+  // r -= alpha q on this lane's row and columns (x += alpha p is done by the
+  // beta kernel, which reads p anyway); every column below CW goes to LDS
 #pragma unroll
-    for (int c = 0; c < RB; ++c) {
-      const bool ok = in && c < R, on = ok && s_act[c];
-      const size_t idx = (size_t)(ok ? c : 0) * N + (in ? e : 0);
-      rv[c] = ld_or0(Rr, idx, 0, ok);
-      qv[c] = ld_or0(Q, idx, 0, on);
+  for (int j = 0; j < HC; ++j) {
+    const int c = hh * HC + j;
+    const bool ok = in && c < R;
+    if (ok && s_act[c]) {
+      const T rnew = (T)((double)rv[j] - s_alpha[c] * (double)qv[j]);
+      Rr[(size_t)c * N + e] = rnew;
+      rv[j] = rnew;
     }
-#pragma unroll
-    for (int c = 0; c < RB; ++c) {
-      if (in && c < R && s_act[c]) {
-        const T rnew = (T)((double)rv[c] - s_alpha[c] * (double)qv[c]);
-        Rr[(size_t)c * N + e] = rnew;
-        rv[c] = rnew;
-      }
-      sx[lane * XP + c] = rv[c];
-    }
-#pragma unroll
-    for (int c = RB; c < CW; ++c) sx[lane * XP + c] = (T)0;
+    sx[rl * XP + c] = ok ? rv[j] : (T)0;
   }
   wave_lds_fence();
-  {  // |r|^2 of every column over the 64 rows: lane c + 32 h sums rows 32 h ..
+  {  // |r|^2 of every column over the 32 rows: lane c + 32 h sums rows 16 h ..
     const int c = lane & 31, h = lane >> 5;
     double acc = 0.0;
     if (c < RB) {
-#pragma unroll 8
-      for (int j = 0; j < 32; ++j) {
-        const double v = (double)sx[(32 * h + j) * XP + c];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double v = (double)sx[(16 * h + j) * XP + c];
         acc += v * v;
       }
     }
     acc += __shfl_xor(acc, 32, 64);
     if (h == 0 && c < RB) s_rr[wv][c] = acc;
   }
-  // scaled B operands of the projection: rows 4 s + kq of the 64
-  double bop[16][MB], rsc[16];
+  // scaled B operands of the projection: rows 4 s + kq of the 32
+  double bop[NS][MB], rsc[NS];
 #pragma unroll
-  for (int st_ = 0; st_ < 16; ++st_) {
-    const int row = 4 * st_ + kq;
-    rsc[st_] = e0 + row < n ? isf : isg;
+  for (int s4 = 0; s4 < NS; ++s4) {
+    const int row = 4 * s4 + kq;
+    rsc[s4] = e0 + row < n ? isf : isg;
 #pragma unroll
-    for (int cb = 0; cb < MB; ++cb) bop[st_][cb] = rsc[st_] * (double)sx[row * XP + 16 * cb + r16];
+    for (int cb = 0; cb < MB; ++cb) bop[s4][cb] = rsc[s4] * (double)sx[row * XP + 16 * cb + r16];
   }
   __syncthreads();  // s_rr complete
   if (threadIdx.x < R)
     rr_part[(size_t)blockIdx.x * R + threadIdx.x] =
         (s_rr[0][threadIdx.x] + s_rr[1][threadIdx.x]) + (s_rr[2][threadIdx.x] + s_rr[3][threadIdx.x]);
   const int KR = k * R;
-  for (int i0 = 0; i0 < k; i0 += 64) {  // groups of four 16-column blocks of U
+  for (int i0 = 0; PC && i0 < k; i0 += 64) {  // groups of four 16-column blocks of U
     dski_pdbl4 acc[4][MB];
     double vacc[4][VR > 0 ? VR : 1];
 #pragma unroll
@@ -254,17 +281,17 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ Q, T* 
     }
     if (i0 > 0) load_u(i0);
 #pragma unroll
-    for (int s16 = 0; s16 < 16; ++s16) {
+    for (int s4 = 0; s4 < NS; ++s4) {
       double vop[VR > 0 ? VR : 1];
 #pragma unroll
-      for (int v = 0; v < VR; ++v) vop[v] = rsc[s16] * (double)sx[(4 * s16 + kq) * XP + 16 + v];
+      for (int v = 0; v < VR; ++v) vop[v] = rsc[s4] * (double)sx[(4 * s4 + kq) * XP + 16 + v];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
 #pragma unroll
         for (int cb = 0; cb < MB; ++cb)
-          acc[b][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s16][b], bop[s16][cb], acc[b][cb], 0, 0, 0);
+          acc[b][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[s4][b], bop[s4][cb], acc[b][cb], 0, 0, 0);
 #pragma unroll
-        for (int v = 0; v < VR; ++v) vacc[b][v] += aop[s16][b] * vop[v];
+        for (int v = 0; v < VR; ++v) vacc[b][v] += aop[s4][b] * vop[v];
       }
     }
     // this wavefront's 64 x RB block of t: matrix-core part (register r of lane
@@ -305,15 +332,21 @@ static dski_status launch_update_rb(int nb, const T* Q, T* Rr, int N, int n, int
                                     const double* Ur, int k, double isf, double isg, double* t_part, double* hist,
                                     int max_iter, hipStream_t st) {
   constexpr size_t sh = UpdShape<RB>::template bytes<T>();
-  static bool done = false;
-  DSKI_TRY(lds_limit(&k_pcg_update<T, RB>, sh, done));
-  k_pcg_update<T, RB><<<nb, kBlock, sh, st>>>(Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, Ur, k, isf, isg,
-                                              t_part, hist, max_iter);
+  static bool done_pc = false, done_plain = false;
+  if (k > 0) {
+    DSKI_TRY(lds_limit(&k_pcg_update<T, RB, true>, sh, done_pc));
+    k_pcg_update<T, RB, true><<<nb, kBlock, sh, st>>>(Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, Ur, k, isf,
+                                                      isg, t_part, hist, max_iter);
+  } else {
+    DSKI_TRY(lds_limit(&k_pcg_update<T, RB, false>, sh, done_plain));
+    k_pcg_update<T, RB, false><<<nb, kBlock, sh, st>>>(Q, Rr, N, n, R, s, par, pq_part, nb_pq, rr_part, Ur, k,
+                                                       isf, isg, t_part, hist, max_iter);
+  }
   DSKI_HIP(hipGetLastError());
   return DSKI_OK;
 }
 
-// Partials are per work-group of 256 rows: nb = ceil(N / 256) blocks.
+// Partials are per update work-group: nb = upd_blocks(N) blocks.
 template <typename T>
 static dski_status launch_update(int nb, const T* Q, T* Rr, int N, int n, int R,
                                  const PcgScal& s, int par, const double* pq_part, int nb_pq, double* rr_part,
@@ -351,14 +384,21 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, double* _
   __shared__ double s_beta;
   __shared__ double s_red[4];
   const int c = blockIdx.y;
+  // the column's state first; an active column then issues its rows of z, p
+  // and x and its r.z partials together
   const int on = s.active[par * R + c];
+  const double rz_old = s.rz[par * R + c], rr_c = s.rr[c];
   if (!on) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      s.rz[(1 - par) * R + c] = s.rz[par * R + c];
+      s.rz[(1 - par) * R + c] = rz_old;
       s.active[(1 - par) * R + c] = 0;
     }
     return;
   }
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t ip = (size_t)c * N + (e < N ? e : 0);
+  const T zv = Z[ip], pv = P[ip];
+  const double xv = Xd[ip];
   // r.z of the column from its partials: every thread of the block takes a
   // share, a fixed-order tree combines them
   double rzs = 0.0;
@@ -369,21 +409,16 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, double* _
     __syncthreads();
     rzs = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
   }
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t ip = (size_t)c * N + (e < N ? e : 0);
-  const T zv = Z[ip], pv = P[ip];  // in flight while thread 0 forms beta
-  const double xv = Xd[ip];
   {
     if (threadIdx.x == 0) {
-      double rz_old = s.rz[par * R + c];
-      double rzn = rz_part ? rzs : s.rr[c];
+      double rzn = rz_part ? rzs : rr_c;
       if (!(rzn >= 0.0) || !isfinite(rzn)) {
         if (blockIdx.x == 0) s.flags[1] = 1;
       }
       double b = rz_old > 0.0 ? rzn / rz_old : 0.0;
       if (blockIdx.x == 0) {
         int it = s.iters[c];
-        bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (s.rr[c] <= s.tol2[c] * s.bb[c]);
+        bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (rr_c <= s.tol2[c] * s.bb[c]);
         if (hist && it < max_iter) hist[(size_t)c * max_iter + it] = b;
         s.iters[c] = it + 1;
         if (done) atomicSub(&s.flags[0], 1);
@@ -495,7 +530,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   const int k = pc ? pc->k : 0;
   const size_t nr = (size_t)N * R;
   const int nbv = nchunks(N), nbg = gather_blocks(p), nbz = vec_blocks(N);
-  const int nbt = (proj_waves(N) + 3) / 4;  // update work-groups (256 rows each)
+  const int nbt = upd_blocks(N);  // update work-groups (their partials of t and r.r)
   const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, nbt)) * R;
   const size_t ntp = (size_t)nbt * std::max(k, 1) * R;
   // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, scratch (R), coef, scalars

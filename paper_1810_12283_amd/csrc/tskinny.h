@@ -215,15 +215,13 @@ static __global__ __launch_bounds__(256) void k_ts_reduce_bm(RedJob j0, RedJob j
   const int per = (J.nblk + 15) / 16, b0 = part * per, b1 = min(J.nblk, b0 + per);
   double a = 0.0;
   if (o < J.nout) {
-    int b = b0;
-    for (; b + 8 <= b1; b += 8) {  // eight loads in flight, added in order
-      double v[8];
+    for (int b = b0; b < b1; b += 16) {  // sixteen loads in flight (zeros past b1), added in order
+      double v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = J.partial[(size_t)(b + u) * J.nout + o];
+      for (int u = 0; u < 16; ++u) v[u] = ld_or0(J.partial, (size_t)(b + u) * J.nout + o, 0, b + u < b1);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a += v[u];
+      for (int u = 0; u < 16; ++u) a += v[u];
     }
-    for (; b < b1; ++b) a += J.partial[(size_t)b * J.nout + o];
   }
   q[part][ol] = a;
   __syncthreads();
@@ -247,98 +245,171 @@ static inline dski_status launch_reduce_bm(const RedJob& a, const RedJob* b, hip
 }
 
 // z[e, c] = post_e * (pre_e * X[e, c] - sum_i U[e, i] coef[i, c]), one wavefront
-// per 64 rows: the product U coef on the FP64 matrix cores (A = U, 16 rows x 4
-// of its columns per load; B = coef, 4 x 16), CB blocks of 16 columns; the
-// result goes through LDS so that X is read and Z written one row per lane;
-// per-work-group partials of X.z (fixed order) stored output-major
-// (dot_partial[c * blocks + block]).  Work-groups cover 256 rows.
-template <typename T, int CB>
-static __global__ __launch_bounds__(256) void k_ts_final(const T* __restrict__ X, int ld, int N, int n, int R,
+// per 32 rows, eight per work-group (256 rows, so that the partials are per
+// vec_blocks block).  The product U coef runs on the FP64 matrix cores (A = U,
+// 16 rows x 4 of its columns per operand; B = coef, 4 x 16) for CB blocks of 16
+// columns, and on the vector ALU for VC further columns (17 - 20 columns: one
+// block plus up to four, instead of two blocks).  Per chunk of 64 columns of U
+// the work-group stages that chunk of coef in LDS (its loads issued first, so
+// that waiting for them does not wait for U), and every wavefront issues all
+// of its U operands before the first product; steps past k are skipped.  The
+// result goes through LDS, and each lane then takes one row and half of the
+// columns for X, Z and the partials of X.z (fixed order), stored output-major
+// (dot_partial[c * blocks + block]).
+constexpr int kFinalRows = 32;
+constexpr int kFinalWaves = 8;
+static_assert(kFinalRows * kFinalWaves == kBlock, "dot partials are counted per vec_blocks block");
+template <typename T, int CB, int VC>
+static __global__ __launch_bounds__(512) void k_ts_final(const T* __restrict__ X, int ld, int N, int n, int R,
                                                          double pre_v, double pre_g, double post_v, double post_g,
                                                          const double* __restrict__ U, int k,
                                                          const double* __restrict__ coef, T* __restrict__ Z,
                                                          int ldz, double* __restrict__ dot_partial) {
-  constexpr int XP = 16 * CB + 1, SB = 8;  // LDS row stride; matrix-core steps per load batch
+  constexpr int FR = kFinalRows, EB = FR / 16, CW = 16 * CB + VC, XP = CW + 1, HC = (CW + 1) / 2;
+  constexpr int NT = 64 * kFinalWaves, CF = (64 * CW + NT - 1) / NT;  // coef entries per thread and chunk
+  static_assert(CW <= 32, "columns per launch");
   extern __shared__ __align__(16) char smem[];
-  __shared__ double red[4][16 * CB];
+  __shared__ double red[kFinalWaves][CW];
+  __shared__ double s_coef[64 * XP];  // one chunk: row i - i0, column c
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
-  const int w = blockIdx.x * 4 + wv;
-  const bool live = w < proj_waves(N);
-  const int e0 = w * kProjRows;
-  double* sz = reinterpret_cast<double*>(smem) + (size_t)wv * kProjRows * XP;
-  dski_pdbl4 acc[4][CB];
+  const int e0 = (blockIdx.x * kFinalWaves + wv) * FR;
+  double* sz = reinterpret_cast<double*>(smem) + (size_t)wv * FR * XP;
+  // this lane's row (rl) and half of the columns (hh) of X (clamped indices,
+  // masked at use)
+  const int rl = lane & (FR - 1), hh = lane / FR;
+  const int e = e0 + rl;
+  const bool in = e < N;
+  T xr[HC];
+  dski_pdbl4 acc[EB][CB];
+  double vacc[EB][VC > 0 ? VC : 1];
 #pragma unroll
-  for (int eb = 0; eb < 4; ++eb)
+  for (int eb = 0; eb < EB; ++eb) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[eb][cb] = dski_pdbl4{0.0, 0.0, 0.0, 0.0};
-  if (live) {
-    for (int i0 = 0; i0 < k; i0 += 4 * SB) {
-      double av[SB][4], bv[SB][CB];
 #pragma unroll
-      for (int st = 0; st < SB; ++st) {
-        const int i = i0 + 4 * st + kq;
-        const bool oi = i < k;
+    for (int v = 0; v < VC; ++v) vacc[eb][v] = 0.0;
+  }
+  // U indices are clamped instead of masked: a column i >= k meets a zero
+  // coefficient, a row past N is never stored
+  const size_t nk_last = (size_t)N * (size_t)(k > 0 ? k : 1) - 1;
+  for (int i0 = 0; i0 < k; i0 += 64) {
+    double cf[CF];
 #pragma unroll
-        for (int eb = 0; eb < 4; ++eb) {
-          const int e = e0 + 16 * eb + r16;
-          av[st][eb] = ld_or0(U, (size_t)i * N + e, 0, oi && e < N);
-        }
+    for (int u = 0; u < CF; ++u) {
+      const int f = threadIdx.x + NT * u, il = f / CW, c = f - il * CW;
+      cf[u] = ld_or0(coef, (size_t)(i0 + il) * R + c, 0, f < 64 * CW && i0 + il < k && c < R);
+    }
+    if (i0 == 0) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          const int c = 16 * cb + r16;
-          bv[st][cb] = ld_or0(coef, (size_t)i * R + c, 0, oi && c < R);
-        }
+      for (int j = 0; j < HC; ++j) {
+        const int c = hh * HC + j;
+        xr[j] = X[(size_t)(c < R ? c : R - 1) * ld + (in ? e : 0)];
       }
+    }
+    double av[16][EB];
 #pragma unroll
-      for (int st = 0; st < SB; ++st)
+    for (int st = 0; st < 16; ++st) {
+      const int i = i0 + 4 * st + kq;
 #pragma unroll
-        for (int eb = 0; eb < 4; ++eb)
+      for (int eb = 0; eb < EB; ++eb) {
+        const size_t o = (size_t)i * N + (size_t)(e0 + 16 * eb + r16);
+        av[st][eb] = U[o < nk_last ? o : nk_last];
+      }
+    }
+    if (i0 > 0) __syncthreads();  // every wavefront is done with the previous chunk
+#pragma unroll
+    for (int u = 0; u < CF; ++u) {
+      const int f = threadIdx.x + NT * u, il = f / CW, c = f - il * CW;
+      if (f < 64 * CW) s_coef[il * XP + c] = cf[u];
+    }
+    __syncthreads();
+    const int steps = min(16, (k - i0 + 3) / 4);  // steps holding a column i < k
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      if (st < steps) {
+        const double* crow = s_coef + (4 * st + kq) * XP;
+        double bv[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) bv[cb] = crow[16 * cb + r16];
+#pragma unroll
+        for (int eb = 0; eb < EB; ++eb) {
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb)
-            acc[eb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st][eb], bv[st][cb], acc[eb][cb], 0, 0, 0);
+            acc[eb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st][eb], bv[cb], acc[eb][cb], 0, 0, 0);
+#pragma unroll
+          for (int v = 0; v < VC; ++v) vacc[eb][v] += av[st][eb] * crow[16 * CB + v];
+        }
+      }
     }
   }
-  // D register r of lane l: row 16 eb + l / 16 + 4 r, column 16 cb + l % 16
+  if (k <= 0) {  // no product: X alone
 #pragma unroll
-  for (int eb = 0; eb < 4; ++eb)
+    for (int j = 0; j < HC; ++j) {
+      const int c = hh * HC + j;
+      xr[j] = X[(size_t)(c < R ? c : R - 1) * ld + (in ? e : 0)];
+    }
+  }
+  // D register r of lane l: row 16 eb + l / 16 + 4 r, column 16 cb + l % 16;
+  // the vector columns summed over the four lanes that share a row
+#pragma unroll
+  for (int eb = 0; eb < EB; ++eb) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) sz[(16 * eb + kq + 4 * r) * XP + 16 * cb + r16] = acc[eb][cb][r];
+#pragma unroll
+    for (int v = 0; v < VC; ++v) {
+      double x = vacc[eb][v];
+      x += __shfl_xor(x, 16, 64);
+      x += __shfl_xor(x, 32, 64);
+      if (kq == 0) sz[(16 * eb + r16) * XP + 16 * CB + v] = x;
+    }
+  }
   wave_lds_fence();
-  const int e = e0 + lane;
-  const bool in = live && e < N;
   const double pre = e < n ? pre_v : pre_g, post = e < n ? post_v : post_g;
-  double xv[16 * CB];
 #pragma unroll
-  for (int c = 0; c < 16 * CB; ++c) xv[c] = (double)ld_or0(X, (size_t)c * ld + e, 0, in && c < R);
-#pragma unroll
-  for (int c = 0; c < 16 * CB; ++c) {
+  for (int j = 0; j < HC; ++j) {
+    const int c = hh * HC + j;  // at most CW: inside the LDS row of XP = CW + 1
     double dot = 0.0;
     if (in && c < R) {
-      const T z = (T)(post * (pre * xv[c] - sz[lane * XP + c]));
+      const double xv = (double)xr[j];
+      const T z = (T)(post * (pre * xv - sz[rl * XP + c]));
       Z[(size_t)c * ldz + e] = z;
-      dot = xv[c] * (double)z;
+      dot = xv * (double)z;
     }
-    sz[lane * XP + c] = dot;
+    sz[rl * XP + c] = dot;
   }
   if (!dot_partial) return;
   wave_lds_fence();
-  {  // column sums over the wavefront's 64 rows: lane c + 32 h sums rows 32 h ..
+  {  // column sums over the wavefront's 32 rows: lane c + 32 h sums rows 16 h ..
     const int c = lane & 31, h = lane >> 5;
     double a = 0.0;
-    if (c < 16 * CB) {
-#pragma unroll 8
-      for (int j = 0; j < 32; ++j) a += sz[(32 * h + j) * XP + c];
+    if (c < CW) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) a += sz[(16 * h + j) * XP + c];
     }
     a += __shfl_xor(a, 32, 64);
-    if (h == 0 && c < 16 * CB) red[wv][c] = a;
+    if (h == 0 && c < CW) red[wv][c] = a;
   }
   __syncthreads();
   if (threadIdx.x < R) {
     const int c = threadIdx.x;
-    dot_partial[(size_t)c * gridDim.x + blockIdx.x] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    dot_partial[(size_t)c * gridDim.x + blockIdx.x] =
+        ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) + ((red[4][c] + red[5][c]) + (red[6][c] + red[7][c]));
   }
+}
+
+template <typename T, int CB, int VC>
+static inline dski_status launch_final_cw(int nb, const T* X, int ld, int N, int n, int R, double pre_v, double pre_g,
+                                          double post_v, double post_g, const double* U, int k, const double* coef,
+                                          T* Z, int ldz, double* dot_partial, hipStream_t st) {
+  constexpr size_t sh = sizeof(double) * kFinalWaves * kFinalRows * (16 * CB + VC + 1);
+  static bool done = false;
+  DSKI_TRY(lds_limit(&k_ts_final<T, CB, VC>, sh, done));
+  k_ts_final<T, CB, VC><<<nb, 64 * kFinalWaves, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef,
+                                                          Z, ldz, dot_partial);
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
 }
 
 template <typename T>
@@ -350,20 +421,16 @@ static inline dski_status launch_final(const T* X, int ld, int N, int n, int R, 
     set_error("at most %d columns per tall-skinny launch", kFinalMaxR);
     return DSKI_ENOTSUP;
   }
-  const int nb = (proj_waves(N) + 3) / 4;  // = ceil(N / 256)
-  if (R <= 16) {
-    constexpr size_t sh = sizeof(double) * 4 * kProjRows * 17;
-    k_ts_final<T, 1><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
-                                          dot_partial);
-  } else {
-    constexpr size_t sh = sizeof(double) * 4 * kProjRows * 33;
-    static bool done = false;
-    DSKI_TRY(lds_limit(&k_ts_final<T, 2>, sh, done));
-    k_ts_final<T, 2><<<nb, 256, sh, st>>>(X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
-                                          dot_partial);
-  }
-  DSKI_HIP(hipGetLastError());
-  return DSKI_OK;
+  constexpr int rows = kFinalRows * kFinalWaves;
+  const int nb = (N + rows - 1) / rows;  // = vec_blocks(N): 256 rows per work-group
+  if (R <= 16)
+    return launch_final_cw<T, 1, 0>(nb, X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
+                                    dot_partial, st);
+  if (R <= 20)
+    return launch_final_cw<T, 1, 4>(nb, X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
+                                    dot_partial, st);
+  return launch_final_cw<T, 2, 0>(nb, X, ld, N, n, R, pre_v, pre_g, post_v, post_g, U, k, coef, Z, ldz,
+                                  dot_partial, st);
 }
 
 }  // namespace dski
