@@ -27,6 +27,7 @@ constexpr int kPcgMaxR = 32;  // columns per fused PCG (larger blocks run in gro
 struct PcgScal {
   double* rz;     // [2][R] r^T M^{-1} r, by parity
   double* rr;     // [R] r^T r (current)
+  double* rrd;    // [R] |D^{-1/2} r|^2 (current), right after rr: one reduction writes both
   double* bb;     // [R] b^T b
   double* alpha;  // [R]
   double* tol2;   // [R]
@@ -109,15 +110,15 @@ __global__ void k_pcg_init_scal(const double* __restrict__ bb_part, int nb_b, co
   }
 }
 
-// alpha, the r update, partials of r.r and of U^T D^{-1/2} r.  A wavefront
+// alpha, the r update, partials of r.r, |D^{-1/2} r|^2 and U^T D^{-1/2} r.  A wavefront
 // takes 32 rows (each lane one row and half of the columns), keeps the new r in
 // LDS and projects it on the FP64 matrix cores (the first 16 columns, and the
 // next 16 when RB > 20) with up to 4 remaining columns on the vector ALU.  Four
 // wavefronts form a work-group of 128 rows, and two work-groups share a CU, so
 // that one's loads overlap the other's products.  The four wavefronts' partials
 // are added in LDS in a fixed order and written once per work-group,
-// block-major (t_part[b k R + i R + c], rr_part[b R + c]).  RB = R padded to a
-// multiple of 4.
+// block-major (t_part[b k R + i R + c], rr_part[b 2 R + c] and [b 2 R + R + c]).
+// RB = R padded to a multiple of 4.
 constexpr int kPqRegs = 16;  // p.q partials per lane held in registers (8 lanes: 128 blocks)
 constexpr int kUpdRows = 32;   // rows per wavefront
 constexpr int kUpdWaves = 4;   // wavefronts per work-group
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(256, 2) void k_pcg_update(const T* __restrict__ Q, 
   double* st = reinterpret_cast<double*>(smem + kUpdWaves * sizeof(T) * (size_t)UR * XP);  // kUpdWaves x TB
   __shared__ double s_alpha[kPcgMaxR];
   __shared__ int s_act[kPcgMaxR];
-  __shared__ double s_rr[kUpdWaves][RB];
+  __shared__ double s_rr[kUpdWaves][RB], s_rrd[kUpdWaves][RB];
   const int* act = s.active + par * R;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
   const int e0 = (blockIdx.x * kUpdWaves + wv) * UR;
@@ -242,18 +243,24 @@ __global__ __launch_bounds__(256, 2) void k_pcg_update(const T* __restrict__ Q, 
     sx[rl * XP + c] = ok ? rv[j] : (T)0;
   }
   wave_lds_fence();
-  {  // |r|^2 of every column over the 32 rows: lane c + 32 h sums rows 16 h ..
+  {  // |r|^2 and |D^{-1/2} r|^2 of every column over the 32 rows: lane c + 32 h sums rows 16 h ..
     const int c = lane & 31, h = lane >> 5;
-    double acc = 0.0;
+    const double isf2 = isf * isf, isg2 = isg * isg;
+    double acc = 0.0, accd = 0.0;
     if (c < RB) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double v = (double)sx[(16 * h + j) * XP + c];
-        acc += v * v;
+        const double v = (double)sx[(16 * h + j) * XP + c], vv = v * v;
+        acc += vv;
+        accd += vv * (e0 + 16 * h + j < n ? isf2 : isg2);
       }
     }
     acc += __shfl_xor(acc, 32, 64);
-    if (h == 0 && c < RB) s_rr[wv][c] = acc;
+    accd += __shfl_xor(accd, 32, 64);
+    if (h == 0 && c < RB) {
+      s_rr[wv][c] = acc;
+      s_rrd[wv][c] = accd;
+    }
   }
   // scaled B operands of the projection: rows 4 s + kq of the 32
   double bop[NS][MB], rsc[NS];
@@ -265,9 +272,11 @@ __global__ __launch_bounds__(256, 2) void k_pcg_update(const T* __restrict__ Q, 
     for (int cb = 0; cb < MB; ++cb) bop[s4][cb] = rsc[s4] * (double)sx[row * XP + 16 * cb + r16];
   }
   __syncthreads();  // s_rr complete
-  if (threadIdx.x < R)
-    rr_part[(size_t)blockIdx.x * R + threadIdx.x] =
-        (s_rr[0][threadIdx.x] + s_rr[1][threadIdx.x]) + (s_rr[2][threadIdx.x] + s_rr[3][threadIdx.x]);
+  if (threadIdx.x < R) {  // block-major, 2 R per block: |r|^2, then |D^{-1/2} r|^2
+    const int c = threadIdx.x;
+    rr_part[(size_t)blockIdx.x * 2 * R + c] = (s_rr[0][c] + s_rr[1][c]) + (s_rr[2][c] + s_rr[3][c]);
+    rr_part[(size_t)blockIdx.x * 2 * R + R + c] = (s_rrd[0][c] + s_rrd[1][c]) + (s_rrd[2][c] + s_rrd[3][c]);
+  }
   const int KR = k * R;
   for (int i0 = 0; PC && i0 < k; i0 += 64) {  // groups of four 16-column blocks of U
     dski_pdbl4 acc[4][MB];
@@ -435,6 +444,235 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, double* _
   }
 }
 
+// The rest of an iteration with a preconditioner M = D + L L^T, after the
+// reductions of t = U^T D^{-1/2} r (coef = w o t, the Woodbury form
+// z = D^{-1/2}(D^{-1/2} r - U coef)) and of |r|^2, |D^{-1/2} r|^2:
+//   r.z = |D^{-1/2} r|^2 - sum_i coef_i t_i   (the same quantity as r^T z),
+//   beta = r.z / r.z_old, x += alpha p, p = z + beta p,
+// so that z never leaves registers.  Every work-group forms each column's r.z
+// from the reduced values in one fixed order (16 lanes per column), so all agree;
+// work-group 0 records the column's next state (beta history, iteration count,
+// convergence, next-parity r.z and flag).  Rows as in k_ts_final: eight 32-row
+// wavefronts per work-group, U coef on the FP64 matrix cores (CB blocks of 16
+// columns, VC more on the vector ALU), coef staged in LDS per 64-column chunk of
+// U, every load but x's issued before the first wait (the column scalars first,
+// then the rows of r and p, then the first chunk).  PC: rank k > 0.
+template <typename T, int CB, int VC, bool PC>
+__global__ __launch_bounds__(512) void k_pcg_step(const T* __restrict__ Rr, T* __restrict__ P,
+                                                  double* __restrict__ Xd, int N, int n, int R, double isf,
+                                                  double isg, const double* __restrict__ U, int k,
+                                                  const double* __restrict__ coef, const double* __restrict__ tv,
+                                                  PcgScal s, int par, double* __restrict__ hist, int max_iter,
+                                                  int fixed_iters) {
+  constexpr int FR = kFinalRows, EB = FR / 16, CW = 16 * CB + VC, XP = CW + 1, HC = (CW + 1) / 2;
+  constexpr int NT = 64 * kFinalWaves, CF = (64 * CW + NT - 1) / NT, QL = 16, QW = 4;  // QL lanes per column
+  static_assert(CW <= kPcgMaxR, "columns per launch");
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double s_coef[64 * XP];
+  __shared__ double s_alpha[kPcgMaxR], s_beta[kPcgMaxR];
+  __shared__ int s_on[kPcgMaxR];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int e0 = (blockIdx.x * kFinalWaves + wv) * FR;
+  double* sz = reinterpret_cast<double*>(smem) + (size_t)wv * FR * XP;
+  const int rl = lane & (FR - 1), hh = lane / FR;  // this lane's row and half of the columns
+  const int e = e0 + rl;
+  const bool in = e < N;
+  // column scalars: QL lanes per column, lane j takes the entries i = j, j + QL, ...
+  static_assert(NT / QL >= kPcgMaxR, "a lane group per column");
+  const int c_q = threadIdx.x / QL, j_q = threadIdx.x % QL;
+  const bool colq = c_q < R;
+  const int cq = colq ? c_q : 0;
+  const int on_q = s.active[par * R + cq];
+  const double rzo_q = s.rz[par * R + cq], rr_q = s.rr[cq], rrd_q = s.rrd[cq], al_q = s.alpha[cq];
+  double tq[QW], cq_[QW];
+#pragma unroll
+  for (int u = 0; u < QW; ++u) {
+    const int i = j_q + QL * u;
+    const bool ok = PC && colq && i < k;
+    tq[u] = ld_or0(tv, (size_t)i * R + cq, 0, ok);
+    cq_[u] = ld_or0(coef, (size_t)i * R + cq, 0, ok);
+  }
+  // this lane's rows of r and p (clamped indices; finished columns are read and
+  // left alone); x is read at the end, where registers are free
+  T rv[HC], pv[HC];
+#pragma unroll
+  for (int j = 0; j < HC; ++j) {
+    const int c = hh * HC + j;
+    const size_t idx = (size_t)(c < R ? c : R - 1) * N + (in ? e : 0);
+    rv[j] = Rr[idx];
+    pv[j] = P[idx];
+  }
+  // a chunk of coef (to LDS) and this wavefront's U operands; U indices are
+  // clamped instead of masked (a column i >= k meets a zero coefficient, a row
+  // past N is never stored)
+  const size_t nk_last = (size_t)N * (size_t)(k > 0 ? k : 1) - 1;
+  double cf[CF], av[16][EB];
+  auto load_chunk = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < CF; ++u) {
+      const int f = threadIdx.x + NT * u, il = f / CW, c = f - il * CW;
+      cf[u] = ld_or0(coef, (size_t)(i0 + il) * R + c, 0, f < 64 * CW && i0 + il < k && c < R);
+    }
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int i = i0 + 4 * st + kq;
+#pragma unroll
+      for (int eb = 0; eb < EB; ++eb) {
+        const size_t o = (size_t)i * N + (size_t)(e0 + 16 * eb + r16);
+        av[st][eb] = U[o < nk_last ? o : nk_last];
+      }
+    }
+  };
+  if (PC) load_chunk(0);
+  {
+    double q = 0.0;  // sum_i coef_i t_i of column c_q
+#pragma unroll
+    for (int u = 0; u < QW; ++u) q += cq_[u] * tq[u];
+    for (int i = j_q + QL * QW; PC && i < k; i += QL)
+      if (colq) q += coef[(size_t)i * R + cq] * tv[(size_t)i * R + cq];
+    q += __shfl_xor(q, 1, 64);
+    q += __shfl_xor(q, 2, 64);
+    q += __shfl_xor(q, 4, 64);
+    q += __shfl_xor(q, 8, 64);
+    if (colq && j_q == 0) {
+      const int c = c_q;
+      double beta = 0.0;
+      if (on_q) {
+        const double rzn = rrd_q - q;
+        if (!(rzn >= 0.0) || !isfinite(rzn)) {
+          if (blockIdx.x == 0) s.flags[1] = 1;
+        }
+        beta = rzo_q > 0.0 ? rzn / rzo_q : 0.0;
+        if (blockIdx.x == 0) {
+          const int it = s.iters[c];
+          const bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (rr_q <= s.tol2[c] * s.bb[c]);
+          if (hist && it < max_iter) hist[(size_t)c * max_iter + it] = beta;
+          s.iters[c] = it + 1;
+          if (done) atomicSub(&s.flags[0], 1);
+          s.rz[(1 - par) * R + c] = rzn;
+          s.active[(1 - par) * R + c] = done ? 0 : 1;
+        }
+      } else if (blockIdx.x == 0) {
+        s.rz[(1 - par) * R + c] = rzo_q;
+        s.active[(1 - par) * R + c] = 0;
+      }
+      s_alpha[c] = al_q;
+      s_beta[c] = beta;
+      s_on[c] = on_q;
+    }
+  }
+  dski_pdbl4 acc[EB][CB];
+  double vacc[EB][VC > 0 ? VC : 1];
+#pragma unroll
+  for (int eb = 0; eb < EB; ++eb) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[eb][cb] = dski_pdbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < VC; ++v) vacc[eb][v] = 0.0;
+  }
+  if (!PC) __syncthreads();  // the column scalars
+  for (int i0 = 0; PC && i0 < k; i0 += 64) {
+    if (i0 > 0) {
+      __syncthreads();  // every wavefront is done with the previous chunk
+      load_chunk(i0);
+    }
+#pragma unroll
+    for (int u = 0; u < CF; ++u) {
+      const int f = threadIdx.x + NT * u, il = f / CW, c = f - il * CW;
+      if (f < 64 * CW) s_coef[il * XP + c] = cf[u];
+    }
+    __syncthreads();  // (the first one also publishes the column scalars)
+    const int steps = min(16, (k - i0 + 3) / 4);  // steps holding a column i < k
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      if (st < steps) {
+        const double* crow = s_coef + (4 * st + kq) * XP;
+        double bv[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) bv[cb] = crow[16 * cb + r16];
+#pragma unroll
+        for (int eb = 0; eb < EB; ++eb) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[eb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st][eb], bv[cb], acc[eb][cb], 0, 0, 0);
+#pragma unroll
+          for (int v = 0; v < VC; ++v) vacc[eb][v] += av[st][eb] * crow[16 * CB + v];
+        }
+      }
+    }
+  }
+  // U coef through LDS (layout as in k_ts_final), then z, x and p per row
+#pragma unroll
+  for (int eb = 0; eb < EB; ++eb) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sz[(16 * eb + kq + 4 * r) * XP + 16 * cb + r16] = acc[eb][cb][r];
+#pragma unroll
+    for (int v = 0; v < VC; ++v) {
+      double x = vacc[eb][v];
+      x += __shfl_xor(x, 16, 64);
+      x += __shfl_xor(x, 32, 64);
+      if (kq == 0) sz[(16 * eb + r16) * XP + 16 * CB + v] = x;
+    }
+  }
+  wave_lds_fence();
+  double xv[HC];
+#pragma unroll
+  for (int j = 0; j < HC; ++j) {
+    const int c = hh * HC + j;
+    xv[j] = Xd[(size_t)(c < R ? c : R - 1) * N + (in ? e : 0)];
+  }
+  const double dsc = e < n ? isf : isg;  // D^{-1/2} of this row
+#pragma unroll
+  for (int j = 0; j < HC; ++j) {
+    const int c = hh * HC + j;
+    if (in && c < R && s_on[c]) {
+      const double z = dsc * (dsc * (double)rv[j] - sz[rl * XP + c]);
+      const double pold = (double)pv[j];
+      const size_t idx = (size_t)c * N + e;
+      Xd[idx] = xv[j] + s_alpha[c] * pold;  // x += alpha p with this iteration's p
+      P[idx] = (T)(z + s_beta[c] * pold);
+    }
+  }
+}
+
+template <typename T, int CB, int VC>
+static dski_status launch_step_cw(const T* Rr, T* P, double* Xd, int N, int n, int R, double isf, double isg,
+                                  const double* U, int k, const double* coef, const double* tv, const PcgScal& s,
+                                  int par, double* hist, int max_iter, int fixed_iters, hipStream_t st) {
+  constexpr size_t sh = sizeof(double) * kFinalWaves * kFinalRows * (16 * CB + VC + 1);
+  constexpr int rows = kFinalRows * kFinalWaves;
+  const int nb = (N + rows - 1) / rows;
+  if (k > 0) {
+    static bool done = false;
+    DSKI_TRY(lds_limit(&k_pcg_step<T, CB, VC, true>, sh, done));
+    k_pcg_step<T, CB, VC, true><<<nb, 64 * kFinalWaves, sh, st>>>(Rr, P, Xd, N, n, R, isf, isg, U, k, coef, tv, s,
+                                                                  par, hist, max_iter, fixed_iters);
+  } else {
+    static bool done = false;
+    DSKI_TRY(lds_limit(&k_pcg_step<T, CB, VC, false>, sh, done));
+    k_pcg_step<T, CB, VC, false><<<nb, 64 * kFinalWaves, sh, st>>>(Rr, P, Xd, N, n, R, isf, isg, U, k, coef, tv,
+                                                                   s, par, hist, max_iter, fixed_iters);
+  }
+  DSKI_HIP(hipGetLastError());
+  return DSKI_OK;
+}
+
+template <typename T>
+static dski_status launch_step(const T* Rr, T* P, double* Xd, int N, int n, int R, double isf, double isg,
+                               const double* U, int k, const double* coef, const double* tv, const PcgScal& s,
+                               int par, double* hist, int max_iter, int fixed_iters, hipStream_t st) {
+  if (R <= 16)
+    return launch_step_cw<T, 1, 0>(Rr, P, Xd, N, n, R, isf, isg, U, k, coef, tv, s, par, hist, max_iter,
+                                   fixed_iters, st);
+  if (R <= 20)
+    return launch_step_cw<T, 1, 4>(Rr, P, Xd, N, n, R, isf, isg, U, k, coef, tv, s, par, hist, max_iter,
+                                   fixed_iters, st);
+  return launch_step_cw<T, 2, 0>(Rr, P, Xd, N, n, R, isf, isg, U, k, coef, tv, s, par, hist, max_iter, fixed_iters,
+                                 st);
+}
+
 // True residual r = b - y (y = K~ x from the FP64-storage operator): stored into Rr
 // for the columns flagged in `verify`, partials of |r|^2 (output-major).
 template <typename T>
@@ -531,7 +769,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   const size_t nr = (size_t)N * R;
   const int nbv = nchunks(N), nbg = gather_blocks(p), nbz = vec_blocks(N);
   const int nbt = upd_blocks(N);  // update work-groups (their partials of t and r.r)
-  const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, nbt)) * R;
+  const size_t npart = (size_t)std::max(std::max(nbv, nbg), std::max(nbz, 2 * nbt)) * R;  // rr_part: 2 R per block
   const size_t ntp = (size_t)nbt * std::max(k, 1) * R;
   // workspace: Rr, Z, P, Q (T), Xd, partials, t partials, t1, scratch (R), coef, scalars
   const size_t kr = (size_t)std::max(k, 1) * R;
@@ -555,7 +793,8 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
   PcgScal s;
   s.rz = coef + kr;
   s.rr = s.rz + 2 * R;
-  s.bb = s.rr + R;
+  s.rrd = s.rr + R;
+  s.bb = s.rrd + R;
   s.alpha = s.bb + R;
   s.tol2 = s.alpha + R;
   double* rz0 = s.tol2 + R;
@@ -590,18 +829,22 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
     DSKI_TRY(mvm_tiled<T>(p, R, P, N, Q, N, pq_part, q));
     DSKI_TRY(launch_update<T>(nbt, Q, Rr, N, n, R, s, par, pq_part, nbg, rr_part, Ur, pc ? k : 0, isf, isg, t_part,
                               hist, max_iter, q));
-    RedJob jr{rr_part, nbt, R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
-    if (pc && k > 0) {
-      RedJob jt{t_part, nbt, k * R, R, t1, pc->w, nullptr, 1.0, coef, nullptr};
-      DSKI_TRY(launch_reduce_bm(jt, &jr, q));
-      DSKI_TRY(launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, k, coef, Z, N, rz_part, q));
+    // |r|^2 to s.rr and |D^{-1/2} r|^2 to s.rrd (2 R outputs), for active columns
+    RedJob jr{rr_part, nbt, 2 * R, R, s.rr, nullptr, nullptr, 0.0, nullptr, s.active + par * R};
+    if (pc) {
+      if (k > 0) {
+        RedJob jt{t_part, nbt, k * R, R, t1, pc->w, nullptr, 1.0, coef, nullptr};
+        DSKI_TRY(launch_reduce_bm(jt, &jr, q));
+      } else {
+        DSKI_TRY(launch_reduce_bm(jr, nullptr, q));
+      }
+      DSKI_TRY(launch_step<T>(Rr, P, Xd, N, n, R, isf, isg, U, k, coef, t1, s, par, hist_b, max_iter, fixed_iters,
+                              q));
     } else {
       DSKI_TRY(launch_reduce_bm(jr, nullptr, q));
-      if (pc)  // rank-0 preconditioner: M = D
-        DSKI_TRY(launch_final<T>(Rr, N, N, n, R, isf, isg, isf, isg, U, 0, nullptr, Z, N, rz_part, q));
+      k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(Rr, P, Xd, N, R, s, par, nullptr, nbz, hist_b, max_iter,
+                                                    fixed_iters);
     }
-    k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(pc ? Z : Rr, P, Xd, N, R, s, par, pc ? rz_part : nullptr, nbz, hist_b,
-                                                  max_iter, fixed_iters);
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
   };
