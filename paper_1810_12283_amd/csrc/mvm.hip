@@ -733,11 +733,10 @@ struct FftShape {
   static constexpr int NL = 2 * PAIRS;                      // lines per work-group
   static constexpr int LGNL = 12 - LG;                      // log2(NL)
   static constexpr int LP = L + L / 8 + 1;                  // odd: pair buffers start on different banks
-  static constexpr bool STAGE = L <= 512;                   // twiddles and spectrum in LDS
-  static constexpr int TW = fft_tw_size(LG);
-  static constexpr size_t lds_bytes() {
-    return sizeof(double2) * (size_t)PAIRS * LP + (STAGE ? sizeof(double2) * TW + sizeof(double) * L : 0);
-  }
+  // The twiddles and the spectrum are read through the caches (every
+  // work-group reads the same small tables): staging them in LDS per
+  // work-group was slower (one more round trip and a barrier before the FFT).
+  static constexpr size_t lds_bytes() { return sizeof(double2) * (size_t)PAIRS * LP; }
 };
 
 // Orders the LDS accesses of the lanes that share a line pair.
@@ -836,16 +835,6 @@ __global__ __launch_bounds__(256) void k_toeplitz(GT* __restrict__ G, long long 
   const int pair = threadIdx.x / TPL;
   const long long line0 = xcd_block(blockIdx.x, gridDim.x) * S::NL;
   double2* buf = smem + (size_t)pair * S::LP;
-  const double2* stw = tw;
-  const double* sspec = spec;
-  if constexpr (S::STAGE) {
-    double2* t = smem + (size_t)S::PAIRS * S::LP;
-    double* sp = reinterpret_cast<double*>(t + S::TW);
-    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
-    for (int f = threadIdx.x; f < L; f += 256) sp[f] = spec[f];
-    stw = t;
-    sspec = sp;
-  }
   double2 v[E];
   const long long la = line0 + 2 * pair;
   if (inner == 1) {
@@ -857,7 +846,6 @@ __global__ __launch_bounds__(256) void k_toeplitz(GT* __restrict__ G, long long 
       const bool in = pos < m;
       v[e] = make_double2(in && va ? (double)A[pos] : 0.0, in && vb ? (double)A[m + pos] : 0.0);
     }
-    if constexpr (S::STAGE) __syncthreads();
   } else {
     // line bases of the block: line = q inner + r  ->  q m inner + r
     {
@@ -895,10 +883,10 @@ __global__ __launch_bounds__(256) void k_toeplitz(GT* __restrict__ G, long long 
     }
     pair_sync<LG>();
   }
-  fft_run<LG, +1, 0>(v, buf, stw, lp);
+  fft_run<LG, +1, 0>(v, buf, tw, lp);
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sspec[lp + (e / RL) * TPL + (e % RL) * (L / RL)]);
-  fft_run<LG, -1, 0>(v, buf, stw, lp);
+  for (int e = 0; e < E; ++e) v[e] = cscale(v[e], spec[lp + (e / RL) * TPL + (e % RL) * (L / RL)]);
+  fft_run<LG, -1, 0>(v, buf, tw, lp);
   if (inner == 1) {
     GT* A = G + la * m;
     const bool va = la < nlines, vb = la + 1 < nlines;
@@ -1168,13 +1156,6 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long 
   const int lp = threadIdx.x % TPL;
   const int slot = threadIdx.x / TPL;
   double2* buf = smem + (size_t)slot * S::LP;
-  const double2* stw = tw;
-  if constexpr (S::STAGE) {
-    double2* t = smem + (size_t)S::PAIRS * S::LP;
-    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
-    stw = t;
-    __syncthreads();
-  }
   const long long line = (long long)blockIdx.x * S::PAIRS + slot;
   const bool ok = line < nlines;
   long long base = 0;
@@ -1193,7 +1174,7 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long 
     const int pos = DIR > 0 ? fft_pos_nat<LG>(lp, e) : fft_pos_freq<LG>(lp, e);
     v[e] = ok && pos < map.valid ? Z[base + (long long)pos * step] : make_double2(0.0, 0.0);
   }
-  fft_run<LG, DIR, 0>(v, buf, stw, lp);
+  fft_run<LG, DIR, 0>(v, buf, tw, lp);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1215,13 +1196,6 @@ __global__ __launch_bounds__(256) void k_fft_last_spec(double2* __restrict__ Z, 
   const int lp = threadIdx.x % TPL;
   const int slot = threadIdx.x / TPL;
   double2* buf = smem + (size_t)slot * S::LP;
-  const double2* stw = tw;
-  if constexpr (S::STAGE) {
-    double2* t = smem + (size_t)S::PAIRS * S::LP;
-    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
-    stw = t;
-    __syncthreads();
-  }
   const long long line = (long long)blockIdx.x * S::PAIRS + slot;
   const bool ok = line < nlines;
   double2* A = Z + (ok ? line : 0) * L;
@@ -1232,10 +1206,10 @@ __global__ __launch_bounds__(256) void k_fft_last_spec(double2* __restrict__ Z, 
     const int pos = fft_pos_nat<LG>(lp, e);
     v[e] = ok && pos < valid ? A[pos] : make_double2(0.0, 0.0);
   }
-  fft_run<LG, +1, 0>(v, buf, stw, lp);
+  fft_run<LG, +1, 0>(v, buf, tw, lp);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sp[fft_pos_freq<LG>(lp, e)]);
-  fft_run<LG, -1, 0>(v, buf, stw, lp);
+  fft_run<LG, -1, 0>(v, buf, tw, lp);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) A[fft_pos_nat<LG>(lp, e)] = v[e];
@@ -1335,7 +1309,7 @@ template <int LG, int DIR>
 static dski_status launch_fft_axis(double2* Z, long long nlines, const LineMap& map, const double2* tw,
                                    hipStream_t st) {
   using S = FftShape<LG>;
-  const size_t sh = sizeof(double2) * ((size_t)S::PAIRS * S::LP + (S::STAGE ? S::TW : 0));
+  const size_t sh = S::lds_bytes();
   if (sh > 64 * 1024) {
     static bool done = false;
     if (!done) {
@@ -1354,7 +1328,7 @@ template <int LG>
 static dski_status launch_fft_last(double2* Z, long long nlines, long long nouter, int valid, const double2* tw,
                                    const double* spec, hipStream_t st) {
   using S = FftShape<LG>;
-  const size_t sh = sizeof(double2) * ((size_t)S::PAIRS * S::LP + (S::STAGE ? S::TW : 0));
+  const size_t sh = S::lds_bytes();
   if (sh > 64 * 1024) {
     static bool done = false;
     if (!done) {
