@@ -733,10 +733,15 @@ struct FftShape {
   static constexpr int NL = 2 * PAIRS;                      // lines per work-group
   static constexpr int LGNL = 12 - LG;                      // log2(NL)
   static constexpr int LP = L + L / 8 + 1;                  // odd: pair buffers start on different banks
-  // The twiddles and the spectrum are read through the caches (every
-  // work-group reads the same small tables): staging them in LDS per
-  // work-group was slower (one more round trip and a barrier before the FFT).
+  // The Toeplitz product reads its twiddles and spectrum through the caches
+  // (every work-group reads the same small tables; staging them in LDS per
+  // work-group was slower: one more round trip and a barrier before the FFT).
+  // The multi-level (spline) passes stage the twiddles up to L = 512: there a
+  // different spectrum row per line streams through the caches beside them.
+  static constexpr bool TW_LDS = L <= 512;
+  static constexpr int TW = fft_tw_size(LG);
   static constexpr size_t lds_bytes() { return sizeof(double2) * (size_t)PAIRS * LP; }
+  static constexpr size_t lds_bytes_tw() { return sizeof(double2) * ((size_t)PAIRS * LP + (TW_LDS ? TW : 0)); }
 };
 
 // Orders the LDS accesses of the lanes that share a line pair.
@@ -1156,6 +1161,13 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long 
   const int lp = threadIdx.x % TPL;
   const int slot = threadIdx.x / TPL;
   double2* buf = smem + (size_t)slot * S::LP;
+  const double2* stw = tw;
+  if constexpr (S::TW_LDS) {
+    double2* t = smem + (size_t)S::PAIRS * S::LP;
+    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
+    stw = t;
+    __syncthreads();
+  }
   const long long line = (long long)blockIdx.x * S::PAIRS + slot;
   const bool ok = line < nlines;
   long long base = 0;
@@ -1174,7 +1186,7 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2* __restrict__ Z, long 
     const int pos = DIR > 0 ? fft_pos_nat<LG>(lp, e) : fft_pos_freq<LG>(lp, e);
     v[e] = ok && pos < map.valid ? Z[base + (long long)pos * step] : make_double2(0.0, 0.0);
   }
-  fft_run<LG, DIR, 0>(v, buf, tw, lp);
+  fft_run<LG, DIR, 0>(v, buf, stw, lp);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1196,6 +1208,13 @@ __global__ __launch_bounds__(256) void k_fft_last_spec(double2* __restrict__ Z, 
   const int lp = threadIdx.x % TPL;
   const int slot = threadIdx.x / TPL;
   double2* buf = smem + (size_t)slot * S::LP;
+  const double2* stw = tw;
+  if constexpr (S::TW_LDS) {
+    double2* t = smem + (size_t)S::PAIRS * S::LP;
+    for (int f = threadIdx.x; f < S::TW; f += 256) t[f] = tw[f];
+    stw = t;
+    __syncthreads();
+  }
   const long long line = (long long)blockIdx.x * S::PAIRS + slot;
   const bool ok = line < nlines;
   double2* A = Z + (ok ? line : 0) * L;
@@ -1206,10 +1225,10 @@ __global__ __launch_bounds__(256) void k_fft_last_spec(double2* __restrict__ Z, 
     const int pos = fft_pos_nat<LG>(lp, e);
     v[e] = ok && pos < valid ? A[pos] : make_double2(0.0, 0.0);
   }
-  fft_run<LG, +1, 0>(v, buf, tw, lp);
+  fft_run<LG, +1, 0>(v, buf, stw, lp);
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sp[fft_pos_freq<LG>(lp, e)]);
-  fft_run<LG, -1, 0>(v, buf, tw, lp);
+  fft_run<LG, -1, 0>(v, buf, stw, lp);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) A[fft_pos_nat<LG>(lp, e)] = v[e];
@@ -1309,7 +1328,7 @@ template <int LG, int DIR>
 static dski_status launch_fft_axis(double2* Z, long long nlines, const LineMap& map, const double2* tw,
                                    hipStream_t st) {
   using S = FftShape<LG>;
-  const size_t sh = S::lds_bytes();
+  const size_t sh = S::lds_bytes_tw();
   if (sh > 64 * 1024) {
     static bool done = false;
     if (!done) {
@@ -1328,7 +1347,7 @@ template <int LG>
 static dski_status launch_fft_last(double2* Z, long long nlines, long long nouter, int valid, const double2* tw,
                                    const double* spec, hipStream_t st) {
   using S = FftShape<LG>;
-  const size_t sh = S::lds_bytes();
+  const size_t sh = S::lds_bytes_tw();
   if (sh > 64 * 1024) {
     static bool done = false;
     if (!done) {
