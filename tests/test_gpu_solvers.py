@@ -346,3 +346,32 @@ def test_pcg_true_residual_column_widths(R, k):
     tr = krylov.true_relres(op.matvec, B, from_gpu(X))
     say("  iters", max(iters), "true relres", tr.max())
     assert tr.max() <= 1e-4
+
+
+def test_pcg_rank0_preconditioner_against_jacobi_oracle():
+    """A rank-0 pivoted-Cholesky preconditioner is M = D, the noise diagonal
+    (the fused iteration without its low-rank term), on 17 columns (one
+    matrix-core column block plus vector columns): with FP64 vectors the
+    iteration counts follow the oracle's PCG with the same diagonal
+    preconditioner (within 2 % + 3), and with FP32 and FP64 vectors the
+    oracle's FP64 true residual meets the tolerance."""
+    W = workloads.terrain(n=3000, grid=60)
+    say("pcg rank 0")
+    plan, op = make(W)
+    pc = plan.pivchol(0)
+    assert pc.rank == 0
+    R, tol = 17, 1e-3
+    B = np.concatenate([W.y[:, None], orng.rademacher(SEED, 0, R - 1, op.N)], axis=1)
+    B = B.astype(np.float32).astype(np.float64)
+    ref = krylov.pcg(op.matvec, B[:, :3], lambda V: V / op.Dn.reshape((-1,) + (1,) * (V.ndim - 1)), tol=tol,
+                     max_iter=20000)
+    X64, it64, _, st64, _ = plan.pcg(torch.tensor(B.T.copy(), device="cuda"), pc, tol=tol, max_iter=20000)
+    X32, it32, _, st32, _ = plan.pcg(to_gpu(B), pc, tol=tol, max_iter=20000)
+    tr64 = krylov.true_relres(op.matvec, B, X64.cpu().numpy().T)
+    tr32 = krylov.true_relres(op.matvec, B, from_gpu(X32))
+    say("  iters oracle", list(ref["iters"]), "fp64", it64[:3], "fp32", max(it32), "true relres", tr64.max(),
+        tr32.max())
+    assert st64 == 0 and st32 == 0
+    assert tr64.max() <= tol and tr32.max() <= tol
+    for c in range(3):
+        assert abs(it64[c] - ref["iters"][c]) <= 0.02 * ref["iters"][c] + 3
