@@ -53,11 +53,16 @@ def source_digest(path=MVM_SOURCE):
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
+def _fastest(times):
+    """Index of the smallest time; -1 marks a variant that was not timed."""
+    return min(range(len(times)), key=lambda i: times[i] if times[i] >= 0 else float("inf"))
+
+
 def tuned_variants(tune):
     """The variants the tuner keeps: the first fastest scatter and gather form, and
     per axis the FFT unless the dense form (timed, not -1) is strictly faster."""
     import numpy as np
-    return {"scatter": int(np.argmin(tune["scatter_us"])), "gather": int(np.argmin(tune["gather_us"])),
+    return {"scatter": _fastest(tune["scatter_us"]), "gather": _fastest(tune["gather_us"]),
             "kuu": [0 if (t[1] < 0 or t[0] <= t[1]) else 1 for t in tune["kuu_us"]]}
 
 
@@ -738,8 +743,8 @@ def main(argv=None):
                               "copy_gbs_same_size": round(2 * (Bs // 8) * 4 / (ms_copy * 1e-3) / 1e9, 1),
                               "stage_ms": {k: round(v, 4) for k, v in stage.items()},
                               "setup_and_tune_s": round(t_setup, 3),
-                              "tuned": {"scatter": int(np.argmin(tune["scatter_us"])),
-                                        "gather": int(np.argmin(tune["gather_us"])),
+                              "tuned": {"scatter": _fastest(tune["scatter_us"]),
+                                        "gather": _fastest(tune["gather_us"]),
                                         "kuu": ["fft" if t[1] < 0 or t[0] <= t[1] else "dense"
                                                 for t in tune["kuu_us"]]}}),
                   flush=True)
@@ -765,6 +770,8 @@ def main(argv=None):
         # every scatter, gather and K_UU variant a few times (the tuner's pick is not
         # stable while counters are collected; the summary keys traffic by variant)
         for sv in range(len(tuned_first["scatter_us"])):
+            if tuned_first["scatter_us"][sv] < 0:  # not a form of this plan
+                continue
             plan.set_variants(sv, 0)
             mark(f"scatter_v{sv}")
             for _ in range(3):

@@ -269,14 +269,18 @@ dski_status dski_mvm_stage(dski_plan plan, int stage, int R, const float* V, int
 /* Times the interchangeable kernel variants for R right-hand sides on this
  * plan's shape (scatter: LDS node tiles with the base number of columns per
  * work-group / direct one column per thread / direct two columns per thread /
- * LDS node tiles with 1.5, 2 and 5 times the base columns; gather: 2 / 1 / 4
- * columns per thread; K_UU factor of each axis: circulant FFT / dense Toeplitz
- * product on the FP64 matrix cores) and keeps the fastest of each.  Scatter
- * variants give bitwise-identical results, and so do gather variants; the
- * K_UU variants agree up to rounding.  times_host (15 entries, may be NULL)
- * receives the measured microseconds: scatter (6), gather (3), then FFT and
- * dense for axes 0, 1, 2 (all 0 for a D-SKIP plan; dense is -1 on an axis
- * longer than 448 nodes, which has no dense form).  The scatter forms are
+ * LDS node tiles with 1.5, 2 and 5 times the base columns / in 3-D, node tiles
+ * whose work is split into (node, first-axis cell) items ordered by length;
+ * gather: 2 / 1 / 4 columns per thread; K_UU factor of each axis: circulant
+ * FFT / dense Toeplitz product on the FP64 matrix cores) and keeps the fastest
+ * of each.  Scatter variants 0-5 give bitwise-identical results, and so do the
+ * gather variants; scatter variant 6 agrees with them up to the grouping of
+ * its additions (outside 3-D it runs variant 3's kernel and is not timed); the
+ * K_UU variants agree up to rounding.  times_host (16 entries, may be NULL)
+ * receives the measured microseconds: scatter (7; -1 for variant 6 outside
+ * 3-D), gather (3), then FFT and dense for axes 0, 1, 2 (all 0 for a D-SKIP
+ * plan; dense is -1 on an axis longer than 448 nodes, which has no dense
+ * form).  The scatter forms are
  * timed once more with FP64 column values (their column chunks differ); that
  * choice, not reported, serves the FP64 MVMs and solvers.  1 <= R <= 32. */
 dski_status dski_autotune(dski_plan plan, int R, double* times_host, dski_stream stream);
@@ -292,7 +296,7 @@ dski_status dski_autotune(dski_plan plan, int R, double* times_host, dski_stream
 dski_status dski_autotune_cached(dski_plan plan, int R, const char* cache_path, int* hit_host,
                                  double* times_host, dski_stream stream);
 
-/* Select the scatter (0..5, for FP32 and FP64 column values alike) and gather
+/* Select the scatter (0..6, for FP32 and FP64 column values alike) and gather
  * (0..2) variants directly. */
 dski_status dski_set_variants(dski_plan plan, int scatter_variant, int gather_variant);
 

@@ -16,7 +16,7 @@
 
 namespace dski {
 
-constexpr int kScatterVariants = 6;
+constexpr int kScatterVariants = 7;  // 6: the grouped 3-D form (elsewhere the same kernel as 3, not timed)
 constexpr int kGatherVariants = 3;
 constexpr int kTuneTimes = kScatterVariants + kGatherVariants + 2 * DSKI_MAXD;
 
@@ -85,7 +85,10 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
   int best_s = 0;
   if (p->kind == 0) DSKI_TRY(p->grid.reserve(sizeof(double) * (size_t)p->M * R));
   double* G = p->grid.as<double>();
-  for (int v = 0; v < (p->kind == 0 ? kScatterVariants : 0); ++v) {
+  // variant 6 exists in 3-D only (elsewhere it repeats variant 3): time -1, never chosen
+  const int nsv = p->d == 3 ? kScatterVariants : kScatterVariants - 1;
+  if (p->kind == 0 && p->d != 3) t[kScatterVariants - 1] = -1.0;
+  for (int v = 0; v < (p->kind == 0 ? nsv : 0); ++v) {
     p->scatter_variant = v;
     DSKI_TRY(time_us([&]() { return scatter<float, double>(p, R, V, N, G, st); }, reps, st, &t[v]));
     if (t[v] < t[best_s]) best_s = v;
@@ -101,7 +104,7 @@ extern "C" dski_status dski_autotune(dski_plan p, int R, double* times_host, dsk
     DSKI_HIP(hipGetLastError());
     int best64 = 0;
     double t64[kScatterVariants] = {0};
-    for (int v = 0; v < kScatterVariants; ++v) {
+    for (int v = 0; v < nsv; ++v) {
       p->scatter_variant64 = v;
       DSKI_TRY(time_us([&]() { return scatter<double, double>(p, R, V64, N, G, st); }, reps, st, &t64[v]));
       if (t64[v] < t64[best64]) best64 = v;

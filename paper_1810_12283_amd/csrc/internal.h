@@ -137,6 +137,11 @@ struct dski_plan_s {
   int* tile_pts = nullptr;     // slots: point (tile order)
   int* tile_cl = nullptr;      // slots: last-axis anchor node of the point
   long long tile_slots = 0;
+  // 3-D grouped scatter (see mvm.hip): per staged chunk of every tile, its
+  // (node, first-axis cell) items ordered by their work
+  unsigned short* grp_items = nullptr;  // node * 8 + group
+  int* grp_chunk_off = nullptr;         // chunks + 1 item offsets
+  int* grp_tile_chunk = nullptr;        // tiles + 1 first chunk of each tile
   // workspaces
   dski::DevBuf grid;           // grid buffer, M * Rmax values (FP32 or FP64)
   dski::DevBuf vin, vout;      // tile-ordered FP32 vectors

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <mutex>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -246,6 +247,89 @@ constexpr int scatter_pmax() {
   return D == 3 ? 128 : 256;
 }
 
+// Stages region slots [q0, q0 + PMAX) of a tile, one thread one point: its
+// last-axis anchor node, its weights (value and derivative per axis, from the
+// offsets) and its CR column values (zeros for columns past rc).
+template <int D, int S, int CR, typename T>
+__device__ __forceinline__ void stage_chunk(int q0, int total, long long off, const int* __restrict__ tile_pts,
+                                            const int* __restrict__ tile_cl, const double* __restrict__ toff, int n,
+                                            const GeoK& g, const T* __restrict__ V, int ldv, int r0, int rc,
+                                            double* s_w, T* s_v, int* s_cl) {
+  constexpr int PMAX = scatter_pmax<D>();
+  constexpr int WS = 2 * S * D + 1;
+  const int q = threadIdx.x;
+  if (q < PMAX && q0 + q < total) {
+    const int kq = tile_pts[off + q0 + q];
+    const int cq = tile_cl[off + q0 + q];
+    double tq[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) tq[a] = toff[(size_t)a * n + kq];
+    T x[CR * (D + 1)];
+#pragma unroll
+    for (int r = 0; r < CR; ++r)
+#pragma unroll
+      for (int b = 0; b <= D; ++b)
+        x[r * (D + 1) + b] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
+                                    (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double w[S], dw[S];
+      interp_weights<S>(tq[a], g.invh[a], w, dw);
+#pragma unroll
+      for (int o = 0; o < S; ++o) {
+        s_w[q * WS + a * 2 * S + o] = w[o];
+        s_w[q * WS + a * 2 * S + S + o] = dw[o];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
+    s_cl[q] = cq;
+  }
+}
+
+// Adds the staged points of slots [qs, qe) (chunk-local index slot - q0) of one
+// cell row of a node to acc, in slot order, two points per step: both points'
+// LDS loads are issued before the first product (the loop is bound by
+// dependent LDS latency), then the points are added in order, exactly as one
+// at a time.  wo[a]: the LDS offsets of the outer axes' weights in this row;
+// jl: the node's index on the last axis.
+template <int D, int S, int CR, typename T>
+__device__ __forceinline__ void accum_row(double (&acc)[CR], int qs, int qe, int q0, const int (&wo)[D], int jl,
+                                          const double* s_w, const T* s_v, const int* s_cl) {
+  constexpr int H = S / 2 - 1;
+  constexpr int WS = 2 * S * D + 1;
+  const int last = D - 1;
+  int qq = qs;
+  for (; qq + 1 < qe; qq += 2) {
+    const int qa = qq - q0, qb = qa + 1;
+    const int cla = s_cl[qa], clb = s_cl[qb];
+    double wva[D], wda[D], wvb[D], wdb[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int oa = a == last ? last * 2 * S + jl - cla + H : wo[a];
+      const int ob = a == last ? last * 2 * S + jl - clb + H : wo[a];
+      wva[a] = s_w[qa * WS + oa];
+      wda[a] = s_w[qa * WS + S + oa];
+      wvb[a] = s_w[qb * WS + ob];
+      wdb[a] = s_w[qb * WS + S + ob];
+    }
+    scatter_accum<D, CR>(acc, wva, wda, s_v + (size_t)qa * CR * (D + 1));
+    scatter_accum<D, CR>(acc, wvb, wdb, s_v + (size_t)qb * CR * (D + 1));
+  }
+  if (qq < qe) {
+    const int ql = qq - q0;
+    const int cl = s_cl[ql];
+    double wv[D], wd[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int o = a == last ? last * 2 * S + jl - cl + H : wo[a];
+      wv[a] = s_w[ql * WS + o];
+      wd[a] = s_w[ql * WS + S + o];
+    }
+    scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)ql * CR * (D + 1));
+  }
+}
+
 template <int D, int S, int CR, typename T, typename GT>
 __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cell,
                                                      const double* __restrict__ toff,
@@ -320,34 +404,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
   // order whatever the chunking (rows ascending, slots ascending in a row).
   for (int q0 = 0; q0 < total; q0 += PMAX) {
     if (q0 > 0) __syncthreads();  // every node is done with the previous chunk
-    const int q = threadIdx.x;
-    if (q < PMAX && q0 + q < total) {
-      const int kq = tile_pts[off + q0 + q];
-      const int cq = tile_cl[off + q0 + q];
-      double tq[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a) tq[a] = toff[(size_t)a * n + kq];
-      T x[CR * (D + 1)];
-#pragma unroll
-      for (int r = 0; r < CR; ++r)
-#pragma unroll
-        for (int b = 0; b <= D; ++b)
-          x[r * (D + 1) + b] = ld_or0(V, (size_t)(r0 + r) * ldv + (size_t)b * n + kq,
-                                      (size_t)r0 * ldv + (size_t)b * n + kq, r < rc);
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        double w[S], dw[S];
-        interp_weights<S>(tq[a], g.invh[a], w, dw);
-#pragma unroll
-        for (int o = 0; o < S; ++o) {
-          s_w[q * WS + a * 2 * S + o] = w[o];
-          s_w[q * WS + a * 2 * S + S + o] = dw[o];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < CR * (D + 1); ++e) s_v[q * CR * (D + 1) + e] = x[e];
-      s_cl[q] = cq;
-    }
+    stage_chunk<D, S, CR, T>(q0, total, off, tile_pts, tile_cl, toff, n, g, V, ldv, r0, rc, s_w, s_v, s_cl);
     __syncthreads();
     if (!inside) continue;
     const int q1 = min(total, q0 + PMAX);
@@ -367,38 +424,7 @@ __global__ __launch_bounds__(256) void k_scatter_lds(const int* __restrict__ cel
       int wo[D];  // LDS offsets of the outer axes' weights in this row
 #pragma unroll
       for (int a = 0; a < last; ++a) wo[a] = a * 2 * S + j[a] - c[a] + H;
-      // two points per step: both points' LDS loads are issued before the first
-      // product (the loop is bound by dependent LDS latency), then the points
-      // are added in order, exactly as one at a time
-      int qq = qs;
-      for (; qq + 1 < qe; qq += 2) {
-        const int qa = qq - q0, qb = qa + 1;
-        const int cla = s_cl[qa], clb = s_cl[qb];
-        double wva[D], wda[D], wvb[D], wdb[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const int oa = a == last ? last * 2 * S + j[a] - cla + H : wo[a];
-          const int ob = a == last ? last * 2 * S + j[a] - clb + H : wo[a];
-          wva[a] = s_w[qa * WS + oa];
-          wda[a] = s_w[qa * WS + S + oa];
-          wvb[a] = s_w[qb * WS + ob];
-          wdb[a] = s_w[qb * WS + S + ob];
-        }
-        scatter_accum<D, CR>(acc, wva, wda, s_v + (size_t)qa * CR * (D + 1));
-        scatter_accum<D, CR>(acc, wvb, wdb, s_v + (size_t)qb * CR * (D + 1));
-      }
-      if (qq < qe) {
-        const int ql = qq - q0;
-        const int cl = s_cl[ql];
-        double wv[D], wd[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const int o = a == last ? last * 2 * S + j[a] - cl + H : wo[a];
-          wv[a] = s_w[ql * WS + o];
-          wd[a] = s_w[ql * WS + S + o];
-        }
-        scatter_accum<D, CR>(acc, wv, wd, s_v + (size_t)ql * CR * (D + 1));
-      }
+      accum_row<D, S, CR, T>(acc, qs, qe, q0, wo, j[last], s_w, s_v, s_cl);
     }
   }
   if (!inside) return;
@@ -451,6 +477,123 @@ static void launch_scatter(dski_plan p, int R, const T* V, int ldv, GT* G, hipSt
   k_scatter_lds<D, S, CR, T, GT><<<grid, 256, 0, st>>>(p->cell, p->toff, p->cell_start, p->n, g, p->tile_off,
                                                         p->tile_lcs, p->tile_pts, p->tile_cl, V, ldv, R, cr, G,
                                                         p->M);
+}
+
+// Grouped 3-D variant.  On surface data a node's point count, and with it the
+// length of its loop, varies widely within a wavefront, and the tiled form
+// steps as long as the busiest node of the wavefront in every cell row (about
+// one lane pair in twelve busy on the torus).  Here the unit of work is an
+// item: one node and one cell c0 of its first axis, i.e. the S cell rows of
+// its support with that c0.  At plan set-up the host lists, for every staged
+// chunk of a tile, the items with points in that chunk, longest first, so that
+// the lanes of a wavefront take items of similar length.  An item continues
+// the running sum of its (node, c0) in LDS from chunk to chunk, adding its
+// points in the tiled form's order; at the end each node adds its S partial
+// sums in c0 order.  The result equals the tiled form's up to that grouping of
+// the additions (it is not bitwise equal to the other forms).
+template <int S, typename T>
+constexpr int scatter_grp_cr() {
+  return sizeof(T) == 4 ? 3 : 2;
+}
+
+template <int S, int CR, typename T, typename GT>
+__global__ __launch_bounds__(256) void k_scatter_grp(const double* __restrict__ toff, int n, GeoK g,
+                                                     const int* __restrict__ tile_off,
+                                                     const int* __restrict__ tile_lcs,
+                                                     const int* __restrict__ tile_pts,
+                                                     const int* __restrict__ tile_cl,
+                                                     const unsigned short* __restrict__ items,
+                                                     const int* __restrict__ chunk_off,
+                                                     const int* __restrict__ tile_chunk, const T* __restrict__ V,
+                                                     int ldv, int R, int cr, GT* __restrict__ G, long long M) {
+  constexpr int D = 3;
+  constexpr int PMAX = scatter_pmax<D>();
+  constexpr int H = S / 2 - 1;
+  using TS = TileShape<D, S>;
+  constexpr int WS = 2 * S * D + 1;
+  static_assert(TS::e0 * TS::e1 * TS::e2 == 256, "one node per thread at the end");
+  __shared__ double s_w[PMAX * WS];
+  __shared__ T s_v[PMAX * CR * (D + 1)];
+  __shared__ int s_lcs[TS::max_cells + 1];
+  __shared__ int s_cl[PMAX];
+  __shared__ double s_part[256 * S * CR];  // running sums per (node, c0 - lo0, column)
+  const TileRegion<D, S> TR(blockIdx.x, g);
+  const int r0 = blockIdx.y * cr;
+  const int rc = min(cr, R - r0);
+  const long long off = tile_off[blockIdx.x];
+  const int total = (int)(tile_off[blockIdx.x + 1] - off);
+  {
+    const int* lcs = tile_lcs + (size_t)blockIdx.x * (TS::max_cells + 1);
+    for (int f = threadIdx.x; f <= TR.ncells; f += blockDim.x) s_lcs[f] = lcs[f];
+  }
+  for (int f = threadIdx.x; f < 256 * S * CR; f += blockDim.x) s_part[f] = 0.0;
+  int ch = tile_chunk[blockIdx.x];
+  for (int q0 = 0; q0 < total; q0 += PMAX, ++ch) {
+    if (q0 > 0) __syncthreads();  // every item is done with the previous chunk
+    stage_chunk<D, S, CR, T>(q0, total, off, tile_pts, tile_cl, toff, n, g, V, ldv, r0, rc, s_w, s_v, s_cl);
+    __syncthreads();
+    const int q1 = min(total, q0 + PMAX);
+    const int ie = chunk_off[ch + 1];
+    for (int it = chunk_off[ch] + threadIdx.x; it < ie; it += blockDim.x) {
+      const int code = items[it];
+      const int node = code >> 3, grp = code & 7;
+      int j[D], lo[D], hi[D];
+      j[0] = TR.origin[0] + node / (TS::e1 * TS::e2);
+      j[1] = TR.origin[1] + (node / TS::e2) % TS::e1;
+      j[2] = TR.origin[2] + node % TS::e2;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        lo[a] = max(H, j[a] - (S - 1 - H));
+        hi[a] = min(g.nc[a] + H - 1, j[a] + H);
+      }
+      const int c0 = lo[0] + grp;
+      double* part = s_part + (size_t)(node * S + grp) * CR;
+      double acc[CR];
+#pragma unroll
+      for (int r = 0; r < CR; ++r) acc[r] = part[r];
+      int wo[D];
+      wo[0] = j[0] - c0 + H;
+      for (int c1 = lo[1]; c1 <= hi[1]; ++c1) {
+        const int lrow = (c0 - TR.rlo[0]) * TR.span[1] + (c1 - TR.rlo[1]);
+        const int qs = max(q0, s_lcs[lrow * TR.span[2] + lo[2] - TR.rlo[2]]);
+        const int qe = min(q1, s_lcs[lrow * TR.span[2] + hi[2] - TR.rlo[2] + 1]);
+        wo[1] = 2 * S + j[1] - c1 + H;
+        accum_row<D, S, CR, T>(acc, qs, qe, q0, wo, j[2], s_w, s_v, s_cl);
+      }
+#pragma unroll
+      for (int r = 0; r < CR; ++r) part[r] = acc[r];
+    }
+  }
+  __syncthreads();
+  int j[D];
+  j[0] = TR.origin[0] + threadIdx.x / (TS::e1 * TS::e2);
+  j[1] = TR.origin[1] + (threadIdx.x / TS::e2) % TS::e1;
+  j[2] = TR.origin[2] + threadIdx.x % TS::e2;
+  if (j[0] >= g.m[0] || j[1] >= g.m[1] || j[2] >= g.m[2]) return;
+  const int ng = min(g.nc[0] + H - 1, j[0] + H) - max(H, j[0] - (S - 1 - H)) + 1;
+  const double* part = s_part + (size_t)threadIdx.x * S * CR;
+  const long long node = ((long long)j[0] * g.m[1] + j[1]) * g.m[2] + j[2];
+#pragma unroll
+  for (int r = 0; r < CR; ++r) {
+    double sum = part[r];
+    for (int q = 1; q < ng; ++q) sum += part[q * CR + r];
+    if (r < rc) __builtin_nontemporal_store((GT)sum, &G[(size_t)(r0 + r) * M + node]);
+  }
+}
+
+template <int S, typename T, typename GT>
+static void launch_scatter_grp(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t st) {
+  GeoK g = geo_of(p);
+  using TS = TileShape<3, S>;
+  long long tiles = 1;
+  for (int a = 0; a < 3; ++a) tiles *= (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
+  constexpr int CR = scatter_grp_cr<S, T>();
+  const int nch = (R + CR - 1) / CR;
+  const int cr = (R + nch - 1) / nch;
+  dim3 grid((unsigned)tiles, nch);
+  k_scatter_grp<S, CR, T, GT><<<grid, 256, 0, st>>>(p->toff, p->n, g, p->tile_off, p->tile_lcs, p->tile_pts,
+                                                     p->tile_cl, p->grp_items, p->grp_chunk_off, p->grp_tile_chunk,
+                                                     V, ldv, R, cr, G, p->M);
 }
 
 // Direct variant: one thread per (grid node, CRD columns), no LDS; cell ranges,
@@ -563,6 +706,12 @@ static void scatter_dispatch(dski_plan p, int R, const T* V, int ldv, GT* G, hip
     case 3: launch_scatter<D, S, T, GT, 1>(p, R, V, ldv, G, st); break;
     case 4: launch_scatter<D, S, T, GT, 2>(p, R, V, ldv, G, st); break;
     case 5: launch_scatter<D, S, T, GT, 3>(p, R, V, ldv, G, st); break;
+    case 6:  // grouped in 3-D; elsewhere the tiled form of variant 3
+      if constexpr (D == 3)
+        launch_scatter_grp<S, T, GT>(p, R, V, ldv, G, st);
+      else
+        launch_scatter<D, S, T, GT, 1>(p, R, V, ldv, G, st);
+      break;
     default: launch_scatter<D, S, T, GT, 0>(p, R, V, ldv, G, st); break;
   }
 }
@@ -588,6 +737,102 @@ dski_status scatter(dski_plan p, int R, const T* V, int ldv, GT* G, hipStream_t 
 }
 template dski_status scatter<float, double>(dski_plan, int, const float*, int, double*, hipStream_t);
 template dski_status scatter<double, double>(dski_plan, int, const double*, int, double*, hipStream_t);
+
+// Item lists of the grouped 3-D scatter (see k_scatter_grp), built on the host
+// from the cell ranges with the tiles' region geometry: for every chunk of
+// PMAX region slots of every tile, the (node, c0) items with points in it, by
+// decreasing work (pairs of points per cell row plus one step per row), ties
+// in (node, c0) order.
+template <int S>
+static dski_status build_groups3(dski_plan p, const GeoK& g, long long tiles, const std::vector<int>& off,
+                                 hipStream_t st) {
+  using TS = TileShape<3, S>;
+  constexpr int H = S / 2 - 1, PMAX = scatter_pmax<3>();
+  std::vector<int> cs((size_t)p->ncells + 1);
+  DSKI_HIP(hipMemcpyAsync(cs.data(), p->cell_start, sizeof(int) * cs.size(), hipMemcpyDeviceToHost, st));
+  DSKI_HIP(hipStreamSynchronize(st));
+  int nt[3];
+  for (int a = 0; a < 3; ++a) nt[a] = (g.m[a] + TS::ext(a) - 1) / TS::ext(a);
+  std::vector<int> tile_chunk((size_t)tiles + 1), chunk_off(1, 0), lcs;
+  std::vector<unsigned short> items;
+  std::vector<std::pair<int, int>> list;  // (work, code)
+  int nchunks = 0;
+  for (long long t = 0; t < tiles; ++t) {
+    tile_chunk[(size_t)t] = nchunks;
+    const int total = off[(size_t)t + 1] - off[(size_t)t];
+    int origin[3], rlo[3], span[3];
+    long long rem = t;
+    for (int a = 2; a >= 0; --a) {
+      origin[a] = (int)(rem % nt[a]) * TS::ext(a);
+      rem /= nt[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+      const int tlast = std::min(origin[a] + TS::ext(a) - 1, g.m[a] - 1);
+      rlo[a] = std::max(H, origin[a] - (S - 1 - H));
+      span[a] = std::min(g.nc[a] + H - 1, tlast + H) - rlo[a] + 1;
+    }
+    // local slot offsets of the region cells, as k_tile_fill lays them out
+    lcs.assign((size_t)span[0] * span[1] * span[2] + 1, 0);
+    int pre = 0;
+    for (int r0 = 0; r0 < span[0]; ++r0)
+      for (int r1 = 0; r1 < span[1]; ++r1) {
+        const int row = r0 * span[1] + r1;
+        const long long base = ((long long)(rlo[0] + r0 - H) * g.nc[1] + (rlo[1] + r1 - H)) * g.nc[2] + rlo[2] - H;
+        for (int k = 0; k < span[2]; ++k) lcs[(size_t)row * span[2] + k] = pre + cs[base + k] - cs[base];
+        pre += cs[base + span[2]] - cs[base];
+      }
+    lcs.back() = pre;
+    if (pre != total) {
+      set_error("grouped scatter tables: region sizes disagree");
+      return DSKI_EINVAL;
+    }
+    for (int q0 = 0; q0 < total; q0 += PMAX) {
+      const int q1 = std::min(total, q0 + PMAX);
+      list.clear();
+      for (int node = 0; node < 256; ++node) {
+        const int j[3] = {origin[0] + node / (TS::e1 * TS::e2), origin[1] + (node / TS::e2) % TS::e1,
+                          origin[2] + node % TS::e2};
+        if (j[0] >= g.m[0] || j[1] >= g.m[1] || j[2] >= g.m[2]) continue;
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::max(H, j[a] - (S - 1 - H));
+          hi[a] = std::min(g.nc[a] + H - 1, j[a] + H);
+        }
+        for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
+          int work = 0, pts = 0;
+          for (int c1 = lo[1]; c1 <= hi[1]; ++c1) {
+            const int lrow = (c0 - rlo[0]) * span[1] + (c1 - rlo[1]);
+            const int qs = std::max(q0, lcs[(size_t)lrow * span[2] + lo[2] - rlo[2]]);
+            const int qe = std::min(q1, lcs[(size_t)lrow * span[2] + hi[2] - rlo[2] + 1]);
+            const int cnt = std::max(0, qe - qs);
+            pts += cnt;
+            work += (cnt + 1) / 2 + 1;
+          }
+          if (pts > 0) list.push_back({work, node * 8 + (c0 - lo[0])});
+        }
+      }
+      std::sort(list.begin(), list.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+        return x.first != y.first ? x.first > y.first : x.second < y.second;
+      });
+      for (const auto& w : list) items.push_back((unsigned short)w.second);
+      chunk_off.push_back((int)items.size());
+      ++nchunks;
+    }
+  }
+  tile_chunk[(size_t)tiles] = nchunks;
+  if (items.empty()) items.push_back(0);
+  DSKI_HIP(hipMalloc(&p->grp_items, sizeof(unsigned short) * items.size()));
+  DSKI_HIP(hipMalloc(&p->grp_chunk_off, sizeof(int) * chunk_off.size()));
+  DSKI_HIP(hipMalloc(&p->grp_tile_chunk, sizeof(int) * tile_chunk.size()));
+  DSKI_HIP(hipMemcpyAsync(p->grp_items, items.data(), sizeof(unsigned short) * items.size(), hipMemcpyHostToDevice,
+                          st));
+  DSKI_HIP(hipMemcpyAsync(p->grp_chunk_off, chunk_off.data(), sizeof(int) * chunk_off.size(),
+                          hipMemcpyHostToDevice, st));
+  DSKI_HIP(hipMemcpyAsync(p->grp_tile_chunk, tile_chunk.data(), sizeof(int) * tile_chunk.size(),
+                          hipMemcpyHostToDevice, st));
+  DSKI_HIP(hipStreamSynchronize(st));
+  return DSKI_OK;
+}
 
 // Region tables of the LDS-tiled scatter, built once per plan: pass 1 counts
 // every tile's region points, the host forms the offsets, pass 2 fills the
@@ -627,6 +872,7 @@ static dski_status build_tiles(dski_plan p, hipStream_t st) {
                                                      p->tile_pts, p->tile_cl);
   DSKI_HIP(hipGetLastError());
   DSKI_HIP(hipStreamSynchronize(st));
+  if constexpr (D == 3) DSKI_TRY(build_groups3<S>(p, g, tiles, off, st));
   return DSKI_OK;
 }
 

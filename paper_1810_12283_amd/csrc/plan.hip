@@ -315,6 +315,9 @@ dski_status dski_plan_destroy(dski_plan p) {
   (void)hipFree(p->tile_lcs);
   (void)hipFree(p->tile_pts);
   (void)hipFree(p->tile_cl);
+  (void)hipFree(p->grp_items);
+  (void)hipFree(p->grp_chunk_off);
+  (void)hipFree(p->grp_tile_chunk);
   (void)hipFree(p->bttb_spec);
   p->bttb_work.release();
   for (int a = 0; a < (p->kind == 0 ? p->d : 0); ++a) {

@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libdski.so")
 OK, NOT_CONVERGED, RANK_TRUNCATED = 0, 1, 2
 INTERP = {"cubic": 0, "quintic": 1}   # DSKI_INTERP_CUBIC, DSKI_INTERP_QUINTIC
 KERNEL = {"se": 0, "spline": 1}       # DSKI_KERNEL_SE, DSKI_KERNEL_SPLINE
+SCATTER_VARIANTS = 7                  # 0-5 bitwise equal; 6 the grouped 3-D form
+GATHER_VARIANTS = 3
 _STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "RANK_TRUNCATED", -1: "EINVAL", -2: "ENOMEM",
            -3: "EHIP", -4: "EBREAKDOWN", -5: "ENOTSUP"}
 
@@ -342,7 +344,7 @@ class Plan:
         """Time the kernel variants for this shape and keep the fastest; with
         cache (a file path) reuse the choice stored for this shape if there is
         one (the result then has cached=True and no timings)."""
-        t = (C.c_double * 15)()
+        t = (C.c_double * 16)()
         if cache is None:
             _check(lib().dski_autotune(self._h, int(R), t, _stream(stream)), "dski_autotune")
             hit = False
@@ -351,8 +353,8 @@ class Plan:
             _check(lib().dski_autotune_cached(self._h, int(R), str(cache).encode(), C.byref(h), t, _stream(stream)),
                    "dski_autotune_cached")
             hit = bool(h.value)
-        return {"scatter_us": [t[i] for i in range(6)], "gather_us": [t[6], t[7], t[8]],
-                "kuu_us": [[t[9 + 2 * a], t[10 + 2 * a]] for a in range(min(self.d, 3))], "cached": hit}
+        return {"scatter_us": [t[i] for i in range(SCATTER_VARIANTS)], "gather_us": [t[7], t[8], t[9]],
+                "kuu_us": [[t[10 + 2 * a], t[11 + 2 * a]] for a in range(min(self.d, 3))], "cached": hit}
 
     def set_variants(self, scatter: int, gather: int = 0):
         _check(lib().dski_set_variants(self._h, int(scatter), int(gather)), "dski_set_variants")

@@ -31,21 +31,28 @@ def test_quintic_mvm_matches_oracle(name):
     say("quintic mvm", name, W.n, W.grid_m)
     plan, op = make(W, interp="quintic")
     r = np.random.default_rng(3)
+    Vs = []
     for R in (1, 5, 17):
         V = r.standard_normal((op.N, R)).astype(np.float32).astype(np.float64)
         V[:, 0] = W.y.astype(np.float32)
-        ref = op.matvec(V)
-        e2, emax = mvm_errors(from_gpu(plan.mvm(to_gpu(V))), ref)
-        say("  R", R, "FP32", e2, emax)
-        assert e2 < 1e-5 and emax < 1e-5
-    V = r.standard_normal((op.N, 3))
-    Y = plan.mvm(torch.tensor(V.T.copy(), device="cuda")).cpu().numpy().T
-    e2, emax = mvm_errors(Y, op.matvec(V))
-    say("  FP64", e2, emax)
-    # element-wise, a 3-D quintic output sums 216 stencil products per column
-    # on each side (and the grid sums as many per node) in a different order
-    # from the oracle's sparse products: 1e-11 of the column's largest entry
-    assert e2 < 1e-12 and emax < (1e-11 if op.d == 3 else 1e-12)
+        Vs.append(V)
+    V64 = r.standard_normal((op.N, 3))
+    # in 3-D the grouped scatter (variant 6) as well as the tiled one
+    for sv in ((0, 6) if op.d == 3 else (0,)):
+        plan.set_variants(sv, 0)
+        for V in Vs:
+            e2, emax = mvm_errors(from_gpu(plan.mvm(to_gpu(V))), op.matvec(V))
+            say("  scatter", sv, "R", V.shape[1], "FP32", e2, emax)
+            assert e2 < 1e-5 and emax < 1e-5
+        Y = plan.mvm(torch.tensor(V64.T.copy(), device="cuda")).cpu().numpy().T
+        e2, emax = mvm_errors(Y, op.matvec(V64))
+        say("  scatter", sv, "FP64", e2, emax)
+        # element-wise, a 3-D quintic output sums 216 stencil products per column
+        # on each side (and the grid sums as many per node) in a different order
+        # from the oracle's sparse products: 1e-11 of the column's largest entry
+        assert e2 < 1e-12 and emax < (1e-11 if op.d == 3 else 1e-12)
+    plan.set_variants(0, 0)
+    V = V64
     for which in range(op.d + 3):
         Yd = plan.mvm_dtheta(which, torch.tensor(V.T.copy(), device="cuda")).cpu().numpy().T
         assert rel_cols(Yd, op.matvec_dtheta(which, V)).max() < 1e-12, which
