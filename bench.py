@@ -640,7 +640,7 @@ def main(argv=None):
         return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the block PCG would shard "
-              f"its right-hand sides across GPUs, which this build does not do.", file=sys.stderr)
+              f"its right-hand sides across GPUs, which is not implemented.", file=sys.stderr)
         return 2
 
     import numpy as np

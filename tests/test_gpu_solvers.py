@@ -119,7 +119,7 @@ def test_slq_fixed_steps_matches_oracle():
     """small2d (the FP64 configuration): 10 probes x 30 Lanczos steps, the
     explicit preconditioned Lanczos process with full re-orthogonalisation on
     both sides, same probes and pivots as the oracle: log det within 1e-3
-    relative (the spec bar; without re-orthogonalisation a 30-step run
+    relative (the log-determinant bar; without re-orthogonalisation a 30-step run
     is ill-conditioned and this bar could not be held).  Also checked with
     FP32 plan storage (the fixed-step path keeps FP64 vectors) and against the
     exact log det within the truncation bias of 30 steps (7 % here)."""
