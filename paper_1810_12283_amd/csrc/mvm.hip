@@ -106,10 +106,10 @@ __device__ __forceinline__ void interp_weight_at(double t, double ih, int o, dou
 // halo of S - 1 - H below and H above), with a table of each cell's range, then
 // every thread sums its node's contributions from LDS in the same fixed order
 // as above.  One thread stages one region point; regions of more than PMAX
-// points (256 in 1-D and 2-D, 128 in 3-D, where the LDS then holds all the
-// columns of a 17-column block) are staged PMAX points at a time, each node
-// adding the points of every chunk that fall in its cells (same order, same
-// result).
+// points (256 in 1-D and 2-D, 192 in 3-D, whose weight tables are larger: 3-D
+// surface regions measured fastest at 192, against 128, 96 and 64) are staged
+// PMAX points at a time, each node adding the points of every chunk that fall
+// in its cells (same order, same result).
 template <int D, int S>
 struct TileShape {
   static constexpr int e0 = D == 1 ? 256 : (D == 2 ? 16 : 4);
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int* __restrict__ cell,
 
 template <int D>
 constexpr int scatter_pmax() {
-  return D == 3 ? 128 : 256;
+  return D == 3 ? 192 : 256;
 }
 
 // Stages region slots [q0, q0 + PMAX) of a tile, one thread one point: its
