@@ -381,22 +381,17 @@ static dski_status launch_update(int nb, const T* Q, T* Rr, int N, int n, int R,
 #undef DSKI_UPD
 }
 
-// beta, history (hist = the beta rows), convergence test, x += alpha p and then
-// p = z + beta p (p of this iteration is read once for both).  Grid (row chunks of 256, R):
-// every block recomputes its column's beta from the r.z partials (same order);
-// block (0, c) writes the column's next-parity state.
+// Without a preconditioner (z = r): beta = r.r / r.r_old from the reduced norms
+// (every thread forms it, the same value), history (hist = the beta rows),
+// convergence test, x += alpha p and then p = r + beta p (p of this iteration
+// is read once for both).  Grid (row chunks of 256, R); block (0, c) writes the
+// column's next-parity state.
 template <typename T>
-__global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, double* __restrict__ Xd, int N, int R,
-                           PcgScal s, int par,
-                           const double* __restrict__ rz_part, int nb_rz, double* __restrict__ hist,
-                           int max_iter, int fixed_iters) {
-  __shared__ double s_beta;
-  __shared__ double s_red[4];
+__global__ void k_pcg_beta(const T* __restrict__ Rr, T* __restrict__ P, double* __restrict__ Xd, int N, int R,
+                           PcgScal s, int par, double* __restrict__ hist, int max_iter, int fixed_iters) {
   const int c = blockIdx.y;
-  // the column's state first; an active column then issues its rows of z, p
-  // and x and its r.z partials together
   const int on = s.active[par * R + c];
-  const double rz_old = s.rz[par * R + c], rr_c = s.rr[c];
+  const double rz_old = s.rz[par * R + c], rzn = s.rr[c];
   if (!on) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       s.rz[(1 - par) * R + c] = rz_old;
@@ -404,43 +399,23 @@ __global__ void k_pcg_beta(const T* __restrict__ Z, T* __restrict__ P, double* _
     }
     return;
   }
+  const double b = rz_old > 0.0 ? rzn / rz_old : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!(rzn >= 0.0) || !isfinite(rzn)) s.flags[1] = 1;
+    const int it = s.iters[c];
+    const bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (rzn <= s.tol2[c] * s.bb[c]);
+    if (hist && it < max_iter) hist[(size_t)c * max_iter + it] = b;
+    s.iters[c] = it + 1;
+    if (done) atomicSub(&s.flags[0], 1);
+    s.rz[(1 - par) * R + c] = rzn;
+    s.active[(1 - par) * R + c] = done ? 0 : 1;
+  }
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t ip = (size_t)c * N + (e < N ? e : 0);
-  const T zv = Z[ip], pv = P[ip];
-  const double xv = Xd[ip];
-  // r.z of the column from its partials: every thread of the block takes a
-  // share, a fixed-order tree combines them
-  double rzs = 0.0;
-  if (rz_part) {
-    for (int b = threadIdx.x; b < nb_rz; b += blockDim.x) rzs += rz_part[(size_t)c * nb_rz + b];
-    rzs = wave_sum64(rzs);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = rzs;
-    __syncthreads();
-    rzs = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
-  }
-  {
-    if (threadIdx.x == 0) {
-      double rzn = rz_part ? rzs : rr_c;
-      if (!(rzn >= 0.0) || !isfinite(rzn)) {
-        if (blockIdx.x == 0) s.flags[1] = 1;
-      }
-      double b = rz_old > 0.0 ? rzn / rz_old : 0.0;
-      if (blockIdx.x == 0) {
-        int it = s.iters[c];
-        bool done = fixed_iters > 0 ? (it + 1 >= fixed_iters) : (rr_c <= s.tol2[c] * s.bb[c]);
-        if (hist && it < max_iter) hist[(size_t)c * max_iter + it] = b;
-        s.iters[c] = it + 1;
-        if (done) atomicSub(&s.flags[0], 1);
-        s.rz[(1 - par) * R + c] = rzn;
-        s.active[(1 - par) * R + c] = done ? 0 : 1;
-      }
-      s_beta = b;
-    }
-  }
-  __syncthreads();
   if (e < N) {
-    Xd[ip] = xv + s.alpha[c] * (double)pv;  // x += alpha p with this iteration's p
-    P[ip] = (T)((double)zv + s_beta * (double)pv);
+    const size_t ip = (size_t)c * N + e;
+    const double pv = (double)P[ip];
+    Xd[ip] = Xd[ip] + s.alpha[c] * pv;  // x += alpha p with this iteration's p
+    P[ip] = (T)((double)Rr[ip] + b * pv);
   }
 }
 
@@ -842,8 +817,7 @@ static dski_status pcg_group(dski_plan p, dski_precond pc, int R, const T* B, in
                               q));
     } else {
       DSKI_TRY(launch_reduce_bm(jr, nullptr, q));
-      k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(Rr, P, Xd, N, R, s, par, nullptr, nbz, hist_b, max_iter,
-                                                    fixed_iters);
+      k_pcg_beta<T><<<dim3(nbz, R), kBlock, 0, q>>>(Rr, P, Xd, N, R, s, par, hist_b, max_iter, fixed_iters);
     }
     DSKI_HIP(hipGetLastError());
     return DSKI_OK;
