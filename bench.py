@@ -61,7 +61,6 @@ def _fastest(times):
 def tuned_variants(tune):
     """The variants the tuner keeps: the first fastest scatter and gather form, and
     per axis the FFT unless the dense form (timed, not -1) is strictly faster."""
-    import numpy as np
     return {"scatter": _fastest(tune["scatter_us"]), "gather": _fastest(tune["gather_us"]),
             "kuu": [0 if (t[1] < 0 or t[0] <= t[1]) else 1 for t in tune["kuu_us"]]}
 

@@ -77,3 +77,12 @@ def test_stats_table_sorted_by_total(tmp_path):
     rows = bench.stats_table(str(p)).splitlines()
     assert rows[2].startswith("| `dski::big<3>` | 4 | 0.0 | 2.25 | 90.0 |")
     assert rows[3].startswith("| `dski::small` | 10 |")
+
+
+def test_fastest_variant_skips_untimed():
+    # -1 marks a variant the tuner did not time (the grouped 3-D scatter on a 2-D plan)
+    assert bench._fastest([13.3, 144.9, 100.4, 13.2, 14.4, 29.3, -1.0]) == 3
+    assert bench._fastest([-1.0, 5.0, 4.0]) == 2
+    tune = {"scatter_us": [2.0, -1.0, 1.5], "gather_us": [1.0, 0.5, 0.7], "kuu_us": [[8.8, 24.9], [7.2, -1.0]]}
+    v = bench.tuned_variants(tune)
+    assert v["scatter"] == 2 and v["gather"] == 1 and v["kuu"] == [0, 0]
